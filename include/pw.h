@@ -1,0 +1,229 @@
+/*
+ * pw.h -- C ABI of libpwdft: plane-wave Hamiltonian application and the
+ * Chebyshev-filtered block subspace iteration around it, on AMD MI355X (gfx950).
+ *
+ * Paper: arXiv 2507.08578 ("Abinit 2025").  Section 5.1 (GPU use for the
+ * ground state) frames the hot path as a "matrix-free" diagonalisation made of
+ * two operations -- applying H to a set of vectors, and the Rayleigh-Ritz
+ * step -- and recommends Chebyshev filtering because it needs few Rayleigh-Ritz
+ * calls; section 5.2, Eq. (ham-nl), gives the Kleinman-Bylander non-local
+ * term applied through stored projectors as matrix products; section 5.4
+ * uses a full-band Cholesky orthogonalisation.  Hartree atomic units
+ * (section 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All functions are extern "C", never throw and never abort; they return a
+ *    pw_status.  On error, outputs are unspecified, handles stay valid, and
+ *    pw_last_error() holds a message.
+ *  - A block of nb wavefunctions is a column-major npw x nb complex matrix
+ *    (band b occupies elements [b*ld, b*ld + npw)), ld >= npw, complex values
+ *    interleaved (re, im).  Precision PW_FP64 = complex128 (the only block
+ *    precision accepted in this version; other values return
+ *    PW_ERR_UNSUPPORTED).
+ *  - Pointers named *_dev are device memory on the context's device, owned by
+ *    the caller; the library never frees them.  Pointers named *_host are host
+ *    memory read during the call only.
+ *  - Every kernel is enqueued on the stream given to pw_ctx_create.  Calls
+ *    return once the work is enqueued, except where a description says the
+ *    call synchronises (it then waits for that stream only).
+ *  - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef PW_H
+#define PW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PW_OK = 0,
+  PW_ERR_INVALID_ARG = 1,   /* null pointer, size or leading dimension out of range   */
+  PW_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement             */
+  PW_ERR_HIP = 3,           /* a HIP runtime call failed (message has the HIP string)  */
+  PW_ERR_OOM = 4,           /* device allocation failed                                */
+  PW_ERR_NOT_POSDEF = 5,    /* Gram matrix not numerically positive definite           */
+  PW_ERR_NONFINITE = 6,     /* NaN/Inf met in a result that must be finite             */
+  PW_ERR_NO_CONVERGENCE = 7 /* the dense eigensolver hit its sweep limit               */
+} pw_status;
+
+typedef enum { PW_FP64 = 0, PW_FP32 = 1, PW_BF16 = 2 } pw_prec;
+
+typedef struct pw_ctx pw_ctx;
+typedef struct pw_ham pw_ham;
+
+/* Name of a status code (static string). */
+const char* pw_status_string(pw_status s);
+
+/* Library version string (static). */
+const char* pw_version(void);
+
+/*
+ * Create a context on HIP device `device` whose work goes to `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  Errors:
+ * INVALID_ARG (out == NULL, device < 0), HIP (no such device / not gfx950-
+ * class LDS), OOM.
+ */
+pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out);
+pw_status pw_ctx_destroy(pw_ctx* ctx);
+
+/* Message of the last error on this context ("" if none); valid until the
+ * next call on it.  pw_last_error(NULL) returns the last error of calls that
+ * had no valid context. */
+const char* pw_last_error(const pw_ctx* ctx);
+
+/*
+ * Description of H at one k-point (section 5.2, Eq. ham-nl, norm-conserving
+ * case: h_{a,ij} diagonal).
+ *   n[3]     FFT box N1, N2, N3.  Each N_i must be a product of the radices
+ *            2, 3, 4, 5 with a factorisation the library supports (all
+ *            {2,3,5}-smooth sizes 2..256 are) and must hold the sphere:
+ *            N_i >= 2*max|n_i| + 1 is NOT required (the local term is the
+ *            box-periodic convolution, aliasing included), but distinct sphere
+ *            points must land in distinct box cells (else INVALID_ARG).
+ *   npw      number of plane waves (> 0).
+ *   miller   HOST, npw x 3 int32 row-major (n1, n2, n3) per point; the order
+ *            of points is the order of rows of every block.  Box index of a
+ *            point: m_i = n_i mod N_i.
+ *   recip    HOST-side values: rows b1, b2, b3 of the reciprocal lattice
+ *            (bohr^-1), G = n1 b1 + n2 b2 + n3 b3.
+ *   kpt      reduced coordinates of k; the kinetic energy is 1/2 |k + G|^2.
+ *   vloc_dev DEVICE, N1*N2*N3 float64, layout [N3][N2][N1] (N1 fastest):
+ *            V_loc at grid points r_j = (j1/N1, j2/N2, j3/N3) A, in Ha.
+ *            Copied at creation; the caller may free it afterwards.
+ *   nproj    number of projectors (>= 0).
+ *   proj_dev DEVICE, npw x nproj complex128, column-major, leading dim npw:
+ *            column j = <k+G|p_j>.  Referenced, not copied: it must stay
+ *            valid and unchanged while the pw_ham lives.
+ *   ekb      HOST, nproj float64: KB energies (diagonal of h), Ha.
+ *   nb_max   largest block size that will be passed to this handle (> 0);
+ *            workspaces are sized for it at creation so hot calls allocate
+ *            nothing.
+ */
+typedef struct {
+  int32_t n[3];
+  int64_t npw;
+  const int32_t* miller;
+  double recip[9];
+  double kpt[3];
+  const double* vloc_dev;
+  int64_t nproj;
+  const void* proj_dev;
+  const double* ekb;
+  int64_t nb_max;
+} pw_ham_desc;
+
+/* Build the plans (sphere columns, box extents, twiddle tables, kinetic
+ * energies, scaled V copy) and workspaces.  Synchronises.  Errors:
+ * INVALID_ARG, UNSUPPORTED (box size or shared-memory need beyond this GPU),
+ * OOM, HIP. */
+pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* desc, pw_ham** out);
+pw_status pw_ham_destroy(pw_ham* ham);
+/* Sizes the handle was built with (any pointer may be NULL). */
+pw_status pw_ham_info(const pw_ham* ham, int64_t* npw, int64_t* nproj, int64_t* nb_max,
+                      int64_t* ncolumns, int64_t* extent1);
+
+/*
+ * hpsi = H psi for a block of nb bands (section 5.1 "apply H to a set of
+ * vectors"; section 5.2 Eq. ham-nl for the non-local part):
+ *   (H psi)_g = 1/2|k+G_g|^2 psi_g + [F_fwd(V . F_bwd(scatter psi))]_g
+ *               + sum_j P_gj E_j (P^H psi)_j,
+ * F_bwd unnormalised with e^{+2 pi i m.j/N}, F_fwd with e^{-2 pi i m.j/N}
+ * and 1/(N1 N2 N3).  psi_dev and hpsi_dev must not overlap.  1 <= nb <= nb_max.
+ */
+pw_status pw_apply_h(pw_ham* ham, pw_prec prec, int64_t nb, const void* psi_dev, int64_t ldpsi,
+                     void* hpsi_dev, int64_t ldh);
+
+/*
+ * Chebyshev filter of degree m >= 1 (section 5.1; the paper cites the
+ * filter without formulas, this is the textbook scaled three-term form):
+ *   y <- p_m(H) y,  p_m(t) = T_m((t-c)/e) / T_m((a0-c)/e),  c=(a+b)/2, e=(b-a)/2,
+ * run as  Y1 = (s/e)(H X - c X), Y_i = (2 s'/e)(H Y_{i-1} - c Y_{i-1}) - s s' Y_{i-2}
+ * with s = e/(a0-c), s' = 1/(2/s_1 - s).  Requires a0 < a < b.
+ * hx_dev (may be NULL): H X already computed (e.g. by the previous
+ * Rayleigh-Ritz); then only m-1 products are formed.
+ */
+pw_status pw_cheb_filter(pw_ham* ham, pw_prec prec, int32_t degree, double a, double b, double a0,
+                         int64_t nb, void* y_dev, int64_t ld, const void* hx_dev, int64_t ldhx);
+
+/*
+ * Cholesky orthonormalisation (section 5.4): S = Y^H Y = U^H U (U upper,
+ * positive diagonal), Y <- Y U^{-1}; if hy_dev != NULL, HY <- HY U^{-1} too.
+ * gram_prec: PW_FP64 only in this version.  Synchronises (reads the
+ * factorisation status).  PW_ERR_NOT_POSDEF when a squared pivot is at or
+ * below nb * eps * max_i S_ii; the message names the pivot.
+ */
+pw_status pw_orthonormalize(pw_ham* ham, pw_prec gram_prec, int64_t nb, void* y_dev, int64_t ld,
+                            void* hy_dev, int64_t ldhy);
+
+/*
+ * Rayleigh-Ritz (section 5.1), all in FP64: W = H Y (written to hy_dev);
+ * Hs = (Y^H W + (Y^H W)^H)/2; Hs = Q diag(lambda) Q^H with lambda ascending;
+ * Y <- Y Q; W <- W Q; resid_b = ||W_b - lambda_b Y_b||_2.  Y must be
+ * orthonormal.  eig_dev (nb doubles) and resid_dev (nb doubles, may be NULL)
+ * are device memory.  Synchronises (eigensolver convergence test).
+ */
+pw_status pw_rayleigh_ritz(pw_ham* ham, int64_t nb, void* y_dev, int64_t ld, void* hy_dev,
+                           int64_t ldhy, double* eig_dev, double* resid_dev);
+
+/*
+ * Upper bound of the spectrum of H used as the filter's upper edge b:
+ * max_g T_g + max_r V(r) + lambda_max(D+^1/2 P^H P D+^1/2), D+ = max(E_KB, 0)
+ * (each term bounds its operator from above).  Synchronises.
+ */
+pw_status pw_upper_bound(pw_ham* ham, double* b_host);
+
+/* ---------------------------------------------------------------------------
+ * Dense building blocks, exposed for testing and for callers that hold their
+ * own subspace matrices.  All FP64 complex, column-major, device memory.
+ * ------------------------------------------------------------------------- */
+
+/* C (m x n, ldc) = alpha * A^H B with A k x m (lda), B k x n (ldb); k may be
+ * large (split over the K dimension with a fixed-order reduction). */
+pw_status pw_gemm_cn(pw_ctx* ctx, int64_t m, int64_t n, int64_t k, double alpha_re,
+                     const void* a_dev, int64_t lda, const void* b_dev, int64_t ldb,
+                     void* c_dev, int64_t ldc);
+/* C (m x n, ldc) = alpha * A B + beta * C with A m x k (lda), B k x n (ldb). */
+pw_status pw_gemm_nn(pw_ctx* ctx, int64_t m, int64_t n, int64_t k, double alpha_re,
+                     const void* a_dev, int64_t lda, const void* b_dev, int64_t ldb,
+                     double beta_re, void* c_dev, int64_t ldc);
+/* Hermitian eigendecomposition a = Q diag(w) Q^H (n x n, lda) by cyclic
+ * Jacobi: a is destroyed, q_dev (n x n, ldq) receives Q, w_dev ascending.
+ * Synchronises.  NO_CONVERGENCE after the sweep limit. */
+pw_status pw_heev(pw_ctx* ctx, int64_t n, void* a_dev, int64_t lda, double* w_dev,
+                  void* q_dev, int64_t ldq);
+/* Upper Cholesky factor in place: a = U^H U (upper triangle of a read and
+ * overwritten; strictly lower part set to 0); then ainv_dev (n x n, ldi)
+ * receives U^{-1} (upper, zeros below).  Synchronises; NOT_POSDEF as above. */
+pw_status pw_potrf_inv(pw_ctx* ctx, int64_t n, void* a_dev, int64_t lda, void* ainv_dev,
+                       int64_t ldi);
+
+/* ---------------------------------------------------------------------------
+ * Stage timing: when enabled, every kernel launch of the hot path is
+ * bracketed by HIP events on the context's stream, grouped by stage.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  PW_STAGE_FFT_COL_INV = 0,  /* scatter + backward transform along N3 (sphere columns)   */
+  PW_STAGE_FFT_PLANE = 1,    /* N2/N1 backward, x V, N1/N2 forward, per z-plane            */
+  PW_STAGE_FFT_COL_FWD = 2,  /* forward along N3 + gather + kinetic + recurrence epilogue */
+  PW_STAGE_PROJ = 3,         /* cprj C = P^H psi (split-K) + reduction x E_KB               */
+  PW_STAGE_NONLOCAL = 4,     /* H psi += P C                                               */
+  PW_STAGE_GRAM = 5,         /* Y^H Y and Y^H W                                            */
+  PW_STAGE_CHOL = 6,         /* Cholesky + triangular inverse                              */
+  PW_STAGE_ROTATE = 7,       /* Y U^{-1}, Y Q, W Q                                         */
+  PW_STAGE_EIGH = 8,         /* dense Hermitian eigensolver                                */
+  PW_STAGE_MISC = 9,         /* residuals, copies, reductions                              */
+  PW_STAGE_COUNT = 10
+} pw_stage;
+
+pw_status pw_ctx_set_timing(pw_ctx* ctx, int enable);
+/* Synchronises; total milliseconds and launch count since the last reset. */
+pw_status pw_ctx_stage_time(pw_ctx* ctx, int stage, double* total_ms, int64_t* launches);
+pw_status pw_ctx_reset_timing(pw_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PW_H */

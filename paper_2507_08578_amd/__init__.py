@@ -1,0 +1,258 @@
+"""MI355X plane-wave H*psi + Chebyshev-filtered subspace iteration (arXiv 2507.08578, section 5).
+
+Python face of libpwdft.so: a thin ctypes layer over the C ABI in include/pw.h.
+PyTorch supplies device memory and streams; every step of the path runs in
+the library's HIP kernels.  Blocks of bands are complex128 CUDA tensors of
+shape (nb, npw) whose rows are bands (column-major npw x nb with leading
+dimension tensor.stride(0)).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import PWError, PW_FP64, PW_FP32, PW_BF16, STAGES  # noqa: F401
+
+_LIB = _lib.load()
+
+
+def lib() -> ctypes.CDLL:
+    return _LIB
+
+
+def version() -> str:
+    return _LIB.pw_version().decode()
+
+
+def status_string(s: int) -> str:
+    return _LIB.pw_status_string(s).decode()
+
+
+def _check(status: int, ctx_handle=None):
+    if status != _lib.PW_OK:
+        msg = _LIB.pw_last_error(ctx_handle).decode()
+        raise PWError(status, f"{status_string(status)}: {msg}")
+
+
+def _block_args(t, npw: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if t.dim() != 2 or t.shape[1] != npw or t.stride(1) != 1:
+        raise ValueError(f"{name} must have shape (nb, npw={npw}) with unit stride along npw")
+    return ctypes.c_void_p(t.data_ptr()), t.stride(0)
+
+
+class Context:
+    """pw_ctx on one HIP device and stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        sh = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+        _check(_LIB.pw_ctx_create(device, sh, ctypes.byref(handle)))
+        self.handle = handle
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _LIB.pw_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, status: int):
+        _check(status, self.handle)
+
+    # --- stage timing ---
+    def set_timing(self, enable: bool):
+        self.check(_LIB.pw_ctx_set_timing(self.handle, int(enable)))
+
+    def reset_timing(self):
+        self.check(_LIB.pw_ctx_reset_timing(self.handle))
+
+    def stage_times(self) -> dict:
+        out = {}
+        for i, name in enumerate(STAGES):
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            self.check(_LIB.pw_ctx_stage_time(self.handle, i, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
+    # --- dense building blocks (complex128 column-major = torch (ncols, nrows) row-major) ---
+    def gemm_cn(self, A, B, alpha: float = 1.0):
+        """C = alpha A^H B for A (m, k) and B (n, k) tensors holding column-major k x m / k x n."""
+        import torch
+        m, k = A.shape
+        n = B.shape[0]
+        C = torch.empty((n, m), dtype=torch.complex128, device=A.device)
+        self.check(_LIB.pw_gemm_cn(self.handle, m, n, k, alpha, A.data_ptr(), A.stride(0),
+                                   B.data_ptr(), B.stride(0), C.data_ptr(), C.stride(0)))
+        return C
+
+    def gemm_nn(self, A, B, alpha: float = 1.0, beta: float = 0.0, C=None):
+        """C = alpha A B + beta C, column-major A (m x k) as tensor (k, m), B (k x n) as (n, k)."""
+        import torch
+        k, m = A.shape
+        n = B.shape[0]
+        if C is None:
+            C = torch.zeros((n, m), dtype=torch.complex128, device=A.device)
+        self.check(_LIB.pw_gemm_nn(self.handle, m, n, k, alpha, A.data_ptr(), A.stride(0),
+                                   B.data_ptr(), B.stride(0), beta, C.data_ptr(), C.stride(0)))
+        return C
+
+    def heev(self, A):
+        """Eigen-decomposition of a Hermitian matrix held column-major in tensor (n, n).
+        Returns (w ascending, Q column-major in a tensor (n, n))."""
+        import torch
+        n = A.shape[0]
+        a = A.clone()
+        w = torch.empty(n, dtype=torch.float64, device=A.device)
+        Q = torch.empty((n, n), dtype=torch.complex128, device=A.device)
+        self.check(_LIB.pw_heev(self.handle, n, a.data_ptr(), a.stride(0), w.data_ptr(),
+                                Q.data_ptr(), Q.stride(0)))
+        return w, Q
+
+    def potrf_inv(self, S):
+        """Upper Cholesky S = U^H U and U^{-1}, column-major tensors (n, n)."""
+        import torch
+        n = S.shape[0]
+        U = S.clone()
+        X = torch.empty_like(S)
+        self.check(_LIB.pw_potrf_inv(self.handle, n, U.data_ptr(), U.stride(0), X.data_ptr(),
+                                     X.stride(0)))
+        return U, X
+
+
+class Hamiltonian:
+    """pw_ham: H at one k-point (section 5.2, Eq. ham-nl, norm-conserving form).
+
+    miller: (npw, 3) int, recip: (3, 3) rows b_i, kpt: reduced (3,), box: (N1, N2, N3),
+    vloc: float64 CUDA tensor (N3, N2, N1), proj: complex128 CUDA tensor (nproj, npw)
+    (row j = projector j; kept referenced for the lifetime of this object),
+    ekb: (nproj,) KB energies.
+    """
+
+    def __init__(self, ctx: Context, miller, recip, kpt, box, vloc, proj, ekb, nb_max: int):
+        import torch
+        self.ctx = ctx
+        miller = np.ascontiguousarray(np.asarray(miller, dtype=np.int32))
+        if miller.ndim != 2 or miller.shape[1] != 3:
+            raise ValueError("miller must be (npw, 3)")
+        self.npw = int(miller.shape[0])
+        if not (isinstance(vloc, torch.Tensor) and vloc.is_cuda and vloc.dtype == torch.float64
+                and vloc.is_contiguous()):
+            raise TypeError("vloc must be a contiguous float64 CUDA tensor (N3, N2, N1)")
+        N1, N2, N3 = (int(x) for x in box)
+        if tuple(vloc.shape) != (N3, N2, N1):
+            raise ValueError(f"vloc shape {tuple(vloc.shape)} != (N3, N2, N1) = {(N3, N2, N1)}")
+        self.nproj = 0 if proj is None else int(proj.shape[0])
+        if self.nproj:
+            if not (proj.is_cuda and proj.dtype == torch.complex128 and proj.is_contiguous()
+                    and proj.shape[1] == self.npw):
+                raise TypeError("proj must be a contiguous complex128 CUDA tensor (nproj, npw)")
+        self._proj = proj                    # the library references this memory
+        ekb = np.ascontiguousarray(np.asarray(ekb if ekb is not None else [], dtype=np.float64))
+        self._miller = miller
+        self._ekb = ekb
+        d = _lib.PwHamDesc()
+        d.n[:] = [N1, N2, N3]
+        d.npw = self.npw
+        d.miller = miller.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.recip[:] = [float(x) for x in np.asarray(recip, dtype=np.float64).reshape(9)]
+        d.kpt[:] = [float(x) for x in np.asarray(kpt, dtype=np.float64).reshape(3)]
+        d.vloc_dev = vloc.data_ptr()
+        d.nproj = self.nproj
+        d.proj_dev = proj.data_ptr() if self.nproj else None
+        d.ekb = ekb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if self.nproj else None
+        d.nb_max = int(nb_max)
+        self.nb_max = int(nb_max)
+        handle = ctypes.c_void_p()
+        ctx.check(_LIB.pw_ham_create(ctx.handle, ctypes.byref(d), ctypes.byref(handle)))
+        self.handle = handle
+        vals = [ctypes.c_int64() for _ in range(5)]
+        ctx.check(_LIB.pw_ham_info(handle, *[ctypes.byref(v) for v in vals]))
+        self.ncolumns = vals[3].value
+        self.extent1 = vals[4].value
+        self.box = (N1, N2, N3)
+
+    @staticmethod
+    def from_workload(ctx: Context, w, nb_max: Optional[int] = None, device: str = "cuda"):
+        """Build from a synth.Workload (arrays copied to the device here)."""
+        import torch
+        vloc = torch.from_numpy(np.ascontiguousarray(w.vloc)).to(device)
+        proj = torch.from_numpy(np.ascontiguousarray(w.proj)).to(device) if w.nproj else None
+        return Hamiltonian(ctx, w.miller, w.recip, w.kred, w.box, vloc, proj, w.ekb,
+                           nb_max or w.nb)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _LIB.pw_ham_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- hot path ---
+    def apply_h(self, psi, out=None):
+        import torch
+        p, ldp = _block_args(psi, self.npw, "psi")
+        if out is None:
+            out = torch.empty_like(psi)
+        o, ldo = _block_args(out, self.npw, "out")
+        self.ctx.check(_LIB.pw_apply_h(self.handle, PW_FP64, psi.shape[0], p, ldp, o, ldo))
+        return out
+
+    def cheb_filter(self, y, degree: int, a: float, b: float, a0: float, hx=None):
+        p, ld = _block_args(y, self.npw, "y")
+        if hx is not None:
+            hp, ldh = _block_args(hx, self.npw, "hx")
+        else:
+            hp, ldh = None, 0
+        self.ctx.check(_LIB.pw_cheb_filter(self.handle, PW_FP64, int(degree), float(a), float(b),
+                                           float(a0), y.shape[0], p, ld, hp, ldh))
+        return y
+
+    def orthonormalize(self, y, hy=None):
+        p, ld = _block_args(y, self.npw, "y")
+        if hy is not None:
+            hp, ldh = _block_args(hy, self.npw, "hy")
+        else:
+            hp, ldh = None, 0
+        self.ctx.check(_LIB.pw_orthonormalize(self.handle, PW_FP64, y.shape[0], p, ld, hp, ldh))
+        return y
+
+    def rayleigh_ritz(self, y, hy, eig, resid=None):
+        import torch
+        p, ld = _block_args(y, self.npw, "y")
+        hp, ldh = _block_args(hy, self.npw, "hy")
+        for t, nm in ((eig, "eig"), (resid, "resid")):
+            if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                                      and t.numel() >= y.shape[0]):
+                raise TypeError(f"{nm} must be a float64 CUDA tensor of >= nb elements")
+        self.ctx.check(_LIB.pw_rayleigh_ritz(self.handle, y.shape[0], p, ld, hp, ldh,
+                                             eig.data_ptr(),
+                                             resid.data_ptr() if resid is not None else None))
+        return eig
+
+    def upper_bound(self) -> float:
+        b = ctypes.c_double()
+        self.ctx.check(_LIB.pw_upper_bound(self.handle, ctypes.byref(b)))
+        return b.value
+
+
+from .chfsi import chfsi, ChfsiState  # noqa: E402,F401

@@ -1,0 +1,87 @@
+"""ctypes binding of libpwdft.so (declared in include/pw.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+the library.  There is no fallback: if the shared library is missing or
+fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpwdft.so")
+
+c_int64 = ctypes.c_int64
+c_int32 = ctypes.c_int32
+c_double = ctypes.c_double
+c_void_p = ctypes.c_void_p
+c_int = ctypes.c_int
+
+PW_OK = 0
+PW_FP64, PW_FP32, PW_BF16 = 0, 1, 2
+STAGES = ["fft_col_inv", "fft_plane", "fft_col_fwd", "proj", "nonlocal", "gram", "chol",
+          "rotate", "eigh", "misc"]
+
+
+class PwHamDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int32 * 3),
+        ("npw", c_int64),
+        ("miller", ctypes.POINTER(c_int32)),
+        ("recip", c_double * 9),
+        ("kpt", c_double * 3),
+        ("vloc_dev", c_void_p),
+        ("nproj", c_int64),
+        ("proj_dev", c_void_p),
+        ("ekb", ctypes.POINTER(c_double)),
+        ("nb_max", c_int64),
+    ]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "pw_status_string": (ctypes.c_char_p, [c_int]),
+    "pw_version": (ctypes.c_char_p, []),
+    "pw_last_error": (ctypes.c_char_p, [c_void_p]),
+    "pw_ctx_create": (c_int, [c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    "pw_ctx_destroy": (c_int, [c_void_p]),
+    "pw_ham_create": (c_int, [c_void_p, ctypes.POINTER(PwHamDesc), ctypes.POINTER(c_void_p)]),
+    "pw_ham_destroy": (c_int, [c_void_p]),
+    "pw_ham_info": (c_int, [c_void_p] + [ctypes.POINTER(c_int64)] * 5),
+    "pw_apply_h": (c_int, [c_void_p, c_int, c_int64, c_void_p, c_int64, c_void_p, c_int64]),
+    "pw_cheb_filter": (c_int, [c_void_p, c_int, c_int32, c_double, c_double, c_double, c_int64,
+                               c_void_p, c_int64, c_void_p, c_int64]),
+    "pw_orthonormalize": (c_int, [c_void_p, c_int, c_int64, c_void_p, c_int64, c_void_p, c_int64]),
+    "pw_rayleigh_ritz": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                 c_void_p]),
+    "pw_upper_bound": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
+    "pw_gemm_cn": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
+                           c_void_p, c_int64, c_void_p, c_int64]),
+    "pw_gemm_nn": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
+                           c_void_p, c_int64, c_double, c_void_p, c_int64]),
+    "pw_heev": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int64]),
+    "pw_potrf_inv": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64]),
+    "pw_ctx_set_timing": (c_int, [c_void_p, c_int]),
+    "pw_ctx_stage_time": (c_int, [c_void_p, c_int, ctypes.POINTER(c_double),
+                                  ctypes.POINTER(c_int64)]),
+    "pw_ctx_reset_timing": (c_int, [c_void_p]),
+}
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libpwdft.so not built at {path}; run __graft_entry__.build() "
+                          "or python paper_2507_08578_amd/build.py")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+class PWError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(message)

@@ -1,0 +1,241 @@
+// Complex FP64 matrix products on the gfx950 matrix cores (MFMA), used for
+// the dense contractions of the path: the projections c = P^H psi ("cprj",
+// section 5.2, Eq. ham-nl), the non-local expansion H psi += P (E c), the
+// Gram matrices Y^H Y and Y^H (H Y), and the subspace rotations Y Q, Y U^{-1}.
+//
+// v_mfma_f64_16x16x4f64 operand layout on gfx950 (checked on the device):
+//   A operand : lane l holds A[i = l % 16][k = l / 16]
+//   B operand : lane l holds B[k = l / 16][j = l % 16]
+//   result    : lane l, element r holds D[i = l / 16 + 4 r][j = l % 16]
+// A complex product is four real MFMAs into two accumulators:
+//   re += ar br - ai bi,  im += ar bi + ai br.
+#include "pw_internal.h"
+
+#include <algorithm>
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kBM = 64;       // workgroup tile rows
+constexpr int kBN = 64;       // workgroup tile columns
+constexpr int kThreads = 256; // 4 waves, 2 x 2, each a 32 x 32 sub-tile
+constexpr int kKcNN = 8;      // complex K per LDS stage (A B)
+constexpr int kKcCN = 16;     // complex K per LDS stage (A^H B)
+constexpr int kTargetBlocks = 2048;
+
+__device__ __forceinline__ void cmfma(d4& re, d4& im, double ar, double ai, double br, double bi) {
+  re = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, re, 0, 0, 0);
+  re = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, re, 0, 0, 0);
+  im = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, im, 0, 0, 0);
+  im = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, im, 0, 0, 0);
+}
+
+// C = alpha A B + beta C; A m x k (lda), B k x n (ldb), column-major.
+__global__ void __launch_bounds__(kThreads)
+k_gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict__ A, int64_t lda,
+          const cplx* __restrict__ B, int64_t ldb, double beta, cplx* __restrict__ C, int64_t ldc) {
+  __shared__ cplx As[kKcNN][kBM];
+  __shared__ cplx Bs[kKcNN][kBN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int64_t i0 = (int64_t)blockIdx.y * kBM, j0 = (int64_t)blockIdx.x * kBN;
+  d4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      accr[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      acci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int64_t k0 = 0; k0 < K; k0 += kKcNN) {
+    for (int e = tid; e < kBM * kKcNN; e += kThreads) {
+      const int kk = e / kBM, ii = e - kk * kBM;
+      const int64_t gi = i0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < M && gk < K) ? A[gi + gk * lda] : make_double2(0.0, 0.0);
+    }
+    for (int e = tid; e < kBN * kKcNN; e += kThreads) {
+      const int jj = e / kKcNN, kk = e - jj * kKcNN;
+      const int64_t gk = k0 + kk, gj = j0 + jj;
+      Bs[kk][jj] = (gk < K && gj < N) ? B[gk + gj * ldb] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kKcNN; ks += 4) {
+      cplx a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[ks + lk][wi * 32 + t * 16 + lr];
+        b[t] = Bs[ks + lk][wj * 32 + t * 16 + lr];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          cmfma(accr[ti][tj], acci[ti][tj], a[ti].x, a[ti].y, b[tj].x, b[tj].y);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wi * 32 + ti * 16 + lk + 4 * r;
+        const int64_t j = j0 + wj * 32 + tj * 16 + lr;
+        if (i < M && j < N) {
+          cplx v = make_double2(alpha * accr[ti][tj][r], alpha * acci[ti][tj][r]);
+          if (beta != 0.0) {
+            const cplx c = C[i + j * ldc];
+            v.x += beta * c.x;
+            v.y += beta * c.y;
+          }
+          C[i + j * ldc] = v;
+        }
+      }
+}
+
+// Partial or final C = alpha diag(rowscale) A^H B over K range [kb, ke) of split z.
+// A k x m (lda), B k x n (ldb).  Output at out + z*zstride, leading dim ldo.
+__global__ void __launch_bounds__(kThreads)
+k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
+          const double* __restrict__ rowscale, const cplx* __restrict__ A, int64_t lda,
+          const cplx* __restrict__ B, int64_t ldb, cplx* __restrict__ out, int64_t ldo,
+          int64_t zstride) {
+  __shared__ cplx As[kKcCN][kBM + 1];
+  __shared__ cplx Bs[kKcCN][kBN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int64_t i0 = (int64_t)blockIdx.y * kBM, j0 = (int64_t)blockIdx.x * kBN;
+  const int64_t kb = (int64_t)blockIdx.z * ksplit;
+  const int64_t ke = min(K, kb + ksplit);
+  d4 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      accr[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      acci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int64_t k0 = kb; k0 < ke; k0 += kKcCN) {
+    for (int e = tid; e < kBM * kKcCN; e += kThreads) {
+      const int ii = e / kKcCN, kk = e - ii * kKcCN;
+      const int64_t gi = i0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < M && gk < ke) ? A[gk + gi * lda] : make_double2(0.0, 0.0);
+    }
+    for (int e = tid; e < kBN * kKcCN; e += kThreads) {
+      const int jj = e / kKcCN, kk = e - jj * kKcCN;
+      const int64_t gj = j0 + jj, gk = k0 + kk;
+      Bs[kk][jj] = (gj < N && gk < ke) ? B[gk + gj * ldb] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kKcCN; ks += 4) {
+      cplx a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[ks + lk][wi * 32 + t * 16 + lr];
+        b[t] = Bs[ks + lk][wj * 32 + t * 16 + lr];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)   // conj(A): negate the imaginary part
+          cmfma(accr[ti][tj], acci[ti][tj], a[ti].x, -a[ti].y, b[tj].x, b[tj].y);
+    }
+    __syncthreads();
+  }
+  cplx* o = out + (int64_t)blockIdx.z * zstride;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wi * 32 + ti * 16 + lk + 4 * r;
+        const int64_t j = j0 + wj * 32 + tj * 16 + lr;
+        if (i < M && j < N) {
+          const double s = alpha * (rowscale ? rowscale[i] : 1.0);
+          o[i + j * ldo] = make_double2(s * accr[ti][tj][r], s * acci[ti][tj][r]);
+        }
+      }
+}
+
+// C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M], z in fixed order.
+__global__ void k_splitk_reduce(int64_t M, int64_t N, int nsplit, const cplx* __restrict__ work,
+                                double alpha, const double* __restrict__ rowscale,
+                                cplx* __restrict__ C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t j = idx / M, i = idx - j * M;
+  double re = 0.0, im = 0.0;
+  for (int z = 0; z < nsplit; ++z) {
+    const cplx w = work[(int64_t)z * M * N + idx];
+    re += w.x;
+    im += w.y;
+  }
+  const double s = alpha * (rowscale ? rowscale[i] : 1.0);
+  C[i + j * ldc] = make_double2(s * re, s * im);
+}
+
+struct SplitPlan {
+  int64_t tiles_m, tiles_n, nsplit, ksplit;
+};
+
+SplitPlan split_plan(int64_t m, int64_t n, int64_t k) {
+  SplitPlan p;
+  p.tiles_m = (m + kBM - 1) / kBM;
+  p.tiles_n = (n + kBN - 1) / kBN;
+  const int64_t tiles = p.tiles_m * p.tiles_n;
+  int64_t want = (kTargetBlocks + tiles - 1) / tiles;
+  const int64_t maxs = std::max<int64_t>(1, (k + kKcCN * 8 - 1) / (kKcCN * 8));
+  want = std::max<int64_t>(1, std::min(want, maxs));
+  int64_t ks = (k + want - 1) / want;
+  ks = ((ks + kKcCN - 1) / kKcCN) * kKcCN;
+  p.ksplit = std::max<int64_t>(ks, kKcCN);
+  p.nsplit = (k + p.ksplit - 1) / p.ksplit;
+  if (p.nsplit < 1) p.nsplit = 1;
+  return p;
+}
+
+}  // namespace
+
+size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k) {
+  const SplitPlan p = split_plan(m, n, k);
+  return p.nsplit > 1 ? (size_t)(p.nsplit * m * n) : 0;
+}
+
+hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
+                          const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
+                          cplx* work, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const SplitPlan p = split_plan(m, n, k);
+  if (p.nsplit == 1) {
+    dim3 grid(p.tiles_n, p.tiles_m, 1);
+    hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, alpha, rowscale,
+                       A, lda, B, ldb, C, ldc, (int64_t)0);
+    return hipGetLastError();
+  }
+  dim3 grid(p.tiles_n, p.tiles_m, p.nsplit);
+  hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, 1.0,
+                     (const double*)nullptr, A, lda, B, ldb, work, m, m * n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = m * n;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((tot + 255) / 256), dim3(256), 0, s, m, n,
+                     (int)p.nsplit, (const cplx*)work, alpha, rowscale, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
+                          const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
+                          hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  dim3 grid((n + kBN - 1) / kBN, (m + kBM - 1) / kBM, 1);
+  hipLaunchKernelGGL(k_gemm_nn, grid, dim3(kThreads), 0, s, m, n, k, alpha, A, lda, B, ldb, beta,
+                     C, ldc);
+  return hipGetLastError();
+}

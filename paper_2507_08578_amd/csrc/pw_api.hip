@@ -1,0 +1,802 @@
+// libpwdft host side: contexts, Hamiltonian handles (plans + workspaces) and
+// the orchestration of the hot path on one HIP stream.
+//
+//   pw_apply_h        section 5.1 (apply H to a block) + section 5.2 Eq. (ham-nl)
+//   pw_cheb_filter    section 5.1 (Chebyshev filtering, textbook scaled recurrence)
+//   pw_orthonormalize section 5.4 (full-band Cholesky orthogonalisation)
+//   pw_rayleigh_ritz  section 5.1 (Rayleigh-Ritz subspace diagonalisation)
+#include "pw_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#define PW_VERSION "0.1.0"
+
+struct EventPair {
+  hipEvent_t a, b;
+  int stage;
+};
+
+struct pw_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  size_t lds_limit = 0;
+  bool timing = false;
+  std::vector<EventPair> pending;
+  std::vector<hipEvent_t> pool;
+  double acc_ms[PW_STAGE_COUNT] = {0};
+  int64_t launches[PW_STAGE_COUNT] = {0};
+  double* pinned = nullptr;   // small pinned host scratch (64 doubles)
+
+  hipEvent_t get_event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
+struct pw_ham {
+  pw_ctx* ctx = nullptr;
+  BoxPlan plan{};
+  FftLaunchCfg cfg{};
+  int64_t npw = 0, nproj = 0, nb_max = 0, chunk = 0;
+  std::vector<void*> allocs;
+  double* kin = nullptr;
+  double* vscaled = nullptr;
+  double vmax = 0.0, kmax = 0.0;
+  const cplx* proj = nullptr;
+  double* ekb_dev = nullptr;
+  std::vector<double> ekb;
+  cplx* T = nullptr;
+  cplx* cprj = nullptr;
+  cplx* gemm_work = nullptr;
+  cplx* blk = nullptr;
+  cplx* sub0 = nullptr;
+  cplx* sub1 = nullptr;
+  void* heev_work = nullptr;
+  int* status_dev = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+pw_status fail(pw_ctx* c, pw_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail((ctx), PW_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+struct StageScope {
+  pw_ctx* c;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageScope(pw_ctx* ctx, int st) : c(ctx), stage(st) {
+    if (c->timing) {
+      a = c->get_event();
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~StageScope() {
+    if (c->timing && a) {
+      hipEvent_t b = c->get_event();
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->pending.push_back({a, b, stage});
+      } else {
+        c->pool.push_back(a);
+      }
+    }
+  }
+};
+
+template <class T>
+pw_status dalloc(pw_ham* h, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return PW_OK;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h->ctx, PW_ERR_OOM,
+                "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  h->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return PW_OK;
+}
+
+void free_ham(pw_ham* h) {
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+}
+
+inline int center(int m, int n) { return m <= n / 2 ? m : m - n; }
+
+bool ranges_overlap(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t rows,
+                    int64_t cols) {
+  const char* a0 = static_cast<const char*>(a);
+  const char* a1 = a0 + ((cols - 1) * lda + rows) * (int64_t)sizeof(cplx);
+  const char* b0 = static_cast<const char*>(b);
+  const char* b1 = b0 + ((cols - 1) * ldb + rows) * (int64_t)sizeof(cplx);
+  return a0 < b1 && b0 < a1;
+}
+
+pw_status check_block(pw_ham* h, const void* p, int64_t ld, const char* name) {
+  if (!p) return fail(h->ctx, PW_ERR_INVALID_ARG, std::string(name) + " is NULL");
+  if (ld < h->npw)
+    return fail(h->ctx, PW_ERR_INVALID_ARG,
+                std::string("leading dimension of ") + name + " (" + std::to_string(ld) +
+                    ") < npw (" + std::to_string(h->npw) + ")");
+  return PW_OK;
+}
+
+pw_status check_hot(pw_ham* h, pw_prec prec, int64_t nb) {
+  if (prec != PW_FP64)
+    return fail(h->ctx, PW_ERR_UNSUPPORTED, "only PW_FP64 blocks are implemented in this version");
+  if (nb < 1 || nb > h->nb_max)
+    return fail(h->ctx, PW_ERR_INVALID_ARG,
+                "nb = " + std::to_string(nb) + " outside [1, nb_max = " + std::to_string(h->nb_max) +
+                    "]");
+  return PW_OK;
+}
+
+// out = alpha (H in) + beta in + gamma prev (prev may alias out).
+pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* out, int64_t ldout,
+                    double alpha, double beta, double gamma, const cplx* prev, int64_t ldprev) {
+  pw_ctx* c = h->ctx;
+  hipStream_t s = c->stream;
+  if (h->nproj > 0) {
+    StageScope sc(c, PW_STAGE_PROJ);
+    HIPCHK(c, launch_gemm_cn(h->nproj, nb, h->npw, alpha, h->proj, h->npw, in, ldin, h->cprj,
+                             h->nproj, h->ekb_dev, h->gemm_work, s));
+  }
+  for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
+    const int nc = (int)std::min<int64_t>(h->chunk, nb - c0);
+    {
+      StageScope sc(c, PW_STAGE_FFT_COL_INV);
+      HIPCHK(c, launch_fft_col_inv(h->plan, h->cfg, nc, in + c0 * ldin, ldin, h->T, s));
+    }
+    {
+      StageScope sc(c, PW_STAGE_FFT_PLANE);
+      HIPCHK(c, launch_fft_plane(h->plan, h->cfg, nc, h->vscaled, h->T, s));
+    }
+    {
+      StageScope sc(c, PW_STAGE_FFT_COL_FWD);
+      HIPCHK(c, launch_fft_col_fwd(h->plan, h->cfg, nc, h->T, h->kin, in + c0 * ldin, ldin,
+                                   gamma != 0.0 ? prev + c0 * ldprev : nullptr, ldprev,
+                                   out + c0 * ldout, ldout, alpha, beta, gamma, s));
+    }
+  }
+  if (h->nproj > 0) {
+    StageScope sc(c, PW_STAGE_NONLOCAL);
+    HIPCHK(c, launch_gemm_nn(h->npw, nb, h->nproj, 1.0, h->proj, h->npw, h->cprj, h->nproj, 1.0,
+                             out, ldout, s));
+  }
+  return PW_OK;
+}
+
+// In-place right multiplication of a block by the nb x nb matrix m (ld nb), via blk.
+pw_status rotate_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, const cplx* m) {
+  pw_ctx* c = h->ctx;
+  StageScope sc(c, PW_STAGE_ROTATE);
+  HIPCHK(c, launch_gemm_nn(h->npw, nb, nb, 1.0, y, ld, m, nb, 0.0, h->blk, h->npw, c->stream));
+  HIPCHK(c, launch_copy_block(h->npw, nb, h->blk, h->npw, y, ld, c->stream));
+  return PW_OK;
+}
+
+pw_status heev_status(pw_ctx* c, int sweeps) {
+  if (sweeps < 0)
+    return fail(c, PW_ERR_NO_CONVERGENCE, "Jacobi eigensolver did not converge in its sweep limit");
+  return PW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pw_status_string(pw_status s) {
+  switch (s) {
+    case PW_OK: return "PW_OK";
+    case PW_ERR_INVALID_ARG: return "PW_ERR_INVALID_ARG";
+    case PW_ERR_UNSUPPORTED: return "PW_ERR_UNSUPPORTED";
+    case PW_ERR_HIP: return "PW_ERR_HIP";
+    case PW_ERR_OOM: return "PW_ERR_OOM";
+    case PW_ERR_NOT_POSDEF: return "PW_ERR_NOT_POSDEF";
+    case PW_ERR_NONFINITE: return "PW_ERR_NONFINITE";
+    case PW_ERR_NO_CONVERGENCE: return "PW_ERR_NO_CONVERGENCE";
+  }
+  return "PW_ERR_UNKNOWN";
+}
+
+const char* pw_version(void) { return PW_VERSION; }
+
+const char* pw_last_error(const pw_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
+  if (!out) return fail(nullptr, PW_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (device < 0) return fail(nullptr, PW_ERR_INVALID_ARG, "device < 0");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || device >= ndev)
+    return fail(nullptr, PW_ERR_HIP,
+                "no HIP device " + std::to_string(device) + " (" + hipGetErrorString(e) + ")");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(nullptr, PW_ERR_HIP, hipGetErrorString(e));
+  int lds = 0;
+  e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+  if (e != hipSuccess) return fail(nullptr, PW_ERR_HIP, hipGetErrorString(e));
+  pw_ctx* c = new pw_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->lds_limit = (size_t)lds;
+  void* pin = nullptr;
+  e = hipHostMalloc(&pin, 64 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, PW_ERR_OOM, "pinned host scratch allocation failed");
+  }
+  c->pinned = static_cast<double*>(pin);
+  e = fft_set_lds_limits(c->lds_limit);
+  if (e == hipSuccess) e = heev_set_lds_limit(c->lds_limit);
+  if (e != hipSuccess) {
+    (void)hipHostFree(pin);
+    delete c;
+    return fail(nullptr, PW_ERR_HIP, std::string("LDS opt-in: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return PW_OK;
+}
+
+pw_status pw_ctx_destroy(pw_ctx* ctx) {
+  if (!ctx) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return PW_OK;
+}
+
+pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
+  if (!ctx) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (!d || !out) return fail(ctx, PW_ERR_INVALID_ARG, "desc or out is NULL");
+  *out = nullptr;
+  if (d->npw <= 0 || d->npw > (int64_t)INT32_MAX)
+    return fail(ctx, PW_ERR_INVALID_ARG, "npw must be in [1, 2^31)");
+  if (!d->miller) return fail(ctx, PW_ERR_INVALID_ARG, "miller is NULL");
+  if (!d->vloc_dev) return fail(ctx, PW_ERR_INVALID_ARG, "vloc_dev is NULL");
+  if (d->nproj < 0) return fail(ctx, PW_ERR_INVALID_ARG, "nproj < 0");
+  if (d->nproj > 0 && (!d->proj_dev || !d->ekb))
+    return fail(ctx, PW_ERR_INVALID_ARG, "nproj > 0 needs proj_dev and ekb");
+  if (d->nb_max < 1 || d->nb_max > 4096)
+    return fail(ctx, PW_ERR_INVALID_ARG, "nb_max must be in [1, 4096]");
+  for (int i = 0; i < 3; ++i)
+    if (d->n[i] < 1 || d->n[i] > 4096)
+      return fail(ctx, PW_ERR_INVALID_ARG, "box dimensions must be in [1, 4096]");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(d->recip[i])) return fail(ctx, PW_ERR_INVALID_ARG, "recip not finite");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(d->kpt[i])) return fail(ctx, PW_ERR_INVALID_ARG, "kpt not finite");
+  for (int64_t j = 0; j < d->nproj; ++j)
+    if (!std::isfinite(d->ekb[j])) return fail(ctx, PW_ERR_INVALID_ARG, "ekb not finite");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+
+  pw_ham* h = new pw_ham();
+  h->ctx = ctx;
+  h->npw = d->npw;
+  h->nproj = d->nproj;
+  h->nb_max = d->nb_max;
+  BoxPlan& P = h->plan;
+  P.n1 = d->n[0];
+  P.n2 = d->n[1];
+  P.n3 = d->n[2];
+  P.npw = d->npw;
+  if (!fft_factor(P.n1, &P.ax1) || !fft_factor(P.n2, &P.ax2) || !fft_factor(P.n3, &P.ax3)) {
+    delete h;
+    return fail(ctx, PW_ERR_UNSUPPORTED,
+                "box sizes must factor into radices 2, 3, 4, 5, 8 with n/radix <= 256");
+  }
+  // ---- sphere -> box maps (host) ----
+  const int64_t npw = d->npw;
+  std::vector<int> m1(npw), m2(npw), m3(npw);
+  {
+    std::unordered_set<int64_t> cells;
+    cells.reserve((size_t)npw * 2);
+    for (int64_t g = 0; g < npw; ++g) {
+      const int64_t a = d->miller[3 * g], b = d->miller[3 * g + 1], cc = d->miller[3 * g + 2];
+      m1[g] = (int)(((a % P.n1) + P.n1) % P.n1);
+      m2[g] = (int)(((b % P.n2) + P.n2) % P.n2);
+      m3[g] = (int)(((cc % P.n3) + P.n3) % P.n3);
+      const int64_t key = ((int64_t)m3[g] * P.n2 + m2[g]) * P.n1 + m1[g];
+      if (!cells.insert(key).second) {
+        delete h;
+        return fail(ctx, PW_ERR_INVALID_ARG,
+                    "two sphere points fall in the same box cell (box too small), point " +
+                        std::to_string(g));
+      }
+    }
+  }
+  // points ordered by (centred m1, centred m2, centred m3): columns = runs of equal (m1, m2)
+  std::vector<int> order(npw);
+  for (int64_t g = 0; g < npw; ++g) order[g] = (int)g;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const int ax = center(m1[x], P.n1), ay = center(m1[y], P.n1);
+    if (ax != ay) return ax < ay;
+    const int bx = center(m2[x], P.n2), by = center(m2[y], P.n2);
+    if (bx != by) return bx < by;
+    return center(m3[x], P.n3) < center(m3[y], P.n3);
+  });
+  std::vector<int> col_start, col_m1, col_m2v, pt_col(npw), pt_m3(npw);
+  for (int64_t k = 0; k < npw; ++k) {
+    const int g = order[k];
+    if (k == 0 || m1[g] != m1[order[k - 1]] || m2[g] != m2[order[k - 1]]) {
+      col_start.push_back((int)k);
+      col_m1.push_back(m1[g]);
+      col_m2v.push_back(m2[g]);
+    }
+    pt_col[k] = (int)col_start.size() - 1;
+    pt_m3[k] = m3[g];
+  }
+  col_start.push_back((int)npw);
+  P.ncols = (int)col_m1.size();
+  std::vector<int> ext;   // distinct m1 sorted by centred value
+  {
+    std::vector<int> tmp(col_m1.begin(), col_m1.end());
+    std::sort(tmp.begin(), tmp.end(), [&](int x, int y) { return center(x, P.n1) < center(y, P.n1); });
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    ext = tmp;
+  }
+  P.xr = (int)ext.size();
+  std::vector<int> slot(P.n1, -1);
+  for (int e = 0; e < P.xr; ++e) slot[ext[e]] = e;
+  std::vector<int> col_e(P.ncols);
+  for (int c = 0; c < P.ncols; ++c) col_e[c] = slot[col_m1[c]];
+
+  pw_status st = PW_OK;
+  auto upload_int = [&](int** dst, const std::vector<int>& v) -> pw_status {
+    pw_status s2 = dalloc(h, dst, v.size());
+    if (s2 != PW_OK) return s2;
+    hipError_t e = hipMemcpy(*dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(ctx, PW_ERR_HIP, hipGetErrorString(e));
+    return PW_OK;
+  };
+#define TRY(x)         \
+  do {                 \
+    st = (x);          \
+    if (st != PW_OK) { \
+      free_ham(h);     \
+      delete h;        \
+      return st;       \
+    }                  \
+  } while (0)
+  TRY(upload_int(&P.col_start, col_start));
+  TRY(upload_int(&P.col_e, col_e));
+  TRY(upload_int(&P.col_m2, col_m2v));
+  TRY(upload_int(&P.pt_perm, order));
+  TRY(upload_int(&P.pt_col, pt_col));
+  TRY(upload_int(&P.pt_m3, pt_m3));
+  TRY(upload_int(&P.ext_m1, ext));
+  // twiddles
+  FftAxis* axes[3] = {&P.ax1, &P.ax2, &P.ax3};
+  for (FftAxis* ax : axes) {
+    std::vector<cplx> tw;
+    fft_host_twiddles(ax->n, &tw);
+    cplx* dtw = nullptr;
+    TRY(dalloc(h, &dtw, tw.size()));
+    if (hipMemcpy(dtw, tw.data(), tw.size() * sizeof(cplx), hipMemcpyHostToDevice) != hipSuccess)
+      TRY(fail(ctx, PW_ERR_HIP, "twiddle upload failed"));
+    ax->tw = dtw;
+  }
+  if (!fft_choose_config(P, ctx->lds_limit, &h->cfg)) {
+    free_ham(h);
+    delete h;
+    return fail(ctx, PW_ERR_UNSUPPORTED,
+                "the plane working set (extent x N2) does not fit this GPU's LDS");
+  }
+  hipStream_t s = ctx->stream;
+  // kinetic energies from the Miller indices
+  {
+    int* dm = nullptr;
+    std::vector<int> mil(d->miller, d->miller + 3 * npw);
+    TRY(upload_int(&dm, mil));
+    TRY(dalloc(h, &h->kin, (size_t)npw));
+    HIPCHK(ctx, launch_kinetic(npw, dm, d->recip, d->kpt, h->kin, s));
+  }
+  // V scaled by 1/N_box; maxima for the spectral bound
+  const int64_t nbox = (int64_t)P.n1 * P.n2 * P.n3;
+  TRY(dalloc(h, &h->vscaled, (size_t)nbox));
+  double* dmax = nullptr;
+  TRY(dalloc(h, &dmax, 2));
+  HIPCHK(ctx, launch_max_reduce(nbox, d->vloc_dev, dmax, s));
+  HIPCHK(ctx, launch_max_reduce(npw, h->kin, dmax + 1, s));
+  HIPCHK(ctx, launch_scale_copy(nbox, d->vloc_dev, 1.0 / (double)nbox, h->vscaled, s));
+  {
+    int* flag = nullptr;
+    TRY(dalloc(h, &flag, 1));
+    HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int), s));
+    HIPCHK(ctx, launch_check_finite(nbox, d->vloc_dev, flag, s));
+    int hflag = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    double hm[2];
+    HIPCHK(ctx, hipMemcpyAsync(hm, dmax, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (hflag) TRY(fail(ctx, PW_ERR_NONFINITE, "vloc contains NaN or Inf"));
+    h->vmax = hm[0];
+    h->kmax = hm[1];
+  }
+  // projectors
+  h->proj = static_cast<const cplx*>(d->proj_dev);
+  if (h->nproj > 0) {
+    h->ekb.assign(d->ekb, d->ekb + h->nproj);
+    TRY(dalloc(h, &h->ekb_dev, (size_t)h->nproj));
+    HIPCHK(ctx, hipMemcpy(h->ekb_dev, h->ekb.data(), h->nproj * sizeof(double),
+                          hipMemcpyHostToDevice));
+  }
+  // workspaces
+  const size_t per_band = (size_t)P.n3 * P.ncols;
+  const size_t budget = (size_t)512 << 20;
+  h->chunk = std::max<int64_t>(1, std::min<int64_t>(h->nb_max, budget / (per_band * sizeof(cplx))));
+  TRY(dalloc(h, &h->T, per_band * h->chunk));
+  if (h->nproj > 0) TRY(dalloc(h, &h->cprj, (size_t)(h->nproj * h->nb_max)));
+  size_t wmax = 0;
+  for (int64_t nb = 1; nb <= h->nb_max; ++nb) {
+    if (h->nproj > 0) wmax = std::max(wmax, gemm_cn_work_elems(h->nproj, nb, npw));
+    wmax = std::max(wmax, gemm_cn_work_elems(nb, nb, npw));
+  }
+  TRY(dalloc(h, &h->gemm_work, std::max<size_t>(wmax, 1)));
+  TRY(dalloc(h, &h->blk, (size_t)(npw * h->nb_max)));
+  TRY(dalloc(h, &h->sub0, (size_t)(h->nb_max * h->nb_max)));
+  TRY(dalloc(h, &h->sub1, (size_t)(h->nb_max * h->nb_max)));
+  {
+    char* hw = nullptr;
+    TRY(dalloc(h, &hw, heev_work_bytes(h->nb_max)));
+    h->heev_work = hw;
+  }
+  TRY(dalloc(h, &h->status_dev, 16));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+#undef TRY
+  *out = h;
+  return PW_OK;
+}
+
+pw_status pw_ham_destroy(pw_ham* h) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  (void)hipSetDevice(h->ctx->device);
+  (void)hipStreamSynchronize(h->ctx->stream);
+  free_ham(h);
+  delete h;
+  return PW_OK;
+}
+
+pw_status pw_ham_info(const pw_ham* h, int64_t* npw, int64_t* nproj, int64_t* nb_max,
+                      int64_t* ncolumns, int64_t* extent1) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  if (npw) *npw = h->npw;
+  if (nproj) *nproj = h->nproj;
+  if (nb_max) *nb_max = h->nb_max;
+  if (ncolumns) *ncolumns = h->plan.ncols;
+  if (extent1) *extent1 = h->plan.xr;
+  return PW_OK;
+}
+
+pw_status pw_apply_h(pw_ham* h, pw_prec prec, int64_t nb, const void* psi, int64_t ldpsi,
+                     void* hpsi, int64_t ldh) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  pw_status st;
+  if ((st = check_hot(h, prec, nb)) != PW_OK) return st;
+  if ((st = check_block(h, psi, ldpsi, "psi")) != PW_OK) return st;
+  if ((st = check_block(h, hpsi, ldh, "hpsi")) != PW_OK) return st;
+  if (ranges_overlap(psi, ldpsi, hpsi, ldh, h->npw, nb))
+    return fail(h->ctx, PW_ERR_INVALID_ARG, "psi and hpsi overlap");
+  HIPCHK(h->ctx, hipSetDevice(h->ctx->device));
+  return ham_apply(h, nb, static_cast<const cplx*>(psi), ldpsi, static_cast<cplx*>(hpsi), ldh, 1.0,
+                   0.0, 0.0, nullptr, 0);
+}
+
+pw_status pw_cheb_filter(pw_ham* h, pw_prec prec, int32_t degree, double a, double b, double a0,
+                         int64_t nb, void* yv, int64_t ld, const void* hxv, int64_t ldhx) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  pw_status st;
+  if ((st = check_hot(h, prec, nb)) != PW_OK) return st;
+  if ((st = check_block(h, yv, ld, "y")) != PW_OK) return st;
+  if (hxv && (st = check_block(h, hxv, ldhx, "hx")) != PW_OK) return st;
+  if (degree < 1) return fail(h->ctx, PW_ERR_INVALID_ARG, "degree must be >= 1");
+  if (!(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0)) || !(a0 < a && a < b))
+    return fail(h->ctx, PW_ERR_INVALID_ARG, "filter bounds must satisfy a0 < a < b (finite)");
+  HIPCHK(h->ctx, hipSetDevice(h->ctx->device));
+  cplx* y = static_cast<cplx*>(yv);
+  const cplx* hx = static_cast<const cplx*>(hxv);
+  const double e = 0.5 * (b - a), c = 0.5 * (b + a);
+  double sigma = e / (a0 - c);
+  const double tau = 2.0 / sigma;
+  // Y0 lives in y, Y1 in blk; Y_i overwrites Y_{i-2} (y for even i, blk for odd i).
+  cplx* buf[2] = {y, h->blk};
+  int64_t lds[2] = {ld, h->npw};
+  if (hx) {
+    StageScope sc(h->ctx, PW_STAGE_MISC);
+    HIPCHK(h->ctx, launch_axpby_block(h->npw, nb, sigma / e, hx, ldhx, -sigma * c / e, y, ld, h->blk,
+                                      h->npw, h->ctx->stream));
+  } else {
+    if ((st = ham_apply(h, nb, y, ld, h->blk, h->npw, sigma / e, -sigma * c / e, 0.0, nullptr, 0)) !=
+        PW_OK)
+      return st;
+  }
+  for (int i = 2; i <= degree; ++i) {
+    const double sn = 1.0 / (tau - sigma);
+    const int cur = (i - 1) & 1, nxt = i & 1;
+    const double al = 2.0 * sn / e;
+    if ((st = ham_apply(h, nb, buf[cur], lds[cur], buf[nxt], lds[nxt], al, -al * c, -sigma * sn,
+                        buf[nxt], lds[nxt])) != PW_OK)
+      return st;
+    sigma = sn;
+  }
+  if (degree & 1) {
+    StageScope sc(h->ctx, PW_STAGE_MISC);
+    HIPCHK(h->ctx, launch_copy_block(h->npw, nb, h->blk, h->npw, y, ld, h->ctx->stream));
+  }
+  return PW_OK;
+}
+
+pw_status pw_orthonormalize(pw_ham* h, pw_prec gram_prec, int64_t nb, void* yv, int64_t ld,
+                            void* hyv, int64_t ldhy) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  pw_status st;
+  if ((st = check_hot(h, gram_prec, nb)) != PW_OK) return st;
+  if ((st = check_block(h, yv, ld, "y")) != PW_OK) return st;
+  if (hyv && (st = check_block(h, hyv, ldhy, "hy")) != PW_OK) return st;
+  pw_ctx* c = h->ctx;
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  cplx* y = static_cast<cplx*>(yv);
+  {
+    StageScope sc(c, PW_STAGE_GRAM);
+    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, y, ld, h->sub0, nb, nullptr, h->gemm_work, s));
+    HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_CHOL);
+    HIPCHK(c, launch_potrf_inv(nb, h->sub0, nb, h->sub1, nb, h->status_dev, s));
+  }
+  int status = 0;
+  HIPCHK(c, hipMemcpyAsync(&status, h->status_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (status >= 0)
+    return fail(c, PW_ERR_NOT_POSDEF,
+                "Gram matrix not positive definite at pivot " + std::to_string(status));
+  if ((st = rotate_block(h, nb, y, ld, h->sub1)) != PW_OK) return st;
+  if (hyv && (st = rotate_block(h, nb, static_cast<cplx*>(hyv), ldhy, h->sub1)) != PW_OK) return st;
+  return PW_OK;
+}
+
+pw_status pw_rayleigh_ritz(pw_ham* h, int64_t nb, void* yv, int64_t ld, void* hyv, int64_t ldhy,
+                           double* eig, double* resid) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  pw_status st;
+  if ((st = check_hot(h, PW_FP64, nb)) != PW_OK) return st;
+  if ((st = check_block(h, yv, ld, "y")) != PW_OK) return st;
+  if ((st = check_block(h, hyv, ldhy, "hy")) != PW_OK) return st;
+  if (!eig) return fail(h->ctx, PW_ERR_INVALID_ARG, "eig_dev is NULL");
+  if (ranges_overlap(yv, ld, hyv, ldhy, h->npw, nb))
+    return fail(h->ctx, PW_ERR_INVALID_ARG, "y and hy overlap");
+  pw_ctx* c = h->ctx;
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  cplx* y = static_cast<cplx*>(yv);
+  cplx* hy = static_cast<cplx*>(hyv);
+  if ((st = ham_apply(h, nb, y, ld, hy, ldhy, 1.0, 0.0, 0.0, nullptr, 0)) != PW_OK) return st;
+  {
+    StageScope sc(c, PW_STAGE_GRAM);
+    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, hy, ldhy, h->sub0, nb, nullptr,
+                             h->gemm_work, s));
+    HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
+  }
+  int sweeps = 0;
+  {
+    StageScope sc(c, PW_STAGE_EIGH);
+    HIPCHK(c, launch_heev(nb, h->sub0, nb, eig, h->sub1, nb, h->heev_work, c->pinned, &sweeps, s));
+  }
+  if ((st = heev_status(c, sweeps)) != PW_OK) return st;
+  if ((st = rotate_block(h, nb, y, ld, h->sub1)) != PW_OK) return st;
+  if ((st = rotate_block(h, nb, hy, ldhy, h->sub1)) != PW_OK) return st;
+  if (resid) {
+    StageScope sc(c, PW_STAGE_MISC);
+    HIPCHK(c, launch_residuals(h->npw, nb, hy, ldhy, y, ld, eig, resid, s));
+  }
+  return PW_OK;
+}
+
+pw_status pw_upper_bound(pw_ham* h, double* b_host) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  if (!b_host) return fail(h->ctx, PW_ERR_INVALID_ARG, "b_host is NULL");
+  pw_ctx* c = h->ctx;
+  HIPCHK(c, hipSetDevice(c->device));
+  double b = h->kmax + h->vmax;
+  if (h->nproj > 0) {
+    const int64_t m = h->nproj;
+    pw_ham tmp;   // scratch owner for the allocations of this call
+    tmp.ctx = c;
+    cplx* M = nullptr;
+    cplx* Q = nullptr;
+    cplx* work = nullptr;
+    double* w = nullptr;
+    double* sq = nullptr;
+    char* hw = nullptr;
+    pw_status st = PW_OK;
+    if ((st = dalloc(&tmp, &M, (size_t)(m * m))) != PW_OK ||
+        (st = dalloc(&tmp, &Q, (size_t)(m * m))) != PW_OK ||
+        (st = dalloc(&tmp, &work, std::max<size_t>(1, gemm_cn_work_elems(m, m, h->npw)))) != PW_OK ||
+        (st = dalloc(&tmp, &w, (size_t)m)) != PW_OK || (st = dalloc(&tmp, &sq, (size_t)m)) != PW_OK ||
+        (st = dalloc(&tmp, &hw, heev_work_bytes(m))) != PW_OK) {
+      free_ham(&tmp);
+      return st;
+    }
+    std::vector<double> sqh(m);
+    for (int64_t j = 0; j < m; ++j) sqh[j] = std::sqrt(std::max(h->ekb[j], 0.0));
+    hipStream_t s = c->stream;
+    hipError_t e = hipMemcpy(sq, sqh.data(), m * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_gemm_cn(m, m, h->npw, 1.0, h->proj, h->npw, h->proj, h->npw, M, m, nullptr, work, s);
+    if (e == hipSuccess) e = launch_scale_rows_cols(m, sq, M, m, s);
+    if (e == hipSuccess) e = launch_hermitize(m, M, m, s);
+    int sweeps = 0;
+    if (e == hipSuccess) e = launch_heev(m, M, m, w, Q, m, hw, c->pinned, &sweeps, s);
+    double wmax = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&wmax, w + (m - 1), sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    free_ham(&tmp);
+    if (e != hipSuccess) return fail(c, PW_ERR_HIP, hipGetErrorString(e));
+    if ((st = heev_status(c, sweeps)) != PW_OK) return st;
+    b += std::max(wmax, 0.0);
+  }
+  *b_host = b;
+  return PW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// dense building blocks
+// ---------------------------------------------------------------------------
+pw_status pw_gemm_cn(pw_ctx* c, int64_t m, int64_t n, int64_t k, double alpha, const void* a,
+                     int64_t lda, const void* bm, int64_t ldb, void* cm, int64_t ldc) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (m < 0 || n < 0 || k < 0 || !a || !bm || !cm || lda < std::max<int64_t>(k, 1) ||
+      ldb < std::max<int64_t>(k, 1) || ldc < std::max<int64_t>(m, 1))
+    return fail(c, PW_ERR_INVALID_ARG, "pw_gemm_cn: bad sizes or pointers");
+  HIPCHK(c, hipSetDevice(c->device));
+  pw_ham tmp;
+  tmp.ctx = c;
+  cplx* work = nullptr;
+  pw_status st = dalloc(&tmp, &work, std::max<size_t>(1, gemm_cn_work_elems(m, n, k)));
+  if (st != PW_OK) return st;
+  hipError_t e = launch_gemm_cn(m, n, k, alpha, static_cast<const cplx*>(a), lda,
+                                static_cast<const cplx*>(bm), ldb, static_cast<cplx*>(cm), ldc,
+                                nullptr, work, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  free_ham(&tmp);
+  if (e != hipSuccess) return fail(c, PW_ERR_HIP, hipGetErrorString(e));
+  return PW_OK;
+}
+
+pw_status pw_gemm_nn(pw_ctx* c, int64_t m, int64_t n, int64_t k, double alpha, const void* a,
+                     int64_t lda, const void* bm, int64_t ldb, double beta, void* cm, int64_t ldc) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (m < 0 || n < 0 || k < 0 || !a || !bm || !cm || lda < std::max<int64_t>(m, 1) ||
+      ldb < std::max<int64_t>(k, 1) || ldc < std::max<int64_t>(m, 1))
+    return fail(c, PW_ERR_INVALID_ARG, "pw_gemm_nn: bad sizes or pointers");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, launch_gemm_nn(m, n, k, alpha, static_cast<const cplx*>(a), lda,
+                           static_cast<const cplx*>(bm), ldb, beta, static_cast<cplx*>(cm), ldc,
+                           c->stream));
+  return PW_OK;
+}
+
+pw_status pw_heev(pw_ctx* c, int64_t n, void* a, int64_t lda, double* w, void* q, int64_t ldq) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (n < 1 || n > 4096 || !a || !w || !q || lda < n || ldq < n)
+    return fail(c, PW_ERR_INVALID_ARG, "pw_heev: bad sizes or pointers");
+  HIPCHK(c, hipSetDevice(c->device));
+  pw_ham tmp;
+  tmp.ctx = c;
+  char* hw = nullptr;
+  pw_status st = dalloc(&tmp, &hw, heev_work_bytes(n));
+  if (st != PW_OK) return st;
+  int sweeps = 0;
+  hipError_t e = launch_heev(n, static_cast<cplx*>(a), lda, w, static_cast<cplx*>(q), ldq, hw,
+                             c->pinned, &sweeps, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  free_ham(&tmp);
+  if (e != hipSuccess) return fail(c, PW_ERR_HIP, hipGetErrorString(e));
+  return heev_status(c, sweeps);
+}
+
+pw_status pw_potrf_inv(pw_ctx* c, int64_t n, void* a, int64_t lda, void* ainv, int64_t ldi) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (n < 1 || n > 4096 || !a || !ainv || lda < n || ldi < n)
+    return fail(c, PW_ERR_INVALID_ARG, "pw_potrf_inv: bad sizes or pointers");
+  HIPCHK(c, hipSetDevice(c->device));
+  pw_ham tmp;
+  tmp.ctx = c;
+  int* stat = nullptr;
+  pw_status st = dalloc(&tmp, &stat, 1);
+  if (st != PW_OK) return st;
+  hipError_t e = launch_potrf_inv(n, static_cast<cplx*>(a), lda, static_cast<cplx*>(ainv), ldi,
+                                  stat, c->stream);
+  int hs = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hs, stat, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  free_ham(&tmp);
+  if (e != hipSuccess) return fail(c, PW_ERR_HIP, hipGetErrorString(e));
+  if (hs >= 0) return fail(c, PW_ERR_NOT_POSDEF, "matrix not positive definite at pivot " + std::to_string(hs));
+  return PW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stage timing
+// ---------------------------------------------------------------------------
+pw_status pw_ctx_set_timing(pw_ctx* c, int enable) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  c->timing = enable != 0;
+  return PW_OK;
+}
+
+static pw_status resolve_timing(pw_ctx* c) {
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->acc_ms[p.stage] += ms;
+      c->launches[p.stage] += 1;
+    }
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+  return PW_OK;
+}
+
+pw_status pw_ctx_stage_time(pw_ctx* c, int stage, double* total_ms, int64_t* launches) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (stage < 0 || stage >= PW_STAGE_COUNT) return fail(c, PW_ERR_INVALID_ARG, "bad stage");
+  pw_status st = resolve_timing(c);
+  if (st != PW_OK) return st;
+  if (total_ms) *total_ms = c->acc_ms[stage];
+  if (launches) *launches = c->launches[stage];
+  return PW_OK;
+}
+
+pw_status pw_ctx_reset_timing(pw_ctx* c) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  pw_status st = resolve_timing(c);
+  if (st != PW_OK) return st;
+  for (int i = 0; i < PW_STAGE_COUNT; ++i) {
+    c->acc_ms[i] = 0.0;
+    c->launches[i] = 0;
+  }
+  return PW_OK;
+}
+
+}  // extern "C"

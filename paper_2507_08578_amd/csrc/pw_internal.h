@@ -1,0 +1,113 @@
+// Internal declarations of libpwdft (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pw.h"
+
+typedef double2 cplx;   // interleaved (re, im), 16 bytes
+
+// ---------------------------------------------------------------------------
+// FFT plan along one axis: N = product of radices, each in {2, 3, 4, 5, 8}.
+// ---------------------------------------------------------------------------
+constexpr int kMaxPasses = 8;
+struct FftAxis {
+  int n;                    // transform length
+  int npass;                // number of radix passes
+  int radix[kMaxPasses];    // radix of each pass, first pass first
+  const cplx* tw;           // device table, tw[t] = exp(-2 pi i t / n), t < n
+};
+
+// Sphere <-> box maps, all device arrays, built once per pw_ham.
+struct BoxPlan {
+  int n1, n2, n3;
+  int64_t npw;
+  int ncols;                // distinct (m1, m2) among sphere points ("columns" along N3)
+  int xr;                   // distinct m1 among sphere points (extent along N1)
+  // columns ordered by (n1, n2) of the Miller indices; column c holds the
+  // points perm[col_start[c] .. col_start[c+1]) (indices into the caller's order)
+  int* col_start;           // ncols + 1
+  int* col_e;               // extent slot e in [0, xr) of the column's m1
+  int* col_m2;              // box index m2 of the column
+  int* pt_perm;             // npw: caller index of the k-th point in column order
+  int* pt_col;              // npw: column of the k-th point (column order)
+  int* pt_m3;               // npw: box index m3 of the k-th point (column order)
+  int* ext_m1;              // xr: box index m1 of extent slot e
+  FftAxis ax1, ax2, ax3;
+};
+
+// ---------------------------------------------------------------------------
+// Launch helpers (defined in the .hip files), all enqueue on `s`.
+// ---------------------------------------------------------------------------
+struct FftLaunchCfg {
+  int col_tile;             // columns per workgroup of the N3 kernels
+  int plane_rows;           // rows per batch in the plane kernel
+  size_t col_lds, plane_lds;
+};
+
+// Host-side choice of tiles and LDS sizes; returns false if this GPU's LDS
+// cannot hold the plane kernel's working set.
+bool fft_choose_config(const BoxPlan& p, size_t lds_limit, FftLaunchCfg* cfg);
+// Build the twiddle table of an axis on the host (exact angle reduction).
+void fft_host_twiddles(int n, std::vector<cplx>* out);
+// Factor n into passes; false if unsupported.
+bool fft_factor(int n, FftAxis* ax);
+
+// psi block (nb bands from band0) -> T[b][j3][c], backward along N3.
+hipError_t launch_fft_col_inv(const BoxPlan& p, const FftLaunchCfg& cfg, int nb,
+                              const cplx* psi, int64_t ldpsi, cplx* T, hipStream_t s);
+// per (band, plane): N2 backward, N1 backward, x V, N1 forward, N2 forward, in place on T.
+hipError_t launch_fft_plane(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const double* vscaled,
+                            cplx* T, hipStream_t s);
+// forward along N3 and gather, with the epilogue
+// out = alpha*(loc + kin*in) + beta*in + gamma*prev   (prev may alias out; may be null if gamma==0)
+hipError_t launch_fft_col_fwd(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const cplx* T,
+                              const double* kin, const cplx* in, int64_t ldin, const cplx* prev,
+                              int64_t ldprev, cplx* out, int64_t ldout, double alpha, double beta,
+                              double gamma, hipStream_t s);
+
+// Allow `bytes` of dynamic LDS for the FFT kernels (above the default cap).
+hipError_t fft_set_lds_limits(size_t bytes);
+
+// Split-K C = alpha * A^H B (see pw_gemm_cn).  `work` holds splits*m*n cplx;
+// rowscale (m doubles on device, may be null) multiplies row i of the result.
+size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k);
+hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
+                          const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
+                          cplx* work, hipStream_t s);
+hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
+                          const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
+                          hipStream_t s);
+
+// Dense kernels (dense_kernels.hip)
+// kin[g] = 1/2 |(n_g + k) B|^2 from device Miller indices; recip9/k3 are host values.
+hipError_t launch_kinetic(int64_t npw, const int* miller, const double* recip9, const double* k3,
+                          double* kin, hipStream_t s);
+hipError_t launch_scale_copy(int64_t n, const double* src, double scale, double* dst, hipStream_t s);
+hipError_t launch_max_reduce(int64_t n, const double* x, double* out1, hipStream_t s);
+hipError_t launch_hermitize(int64_t n, cplx* a, int64_t lda, hipStream_t s);
+hipError_t launch_copy_block(int64_t rows, int64_t cols, const cplx* src, int64_t lds, cplx* dst,
+                             int64_t ldd, hipStream_t s);
+hipError_t launch_scale_rows_cols(int64_t n, const double* d, cplx* a, int64_t lda, hipStream_t s);
+// out = a*x + b*y for npw x nb blocks (out may alias y)
+hipError_t launch_axpby_block(int64_t npw, int64_t nb, double a, const cplx* x, int64_t ldx, double b,
+                              const cplx* y, int64_t ldy, cplx* out, int64_t ldo, hipStream_t s);
+// status: 0 if every element finite, else 1
+hipError_t launch_check_finite(int64_t n, const double* x, int* flag, hipStream_t s);
+// upper Cholesky + inverse, status[0] = -1 on success else failing pivot index
+hipError_t launch_potrf_inv(int64_t n, cplx* a, int64_t lda, cplx* ainv, int64_t ldi, int* status,
+                            hipStream_t s);
+// Cyclic Jacobi eigensolver of a Hermitian n x n matrix (a is destroyed):
+// w ascending, q = eigenvectors.  work: heev_work_bytes(n) device bytes;
+// host_scratch: >= 4 doubles of pinned host memory.  Synchronises the stream
+// once per sweep.  *sweeps_done = sweeps used, or -1 if not converged.
+size_t heev_work_bytes(int64_t n);
+hipError_t heev_set_lds_limit(size_t bytes);
+hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int64_t ldq, void* work,
+                       double* host_scratch, int* sweeps_done, hipStream_t s);
+hipError_t launch_residuals(int64_t npw, int64_t nb, const cplx* W, int64_t ldw, const cplx* Y,
+                            int64_t ldy, const double* lam, double* resid, hipStream_t s);
