@@ -9,5 +9,5 @@ and the GPU library receive its arrays as inputs.
 from .cells import (  # noqa: F401
     Cell, Workload, diamond_cell, make_workload, sphere_miller, box_rule,
     local_potential, kb_projectors, start_block, kpoint_grid_shifted,
-    config_c1, config_c2, config_c3, config_c4, config_c5, CONFIGS,
+    config_c1, config_c2, config_c3, config_c4, config_c5, c4_cell_params, CONFIGS,
 )
