@@ -1,0 +1,289 @@
+// Device-side building blocks of the FFT kernels: complex helpers, small
+// DFTs in registers (radix 2, 3, 4, 5, 8 and their products), compile-time
+// twiddles, and transforms spread over a group of G lanes of one wavefront.
+#pragma once
+
+#include "pw_internal.h"
+
+namespace pwfft {
+
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
+// (S i) z for S = +1 / -1
+template <int S>
+__device__ __forceinline__ cplx mul_si(cplx z) {
+  return S > 0 ? make_double2(-z.y, z.x) : make_double2(z.y, -z.x);
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time exp(-2 pi i t / n): octant reduction in exact integer
+// arithmetic, then Taylor series on [0, pi/4].
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr double cx_sin_poly(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / (double)((2 * k) * (2 * k + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos_poly(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / (double)((2 * k - 1) * (2 * k));
+    sum += term;
+  }
+  return sum;
+}
+struct CW {
+  double re, im;
+};
+// exp(-2 pi i t / n)
+constexpr CW cx_tw(long t, long n) {
+  t %= n;
+  if (t < 0) t += n;
+  const long e8 = 8 * t;
+  const long oct = e8 / n;
+  const long rem = e8 - oct * n;
+  const bool odd = (oct & 1) != 0;
+  const double frac = odd ? (double)(n - rem) / (double)n : (double)rem / (double)n;
+  const double th = frac * kPi / 4.0;
+  const double ct = cx_cos_poly(th), st = cx_sin_poly(th);
+  double c = 0.0, s = 0.0;
+  switch (oct) {
+    case 0: c = ct; s = st; break;
+    case 1: c = st; s = ct; break;
+    case 2: c = -st; s = ct; break;
+    case 3: c = -ct; s = st; break;
+    case 4: c = -ct; s = -st; break;
+    case 5: c = -st; s = -ct; break;
+    case 6: c = st; s = -ct; break;
+    default: c = ct; s = -st; break;
+  }
+  return CW{c, -s};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs y_k = sum_n x_n exp(S 2 pi i n k / R) in registers.
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ __forceinline__ void dft2(cplx* v) {
+  cplx a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <int S>
+__device__ __forceinline__ void dft3(cplx* v) {
+  const double h = 0.86602540378443864676;  // sin(2 pi / 3)
+  cplx s = cadd(v[1], v[2]);
+  cplx d = csub(v[1], v[2]);
+  cplx t = make_double2(v[0].x - 0.5 * s.x, v[0].y - 0.5 * s.y);
+  cplx r = mul_si<S>(cscale(d, h));
+  v[0] = cadd(v[0], s);
+  v[1] = cadd(t, r);
+  v[2] = csub(t, r);
+}
+template <int S>
+__device__ __forceinline__ void dft4(cplx* v) {
+  cplx a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  cplx c = cadd(v[1], v[3]), d = mul_si<S>(csub(v[1], v[3]));
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+template <int S>
+__device__ __forceinline__ void dft5(cplx* v) {
+  const double c1 = 0.30901699437494742410;   // cos(2 pi/5)
+  const double c2 = -0.80901699437494742410;  // cos(4 pi/5)
+  const double s1 = 0.95105651629515357212;   // sin(2 pi/5)
+  const double s2 = 0.58778525229247312917;   // sin(4 pi/5)
+  cplx a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+  cplx a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+  cplx x0 = v[0];
+  cplx p1 = make_double2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+  cplx p2 = make_double2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+  cplx q1 = mul_si<S>(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+  cplx q2 = mul_si<S>(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+  v[0] = make_double2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+  v[1] = cadd(p1, q1);
+  v[4] = csub(p1, q1);
+  v[2] = cadd(p2, q2);
+  v[3] = csub(p2, q2);
+}
+template <int S>
+__device__ __forceinline__ void dft8(cplx* v) {
+  const double h = 0.70710678118654752440;  // sqrt(2)/2
+  cplx e[4] = {v[0], v[2], v[4], v[6]};
+  cplx o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<S>(e);
+  dft4<S>(o);
+  cplx o1 = make_double2(h * (o[1].x - S * o[1].y), h * (o[1].y + S * o[1].x));
+  cplx o2 = mul_si<S>(o[2]);
+  cplx o3 = make_double2(h * (-o[3].x - S * o[3].y), h * (-o[3].y + S * o[3].x));
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+template <int R, int S>
+__device__ __forceinline__ void dft_base(cplx* v) {
+  if constexpr (R == 2) dft2<S>(v);
+  else if constexpr (R == 3) dft3<S>(v);
+  else if constexpr (R == 4) dft4<S>(v);
+  else if constexpr (R == 5) dft5<S>(v);
+  else dft8<S>(v);
+}
+
+template <int R>
+struct Split {
+  static constexpr int P = (R % 4 == 0) ? 4 : (R % 2 == 0) ? 2 : (R % 3 == 0) ? 3 : 5;
+  static constexpr int Q = R / P;
+};
+
+// R-point DFT in registers for R a product of 2, 3, 5 (mixed-radix
+// Cooley-Tukey, n = Q a + b, k = k1 + P k2, compile-time twiddles).
+template <int R, int S>
+__device__ __forceinline__ void dft_reg(cplx* v) {
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2 || R == 3 || R == 4 || R == 5 || R == 8) {
+    dft_base<R, S>(v);
+  } else {
+    constexpr int P = Split<R>::P, Q = Split<R>::Q;
+    cplx y[Q][P];
+#pragma unroll
+    for (int b = 0; b < Q; ++b) {
+      cplx u[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) u[a] = v[Q * a + b];
+      dft_reg<P, S>(u);
+#pragma unroll
+      for (int k1 = 0; k1 < P; ++k1) {
+        if (b * k1 == 0) {
+          y[b][k1] = u[k1];
+        } else {
+          const CW w = cx_tw(b * k1, R);           // exp(-2 pi i b k1 / R)
+          y[b][k1] = cmul(u[k1], make_double2(w.re, S > 0 ? -w.im : w.im));
+        }
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+      cplx w[Q];
+#pragma unroll
+      for (int b = 0; b < Q; ++b) w[b] = y[b][k1];
+      dft_reg<Q, S>(w);
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) v[k1 + P * k2] = w[k2];
+    }
+  }
+}
+
+__device__ __forceinline__ cplx shfl_xor(cplx v, int m) {
+  return make_double2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+}
+
+// Bit reversal of b in log2(G) bits.
+template <int G>
+__device__ __forceinline__ int brev(int b) {
+  if constexpr (G == 1) {
+    return 0;
+  } else {
+    constexpr int bits = __builtin_ctz(G);
+    return (int)(__brev((unsigned)b) >> (32 - bits));
+  }
+}
+
+// Per-lane twiddles of a length-N = G R transform for lane b of its group,
+// loaded once and shared by both directions (all exp(-2 pi i t/N) values):
+//   k[q-1] = exp(-2 pi i b q / N), q = 1..R-1      (between registers and lanes)
+//   st[s]  = exp(-2 pi i (b mod h) / (2h)), h = 2^s (cross-lane stage of span h)
+template <int R, int G>
+struct LaneTw {
+  static constexpr int kStages = (G > 1) ? __builtin_ctz(G) : 1;
+  cplx k[R > 1 ? R - 1 : 1];
+  cplx st[kStages];
+  __device__ __forceinline__ void load(int b, const cplx* __restrict__ tw) {
+    constexpr int N = R * G;
+    if constexpr (G > 1) {
+#pragma unroll
+      for (int q = 1; q < R; ++q) k[q - 1] = tw[b * q];
+#pragma unroll
+      for (int s = 0; s < kStages; ++s) {
+        const int h = 1 << s;
+        st[s] = tw[(b & (h - 1)) * (N / (2 * h))];
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ cplx conj_mul(cplx a, cplx w) {   // a * conj(w)
+  return make_double2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
+}
+
+// Transform of length N = G R spread over a group of G lanes (lane b, local
+// index in its group), R values per lane.
+//
+// backward (+):  in : v[a]  = x[G a + b]
+//                out: v[k1] = X[k1 + R brev(b)]
+// forward  (-):  in : v[k1] = Z[k1 + R brev(b)]    (the backward's layout)
+//                out: v[a]  = X'[G a + b]
+// The forward is the exact adjoint of the backward, stage by stage.
+template <int R, int G>
+__device__ __forceinline__ void lane_fft_bwd(cplx* v, int b, const LaneTw<R, G>& t) {
+  dft_reg<R, +1>(v);
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int k1 = 1; k1 < R; ++k1) v[k1] = conj_mul(v[k1], t.k[k1 - 1]);   // exp(+2 pi i b k1/N)
+#pragma unroll
+    for (int s = LaneTw<R, G>::kStages - 1; s >= 0; --s) {
+      const int h = 1 << s;
+      const bool up = (b & h) != 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const cplx p = shfl_xor(v[r], h);
+        v[r] = up ? conj_mul(csub(p, v[r]), t.st[s]) : cadd(v[r], p);
+      }
+    }
+  }
+}
+
+template <int R, int G>
+__device__ __forceinline__ void lane_fft_fwd(cplx* v, int b, const LaneTw<R, G>& t) {
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int s = 0; s < LaneTw<R, G>::kStages; ++s) {
+      const int h = 1 << s;
+      const bool up = (b & h) != 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const cplx p = shfl_xor(v[r], h);
+        v[r] = up ? csub(p, cmul(t.st[s], v[r])) : cadd(v[r], cmul(t.st[s], p));
+      }
+    }
+#pragma unroll
+    for (int k1 = 1; k1 < R; ++k1) v[k1] = cmul(v[k1], t.k[k1 - 1]);       // exp(-2 pi i b k1/N)
+  }
+  dft_reg<R, -1>(v);
+}
+
+// Lane-group shape used for a length-N transform: G a power of two <= 16,
+// as large as possible with R = N / G >= 3.
+constexpr int lane_group(int n) {
+  int g = 1;
+  while (g < 16 && n % (2 * g) == 0 && n / (2 * g) >= 3) g *= 2;
+  return g;
+}
+
+}  // namespace pwfft

@@ -386,11 +386,14 @@ bool fft_choose_config(const BoxPlan& p, size_t lds_limit, FftLaunchCfg* cfg) {
   cfg->col_lds = col_lds;
   cfg->plane_rows = rb;
   cfg->plane_lds = plane_bytes(rb);
+  cfg->reg_col = fft_reg_col_supported(p.n3);
+  cfg->reg_plane = fft_reg_plane_supported(p, lds_limit);
   return true;
 }
 
 hipError_t launch_fft_col_inv(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const cplx* psi,
                               int64_t ldpsi, cplx* T, hipStream_t s) {
+  if (cfg.reg_col) return launch_fft_col_inv_reg(p, nb, psi, ldpsi, T, s);
   dim3 grid((p.ncols + cfg.col_tile - 1) / cfg.col_tile, nb);
   hipLaunchKernelGGL(k_col_inv, grid, dim3(kThreads), cfg.col_lds, s, plan_args(p), cfg.col_tile,
                      psi, ldpsi, T);
@@ -399,6 +402,7 @@ hipError_t launch_fft_col_inv(const BoxPlan& p, const FftLaunchCfg& cfg, int nb,
 
 hipError_t launch_fft_plane(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const double* vscaled,
                             cplx* T, hipStream_t s) {
+  if (cfg.reg_plane) return launch_fft_plane_reg(p, nb, vscaled, T, s);
   dim3 grid(p.n3, nb);
   hipLaunchKernelGGL(k_plane, grid, dim3(kThreads), cfg.plane_lds, s, plan_args(p), cfg.plane_rows,
                      vscaled, T);
@@ -409,6 +413,9 @@ hipError_t launch_fft_col_fwd(const BoxPlan& p, const FftLaunchCfg& cfg, int nb,
                               const double* kin, const cplx* in, int64_t ldin, const cplx* prev,
                               int64_t ldprev, cplx* out, int64_t ldout, double alpha, double beta,
                               double gamma, hipStream_t s) {
+  if (cfg.reg_col)
+    return launch_fft_col_fwd_reg(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, alpha, beta,
+                                  gamma, s);
   dim3 grid((p.ncols + cfg.col_tile - 1) / cfg.col_tile, nb);
   hipLaunchKernelGGL(k_col_fwd, grid, dim3(kThreads), cfg.col_lds, s, plan_args(p), cfg.col_tile, T,
                      kin, in, ldin, prev, ldprev, out, ldout, alpha, beta, gamma);

@@ -1,0 +1,278 @@
+// Register-resident variants of the three FFT-route kernels for the box
+// lengths listed in kFastSizes.  Each 1D transform of length N = G R lives
+// in the registers of G lanes of one wavefront (R values per lane): an
+// R-point DFT in registers, then log2(G) radix-2 stages across lanes with
+// wavefront shuffles (pwfft::lane_fft_bwd / lane_fft_fwd).  LDS holds only
+// the data that must change hands between axes:
+//   col kernels : a tile of columns (one column per lane group),
+//   plane kernel: the extent array E[e][m2] of one z-plane; every N2
+//                 transform and every N1 row (backward, x V/N_box, forward)
+//                 reads its input from E and writes its output back in place.
+#include "fft_common.h"
+
+#include <algorithm>
+
+using namespace pwfft;
+
+namespace {
+
+constexpr int kColThreads = 256;
+constexpr int kPlaneMaxThreads = 512;
+
+template <int N3>
+__global__ void __launch_bounds__(kColThreads)
+k_col_inv_reg(BoxPlan P, const cplx* __restrict__ psi, int64_t ldpsi, cplx* __restrict__ T) {
+  constexpr int G = lane_group(N3), R = N3 / G, CT = kColThreads / G, TRS = N3 + 1;
+  __shared__ cplx tile[CT * TRS];
+  const int c0 = blockIdx.x * CT;
+  const int b = blockIdx.y;
+  const int ncl = min(CT, P.ncols - c0);
+  for (int i = threadIdx.x; i < CT * TRS; i += blockDim.x) tile[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
+  const cplx* src = psi + (size_t)b * ldpsi;
+  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
+    tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]] = src[P.pt_perm[k]];
+  __syncthreads();
+  const int grp = threadIdx.x / G, lb = threadIdx.x % G;
+  if (grp < ncl) {
+    cplx v[R];
+    cplx* col = tile + grp * TRS;
+    LaneTw<R, G> tw;
+    tw.load(lb, P.ax3.tw);
+#pragma unroll
+    for (int a = 0; a < R; ++a) v[a] = col[G * a + lb];
+    lane_fft_bwd<R, G>(v, lb, tw);
+    const int base = R * brev<G>(lb);
+#pragma unroll
+    for (int q = 0; q < R; ++q) col[q + base] = v[q];
+  }
+  __syncthreads();
+  cplx* dst = T + (size_t)b * N3 * P.ncols + c0;
+  for (int i = threadIdx.x; i < ncl * N3; i += blockDim.x) {
+    const int j3 = i / ncl, lc = i - j3 * ncl;
+    dst[(size_t)j3 * P.ncols + lc] = tile[lc * TRS + j3];
+  }
+}
+
+template <int N3>
+__global__ void __launch_bounds__(kColThreads)
+k_col_fwd_reg(BoxPlan P, const cplx* __restrict__ T, const double* __restrict__ kin,
+              const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev, cplx* out,
+              int64_t ldout, double alpha, double beta, double gamma) {
+  constexpr int G = lane_group(N3), R = N3 / G, CT = kColThreads / G, TRS = N3 + 1;
+  __shared__ cplx tile[CT * TRS];
+  const int c0 = blockIdx.x * CT;
+  const int b = blockIdx.y;
+  const int ncl = min(CT, P.ncols - c0);
+  const cplx* srcT = T + (size_t)b * N3 * P.ncols + c0;
+  for (int i = threadIdx.x; i < ncl * N3; i += blockDim.x) {
+    const int j3 = i / ncl, lc = i - j3 * ncl;
+    tile[lc * TRS + j3] = srcT[(size_t)j3 * P.ncols + lc];
+  }
+  __syncthreads();
+  const int grp = threadIdx.x / G, lb = threadIdx.x % G;
+  if (grp < ncl) {
+    cplx v[R];
+    cplx* col = tile + grp * TRS;
+    const int base = R * brev<G>(lb);
+    LaneTw<R, G> tw;
+    tw.load(lb, P.ax3.tw);
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = col[q + base];
+    lane_fft_fwd<R, G>(v, lb, tw);
+#pragma unroll
+    for (int a = 0; a < R; ++a) col[G * a + lb] = v[a];
+  }
+  __syncthreads();
+  const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
+  const cplx* inb = in + (size_t)b * ldin;
+  cplx* outb = out + (size_t)b * ldout;
+  const cplx* prevb = prev ? prev + (size_t)b * ldprev : nullptr;
+  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    const int g = P.pt_perm[k];
+    const cplx loc = tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]];
+    const cplx x = inb[g];
+    const double t = kin[g];
+    cplx val = make_double2(alpha * (loc.x + t * x.x) + beta * x.x,
+                            alpha * (loc.y + t * x.y) + beta * x.y);
+    if (gamma != 0.0) {
+      const cplx p = prevb[g];
+      val.x += gamma * p.x;
+      val.y += gamma * p.y;
+    }
+    outb[g] = val;
+  }
+}
+
+template <int N1, int N2>
+__global__ void __launch_bounds__(kPlaneMaxThreads)
+k_plane_reg(BoxPlan P, const double* __restrict__ vs, cplx* __restrict__ T) {
+  constexpr int G1 = lane_group(N1), R1 = N1 / G1;
+  constexpr int G2 = lane_group(N2), R2 = N2 / G2;
+  constexpr int TRS = N2 + 1;
+  extern __shared__ cplx lds[];
+  cplx* E = lds;                                               // xr x TRS
+  int* slot = reinterpret_cast<int*>(lds + (size_t)P.xr * TRS); // N1 entries
+  const int j3 = blockIdx.x;
+  const int b = blockIdx.y;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  cplx* tp = T + (size_t)b * P.n3 * P.ncols + (size_t)j3 * P.ncols;
+  for (int i = tid; i < P.xr * TRS; i += nt) E[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < N1; i += nt) slot[i] = -1;
+  __syncthreads();
+  for (int e = tid; e < P.xr; e += nt) slot[P.ext_m1[e]] = e;
+  for (int c = tid; c < P.ncols; c += nt) E[P.col_e[c] * TRS + P.col_m2[c]] = tp[c];
+  __syncthreads();
+  // backward along N2 for every extent column (in place, one column per lane group)
+  {
+    const int grp = tid / G2, lb = tid % G2, ngr = nt / G2;
+    const int base = R2 * brev<G2>(lb);
+    LaneTw<R2, G2> tw;
+    tw.load(lb, P.ax2.tw);
+    for (int e = grp; e < P.xr; e += ngr) {
+      cplx v[R2];
+      cplx* col = E + e * TRS;
+#pragma unroll
+      for (int a = 0; a < R2; ++a) v[a] = col[G2 * a + lb];
+      lane_fft_bwd<R2, G2>(v, lb, tw);
+#pragma unroll
+      for (int q = 0; q < R2; ++q) col[q + base] = v[q];
+    }
+  }
+  __syncthreads();
+  // rows: backward along N1, x V/N_box, forward along N1; only extent entries live in E
+  {
+    const int grp = tid / G1, lb = tid % G1, ngr = nt / G1;
+    const int base = R1 * brev<G1>(lb);
+    LaneTw<R1, G1> tw;
+    tw.load(lb, P.ax1.tw);
+    const double* vp = vs + (size_t)j3 * N2 * N1;
+    for (int row = grp; row < N2; row += ngr) {
+      cplx v[R1];
+#pragma unroll
+      for (int a = 0; a < R1; ++a) {
+        const int s = slot[G1 * a + lb];
+        v[a] = s >= 0 ? E[s * TRS + row] : make_double2(0.0, 0.0);
+      }
+      lane_fft_bwd<R1, G1>(v, lb, tw);
+      const double* vr = vp + (size_t)row * N1 + base;
+#pragma unroll
+      for (int q = 0; q < R1; ++q) v[q] = cscale(v[q], vr[q]);
+      lane_fft_fwd<R1, G1>(v, lb, tw);
+#pragma unroll
+      for (int a = 0; a < R1; ++a) {
+        const int s = slot[G1 * a + lb];
+        if (s >= 0) E[s * TRS + row] = v[a];
+      }
+    }
+  }
+  __syncthreads();
+  // forward along N2
+  {
+    const int grp = tid / G2, lb = tid % G2, ngr = nt / G2;
+    const int base = R2 * brev<G2>(lb);
+    LaneTw<R2, G2> tw;
+    tw.load(lb, P.ax2.tw);
+    for (int e = grp; e < P.xr; e += ngr) {
+      cplx v[R2];
+      cplx* col = E + e * TRS;
+#pragma unroll
+      for (int q = 0; q < R2; ++q) v[q] = col[q + base];
+      lane_fft_fwd<R2, G2>(v, lb, tw);
+#pragma unroll
+      for (int a = 0; a < R2; ++a) col[G2 * a + lb] = v[a];
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < P.ncols; c += nt) tp[c] = E[P.col_e[c] * TRS + P.col_m2[c]];
+}
+
+size_t plane_reg_lds(const BoxPlan& p) {
+  return (size_t)p.xr * (p.n2 + 1) * sizeof(cplx) + (size_t)p.n1 * sizeof(int);
+}
+
+int plane_reg_threads(const BoxPlan& p) {
+  const int g1 = lane_group(p.n1), g2 = lane_group(p.n2);
+  int t = std::max(p.xr * g2, p.n2 * g1);
+  t = ((t + 63) / 64) * 64;
+  return std::min(t, kPlaneMaxThreads);
+}
+
+#define PW_FAST_SIZES(X) X(24) X(32) X(36) X(48) X(64) X(72) X(96) X(120) X(128) X(144) X(160)
+
+}  // namespace
+
+bool fft_reg_col_supported(int n3) {
+#define CASE(N) if (n3 == N) return true;
+  PW_FAST_SIZES(CASE)
+#undef CASE
+  return false;
+}
+
+bool fft_reg_plane_supported(const BoxPlan& p, size_t lds_limit) {
+  if (p.n1 != p.n2) return false;
+  bool ok = false;
+#define CASE(N) if (p.n1 == N) ok = true;
+  PW_FAST_SIZES(CASE)
+#undef CASE
+  return ok && plane_reg_lds(p) <= lds_limit;
+}
+
+hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int64_t ldpsi, cplx* T,
+                                  hipStream_t s) {
+#define CASE(N)                                                                              \
+  if (p.n3 == N) {                                                                           \
+    constexpr int CT = kColThreads / lane_group(N);                                          \
+    dim3 grid((p.ncols + CT - 1) / CT, nb);                                                  \
+    hipLaunchKernelGGL(k_col_inv_reg<N>, grid, dim3(kColThreads), 0, s, p, psi, ldpsi, T);   \
+    return hipGetLastError();                                                                \
+  }
+  PW_FAST_SIZES(CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const double* kin,
+                                  const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev,
+                                  cplx* out, int64_t ldout, double alpha, double beta, double gamma,
+                                  hipStream_t s) {
+#define CASE(N)                                                                               \
+  if (p.n3 == N) {                                                                            \
+    constexpr int CT = kColThreads / lane_group(N);                                           \
+    dim3 grid((p.ncols + CT - 1) / CT, nb);                                                   \
+    hipLaunchKernelGGL(k_col_fwd_reg<N>, grid, dim3(kColThreads), 0, s, p, T, kin, in, ldin,  \
+                       prev, ldprev, out, ldout, alpha, beta, gamma);                         \
+    return hipGetLastError();                                                                 \
+  }
+  PW_FAST_SIZES(CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fft_plane_reg(const BoxPlan& p, int nb, const double* vscaled, cplx* T,
+                                hipStream_t s) {
+  const size_t lds = plane_reg_lds(p);
+  const int threads = plane_reg_threads(p);
+#define CASE(N)                                                                        \
+  if (p.n1 == N && p.n2 == N) {                                                        \
+    hipLaunchKernelGGL((k_plane_reg<N, N>), dim3(p.n3, nb), dim3(threads), lds, s, p,  \
+                       vscaled, T);                                                    \
+    return hipGetLastError();                                                          \
+  }
+  PW_FAST_SIZES(CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t fft_reg_set_lds_limits(size_t bytes) {
+#define CASE(N)                                                                              \
+  {                                                                                          \
+    hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N>,                       \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
+    if (e != hipSuccess) return e;                                                           \
+  }
+  PW_FAST_SIZES(CASE)
+#undef CASE
+  return hipSuccess;
+}

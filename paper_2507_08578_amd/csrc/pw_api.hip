@@ -258,6 +258,7 @@ pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
   }
   c->pinned = static_cast<double*>(pin);
   e = fft_set_lds_limits(c->lds_limit);
+  if (e == hipSuccess) e = fft_reg_set_lds_limits(c->lds_limit);
   if (e == hipSuccess) e = heev_set_lds_limit(c->lds_limit);
   if (e != hipSuccess) {
     (void)hipHostFree(pin);

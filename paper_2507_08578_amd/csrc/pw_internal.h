@@ -44,9 +44,11 @@ struct BoxPlan {
 // Launch helpers (defined in the .hip files), all enqueue on `s`.
 // ---------------------------------------------------------------------------
 struct FftLaunchCfg {
-  int col_tile;             // columns per workgroup of the N3 kernels
-  int plane_rows;           // rows per batch in the plane kernel
+  int col_tile;             // columns per workgroup of the N3 kernels (generic path)
+  int plane_rows;           // rows per batch in the plane kernel (generic path)
   size_t col_lds, plane_lds;
+  bool reg_col;             // register-resident column kernels available for N3
+  bool reg_plane;           // register-resident plane kernel available for (N1, N2)
 };
 
 // Host-side choice of tiles and LDS sizes; returns false if this GPU's LDS
@@ -72,6 +74,19 @@ hipError_t launch_fft_col_fwd(const BoxPlan& p, const FftLaunchCfg& cfg, int nb,
 
 // Allow `bytes` of dynamic LDS for the FFT kernels (above the default cap).
 hipError_t fft_set_lds_limits(size_t bytes);
+
+// Register-resident variants (fft_reg.hip) for the box lengths they are built for.
+bool fft_reg_col_supported(int n3);
+bool fft_reg_plane_supported(const BoxPlan& p, size_t lds_limit);
+hipError_t fft_reg_set_lds_limits(size_t bytes);
+hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int64_t ldpsi, cplx* T,
+                                  hipStream_t s);
+hipError_t launch_fft_plane_reg(const BoxPlan& p, int nb, const double* vscaled, cplx* T,
+                                hipStream_t s);
+hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const double* kin,
+                                  const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev,
+                                  cplx* out, int64_t ldout, double alpha, double beta, double gamma,
+                                  hipStream_t s);
 
 // Split-K C = alpha * A^H B (see pw_gemm_cn).  `work` holds splits*m*n cplx;
 // rowscale (m doubles on device, may be null) multiplies row i of the result.
