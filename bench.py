@@ -123,11 +123,14 @@ def main():
     ham.rayleigh_ritz(Y, HY, eig, resid)
     lam = eig.cpu()
 
+    sweeps = []
+
     def step():
         nonlocal lam
         ham.cheb_filter(Y, w.degree, float(lam[-1]), b, float(lam[0]), hx=HY)
         ham.orthonormalize(Y)
         ham.rayleigh_ritz(Y, HY, eig, resid)
+        sweeps.append(ctx.last_sweeps())
         lam = eig.cpu()
 
     for i in range(args.warmup):
@@ -186,6 +189,7 @@ def main():
                    "applies_per_step": applies_per_step, "nb": nb},
         "filter_iter_ms": ms_per_step,
         "max_resid": float(resid.max().cpu()),
+        "eigensolver_sweeps": sweeps,
         "roofline": roof,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
     }

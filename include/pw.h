@@ -151,6 +151,8 @@ pw_status pw_cheb_filter(pw_ham* ham, pw_prec prec, int32_t degree, double a, do
 /*
  * Cholesky orthonormalisation (section 5.4): S = Y^H Y = U^H U (U upper,
  * positive diagonal), Y <- Y U^{-1}; if hy_dev != NULL, HY <- HY U^{-1} too.
+ * U is factored in diagonal blocks of 64; Y U^{-1} is a blocked right-side
+ * triangular solve (no explicit inverse).
  * gram_prec: PW_FP64 only in this version.  Synchronises (reads the
  * factorisation status).  PW_ERR_NOT_POSDEF when a squared pivot is at or
  * below nb * eps * max_i S_ii; the message names the pivot.
@@ -196,7 +198,9 @@ pw_status pw_heev(pw_ctx* ctx, int64_t n, void* a_dev, int64_t lda, double* w_de
                   void* q_dev, int64_t ldq);
 /* Upper Cholesky factor in place: a = U^H U (upper triangle of a read and
  * overwritten; strictly lower part set to 0); then ainv_dev (n x n, ldi)
- * receives U^{-1} (upper, zeros below).  Synchronises; NOT_POSDEF as above. */
+ * receives U^{-1} (upper, zeros below), formed as I U^{-1} by the same
+ * blocked right-side triangular solve pw_orthonormalize applies to Y.
+ * Synchronises; NOT_POSDEF as above. */
 pw_status pw_potrf_inv(pw_ctx* ctx, int64_t n, void* a_dev, int64_t lda, void* ainv_dev,
                        int64_t ldi);
 
@@ -222,6 +226,9 @@ pw_status pw_ctx_set_timing(pw_ctx* ctx, int enable);
 /* Synchronises; total milliseconds and launch count since the last reset. */
 pw_status pw_ctx_stage_time(pw_ctx* ctx, int stage, double* total_ms, int64_t* launches);
 pw_status pw_ctx_reset_timing(pw_ctx* ctx);
+/* Sweeps used by the last dense Hermitian eigensolve on this context
+ * (-1 if it hit the sweep limit). */
+pw_status pw_ctx_last_sweeps(const pw_ctx* ctx, int* sweeps);
 
 #ifdef __cplusplus
 }

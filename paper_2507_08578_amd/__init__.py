@@ -81,6 +81,11 @@ class Context:
     def reset_timing(self):
         self.check(_LIB.pw_ctx_reset_timing(self.handle))
 
+    def last_sweeps(self) -> int:
+        n = ctypes.c_int()
+        self.check(_LIB.pw_ctx_last_sweeps(self.handle, ctypes.byref(n)))
+        return n.value
+
     def stage_times(self) -> dict:
         out = {}
         for i, name in enumerate(STAGES):

@@ -66,6 +66,7 @@ SIGNATURES = {
     "pw_ctx_stage_time": (c_int, [c_void_p, c_int, ctypes.POINTER(c_double),
                                   ctypes.POINTER(c_int64)]),
     "pw_ctx_reset_timing": (c_int, [c_void_p]),
+    "pw_ctx_last_sweeps": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
 }
 
 

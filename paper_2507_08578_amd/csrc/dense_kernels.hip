@@ -2,13 +2,14 @@
 // helpers.  Section 5.1 (Rayleigh-Ritz: a dense Hermitian eigenproblem of
 // the block size) and section 5.4 (full-band Cholesky orthogonalisation).
 //
-//  * potrf_inv : S = U^H U (upper Cholesky, right-looking) then U^{-1}
-//                (column-oriented triangular inverse), one workgroup.
+//  * chol      : S = U^H U (upper Cholesky), blocked: each 64-wide diagonal
+//                block is factored and inverted in LDS by one workgroup; the
+//                row panels and trailing updates are MFMA products.
 //  * heev      : cyclic two-sided Jacobi with the round-robin (circle)
 //                ordering: in each round all n/2 disjoint pairs rotate at
 //                once, A <- G^H A G, V <- V G.  For n <= 64 the whole solve
 //                runs in one workgroup with A and V in LDS; larger n run one
-//                kernel per round over 2x2 blocks of A (ping-pong buffers).
+//                kernel per round in position space (pairs adjacent).
 #include "pw_internal.h"
 
 #include <algorithm>
@@ -134,104 +135,118 @@ k_residuals(int64_t npw, const cplx* __restrict__ W, int64_t ldw, const cplx* __
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky (upper, S = U^H U) and triangular inverse, single workgroup.
-// A is read from its upper triangle and overwritten by U (strict lower part
-// set to zero); X receives U^{-1}.  status[0] = -1 on success, else the index
-// of the first pivot whose value is at or below n eps max_i S_ii.
+// Blocked Cholesky (S = U^H U) for large n: per diagonal block of kb <= 64
+// one workgroup factors it in LDS and inverts the factor; the row panel and
+// the trailing update are matrix products (k_gemm_cn) issued by the host.
 // ---------------------------------------------------------------------------
-constexpr int kCholThreads = 1024;
-
-__global__ void __launch_bounds__(kCholThreads)
-k_potrf_inv(int n, cplx* A, int64_t lda, cplx* X, int64_t ldx, int* status) {
-  extern __shared__ cplx rowk[];   // n entries
-  __shared__ double red[kCholThreads];
-  __shared__ int fail;
-  __shared__ double sh_tol, sh_inv;
-  const int tid = threadIdx.x, nt = blockDim.x;
+__global__ void __launch_bounds__(1024) k_chol_init(int n, const cplx* __restrict__ A, int64_t lda,
+                                                    double* tol, int* status) {
+  __shared__ double red[1024];
   double m = 0.0;
-  for (int i = tid; i < n; i += nt) m = fmax(m, A[i + (int64_t)i * lda].x);
-  red[tid] = m;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, A[i + (int64_t)i * lda].x);
+  red[threadIdx.x] = m;
   __syncthreads();
-  for (int s = nt / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (tid == 0) {
-    sh_tol = (double)n * DBL_EPSILON * red[0];
-    fail = -1;
+  if (threadIdx.x == 0) {
+    tol[0] = (double)n * DBL_EPSILON * red[0];
+    status[0] = -1;
   }
+}
+
+// Factor the kb x kb diagonal block at A(k0, k0) (upper triangle read),
+// write U back (zeros below its diagonal) and U^{-1} to dinv (ld kb).  A
+// pivot at or below tol records k0 + p in status unless an earlier block did.
+__global__ void __launch_bounds__(256)
+k_chol_diag(int kb, int k0, cplx* __restrict__ A, int64_t lda, cplx* __restrict__ dinv,
+            const double* __restrict__ tol, int* status) {
+  extern __shared__ cplx sm[];
+  const int trs = kb + 1;
+  cplx* a = sm;
+  cplx* x = sm + kb * trs;
+  __shared__ int fail;
+  __shared__ double sinv;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  cplx* Ab = A + k0 + (int64_t)k0 * lda;
+  for (int idx = tid; idx < kb * kb; idx += nt) {
+    const int j = idx / kb, i = idx - j * kb;
+    a[i + j * trs] = (i <= j) ? Ab[i + (int64_t)j * lda] : make_double2(0.0, 0.0);
+  }
+  if (tid == 0) fail = -1;
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
+  const double t = tol[0];
+  for (int p = 0; p < kb; ++p) {
     if (tid == 0) {
-      const double d = A[k + (int64_t)k * lda].x;
-      if (!(d > sh_tol)) {
-        fail = k;
+      const double d = a[p + p * trs].x;
+      if (!(d > t)) {
+        fail = p;
       } else {
         const double u = sqrt(d);
-        A[k + (int64_t)k * lda] = make_double2(u, 0.0);
-        sh_inv = 1.0 / u;
+        a[p + p * trs] = make_double2(u, 0.0);
+        sinv = 1.0 / u;
       }
     }
     __syncthreads();
     if (fail >= 0) break;
-    const double inv = sh_inv;
-    for (int j = k + 1 + tid; j < n; j += nt) {
-      const cplx v = cscale(A[k + (int64_t)j * lda], inv);
-      A[k + (int64_t)j * lda] = v;
-      rowk[j] = v;
-    }
+    for (int j = p + 1 + tid; j < kb; j += nt) a[p + j * trs] = cscale(a[p + j * trs], sinv);
     __syncthreads();
-    // trailing update of the upper triangle: A[i][j] -= conj(U[k][i]) U[k][j], k < i <= j
-    const int mrem = n - k - 1;
-    const int64_t tot = (int64_t)mrem * mrem;
-    for (int64_t idx = tid; idx < tot; idx += nt) {
-      const int jj = (int)(idx / mrem), ii = (int)(idx - (int64_t)jj * mrem);
+    const int m = kb - p - 1;
+    for (int idx = tid; idx < m * m; idx += nt) {
+      const int jj = idx / m, ii = idx - jj * m;
       if (ii > jj) continue;
-      const int i = k + 1 + ii, j = k + 1 + jj;
-      const cplx p = cmul(cconj(rowk[i]), rowk[j]);
-      cplx a = A[i + (int64_t)j * lda];
-      A[i + (int64_t)j * lda] = csub(a, p);
+      const int i = p + 1 + ii, j = p + 1 + jj;
+      a[i + j * trs] = csub(a[i + j * trs], cmul(cconj(a[p + i * trs]), a[p + j * trs]));
     }
     __syncthreads();
   }
   if (fail >= 0) {
-    if (tid == 0) status[0] = fail;
+    if (tid == 0 && status[0] < 0) status[0] = k0 + fail;
     return;
   }
-  // zero the strict lower triangle of U
-  for (int64_t idx = tid; idx < (int64_t)n * n; idx += nt) {
-    const int j = (int)(idx / n), i = (int)(idx - (int64_t)j * n);
-    if (i > j) A[i + (int64_t)j * lda] = make_double2(0.0, 0.0);
+  for (int idx = tid; idx < kb * kb; idx += nt) {
+    const int j = idx / kb, i = idx - j * kb;
+    Ab[i + (int64_t)j * lda] = (i <= j) ? a[i + j * trs] : make_double2(0.0, 0.0);
   }
-  __syncthreads();
-  // X = U^{-1}, column by column: X[j][j] = 1/U[j][j];
-  // X[i][j] = -(sum_{p=i}^{j-1} X[i][p] U[p][j]) / U[j][j] for i < j.
-  for (int j = 0; j < n; ++j) {
-    for (int p = tid; p <= j; p += nt) rowk[p] = A[p + (int64_t)j * lda];
-    __syncthreads();
-    const double ujj = rowk[j].x;
-    const double rinv = 1.0 / ujj;
-    for (int i = tid; i < n; i += nt) {
-      cplx v;
+  // x = U^{-1} column by column
+  for (int j = 0; j < kb; ++j) {
+    const double rinv = 1.0 / a[j + j * trs].x;
+    for (int i = tid; i < kb; i += nt) {
+      cplx v = make_double2(0.0, 0.0);
       if (i < j) {
         double sr = 0.0, si = 0.0;
         for (int p = i; p < j; ++p) {
-          const cplx x = X[i + (int64_t)p * ldx];
-          const cplx u = rowk[p];
-          sr += x.x * u.x - x.y * u.y;
-          si += x.x * u.y + x.y * u.x;
+          const cplx xv = x[i + p * trs], uv = a[p + j * trs];
+          sr += xv.x * uv.x - xv.y * uv.y;
+          si += xv.x * uv.y + xv.y * uv.x;
         }
         v = make_double2(-sr * rinv, -si * rinv);
       } else if (i == j) {
         v = make_double2(rinv, 0.0);
-      } else {
-        v = make_double2(0.0, 0.0);
       }
-      X[i + (int64_t)j * ldx] = v;
+      x[i + j * trs] = v;
     }
     __syncthreads();
   }
-  if (tid == 0) status[0] = -1;
+  for (int idx = tid; idx < kb * kb; idx += nt) {
+    const int j = idx / kb, i = idx - j * kb;
+    dinv[i + j * kb] = x[i + j * trs];
+  }
+}
+
+__global__ void k_zero_lower(int n, cplx* A, int64_t lda) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int64_t j = idx / n, i = idx - j * n;
+  if (i > j) A[i + j * lda] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_identity_ld(int n, cplx* A, int64_t lda) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int64_t j = idx / n, i = idx - j * n;
+  A[i + j * lda] = make_double2(i == j ? 1.0 : 0.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -444,44 +459,50 @@ k_jacobi_small(int n, const cplx* __restrict__ Ain, int64_t lda, double* __restr
   if (tid == 0) sweeps_out[0] = done ? sweeps : -1;
 }
 
-// One round for n > 64: A_out = G^H A_in G over 2x2 blocks; V <- V G in place.
-// Threads [0, h*h) own the blocks, [h*h, h*h + n*h) own the V row pairs.
-__global__ void k_jacobi_round(int n, int r, const cplx* __restrict__ Ai, cplx* __restrict__ Ao,
-                               cplx* __restrict__ V) {
-  const int n2 = n + (n & 1);
+// Rounds for n > 64 run in "position space": the n2 x n2 matrix (n2 = n
+// rounded up to even, padding row/column zero) is stored so that the pair k
+// of every round occupies positions (2k, 2k+1).  Position 0 holds a fixed
+// player; positions 1..n2-1 are the slots of a circle (odd position 2s+1 is
+// slot s < n2/2, even position 2(n2-1-s) is slot s >= n2/2) and after every
+// round each circle player moves to the next slot.  This is the circle-method
+// ordering, so n2-1 rounds meet every pair once; each round reads contiguous
+// 2x2 blocks and writes them to the players' next positions (ping-pong).
+__device__ __forceinline__ int jac_next_pos(int pos, int n2) {
+  if (pos == 0) return 0;
+  const int h = n2 / 2;
+  const int slot = (pos & 1) ? (pos - 1) / 2 : n2 - 1 - pos / 2;
+  const int ns = (slot + 1 == n2 - 1) ? 0 : slot + 1;
+  return ns < h ? 2 * ns + 1 : 2 * (n2 - 1 - ns);
+}
+
+// Position of player p after r rounds (player p starts at position p).
+__device__ __forceinline__ int jac_pos_after(int p, int r, int n2) {
+  if (p == 0) return 0;
+  const int h = n2 / 2;
+  const int slot0 = (p & 1) ? (p - 1) / 2 : n2 - 1 - p / 2;
+  const int ns = (int)(((int64_t)slot0 + r) % (n2 - 1));
+  return ns < h ? 2 * ns + 1 : 2 * (n2 - 1 - ns);
+}
+
+__device__ __forceinline__ Rot pos_rot(const cplx* A, int P, int n2) {
+  const int p = 2 * P, q = 2 * P + 1;
+  return make_rot(A[p + (int64_t)p * n2].x, A[q + (int64_t)q * n2].x, A[p + (int64_t)q * n2]);
+}
+
+// A: n2 x n2 (ld n2), V: n x n2 (ld n).  Threads [0, h*h) own 2x2 blocks of A
+// (consecutive threads walk down a block column), [h*h, h*h + n*h) own V row pairs.
+__global__ void k_jacobi_round(int n, int n2, const cplx* __restrict__ Ai, cplx* __restrict__ Ao,
+                               const cplx* __restrict__ Vi, cplx* __restrict__ Vo) {
   const int h = n2 / 2;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nblk = (int64_t)h * h;
-  auto rot_of = [&](int pair, int* p, int* q) {
-    rr_pair(r, pair, n2, p, q);
-    if (*q >= n) return make_rot(0.0, 0.0, make_double2(0.0, 0.0));
-    return make_rot(Ai[*p + (int64_t)*p * n].x, Ai[*q + (int64_t)*q * n].x, Ai[*p + (int64_t)*q * n]);
-  };
   if (idx < nblk) {
-    const int P = (int)(idx / h), Qb = (int)(idx - (int64_t)P * h);
-    int p1, q1, p2, q2;
-    const Rot RP = rot_of(P, &p1, &q1);
-    const Rot RQ = rot_of(Qb, &p2, &q2);
-    if (q1 >= n && q2 >= n) {
-      Ao[p1 + (int64_t)p2 * n] = Ai[p1 + (int64_t)p2 * n];
-      return;
-    }
-    if (q1 >= n) {   // row p1 only, columns (p2, q2)
-      cplx x1 = Ai[p1 + (int64_t)p2 * n], x2 = Ai[p1 + (int64_t)q2 * n];
-      rot_row(RQ, &x1, &x2);
-      Ao[p1 + (int64_t)p2 * n] = x1;
-      Ao[p1 + (int64_t)q2 * n] = x2;
-      return;
-    }
-    if (q2 >= n) {   // column p2 only, rows (p1, q1)
-      const cplx x1 = Ai[p1 + (int64_t)p2 * n], x2 = Ai[q1 + (int64_t)p2 * n];
-      const cplx p12 = cscale(RP.ph, -RP.sn), p21 = cscale(cconj(RP.ph), RP.sn);
-      Ao[p1 + (int64_t)p2 * n] = cadd(cscale(x1, RP.cs), cmul(p12, x2));
-      Ao[q1 + (int64_t)p2 * n] = cadd(cmul(p21, x1), cscale(x2, RP.cs));
-      return;
-    }
-    cplx x11 = Ai[p1 + (int64_t)p2 * n], x12 = Ai[p1 + (int64_t)q2 * n];
-    cplx x21 = Ai[q1 + (int64_t)p2 * n], x22 = Ai[q1 + (int64_t)q2 * n];
+    const int Qb = (int)(idx / h), P = (int)(idx - (int64_t)Qb * h);
+    const Rot RP = pos_rot(Ai, P, n2);
+    const Rot RQ = pos_rot(Ai, Qb, n2);
+    const int r0 = 2 * P, c0 = 2 * Qb;
+    cplx x11 = Ai[r0 + (int64_t)c0 * n2], x21 = Ai[r0 + 1 + (int64_t)c0 * n2];
+    cplx x12 = Ai[r0 + (int64_t)(c0 + 1) * n2], x22 = Ai[r0 + 1 + (int64_t)(c0 + 1) * n2];
     if (P == Qb) {
       if (RP.on) {
         x11 = make_double2(x11.x - RP.t, 0.0);
@@ -492,22 +513,67 @@ __global__ void k_jacobi_round(int n, int r, const cplx* __restrict__ Ai, cplx* 
     } else if (RP.on || RQ.on) {
       rot_block(RP, RQ, &x11, &x12, &x21, &x22);
     }
-    Ao[p1 + (int64_t)p2 * n] = x11;
-    Ao[p1 + (int64_t)q2 * n] = x12;
-    Ao[q1 + (int64_t)p2 * n] = x21;
-    Ao[q1 + (int64_t)q2 * n] = x22;
+    const int nr0 = jac_next_pos(r0, n2), nr1 = jac_next_pos(r0 + 1, n2);
+    const int nc0 = jac_next_pos(c0, n2), nc1 = jac_next_pos(c0 + 1, n2);
+    Ao[nr0 + (int64_t)nc0 * n2] = x11;
+    Ao[nr1 + (int64_t)nc0 * n2] = x21;
+    Ao[nr0 + (int64_t)nc1 * n2] = x12;
+    Ao[nr1 + (int64_t)nc1 * n2] = x22;
     return;
   }
   const int64_t vi = idx - nblk;
   if (vi >= (int64_t)n * h) return;
   const int Qb = (int)(vi / n), i = (int)(vi - (int64_t)Qb * n);
-  int p2, q2;
-  const Rot RQ = rot_of(Qb, &p2, &q2);
-  if (q2 >= n || !RQ.on) return;
-  cplx x1 = V[i + (int64_t)p2 * n], x2 = V[i + (int64_t)q2 * n];
-  rot_row(RQ, &x1, &x2);
-  V[i + (int64_t)p2 * n] = x1;
-  V[i + (int64_t)q2 * n] = x2;
+  const Rot RQ = pos_rot(Ai, Qb, n2);
+  const int c0 = 2 * Qb;
+  cplx x1 = Vi[i + (int64_t)c0 * n], x2 = Vi[i + (int64_t)(c0 + 1) * n];
+  if (RQ.on) rot_row(RQ, &x1, &x2);
+  Vo[i + (int64_t)jac_next_pos(c0, n2) * n] = x1;
+  Vo[i + (int64_t)jac_next_pos(c0 + 1, n2) * n] = x2;
+}
+
+// A0 = [a 0; 0 0] (n2 x n2), V0 = [I 0] (n x n2)
+__global__ void k_jacobi_init(int n, int n2, const cplx* __restrict__ a, int64_t lda,
+                              cplx* __restrict__ A0, cplx* __restrict__ V0) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t na = (int64_t)n2 * n2;
+  if (idx < na) {
+    const int j = (int)(idx / n2), i = (int)(idx - (int64_t)j * n2);
+    A0[idx] = (i < n && j < n) ? a[i + (int64_t)j * lda] : make_double2(0.0, 0.0);
+    return;
+  }
+  const int64_t vi = idx - na;
+  if (vi >= (int64_t)n * n2) return;
+  const int j = (int)(vi / n), i = (int)(vi - (int64_t)j * n);
+  V0[vi] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+}
+
+// Rank of player p's eigenvalue (ties by player index), players 0..n-1.
+__global__ void k_jacobi_rank(int n, int n2, int rounds, const cplx* __restrict__ A,
+                              int* __restrict__ rank) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int sp = jac_pos_after(p, rounds, n2);
+  const double dp = A[sp + (int64_t)sp * n2].x;
+  int rk = 0;
+  for (int q = 0; q < n; ++q) {
+    const int sq = jac_pos_after(q, rounds, n2);
+    const double dq = A[sq + (int64_t)sq * n2].x;
+    if (dq < dp || (dq == dp && q < p)) ++rk;
+  }
+  rank[p] = rk;
+}
+
+__global__ void k_jacobi_scatter(int n, int n2, int rounds, const cplx* __restrict__ A,
+                                 const cplx* __restrict__ V, const int* __restrict__ rank,
+                                 double* __restrict__ w, cplx* __restrict__ Q, int64_t ldq) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int p = (int)(idx / n), i = (int)(idx - (int64_t)p * n);
+  const int sp = jac_pos_after(p, rounds, n2);
+  const int rp = rank[p];
+  Q[i + (int64_t)rp * ldq] = V[i + (int64_t)sp * n];
+  if (i == 0) w[rp] = A[sp + (int64_t)sp * n2].x;
 }
 
 __global__ void __launch_bounds__(1024) k_offnorm(int n, const cplx* __restrict__ A, double* out) {
@@ -534,36 +600,6 @@ __global__ void __launch_bounds__(1024) k_offnorm(int n, const cplx* __restrict_
     out[0] = r1[0];
     out[1] = r2[0];
   }
-}
-
-__global__ void k_identity(int n, cplx* V) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
-  const int64_t j = idx / n, i = idx - j * n;
-  V[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-}
-
-__global__ void k_eig_rank(int n, const cplx* __restrict__ A, int* __restrict__ rank) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double di = A[i + (int64_t)i * n].x;
-  int rk = 0;
-  for (int j = 0; j < n; ++j) {
-    const double dj = A[j + (int64_t)j * n].x;
-    if (dj < di || (dj == di && j < i)) ++rk;
-  }
-  rank[i] = rk;
-}
-
-__global__ void k_eig_scatter(int n, const cplx* __restrict__ A, const cplx* __restrict__ V,
-                              const int* __restrict__ rank, double* __restrict__ w,
-                              cplx* __restrict__ Q, int64_t ldq) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
-  const int j = (int)(idx / n), i = (int)(idx - (int64_t)j * n);
-  const int rj = rank[j];
-  Q[i + (int64_t)rj * ldq] = V[idx];
-  if (i == 0) w[rj] = A[j + (int64_t)j * n].x;
 }
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -626,21 +662,38 @@ hipError_t launch_residuals(int64_t npw, int64_t nb, const cplx* W, int64_t ldw,
   return hipGetLastError();
 }
 
-hipError_t launch_potrf_inv(int64_t n, cplx* a, int64_t lda, cplx* ainv, int64_t ldi, int* status,
+hipError_t launch_chol_init(int64_t n, const cplx* a, int64_t lda, double* tol, int* status,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_potrf_inv, dim3(1), dim3(kCholThreads), (size_t)n * sizeof(cplx), s, (int)n,
-                     a, lda, ainv, ldi, status);
+  hipLaunchKernelGGL(k_chol_init, dim3(1), dim3(1024), 0, s, (int)n, a, lda, tol, status);
   return hipGetLastError();
 }
 
-size_t heev_work_bytes(int64_t n) {
-  return (size_t)(3 * n * n) * sizeof(cplx) + (size_t)(n + 8) * sizeof(int) + 64;
+hipError_t launch_chol_diag(int kb, int k0, cplx* a, int64_t lda, cplx* dinv, const double* tol,
+                            int* status, hipStream_t s) {
+  const size_t lds = (size_t)2 * kb * (kb + 1) * sizeof(cplx);
+  hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), lds, s, kb, k0, a, lda, dinv, tol, status);
+  return hipGetLastError();
 }
 
-// Opt the kernels with large dynamic LDS into `bytes` of LDS per workgroup
-// (minus their static shared memory).
+hipError_t launch_zero_lower(int64_t n, cplx* a, int64_t lda, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_lower, dim3(nblocks(n * n, 256)), dim3(256), 0, s, (int)n, a, lda);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity(int64_t n, cplx* a, int64_t lda, hipStream_t s) {
+  hipLaunchKernelGGL(k_identity_ld, dim3(nblocks(n * n, 256)), dim3(256), 0, s, (int)n, a, lda);
+  return hipGetLastError();
+}
+
+// Work layout for n > 64: A0, A1 (n2 x n2), V0, V1 (n x n2), n ints of ranks,
+// then two 16-byte aligned doubles.
+size_t heev_work_bytes(int64_t n) {
+  const int64_t n2 = n + (n & 1);
+  return (size_t)(2 * n2 * n2 + 2 * n * n2) * sizeof(cplx) + (size_t)(n + 8) * sizeof(int) + 64;
+}
+
 hipError_t heev_set_lds_limit(size_t bytes) {
-  const void* fns[2] = {(const void*)k_jacobi_small, (const void*)k_potrf_inv};
+  const void* fns[2] = {(const void*)k_jacobi_small, (const void*)k_chol_diag};
   for (const void* f : fns) {
     hipFuncAttributes at;
     hipError_t e = hipFuncGetAttributes(&at, f);
@@ -654,10 +707,12 @@ hipError_t heev_set_lds_limit(size_t bytes) {
 
 hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int64_t ldq, void* work,
                        double* host_scratch, int* sweeps_done, hipStream_t s) {
-  // layout: A0, A1, V (n*n cplx each) | n ints (ranks) + flag | 16-byte aligned 2 doubles
-  int* dev_int = reinterpret_cast<int*>(static_cast<char*>(work) + (size_t)(3 * n * n) * sizeof(cplx));
-  const size_t stat_off = (((size_t)(3 * n * n) * sizeof(cplx) + (size_t)(n + 8) * sizeof(int)) + 15) & ~(size_t)15;
-  double* dstat = reinterpret_cast<double*>(static_cast<char*>(work) + stat_off);
+  const int64_t n2 = n + (n & 1);
+  char* base = static_cast<char*>(work);
+  const size_t mat_bytes = (size_t)(2 * n2 * n2 + 2 * n * n2) * sizeof(cplx);
+  int* dev_int = reinterpret_cast<int*>(base + mat_bytes);
+  const size_t stat_off = (mat_bytes + (size_t)(n + 8) * sizeof(int) + 15) & ~(size_t)15;
+  double* dstat = reinterpret_cast<double*>(base + stat_off);
   if (n <= kJacSmallMax) {
     const size_t lds = (size_t)(2 * n * n) * sizeof(cplx);
     hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(kJacThreads), lds, s, (int)n, (const cplx*)a,
@@ -671,20 +726,21 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
     *sweeps_done = hs;
     return e;
   }
-  cplx* A0 = static_cast<cplx*>(work);
-  cplx* A1 = A0 + n * n;
-  cplx* V = A1 + n * n;
-  hipError_t e = launch_copy_block(n, n, a, lda, A0, n, s);
+  cplx* A0 = reinterpret_cast<cplx*>(base);
+  cplx* A1 = A0 + n2 * n2;
+  cplx* V0 = A1 + n2 * n2;
+  cplx* V1 = V0 + n * n2;
+  hipLaunchKernelGGL(k_jacobi_init, dim3(nblocks(n2 * n2 + n * n2, 256)), dim3(256), 0, s, (int)n,
+                     (int)n2, (const cplx*)a, lda, A0, V0);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_identity, dim3(nblocks(n * n, 256)), dim3(256), 0, s, (int)n, V);
-  const int n2 = (int)(n + (n & 1));
   const int64_t h = n2 / 2;
   const int64_t threads = h * h + n * h;
   const double tl = std::max(1e-15, 2.2e-16 * (double)n);
-  int sw = 0;
+  int sw = 0, rounds = 0;
   bool conv = false;
   for (; sw <= kMaxSweeps; ++sw) {
-    hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, s, (int)n, (const cplx*)A0, dstat);
+    hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, s, (int)n2, (const cplx*)A0, dstat);
     e = hipMemcpyAsync(host_scratch, dstat, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
@@ -695,17 +751,19 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
     }
     if (sw == kMaxSweeps) break;
     for (int r = 0; r < n2 - 1; ++r) {
-      hipLaunchKernelGGL(k_jacobi_round, dim3(nblocks(threads, 256)), dim3(256), 0, s, (int)n, r,
-                         (const cplx*)A0, A1, V);
+      hipLaunchKernelGGL(k_jacobi_round, dim3(nblocks(threads, 256)), dim3(256), 0, s, (int)n,
+                         (int)n2, (const cplx*)A0, A1, (const cplx*)V0, V1);
       std::swap(A0, A1);
+      std::swap(V0, V1);
+      ++rounds;
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_eig_rank, dim3(nblocks(n, 256)), dim3(256), 0, s, (int)n, (const cplx*)A0,
-                     dev_int);
-  hipLaunchKernelGGL(k_eig_scatter, dim3(nblocks(n * n, 256)), dim3(256), 0, s, (int)n,
-                     (const cplx*)A0, (const cplx*)V, (const int*)dev_int, w, q, ldq);
+  hipLaunchKernelGGL(k_jacobi_rank, dim3(nblocks(n, 256)), dim3(256), 0, s, (int)n, (int)n2, rounds,
+                     (const cplx*)A0, dev_int);
+  hipLaunchKernelGGL(k_jacobi_scatter, dim3(nblocks(n * n, 256)), dim3(256), 0, s, (int)n, (int)n2,
+                     rounds, (const cplx*)A0, (const cplx*)V0, (const int*)dev_int, w, q, ldq);
   *sweeps_done = conv ? sw : -1;
   return hipGetLastError();
 }

@@ -190,8 +190,38 @@ __device__ __forceinline__ void dft_reg(cplx* v) {
   }
 }
 
-__device__ __forceinline__ cplx shfl_xor(cplx v, int m) {
-  return make_double2(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+// Exchange with lane (lane ^ M) inside a 16-lane DPP row, on the VALU:
+//   M = 1, 2 : quad_perm [1,0,3,2] / [2,3,0,1]
+//   M = 4    : row_half_mirror (i -> 7-i) then quad_perm [3,2,1,0]  (7 - (i^3) = i^4)
+//   M = 8    : row_ror:8
+// Larger masks fall back to ds_bpermute.
+template <int M>
+__device__ __forceinline__ int xor_lane_i32(int v) {
+  if constexpr (M == 1) {
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+  } else if constexpr (M == 2) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+  } else if constexpr (M == 4) {
+    const int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);
+  } else if constexpr (M == 8) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+  } else {
+    return __shfl_xor(v, M);
+  }
+}
+
+template <int M>
+__device__ __forceinline__ double xor_lane(double x) {
+  const long long bits = __double_as_longlong(x);
+  const int lo = xor_lane_i32<M>((int)(bits & 0xffffffffLL));
+  const int hi = xor_lane_i32<M>((int)(bits >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int M>
+__device__ __forceinline__ cplx xor_lane(cplx v) {
+  return make_double2(xor_lane<M>(v.x), xor_lane<M>(v.y));
 }
 
 // Bit reversal of b in log2(G) bits.
@@ -240,49 +270,59 @@ __device__ __forceinline__ cplx conj_mul(cplx a, cplx w) {   // a * conj(w)
 // forward  (-):  in : v[k1] = Z[k1 + R brev(b)]    (the backward's layout)
 //                out: v[a]  = X'[G a + b]
 // The forward is the exact adjoint of the backward, stage by stage.
+template <int R, int G, int SI>
+__device__ __forceinline__ void dif_stages(cplx* v, int b, const LaneTw<R, G>& t) {
+  if constexpr (SI >= 0) {
+    constexpr int h = 1 << SI;
+    const bool up = (b & h) != 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const cplx p = xor_lane<h>(v[r]);
+      v[r] = up ? conj_mul(csub(p, v[r]), t.st[SI]) : cadd(v[r], p);
+    }
+    dif_stages<R, G, SI - 1>(v, b, t);
+  }
+}
+
+template <int R, int G, int SI>
+__device__ __forceinline__ void dit_stages(cplx* v, int b, const LaneTw<R, G>& t) {
+  if constexpr (SI < LaneTw<R, G>::kStages) {
+    constexpr int h = 1 << SI;
+    const bool up = (b & h) != 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const cplx p = xor_lane<h>(v[r]);
+      v[r] = up ? csub(p, cmul(t.st[SI], v[r])) : cadd(v[r], cmul(t.st[SI], p));
+    }
+    dit_stages<R, G, SI + 1>(v, b, t);
+  }
+}
+
 template <int R, int G>
 __device__ __forceinline__ void lane_fft_bwd(cplx* v, int b, const LaneTw<R, G>& t) {
   dft_reg<R, +1>(v);
   if constexpr (G > 1) {
 #pragma unroll
     for (int k1 = 1; k1 < R; ++k1) v[k1] = conj_mul(v[k1], t.k[k1 - 1]);   // exp(+2 pi i b k1/N)
-#pragma unroll
-    for (int s = LaneTw<R, G>::kStages - 1; s >= 0; --s) {
-      const int h = 1 << s;
-      const bool up = (b & h) != 0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const cplx p = shfl_xor(v[r], h);
-        v[r] = up ? conj_mul(csub(p, v[r]), t.st[s]) : cadd(v[r], p);
-      }
-    }
+    dif_stages<R, G, LaneTw<R, G>::kStages - 1>(v, b, t);
   }
 }
 
 template <int R, int G>
 __device__ __forceinline__ void lane_fft_fwd(cplx* v, int b, const LaneTw<R, G>& t) {
   if constexpr (G > 1) {
-#pragma unroll
-    for (int s = 0; s < LaneTw<R, G>::kStages; ++s) {
-      const int h = 1 << s;
-      const bool up = (b & h) != 0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const cplx p = shfl_xor(v[r], h);
-        v[r] = up ? csub(p, cmul(t.st[s], v[r])) : cadd(v[r], cmul(t.st[s], p));
-      }
-    }
+    dit_stages<R, G, 0>(v, b, t);
 #pragma unroll
     for (int k1 = 1; k1 < R; ++k1) v[k1] = cmul(v[k1], t.k[k1 - 1]);       // exp(-2 pi i b k1/N)
   }
   dft_reg<R, -1>(v);
 }
 
-// Lane-group shape used for a length-N transform: G a power of two <= 16,
-// as large as possible with R = N / G >= 3.
-constexpr int lane_group(int n) {
+// Lane-group shape used for a length-N transform: G a power of two <= gmax
+// (<= 16, one DPP row), as large as possible with R = N / G >= 3.
+constexpr int lane_group(int n, int gmax = 16) {
   int g = 1;
-  while (g < 16 && n % (2 * g) == 0 && n / (2 * g) >= 3) g *= 2;
+  while (g < gmax && n % (2 * g) == 0 && n / (2 * g) >= 3) g *= 2;
   return g;
 }
 

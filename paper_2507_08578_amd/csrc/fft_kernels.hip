@@ -388,6 +388,7 @@ bool fft_choose_config(const BoxPlan& p, size_t lds_limit, FftLaunchCfg* cfg) {
   cfg->plane_lds = plane_bytes(rb);
   cfg->reg_col = fft_reg_col_supported(p.n3);
   cfg->reg_plane = fft_reg_plane_supported(p, lds_limit);
+  cfg->plane_variant = 0;
   return true;
 }
 
@@ -402,7 +403,7 @@ hipError_t launch_fft_col_inv(const BoxPlan& p, const FftLaunchCfg& cfg, int nb,
 
 hipError_t launch_fft_plane(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const double* vscaled,
                             cplx* T, hipStream_t s) {
-  if (cfg.reg_plane) return launch_fft_plane_reg(p, nb, vscaled, T, s);
+  if (cfg.reg_plane) return launch_fft_plane_reg(p, cfg.plane_variant, nb, vscaled, T, s);
   dim3 grid(p.n3, nb);
   hipLaunchKernelGGL(k_plane, grid, dim3(kThreads), cfg.plane_lds, s, plan_args(p), cfg.plane_rows,
                      vscaled, T);

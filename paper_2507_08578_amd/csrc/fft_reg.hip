@@ -105,11 +105,11 @@ k_col_fwd_reg(BoxPlan P, const cplx* __restrict__ T, const double* __restrict__ 
   }
 }
 
-template <int N1, int N2>
+template <int N1, int N2, int GMAX>
 __global__ void __launch_bounds__(kPlaneMaxThreads)
 k_plane_reg(BoxPlan P, const double* __restrict__ vs, cplx* __restrict__ T) {
-  constexpr int G1 = lane_group(N1), R1 = N1 / G1;
-  constexpr int G2 = lane_group(N2), R2 = N2 / G2;
+  constexpr int G1 = lane_group(N1, GMAX), R1 = N1 / G1;
+  constexpr int G2 = lane_group(N2, GMAX), R2 = N2 / G2;
   constexpr int TRS = N2 + 1;
   extern __shared__ cplx lds[];
   cplx* E = lds;                                               // xr x TRS
@@ -192,20 +192,29 @@ size_t plane_reg_lds(const BoxPlan& p) {
   return (size_t)p.xr * (p.n2 + 1) * sizeof(cplx) + (size_t)p.n1 * sizeof(int);
 }
 
-int plane_reg_threads(const BoxPlan& p) {
-  const int g1 = lane_group(p.n1), g2 = lane_group(p.n2);
+int plane_reg_threads(const BoxPlan& p, int gmax) {
+  const int g1 = lane_group(p.n1, gmax), g2 = lane_group(p.n2, gmax);
   int t = std::max(p.xr * g2, p.n2 * g1);
   t = ((t + 63) / 64) * 64;
   return std::min(t, kPlaneMaxThreads);
 }
 
 #define PW_FAST_SIZES(X) X(24) X(32) X(36) X(48) X(64) X(72) X(96) X(120) X(128) X(144) X(160)
+// sizes whose 8-lane variant differs from the 16-lane one and fits the registers
+#define PW_NARROW_SIZES(X) X(48) X(64) X(96)
 
 }  // namespace
 
 bool fft_reg_col_supported(int n3) {
 #define CASE(N) if (n3 == N) return true;
   PW_FAST_SIZES(CASE)
+#undef CASE
+  return false;
+}
+
+bool fft_reg_plane_narrow(const BoxPlan& p) {
+#define CASE(N) if (p.n1 == N && p.n2 == N) return true;
+  PW_NARROW_SIZES(CASE)
 #undef CASE
   return false;
 }
@@ -250,15 +259,29 @@ hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fft_plane_reg(const BoxPlan& p, int nb, const double* vscaled, cplx* T,
-                                hipStream_t s) {
+// variant 0: lane groups of up to 16 lanes; variant 1: up to 8 lanes (more
+// values per lane, fewer cross-lane stages).
+hipError_t launch_fft_plane_reg(const BoxPlan& p, int variant, int nb, const double* vscaled,
+                                cplx* T, hipStream_t s) {
   const size_t lds = plane_reg_lds(p);
-  const int threads = plane_reg_threads(p);
-#define CASE(N)                                                                        \
-  if (p.n1 == N && p.n2 == N) {                                                        \
-    hipLaunchKernelGGL((k_plane_reg<N, N>), dim3(p.n3, nb), dim3(threads), lds, s, p,  \
-                       vscaled, T);                                                    \
-    return hipGetLastError();                                                          \
+  const int gmax = variant == 1 ? 8 : 16;
+  const int threads = plane_reg_threads(p, gmax);
+  if (variant == 1) {
+#define CASE(N)                                                                                  \
+    if (p.n1 == N && p.n2 == N) {                                                                \
+      hipLaunchKernelGGL((k_plane_reg<N, N, 8>), dim3(p.n3, nb), dim3(threads), lds, s, p,       \
+                         vscaled, T);                                                            \
+      return hipGetLastError();                                                                  \
+    }
+    PW_NARROW_SIZES(CASE)
+#undef CASE
+    return hipErrorInvalidValue;
+  }
+#define CASE(N)                                                                                  \
+  if (p.n1 == N && p.n2 == N) {                                                                  \
+    hipLaunchKernelGGL((k_plane_reg<N, N, 16>), dim3(p.n3, nb), dim3(threads), lds, s, p,        \
+                       vscaled, T);                                                              \
+    return hipGetLastError();                                                                    \
   }
   PW_FAST_SIZES(CASE)
 #undef CASE
@@ -268,11 +291,19 @@ hipError_t launch_fft_plane_reg(const BoxPlan& p, int nb, const double* vscaled,
 hipError_t fft_reg_set_lds_limits(size_t bytes) {
 #define CASE(N)                                                                              \
   {                                                                                          \
-    hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N>,                       \
+    hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N, 16>,                   \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
     if (e != hipSuccess) return e;                                                           \
   }
   PW_FAST_SIZES(CASE)
+#undef CASE
+#define CASE(N)                                                                              \
+  {                                                                                          \
+    hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N, 8>,                    \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
+    if (e != hipSuccess) return e;                                                           \
+  }
+  PW_NARROW_SIZES(CASE)
 #undef CASE
   return hipSuccess;
 }

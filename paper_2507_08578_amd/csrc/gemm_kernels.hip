@@ -102,7 +102,7 @@ k_gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict_
 __global__ void __launch_bounds__(kThreads)
 k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
           const double* __restrict__ rowscale, const cplx* __restrict__ A, int64_t lda,
-          const cplx* __restrict__ B, int64_t ldb, cplx* __restrict__ out, int64_t ldo,
+          const cplx* __restrict__ B, int64_t ldb, double beta, cplx* __restrict__ out, int64_t ldo,
           int64_t zstride) {
   __shared__ cplx As[kKcCN][kBM + 1];
   __shared__ cplx Bs[kKcCN][kBN + 1];
@@ -159,14 +159,20 @@ k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
         const int64_t j = j0 + wj * 32 + tj * 16 + lr;
         if (i < M && j < N) {
           const double s = alpha * (rowscale ? rowscale[i] : 1.0);
-          o[i + j * ldo] = make_double2(s * accr[ti][tj][r], s * acci[ti][tj][r]);
+          cplx v = make_double2(s * accr[ti][tj][r], s * acci[ti][tj][r]);
+          if (beta != 0.0) {
+            const cplx c = o[i + j * ldo];
+            v.x += beta * c.x;
+            v.y += beta * c.y;
+          }
+          o[i + j * ldo] = v;
         }
       }
 }
 
 // C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M], z in fixed order.
 __global__ void k_splitk_reduce(int64_t M, int64_t N, int nsplit, const cplx* __restrict__ work,
-                                double alpha, const double* __restrict__ rowscale,
+                                double alpha, const double* __restrict__ rowscale, double beta,
                                 cplx* __restrict__ C, int64_t ldc) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
@@ -178,7 +184,13 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int nsplit, const cplx* __
     im += w.y;
   }
   const double s = alpha * (rowscale ? rowscale[i] : 1.0);
-  C[i + j * ldc] = make_double2(s * re, s * im);
+  cplx v = make_double2(s * re, s * im);
+  if (beta != 0.0) {
+    const cplx c = C[i + j * ldc];
+    v.x += beta * c.x;
+    v.y += beta * c.y;
+  }
+  C[i + j * ldc] = v;
 }
 
 struct SplitPlan {
@@ -210,23 +222,23 @@ size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k) {
 
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
-                          cplx* work, hipStream_t s) {
+                          cplx* work, hipStream_t s, double beta) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const SplitPlan p = split_plan(m, n, k);
   if (p.nsplit == 1) {
     dim3 grid(p.tiles_n, p.tiles_m, 1);
     hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, alpha, rowscale,
-                       A, lda, B, ldb, C, ldc, (int64_t)0);
+                       A, lda, B, ldb, beta, C, ldc, (int64_t)0);
     return hipGetLastError();
   }
   dim3 grid(p.tiles_n, p.tiles_m, p.nsplit);
   hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, 1.0,
-                     (const double*)nullptr, A, lda, B, ldb, work, m, m * n);
+                     (const double*)nullptr, A, lda, B, ldb, 0.0, work, m, m * n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = m * n;
   hipLaunchKernelGGL(k_splitk_reduce, dim3((tot + 255) / 256), dim3(256), 0, s, m, n,
-                     (int)p.nsplit, (const cplx*)work, alpha, rowscale, C, ldc);
+                     (int)p.nsplit, (const cplx*)work, alpha, rowscale, beta, C, ldc);
   return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ struct pw_ctx {
   double acc_ms[PW_STAGE_COUNT] = {0};
   int64_t launches[PW_STAGE_COUNT] = {0};
   double* pinned = nullptr;   // small pinned host scratch (64 doubles)
+  int last_sweeps = 0;        // sweeps of the last dense eigensolve
 
   hipEvent_t get_event() {
     if (!pool.empty()) {
@@ -67,6 +68,9 @@ struct pw_ham {
   cplx* sub1 = nullptr;
   void* heev_work = nullptr;
   int* status_dev = nullptr;
+  cplx* dinv = nullptr;     // inverses of the Cholesky diagonal blocks
+  cplx* panel = nullptr;    // kb x nb_max row panel
+  double* dtol = nullptr;   // pivot threshold
 };
 
 namespace {
@@ -205,9 +209,54 @@ pw_status rotate_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, const cplx* m
 }
 
 pw_status heev_status(pw_ctx* c, int sweeps) {
+  c->last_sweeps = sweeps;
   if (sweeps < 0)
     return fail(c, PW_ERR_NO_CONVERGENCE, "Jacobi eigensolver did not converge in its sweep limit");
   return PW_OK;
+}
+
+// Blocked upper Cholesky a = U^H U in place (upper triangle read; blocks
+// below the diagonal are left with scratch values).  dinv receives the
+// inverse of diagonal block j at dinv + j*kb*kb (ld = that block's size);
+// panel holds kb x n; status[0] = -1 or the failing pivot.
+hipError_t chol_blocked(int64_t n, cplx* a, int64_t lda, cplx* dinv, cplx* panel, double* tol,
+                        int* status, hipStream_t s) {
+  const int kb = kCholBlock;
+  hipError_t e = launch_chol_init(n, a, lda, tol, status, s);
+  for (int64_t k0 = 0; k0 < n && e == hipSuccess; k0 += kb) {
+    const int kbk = (int)std::min<int64_t>(kb, n - k0);
+    const int64_t m = n - k0 - kbk;
+    cplx* dk = dinv + (k0 / kb) * kb * kb;
+    e = launch_chol_diag(kbk, (int)k0, a, lda, dk, tol, status, s);
+    if (e != hipSuccess || m == 0) break;
+    cplx* row = a + k0 + (k0 + kbk) * lda;                       // U[k, k+1:]
+    // row <- U_kk^{-H} A[k, k+1:]  (K = kbk <= 64: one split, no workspace)
+    e = launch_gemm_cn(kbk, m, kbk, 1.0, dk, kbk, row, lda, panel, kbk, nullptr, nullptr, s);
+    if (e == hipSuccess) e = launch_copy_block(kbk, m, panel, kbk, row, lda, s);
+    // A[k+1:, k+1:] -= row^H row
+    if (e == hipSuccess)
+      e = launch_gemm_cn(m, m, kbk, -1.0, row, lda, row, lda, a + (k0 + kbk) + (k0 + kbk) * lda, lda,
+                         nullptr, nullptr, s, 1.0);
+  }
+  return e;
+}
+
+// y <- y U^{-1} for a rows x n block (ld), by column blocks J:
+// y[:, J] = (y[:, J] - y[:, <J] U[<J, J]) U_JJ^{-1}.  tmp: rows x kb.
+hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* u, int64_t ldu,
+                      const cplx* dinv, cplx* tmp, hipStream_t s) {
+  const int kb = kCholBlock;
+  hipError_t e = hipSuccess;
+  for (int64_t j0 = 0; j0 < n && e == hipSuccess; j0 += kb) {
+    const int kbj = (int)std::min<int64_t>(kb, n - j0);
+    if (j0 > 0)
+      e = launch_gemm_nn(rows, kbj, j0, -1.0, y, ld, u + j0 * ldu, ldu, 1.0, y + j0 * ld, ld, s);
+    if (e == hipSuccess)
+      e = launch_gemm_nn(rows, kbj, kbj, 1.0, y + j0 * ld, ld, dinv + (j0 / kb) * kb * kb, kbj, 0.0,
+                         tmp, rows, s);
+    if (e == hipSuccess) e = launch_copy_block(rows, kbj, tmp, rows, y + j0 * ld, ld, s);
+  }
+  return e;
 }
 
 }  // namespace
@@ -479,6 +528,9 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
     h->heev_work = hw;
   }
   TRY(dalloc(h, &h->status_dev, 16));
+  TRY(dalloc(h, &h->dinv, (size_t)((h->nb_max + kCholBlock) * kCholBlock)));
+  TRY(dalloc(h, &h->panel, (size_t)(kCholBlock * h->nb_max)));
+  TRY(dalloc(h, &h->dtol, 2));
   HIPCHK(ctx, hipStreamSynchronize(s));
 #undef TRY
   *out = h;
@@ -581,7 +633,7 @@ pw_status pw_orthonormalize(pw_ham* h, pw_prec gram_prec, int64_t nb, void* yv, 
   }
   {
     StageScope sc(c, PW_STAGE_CHOL);
-    HIPCHK(c, launch_potrf_inv(nb, h->sub0, nb, h->sub1, nb, h->status_dev, s));
+    HIPCHK(c, chol_blocked(nb, h->sub0, nb, h->dinv, h->panel, h->dtol, h->status_dev, s));
   }
   int status = 0;
   HIPCHK(c, hipMemcpyAsync(&status, h->status_dev, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -589,8 +641,12 @@ pw_status pw_orthonormalize(pw_ham* h, pw_prec gram_prec, int64_t nb, void* yv, 
   if (status >= 0)
     return fail(c, PW_ERR_NOT_POSDEF,
                 "Gram matrix not positive definite at pivot " + std::to_string(status));
-  if ((st = rotate_block(h, nb, y, ld, h->sub1)) != PW_OK) return st;
-  if (hyv && (st = rotate_block(h, nb, static_cast<cplx*>(hyv), ldhy, h->sub1)) != PW_OK) return st;
+  {
+    StageScope sc(c, PW_STAGE_ROTATE);
+    HIPCHK(c, trsm_right(h->npw, nb, y, ld, h->sub0, nb, h->dinv, h->blk, s));
+    if (hyv)
+      HIPCHK(c, trsm_right(h->npw, nb, static_cast<cplx*>(hyv), ldhy, h->sub0, nb, h->dinv, h->blk, s));
+  }
   return PW_OK;
 }
 
@@ -741,13 +797,31 @@ pw_status pw_potrf_inv(pw_ctx* c, int64_t n, void* a, int64_t lda, void* ainv, i
   pw_ham tmp;
   tmp.ctx = c;
   int* stat = nullptr;
-  pw_status st = dalloc(&tmp, &stat, 1);
-  if (st != PW_OK) return st;
-  hipError_t e = launch_potrf_inv(n, static_cast<cplx*>(a), lda, static_cast<cplx*>(ainv), ldi,
-                                  stat, c->stream);
+  double* tol = nullptr;
+  cplx* dinv = nullptr;
+  cplx* panel = nullptr;
+  cplx* ytmp = nullptr;
+  pw_status st = PW_OK;
+  if ((st = dalloc(&tmp, &stat, 1)) != PW_OK || (st = dalloc(&tmp, &tol, 1)) != PW_OK ||
+      (st = dalloc(&tmp, &dinv, (size_t)((n + kCholBlock) * kCholBlock))) != PW_OK ||
+      (st = dalloc(&tmp, &panel, (size_t)(kCholBlock * n))) != PW_OK ||
+      (st = dalloc(&tmp, &ytmp, (size_t)(kCholBlock * n))) != PW_OK) {
+    free_ham(&tmp);
+    return st;
+  }
+  cplx* A = static_cast<cplx*>(a);
+  cplx* X = static_cast<cplx*>(ainv);
+  hipStream_t s = c->stream;
+  hipError_t e = chol_blocked(n, A, lda, dinv, panel, tol, stat, s);
   int hs = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&hs, stat, sizeof(int), hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hs, stat, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && hs < 0) {
+    e = launch_zero_lower(n, A, lda, s);
+    if (e == hipSuccess) e = launch_identity(n, X, ldi, s);
+    if (e == hipSuccess) e = trsm_right(n, n, X, ldi, A, lda, dinv, ytmp, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
   free_ham(&tmp);
   if (e != hipSuccess) return fail(c, PW_ERR_HIP, hipGetErrorString(e));
   if (hs >= 0) return fail(c, PW_ERR_NOT_POSDEF, "matrix not positive definite at pivot " + std::to_string(hs));
@@ -786,6 +860,12 @@ pw_status pw_ctx_stage_time(pw_ctx* c, int stage, double* total_ms, int64_t* lau
   if (st != PW_OK) return st;
   if (total_ms) *total_ms = c->acc_ms[stage];
   if (launches) *launches = c->launches[stage];
+  return PW_OK;
+}
+
+pw_status pw_ctx_last_sweeps(const pw_ctx* c, int* sweeps) {
+  if (!c || !sweeps) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx or sweeps is NULL");
+  *sweeps = c->last_sweeps;
   return PW_OK;
 }
 

@@ -49,6 +49,7 @@ struct FftLaunchCfg {
   size_t col_lds, plane_lds;
   bool reg_col;             // register-resident column kernels available for N3
   bool reg_plane;           // register-resident plane kernel available for (N1, N2)
+  int plane_variant;        // register plane kernel: 0 = lane groups <= 16, 1 = <= 8
 };
 
 // Host-side choice of tiles and LDS sizes; returns false if this GPU's LDS
@@ -78,22 +79,23 @@ hipError_t fft_set_lds_limits(size_t bytes);
 // Register-resident variants (fft_reg.hip) for the box lengths they are built for.
 bool fft_reg_col_supported(int n3);
 bool fft_reg_plane_supported(const BoxPlan& p, size_t lds_limit);
+bool fft_reg_plane_narrow(const BoxPlan& p);   // an 8-lane plane variant exists
 hipError_t fft_reg_set_lds_limits(size_t bytes);
 hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int64_t ldpsi, cplx* T,
                                   hipStream_t s);
-hipError_t launch_fft_plane_reg(const BoxPlan& p, int nb, const double* vscaled, cplx* T,
-                                hipStream_t s);
+hipError_t launch_fft_plane_reg(const BoxPlan& p, int variant, int nb, const double* vscaled,
+                                cplx* T, hipStream_t s);
 hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const double* kin,
                                   const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev,
                                   cplx* out, int64_t ldout, double alpha, double beta, double gamma,
                                   hipStream_t s);
 
-// Split-K C = alpha * A^H B (see pw_gemm_cn).  `work` holds splits*m*n cplx;
-// rowscale (m doubles on device, may be null) multiplies row i of the result.
+// Split-K C = alpha diag(rowscale) A^H B + beta C (see pw_gemm_cn).  `work`
+// holds splits*m*n cplx; rowscale (m doubles on device) may be null.
 size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k);
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
-                          cplx* work, hipStream_t s);
+                          cplx* work, hipStream_t s, double beta = 0.0);
 hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
                           hipStream_t s);
@@ -113,9 +115,15 @@ hipError_t launch_axpby_block(int64_t npw, int64_t nb, double a, const cplx* x, 
                               const cplx* y, int64_t ldy, cplx* out, int64_t ldo, hipStream_t s);
 // status: 0 if every element finite, else 1
 hipError_t launch_check_finite(int64_t n, const double* x, int* flag, hipStream_t s);
-// upper Cholesky + inverse, status[0] = -1 on success else failing pivot index
-hipError_t launch_potrf_inv(int64_t n, cplx* a, int64_t lda, cplx* ainv, int64_t ldi, int* status,
+// Blocked Cholesky pieces: tol = n eps max diag, status = -1; per diagonal
+// block (kb <= 64) factor + inverse of the factor in LDS.
+constexpr int kCholBlock = 64;
+hipError_t launch_chol_init(int64_t n, const cplx* a, int64_t lda, double* tol, int* status,
                             hipStream_t s);
+hipError_t launch_chol_diag(int kb, int k0, cplx* a, int64_t lda, cplx* dinv, const double* tol,
+                            int* status, hipStream_t s);
+hipError_t launch_zero_lower(int64_t n, cplx* a, int64_t lda, hipStream_t s);
+hipError_t launch_identity(int64_t n, cplx* a, int64_t lda, hipStream_t s);
 // Cyclic Jacobi eigensolver of a Hermitian n x n matrix (a is destroyed):
 // w ascending, q = eigenvectors.  work: heev_work_bytes(n) device bytes;
 // host_scratch: >= 4 doubles of pinned host memory.  Synchronises the stream

@@ -41,7 +41,7 @@ def hpd(rng, n, cond=1e3):
     return (Q * d) @ Q.conj().T
 
 
-@pytest.mark.parametrize("n", [1, 16, 64, 100, 160])
+@pytest.mark.parametrize("n", [1, 16, 64, 100, 160, 200])
 def test_potrf_inv(ctx, n):
     rng = np.random.default_rng(n)
     S = hpd(rng, n)
@@ -65,7 +65,7 @@ def test_potrf_not_posdef(pw, ctx):
     assert e.value.status == 5 and "pivot 4" in str(e.value)
 
 
-@pytest.mark.parametrize("n", [1, 2, 16, 24, 63, 64, 65, 100, 160])
+@pytest.mark.parametrize("n", [1, 2, 16, 24, 63, 64, 65, 100, 160, 257, 512])
 def test_heev_random(ctx, n):
     rng = np.random.default_rng(100 + n)
     M = crand(rng, n, n)
@@ -74,17 +74,18 @@ def test_heev_random(ctx, n):
     w, Q = to_host(w), to_host(Qd).T
     ref = np.linalg.eigvalsh(A)
     scale = np.abs(ref).max()
+    assert ctx.last_sweeps() > 0 or n == 1
     assert np.abs(w - ref).max() < 1e-12 * scale
     assert np.abs(Q.conj().T @ Q - np.eye(n)).max() < 1e-12
     assert np.abs(A @ Q - Q * w[None, :]).max() < 1e-11 * scale
 
 
-@pytest.mark.parametrize("n", [24, 96])
+@pytest.mark.parametrize("n", [24, 96, 129])
 def test_heev_degenerate(ctx, n):
     """Exactly repeated eigenvalues (multiplets, as cubic cells produce)."""
     rng = np.random.default_rng(n)
     Q0, _ = np.linalg.qr(crand(rng, n, n))
-    lam = np.repeat(np.linspace(-1.0, 2.0, n // 6), 6)[:n]
+    lam = np.repeat(np.linspace(-1.0, 2.0, -(-n // 6)), 6)[:n]
     A = (Q0 * lam) @ Q0.conj().T
     A = 0.5 * (A + A.conj().T)
     w, Qd = ctx.heev(to_dev(A.T.copy()))
