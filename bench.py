@@ -2,16 +2,22 @@
 """Benchmark: Chebyshev-filtered subspace iteration on one MI355X.
 
 One step = one filter iteration of the hot path on one block: Chebyshev
-filter of degree m (H*psi applications), Cholesky orthonormalisation and
-Rayleigh-Ritz (one more H*psi), exactly as the solver runs it.  Inputs are
-synthetic diamond cells (see synth/), resident in HBM before timing.
+filter of degree m (H*psi applications, reusing the H*Y left by the previous
+Rayleigh-Ritz), Cholesky orthonormalisation and Rayleigh-Ritz (one more
+H*psi, always FP64).  Inputs are synthetic diamond cells (synth/), resident
+in HBM before timing.
 
-Prints one JSON line (rank 0):
-  value       = band*H*psi applications per second over the timed steps
-  ms_per_step = filter-iteration time
-  roofline    = the dominant kernel against its roofline (HIP events on the
-                library's stream), traffic from rocprofv3 counters if given
-  cpu_baseline= the FP64 oracle timed on the host on a bounded band sample
+The default run times the mixed path (filter in FP32: FFT route in FP32,
+projector products on FP32 MFMA; orthonormalisation and Rayleigh-Ritz in
+FP64) and then the plain FP64 path from the same start block, and prints one
+JSON line for the mixed path with the FP64 figures and the Ritz-value
+difference between the two trajectories beside it.
+
+  value        band*H*psi applications per second over the timed steps
+  ms_per_step  filter-iteration time
+  roofline     dominant kernel vs its roofline, from HIP events recorded by
+               the library on its own stream over the timed steps
+  cpu_baseline the FP64 oracle's H*psi timed on the host on a band sample
 """
 from __future__ import annotations
 
@@ -26,8 +32,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "band·H·ψ applies/sec + filter-iter time, mixed vs FP64, eig err ≤1e-6 Ha"
 UNIT = "band·H·ψ applies/s"
-PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
-PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+PEAK = {   # MI355X published dense peaks
+    "fp64_mfma": 78.6, "fp32_mfma": 157.3, "bf16_mfma": 2500.0,
+    "fp64_valu": 78.6, "fp32_valu": 157.3, "hbm_gbs": 8000.0,
+}
 
 WORKLOADS = {
     "C1": "8-atom diamond cell a=10.26 bohr, Gamma, ecut 8 Ha, 1189 PW, box 24^3, 8 s-projectors, "
@@ -48,25 +56,57 @@ def make_workload(name):
     return {"C1": synth.config_c1, "C3": synth.config_c3, "C5": synth.config_c5}[name]()
 
 
-def stage_flops_bytes(w, ham, nb):
-    """Algorithmic work of one launch of each single-kernel stage (FP64)."""
-    npw, nproj = w.npw, w.nproj
+def fft_flops(n):
+    import math
+    return 5.0 * n * math.log2(n)
+
+
+def roofline(stages, steps, applies, w, ham, nb, prec):
+    """Dominant single-kernel stage of the filter path against its bound.
+
+    nonlocal (k_gemm_nn: H psi += P C): MFMA, 8 npw nproj nb flop per launch.
+    fft_plane: vector ALU, per band and z-plane 2 (xr 5 N2 log2 N2 + N2 5 N1 log2 N1)
+               + 2 N1 N2 flop (the V product), per launch x bands in the launch.
+    fft_col_inv / fft_col_fwd: HBM, (npw + ncols N3) / (ncols N3 + 2 npw) elements per band.
+    """
     N1, N2, N3 = w.box
     ncols, xr = ham.ncolumns, ham.extent1
-    per_band_fft_bytes = 16 * (2 * npw + 4 * ncols * N3)     # 3-kernel model
-    return {
-        "nonlocal": {"flops": 8.0 * npw * nproj * nb, "bytes": 16.0 * (npw * nproj + 2 * npw * nb)},
-        "proj": {"flops": 8.0 * npw * nproj * nb, "bytes": 16.0 * (npw * nproj + npw * nb)},
-        "fft_per_band_bytes": per_band_fft_bytes,
-        "fft_col_inv_bytes_per_band": 16.0 * (npw + ncols * N3),
-        "fft_plane_bytes_per_band": 16.0 * (2 * ncols * N3),
-        "fft_col_fwd_bytes_per_band": 16.0 * (ncols * N3 + 2 * npw),
-    }
+    elem = 16 if prec == "fp64" else 8
+    cand = {k: v for k, v in stages.items()
+            if k in ("nonlocal", "fft_plane", "fft_col_inv", "fft_col_fwd") and v[1] > 0}
+    dom = max(cand, key=lambda k: cand[k][0])
+    total_ms, launches = cand[dom]
+    avg_ms = total_ms / launches
+    # bands per launch: the FFT kernels run once per band chunk and application
+    bands_per_launch = nb * steps * applies / launches
+    if dom == "nonlocal":
+        fl = 8.0 * w.npw * w.nproj * nb
+        peak = PEAK["fp64_mfma" if prec == "fp64" else ("bf16_mfma" if prec == "bf16" else "fp32_mfma")]
+        ach = fl / (avg_ms * 1e-3) / 1e12
+        return {"kernel": "k_gemm_nn (H psi += P C)", "bound": "mfma", "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "avg_launch_ms": avg_ms,
+                "per_launch": f"8*npw*nproj*nb = {fl:.4g} flop"}
+    if dom == "fft_plane":
+        per_band = N3 * (2 * (xr * fft_flops(N2) + N2 * fft_flops(N1)) + 2.0 * N1 * N2)
+        fl = per_band * bands_per_launch
+        peak = PEAK["fp64_valu" if prec == "fp64" else "fp32_valu"]
+        ach = fl / (avg_ms * 1e-3) / 1e12
+        return {"kernel": "k_plane_reg (N2/N1 transforms x V per z-plane)", "bound": "alu",
+                "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "avg_launch_ms": avg_ms,
+                "per_launch": f"{per_band:.4g} flop/band (5 N log2 N per transform) x "
+                              f"{bands_per_launch:.0f} bands",
+                "hbm_view": {"bytes_per_band": elem * 2 * ncols * N3,
+                             "GBs": elem * 2 * ncols * N3 * bands_per_launch / (avg_ms * 1e-3) / 1e9}}
+    per_band = elem * ((w.npw + ncols * N3) if dom == "fft_col_inv" else (ncols * N3 + 2 * w.npw))
+    ach = per_band * bands_per_launch / (avg_ms * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+            "frac": ach / PEAK["hbm_gbs"], "avg_launch_ms": avg_ms,
+            "per_launch": f"{per_band:.4g} B/band x {bands_per_launch:.0f} bands"}
 
 
 def cpu_baseline(w, nb_sample, seed=0):
     """Oracle H*psi on nb_sample bands of the same workload, timed on the host."""
-    import numpy as np
     import oracle
     import synth
     try:
@@ -86,22 +126,63 @@ def cpu_baseline(w, nb_sample, seed=0):
                       f"(numpy FFT + BLAS), {dt:.2f} s"}
 
 
+def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup):
+    """Iteration 0 + warmup + timed steps from X0; returns timings and the last Ritz values."""
+    import torch
+    nb = w.nb
+    Y = X0.clone()
+    HY = torch.empty_like(Y)
+    eig = torch.empty(nb, dtype=torch.float64, device="cuda")
+    resid = torch.empty(nb, dtype=torch.float64, device="cuda")
+    ham.orthonormalize(Y)
+    ham.rayleigh_ritz(Y, HY, eig, resid)
+    lam = eig.cpu()
+    sweeps = []
+
+    def step():
+        nonlocal lam
+        ham.cheb_filter(Y, w.degree, float(lam[-1]), b, float(lam[0]), hx=HY, prec=prec)
+        ham.orthonormalize(Y)
+        ham.rayleigh_ritz(Y, HY, eig, resid)
+        sweeps.append(ctx.last_sweeps())
+        lam = eig.cpu()
+
+    for i in range(warmup):
+        step()
+        log(f"{prec}: warmup {i + 1}/{warmup} done")
+    ctx.set_timing(True)
+    ctx.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step()
+        log(f"{prec}: step {i + 1}/{steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.set_timing(False)
+    applies = w.degree                       # (degree - 1) filter products + 1 in Rayleigh-Ritz
+    return {"ms_per_step": 1e3 * dt / steps, "value": applies * nb * steps / dt,
+            "stages": stages, "applies": applies, "lam": lam.numpy().copy(),
+            "max_resid": float(resid.max().cpu()), "sweeps": sweeps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C5", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"],
+                    help="filter precision of the reported path (subspace steps are FP64)")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=0, help="oracle band sample (0 = auto)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="per-kernel HBM bytes measured with rocprofv3 counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
     import synth
     import paper_2507_08578_amd as pw
@@ -111,88 +192,38 @@ def main():
     nb = w.nb
     log(f"npw={w.npw} nproj={w.nproj} box={w.box} nb={nb} degree={w.degree}")
     ctx = pw.Context(0)
-    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=nb)
+    mixed = args.precision != "fp64"
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=nb, low_prec=mixed)
     X0 = torch.from_numpy(synth.start_block(w.npw, nb, 0)).cuda()
-    Y = X0.clone()
-    HY = torch.empty_like(Y)
-    eig = torch.empty(nb, dtype=torch.float64, device="cuda")
-    resid = torch.empty(nb, dtype=torch.float64, device="cuda")
-    log("upper bound + iteration 0")
+    log("upper bound")
     b = ham.upper_bound()
-    ham.orthonormalize(Y)
-    ham.rayleigh_ritz(Y, HY, eig, resid)
-    lam = eig.cpu()
-
-    sweeps = []
-
-    def step():
-        nonlocal lam
-        ham.cheb_filter(Y, w.degree, float(lam[-1]), b, float(lam[0]), hx=HY)
-        ham.orthonormalize(Y)
-        ham.rayleigh_ritz(Y, HY, eig, resid)
-        sweeps.append(ctx.last_sweeps())
-        lam = eig.cpu()
-
-    for i in range(args.warmup):
-        step()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    ctx.set_timing(True)
-    ctx.reset_timing()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-        log(f"step {i + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    stages = ctx.stage_times()
-    ctx.set_timing(False)
-    applies_per_step = (w.degree - 1) + 1          # filter reuses H Y from Rayleigh-Ritz
-    ms_per_step = 1e3 * dt / args.steps
-    value = applies_per_step * nb * args.steps / dt
-
-    # dominant single-kernel stage and its roofline
-    work = stage_flops_bytes(w, ham, nb)
-    cand = {k: v for k, v in stages.items() if k in ("nonlocal", "fft_plane", "fft_col_inv",
-                                                      "fft_col_fwd") and v[1] > 0}
-    dom = max(cand, key=lambda k: cand[k][0])
-    avg_ms = cand[dom][0] / cand[dom][1]
-    traffic = None
-    try:
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        traffic = tj.get(args.config, {}).get(dom)
-    except (OSError, ValueError):
-        traffic = None
-    if dom == "nonlocal":
-        ach = work["nonlocal"]["flops"] / (avg_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_gemm_nn (H psi += P C)", "bound": "mfma", "achieved": ach,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
-                "traffic": traffic, "avg_launch_ms": avg_ms,
-                "per_launch": f"8*npw*nproj*nb = {work['nonlocal']['flops']:.4g} flop"}
-    else:
-        per_band = work[f"{dom}_bytes_per_band"]
-        # launches per step = number of band chunks; bytes per launch = bands per launch * per_band
-        launches_per_apply = max(1, round(cand[dom][1] / (args.steps * applies_per_step)))
-        chunk_bands = nb / launches_per_apply
-        ach = per_band * chunk_bands / (avg_ms * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": traffic,
-                "avg_launch_ms": avg_ms,
-                "per_launch": f"{per_band:.4g} B/band x {chunk_bands:.0f} bands"}
+    res = run_path(pw, ctx, ham, w, X0, b, args.precision, args.steps, args.warmup)
+    ref = None
+    if mixed and not args.no_compare:
+        ref = run_path(pw, ctx, ham, w, X0, b, "fp64", args.steps, args.warmup)
+    roof = roofline(res["stages"], args.steps, res["applies"], w, ham, nb, args.precision)
+    dtype = "f64" if not mixed else ("f32+f64" if args.precision == "fp32" else "bf16/f32+f64")
     out = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "precision": "fp64",
+        "metric": METRIC, "value": res["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
+                   "filter_precision": args.precision, "subspace_precision": "fp64",
                    "step": f"filter (degree {w.degree}, H*Y reused) + Cholesky + Rayleigh-Ritz",
-                   "applies_per_step": applies_per_step, "nb": nb},
-        "filter_iter_ms": ms_per_step,
-        "max_resid": float(resid.max().cpu()),
-        "eigensolver_sweeps": sweeps,
+                   "applies_per_step": res["applies"], "nb": nb},
+        "filter_iter_ms": res["ms_per_step"],
+        "max_resid": res["max_resid"],
+        "eigensolver_sweeps": res["sweeps"],
         "roofline": roof,
-        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in res["stages"].items()},
     }
+    if ref is not None:
+        d = float(abs(res["lam"] - ref["lam"]).max())
+        out["fp64_path"] = {"ms_per_step": ref["ms_per_step"], "value": ref["value"],
+                            "speedup_mixed_over_fp64": ref["ms_per_step"] / res["ms_per_step"],
+                            "stages_ms_per_step": {k: v[0] / args.steps
+                                                   for k, v in ref["stages"].items()}}
+        out["eig_diff_vs_fp64_Ha"] = d
     if not args.no_cpu_baseline:
         nbs = args.cpu_bands or {"C1": 256, "C3": 64, "C5": 64}[args.config]
         log(f"cpu baseline: oracle H*psi on {nbs} bands")

@@ -18,9 +18,12 @@
  *    pw_last_error() holds a message.
  *  - A block of nb wavefunctions is a column-major npw x nb complex matrix
  *    (band b occupies elements [b*ld, b*ld + npw)), ld >= npw, complex values
- *    interleaved (re, im).  Precision PW_FP64 = complex128 (the only block
- *    precision accepted in this version; other values return
- *    PW_ERR_UNSUPPORTED).
+ *    interleaved (re, im).  pw_apply_h blocks are complex128 for PW_FP64 and
+ *    complex64 for PW_FP32 / PW_BF16; every other entry point takes
+ *    complex128 blocks whatever its internal precision.
+ *  - Precision of a call: PW_FP64 everything in FP64.  PW_FP32: FFT route in
+ *    FP32, projector products on FP32 MFMA.  PW_BF16: FFT route in FP32,
+ *    projector products with bfloat16 operands.  Both accumulate in FP32.
  *  - Pointers named *_dev are device memory on the context's device, owned by
  *    the caller; the library never frees them.  Pointers named *_host are host
  *    memory read during the call only.
@@ -101,6 +104,10 @@ const char* pw_last_error(const pw_ctx* ctx);
  *   nb_max   largest block size that will be passed to this handle (> 0);
  *            workspaces are sized for it at creation so hot calls allocate
  *            nothing.
+ *   low_prec 0: FP64 only.  1: also build the FP32 copies (projectors,
+ *            V/N_box, kinetic energies, twiddles) and complex64 workspaces
+ *            that PW_FP32 / PW_BF16 calls need (cubic boxes of the lengths
+ *            with register-resident FFT kernels; else UNSUPPORTED).
  */
 typedef struct {
   int32_t n[3];
@@ -113,6 +120,7 @@ typedef struct {
   const void* proj_dev;
   const double* ekb;
   int64_t nb_max;
+  int32_t low_prec;
 } pw_ham_desc;
 
 /* Build the plans (sphere columns, box extents, twiddle tables, kinetic
@@ -144,6 +152,8 @@ pw_status pw_apply_h(pw_ham* ham, pw_prec prec, int64_t nb, const void* psi_dev,
  * with s = e/(a0-c), s' = 1/(2/s_1 - s).  Requires a0 < a < b.
  * hx_dev (may be NULL): H X already computed (e.g. by the previous
  * Rayleigh-Ritz); then only m-1 products are formed.
+ * prec PW_FP32 / PW_BF16: y and hx stay complex128; the recurrence runs on
+ * complex64 copies (y converted on entry, the result converted back).
  */
 pw_status pw_cheb_filter(pw_ham* ham, pw_prec prec, int32_t degree, double a, double b, double a0,
                          int64_t nb, void* y_dev, int64_t ld, const void* hx_dev, int64_t ldhx);

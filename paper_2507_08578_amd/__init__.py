@@ -37,10 +37,22 @@ def _check(status: int, ctx_handle=None):
         raise PWError(status, f"{status_string(status)}: {msg}")
 
 
-def _block_args(t, npw: int, name: str):
+PRECISIONS = {"fp64": PW_FP64, "fp32": PW_FP32, "bf16": PW_BF16}
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        if p not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _block_args(t, npw: int, name: str, complex64: bool = False):
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.complex128:
-        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    want = torch.complex64 if complex64 else torch.complex128
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != want:
+        raise TypeError(f"{name} must be a {want} CUDA tensor")
     if t.dim() != 2 or t.shape[1] != npw or t.stride(1) != 1:
         raise ValueError(f"{name} must have shape (nb, npw={npw}) with unit stride along npw")
     return ctypes.c_void_p(t.data_ptr()), t.stride(0)
@@ -149,7 +161,8 @@ class Hamiltonian:
     ekb: (nproj,) KB energies.
     """
 
-    def __init__(self, ctx: Context, miller, recip, kpt, box, vloc, proj, ekb, nb_max: int):
+    def __init__(self, ctx: Context, miller, recip, kpt, box, vloc, proj, ekb, nb_max: int,
+                 low_prec: bool = False):
         import torch
         self.ctx = ctx
         miller = np.ascontiguousarray(np.asarray(miller, dtype=np.int32))
@@ -182,7 +195,9 @@ class Hamiltonian:
         d.proj_dev = proj.data_ptr() if self.nproj else None
         d.ekb = ekb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if self.nproj else None
         d.nb_max = int(nb_max)
+        d.low_prec = 1 if low_prec else 0
         self.nb_max = int(nb_max)
+        self.low_prec = bool(low_prec)
         handle = ctypes.c_void_p()
         ctx.check(_LIB.pw_ham_create(ctx.handle, ctypes.byref(d), ctypes.byref(handle)))
         self.handle = handle
@@ -193,13 +208,14 @@ class Hamiltonian:
         self.box = (N1, N2, N3)
 
     @staticmethod
-    def from_workload(ctx: Context, w, nb_max: Optional[int] = None, device: str = "cuda"):
+    def from_workload(ctx: Context, w, nb_max: Optional[int] = None, device: str = "cuda",
+                      low_prec: bool = False):
         """Build from a synth.Workload (arrays copied to the device here)."""
         import torch
         vloc = torch.from_numpy(np.ascontiguousarray(w.vloc)).to(device)
         proj = torch.from_numpy(np.ascontiguousarray(w.proj)).to(device) if w.nproj else None
         return Hamiltonian(ctx, w.miller, w.recip, w.kred, w.box, vloc, proj, w.ekb,
-                           nb_max or w.nb)
+                           nb_max or w.nb, low_prec=low_prec)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -213,23 +229,27 @@ class Hamiltonian:
             pass
 
     # --- hot path ---
-    def apply_h(self, psi, out=None):
+    def apply_h(self, psi, out=None, prec="fp64"):
+        """H psi; complex128 blocks for fp64, complex64 blocks for fp32/bf16."""
         import torch
-        p, ldp = _block_args(psi, self.npw, "psi")
+        pr = _prec(prec)
+        c64 = pr != PW_FP64
+        p, ldp = _block_args(psi, self.npw, "psi", c64)
         if out is None:
             out = torch.empty_like(psi)
-        o, ldo = _block_args(out, self.npw, "out")
-        self.ctx.check(_LIB.pw_apply_h(self.handle, PW_FP64, psi.shape[0], p, ldp, o, ldo))
+        o, ldo = _block_args(out, self.npw, "out", c64)
+        self.ctx.check(_LIB.pw_apply_h(self.handle, pr, psi.shape[0], p, ldp, o, ldo))
         return out
 
-    def cheb_filter(self, y, degree: int, a: float, b: float, a0: float, hx=None):
+    def cheb_filter(self, y, degree: int, a: float, b: float, a0: float, hx=None, prec="fp64"):
+        """y <- p_m(H) y in place (complex128 block; prec selects the internal arithmetic)."""
         p, ld = _block_args(y, self.npw, "y")
         if hx is not None:
             hp, ldh = _block_args(hx, self.npw, "hx")
         else:
             hp, ldh = None, 0
-        self.ctx.check(_LIB.pw_cheb_filter(self.handle, PW_FP64, int(degree), float(a), float(b),
-                                           float(a0), y.shape[0], p, ld, hp, ldh))
+        self.ctx.check(_LIB.pw_cheb_filter(self.handle, _prec(prec), int(degree), float(a),
+                                           float(b), float(a0), y.shape[0], p, ld, hp, ldh))
         return y
 
     def orthonormalize(self, y, hy=None):

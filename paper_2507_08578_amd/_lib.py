@@ -36,6 +36,7 @@ class PwHamDesc(ctypes.Structure):
         ("proj_dev", c_void_p),
         ("ekb", ctypes.POINTER(c_double)),
         ("nb_max", c_int64),
+        ("low_prec", c_int32),
     ]
 
 

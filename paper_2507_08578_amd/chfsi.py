@@ -28,8 +28,11 @@ class ChfsiState:
 
 
 def chfsi(ham, X0, degree: int, iters: int, upper: Optional[float] = None,
-          reuse_hx: bool = True, record: bool = True,
+          reuse_hx: bool = True, record: bool = True, filter_prec="fp64",
           callback: Optional[Callable[[int, ChfsiState], None]] = None) -> ChfsiState:
+    """filter_prec: "fp64", "fp32", "bf16", or a callable t -> precision for
+    iteration t (a precision ladder, e.g. bf16 early and fp32 late).  The
+    orthonormalisation and Rayleigh-Ritz always run in FP64."""
     import torch
     nb = X0.shape[0]
     Y = X0.clone()
@@ -48,7 +51,9 @@ def chfsi(ham, X0, degree: int, iters: int, upper: Optional[float] = None,
     if callback:
         callback(0, st)
     for t in range(1, iters + 1):
-        ham.cheb_filter(Y, degree, float(lam[-1]), b, float(lam[0]), hx=HY if reuse_hx else None)
+        fp = filter_prec(t) if callable(filter_prec) else filter_prec
+        ham.cheb_filter(Y, degree, float(lam[-1]), b, float(lam[0]), hx=HY if reuse_hx else None,
+                        prec=fp)
         st.applies += degree - 1 if reuse_hx else degree
         ham.orthonormalize(Y)
         ham.rayleigh_ritz(Y, HY, eig, resid)

@@ -602,6 +602,49 @@ __global__ void __launch_bounds__(1024) k_offnorm(int n, const cplx* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// precision conversions for the low-precision filter path
+// ---------------------------------------------------------------------------
+__global__ void k_block_to_f32(int64_t rows, int64_t cols, const cplx* __restrict__ x, int64_t ldx,
+                               float2* __restrict__ y, int64_t ldy) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = idx - j * rows;
+  const cplx v = x[i + j * ldx];
+  y[i + j * ldy] = make_float2((float)v.x, (float)v.y);
+}
+
+__global__ void k_block_to_f64(int64_t rows, int64_t cols, const float2* __restrict__ x, int64_t ldx,
+                               cplx* __restrict__ y, int64_t ldy) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = idx - j * rows;
+  const float2 v = x[i + j * ldx];
+  y[i + j * ldy] = make_double2((double)v.x, (double)v.y);
+}
+
+// out = fp32(a x + b y), x and y FP64
+__global__ void k_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx* __restrict__ x,
+                               int64_t ldx, double b, const cplx* __restrict__ y, int64_t ldy,
+                               float2* __restrict__ out, int64_t ldo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = idx - j * rows;
+  const cplx u = x[i + j * ldx], v = y[i + j * ldy];
+  out[i + j * ldo] = make_float2((float)(a * u.x + b * v.x), (float)(a * u.y + b * v.y));
+}
+
+__global__ void k_real_to_f32(int64_t n, const double* __restrict__ src, double scale,
+                              float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)(scale * src[i]);
+}
+
+__global__ void k_tw_to_f32(int n, const cplx* __restrict__ src, float2* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = make_float2((float)src[i].x, (float)src[i].y);
+}
+
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -652,6 +695,40 @@ hipError_t launch_axpby_block(int64_t npw, int64_t nb, double a, const cplx* x, 
                               const cplx* y, int64_t ldy, cplx* out, int64_t ldo, hipStream_t s) {
   hipLaunchKernelGGL(k_axpby_block, dim3(nblocks(npw * nb, 256)), dim3(256), 0, s, npw, nb, a, x,
                      ldx, b, y, ldy, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_to_f32(int64_t rows, int64_t cols, const cplx* x, int64_t ldx, float2* y,
+                               int64_t ldy, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_to_f32, dim3(nblocks(rows * cols, 256)), dim3(256), 0, s, rows, cols, x,
+                     ldx, y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_to_f64(int64_t rows, int64_t cols, const float2* x, int64_t ldx, cplx* y,
+                               int64_t ldy, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_to_f64, dim3(nblocks(rows * cols, 256)), dim3(256), 0, s, rows, cols, x,
+                     ldx, y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx* x, int64_t ldx,
+                               double b, const cplx* y, int64_t ldy, float2* out, int64_t ldo,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby_to_f32, dim3(nblocks(rows * cols, 256)), dim3(256), 0, s, rows, cols, a,
+                     x, ldx, b, y, ldy, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_to_f32(int64_t n, const double* src, double scale, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_real_to_f32, dim3(nblocks(n, 256)), dim3(256), 0, s, n, src, scale, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_tw_to_f32(int n, const cplx* src, float2* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_tw_to_f32, dim3(nblocks(n, 256)), dim3(256), 0, s, n, src, dst);
   return hipGetLastError();
 }
 

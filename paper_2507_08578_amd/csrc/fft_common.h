@@ -1,22 +1,88 @@
-// Device-side building blocks of the FFT kernels: complex helpers, small
-// DFTs in registers (radix 2, 3, 4, 5, 8 and their products), compile-time
-// twiddles, and transforms spread over a group of G lanes of one wavefront.
+// Device-side building blocks of the FFT kernels, generic over the complex
+// type (double2 for the FP64 path, float2 for the FP32 filter path):
+// complex helpers, small DFTs in registers (radix 2, 3, 4, 5, 8 and their
+// products), compile-time twiddles, and transforms spread over a group of G
+// lanes of one wavefront.
 #pragma once
 
 #include "pw_internal.h"
 
 namespace pwfft {
 
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <class C>
+struct RealOf;
+template <>
+struct RealOf<double2> {
+  using type = double;
+};
+template <>
+struct RealOf<float2> {
+  using type = float;
+};
+template <class C>
+using real_t = typename RealOf<C>::type;
+
+template <class C>
+__device__ __forceinline__ C mkc(double re, double im) {
+  C r;
+  r.x = (real_t<C>)re;
+  r.y = (real_t<C>)im;
+  return r;
 }
-__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
+template <class C>
+__device__ __forceinline__ C czero() {
+  C r;
+  r.x = 0;
+  r.y = 0;
+  return r;
+}
+template <class C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <class C>
+__device__ __forceinline__ C cadd(C a, C b) {
+  C r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <class C>
+__device__ __forceinline__ C csub(C a, C b) {
+  C r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
+}
+template <class C, class S>
+__device__ __forceinline__ C cscale(C a, S s) {
+  C r;
+  r.x = a.x * (real_t<C>)s;
+  r.y = a.y * (real_t<C>)s;
+  return r;
+}
 // (S i) z for S = +1 / -1
-template <int S>
-__device__ __forceinline__ cplx mul_si(cplx z) {
-  return S > 0 ? make_double2(-z.y, z.x) : make_double2(z.y, -z.x);
+template <int S, class C>
+__device__ __forceinline__ C mul_si(C z) {
+  C r;
+  if (S > 0) {
+    r.x = -z.y;
+    r.y = z.x;
+  } else {
+    r.x = z.y;
+    r.y = -z.x;
+  }
+  return r;
+}
+template <class C>
+__device__ __forceinline__ C conj_mul(C a, C w) {   // a * conj(w)
+  C r;
+  r.x = a.x * w.x + a.y * w.y;
+  r.y = a.y * w.x - a.x * w.y;
+  return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -72,61 +138,77 @@ constexpr CW cx_tw(long t, long n) {
 // ---------------------------------------------------------------------------
 // Small DFTs y_k = sum_n x_n exp(S 2 pi i n k / R) in registers.
 // ---------------------------------------------------------------------------
-template <int S>
-__device__ __forceinline__ void dft2(cplx* v) {
-  cplx a = v[0], b = v[1];
+template <int S, class C>
+__device__ __forceinline__ void dft2(C* v) {
+  C a = v[0], b = v[1];
   v[0] = cadd(a, b);
   v[1] = csub(a, b);
 }
-template <int S>
-__device__ __forceinline__ void dft3(cplx* v) {
-  const double h = 0.86602540378443864676;  // sin(2 pi / 3)
-  cplx s = cadd(v[1], v[2]);
-  cplx d = csub(v[1], v[2]);
-  cplx t = make_double2(v[0].x - 0.5 * s.x, v[0].y - 0.5 * s.y);
-  cplx r = mul_si<S>(cscale(d, h));
+template <int S, class C>
+__device__ __forceinline__ void dft3(C* v) {
+  using Rl = real_t<C>;
+  const Rl h = (Rl)0.86602540378443864676;  // sin(2 pi / 3)
+  C s = cadd(v[1], v[2]);
+  C d = csub(v[1], v[2]);
+  C t;
+  t.x = v[0].x - (Rl)0.5 * s.x;
+  t.y = v[0].y - (Rl)0.5 * s.y;
+  C r = mul_si<S>(cscale(d, h));
   v[0] = cadd(v[0], s);
   v[1] = cadd(t, r);
   v[2] = csub(t, r);
 }
-template <int S>
-__device__ __forceinline__ void dft4(cplx* v) {
-  cplx a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-  cplx c = cadd(v[1], v[3]), d = mul_si<S>(csub(v[1], v[3]));
+template <int S, class C>
+__device__ __forceinline__ void dft4(C* v) {
+  C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  C c = cadd(v[1], v[3]), d = mul_si<S>(csub(v[1], v[3]));
   v[0] = cadd(a, c);
   v[2] = csub(a, c);
   v[1] = cadd(b, d);
   v[3] = csub(b, d);
 }
-template <int S>
-__device__ __forceinline__ void dft5(cplx* v) {
-  const double c1 = 0.30901699437494742410;   // cos(2 pi/5)
-  const double c2 = -0.80901699437494742410;  // cos(4 pi/5)
-  const double s1 = 0.95105651629515357212;   // sin(2 pi/5)
-  const double s2 = 0.58778525229247312917;   // sin(4 pi/5)
-  cplx a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
-  cplx a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
-  cplx x0 = v[0];
-  cplx p1 = make_double2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
-  cplx p2 = make_double2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
-  cplx q1 = mul_si<S>(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
-  cplx q2 = mul_si<S>(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
-  v[0] = make_double2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+template <int S, class C>
+__device__ __forceinline__ void dft5(C* v) {
+  using Rl = real_t<C>;
+  const Rl c1 = (Rl)0.30901699437494742410;   // cos(2 pi/5)
+  const Rl c2 = (Rl)-0.80901699437494742410;  // cos(4 pi/5)
+  const Rl s1 = (Rl)0.95105651629515357212;   // sin(2 pi/5)
+  const Rl s2 = (Rl)0.58778525229247312917;   // sin(4 pi/5)
+  C a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+  C a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+  C x0 = v[0];
+  C p1, p2, z;
+  p1.x = x0.x + c1 * a1.x + c2 * a2.x;
+  p1.y = x0.y + c1 * a1.y + c2 * a2.y;
+  p2.x = x0.x + c2 * a1.x + c1 * a2.x;
+  p2.y = x0.y + c2 * a1.y + c1 * a2.y;
+  z.x = s1 * b1.x + s2 * b2.x;
+  z.y = s1 * b1.y + s2 * b2.y;
+  const C q1 = mul_si<S>(z);
+  z.x = s2 * b1.x - s1 * b2.x;
+  z.y = s2 * b1.y - s1 * b2.y;
+  const C q2 = mul_si<S>(z);
+  v[0].x = x0.x + a1.x + a2.x;
+  v[0].y = x0.y + a1.y + a2.y;
   v[1] = cadd(p1, q1);
   v[4] = csub(p1, q1);
   v[2] = cadd(p2, q2);
   v[3] = csub(p2, q2);
 }
-template <int S>
-__device__ __forceinline__ void dft8(cplx* v) {
-  const double h = 0.70710678118654752440;  // sqrt(2)/2
-  cplx e[4] = {v[0], v[2], v[4], v[6]};
-  cplx o[4] = {v[1], v[3], v[5], v[7]};
+template <int S, class C>
+__device__ __forceinline__ void dft8(C* v) {
+  using Rl = real_t<C>;
+  const Rl h = (Rl)0.70710678118654752440;  // sqrt(2)/2
+  C e[4] = {v[0], v[2], v[4], v[6]};
+  C o[4] = {v[1], v[3], v[5], v[7]};
   dft4<S>(e);
   dft4<S>(o);
-  cplx o1 = make_double2(h * (o[1].x - S * o[1].y), h * (o[1].y + S * o[1].x));
-  cplx o2 = mul_si<S>(o[2]);
-  cplx o3 = make_double2(h * (-o[3].x - S * o[3].y), h * (-o[3].y + S * o[3].x));
+  C o1, o3;
+  o1.x = h * (o[1].x - (Rl)S * o[1].y);
+  o1.y = h * (o[1].y + (Rl)S * o[1].x);
+  const C o2 = mul_si<S>(o[2]);
+  o3.x = h * (-o[3].x - (Rl)S * o[3].y);
+  o3.y = h * (-o[3].y + (Rl)S * o[3].x);
   v[0] = cadd(e[0], o[0]);
   v[4] = csub(e[0], o[0]);
   v[1] = cadd(e[1], o1);
@@ -136,8 +218,8 @@ __device__ __forceinline__ void dft8(cplx* v) {
   v[3] = cadd(e[3], o3);
   v[7] = csub(e[3], o3);
 }
-template <int R, int S>
-__device__ __forceinline__ void dft_base(cplx* v) {
+template <int R, int S, class C>
+__device__ __forceinline__ void dft_base(C* v) {
   if constexpr (R == 2) dft2<S>(v);
   else if constexpr (R == 3) dft3<S>(v);
   else if constexpr (R == 4) dft4<S>(v);
@@ -153,18 +235,18 @@ struct Split {
 
 // R-point DFT in registers for R a product of 2, 3, 5 (mixed-radix
 // Cooley-Tukey, n = Q a + b, k = k1 + P k2, compile-time twiddles).
-template <int R, int S>
-__device__ __forceinline__ void dft_reg(cplx* v) {
+template <int R, int S, class C>
+__device__ __forceinline__ void dft_reg(C* v) {
   if constexpr (R == 1) {
     return;
   } else if constexpr (R == 2 || R == 3 || R == 4 || R == 5 || R == 8) {
     dft_base<R, S>(v);
   } else {
     constexpr int P = Split<R>::P, Q = Split<R>::Q;
-    cplx y[Q][P];
+    C y[Q][P];
 #pragma unroll
     for (int b = 0; b < Q; ++b) {
-      cplx u[P];
+      C u[P];
 #pragma unroll
       for (int a = 0; a < P; ++a) u[a] = v[Q * a + b];
       dft_reg<P, S>(u);
@@ -174,13 +256,13 @@ __device__ __forceinline__ void dft_reg(cplx* v) {
           y[b][k1] = u[k1];
         } else {
           const CW w = cx_tw(b * k1, R);           // exp(-2 pi i b k1 / R)
-          y[b][k1] = cmul(u[k1], make_double2(w.re, S > 0 ? -w.im : w.im));
+          y[b][k1] = cmul(u[k1], mkc<C>(w.re, S > 0 ? -w.im : w.im));
         }
       }
     }
 #pragma unroll
     for (int k1 = 0; k1 < P; ++k1) {
-      cplx w[Q];
+      C w[Q];
 #pragma unroll
       for (int b = 0; b < Q; ++b) w[b] = y[b][k1];
       dft_reg<Q, S>(w);
@@ -220,8 +302,16 @@ __device__ __forceinline__ double xor_lane(double x) {
 }
 
 template <int M>
-__device__ __forceinline__ cplx xor_lane(cplx v) {
-  return make_double2(xor_lane<M>(v.x), xor_lane<M>(v.y));
+__device__ __forceinline__ float xor_lane(float x) {
+  return __int_as_float(xor_lane_i32<M>(__float_as_int(x)));
+}
+
+template <int M, class C>
+__device__ __forceinline__ C xor_lane(C v) {
+  C r;
+  r.x = xor_lane<M>(v.x);
+  r.y = xor_lane<M>(v.y);
+  return r;
 }
 
 // Bit reversal of b in log2(G) bits.
@@ -239,12 +329,12 @@ __device__ __forceinline__ int brev(int b) {
 // loaded once and shared by both directions (all exp(-2 pi i t/N) values):
 //   k[q-1] = exp(-2 pi i b q / N), q = 1..R-1      (between registers and lanes)
 //   st[s]  = exp(-2 pi i (b mod h) / (2h)), h = 2^s (cross-lane stage of span h)
-template <int R, int G>
+template <int R, int G, class C>
 struct LaneTw {
   static constexpr int kStages = (G > 1) ? __builtin_ctz(G) : 1;
-  cplx k[R > 1 ? R - 1 : 1];
-  cplx st[kStages];
-  __device__ __forceinline__ void load(int b, const cplx* __restrict__ tw) {
+  C k[R > 1 ? R - 1 : 1];
+  C st[kStages];
+  __device__ __forceinline__ void load(int b, const C* __restrict__ tw) {
     constexpr int N = R * G;
     if constexpr (G > 1) {
 #pragma unroll
@@ -258,10 +348,6 @@ struct LaneTw {
   }
 };
 
-__device__ __forceinline__ cplx conj_mul(cplx a, cplx w) {   // a * conj(w)
-  return make_double2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
-}
-
 // Transform of length N = G R spread over a group of G lanes (lane b, local
 // index in its group), R values per lane.
 //
@@ -270,46 +356,46 @@ __device__ __forceinline__ cplx conj_mul(cplx a, cplx w) {   // a * conj(w)
 // forward  (-):  in : v[k1] = Z[k1 + R brev(b)]    (the backward's layout)
 //                out: v[a]  = X'[G a + b]
 // The forward is the exact adjoint of the backward, stage by stage.
-template <int R, int G, int SI>
-__device__ __forceinline__ void dif_stages(cplx* v, int b, const LaneTw<R, G>& t) {
+template <int R, int G, int SI, class C>
+__device__ __forceinline__ void dif_stages(C* v, int b, const LaneTw<R, G, C>& t) {
   if constexpr (SI >= 0) {
     constexpr int h = 1 << SI;
     const bool up = (b & h) != 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const cplx p = xor_lane<h>(v[r]);
+      const C p = xor_lane<h>(v[r]);
       v[r] = up ? conj_mul(csub(p, v[r]), t.st[SI]) : cadd(v[r], p);
     }
     dif_stages<R, G, SI - 1>(v, b, t);
   }
 }
 
-template <int R, int G, int SI>
-__device__ __forceinline__ void dit_stages(cplx* v, int b, const LaneTw<R, G>& t) {
-  if constexpr (SI < LaneTw<R, G>::kStages) {
+template <int R, int G, int SI, class C>
+__device__ __forceinline__ void dit_stages(C* v, int b, const LaneTw<R, G, C>& t) {
+  if constexpr (SI < LaneTw<R, G, C>::kStages) {
     constexpr int h = 1 << SI;
     const bool up = (b & h) != 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const cplx p = xor_lane<h>(v[r]);
+      const C p = xor_lane<h>(v[r]);
       v[r] = up ? csub(p, cmul(t.st[SI], v[r])) : cadd(v[r], cmul(t.st[SI], p));
     }
     dit_stages<R, G, SI + 1>(v, b, t);
   }
 }
 
-template <int R, int G>
-__device__ __forceinline__ void lane_fft_bwd(cplx* v, int b, const LaneTw<R, G>& t) {
+template <int R, int G, class C>
+__device__ __forceinline__ void lane_fft_bwd(C* v, int b, const LaneTw<R, G, C>& t) {
   dft_reg<R, +1>(v);
   if constexpr (G > 1) {
 #pragma unroll
     for (int k1 = 1; k1 < R; ++k1) v[k1] = conj_mul(v[k1], t.k[k1 - 1]);   // exp(+2 pi i b k1/N)
-    dif_stages<R, G, LaneTw<R, G>::kStages - 1>(v, b, t);
+    dif_stages<R, G, LaneTw<R, G, C>::kStages - 1>(v, b, t);
   }
 }
 
-template <int R, int G>
-__device__ __forceinline__ void lane_fft_fwd(cplx* v, int b, const LaneTw<R, G>& t) {
+template <int R, int G, class C>
+__device__ __forceinline__ void lane_fft_fwd(C* v, int b, const LaneTw<R, G, C>& t) {
   if constexpr (G > 1) {
     dit_stages<R, G, 0>(v, b, t);
 #pragma unroll

@@ -19,27 +19,28 @@ namespace {
 constexpr int kColThreads = 256;
 constexpr int kPlaneMaxThreads = 512;
 
-template <int N3>
+template <int N3, class C>
 __global__ void __launch_bounds__(kColThreads)
-k_col_inv_reg(BoxPlan P, const cplx* __restrict__ psi, int64_t ldpsi, cplx* __restrict__ T) {
+k_col_inv_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ psi, int64_t ldpsi,
+              C* __restrict__ T) {
   constexpr int G = lane_group(N3), R = N3 / G, CT = kColThreads / G, TRS = N3 + 1;
-  __shared__ cplx tile[CT * TRS];
+  __shared__ C tile[CT * TRS];
   const int c0 = blockIdx.x * CT;
   const int b = blockIdx.y;
   const int ncl = min(CT, P.ncols - c0);
-  for (int i = threadIdx.x; i < CT * TRS; i += blockDim.x) tile[i] = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < CT * TRS; i += blockDim.x) tile[i] = czero<C>();
   __syncthreads();
   const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
-  const cplx* src = psi + (size_t)b * ldpsi;
+  const C* src = psi + (size_t)b * ldpsi;
   for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
     tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]] = src[P.pt_perm[k]];
   __syncthreads();
   const int grp = threadIdx.x / G, lb = threadIdx.x % G;
   if (grp < ncl) {
-    cplx v[R];
-    cplx* col = tile + grp * TRS;
-    LaneTw<R, G> tw;
-    tw.load(lb, P.ax3.tw);
+    C v[R];
+    C* col = tile + grp * TRS;
+    LaneTw<R, G, C> tw;
+    tw.load(lb, tw3);
 #pragma unroll
     for (int a = 0; a < R; ++a) v[a] = col[G * a + lb];
     lane_fft_bwd<R, G>(v, lb, tw);
@@ -48,24 +49,27 @@ k_col_inv_reg(BoxPlan P, const cplx* __restrict__ psi, int64_t ldpsi, cplx* __re
     for (int q = 0; q < R; ++q) col[q + base] = v[q];
   }
   __syncthreads();
-  cplx* dst = T + (size_t)b * N3 * P.ncols + c0;
+  C* dst = T + (size_t)b * N3 * P.ncols + c0;
   for (int i = threadIdx.x; i < ncl * N3; i += blockDim.x) {
     const int j3 = i / ncl, lc = i - j3 * ncl;
     dst[(size_t)j3 * P.ncols + lc] = tile[lc * TRS + j3];
   }
 }
 
-template <int N3>
+template <int N3, class C>
 __global__ void __launch_bounds__(kColThreads)
-k_col_fwd_reg(BoxPlan P, const cplx* __restrict__ T, const double* __restrict__ kin,
-              const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev, cplx* out,
-              int64_t ldout, double alpha, double beta, double gamma) {
+k_col_fwd_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ T,
+              const real_t<C>* __restrict__ kin, const C* in, int64_t ldin, const C* prev,
+              int64_t ldprev, C* out, int64_t ldout, double alpha_d, double beta_d,
+              double gamma_d) {
+  using Rl = real_t<C>;
   constexpr int G = lane_group(N3), R = N3 / G, CT = kColThreads / G, TRS = N3 + 1;
-  __shared__ cplx tile[CT * TRS];
+  __shared__ C tile[CT * TRS];
+  const Rl alpha = (Rl)alpha_d, beta = (Rl)beta_d, gamma = (Rl)gamma_d;
   const int c0 = blockIdx.x * CT;
   const int b = blockIdx.y;
   const int ncl = min(CT, P.ncols - c0);
-  const cplx* srcT = T + (size_t)b * N3 * P.ncols + c0;
+  const C* srcT = T + (size_t)b * N3 * P.ncols + c0;
   for (int i = threadIdx.x; i < ncl * N3; i += blockDim.x) {
     const int j3 = i / ncl, lc = i - j3 * ncl;
     tile[lc * TRS + j3] = srcT[(size_t)j3 * P.ncols + lc];
@@ -73,11 +77,11 @@ k_col_fwd_reg(BoxPlan P, const cplx* __restrict__ T, const double* __restrict__ 
   __syncthreads();
   const int grp = threadIdx.x / G, lb = threadIdx.x % G;
   if (grp < ncl) {
-    cplx v[R];
-    cplx* col = tile + grp * TRS;
+    C v[R];
+    C* col = tile + grp * TRS;
     const int base = R * brev<G>(lb);
-    LaneTw<R, G> tw;
-    tw.load(lb, P.ax3.tw);
+    LaneTw<R, G, C> tw;
+    tw.load(lb, tw3);
 #pragma unroll
     for (int q = 0; q < R; ++q) v[q] = col[q + base];
     lane_fft_fwd<R, G>(v, lb, tw);
@@ -86,18 +90,19 @@ k_col_fwd_reg(BoxPlan P, const cplx* __restrict__ T, const double* __restrict__ 
   }
   __syncthreads();
   const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
-  const cplx* inb = in + (size_t)b * ldin;
-  cplx* outb = out + (size_t)b * ldout;
-  const cplx* prevb = prev ? prev + (size_t)b * ldprev : nullptr;
+  const C* inb = in + (size_t)b * ldin;
+  C* outb = out + (size_t)b * ldout;
+  const C* prevb = prev ? prev + (size_t)b * ldprev : nullptr;
   for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
     const int g = P.pt_perm[k];
-    const cplx loc = tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]];
-    const cplx x = inb[g];
-    const double t = kin[g];
-    cplx val = make_double2(alpha * (loc.x + t * x.x) + beta * x.x,
-                            alpha * (loc.y + t * x.y) + beta * x.y);
-    if (gamma != 0.0) {
-      const cplx p = prevb[g];
+    const C loc = tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]];
+    const C x = inb[g];
+    const Rl t = kin[g];
+    C val;
+    val.x = alpha * (loc.x + t * x.x) + beta * x.x;
+    val.y = alpha * (loc.y + t * x.y) + beta * x.y;
+    if (gamma_d != 0.0) {
+      const C p = prevb[g];
       val.x += gamma * p.x;
       val.y += gamma * p.y;
     }
@@ -105,20 +110,21 @@ k_col_fwd_reg(BoxPlan P, const cplx* __restrict__ T, const double* __restrict__ 
   }
 }
 
-template <int N1, int N2, int GMAX>
+template <int N1, int N2, int GMAX, class C>
 __global__ void __launch_bounds__(kPlaneMaxThreads)
-k_plane_reg(BoxPlan P, const double* __restrict__ vs, cplx* __restrict__ T) {
+k_plane_reg(BoxPlan P, const C* __restrict__ tw1, const C* __restrict__ tw2,
+            const real_t<C>* __restrict__ vs, C* __restrict__ T) {
   constexpr int G1 = lane_group(N1, GMAX), R1 = N1 / G1;
   constexpr int G2 = lane_group(N2, GMAX), R2 = N2 / G2;
   constexpr int TRS = N2 + 1;
-  extern __shared__ cplx lds[];
-  cplx* E = lds;                                               // xr x TRS
-  int* slot = reinterpret_cast<int*>(lds + (size_t)P.xr * TRS); // N1 entries
+  extern __shared__ __align__(16) char lds_raw[];
+  C* E = reinterpret_cast<C*>(lds_raw);                            // xr x TRS
+  int* slot = reinterpret_cast<int*>(E + (size_t)P.xr * TRS);      // N1 entries
   const int j3 = blockIdx.x;
   const int b = blockIdx.y;
   const int tid = threadIdx.x, nt = blockDim.x;
-  cplx* tp = T + (size_t)b * P.n3 * P.ncols + (size_t)j3 * P.ncols;
-  for (int i = tid; i < P.xr * TRS; i += nt) E[i] = make_double2(0.0, 0.0);
+  C* tp = T + (size_t)b * P.n3 * P.ncols + (size_t)j3 * P.ncols;
+  for (int i = tid; i < P.xr * TRS; i += nt) E[i] = czero<C>();
   for (int i = tid; i < N1; i += nt) slot[i] = -1;
   __syncthreads();
   for (int e = tid; e < P.xr; e += nt) slot[P.ext_m1[e]] = e;
@@ -128,11 +134,11 @@ k_plane_reg(BoxPlan P, const double* __restrict__ vs, cplx* __restrict__ T) {
   {
     const int grp = tid / G2, lb = tid % G2, ngr = nt / G2;
     const int base = R2 * brev<G2>(lb);
-    LaneTw<R2, G2> tw;
-    tw.load(lb, P.ax2.tw);
+    LaneTw<R2, G2, C> tw;
+    tw.load(lb, tw2);
     for (int e = grp; e < P.xr; e += ngr) {
-      cplx v[R2];
-      cplx* col = E + e * TRS;
+      C v[R2];
+      C* col = E + e * TRS;
 #pragma unroll
       for (int a = 0; a < R2; ++a) v[a] = col[G2 * a + lb];
       lane_fft_bwd<R2, G2>(v, lb, tw);
@@ -145,18 +151,18 @@ k_plane_reg(BoxPlan P, const double* __restrict__ vs, cplx* __restrict__ T) {
   {
     const int grp = tid / G1, lb = tid % G1, ngr = nt / G1;
     const int base = R1 * brev<G1>(lb);
-    LaneTw<R1, G1> tw;
-    tw.load(lb, P.ax1.tw);
-    const double* vp = vs + (size_t)j3 * N2 * N1;
+    LaneTw<R1, G1, C> tw;
+    tw.load(lb, tw1);
+    const real_t<C>* vp = vs + (size_t)j3 * N2 * N1;
     for (int row = grp; row < N2; row += ngr) {
-      cplx v[R1];
+      C v[R1];
 #pragma unroll
       for (int a = 0; a < R1; ++a) {
         const int s = slot[G1 * a + lb];
-        v[a] = s >= 0 ? E[s * TRS + row] : make_double2(0.0, 0.0);
+        v[a] = s >= 0 ? E[s * TRS + row] : czero<C>();
       }
       lane_fft_bwd<R1, G1>(v, lb, tw);
-      const double* vr = vp + (size_t)row * N1 + base;
+      const real_t<C>* vr = vp + (size_t)row * N1 + base;
 #pragma unroll
       for (int q = 0; q < R1; ++q) v[q] = cscale(v[q], vr[q]);
       lane_fft_fwd<R1, G1>(v, lb, tw);
@@ -172,11 +178,11 @@ k_plane_reg(BoxPlan P, const double* __restrict__ vs, cplx* __restrict__ T) {
   {
     const int grp = tid / G2, lb = tid % G2, ngr = nt / G2;
     const int base = R2 * brev<G2>(lb);
-    LaneTw<R2, G2> tw;
-    tw.load(lb, P.ax2.tw);
+    LaneTw<R2, G2, C> tw;
+    tw.load(lb, tw2);
     for (int e = grp; e < P.xr; e += ngr) {
-      cplx v[R2];
-      cplx* col = E + e * TRS;
+      C v[R2];
+      C* col = E + e * TRS;
 #pragma unroll
       for (int q = 0; q < R2; ++q) v[q] = col[q + base];
       lane_fft_fwd<R2, G2>(v, lb, tw);
@@ -188,8 +194,8 @@ k_plane_reg(BoxPlan P, const double* __restrict__ vs, cplx* __restrict__ T) {
   for (int c = tid; c < P.ncols; c += nt) tp[c] = E[P.col_e[c] * TRS + P.col_m2[c]];
 }
 
-size_t plane_reg_lds(const BoxPlan& p) {
-  return (size_t)p.xr * (p.n2 + 1) * sizeof(cplx) + (size_t)p.n1 * sizeof(int);
+size_t plane_reg_lds(const BoxPlan& p, size_t elem) {
+  return (size_t)p.xr * (p.n2 + 1) * elem + (size_t)p.n1 * sizeof(int);
 }
 
 int plane_reg_threads(const BoxPlan& p, int gmax) {
@@ -225,16 +231,26 @@ bool fft_reg_plane_supported(const BoxPlan& p, size_t lds_limit) {
 #define CASE(N) if (p.n1 == N) ok = true;
   PW_FAST_SIZES(CASE)
 #undef CASE
-  return ok && plane_reg_lds(p) <= lds_limit;
+  return ok && plane_reg_lds(p, sizeof(cplx)) <= lds_limit;
 }
 
-hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int64_t ldpsi, cplx* T,
-                                  hipStream_t s) {
+namespace {
+
+template <class C>
+const C* axis_tw(const FftAxis& ax);
+template <>
+const double2* axis_tw<double2>(const FftAxis& ax) { return ax.tw; }
+template <>
+const float2* axis_tw<float2>(const FftAxis& ax) { return ax.tw32; }
+
+template <class C>
+hipError_t col_inv_reg(const BoxPlan& p, int nb, const C* psi, int64_t ldpsi, C* T, hipStream_t s) {
 #define CASE(N)                                                                              \
   if (p.n3 == N) {                                                                           \
     constexpr int CT = kColThreads / lane_group(N);                                          \
     dim3 grid((p.ncols + CT - 1) / CT, nb);                                                  \
-    hipLaunchKernelGGL(k_col_inv_reg<N>, grid, dim3(kColThreads), 0, s, p, psi, ldpsi, T);   \
+    hipLaunchKernelGGL((k_col_inv_reg<N, C>), grid, dim3(kColThreads), 0, s, p,              \
+                       axis_tw<C>(p.ax3), psi, ldpsi, T);                                    \
     return hipGetLastError();                                                                \
   }
   PW_FAST_SIZES(CASE)
@@ -242,16 +258,17 @@ hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const double* kin,
-                                  const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev,
-                                  cplx* out, int64_t ldout, double alpha, double beta, double gamma,
-                                  hipStream_t s) {
+template <class C>
+hipError_t col_fwd_reg(const BoxPlan& p, int nb, const C* T, const real_t<C>* kin, const C* in,
+                       int64_t ldin, const C* prev, int64_t ldprev, C* out, int64_t ldout,
+                       double alpha, double beta, double gamma, hipStream_t s) {
 #define CASE(N)                                                                               \
   if (p.n3 == N) {                                                                            \
     constexpr int CT = kColThreads / lane_group(N);                                           \
     dim3 grid((p.ncols + CT - 1) / CT, nb);                                                   \
-    hipLaunchKernelGGL(k_col_fwd_reg<N>, grid, dim3(kColThreads), 0, s, p, T, kin, in, ldin,  \
-                       prev, ldprev, out, ldout, alpha, beta, gamma);                         \
+    hipLaunchKernelGGL((k_col_fwd_reg<N, C>), grid, dim3(kColThreads), 0, s, p,               \
+                       axis_tw<C>(p.ax3), T, kin, in, ldin, prev, ldprev, out, ldout, alpha,  \
+                       beta, gamma);                                                          \
     return hipGetLastError();                                                                 \
   }
   PW_FAST_SIZES(CASE)
@@ -261,37 +278,41 @@ hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const
 
 // variant 0: lane groups of up to 16 lanes; variant 1: up to 8 lanes (more
 // values per lane, fewer cross-lane stages).
-hipError_t launch_fft_plane_reg(const BoxPlan& p, int variant, int nb, const double* vscaled,
-                                cplx* T, hipStream_t s) {
-  const size_t lds = plane_reg_lds(p);
+template <class C>
+hipError_t plane_reg(const BoxPlan& p, int variant, int nb, const real_t<C>* vscaled, C* T,
+                     hipStream_t s) {
+  const size_t lds = plane_reg_lds(p, sizeof(C));
   const int gmax = variant == 1 ? 8 : 16;
   const int threads = plane_reg_threads(p, gmax);
+  const C* tw1 = axis_tw<C>(p.ax1);
+  const C* tw2 = axis_tw<C>(p.ax2);
   if (variant == 1) {
-#define CASE(N)                                                                                  \
-    if (p.n1 == N && p.n2 == N) {                                                                \
-      hipLaunchKernelGGL((k_plane_reg<N, N, 8>), dim3(p.n3, nb), dim3(threads), lds, s, p,       \
-                         vscaled, T);                                                            \
-      return hipGetLastError();                                                                  \
+#define CASE(N)                                                                                \
+    if (p.n1 == N && p.n2 == N) {                                                              \
+      hipLaunchKernelGGL((k_plane_reg<N, N, 8, C>), dim3(p.n3, nb), dim3(threads), lds, s, p,  \
+                         tw1, tw2, vscaled, T);                                                \
+      return hipGetLastError();                                                                \
     }
     PW_NARROW_SIZES(CASE)
 #undef CASE
     return hipErrorInvalidValue;
   }
-#define CASE(N)                                                                                  \
-  if (p.n1 == N && p.n2 == N) {                                                                  \
-    hipLaunchKernelGGL((k_plane_reg<N, N, 16>), dim3(p.n3, nb), dim3(threads), lds, s, p,        \
-                       vscaled, T);                                                              \
-    return hipGetLastError();                                                                    \
+#define CASE(N)                                                                                \
+  if (p.n1 == N && p.n2 == N) {                                                                \
+    hipLaunchKernelGGL((k_plane_reg<N, N, 16, C>), dim3(p.n3, nb), dim3(threads), lds, s, p,   \
+                       tw1, tw2, vscaled, T);                                                  \
+    return hipGetLastError();                                                                  \
   }
   PW_FAST_SIZES(CASE)
 #undef CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t fft_reg_set_lds_limits(size_t bytes) {
+template <class C>
+hipError_t set_plane_lds(size_t bytes) {
 #define CASE(N)                                                                              \
   {                                                                                          \
-    hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N, 16>,                   \
+    hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N, 16, C>,                \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
     if (e != hipSuccess) return e;                                                           \
   }
@@ -299,11 +320,50 @@ hipError_t fft_reg_set_lds_limits(size_t bytes) {
 #undef CASE
 #define CASE(N)                                                                              \
   {                                                                                          \
-    hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N, 8>,                    \
+    hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N, 8, C>,                 \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
     if (e != hipSuccess) return e;                                                           \
   }
   PW_NARROW_SIZES(CASE)
 #undef CASE
   return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int64_t ldpsi, cplx* T,
+                                  hipStream_t s) {
+  return col_inv_reg<double2>(p, nb, psi, ldpsi, T, s);
+}
+hipError_t launch_fft_col_inv_reg32(const BoxPlan& p, int nb, const float2* psi, int64_t ldpsi,
+                                    float2* T, hipStream_t s) {
+  return col_inv_reg<float2>(p, nb, psi, ldpsi, T, s);
+}
+
+hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const double* kin,
+                                  const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev,
+                                  cplx* out, int64_t ldout, double alpha, double beta, double gamma,
+                                  hipStream_t s) {
+  return col_fwd_reg<double2>(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, alpha, beta, gamma, s);
+}
+hipError_t launch_fft_col_fwd_reg32(const BoxPlan& p, int nb, const float2* T, const float* kin,
+                                    const float2* in, int64_t ldin, const float2* prev,
+                                    int64_t ldprev, float2* out, int64_t ldout, double alpha,
+                                    double beta, double gamma, hipStream_t s) {
+  return col_fwd_reg<float2>(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, alpha, beta, gamma, s);
+}
+
+hipError_t launch_fft_plane_reg(const BoxPlan& p, int variant, int nb, const double* vscaled,
+                                cplx* T, hipStream_t s) {
+  return plane_reg<double2>(p, variant, nb, vscaled, T, s);
+}
+hipError_t launch_fft_plane_reg32(const BoxPlan& p, int variant, int nb, const float* vscaled,
+                                  float2* T, hipStream_t s) {
+  return plane_reg<float2>(p, variant, nb, vscaled, T, s);
+}
+
+hipError_t fft_reg_set_lds_limits(size_t bytes) {
+  hipError_t e = set_plane_lds<double2>(bytes);
+  if (e != hipSuccess) return e;
+  return set_plane_lds<float2>(bytes);
 }

@@ -1,0 +1,276 @@
+// Complex matrix products of the low-precision filter path on the gfx950
+// matrix cores, FP32 accumulation (the projections c = P^H psi and the
+// non-local expansion H psi += P c of section 5.2, Eq. ham-nl, applied to
+// complex64 blocks).
+//
+//   MODE_F32 : v_mfma_f32_16x16x4f32, operands FP32.
+//   MODE_BF16: v_mfma_f32_16x16x32_bf16, operands rounded to bfloat16
+//              (round to nearest even) when the MFMA operands are formed from
+//              the FP32 tiles staged in LDS.
+// Operand layouts (checked on the device):
+//   f32 16x16x4 : A lane l -> A[l%16][l/16], B lane l -> B[l/16][l%16]
+//   bf16 16x16x32: A lane l -> A[l%16][8(l/16)+e], B lane l -> B[8(l/16)+e][l%16], e < 8
+//   result (both): lane l, element r -> D[4(l/16) + r][l%16]
+// A complex product is four real MFMAs into two accumulators:
+//   re += ar br - ai bi,  im += ar bi + ai br.
+#include "pw_internal.h"
+
+#include <algorithm>
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int kBM = 64, kBN = 64, kThreads = 256;
+constexpr int kTargetBlocks = 2048;
+enum { MODE_F32 = 0, MODE_BF16 = 1 };
+
+template <int MODE>
+struct KC {
+  static constexpr int value = MODE == MODE_F32 ? 16 : 32;   // complex K per LDS stage
+};
+
+__device__ __forceinline__ void f4zero(f4& a) { a = f4{0.f, 0.f, 0.f, 0.f}; }
+
+// One complex K-stage of MFMAs for a wave's 2x2 sub-tiles.  As/Bs are LDS
+// tiles [k][i] / [k][j] (row pitch pa/pb in float2); conjA negates Im(A).
+template <int MODE, bool CONJA>
+__device__ __forceinline__ void mfma_stage(const float2* As, int pa, const float2* Bs, int pb,
+                                           int wi, int wj, int lane, f4 (&ar)[2][2],
+                                           f4 (&ai)[2][2]) {
+  const int lr = lane & 15, lk = lane >> 4;
+  if constexpr (MODE == MODE_F32) {
+#pragma unroll
+    for (int ks = 0; ks < KC<MODE>::value; ks += 4) {
+      float2 a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[(ks + lk) * pa + wi * 32 + t * 16 + lr];
+        b[t] = Bs[(ks + lk) * pb + wj * 32 + t * 16 + lr];
+        if (CONJA) a[t].y = -a[t].y;
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti].x, b[tj].x, ar[ti][tj], 0, 0, 0);
+          ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[ti].y, b[tj].y, ar[ti][tj], 0, 0, 0);
+          ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti].x, b[tj].y, ai[ti][tj], 0, 0, 0);
+          ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti].y, b[tj].x, ai[ti][tj], 0, 0, 0);
+        }
+    }
+  } else {
+    bf8 are[2], aim[2], anim[2], bre[2], bim[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float2 a = As[(8 * lk + e) * pa + wi * 32 + t * 16 + lr];
+        if (CONJA) a.y = -a.y;
+        const float2 b = Bs[(8 * lk + e) * pb + wj * 32 + t * 16 + lr];
+        are[t][e] = (__bf16)a.x;
+        aim[t][e] = (__bf16)a.y;
+        anim[t][e] = (__bf16)(-a.y);
+        bre[t][e] = (__bf16)b.x;
+        bim[t][e] = (__bf16)b.y;
+      }
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(are[ti], bre[tj], ar[ti][tj], 0, 0, 0);
+        ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anim[ti], bim[tj], ar[ti][tj], 0, 0, 0);
+        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(are[ti], bim[tj], ai[ti][tj], 0, 0, 0);
+        ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aim[ti], bre[tj], ai[ti][tj], 0, 0, 0);
+      }
+  }
+}
+
+// C = alpha A B + beta C; A m x k (lda), B k x n (ldb), complex64 column-major.
+template <int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_gemm_nn32(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restrict__ A,
+            int64_t lda, const float2* __restrict__ B, int64_t ldb, float beta,
+            float2* __restrict__ C, int64_t ldc) {
+  constexpr int Kc = KC<MODE>::value;
+  constexpr int PA = kBM, PB = kBN + 1;
+  __shared__ float2 As[Kc * PA];
+  __shared__ float2 Bs[Kc * PB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int64_t i0 = (int64_t)blockIdx.y * kBM, j0 = (int64_t)blockIdx.x * kBN;
+  f4 ar[2][2], ai[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      f4zero(ar[a][b]);
+      f4zero(ai[a][b]);
+    }
+  for (int64_t k0 = 0; k0 < K; k0 += Kc) {
+    for (int e = tid; e < kBM * Kc; e += kThreads) {
+      const int kk = e / kBM, ii = e - kk * kBM;
+      const int64_t gi = i0 + ii, gk = k0 + kk;
+      As[kk * PA + ii] = (gi < M && gk < K) ? A[gi + gk * lda] : make_float2(0.f, 0.f);
+    }
+    for (int e = tid; e < kBN * Kc; e += kThreads) {
+      const int jj = e / Kc, kk = e - jj * Kc;
+      const int64_t gk = k0 + kk, gj = j0 + jj;
+      Bs[kk * PB + jj] = (gk < K && gj < N) ? B[gk + gj * ldb] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    mfma_stage<MODE, false>(As, PA, Bs, PB, wi, wj, lane, ar, ai);
+    __syncthreads();
+  }
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wi * 32 + ti * 16 + 4 * lk + r;
+        const int64_t j = j0 + wj * 32 + tj * 16 + lr;
+        if (i < M && j < N) {
+          float2 v = make_float2(alpha * ar[ti][tj][r], alpha * ai[ti][tj][r]);
+          if (beta != 0.f) {
+            const float2 c = C[i + j * ldc];
+            v.x += beta * c.x;
+            v.y += beta * c.y;
+          }
+          C[i + j * ldc] = v;
+        }
+      }
+}
+
+// Partial (split z over K) A^H B; A k x m (lda), B k x n (ldb); out ld = M.
+template <int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __restrict__ A,
+            int64_t lda, const float2* __restrict__ B, int64_t ldb, float2* __restrict__ out) {
+  constexpr int Kc = KC<MODE>::value;
+  constexpr int PA = kBM + 1, PB = kBN + 1;
+  __shared__ float2 As[Kc * PA];
+  __shared__ float2 Bs[Kc * PB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int64_t i0 = (int64_t)blockIdx.y * kBM, j0 = (int64_t)blockIdx.x * kBN;
+  const int64_t kb = (int64_t)blockIdx.z * ksplit;
+  const int64_t ke = min(K, kb + ksplit);
+  f4 ar[2][2], ai[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      f4zero(ar[a][b]);
+      f4zero(ai[a][b]);
+    }
+  for (int64_t k0 = kb; k0 < ke; k0 += Kc) {
+    for (int e = tid; e < kBM * Kc; e += kThreads) {
+      const int ii = e / Kc, kk = e - ii * Kc;
+      const int64_t gi = i0 + ii, gk = k0 + kk;
+      As[kk * PA + ii] = (gi < M && gk < ke) ? A[gk + gi * lda] : make_float2(0.f, 0.f);
+    }
+    for (int e = tid; e < kBN * Kc; e += kThreads) {
+      const int jj = e / Kc, kk = e - jj * Kc;
+      const int64_t gj = j0 + jj, gk = k0 + kk;
+      Bs[kk * PB + jj] = (gj < N && gk < ke) ? B[gk + gj * ldb] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    mfma_stage<MODE, true>(As, PA, Bs, PB, wi, wj, lane, ar, ai);
+    __syncthreads();
+  }
+  float2* o = out + (int64_t)blockIdx.z * M * N;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wi * 32 + ti * 16 + 4 * lk + r;
+        const int64_t j = j0 + wj * 32 + tj * 16 + lr;
+        if (i < M && j < N) o[i + j * M] = make_float2(ar[ti][tj][r], ai[ti][tj][r]);
+      }
+}
+
+// C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M] (FP64 sum, fixed order), rounded.
+__global__ void k_splitk_reduce32(int64_t M, int64_t N, int nsplit, const float2* __restrict__ work,
+                                  double alpha, const double* __restrict__ rowscale,
+                                  float2* __restrict__ C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t j = idx / M, i = idx - j * M;
+  double re = 0.0, im = 0.0;
+  for (int z = 0; z < nsplit; ++z) {
+    const float2 w = work[(int64_t)z * M * N + idx];
+    re += w.x;
+    im += w.y;
+  }
+  const double s = alpha * (rowscale ? rowscale[i] : 1.0);
+  C[i + j * ldc] = make_float2((float)(s * re), (float)(s * im));
+}
+
+struct SplitPlan {
+  int64_t tiles_m, tiles_n, nsplit, ksplit;
+};
+
+template <int MODE>
+SplitPlan split_plan32(int64_t m, int64_t n, int64_t k) {
+  constexpr int Kc = KC<MODE>::value;
+  SplitPlan p;
+  p.tiles_m = (m + kBM - 1) / kBM;
+  p.tiles_n = (n + kBN - 1) / kBN;
+  const int64_t tiles = p.tiles_m * p.tiles_n;
+  int64_t want = (kTargetBlocks + tiles - 1) / tiles;
+  const int64_t maxs = std::max<int64_t>(1, (k + Kc * 8 - 1) / (Kc * 8));
+  want = std::max<int64_t>(1, std::min(want, maxs));
+  int64_t ks = (k + want - 1) / want;
+  ks = ((ks + Kc - 1) / Kc) * Kc;
+  p.ksplit = std::max<int64_t>(ks, Kc);
+  p.nsplit = std::max<int64_t>(1, (k + p.ksplit - 1) / p.ksplit);
+  return p;
+}
+
+}  // namespace
+
+size_t gemm_cn32_work_elems(int64_t m, int64_t n, int64_t k, int bf16) {
+  const SplitPlan p = bf16 ? split_plan32<MODE_BF16>(m, n, k) : split_plan32<MODE_F32>(m, n, k);
+  return (size_t)(p.nsplit * m * n);
+}
+
+hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
+                            int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
+                            const double* rowscale, float2* work, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const SplitPlan p = bf16 ? split_plan32<MODE_BF16>(m, n, k) : split_plan32<MODE_F32>(m, n, k);
+  dim3 grid(p.tiles_n, p.tiles_m, p.nsplit);
+  if (bf16)
+    hipLaunchKernelGGL(k_gemm_cn32<MODE_BF16>, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, A, lda,
+                       B, ldb, work);
+  else
+    hipLaunchKernelGGL(k_gemm_cn32<MODE_F32>, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, A, lda,
+                       B, ldb, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = m * n;
+  hipLaunchKernelGGL(k_splitk_reduce32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, n,
+                     (int)p.nsplit, (const float2*)work, alpha, rowscale, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
+                            int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
+                            int64_t ldc, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  dim3 grid((n + kBN - 1) / kBN, (m + kBM - 1) / kBM, 1);
+  if (bf16)
+    hipLaunchKernelGGL(k_gemm_nn32<MODE_BF16>, grid, dim3(kThreads), 0, s, m, n, k, (float)alpha, A,
+                       lda, B, ldb, (float)beta, C, ldc);
+  else
+    hipLaunchKernelGGL(k_gemm_nn32<MODE_F32>, grid, dim3(kThreads), 0, s, m, n, k, (float)alpha, A,
+                       lda, B, ldb, (float)beta, C, ldc);
+  return hipGetLastError();
+}

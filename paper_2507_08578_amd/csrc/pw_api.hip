@@ -71,6 +71,15 @@ struct pw_ham {
   cplx* dinv = nullptr;     // inverses of the Cholesky diagonal blocks
   cplx* panel = nullptr;    // kb x nb_max row panel
   double* dtol = nullptr;   // pivot threshold
+  // low-precision filter path (allocated when desc->low_prec != 0)
+  bool low_prec = false;
+  float* kin32 = nullptr;
+  float* vs32 = nullptr;
+  float2* proj32 = nullptr;
+  float2* T32 = nullptr;
+  float2* cprj32 = nullptr;
+  float2* work32 = nullptr;
+  float2* blk32[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -137,11 +146,11 @@ void free_ham(pw_ham* h) {
 inline int center(int m, int n) { return m <= n / 2 ? m : m - n; }
 
 bool ranges_overlap(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t rows,
-                    int64_t cols) {
+                    int64_t cols, int64_t elem = (int64_t)sizeof(cplx)) {
   const char* a0 = static_cast<const char*>(a);
-  const char* a1 = a0 + ((cols - 1) * lda + rows) * (int64_t)sizeof(cplx);
+  const char* a1 = a0 + ((cols - 1) * lda + rows) * elem;
   const char* b0 = static_cast<const char*>(b);
-  const char* b1 = b0 + ((cols - 1) * ldb + rows) * (int64_t)sizeof(cplx);
+  const char* b1 = b0 + ((cols - 1) * ldb + rows) * elem;
   return a0 < b1 && b0 < a1;
 }
 
@@ -155,8 +164,11 @@ pw_status check_block(pw_ham* h, const void* p, int64_t ld, const char* name) {
 }
 
 pw_status check_hot(pw_ham* h, pw_prec prec, int64_t nb) {
-  if (prec != PW_FP64)
-    return fail(h->ctx, PW_ERR_UNSUPPORTED, "only PW_FP64 blocks are implemented in this version");
+  if (prec != PW_FP64 && prec != PW_FP32 && prec != PW_BF16)
+    return fail(h->ctx, PW_ERR_INVALID_ARG, "unknown precision");
+  if (prec != PW_FP64 && !h->low_prec)
+    return fail(h->ctx, PW_ERR_UNSUPPORTED,
+                "FP32/BF16 need a handle created with low_prec = 1");
   if (nb < 1 || nb > h->nb_max)
     return fail(h->ctx, PW_ERR_INVALID_ARG,
                 "nb = " + std::to_string(nb) + " outside [1, nb_max = " + std::to_string(h->nb_max) +
@@ -195,6 +207,44 @@ pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* o
     StageScope sc(c, PW_STAGE_NONLOCAL);
     HIPCHK(c, launch_gemm_nn(h->npw, nb, h->nproj, 1.0, h->proj, h->npw, h->cprj, h->nproj, 1.0,
                              out, ldout, s));
+  }
+  return PW_OK;
+}
+
+// Low-precision H application on complex64 blocks (FFT route in FP32; the
+// projector products in FP32 or, with bf16, bfloat16 operands; FP32
+// accumulation): out = alpha (H in) + beta in + gamma prev.
+pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t ldin, float2* out,
+                      int64_t ldout, double alpha, double beta, double gamma, const float2* prev,
+                      int64_t ldprev) {
+  pw_ctx* c = h->ctx;
+  hipStream_t s = c->stream;
+  if (h->nproj > 0) {
+    StageScope sc(c, PW_STAGE_PROJ);
+    HIPCHK(c, launch_gemm_cn32(bf16, h->nproj, nb, h->npw, alpha, h->proj32, h->npw, in, ldin,
+                               h->cprj32, h->nproj, h->ekb_dev, h->work32, s));
+  }
+  for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
+    const int nc = (int)std::min<int64_t>(h->chunk, nb - c0);
+    {
+      StageScope sc(c, PW_STAGE_FFT_COL_INV);
+      HIPCHK(c, launch_fft_col_inv_reg32(h->plan, nc, in + c0 * ldin, ldin, h->T32, s));
+    }
+    {
+      StageScope sc(c, PW_STAGE_FFT_PLANE);
+      HIPCHK(c, launch_fft_plane_reg32(h->plan, h->cfg.plane_variant, nc, h->vs32, h->T32, s));
+    }
+    {
+      StageScope sc(c, PW_STAGE_FFT_COL_FWD);
+      HIPCHK(c, launch_fft_col_fwd_reg32(h->plan, nc, h->T32, h->kin32, in + c0 * ldin, ldin,
+                                         gamma != 0.0 ? prev + c0 * ldprev : nullptr, ldprev,
+                                         out + c0 * ldout, ldout, alpha, beta, gamma, s));
+    }
+  }
+  if (h->nproj > 0) {
+    StageScope sc(c, PW_STAGE_NONLOCAL);
+    HIPCHK(c, launch_gemm_nn32(bf16, h->npw, nb, h->nproj, 1.0, h->proj32, h->npw, h->cprj32,
+                               h->nproj, 1.0, out, ldout, s));
   }
   return PW_OK;
 }
@@ -531,6 +581,41 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   TRY(dalloc(h, &h->dinv, (size_t)((h->nb_max + kCholBlock) * kCholBlock)));
   TRY(dalloc(h, &h->panel, (size_t)(kCholBlock * h->nb_max)));
   TRY(dalloc(h, &h->dtol, 2));
+  // FP32 twiddle tables (all axes)
+  for (FftAxis* ax : axes) {
+    float2* t32 = nullptr;
+    TRY(dalloc(h, &t32, (size_t)ax->n));
+    HIPCHK(ctx, launch_tw_to_f32(ax->n, ax->tw, t32, s));
+    ax->tw32 = t32;
+  }
+  if (d->low_prec) {
+    if (!h->cfg.reg_col || !h->cfg.reg_plane) {
+      free_ham(h);
+      delete h;
+      return fail(ctx, PW_ERR_UNSUPPORTED,
+                  "the FP32/BF16 path needs a cubic box of a length with register-resident FFT "
+                  "kernels (24, 32, 36, 48, 64, 72, 96, 120, 128, 144, 160)");
+    }
+    h->low_prec = true;
+    TRY(dalloc(h, &h->kin32, (size_t)npw));
+    TRY(dalloc(h, &h->vs32, (size_t)nbox));
+    HIPCHK(ctx, launch_real_to_f32(npw, h->kin, 1.0, h->kin32, s));
+    HIPCHK(ctx, launch_real_to_f32(nbox, h->vscaled, 1.0, h->vs32, s));
+    if (h->nproj > 0) {
+      TRY(dalloc(h, &h->proj32, (size_t)(npw * h->nproj)));
+      HIPCHK(ctx, launch_block_to_f32(npw, h->nproj, h->proj, npw, h->proj32, npw, s));
+      TRY(dalloc(h, &h->cprj32, (size_t)(h->nproj * h->nb_max)));
+      size_t w32 = 1;
+      for (int64_t nb = 1; nb <= h->nb_max; ++nb)
+        for (int bf = 0; bf < 2; ++bf)
+          w32 = std::max(w32, gemm_cn32_work_elems(h->nproj, nb, npw, bf));
+      TRY(dalloc(h, &h->work32, w32));
+    }
+    const size_t per_band32 = (size_t)P.n3 * P.ncols;
+    TRY(dalloc(h, &h->T32, per_band32 * h->chunk));
+    TRY(dalloc(h, &h->blk32[0], (size_t)(npw * h->nb_max)));
+    TRY(dalloc(h, &h->blk32[1], (size_t)(npw * h->nb_max)));
+  }
   HIPCHK(ctx, hipStreamSynchronize(s));
 #undef TRY
   *out = h;
@@ -564,9 +649,13 @@ pw_status pw_apply_h(pw_ham* h, pw_prec prec, int64_t nb, const void* psi, int64
   if ((st = check_hot(h, prec, nb)) != PW_OK) return st;
   if ((st = check_block(h, psi, ldpsi, "psi")) != PW_OK) return st;
   if ((st = check_block(h, hpsi, ldh, "hpsi")) != PW_OK) return st;
-  if (ranges_overlap(psi, ldpsi, hpsi, ldh, h->npw, nb))
+  const int64_t elem = prec == PW_FP64 ? (int64_t)sizeof(cplx) : (int64_t)sizeof(float2);
+  if (ranges_overlap(psi, ldpsi, hpsi, ldh, h->npw, nb, elem))
     return fail(h->ctx, PW_ERR_INVALID_ARG, "psi and hpsi overlap");
   HIPCHK(h->ctx, hipSetDevice(h->ctx->device));
+  if (prec != PW_FP64)
+    return ham_apply32(h, prec == PW_BF16, nb, static_cast<const float2*>(psi), ldpsi,
+                       static_cast<float2*>(hpsi), ldh, 1.0, 0.0, 0.0, nullptr, 0);
   return ham_apply(h, nb, static_cast<const cplx*>(psi), ldpsi, static_cast<cplx*>(hpsi), ldh, 1.0,
                    0.0, 0.0, nullptr, 0);
 }
@@ -587,6 +676,36 @@ pw_status pw_cheb_filter(pw_ham* h, pw_prec prec, int32_t degree, double a, doub
   const double e = 0.5 * (b - a), c = 0.5 * (b + a);
   double sigma = e / (a0 - c);
   const double tau = 2.0 / sigma;
+  if (prec != PW_FP64) {
+    // the block enters and leaves in FP64; the recurrence runs on complex64 copies
+    const int bf16 = prec == PW_BF16;
+    float2* buf[2] = {h->blk32[0], h->blk32[1]};
+    const int64_t l32 = h->npw;
+    hipStream_t s = h->ctx->stream;
+    {
+      StageScope sc(h->ctx, PW_STAGE_MISC);
+      HIPCHK(h->ctx, launch_block_to_f32(h->npw, nb, y, ld, buf[0], l32, s));
+      if (hx)
+        HIPCHK(h->ctx, launch_axpby_to_f32(h->npw, nb, sigma / e, hx, ldhx, -sigma * c / e, y, ld,
+                                           buf[1], l32, s));
+    }
+    if (!hx &&
+        (st = ham_apply32(h, bf16, nb, buf[0], l32, buf[1], l32, sigma / e, -sigma * c / e, 0.0,
+                          nullptr, 0)) != PW_OK)
+      return st;
+    for (int i = 2; i <= degree; ++i) {
+      const double sn = 1.0 / (tau - sigma);
+      const int cur = (i - 1) & 1, nxt = i & 1;
+      const double al = 2.0 * sn / e;
+      if ((st = ham_apply32(h, bf16, nb, buf[cur], l32, buf[nxt], l32, al, -al * c, -sigma * sn,
+                            buf[nxt], l32)) != PW_OK)
+        return st;
+      sigma = sn;
+    }
+    StageScope sc(h->ctx, PW_STAGE_MISC);
+    HIPCHK(h->ctx, launch_block_to_f64(h->npw, nb, buf[degree & 1], l32, y, ld, s));
+    return PW_OK;
+  }
   // Y0 lives in y, Y1 in blk; Y_i overwrites Y_{i-2} (y for even i, blk for odd i).
   cplx* buf[2] = {y, h->blk};
   int64_t lds[2] = {ld, h->npw};

@@ -20,6 +20,7 @@ struct FftAxis {
   int npass;                // number of radix passes
   int radix[kMaxPasses];    // radix of each pass, first pass first
   const cplx* tw;           // device table, tw[t] = exp(-2 pi i t / n), t < n
+  const float2* tw32;       // the same table rounded to FP32
 };
 
 // Sphere <-> box maps, all device arrays, built once per pw_ham.
@@ -89,6 +90,15 @@ hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const
                                   const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev,
                                   cplx* out, int64_t ldout, double alpha, double beta, double gamma,
                                   hipStream_t s);
+// FP32 (complex64 blocks, FP32 V/N_box and kinetic tables) variants
+hipError_t launch_fft_col_inv_reg32(const BoxPlan& p, int nb, const float2* psi, int64_t ldpsi,
+                                    float2* T, hipStream_t s);
+hipError_t launch_fft_plane_reg32(const BoxPlan& p, int variant, int nb, const float* vscaled,
+                                  float2* T, hipStream_t s);
+hipError_t launch_fft_col_fwd_reg32(const BoxPlan& p, int nb, const float2* T, const float* kin,
+                                    const float2* in, int64_t ldin, const float2* prev,
+                                    int64_t ldprev, float2* out, int64_t ldout, double alpha,
+                                    double beta, double gamma, hipStream_t s);
 
 // Split-K C = alpha diag(rowscale) A^H B + beta C (see pw_gemm_cn).  `work`
 // holds splits*m*n cplx; rowscale (m doubles on device) may be null.
@@ -99,6 +109,27 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
 hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
                           hipStream_t s);
+
+// Low-precision products (gemm32_kernels.hip): complex64 operands, FP32
+// accumulation; bf16 != 0 rounds the MFMA operands to bfloat16.
+size_t gemm_cn32_work_elems(int64_t m, int64_t n, int64_t k, int bf16);
+hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
+                            int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
+                            const double* rowscale, float2* work, hipStream_t s);
+hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
+                            int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
+                            int64_t ldc, hipStream_t s);
+
+// Precision conversions
+hipError_t launch_block_to_f32(int64_t rows, int64_t cols, const cplx* x, int64_t ldx, float2* y,
+                               int64_t ldy, hipStream_t s);
+hipError_t launch_block_to_f64(int64_t rows, int64_t cols, const float2* x, int64_t ldx, cplx* y,
+                               int64_t ldy, hipStream_t s);
+hipError_t launch_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx* x, int64_t ldx,
+                               double b, const cplx* y, int64_t ldy, float2* out, int64_t ldo,
+                               hipStream_t s);
+hipError_t launch_real_to_f32(int64_t n, const double* src, double scale, float* dst, hipStream_t s);
+hipError_t launch_tw_to_f32(int n, const cplx* src, float2* dst, hipStream_t s);
 
 // Dense kernels (dense_kernels.hip)
 // kin[g] = 1/2 |(n_g + k) B|^2 from device Miller indices; recip9/k3 are host values.

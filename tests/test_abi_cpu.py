@@ -62,10 +62,22 @@ def test_invalid_arguments_without_device(lib):
     assert b"NULL" in lib.pw_last_error(None)
 
 
-def test_desc_layout_matches_header():
-    """ctypes mirror of pw_ham_desc: offsets follow C layout rules (int32[3] then int64)."""
+def test_desc_layout_matches_header(tmp_path):
+    """The ctypes mirror of pw_ham_desc has the C compiler's offsets (checked with gcc)."""
+    import shutil
+    import subprocess
     from paper_2507_08578_amd._lib import PwHamDesc
-    assert PwHamDesc.npw.offset == 16
-    assert PwHamDesc.miller.offset == 24
-    assert PwHamDesc.recip.offset == 32
-    assert PwHamDesc.nb_max.offset == ctypes.sizeof(PwHamDesc) - 8
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    fields = [f[0] for f in PwHamDesc._fields_]
+    src = tmp_path / "off.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "pw.h"\nint main(void){\n' +
+                   "".join(f'printf("%zu\\n", offsetof(pw_ham_desc, {f}));\n' for f in fields) +
+                   'printf("%zu\\n", sizeof(pw_ham_desc));\nreturn 0;}\n')
+    exe = tmp_path / "off"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert out[:-1] == [getattr(PwHamDesc, f).offset for f in fields]
+    assert out[-1] == ctypes.sizeof(PwHamDesc)

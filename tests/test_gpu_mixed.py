@@ -1,0 +1,111 @@
+"""Low-precision filter path (FP32 FFT route; FP32 or bfloat16 MFMA projector
+products, FP32 accumulation) against the FP64 oracle.
+
+Bars: H*psi relative error <= 2e-6 (FP32) and <= 2e-2 (bf16 operands of the
+projector products); ChFSI with the low-precision filter and FP64
+orthonormalisation / Rayleigh-Ritz reaches the exact spectrum within 1e-6 Ha
+(the stated target for the mixed path).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def apply_err(pw, ctx, w, nb, prec, seed=0):
+    import torch
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=nb, low_prec=True)
+    X0 = synth.start_block(w.npw, nb, seed)
+    X = to_dev(X0).to(torch.complex64)
+    HX = to_host(ham.apply_h(X, prec=prec)).astype(np.complex128)
+    ref = oracle.apply_h(oracle.OracleHam.from_workload(w), X0.astype(np.complex64).T).T
+    return rel_err(HX, ref)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("bf16", 2e-2)])
+def test_apply_c1(pw, ctx, prec, tol):
+    err = apply_err(pw, ctx, synth.config_c1(), 16, prec)
+    print(f"C1 {prec} H*psi relative error {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("bf16", 2e-2)])
+def test_apply_c3(pw, ctx, prec, tol):
+    err = apply_err(pw, ctx, synth.config_c3(), 8, prec)
+    print(f"C3 {prec} H*psi relative error {err:.3e}")
+    assert err < tol
+
+
+def test_filter_fp32_matches_oracle(pw, ctx):
+    w = synth.config_c1()
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=16, low_prec=True)
+    oh = oracle.OracleHam.from_workload(w)
+    X0 = synth.start_block(w.npw, 16, 1)
+    b = oracle.upper_bound(oh)
+    for use_hx in (False, True):
+        Y = to_dev(X0)
+        hx = ham.apply_h(Y) if use_hx else None
+        ham.cheb_filter(Y, 8, 0.1, b, -0.18, hx=hx, prec="fp32")
+        ref = oracle.cheb_filter(oh, X0.T, 8, 0.1, b, -0.18).T
+        err = rel_err(to_host(Y), ref)
+        print(f"fp32 filter (hx={use_hx}) relative error {err:.3e}")
+        assert err < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ladder"])
+def test_chfsi_c1_mixed_reaches_exact(pw, ctx, prec):
+    w = synth.config_c1()
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=24, low_prec=True)
+    X0 = synth.start_block(w.npw, 24, 1)
+    fp = (lambda t: "bf16" if t <= 14 else "fp32") if prec == "ladder" else prec
+    st = pw.chfsi(ham, to_dev(X0), degree=8, iters=20, filter_prec=fp)
+    exact = np.linalg.eigvalsh(oracle.dense_h(oracle.OracleHam.from_workload(w)))
+    err = np.abs(st.eig_history[-1][:16] - exact[:16]).max()
+    print(f"C1 block 24, {prec} filter: max eigenvalue error {err:.3e} Ha")
+    assert err < 1e-6
+
+
+def test_chfsi_c1_bf16_throughout(pw, ctx):
+    """bf16 projector operands in every filter step: reported, bounded loosely."""
+    w = synth.config_c1()
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=24, low_prec=True)
+    X0 = synth.start_block(w.npw, 24, 1)
+    st = pw.chfsi(ham, to_dev(X0), degree=8, iters=20, filter_prec="bf16")
+    exact = np.linalg.eigvalsh(oracle.dense_h(oracle.OracleHam.from_workload(w)))
+    err = np.abs(st.eig_history[-1][:16] - exact[:16]).max()
+    print(f"C1 block 24, bf16 filter throughout: max eigenvalue error {err:.3e} Ha")
+    assert err < 1e-4
+
+
+def test_chfsi_c3_mixed_tracks_fp64(pw, ctx):
+    """C3 (160 bands): two iterations with the FP32 filter track the FP64 run within 1e-6 Ha."""
+    w = synth.config_c3()
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=160, low_prec=True)
+    X0 = to_dev(synth.start_block(w.npw, 160, 0))
+    b = ham.upper_bound()
+    s64 = pw.chfsi(ham, X0, degree=8, iters=2, upper=b)
+    s32 = pw.chfsi(ham, X0, degree=8, iters=2, upper=b, filter_prec="fp32")
+    d = max(np.abs(g - o).max() for g, o in zip(s64.eig_history, s32.eig_history))
+    print(f"C3 fp32 vs fp64 trajectory max |diff| {d:.3e} Ha")
+    assert d < 1e-6
+
+
+def test_low_precision_errors(pw, ctx):
+    import torch
+    w = synth.config_c1()
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=4)              # FP64-only handle
+    X = to_dev(synth.start_block(w.npw, 4, 0)).to(torch.complex64)
+    with pytest.raises(pw.PWError) as e:
+        ham.apply_h(X, prec="fp32")
+    assert e.value.status == 2
+    u, ecut, nb = synth.c4_cell_params(1)
+    w4 = synth.make_workload("C4.1", synth.diamond_cell(strain=u), (0, 0, 0), ecut, None, "s",
+                             nb, 8, 20)
+    if w4.box[0] != w4.box[1]:
+        with pytest.raises(pw.PWError) as e:
+            pw.Hamiltonian.from_workload(ctx, w4, low_prec=True)
+        assert e.value.status == 2
