@@ -70,6 +70,8 @@ const char* pw_version(void);
  * class LDS), OOM.
  */
 pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out);
+/* Drops the caller's handle.  Hams and batches made on the context keep it
+ * alive; it is freed when the last of them is destroyed, in any order. */
 pw_status pw_ctx_destroy(pw_ctx* ctx);
 
 /* Message of the last error on this context ("" if none); valid until the
@@ -186,6 +188,56 @@ pw_status pw_rayleigh_ritz(pw_ham* ham, int64_t nb, void* y_dev, int64_t ld, voi
  * (each term bounds its operator from above).  Synchronises.
  */
 pw_status pw_upper_bound(pw_ham* ham, double* b_host);
+
+/* ---------------------------------------------------------------------------
+ * Batched subspace iteration over independent Hamiltonians (k-points of one
+ * cell, or separate cells), section 5.1's Chebyshev-filtered iteration run
+ * for many small problems at once (section 5.4 notes that k-points are
+ * independent and are the first level of parallelism).
+ *
+ * One iteration of item i: filter coefficients are computed ON THE DEVICE
+ * from the item's current Ritz values (a = largest, a0 = smallest) and its
+ * upper bound b (pw_upper_bound, taken at creation); Y is filtered (degree
+ * products, the first one reusing W = H Y of the last Rayleigh-Ritz), Gram
+ * + Cholesky + Y <- Y U^{-1}, then Rayleigh-Ritz (FP64, one-workgroup Jacobi
+ * eigensolve) leaving Y, W = H Y, eig and resid.  Nothing in an iteration
+ * reads back to the host, so the whole iteration of every item is captured
+ * once into one HIP graph (one independent branch per item, items spread
+ * over the batch's streams) and replayed.
+ * ------------------------------------------------------------------------- */
+typedef struct pw_batch pw_batch;
+
+/*
+ * n items; for item i: hams[i] (distinct handles of this ctx, nb_max >= nb[i],
+ * created with low_prec when filter_prec is not PW_FP64), nb[i] in [1, 64],
+ * y_dev[i] / hy_dev[i]: complex128 npw_i x nb[i] blocks with ld = npw_i,
+ * eig_dev[i] / resid_dev[i]: nb[i] doubles each.  All buffers are owned by
+ * the caller and must outlive the batch; the batch keeps their addresses
+ * (they are baked into the captured graph).  degree >= 1.  nstreams in
+ * [1, 64]: the number of concurrent branches.  Synchronises.
+ */
+pw_status pw_batch_create(pw_ctx* ctx, int32_t n, pw_ham* const* hams, const int64_t* nb,
+                          void* const* y_dev, void* const* hy_dev, double* const* eig_dev,
+                          double* const* resid_dev, int32_t degree, pw_prec filter_prec,
+                          int32_t nstreams, pw_batch** out);
+pw_status pw_batch_destroy(pw_batch* b);
+/* Iteration 0 of every item: orthonormalise the start block in y_dev, then
+ * Rayleigh-Ritz.  Ordered after prior work on the context's stream;
+ * synchronises and reports failures as pw_batch_iterate does. */
+pw_status pw_batch_start(pw_batch* b);
+/*
+ * iters further iterations of every item.  use_graph != 0: replay the
+ * captured graph (captured on first use); 0: issue the same kernels
+ * directly on the batch's streams.  Ordered after prior work on the
+ * context's stream and before later work on it.  Synchronises once at the
+ * end and returns PW_ERR_NOT_POSDEF (Cholesky pivot), PW_ERR_NO_CONVERGENCE
+ * (eigensolver sweep limit) or PW_ERR_INVALID_ARG (Ritz values not inside
+ * a0 < a < b: that item's filter became the identity) for the first item
+ * that failed in any of the iterations; pw_last_error names it.
+ */
+pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph);
+/* Largest number of Jacobi sweeps any item used in the last start/iterate. */
+pw_status pw_batch_max_sweeps(const pw_batch* b, int32_t* sweeps);
 
 /* ---------------------------------------------------------------------------
  * Dense building blocks, exposed for testing and for callers that hold their

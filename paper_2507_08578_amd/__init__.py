@@ -280,4 +280,64 @@ class Hamiltonian:
         return b.value
 
 
+class Batch:
+    """pw_batch: the Chebyshev-filtered subspace iteration of many independent
+    Hamiltonians at once (k-points or cells), each iteration captured once into
+    one HIP graph with a branch per item.
+
+    hams: distinct Hamiltonians of one Context; X0s: start blocks, complex128
+    CUDA tensors (nb_i, npw_i) with nb_i <= 64 (copied; the batch owns Y, HY,
+    eig and resid, whose addresses live in the captured graph)."""
+
+    def __init__(self, ctx: Context, hams, X0s, degree: int, filter_prec="fp64",
+                 nstreams: int = 8):
+        import torch
+        if len(hams) != len(X0s) or not hams:
+            raise ValueError("need one start block per Hamiltonian")
+        self.ctx = ctx
+        self.hams = list(hams)
+        self.Y = [x.contiguous().clone() for x in X0s]
+        for h, y in zip(self.hams, self.Y):
+            _block_args(y, h.npw, "X0")
+        self.HY = [torch.empty_like(y) for y in self.Y]
+        self.eig = [torch.empty(y.shape[0], dtype=torch.float64, device=y.device) for y in self.Y]
+        self.resid = [torch.empty_like(e) for e in self.eig]
+        n = len(self.hams)
+        ptrs = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])  # noqa: E731
+        hh = (ctypes.c_void_p * n)(*[h.handle.value for h in self.hams])
+        nbs = (ctypes.c_int64 * n)(*[y.shape[0] for y in self.Y])
+        handle = ctypes.c_void_p()
+        ctx.check(_LIB.pw_batch_create(ctx.handle, n, hh, nbs, ptrs(self.Y), ptrs(self.HY),
+                                       ptrs(self.eig), ptrs(self.resid), int(degree),
+                                       _prec(filter_prec), int(nstreams), ctypes.byref(handle)))
+        self.handle = handle
+        self.degree = int(degree)
+
+    def start(self):
+        """Iteration 0: orthonormalise the start blocks, then Rayleigh-Ritz."""
+        self.ctx.check(_LIB.pw_batch_start(self.handle))
+
+    def iterate(self, iters: int = 1, graph: bool = True):
+        self.ctx.check(_LIB.pw_batch_iterate(self.handle, int(iters), int(bool(graph))))
+
+    def max_sweeps(self) -> int:
+        n = ctypes.c_int32()
+        self.ctx.check(_LIB.pw_batch_max_sweeps(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def eigenvalues(self):
+        return [e.cpu().numpy().copy() for e in self.eig]
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _LIB.pw_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 from .chfsi import chfsi, ChfsiState  # noqa: E402,F401

@@ -68,6 +68,15 @@ SIGNATURES = {
                                   ctypes.POINTER(c_int64)]),
     "pw_ctx_reset_timing": (c_int, [c_void_p]),
     "pw_ctx_last_sweeps": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
+    "pw_batch_create": (c_int, [c_void_p, c_int32, ctypes.POINTER(c_void_p),
+                                ctypes.POINTER(c_int64), ctypes.POINTER(c_void_p),
+                                ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                ctypes.POINTER(c_void_p), c_int32, c_int, c_int32,
+                                ctypes.POINTER(c_void_p)]),
+    "pw_batch_destroy": (c_int, [c_void_p]),
+    "pw_batch_start": (c_int, [c_void_p]),
+    "pw_batch_iterate": (c_int, [c_void_p, c_int32, c_int32]),
+    "pw_batch_max_sweeps": (c_int, [c_void_p, ctypes.POINTER(c_int32)]),
 }
 
 

@@ -104,9 +104,14 @@ __global__ void k_scale_rows_cols(int64_t n, const double* __restrict__ d, cplx*
 }
 
 __global__ void k_axpby_block(int64_t npw, int64_t nb, double a, const cplx* x, int64_t ldx,
-                              double b, const cplx* y, int64_t ldy, cplx* out, int64_t ldo) {
+                              double b, const cplx* y, int64_t ldy, cplx* out, int64_t ldo,
+                              const double* __restrict__ coef) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= npw * nb) return;
+  if (coef) {
+    a = coef[0];
+    b = coef[1];
+  }
   const int64_t j = idx / npw, i = idx - j * npw;
   const cplx u = x[i + j * ldx], v = y[i + j * ldy];
   out[i + j * ldo] = make_double2(a * u.x + b * v.x, a * u.y + b * v.y);
@@ -626,9 +631,13 @@ __global__ void k_block_to_f64(int64_t rows, int64_t cols, const float2* __restr
 // out = fp32(a x + b y), x and y FP64
 __global__ void k_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx* __restrict__ x,
                                int64_t ldx, double b, const cplx* __restrict__ y, int64_t ldy,
-                               float2* __restrict__ out, int64_t ldo) {
+                               float2* __restrict__ out, int64_t ldo, const double* __restrict__ coef) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
+  if (coef) {
+    a = coef[0];
+    b = coef[1];
+  }
   const int64_t j = idx / rows, i = idx - j * rows;
   const cplx u = x[i + j * ldx], v = y[i + j * ldy];
   out[i + j * ldo] = make_float2((float)(a * u.x + b * v.x), (float)(a * u.y + b * v.y));
@@ -643,6 +652,54 @@ __global__ void k_real_to_f32(int64_t n, const double* __restrict__ src, double 
 __global__ void k_tw_to_f32(int n, const cplx* __restrict__ src, float2* __restrict__ dst) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = make_float2((float)src[i].x, (float)src[i].y);
+}
+
+// Chebyshev filter coefficients on the device from the current Ritz values
+// (a = largest, a0 = smallest) and the upper bound b: step i (0-based) of the
+// scaled recurrence is out = alpha (H in) + beta in + gamma prev with
+//   i = 0: alpha = s/e, beta = -s c/e, gamma = 0            (s = e/(a0 - c))
+//   i > 0: s' = 1/(2/s_0 - s), alpha = 2 s'/e, beta = -alpha c, gamma = -s s'; s = s'
+// If a0 < a < b fails, every step becomes the identity and flag[0] is set.
+__global__ void k_cheb_coef(const double* __restrict__ eig, int nb, const double* __restrict__ upper,
+                            int degree, double* __restrict__ coef, int* flag) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double a = eig[nb - 1], a0 = eig[0], b = upper[0];
+  if (!(a0 < a && a < b)) {
+    for (int i = 0; i < degree; ++i) {
+      coef[3 * i] = 0.0;
+      coef[3 * i + 1] = 1.0;
+      coef[3 * i + 2] = 0.0;
+    }
+    flag[0] = 1;
+    return;
+  }
+  const double e = 0.5 * (b - a), c = 0.5 * (b + a);
+  double sigma = e / (a0 - c);
+  const double tau = 2.0 / sigma;
+  coef[0] = sigma / e;
+  coef[1] = -sigma * c / e;
+  coef[2] = 0.0;
+  for (int i = 1; i < degree; ++i) {
+    const double sn = 1.0 / (tau - sigma);
+    const double al = 2.0 * sn / e;
+    coef[3 * i] = al;
+    coef[3 * i + 1] = -al * c;
+    coef[3 * i + 2] = -sigma * sn;
+    sigma = sn;
+  }
+}
+
+// Sticky per-item failure flags of a batched iteration:
+// flags[0] = first failing Cholesky pivot + 1, flags[1] = eigensolver hit the
+// sweep limit, flags[2] = bad filter interval (set by k_cheb_coef),
+// flags[3] = largest sweep count seen.
+__global__ void k_batch_flags(const int* __restrict__ chol_status, const int* __restrict__ sweeps,
+                              int* flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (chol_status && chol_status[0] >= 0 && flags[0] == 0) flags[0] = chol_status[0] + 1;
+  const int sw = sweeps[0];
+  if (sw < 0) flags[1] = 1;
+  else if (sw > flags[3]) flags[3] = sw;
 }
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -692,9 +749,21 @@ hipError_t launch_scale_rows_cols(int64_t n, const double* d, cplx* a, int64_t l
 }
 
 hipError_t launch_axpby_block(int64_t npw, int64_t nb, double a, const cplx* x, int64_t ldx, double b,
-                              const cplx* y, int64_t ldy, cplx* out, int64_t ldo, hipStream_t s) {
+                              const cplx* y, int64_t ldy, cplx* out, int64_t ldo, hipStream_t s,
+                              const double* coef) {
   hipLaunchKernelGGL(k_axpby_block, dim3(nblocks(npw * nb, 256)), dim3(256), 0, s, npw, nb, a, x,
-                     ldx, b, y, ldy, out, ldo);
+                     ldx, b, y, ldy, out, ldo, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_flags(const int* chol_status, const int* sweeps, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_flags, dim3(1), dim3(64), 0, s, chol_status, sweeps, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_coef(const double* eig, int nb, const double* upper, int degree, double* coef,
+                            int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_coef, dim3(1), dim3(64), 0, s, eig, nb, upper, degree, coef, flag);
   return hipGetLastError();
 }
 
@@ -716,9 +785,9 @@ hipError_t launch_block_to_f64(int64_t rows, int64_t cols, const float2* x, int6
 
 hipError_t launch_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx* x, int64_t ldx,
                                double b, const cplx* y, int64_t ldy, float2* out, int64_t ldo,
-                               hipStream_t s) {
+                               hipStream_t s, const double* coef) {
   hipLaunchKernelGGL(k_axpby_to_f32, dim3(nblocks(rows * cols, 256)), dim3(256), 0, s, rows, cols, a,
-                     x, ldx, b, y, ldy, out, ldo);
+                     x, ldx, b, y, ldy, out, ldo, coef);
   return hipGetLastError();
 }
 
@@ -780,6 +849,15 @@ hipError_t heev_set_lds_limit(size_t bytes) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_heev_small_async(int64_t n, const cplx* a, int64_t lda, double* w, cplx* q,
+                                   int64_t ldq, int* sweeps_dev, hipStream_t s) {
+  if (n > kJacSmallMax) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(2 * n * n) * sizeof(cplx);
+  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(kJacThreads), lds, s, (int)n, a, lda, w, q, ldq,
+                     sweeps_dev);
+  return hipGetLastError();
 }
 
 hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int64_t ldq, void* work,

@@ -20,109 +20,23 @@
 // Every 1D transform is a sequence of in-place Stockham radix passes in LDS
 // (radices 2, 3, 4, 5, 8), each pass a register-staged read / barrier /
 // write so that no second buffer is needed.
-#include "pw_internal.h"
+#include "fft_common.h"
 
 #include <algorithm>
 #include <cmath>
+
+using namespace pwfft;
 
 namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
-// (S i) z for S = +1 / -1
-template <int S>
-__device__ __forceinline__ cplx mul_si(cplx z) {
-  return S > 0 ? make_double2(-z.y, z.x) : make_double2(z.y, -z.x);
-}
-
-// Small DFTs y_k = sum_n x_n exp(S 2 pi i n k / R), in registers.
-template <int S>
-__device__ __forceinline__ void dft2(cplx* v) {
-  cplx a = v[0], b = v[1];
-  v[0] = cadd(a, b);
-  v[1] = csub(a, b);
-}
-template <int S>
-__device__ __forceinline__ void dft3(cplx* v) {
-  const double h = 0.86602540378443864676;  // sin(2 pi / 3)
-  cplx s = cadd(v[1], v[2]);
-  cplx d = csub(v[1], v[2]);
-  cplx t = make_double2(v[0].x - 0.5 * s.x, v[0].y - 0.5 * s.y);
-  cplx r = mul_si<S>(cscale(d, h));
-  v[0] = cadd(v[0], s);
-  v[1] = cadd(t, r);
-  v[2] = csub(t, r);
-}
-template <int S>
-__device__ __forceinline__ void dft4(cplx* v) {
-  cplx a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-  cplx c = cadd(v[1], v[3]), d = mul_si<S>(csub(v[1], v[3]));
-  v[0] = cadd(a, c);
-  v[2] = csub(a, c);
-  v[1] = cadd(b, d);
-  v[3] = csub(b, d);
-}
-template <int S>
-__device__ __forceinline__ void dft5(cplx* v) {
-  const double c1 = 0.30901699437494742410;   // cos(2 pi/5)
-  const double c2 = -0.80901699437494742410;  // cos(4 pi/5)
-  const double s1 = 0.95105651629515357212;   // sin(2 pi/5)
-  const double s2 = 0.58778525229247312917;   // sin(4 pi/5)
-  cplx a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
-  cplx a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
-  cplx x0 = v[0];
-  cplx p1 = make_double2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
-  cplx p2 = make_double2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
-  cplx q1 = mul_si<S>(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
-  cplx q2 = mul_si<S>(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
-  v[0] = make_double2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
-  v[1] = cadd(p1, q1);
-  v[4] = csub(p1, q1);
-  v[2] = cadd(p2, q2);
-  v[3] = csub(p2, q2);
-}
-template <int S>
-__device__ __forceinline__ void dft8(cplx* v) {
-  const double h = 0.70710678118654752440;  // sqrt(2)/2
-  cplx e[4] = {v[0], v[2], v[4], v[6]};
-  cplx o[4] = {v[1], v[3], v[5], v[7]};
-  dft4<S>(e);
-  dft4<S>(o);
-  // w8^k = exp(S 2 pi i k / 8)
-  cplx o1 = make_double2(h * (o[1].x - S * o[1].y), h * (o[1].y + S * o[1].x));
-  cplx o2 = mul_si<S>(o[2]);
-  cplx o3 = make_double2(h * (-o[3].x - S * o[3].y), h * (-o[3].y + S * o[3].x));
-  v[0] = cadd(e[0], o[0]);
-  v[4] = csub(e[0], o[0]);
-  v[1] = cadd(e[1], o1);
-  v[5] = csub(e[1], o1);
-  v[2] = cadd(e[2], o2);
-  v[6] = csub(e[2], o2);
-  v[3] = cadd(e[3], o3);
-  v[7] = csub(e[3], o3);
-}
-template <int R, int S>
-__device__ __forceinline__ void dft(cplx* v) {
-  if constexpr (R == 2) dft2<S>(v);
-  else if constexpr (R == 3) dft3<S>(v);
-  else if constexpr (R == 4) dft4<S>(v);
-  else if constexpr (R == 5) dft5<S>(v);
-  else dft8<S>(v);
-}
-
 // One Stockham radix-R pass over `ntr` transforms of length n stored at
 // buf[t*trs + i], in place.  ns = product of the radices already applied.
 // Stockham step: butterfly j reads x[j + r*n/R], twiddles by
 // exp(S 2 pi i r (j mod ns) / (ns R)), and writes y[(j - j mod ns) R + j mod ns + r ns].
-template <int R, int S>
-__device__ void stockham_pass(cplx* buf, int ntr, int trs, int n, int ns,
-                              const cplx* __restrict__ tw) {
+template <int R, int S, class C>
+__device__ void stockham_pass(C* buf, int ntr, int trs, int n, int ns, const C* __restrict__ tw) {
   const int nbf = n / R;            // butterflies per transform
   const int rest = nbf / ns;        // n / (ns R)
   const int group = blockDim.x / nbf;
@@ -130,28 +44,28 @@ __device__ void stockham_pass(cplx* buf, int ntr, int trs, int n, int ns,
     const int cnt = min(group, ntr - t0);
     const int u = threadIdx.x;
     const bool act = u < cnt * nbf;
-    cplx v[R];
+    C v[R];
     int t = 0, j = 0, k = 0;
     if (act) {
       t = t0 + u / nbf;
       j = u - (u / nbf) * nbf;
       k = j % ns;
-      const cplx* b = buf + (size_t)t * trs;
+      const C* b = buf + (size_t)t * trs;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        cplx x = b[j + r * nbf];
+        C x = b[j + r * nbf];
         if (r > 0 && k > 0) {
-          cplx w = tw[r * k * rest];          // r k rest < n: no reduction needed
+          C w = tw[r * k * rest];          // r k rest < n: no reduction needed
           if (S > 0) w.y = -w.y;
           x = cmul(x, w);
         }
         v[r] = x;
       }
-      dft<R, S>(v);
+      dft_base<R, S>(v);
     }
     __syncthreads();
     if (act) {
-      cplx* b = buf + (size_t)t * trs;
+      C* b = buf + (size_t)t * trs;
       const int idxd = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) b[idxd + r * ns] = v[r];
@@ -160,16 +74,24 @@ __device__ void stockham_pass(cplx* buf, int ntr, int trs, int n, int ns,
   }
 }
 
-template <int S>
-__device__ void fft_lds(cplx* buf, int ntr, int trs, const FftAxis& ax) {
+template <class C>
+__device__ __forceinline__ const C* ax_tw(const FftAxis& ax);
+template <>
+__device__ __forceinline__ const double2* ax_tw<double2>(const FftAxis& ax) { return ax.tw; }
+template <>
+__device__ __forceinline__ const float2* ax_tw<float2>(const FftAxis& ax) { return ax.tw32; }
+
+template <int S, class C>
+__device__ void fft_lds(C* buf, int ntr, int trs, const FftAxis& ax) {
   int ns = 1;
+  const C* tw = ax_tw<C>(ax);
   for (int p = 0; p < ax.npass; ++p) {
     switch (ax.radix[p]) {
-      case 2: stockham_pass<2, S>(buf, ntr, trs, ax.n, ns, ax.tw); break;
-      case 3: stockham_pass<3, S>(buf, ntr, trs, ax.n, ns, ax.tw); break;
-      case 4: stockham_pass<4, S>(buf, ntr, trs, ax.n, ns, ax.tw); break;
-      case 5: stockham_pass<5, S>(buf, ntr, trs, ax.n, ns, ax.tw); break;
-      default: stockham_pass<8, S>(buf, ntr, trs, ax.n, ns, ax.tw); break;
+      case 2: stockham_pass<2, S>(buf, ntr, trs, ax.n, ns, tw); break;
+      case 3: stockham_pass<3, S>(buf, ntr, trs, ax.n, ns, tw); break;
+      case 4: stockham_pass<4, S>(buf, ntr, trs, ax.n, ns, tw); break;
+      case 5: stockham_pass<5, S>(buf, ntr, trs, ax.n, ns, tw); break;
+      default: stockham_pass<8, S>(buf, ntr, trs, ax.n, ns, tw); break;
     }
     ns *= ax.radix[p];
   }
@@ -196,47 +118,51 @@ PlanArgs plan_args(const BoxPlan& p) {
   return a;
 }
 
+template <class C>
 __global__ void __launch_bounds__(kThreads)
-k_col_inv(PlanArgs P, int ct, const cplx* __restrict__ psi, int64_t ldpsi, cplx* __restrict__ T) {
-  extern __shared__ cplx lds[];
+k_col_inv(PlanArgs P, int ct, const C* __restrict__ psi, int64_t ldpsi, C* __restrict__ T) {
+  extern __shared__ __align__(16) char lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
   const int c0 = blockIdx.x * ct;
   const int b = blockIdx.y;
   const int ncl = min(ct, P.ncols - c0);
   const int trs = P.n3 + 1;
-  for (int i = threadIdx.x; i < ncl * trs; i += blockDim.x) lds[i] = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < ncl * trs; i += blockDim.x) lds[i] = czero<C>();
   __syncthreads();
   const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
-  const cplx* src = psi + (size_t)b * ldpsi;
+  const C* src = psi + (size_t)b * ldpsi;
   for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
     lds[(P.pt_col[k] - c0) * trs + P.pt_m3[k]] = src[P.pt_perm[k]];
   __syncthreads();
   fft_lds<+1>(lds, ncl, trs, P.ax3);
-  cplx* dst = T + (size_t)b * P.n3 * P.ncols + c0;
+  C* dst = T + (size_t)b * P.n3 * P.ncols + c0;
   for (int i = threadIdx.x; i < ncl * P.n3; i += blockDim.x) {
     const int j3 = i / ncl, lc = i - j3 * ncl;
     dst[(size_t)j3 * P.ncols + lc] = lds[lc * trs + j3];
   }
 }
 
+template <class C>
 __global__ void __launch_bounds__(kThreads)
-k_plane(PlanArgs P, int rb, const double* __restrict__ v, cplx* __restrict__ T) {
-  extern __shared__ cplx lds[];
+k_plane(PlanArgs P, int rb, const real_t<C>* __restrict__ v, C* __restrict__ T) {
+  extern __shared__ __align__(16) char lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
   const int trse = P.n2 + 1;
   const int trsr = P.n1 + 1;
-  cplx* E = lds;
-  cplx* Rw = lds + P.xr * trse;
+  C* E = lds;
+  C* Rw = lds + P.xr * trse;
   const int j3 = blockIdx.x;
   const int b = blockIdx.y;
-  cplx* tp = T + (size_t)b * P.n3 * P.ncols + (size_t)j3 * P.ncols;
-  for (int i = threadIdx.x; i < P.xr * trse; i += blockDim.x) E[i] = make_double2(0.0, 0.0);
+  C* tp = T + (size_t)b * P.n3 * P.ncols + (size_t)j3 * P.ncols;
+  for (int i = threadIdx.x; i < P.xr * trse; i += blockDim.x) E[i] = czero<C>();
   __syncthreads();
   for (int c = threadIdx.x; c < P.ncols; c += blockDim.x) E[P.col_e[c] * trse + P.col_m2[c]] = tp[c];
   __syncthreads();
   fft_lds<+1>(E, P.xr, trse, P.ax2);
-  const double* vp = v + (size_t)j3 * P.n2 * P.n1;
+  const real_t<C>* vp = v + (size_t)j3 * P.n2 * P.n1;
   for (int r0 = 0; r0 < P.n2; r0 += rb) {
     const int nr = min(rb, P.n2 - r0);
-    for (int i = threadIdx.x; i < nr * trsr; i += blockDim.x) Rw[i] = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < nr * trsr; i += blockDim.x) Rw[i] = czero<C>();
     __syncthreads();
     for (int i = threadIdx.x; i < nr * P.xr; i += blockDim.x) {
       const int r = i / P.xr, e = i - r * P.xr;
@@ -246,9 +172,7 @@ k_plane(PlanArgs P, int rb, const double* __restrict__ v, cplx* __restrict__ T) 
     fft_lds<+1>(Rw, nr, trsr, P.ax1);
     for (int i = threadIdx.x; i < nr * P.n1; i += blockDim.x) {
       const int r = i / P.n1, j1 = i - r * P.n1;
-      const double s = vp[(size_t)(r0 + r) * P.n1 + j1];
-      cplx x = Rw[r * trsr + j1];
-      Rw[r * trsr + j1] = make_double2(x.x * s, x.y * s);
+      Rw[r * trsr + j1] = cscale(Rw[r * trsr + j1], vp[(size_t)(r0 + r) * P.n1 + j1]);
     }
     __syncthreads();
     fft_lds<-1>(Rw, nr, trsr, P.ax1);
@@ -262,16 +186,25 @@ k_plane(PlanArgs P, int rb, const double* __restrict__ v, cplx* __restrict__ T) 
   for (int c = threadIdx.x; c < P.ncols; c += blockDim.x) tp[c] = E[P.col_e[c] * trse + P.col_m2[c]];
 }
 
+template <class C>
 __global__ void __launch_bounds__(kThreads)
-k_col_fwd(PlanArgs P, int ct, const cplx* __restrict__ T, const double* __restrict__ kin,
-          const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev, cplx* out,
-          int64_t ldout, double alpha, double beta, double gamma) {
-  extern __shared__ cplx lds[];
+k_col_fwd(PlanArgs P, int ct, const C* __restrict__ T, const real_t<C>* __restrict__ kin,
+          const C* in, int64_t ldin, const C* prev, int64_t ldprev, C* out, int64_t ldout,
+          double alpha_d, double beta_d, double gamma_d, const double* __restrict__ coef) {
+  using Rl = real_t<C>;
+  extern __shared__ __align__(16) char lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
+  if (coef) {
+    alpha_d = coef[0];
+    beta_d = coef[1];
+    gamma_d = coef[2];
+  }
+  const Rl alpha = (Rl)alpha_d, beta = (Rl)beta_d, gamma = (Rl)gamma_d;
   const int c0 = blockIdx.x * ct;
   const int b = blockIdx.y;
   const int ncl = min(ct, P.ncols - c0);
   const int trs = P.n3 + 1;
-  const cplx* srcT = T + (size_t)b * P.n3 * P.ncols + c0;
+  const C* srcT = T + (size_t)b * P.n3 * P.ncols + c0;
   for (int i = threadIdx.x; i < ncl * P.n3; i += blockDim.x) {
     const int j3 = i / ncl, lc = i - j3 * ncl;
     lds[lc * trs + j3] = srcT[(size_t)j3 * P.ncols + lc];
@@ -279,18 +212,19 @@ k_col_fwd(PlanArgs P, int ct, const cplx* __restrict__ T, const double* __restri
   __syncthreads();
   fft_lds<-1>(lds, ncl, trs, P.ax3);
   const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
-  const cplx* inb = in + (size_t)b * ldin;
-  cplx* outb = out + (size_t)b * ldout;
-  const cplx* prevb = prev ? prev + (size_t)b * ldprev : nullptr;
+  const C* inb = in + (size_t)b * ldin;
+  C* outb = out + (size_t)b * ldout;
+  const C* prevb = prev ? prev + (size_t)b * ldprev : nullptr;
   for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
     const int g = P.pt_perm[k];
-    const cplx loc = lds[(P.pt_col[k] - c0) * trs + P.pt_m3[k]];
-    const cplx x = inb[g];
-    const double t = kin[g];
-    cplx val = make_double2(alpha * (loc.x + t * x.x) + beta * x.x,
-                            alpha * (loc.y + t * x.y) + beta * x.y);
-    if (gamma != 0.0) {
-      const cplx p = prevb[g];
+    const C loc = lds[(P.pt_col[k] - c0) * trs + P.pt_m3[k]];
+    const C x = inb[g];
+    const Rl t = kin[g];
+    C val;
+    val.x = alpha * (loc.x + t * x.x) + beta * x.x;
+    val.y = alpha * (loc.y + t * x.y) + beta * x.y;
+    if (prevb) {
+      const C p = prevb[g];
       val.x += gamma * p.x;
       val.y += gamma * p.y;
     }
@@ -392,45 +326,86 @@ bool fft_choose_config(const BoxPlan& p, size_t lds_limit, FftLaunchCfg* cfg) {
   return true;
 }
 
+namespace {
+
+template <class C>
+hipError_t col_inv_generic(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const C* psi,
+                           int64_t ldpsi, C* T, hipStream_t s) {
+  dim3 grid((p.ncols + cfg.col_tile - 1) / cfg.col_tile, nb);
+  hipLaunchKernelGGL(k_col_inv<C>, grid, dim3(kThreads), cfg.col_lds, s, plan_args(p), cfg.col_tile,
+                     psi, ldpsi, T);
+  return hipGetLastError();
+}
+
+template <class C>
+hipError_t plane_generic(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const real_t<C>* vs, C* T,
+                         hipStream_t s) {
+  dim3 grid(p.n3, nb);
+  hipLaunchKernelGGL(k_plane<C>, grid, dim3(kThreads), cfg.plane_lds, s, plan_args(p),
+                     cfg.plane_rows, vs, T);
+  return hipGetLastError();
+}
+
+template <class C>
+hipError_t col_fwd_generic(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const C* T,
+                           const real_t<C>* kin, const C* in, int64_t ldin, const C* prev,
+                           int64_t ldprev, C* out, int64_t ldout, const Epilogue& ep, hipStream_t s) {
+  dim3 grid((p.ncols + cfg.col_tile - 1) / cfg.col_tile, nb);
+  hipLaunchKernelGGL(k_col_fwd<C>, grid, dim3(kThreads), cfg.col_lds, s, plan_args(p), cfg.col_tile,
+                     T, kin, in, ldin, prev, ldprev, out, ldout, ep.alpha, ep.beta, ep.gamma,
+                     ep.coef);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_fft_col_inv(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const cplx* psi,
                               int64_t ldpsi, cplx* T, hipStream_t s) {
   if (cfg.reg_col) return launch_fft_col_inv_reg(p, nb, psi, ldpsi, T, s);
-  dim3 grid((p.ncols + cfg.col_tile - 1) / cfg.col_tile, nb);
-  hipLaunchKernelGGL(k_col_inv, grid, dim3(kThreads), cfg.col_lds, s, plan_args(p), cfg.col_tile,
-                     psi, ldpsi, T);
-  return hipGetLastError();
+  return col_inv_generic<double2>(p, cfg, nb, psi, ldpsi, T, s);
+}
+hipError_t launch_fft_col_inv32(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const float2* psi,
+                                int64_t ldpsi, float2* T, hipStream_t s) {
+  if (cfg.reg_col) return launch_fft_col_inv_reg32(p, nb, psi, ldpsi, T, s);
+  return col_inv_generic<float2>(p, cfg, nb, psi, ldpsi, T, s);
 }
 
 hipError_t launch_fft_plane(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const double* vscaled,
                             cplx* T, hipStream_t s) {
   if (cfg.reg_plane) return launch_fft_plane_reg(p, cfg.plane_variant, nb, vscaled, T, s);
-  dim3 grid(p.n3, nb);
-  hipLaunchKernelGGL(k_plane, grid, dim3(kThreads), cfg.plane_lds, s, plan_args(p), cfg.plane_rows,
-                     vscaled, T);
-  return hipGetLastError();
+  return plane_generic<double2>(p, cfg, nb, vscaled, T, s);
+}
+hipError_t launch_fft_plane32(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const float* vscaled,
+                              float2* T, hipStream_t s) {
+  if (cfg.reg_plane) return launch_fft_plane_reg32(p, cfg.plane_variant, nb, vscaled, T, s);
+  return plane_generic<float2>(p, cfg, nb, vscaled, T, s);
 }
 
 hipError_t launch_fft_col_fwd(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const cplx* T,
                               const double* kin, const cplx* in, int64_t ldin, const cplx* prev,
-                              int64_t ldprev, cplx* out, int64_t ldout, double alpha, double beta,
-                              double gamma, hipStream_t s) {
+                              int64_t ldprev, cplx* out, int64_t ldout, const Epilogue& ep,
+                              hipStream_t s) {
   if (cfg.reg_col)
-    return launch_fft_col_fwd_reg(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, alpha, beta,
-                                  gamma, s);
-  dim3 grid((p.ncols + cfg.col_tile - 1) / cfg.col_tile, nb);
-  hipLaunchKernelGGL(k_col_fwd, grid, dim3(kThreads), cfg.col_lds, s, plan_args(p), cfg.col_tile, T,
-                     kin, in, ldin, prev, ldprev, out, ldout, alpha, beta, gamma);
-  return hipGetLastError();
+    return launch_fft_col_fwd_reg(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, ep, s);
+  return col_fwd_generic<double2>(p, cfg, nb, T, kin, in, ldin, prev, ldprev, out, ldout, ep, s);
+}
+hipError_t launch_fft_col_fwd32(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const float2* T,
+                                const float* kin, const float2* in, int64_t ldin, const float2* prev,
+                                int64_t ldprev, float2* out, int64_t ldout, const Epilogue& ep,
+                                hipStream_t s) {
+  if (cfg.reg_col)
+    return launch_fft_col_fwd_reg32(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, ep, s);
+  return col_fwd_generic<float2>(p, cfg, nb, T, kin, in, ldin, prev, ldprev, out, ldout, ep, s);
 }
 
 // Dynamic LDS above the default limit must be opted into per kernel.
 hipError_t fft_set_lds_limits(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_col_inv,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_plane, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_col_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+  const void* fns[6] = {(const void*)k_col_inv<double2>, (const void*)k_plane<double2>,
+                        (const void*)k_col_fwd<double2>, (const void*)k_col_inv<float2>,
+                        (const void*)k_plane<float2>, (const void*)k_col_fwd<float2>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }

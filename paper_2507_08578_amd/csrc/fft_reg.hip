@@ -61,10 +61,15 @@ __global__ void __launch_bounds__(kColThreads)
 k_col_fwd_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ T,
               const real_t<C>* __restrict__ kin, const C* in, int64_t ldin, const C* prev,
               int64_t ldprev, C* out, int64_t ldout, double alpha_d, double beta_d,
-              double gamma_d) {
+              double gamma_d, const double* __restrict__ coef) {
   using Rl = real_t<C>;
   constexpr int G = lane_group(N3), R = N3 / G, CT = kColThreads / G, TRS = N3 + 1;
   __shared__ C tile[CT * TRS];
+  if (coef) {
+    alpha_d = coef[0];
+    beta_d = coef[1];
+    gamma_d = coef[2];
+  }
   const Rl alpha = (Rl)alpha_d, beta = (Rl)beta_d, gamma = (Rl)gamma_d;
   const int c0 = blockIdx.x * CT;
   const int b = blockIdx.y;
@@ -101,7 +106,7 @@ k_col_fwd_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ T,
     C val;
     val.x = alpha * (loc.x + t * x.x) + beta * x.x;
     val.y = alpha * (loc.y + t * x.y) + beta * x.y;
-    if (gamma_d != 0.0) {
+    if (prevb) {
       const C p = prevb[g];
       val.x += gamma * p.x;
       val.y += gamma * p.y;
@@ -261,14 +266,14 @@ hipError_t col_inv_reg(const BoxPlan& p, int nb, const C* psi, int64_t ldpsi, C*
 template <class C>
 hipError_t col_fwd_reg(const BoxPlan& p, int nb, const C* T, const real_t<C>* kin, const C* in,
                        int64_t ldin, const C* prev, int64_t ldprev, C* out, int64_t ldout,
-                       double alpha, double beta, double gamma, hipStream_t s) {
+                       const Epilogue& ep, hipStream_t s) {
 #define CASE(N)                                                                               \
   if (p.n3 == N) {                                                                            \
     constexpr int CT = kColThreads / lane_group(N);                                           \
     dim3 grid((p.ncols + CT - 1) / CT, nb);                                                   \
     hipLaunchKernelGGL((k_col_fwd_reg<N, C>), grid, dim3(kColThreads), 0, s, p,               \
-                       axis_tw<C>(p.ax3), T, kin, in, ldin, prev, ldprev, out, ldout, alpha,  \
-                       beta, gamma);                                                          \
+                       axis_tw<C>(p.ax3), T, kin, in, ldin, prev, ldprev, out, ldout, ep.alpha,  \
+                       ep.beta, ep.gamma, ep.coef);                                           \
     return hipGetLastError();                                                                 \
   }
   PW_FAST_SIZES(CASE)
@@ -342,15 +347,14 @@ hipError_t launch_fft_col_inv_reg32(const BoxPlan& p, int nb, const float2* psi,
 
 hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const double* kin,
                                   const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev,
-                                  cplx* out, int64_t ldout, double alpha, double beta, double gamma,
-                                  hipStream_t s) {
-  return col_fwd_reg<double2>(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, alpha, beta, gamma, s);
+                                  cplx* out, int64_t ldout, const Epilogue& ep, hipStream_t s) {
+  return col_fwd_reg<double2>(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, ep, s);
 }
 hipError_t launch_fft_col_fwd_reg32(const BoxPlan& p, int nb, const float2* T, const float* kin,
                                     const float2* in, int64_t ldin, const float2* prev,
-                                    int64_t ldprev, float2* out, int64_t ldout, double alpha,
-                                    double beta, double gamma, hipStream_t s) {
-  return col_fwd_reg<float2>(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, alpha, beta, gamma, s);
+                                    int64_t ldprev, float2* out, int64_t ldout, const Epilogue& ep,
+                                    hipStream_t s) {
+  return col_fwd_reg<float2>(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, ep, s);
 }
 
 hipError_t launch_fft_plane_reg(const BoxPlan& p, int variant, int nb, const double* vscaled,

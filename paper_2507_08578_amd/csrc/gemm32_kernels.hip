@@ -198,8 +198,10 @@ k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __res
 
 // C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M] (FP64 sum, fixed order), rounded.
 __global__ void k_splitk_reduce32(int64_t M, int64_t N, int nsplit, const float2* __restrict__ work,
-                                  double alpha, const double* __restrict__ rowscale,
-                                  float2* __restrict__ C, int64_t ldc) {
+                                  double alpha, const double* __restrict__ alpha_dev,
+                                  const double* __restrict__ rowscale, float2* __restrict__ C,
+                                  int64_t ldc) {
+  if (alpha_dev) alpha = alpha_dev[0];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const int64_t j = idx / M, i = idx - j * M;
@@ -243,7 +245,8 @@ size_t gemm_cn32_work_elems(int64_t m, int64_t n, int64_t k, int bf16) {
 
 hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
-                            const double* rowscale, float2* work, hipStream_t s) {
+                            const double* rowscale, float2* work, hipStream_t s,
+                            const double* alpha_dev) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const SplitPlan p = bf16 ? split_plan32<MODE_BF16>(m, n, k) : split_plan32<MODE_F32>(m, n, k);
   dim3 grid(p.tiles_n, p.tiles_m, p.nsplit);
@@ -257,7 +260,7 @@ hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double al
   if (e != hipSuccess) return e;
   const int64_t tot = m * n;
   hipLaunchKernelGGL(k_splitk_reduce32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, n,
-                     (int)p.nsplit, (const float2*)work, alpha, rowscale, C, ldc);
+                     (int)p.nsplit, (const float2*)work, alpha, alpha_dev, rowscale, C, ldc);
   return hipGetLastError();
 }
 

@@ -101,9 +101,10 @@ k_gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict_
 // A k x m (lda), B k x n (ldb).  Output at out + z*zstride, leading dim ldo.
 __global__ void __launch_bounds__(kThreads)
 k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
-          const double* __restrict__ rowscale, const cplx* __restrict__ A, int64_t lda,
-          const cplx* __restrict__ B, int64_t ldb, double beta, cplx* __restrict__ out, int64_t ldo,
-          int64_t zstride) {
+          const double* __restrict__ alpha_dev, const double* __restrict__ rowscale,
+          const cplx* __restrict__ A, int64_t lda, const cplx* __restrict__ B, int64_t ldb,
+          double beta, cplx* __restrict__ out, int64_t ldo, int64_t zstride) {
+  if (alpha_dev) alpha = alpha_dev[0];
   __shared__ cplx As[kKcCN][kBM + 1];
   __shared__ cplx Bs[kKcCN][kBN + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -172,8 +173,10 @@ k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
 
 // C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M], z in fixed order.
 __global__ void k_splitk_reduce(int64_t M, int64_t N, int nsplit, const cplx* __restrict__ work,
-                                double alpha, const double* __restrict__ rowscale, double beta,
+                                double alpha, const double* __restrict__ alpha_dev,
+                                const double* __restrict__ rowscale, double beta,
                                 cplx* __restrict__ C, int64_t ldc) {
+  if (alpha_dev) alpha = alpha_dev[0];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const int64_t j = idx / M, i = idx - j * M;
@@ -222,23 +225,24 @@ size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k) {
 
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
-                          cplx* work, hipStream_t s, double beta) {
+                          cplx* work, hipStream_t s, double beta, const double* alpha_dev) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const SplitPlan p = split_plan(m, n, k);
   if (p.nsplit == 1) {
     dim3 grid(p.tiles_n, p.tiles_m, 1);
-    hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, alpha, rowscale,
-                       A, lda, B, ldb, beta, C, ldc, (int64_t)0);
+    hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, alpha, alpha_dev,
+                       rowscale, A, lda, B, ldb, beta, C, ldc, (int64_t)0);
     return hipGetLastError();
   }
   dim3 grid(p.tiles_n, p.tiles_m, p.nsplit);
   hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, 1.0,
-                     (const double*)nullptr, A, lda, B, ldb, 0.0, work, m, m * n);
+                     (const double*)nullptr, (const double*)nullptr, A, lda, B, ldb, 0.0, work, m,
+                     m * n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = m * n;
   hipLaunchKernelGGL(k_splitk_reduce, dim3((tot + 255) / 256), dim3(256), 0, s, m, n,
-                     (int)p.nsplit, (const cplx*)work, alpha, rowscale, beta, C, ldc);
+                     (int)p.nsplit, (const cplx*)work, alpha, alpha_dev, rowscale, beta, C, ldc);
   return hipGetLastError();
 }
 

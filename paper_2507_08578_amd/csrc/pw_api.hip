@@ -35,6 +35,7 @@ struct pw_ctx {
   int64_t launches[PW_STAGE_COUNT] = {0};
   double* pinned = nullptr;   // small pinned host scratch (64 doubles)
   int last_sweeps = 0;        // sweeps of the last dense eigensolve
+  int refs = 1;               // the caller's handle + one per live ham / batch
 
   hipEvent_t get_event() {
     if (!pool.empty()) {
@@ -80,6 +81,36 @@ struct pw_ham {
   float2* cprj32 = nullptr;
   float2* work32 = nullptr;
   float2* blk32[2] = {nullptr, nullptr};
+};
+
+struct BatchItem {
+  pw_ham* h = nullptr;
+  int64_t nb = 0;
+  cplx* y = nullptr;
+  cplx* hy = nullptr;
+  double* eig = nullptr;
+  double* resid = nullptr;
+  double* coef = nullptr;    // 3 * degree filter coefficients (device)
+  double* upper = nullptr;   // spectral upper bound (device)
+  int* flags = nullptr;      // 4 sticky failure flags (device)
+  int* sweeps = nullptr;     // sweeps of the last eigensolve (device)
+  int stream = 0;
+};
+
+struct pw_batch {
+  pw_ctx* ctx = nullptr;
+  int degree = 0;
+  pw_prec prec = PW_FP64;
+  std::vector<BatchItem> items;
+  std::vector<hipStream_t> streams;
+  hipStream_t s0 = nullptr;         // graph launch / fork-join stream
+  std::vector<hipEvent_t> ev;       // [0] ctx->s0, [1] s0->ctx, [2] fork, [3 + k] join of stream k
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<void*> allocs;
+  int* flags_dev = nullptr;         // 4 per item
+  int* flags_host = nullptr;        // pinned copy
+  int max_sweeps = 0;
 };
 
 namespace {
@@ -176,16 +207,20 @@ pw_status check_hot(pw_ham* h, pw_prec prec, int64_t nb) {
   return PW_OK;
 }
 
-// out = alpha (H in) + beta in + gamma prev (prev may alias out).
+// out = alpha (H in) + beta in + gamma prev (prev may alias out).  coef (device,
+// may be null) holds {alpha, beta, gamma} and then overrides the host scalars;
+// prev is read whenever it is non-null.
 pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* out, int64_t ldout,
-                    double alpha, double beta, double gamma, const cplx* prev, int64_t ldprev) {
+                    double alpha, double beta, double gamma, const cplx* prev, int64_t ldprev,
+                    const double* coef = nullptr) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_PROJ);
     HIPCHK(c, launch_gemm_cn(h->nproj, nb, h->npw, alpha, h->proj, h->npw, in, ldin, h->cprj,
-                             h->nproj, h->ekb_dev, h->gemm_work, s));
+                             h->nproj, h->ekb_dev, h->gemm_work, s, 0.0, coef));
   }
+  const Epilogue ep{alpha, beta, gamma, coef};
   for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
     const int nc = (int)std::min<int64_t>(h->chunk, nb - c0);
     {
@@ -199,8 +234,8 @@ pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* o
     {
       StageScope sc(c, PW_STAGE_FFT_COL_FWD);
       HIPCHK(c, launch_fft_col_fwd(h->plan, h->cfg, nc, h->T, h->kin, in + c0 * ldin, ldin,
-                                   gamma != 0.0 ? prev + c0 * ldprev : nullptr, ldprev,
-                                   out + c0 * ldout, ldout, alpha, beta, gamma, s));
+                                   prev ? prev + c0 * ldprev : nullptr, ldprev, out + c0 * ldout,
+                                   ldout, ep, s));
     }
   }
   if (h->nproj > 0) {
@@ -213,32 +248,33 @@ pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* o
 
 // Low-precision H application on complex64 blocks (FFT route in FP32; the
 // projector products in FP32 or, with bf16, bfloat16 operands; FP32
-// accumulation): out = alpha (H in) + beta in + gamma prev.
+// accumulation): out = alpha (H in) + beta in + gamma prev, coef as above.
 pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t ldin, float2* out,
                       int64_t ldout, double alpha, double beta, double gamma, const float2* prev,
-                      int64_t ldprev) {
+                      int64_t ldprev, const double* coef = nullptr) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_PROJ);
     HIPCHK(c, launch_gemm_cn32(bf16, h->nproj, nb, h->npw, alpha, h->proj32, h->npw, in, ldin,
-                               h->cprj32, h->nproj, h->ekb_dev, h->work32, s));
+                               h->cprj32, h->nproj, h->ekb_dev, h->work32, s, coef));
   }
+  const Epilogue ep{alpha, beta, gamma, coef};
   for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
     const int nc = (int)std::min<int64_t>(h->chunk, nb - c0);
     {
       StageScope sc(c, PW_STAGE_FFT_COL_INV);
-      HIPCHK(c, launch_fft_col_inv_reg32(h->plan, nc, in + c0 * ldin, ldin, h->T32, s));
+      HIPCHK(c, launch_fft_col_inv32(h->plan, h->cfg, nc, in + c0 * ldin, ldin, h->T32, s));
     }
     {
       StageScope sc(c, PW_STAGE_FFT_PLANE);
-      HIPCHK(c, launch_fft_plane_reg32(h->plan, h->cfg.plane_variant, nc, h->vs32, h->T32, s));
+      HIPCHK(c, launch_fft_plane32(h->plan, h->cfg, nc, h->vs32, h->T32, s));
     }
     {
       StageScope sc(c, PW_STAGE_FFT_COL_FWD);
-      HIPCHK(c, launch_fft_col_fwd_reg32(h->plan, nc, h->T32, h->kin32, in + c0 * ldin, ldin,
-                                         gamma != 0.0 ? prev + c0 * ldprev : nullptr, ldprev,
-                                         out + c0 * ldout, ldout, alpha, beta, gamma, s));
+      HIPCHK(c, launch_fft_col_fwd32(h->plan, h->cfg, nc, h->T32, h->kin32, in + c0 * ldin, ldin,
+                                     prev ? prev + c0 * ldprev : nullptr, ldprev, out + c0 * ldout,
+                                     ldout, ep, s));
     }
   }
   if (h->nproj > 0) {
@@ -309,6 +345,139 @@ hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* 
   return e;
 }
 
+// Runs the hot-path helpers of one context on another stream, untimed.
+struct StreamSwap {
+  pw_ctx* c;
+  hipStream_t old;
+  bool timing;
+  StreamSwap(pw_ctx* ctx, hipStream_t s) : c(ctx), old(ctx->stream), timing(ctx->timing) {
+    c->stream = s;
+    c->timing = false;
+  }
+  ~StreamSwap() {
+    c->stream = old;
+    c->timing = timing;
+  }
+};
+
+// Chebyshev filter of one batch item with coefficients formed on the device
+// from its Ritz values; the first product reuses W = H Y.
+pw_status batch_filter(pw_batch* b, BatchItem& it) {
+  pw_ham* h = it.h;
+  pw_ctx* c = h->ctx;
+  hipStream_t s = c->stream;
+  const int64_t nb = it.nb, npw = h->npw;
+  const int m = b->degree;
+  HIPCHK(c, launch_cheb_coef(it.eig, (int)nb, it.upper, m, it.coef, it.flags + 2, s));
+  pw_status st;
+  if (b->prec != PW_FP64) {
+    const int bf16 = b->prec == PW_BF16;
+    float2* buf[2] = {h->blk32[0], h->blk32[1]};
+    HIPCHK(c, launch_block_to_f32(npw, nb, it.y, npw, buf[0], npw, s));
+    HIPCHK(c, launch_axpby_to_f32(npw, nb, 0.0, it.hy, npw, 0.0, it.y, npw, buf[1], npw, s, it.coef));
+    for (int i = 2; i <= m; ++i) {
+      const int cur = (i - 1) & 1, nxt = i & 1;
+      if ((st = ham_apply32(h, bf16, nb, buf[cur], npw, buf[nxt], npw, 0.0, 0.0, 0.0, buf[nxt], npw,
+                            it.coef + 3 * (i - 1))) != PW_OK)
+        return st;
+    }
+    HIPCHK(c, launch_block_to_f64(npw, nb, buf[m & 1], npw, it.y, npw, s));
+    return PW_OK;
+  }
+  cplx* buf[2] = {it.y, h->blk};
+  HIPCHK(c, launch_axpby_block(npw, nb, 0.0, it.hy, npw, 0.0, it.y, npw, h->blk, npw, s, it.coef));
+  for (int i = 2; i <= m; ++i) {
+    const int cur = (i - 1) & 1, nxt = i & 1;
+    if ((st = ham_apply(h, nb, buf[cur], npw, buf[nxt], npw, 0.0, 0.0, 0.0, buf[nxt], npw,
+                        it.coef + 3 * (i - 1))) != PW_OK)
+      return st;
+  }
+  if (m & 1) HIPCHK(c, launch_copy_block(npw, nb, h->blk, npw, it.y, npw, s));
+  return PW_OK;
+}
+
+// Cholesky orthonormalisation then Rayleigh-Ritz of one batch item, with no
+// host synchronisation (one-workgroup eigensolve, failures go to its flags).
+pw_status batch_ortho_rr(BatchItem& it) {
+  pw_ham* h = it.h;
+  pw_ctx* c = h->ctx;
+  hipStream_t s = c->stream;
+  const int64_t nb = it.nb, npw = h->npw;
+  HIPCHK(c, launch_gemm_cn(nb, nb, npw, 1.0, it.y, npw, it.y, npw, h->sub0, nb, nullptr,
+                           h->gemm_work, s));
+  HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
+  HIPCHK(c, chol_blocked(nb, h->sub0, nb, h->dinv, h->panel, h->dtol, h->status_dev, s));
+  HIPCHK(c, trsm_right(npw, nb, it.y, npw, h->sub0, nb, h->dinv, h->blk, s));
+  pw_status st = ham_apply(h, nb, it.y, npw, it.hy, npw, 1.0, 0.0, 0.0, nullptr, 0);
+  if (st != PW_OK) return st;
+  HIPCHK(c, launch_gemm_cn(nb, nb, npw, 1.0, it.y, npw, it.hy, npw, h->sub0, nb, nullptr,
+                           h->gemm_work, s));
+  HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
+  HIPCHK(c, launch_heev_small_async(nb, h->sub0, nb, it.eig, h->sub1, nb, it.sweeps, s));
+  if ((st = rotate_block(h, nb, it.y, npw, h->sub1)) != PW_OK) return st;
+  if ((st = rotate_block(h, nb, it.hy, npw, h->sub1)) != PW_OK) return st;
+  HIPCHK(c, launch_residuals(npw, nb, it.hy, npw, it.y, npw, it.eig, it.resid, s));
+  HIPCHK(c, launch_batch_flags(h->status_dev, it.sweeps, it.flags, s));
+  return PW_OK;
+}
+
+// One iteration of every item, forked from s0 over the batch streams and
+// joined back (also the body of the captured graph).
+pw_status batch_issue(pw_batch* b, bool filter) {
+  pw_ctx* c = b->ctx;
+  HIPCHK(c, hipEventRecord(b->ev[2], b->s0));
+  for (hipStream_t st : b->streams) HIPCHK(c, hipStreamWaitEvent(st, b->ev[2], 0));
+  for (BatchItem& it : b->items) {
+    StreamSwap sw(c, b->streams[it.stream]);
+    pw_status st;
+    if (filter && (st = batch_filter(b, it)) != PW_OK) return st;
+    if ((st = batch_ortho_rr(it)) != PW_OK) return st;
+  }
+  for (size_t k = 0; k < b->streams.size(); ++k) {
+    HIPCHK(c, hipEventRecord(b->ev[3 + k], b->streams[k]));
+    HIPCHK(c, hipStreamWaitEvent(b->s0, b->ev[3 + k], 0));
+  }
+  return PW_OK;
+}
+
+// Reads the flags of all items (synchronises s0) and reports the first failure.
+pw_status batch_check(pw_batch* b) {
+  pw_ctx* c = b->ctx;
+  const size_t bytes = 4 * b->items.size() * sizeof(int);
+  HIPCHK(c, hipMemcpyAsync(b->flags_host, b->flags_dev, bytes, hipMemcpyDeviceToHost, b->s0));
+  HIPCHK(c, hipStreamSynchronize(b->s0));
+  b->max_sweeps = 0;
+  for (size_t i = 0; i < b->items.size(); ++i) {
+    const int* f = b->flags_host + 4 * i;
+    b->max_sweeps = std::max(b->max_sweeps, f[3]);
+    const std::string who = "batch item " + std::to_string(i) + ": ";
+    if (f[0])
+      return fail(c, PW_ERR_NOT_POSDEF,
+                  who + "Gram matrix not positive definite at pivot " + std::to_string(f[0] - 1));
+    if (f[1]) return fail(c, PW_ERR_NO_CONVERGENCE, who + "Jacobi eigensolver hit its sweep limit");
+    if (f[2])
+      return fail(c, PW_ERR_INVALID_ARG,
+                  who + "Ritz values outside a0 < a < b; the filter was skipped");
+  }
+  return PW_OK;
+}
+
+// Orders s0 after the context stream and clears the flags.
+pw_status batch_enter(pw_batch* b) {
+  pw_ctx* c = b->ctx;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipEventRecord(b->ev[0], c->stream));
+  HIPCHK(c, hipStreamWaitEvent(b->s0, b->ev[0], 0));
+  HIPCHK(c, hipMemsetAsync(b->flags_dev, 0, 4 * b->items.size() * sizeof(int), b->s0));
+  return PW_OK;
+}
+// Orders the context stream after s0 and checks the flags.
+pw_status batch_leave(pw_batch* b) {
+  pw_ctx* c = b->ctx;
+  HIPCHK(c, hipEventRecord(b->ev[1], b->s0));
+  HIPCHK(c, hipStreamWaitEvent(c->stream, b->ev[1], 0));
+  return batch_check(b);
+}
 }  // namespace
 
 extern "C" {
@@ -368,8 +537,11 @@ pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
   return PW_OK;
 }
 
-pw_status pw_ctx_destroy(pw_ctx* ctx) {
-  if (!ctx) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+namespace {
+// Frees the context once the caller's handle and every ham / batch made on
+// it are gone, whatever order they are destroyed in.
+void ctx_release(pw_ctx* ctx) {
+  if (--ctx->refs > 0) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& p : ctx->pending) {
@@ -379,6 +551,12 @@ pw_status pw_ctx_destroy(pw_ctx* ctx) {
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
+}
+}  // namespace
+
+pw_status pw_ctx_destroy(pw_ctx* ctx) {
+  if (!ctx) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  ctx_release(ctx);
   return PW_OK;
 }
 
@@ -589,13 +767,6 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
     ax->tw32 = t32;
   }
   if (d->low_prec) {
-    if (!h->cfg.reg_col || !h->cfg.reg_plane) {
-      free_ham(h);
-      delete h;
-      return fail(ctx, PW_ERR_UNSUPPORTED,
-                  "the FP32/BF16 path needs a cubic box of a length with register-resident FFT "
-                  "kernels (24, 32, 36, 48, 64, 72, 96, 120, 128, 144, 160)");
-    }
     h->low_prec = true;
     TRY(dalloc(h, &h->kin32, (size_t)npw));
     TRY(dalloc(h, &h->vs32, (size_t)nbox));
@@ -618,16 +789,19 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   }
   HIPCHK(ctx, hipStreamSynchronize(s));
 #undef TRY
+  ++ctx->refs;
   *out = h;
   return PW_OK;
 }
 
 pw_status pw_ham_destroy(pw_ham* h) {
   if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
-  (void)hipSetDevice(h->ctx->device);
-  (void)hipStreamSynchronize(h->ctx->stream);
+  pw_ctx* c = h->ctx;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
   free_ham(h);
   delete h;
+  ctx_release(c);
   return PW_OK;
 }
 
@@ -849,6 +1023,183 @@ pw_status pw_upper_bound(pw_ham* h, double* b_host) {
     b += std::max(wmax, 0.0);
   }
   *b_host = b;
+  return PW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched subspace iteration
+// ---------------------------------------------------------------------------
+pw_status pw_batch_destroy(pw_batch* b) {
+  if (!b) return fail(nullptr, PW_ERR_INVALID_ARG, "batch is NULL");
+  (void)hipSetDevice(b->ctx->device);
+  if (b->s0) (void)hipStreamSynchronize(b->s0);
+  for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  if (b->s0) (void)hipStreamDestroy(b->s0);
+  for (void* p : b->allocs) (void)hipFree(p);
+  if (b->flags_host) (void)hipHostFree(b->flags_host);
+  pw_ctx* c = b->ctx;
+  delete b;
+  ctx_release(c);
+  return PW_OK;
+}
+
+pw_status pw_batch_create(pw_ctx* ctx, int32_t n, pw_ham* const* hams, const int64_t* nb,
+                          void* const* y, void* const* hy, double* const* eig,
+                          double* const* resid, int32_t degree, pw_prec prec, int32_t nstreams,
+                          pw_batch** out) {
+  if (!ctx) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (!out) return fail(ctx, PW_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1) return fail(ctx, PW_ERR_INVALID_ARG, "batch needs n >= 1 items");
+  if (!hams || !nb || !y || !hy || !eig || !resid)
+    return fail(ctx, PW_ERR_INVALID_ARG, "NULL item array");
+  if (degree < 1) return fail(ctx, PW_ERR_INVALID_ARG, "degree must be >= 1");
+  if (prec != PW_FP64 && prec != PW_FP32 && prec != PW_BF16)
+    return fail(ctx, PW_ERR_INVALID_ARG, "unknown precision");
+  if (nstreams < 1 || nstreams > 64) return fail(ctx, PW_ERR_INVALID_ARG, "nstreams outside [1, 64]");
+  std::unordered_set<const pw_ham*> seen;
+  for (int32_t i = 0; i < n; ++i) {
+    const std::string who = "item " + std::to_string(i) + ": ";
+    pw_ham* h = hams[i];
+    if (!h || h->ctx != ctx) return fail(ctx, PW_ERR_INVALID_ARG, who + "ham NULL or of another ctx");
+    if (!seen.insert(h).second) return fail(ctx, PW_ERR_INVALID_ARG, who + "ham used twice");
+    if (nb[i] < 1 || nb[i] > 64 || nb[i] > h->nb_max)
+      return fail(ctx, PW_ERR_INVALID_ARG, who + "nb outside [1, min(64, nb_max)]");
+    if (prec != PW_FP64 && !h->low_prec)
+      return fail(ctx, PW_ERR_UNSUPPORTED, who + "FP32/BF16 filter needs a low_prec handle");
+    if (!y[i] || !hy[i] || !eig[i] || !resid[i])
+      return fail(ctx, PW_ERR_INVALID_ARG, who + "NULL buffer");
+    if (ranges_overlap(y[i], h->npw, hy[i], h->npw, h->npw, nb[i]))
+      return fail(ctx, PW_ERR_INVALID_ARG, who + "y and hy overlap");
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  std::vector<double> upper(n);
+  for (int32_t i = 0; i < n; ++i) {
+    pw_status st = pw_upper_bound(hams[i], &upper[i]);
+    if (st != PW_OK) return st;
+  }
+  pw_batch* b = new pw_batch();
+  b->ctx = ctx;
+  ++ctx->refs;   // released by pw_batch_destroy, also on the failure paths below
+  b->degree = degree;
+  b->prec = prec;
+  const int ns = std::min<int32_t>(nstreams, n);
+  auto bail_hip = [&](hipError_t e, const char* what) {
+    (void)hipGetLastError();
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    pw_batch_destroy(b);
+    return fail(ctx, e == hipErrorOutOfMemory ? PW_ERR_OOM : PW_ERR_HIP, msg);
+  };
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&b->s0, hipStreamNonBlocking)) != hipSuccess)
+    return bail_hip(e, "hipStreamCreateWithFlags");
+  for (int k = 0; k < ns; ++k) {
+    hipStream_t st = nullptr;
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
+      return bail_hip(e, "hipStreamCreateWithFlags");
+    b->streams.push_back(st);
+  }
+  for (int k = 0; k < 3 + ns; ++k) {
+    hipEvent_t ev = nullptr;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+      return bail_hip(e, "hipEventCreateWithFlags");
+    b->ev.push_back(ev);
+  }
+  const size_t per_item = (size_t)3 * degree + 1;
+  double* dbl = nullptr;
+  int* ints = nullptr;
+  if ((e = hipMalloc(&dbl, per_item * n * sizeof(double))) != hipSuccess)
+    return bail_hip(e, "hipMalloc");
+  b->allocs.push_back(dbl);
+  if ((e = hipMalloc(&ints, (size_t)5 * n * sizeof(int))) != hipSuccess) return bail_hip(e, "hipMalloc");
+  b->allocs.push_back(ints);
+  void* pin = nullptr;
+  if ((e = hipHostMalloc(&pin, (size_t)4 * n * sizeof(int), hipHostMallocDefault)) != hipSuccess)
+    return bail_hip(e, "hipHostMalloc");
+  b->flags_host = static_cast<int*>(pin);
+  b->flags_dev = ints;
+  // items go to the least-loaded stream, largest first
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int p, int q) {
+    return hams[p]->npw * nb[p] > hams[q]->npw * nb[q];
+  });
+  std::vector<double> load(ns, 0.0);
+  b->items.resize(n);
+  for (int i = 0; i < n; ++i) {
+    BatchItem& it = b->items[i];
+    it.h = hams[i];
+    it.nb = nb[i];
+    it.y = static_cast<cplx*>(y[i]);
+    it.hy = static_cast<cplx*>(hy[i]);
+    it.eig = eig[i];
+    it.resid = resid[i];
+    it.coef = dbl + per_item * i;
+    it.upper = it.coef + 3 * degree;
+    it.flags = ints + 4 * i;
+    it.sweeps = ints + 4 * n + i;
+  }
+  for (int i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->items[i].stream = k;
+    load[k] += (double)hams[i]->npw * nb[i];
+  }
+  for (int i = 0; i < n; ++i)
+    if ((e = hipMemcpyAsync(b->items[i].upper, &upper[i], sizeof(double), hipMemcpyHostToDevice,
+                            b->s0)) != hipSuccess)
+      return bail_hip(e, "hipMemcpyAsync");
+  if ((e = hipMemsetAsync(ints, 0, (size_t)5 * n * sizeof(int), b->s0)) != hipSuccess)
+    return bail_hip(e, "hipMemsetAsync");
+  if ((e = hipStreamSynchronize(b->s0)) != hipSuccess) return bail_hip(e, "hipStreamSynchronize");
+  *out = b;
+  return PW_OK;
+}
+
+
+pw_status pw_batch_start(pw_batch* b) {
+  if (!b) return fail(nullptr, PW_ERR_INVALID_ARG, "batch is NULL");
+  pw_status st;
+  if ((st = batch_enter(b)) != PW_OK) return st;
+  if ((st = batch_issue(b, false)) != PW_OK) return st;
+  return batch_leave(b);
+}
+
+pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
+  if (!b) return fail(nullptr, PW_ERR_INVALID_ARG, "batch is NULL");
+  if (iters < 0) return fail(b->ctx, PW_ERR_INVALID_ARG, "iters < 0");
+  pw_ctx* c = b->ctx;
+  pw_status st;
+  if ((st = batch_enter(b)) != PW_OK) return st;
+  if (use_graph && !b->exec) {
+    HIPCHK(c, hipStreamBeginCapture(b->s0, hipStreamCaptureModeThreadLocal));
+    st = batch_issue(b, true);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->s0, &g);
+    if (st != PW_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(c, PW_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    b->graph = g;
+    HIPCHK(c, hipGraphInstantiateWithFlags(&b->exec, b->graph, 0));
+  }
+  for (int32_t t = 0; t < iters; ++t) {
+    if (use_graph) HIPCHK(c, hipGraphLaunch(b->exec, b->s0));
+    else if ((st = batch_issue(b, true)) != PW_OK) return st;
+  }
+  return batch_leave(b);
+}
+
+pw_status pw_batch_max_sweeps(const pw_batch* b, int32_t* sweeps) {
+  if (!b || !sweeps) return fail(nullptr, PW_ERR_INVALID_ARG, "batch or sweeps is NULL");
+  *sweeps = b->max_sweeps;
   return PW_OK;
 }
 

@@ -61,18 +61,34 @@ void fft_host_twiddles(int n, std::vector<cplx>* out);
 // Factor n into passes; false if unsupported.
 bool fft_factor(int n, FftAxis* ax);
 
+// Coefficients of the gather epilogue out = alpha (loc + kin in) + beta in + gamma prev.
+// If coef is non-null the kernel reads (alpha, beta, gamma) = coef[0..2] from
+// device memory (graph-replayable filter steps); prev is read iff non-null.
+struct Epilogue {
+  double alpha, beta, gamma;
+  const double* coef;
+};
+
 // psi block (nb bands from band0) -> T[b][j3][c], backward along N3.
 hipError_t launch_fft_col_inv(const BoxPlan& p, const FftLaunchCfg& cfg, int nb,
                               const cplx* psi, int64_t ldpsi, cplx* T, hipStream_t s);
 // per (band, plane): N2 backward, N1 backward, x V, N1 forward, N2 forward, in place on T.
 hipError_t launch_fft_plane(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const double* vscaled,
                             cplx* T, hipStream_t s);
-// forward along N3 and gather, with the epilogue
-// out = alpha*(loc + kin*in) + beta*in + gamma*prev   (prev may alias out; may be null if gamma==0)
+// forward along N3 and gather, with the epilogue (prev may alias out)
 hipError_t launch_fft_col_fwd(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const cplx* T,
                               const double* kin, const cplx* in, int64_t ldin, const cplx* prev,
-                              int64_t ldprev, cplx* out, int64_t ldout, double alpha, double beta,
-                              double gamma, hipStream_t s);
+                              int64_t ldprev, cplx* out, int64_t ldout, const Epilogue& ep,
+                              hipStream_t s);
+// FP32 versions (complex64 blocks, FP32 tables): register kernels when the box allows, else generic
+hipError_t launch_fft_col_inv32(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const float2* psi,
+                                int64_t ldpsi, float2* T, hipStream_t s);
+hipError_t launch_fft_plane32(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const float* vscaled,
+                              float2* T, hipStream_t s);
+hipError_t launch_fft_col_fwd32(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const float2* T,
+                                const float* kin, const float2* in, int64_t ldin, const float2* prev,
+                                int64_t ldprev, float2* out, int64_t ldout, const Epilogue& ep,
+                                hipStream_t s);
 
 // Allow `bytes` of dynamic LDS for the FFT kernels (above the default cap).
 hipError_t fft_set_lds_limits(size_t bytes);
@@ -88,8 +104,7 @@ hipError_t launch_fft_plane_reg(const BoxPlan& p, int variant, int nb, const dou
                                 cplx* T, hipStream_t s);
 hipError_t launch_fft_col_fwd_reg(const BoxPlan& p, int nb, const cplx* T, const double* kin,
                                   const cplx* in, int64_t ldin, const cplx* prev, int64_t ldprev,
-                                  cplx* out, int64_t ldout, double alpha, double beta, double gamma,
-                                  hipStream_t s);
+                                  cplx* out, int64_t ldout, const Epilogue& ep, hipStream_t s);
 // FP32 (complex64 blocks, FP32 V/N_box and kinetic tables) variants
 hipError_t launch_fft_col_inv_reg32(const BoxPlan& p, int nb, const float2* psi, int64_t ldpsi,
                                     float2* T, hipStream_t s);
@@ -97,15 +112,17 @@ hipError_t launch_fft_plane_reg32(const BoxPlan& p, int variant, int nb, const f
                                   float2* T, hipStream_t s);
 hipError_t launch_fft_col_fwd_reg32(const BoxPlan& p, int nb, const float2* T, const float* kin,
                                     const float2* in, int64_t ldin, const float2* prev,
-                                    int64_t ldprev, float2* out, int64_t ldout, double alpha,
-                                    double beta, double gamma, hipStream_t s);
+                                    int64_t ldprev, float2* out, int64_t ldout, const Epilogue& ep,
+                                    hipStream_t s);
 
 // Split-K C = alpha diag(rowscale) A^H B + beta C (see pw_gemm_cn).  `work`
 // holds splits*m*n cplx; rowscale (m doubles on device) may be null.
 size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k);
+// alpha_dev (may be null): device scalar read in place of alpha.
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
-                          cplx* work, hipStream_t s, double beta = 0.0);
+                          cplx* work, hipStream_t s, double beta = 0.0,
+                          const double* alpha_dev = nullptr);
 hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
                           hipStream_t s);
@@ -115,7 +132,8 @@ hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const c
 size_t gemm_cn32_work_elems(int64_t m, int64_t n, int64_t k, int bf16);
 hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
-                            const double* rowscale, float2* work, hipStream_t s);
+                            const double* rowscale, float2* work, hipStream_t s,
+                            const double* alpha_dev = nullptr);
 hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
                             int64_t ldc, hipStream_t s);
@@ -127,7 +145,7 @@ hipError_t launch_block_to_f64(int64_t rows, int64_t cols, const float2* x, int6
                                int64_t ldy, hipStream_t s);
 hipError_t launch_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx* x, int64_t ldx,
                                double b, const cplx* y, int64_t ldy, float2* out, int64_t ldo,
-                               hipStream_t s);
+                               hipStream_t s, const double* coef = nullptr);
 hipError_t launch_real_to_f32(int64_t n, const double* src, double scale, float* dst, hipStream_t s);
 hipError_t launch_tw_to_f32(int n, const cplx* src, float2* dst, hipStream_t s);
 
@@ -141,9 +159,15 @@ hipError_t launch_hermitize(int64_t n, cplx* a, int64_t lda, hipStream_t s);
 hipError_t launch_copy_block(int64_t rows, int64_t cols, const cplx* src, int64_t lds, cplx* dst,
                              int64_t ldd, hipStream_t s);
 hipError_t launch_scale_rows_cols(int64_t n, const double* d, cplx* a, int64_t lda, hipStream_t s);
-// out = a*x + b*y for npw x nb blocks (out may alias y)
+// out = a*x + b*y for npw x nb blocks (out may alias y); coef (device, may be null) overrides a, b
 hipError_t launch_axpby_block(int64_t npw, int64_t nb, double a, const cplx* x, int64_t ldx, double b,
-                              const cplx* y, int64_t ldy, cplx* out, int64_t ldo, hipStream_t s);
+                              const cplx* y, int64_t ldy, cplx* out, int64_t ldo, hipStream_t s,
+                              const double* coef = nullptr);
+// Sticky failure flags of one batch item (chol_status may be null).
+hipError_t launch_batch_flags(const int* chol_status, const int* sweeps, int* flags, hipStream_t s);
+// Filter coefficients (3 per step) on the device from eig (ascending) and upper[0].
+hipError_t launch_cheb_coef(const double* eig, int nb, const double* upper, int degree, double* coef,
+                            int* flag, hipStream_t s);
 // status: 0 if every element finite, else 1
 hipError_t launch_check_finite(int64_t n, const double* x, int* flag, hipStream_t s);
 // Blocked Cholesky pieces: tol = n eps max diag, status = -1; per diagonal
@@ -160,6 +184,10 @@ hipError_t launch_identity(int64_t n, cplx* a, int64_t lda, hipStream_t s);
 // host_scratch: >= 4 doubles of pinned host memory.  Synchronises the stream
 // once per sweep.  *sweeps_done = sweeps used, or -1 if not converged.
 size_t heev_work_bytes(int64_t n);
+// n <= 64 only: the whole solve in one workgroup, no host synchronisation;
+// sweeps_dev[0] = sweeps used or -1.
+hipError_t launch_heev_small_async(int64_t n, const cplx* a, int64_t lda, double* w, cplx* q,
+                                   int64_t ldq, int* sweeps_dev, hipStream_t s);
 hipError_t heev_set_lds_limit(size_t bytes);
 hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int64_t ldq, void* work,
                        double* host_scratch, int* sweeps_done, hipStream_t s);
