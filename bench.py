@@ -40,6 +40,11 @@ PEAK = {   # MI355X published dense peaks
 WORKLOADS = {
     "C1": "8-atom diamond cell a=10.26 bohr, Gamma, ecut 8 Ha, 1189 PW, box 24^3, 8 s-projectors, "
           "16 bands, Chebyshev degree 8",
+    "C2": "8-atom diamond cell a=10.26 bohr, 27 k-points on the shifted 3x3x3 grid (1088-1180 PW "
+          "each), ecut 8 Ha, box 24^3, 8 s-projectors, 16 bands per k-point, Chebyshev degree 8, "
+          "all k-points in one batch (HIP graph)",
+    "C4": "64 independent 8-atom diamond cells, strain +-6%, ecut 8-16 Ha (1.1k-3.6k PW, boxes "
+          "24-36 per axis), 8 s-projectors, 16-32 bands, Chebyshev degree 8, one batch (HIP graph)",
     "C3": "64-atom 2x2x2 diamond supercell (jitter 0.05 bohr), Gamma, ecut 20 Ha, 37073 PW, box 96^3, "
           "256 s+p projectors, 160 bands, Chebyshev degree 8",
     "C5": "216-atom 3x3x3 diamond supercell a=30.78 bohr, Gamma, ecut 20 Ha, 124289 PW, box 144^3, "
@@ -53,7 +58,11 @@ def log(msg):
 
 def make_workload(name):
     import synth
-    return {"C1": synth.config_c1, "C3": synth.config_c3, "C5": synth.config_c5}[name]()
+    return {"C1": synth.config_c1, "C2": synth.config_c2, "C3": synth.config_c3,
+            "C4": synth.config_c4, "C5": synth.config_c5}[name]()
+
+
+BATCHED = ("C2", "C4")
 
 
 def fft_flops(n):
@@ -167,6 +176,174 @@ def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup):
             "max_resid": float(resid.max().cpu()), "sweeps": sweeps}
 
 
+def batch_roofline(stages, items, prec, degree):
+    """Dominant kernel of a directly issued batch iteration (per-branch HIP
+    events; concurrent branches overlap, so durations include sharing)."""
+    elem = 16 if prec == "fp64" else 8
+    cand = {k: v for k, v in stages.items()
+            if k in ("nonlocal", "proj", "fft_plane", "fft_col_inv", "fft_col_fwd") and v[1] > 0}
+    dom = max(cand, key=lambda k: cand[k][0])
+    total_ms, launches = cand[dom]
+    # one iteration: degree-1 filter products (prec) + 1 Rayleigh-Ritz product (fp64)
+    units = []
+    for w, ham in items:
+        N1, N2, N3 = w.box
+        nc, xr = ham.ncolumns, ham.extent1
+        for e, napp in ((elem, degree - 1), (16, 1)):
+            if dom == "fft_col_inv":
+                units.append(e * (w.npw + nc * N3) * w.nb * napp)
+            elif dom == "fft_col_fwd":
+                units.append(e * (nc * N3 + 2 * w.npw) * w.nb * napp)
+            elif dom == "fft_plane":
+                units.append(e * 2 * nc * N3 * w.nb * napp)
+            else:
+                units.append(e * (w.npw * w.nproj + w.nproj * w.nb + w.npw * w.nb) * napp)
+    total_bytes = sum(units)
+    ach = total_bytes / (total_ms * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+            "frac": ach / PEAK["hbm_gbs"], "avg_launch_ms": total_ms / launches,
+            "per_launch": f"algorithmic bytes of all {len(items)} items over one iteration "
+                          f"({total_bytes:.4g} B) / summed kernel time",
+            "note": "latency-bound configuration: kernels of concurrent branches overlap"}
+
+
+def run_batch(args):
+    """C2 / C4: all items in one pw_batch (graph replays), against the plain
+    FP64 per-item path (host-driven iterations, one item after another)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2507_08578_amd as pw
+    ws = make_workload(args.config)
+    mixed = args.precision != "fp64"
+    log(f"{len(ws)} items, npw {min(w.npw for w in ws)}-{max(w.npw for w in ws)}, "
+        f"nb {min(w.nb for w in ws)}-{max(w.nb for w in ws)}")
+    ctx = pw.Context(0)
+    hams = [pw.Hamiltonian.from_workload(ctx, w, nb_max=w.nb, low_prec=mixed) for w in ws]
+    X0 = [torch.from_numpy(synth.start_block(w.npw, w.nb, 100 + i)).cuda() for i, w in enumerate(ws)]
+    degree = ws[0].degree
+    bands = sum(w.nb for w in ws)
+    tuning = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        res = [h.autotune(args.precision, nb=w.nb, reps=3) for h, w in zip(hams, ws)]
+        tuning = {"items_tuned": len(res),
+                  "apply_ms_default_sum": sum(r["default_ms"] for r in res),
+                  "apply_ms_tuned_sum": sum(r["ms"] for r in res),
+                  "choices": sorted({json.dumps({k: r[k] for k in ("reg_col", "reg_plane",
+                                                                   "plane_variant", "chunk",
+                                                                   "gemm_blocks")})
+                                     for r in res}),
+                  "tuning_s": time.perf_counter() - t0}
+        log(f"autotuned {len(res)} items in {tuning['tuning_s']:.1f} s")
+    bt = pw.Batch(ctx, hams, X0, degree=degree, filter_prec=args.precision,
+                  nstreams=args.streams)
+    bt.start()
+    bt.iterate(args.warmup, graph=True)
+    log("batch warmup done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        bt.iterate(1, graph=True)
+        log(f"batch step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lam_batch = bt.eigenvalues()
+    sweeps = bt.max_sweeps()
+    max_resid = max(float(r.max().cpu()) for r in bt.resid)
+    # one directly issued, stage-timed iteration for the roofline
+    ctx.set_timing(True)
+    ctx.reset_timing()
+    bt.iterate(1, graph=False)
+    stages = ctx.stage_times()
+    ctx.set_timing(False)
+    roof = batch_roofline(stages, list(zip(ws, hams)), args.precision, degree)
+    value = bands * degree * args.steps / dt
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if not mixed else ("f32+f64" if args.precision == "fp32" else "bf16/f32+f64"),
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
+                   "filter_precision": args.precision, "subspace_precision": "fp64",
+                   "items": len(ws), "bands_total": bands, "streams": args.streams,
+                   "step": f"one iteration of every item: filter (degree {degree}, H*Y reused) "
+                           "+ Cholesky + Rayleigh-Ritz, replayed as one HIP graph"},
+        "filter_iter_ms": 1e3 * dt / args.steps,
+        "max_resid": max_resid, "eigensolver_max_sweeps": sweeps,
+        "roofline": roof,
+        "autotune": tuning,
+    }
+    bt.close()
+    if not args.no_compare:
+        # plain FP64 path: per-item handles and host-driven iterations, item after item
+        hams64 = hams if not mixed else [pw.Hamiltonian.from_workload(ctx, w, nb_max=w.nb)
+                                         for w in ws]
+        if mixed and not args.no_autotune:
+            for h, w in zip(hams64, ws):
+                h.autotune("fp64", nb=w.nb, reps=3)
+        states = []
+        for h, x in zip(hams64, X0):
+            Y = x.clone()
+            HY = torch.empty_like(Y)
+            eig = torch.empty(Y.shape[0], dtype=torch.float64, device="cuda")
+            res = torch.empty_like(eig)
+            h.orthonormalize(Y)
+            h.rayleigh_ritz(Y, HY, eig, res)
+            states.append([h, Y, HY, eig, res, eig.cpu(), h.upper_bound()])
+
+        def step_all():
+            for st in states:
+                h, Y, HY, eig, res, lam, b = st
+                h.cheb_filter(Y, degree, float(lam[-1]), b, float(lam[0]), hx=HY)
+                h.orthonormalize(Y)
+                h.rayleigh_ritz(Y, HY, eig, res)
+                st[5] = eig.cpu()
+
+        for _ in range(args.warmup):
+            step_all()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step_all()
+            log(f"per-item fp64 step {i + 1}/{args.steps} done")
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t0
+        d = max(float(np.abs(lb - st[5].numpy()).max()) for lb, st in zip(lam_batch, states))
+        out["fp64_per_item_path"] = {"ms_per_step": 1e3 * dt64 / args.steps,
+                                     "value": bands * degree * args.steps / dt64,
+                                     "speedup_batch_over_per_item": dt64 / dt}
+        out["eig_diff_vs_fp64_Ha"] = d
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_items(ws, args.cpu_bands or 16)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_items(ws, nb_each):
+    """Oracle H*psi on nb_each bands of every item, timed on the host."""
+    import oracle
+    import synth
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        threads = max([p.get("num_threads", 1) for p in blas] or [1])
+    except Exception:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    hs = [oracle.OracleHam.from_workload(w) for w in ws]
+    Xs = [synth.start_block(w.npw, min(nb_each, w.nb), 7).T for w in ws]
+    oracle.apply_h(hs[0], Xs[0][:, :1])
+    t0 = time.perf_counter()
+    n = 0
+    for h, X in zip(hs, Xs):
+        oracle.apply_h(h, X)
+        n += X.shape[1]
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": UNIT, "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} bands ({min(nb_each, max(w.nb for w in ws))} per item) of one FP64 "
+                      f"oracle H*psi over all {len(ws)} items, {dt:.2f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,10 +355,15 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=0, help="oracle band sample (0 = auto)")
+    ap.add_argument("--streams", type=int, default=8, help="batch branches (C2, C4)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of timing alternatives")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.config in BATCHED:
+        return run_batch(args)
 
     import torch
     import synth
@@ -197,9 +379,22 @@ def main():
     X0 = torch.from_numpy(synth.start_block(w.npw, nb, 0)).cuda()
     log("upper bound")
     b = ham.upper_bound()
+    tunings = {}
+
+    def tune(prec):
+        if args.no_autotune:
+            return
+        t0 = time.perf_counter()
+        r = ham.autotune(prec, nb=nb, reps=2)
+        r["tuning_s"] = time.perf_counter() - t0
+        tunings[prec] = r
+        log(f"autotune {prec}: {r}")
+
+    tune(args.precision)
     res = run_path(pw, ctx, ham, w, X0, b, args.precision, args.steps, args.warmup)
     ref = None
     if mixed and not args.no_compare:
+        tune("fp64")
         ref = run_path(pw, ctx, ham, w, X0, b, "fp64", args.steps, args.warmup)
     roof = roofline(res["stages"], args.steps, res["applies"], w, ham, nb, args.precision)
     dtype = "f64" if not mixed else ("f32+f64" if args.precision == "fp32" else "bf16/f32+f64")
@@ -216,6 +411,7 @@ def main():
         "eigensolver_sweeps": res["sweeps"],
         "roofline": roof,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in res["stages"].items()},
+        "autotune": tunings or None,
     }
     if ref is not None:
         d = float(abs(res["lam"] - ref["lam"]).max())
@@ -225,7 +421,7 @@ def main():
                                                    for k, v in ref["stages"].items()}}
         out["eig_diff_vs_fp64_Ha"] = d
     if not args.no_cpu_baseline:
-        nbs = args.cpu_bands or {"C1": 256, "C3": 64, "C5": 64}[args.config]
+        nbs = args.cpu_bands or {"C1": 2048, "C3": 64, "C5": 160}[args.config]
         log(f"cpu baseline: oracle H*psi on {nbs} bands")
         out["cpu_baseline"] = cpu_baseline(w, nbs)
     print(json.dumps(out), flush=True)

@@ -190,6 +190,36 @@ pw_status pw_rayleigh_ritz(pw_ham* ham, int64_t nb, void* y_dev, int64_t ld, voi
 pw_status pw_upper_bound(pw_ham* ham, double* b_host);
 
 /* ---------------------------------------------------------------------------
+ * Launch-shape tuning of H*psi.  A handle starts with the register-resident
+ * FFT kernels where they exist, the largest band chunk its buffer holds and
+ * 2048 target blocks for the split-K projector product; pw_ham_autotune
+ * times alternatives on the device and keeps the fastest.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t reg_col;        /* 1: register-resident column kernels (N3 in the fast set)       */
+  int32_t reg_plane;      /* 1: register-resident plane kernel (N1 = N2 in the fast set)     */
+  int32_t plane_variant;  /* 0: lane groups of up to 16 lanes; 1: up to 8 (N1 = 48, 64, 96)  */
+  int32_t chunk;          /* bands per FFT launch, [1, the handle's buffer]                  */
+  int32_t gemm_blocks;    /* split-K target block count of P^H psi, [1, 2048]                */
+  double ms;              /* pw_ham_autotune: median time of one H*psi of nb bands           */
+} pw_tuning;
+
+pw_status pw_ham_get_tuning(const pw_ham* ham, pw_tuning* t);
+/* UNSUPPORTED for a kernel family the box has no kernel for. */
+pw_status pw_ham_set_tuning(pw_ham* ham, const pw_tuning* t);
+/*
+ * Coordinate search over (1) the FFT kernel families, (2) the band chunk,
+ * (3) the split-K block count, each step keeping the fastest; every
+ * candidate timed as the median of reps H*psi applications of nb bands in
+ * precision prec (after one warm-up) with HIP events on the context's
+ * stream.  Leaves the handle at *best; *initial (may be NULL) receives the
+ * starting tuning and its time.  Overwrites the handle's internal work
+ * blocks; synchronises.
+ */
+pw_status pw_ham_autotune(pw_ham* ham, pw_prec prec, int64_t nb, int32_t reps, pw_tuning* best,
+                          pw_tuning* initial);
+
+/* ---------------------------------------------------------------------------
  * Batched subspace iteration over independent Hamiltonians (k-points of one
  * cell, or separate cells), section 5.1's Chebyshev-filtered iteration run
  * for many small problems at once (section 5.4 notes that k-points are
@@ -234,6 +264,9 @@ pw_status pw_batch_start(pw_batch* b);
  * (eigensolver sweep limit) or PW_ERR_INVALID_ARG (Ritz values not inside
  * a0 < a < b: that item's filter became the identity) for the first item
  * that failed in any of the iterations; pw_last_error names it.
+ * With stage timing on, directly issued iterations are timed per stage on
+ * the branch streams (kernels of concurrent branches overlap, so stage sums
+ * exceed wall time); graph replays are not timed.
  */
 pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph);
 /* Largest number of Jacobi sweeps any item used in the last start/iterate. */

@@ -279,6 +279,57 @@ class Hamiltonian:
         self.ctx.check(_LIB.pw_upper_bound(self.handle, ctypes.byref(b)))
         return b.value
 
+    # --- launch-shape tuning ---
+    _TUNING_KEYS = ("reg_col", "reg_plane", "plane_variant", "chunk", "gemm_blocks")
+
+    def get_tuning(self) -> dict:
+        t = _lib.PwTuning()
+        self.ctx.check(_LIB.pw_ham_get_tuning(self.handle, ctypes.byref(t)))
+        return {k: getattr(t, k) for k in self._TUNING_KEYS}
+
+    def set_tuning(self, tuning: dict):
+        t = _lib.PwTuning()
+        cur = self.get_tuning()
+        cur.update({k: int(v) for k, v in tuning.items() if k in self._TUNING_KEYS})
+        for k in self._TUNING_KEYS:
+            setattr(t, k, cur[k])
+        self.ctx.check(_LIB.pw_ham_set_tuning(self.handle, ctypes.byref(t)))
+
+    def tuning_key(self, prec, nb: int) -> str:
+        """Shape key of the tuning cache: box, sphere columns and extent, npw, nproj, nb, prec."""
+        N1, N2, N3 = self.box
+        return (f"{N1}x{N2}x{N3}/cols{self.ncolumns}/xr{self.extent1}/npw{self.npw}/"
+                f"proj{self.nproj}/nb{nb}/{prec if isinstance(prec, str) else int(prec)}")
+
+    def autotune(self, prec="fp64", nb: Optional[int] = None, reps: int = 3,
+                 cache: Optional[str] = None) -> dict:
+        """Time launch-shape alternatives on the device and keep the fastest.
+        cache: path of a JSON file of earlier choices keyed by tuning_key();
+        a hit is applied without timing, a miss is tuned and stored."""
+        import json
+        import os
+        nb = int(nb or self.nb_max)
+        key = self.tuning_key(prec, nb)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_tuning(table[key])
+                return dict(table[key], cached=True)
+        best, init = _lib.PwTuning(), _lib.PwTuning()
+        self.ctx.check(_LIB.pw_ham_autotune(self.handle, _prec(prec), nb, int(reps),
+                                            ctypes.byref(best), ctypes.byref(init)))
+        out = {k: getattr(best, k) for k in self._TUNING_KEYS}
+        out.update(ms=best.ms, default_ms=init.ms, cached=False)
+        if cache:
+            table[key] = {k: out[k] for k in self._TUNING_KEYS + ("ms", "default_ms")}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return out
+
 
 class Batch:
     """pw_batch: the Chebyshev-filtered subspace iteration of many independent

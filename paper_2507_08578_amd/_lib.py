@@ -41,6 +41,12 @@ class PwHamDesc(ctypes.Structure):
 
 
 # name -> (restype, argtypes)
+class PwTuning(ctypes.Structure):
+    """pw_tuning (include/pw.h)."""
+    _fields_ = [("reg_col", c_int32), ("reg_plane", c_int32), ("plane_variant", c_int32),
+                ("chunk", c_int32), ("gemm_blocks", c_int32), ("ms", c_double)]
+
+
 SIGNATURES = {
     "pw_status_string": (ctypes.c_char_p, [c_int]),
     "pw_version": (ctypes.c_char_p, []),
@@ -68,6 +74,10 @@ SIGNATURES = {
                                   ctypes.POINTER(c_int64)]),
     "pw_ctx_reset_timing": (c_int, [c_void_p]),
     "pw_ctx_last_sweeps": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
+    "pw_ham_get_tuning": (c_int, [c_void_p, ctypes.POINTER(PwTuning)]),
+    "pw_ham_set_tuning": (c_int, [c_void_p, ctypes.POINTER(PwTuning)]),
+    "pw_ham_autotune": (c_int, [c_void_p, c_int, c_int64, c_int32, ctypes.POINTER(PwTuning),
+                                ctypes.POINTER(PwTuning)]),
     "pw_batch_create": (c_int, [c_void_p, c_int32, ctypes.POINTER(c_void_p),
                                 ctypes.POINTER(c_int64), ctypes.POINTER(c_void_p),
                                 ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),

@@ -220,13 +220,13 @@ struct SplitPlan {
 };
 
 template <int MODE>
-SplitPlan split_plan32(int64_t m, int64_t n, int64_t k) {
+SplitPlan split_plan32(int64_t m, int64_t n, int64_t k, int target) {
   constexpr int Kc = KC<MODE>::value;
   SplitPlan p;
   p.tiles_m = (m + kBM - 1) / kBM;
   p.tiles_n = (n + kBN - 1) / kBN;
   const int64_t tiles = p.tiles_m * p.tiles_n;
-  int64_t want = (kTargetBlocks + tiles - 1) / tiles;
+  int64_t want = (target + tiles - 1) / tiles;
   const int64_t maxs = std::max<int64_t>(1, (k + Kc * 8 - 1) / (Kc * 8));
   want = std::max<int64_t>(1, std::min(want, maxs));
   int64_t ks = (k + want - 1) / want;
@@ -239,16 +239,19 @@ SplitPlan split_plan32(int64_t m, int64_t n, int64_t k) {
 }  // namespace
 
 size_t gemm_cn32_work_elems(int64_t m, int64_t n, int64_t k, int bf16) {
-  const SplitPlan p = bf16 ? split_plan32<MODE_BF16>(m, n, k) : split_plan32<MODE_F32>(m, n, k);
+  const SplitPlan p = bf16 ? split_plan32<MODE_BF16>(m, n, k, kTargetBlocks)
+                           : split_plan32<MODE_F32>(m, n, k, kTargetBlocks);
   return (size_t)(p.nsplit * m * n);
 }
 
 hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
                             const double* rowscale, float2* work, hipStream_t s,
-                            const double* alpha_dev) {
+                            const double* alpha_dev, int target) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  const SplitPlan p = bf16 ? split_plan32<MODE_BF16>(m, n, k) : split_plan32<MODE_F32>(m, n, k);
+  if (target < 1 || target > kTargetBlocks) target = kTargetBlocks;
+  const SplitPlan p = bf16 ? split_plan32<MODE_BF16>(m, n, k, target)
+                           : split_plan32<MODE_F32>(m, n, k, target);
   dim3 grid(p.tiles_n, p.tiles_m, p.nsplit);
   if (bf16)
     hipLaunchKernelGGL(k_gemm_cn32<MODE_BF16>, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, A, lda,

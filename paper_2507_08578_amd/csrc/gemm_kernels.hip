@@ -200,12 +200,12 @@ struct SplitPlan {
   int64_t tiles_m, tiles_n, nsplit, ksplit;
 };
 
-SplitPlan split_plan(int64_t m, int64_t n, int64_t k) {
+SplitPlan split_plan(int64_t m, int64_t n, int64_t k, int target) {
   SplitPlan p;
   p.tiles_m = (m + kBM - 1) / kBM;
   p.tiles_n = (n + kBN - 1) / kBN;
   const int64_t tiles = p.tiles_m * p.tiles_n;
-  int64_t want = (kTargetBlocks + tiles - 1) / tiles;
+  int64_t want = (target + tiles - 1) / tiles;
   const int64_t maxs = std::max<int64_t>(1, (k + kKcCN * 8 - 1) / (kKcCN * 8));
   want = std::max<int64_t>(1, std::min(want, maxs));
   int64_t ks = (k + want - 1) / want;
@@ -219,15 +219,17 @@ SplitPlan split_plan(int64_t m, int64_t n, int64_t k) {
 }  // namespace
 
 size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k) {
-  const SplitPlan p = split_plan(m, n, k);
+  const SplitPlan p = split_plan(m, n, k, kTargetBlocks);
   return p.nsplit > 1 ? (size_t)(p.nsplit * m * n) : 0;
 }
 
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
-                          cplx* work, hipStream_t s, double beta, const double* alpha_dev) {
+                          cplx* work, hipStream_t s, double beta, const double* alpha_dev,
+                          int target) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  const SplitPlan p = split_plan(m, n, k);
+  if (target < 1 || target > kTargetBlocks) target = kTargetBlocks;
+  const SplitPlan p = split_plan(m, n, k, target);
   if (p.nsplit == 1) {
     dim3 grid(p.tiles_n, p.tiles_m, 1);
     hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, alpha, alpha_dev,

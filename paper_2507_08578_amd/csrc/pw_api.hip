@@ -53,7 +53,11 @@ struct pw_ham {
   pw_ctx* ctx = nullptr;
   BoxPlan plan{};
   FftLaunchCfg cfg{};
-  int64_t npw = 0, nproj = 0, nb_max = 0, chunk = 0;
+  int64_t npw = 0, nproj = 0, nb_max = 0;
+  int64_t chunk = 0;         // bands per FFT launch (tunable, <= chunk_alloc)
+  int64_t chunk_alloc = 0;   // bands the FFT work buffer holds
+  int gemm_target = 2048;    // split-K target block count of the projector product (tunable)
+  bool reg_col_ok = false, reg_plane_ok = false, narrow_ok = false;
   std::vector<void*> allocs;
   double* kin = nullptr;
   double* vscaled = nullptr;
@@ -218,7 +222,7 @@ pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* o
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_PROJ);
     HIPCHK(c, launch_gemm_cn(h->nproj, nb, h->npw, alpha, h->proj, h->npw, in, ldin, h->cprj,
-                             h->nproj, h->ekb_dev, h->gemm_work, s, 0.0, coef));
+                             h->nproj, h->ekb_dev, h->gemm_work, s, 0.0, coef, h->gemm_target));
   }
   const Epilogue ep{alpha, beta, gamma, coef};
   for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
@@ -257,7 +261,8 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_PROJ);
     HIPCHK(c, launch_gemm_cn32(bf16, h->nproj, nb, h->npw, alpha, h->proj32, h->npw, in, ldin,
-                               h->cprj32, h->nproj, h->ekb_dev, h->work32, s, coef));
+                               h->cprj32, h->nproj, h->ekb_dev, h->work32, s, coef,
+                               h->gemm_target));
   }
   const Epilogue ep{alpha, beta, gamma, coef};
   for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
@@ -345,14 +350,16 @@ hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* 
   return e;
 }
 
-// Runs the hot-path helpers of one context on another stream, untimed.
+// Runs the hot-path helpers of one context on another stream (untimed while
+// a graph is being captured).
 struct StreamSwap {
   pw_ctx* c;
   hipStream_t old;
   bool timing;
-  StreamSwap(pw_ctx* ctx, hipStream_t s) : c(ctx), old(ctx->stream), timing(ctx->timing) {
+  StreamSwap(pw_ctx* ctx, hipStream_t s, bool untimed)
+      : c(ctx), old(ctx->stream), timing(ctx->timing) {
     c->stream = s;
-    c->timing = false;
+    if (untimed) c->timing = false;
   }
   ~StreamSwap() {
     c->stream = old;
@@ -423,12 +430,12 @@ pw_status batch_ortho_rr(BatchItem& it) {
 
 // One iteration of every item, forked from s0 over the batch streams and
 // joined back (also the body of the captured graph).
-pw_status batch_issue(pw_batch* b, bool filter) {
+pw_status batch_issue(pw_batch* b, bool filter, bool capturing) {
   pw_ctx* c = b->ctx;
   HIPCHK(c, hipEventRecord(b->ev[2], b->s0));
   for (hipStream_t st : b->streams) HIPCHK(c, hipStreamWaitEvent(st, b->ev[2], 0));
   for (BatchItem& it : b->items) {
-    StreamSwap sw(c, b->streams[it.stream]);
+    StreamSwap sw(c, b->streams[it.stream], capturing);
     pw_status st;
     if (filter && (st = batch_filter(b, it)) != PW_OK) return st;
     if ((st = batch_ortho_rr(it)) != PW_OK) return st;
@@ -477,6 +484,39 @@ pw_status batch_leave(pw_batch* b) {
   HIPCHK(c, hipEventRecord(b->ev[1], b->s0));
   HIPCHK(c, hipStreamWaitEvent(c->stream, b->ev[1], 0));
   return batch_check(b);
+}
+struct EventGuard {
+  hipEvent_t e = nullptr;
+  ~EventGuard() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+
+// Median time of one H application of nb bands under the handle's current
+// tuning (one untimed warm-up).
+pw_status time_apply(pw_ham* h, pw_prec prec, int64_t nb, void* in, void* out, int reps, double* ms) {
+  pw_ctx* c = h->ctx;
+  EventGuard a, b;
+  HIPCHK(c, hipEventCreate(&a.e));
+  HIPCHK(c, hipEventCreate(&b.e));
+  std::vector<double> v;
+  for (int r = -1; r < reps; ++r) {
+    HIPCHK(c, hipEventRecord(a.e, c->stream));
+    pw_status st = prec == PW_FP64
+                       ? ham_apply(h, nb, static_cast<const cplx*>(in), h->npw,
+                                   static_cast<cplx*>(out), h->npw, 1.0, 0.0, 0.0, nullptr, 0)
+                       : ham_apply32(h, prec == PW_BF16, nb, static_cast<const float2*>(in), h->npw,
+                                     static_cast<float2*>(out), h->npw, 1.0, 0.0, 0.0, nullptr, 0);
+    if (st != PW_OK) return st;
+    HIPCHK(c, hipEventRecord(b.e, c->stream));
+    HIPCHK(c, hipEventSynchronize(b.e));
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, a.e, b.e));
+    if (r >= 0) v.push_back(t);
+  }
+  std::sort(v.begin(), v.end());
+  *ms = v[v.size() / 2];
+  return PW_OK;
 }
 }  // namespace
 
@@ -739,6 +779,10 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   const size_t per_band = (size_t)P.n3 * P.ncols;
   const size_t budget = (size_t)512 << 20;
   h->chunk = std::max<int64_t>(1, std::min<int64_t>(h->nb_max, budget / (per_band * sizeof(cplx))));
+  h->chunk_alloc = h->chunk;
+  h->reg_col_ok = h->cfg.reg_col;
+  h->reg_plane_ok = h->cfg.reg_plane;
+  h->narrow_ok = h->cfg.reg_plane && fft_reg_plane_narrow(P);
   TRY(dalloc(h, &h->T, per_band * h->chunk));
   if (h->nproj > 0) TRY(dalloc(h, &h->cprj, (size_t)(h->nproj * h->nb_max)));
   size_t wmax = 0;
@@ -783,7 +827,7 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
       TRY(dalloc(h, &h->work32, w32));
     }
     const size_t per_band32 = (size_t)P.n3 * P.ncols;
-    TRY(dalloc(h, &h->T32, per_band32 * h->chunk));
+    TRY(dalloc(h, &h->T32, per_band32 * h->chunk_alloc));
     TRY(dalloc(h, &h->blk32[0], (size_t)(npw * h->nb_max)));
     TRY(dalloc(h, &h->blk32[1], (size_t)(npw * h->nb_max)));
   }
@@ -1027,6 +1071,135 @@ pw_status pw_upper_bound(pw_ham* h, double* b_host) {
 }
 
 // ---------------------------------------------------------------------------
+// autotuning of the H*psi launch shapes
+// ---------------------------------------------------------------------------
+pw_status pw_ham_get_tuning(const pw_ham* h, pw_tuning* t) {
+  if (!h || !t) return fail(nullptr, PW_ERR_INVALID_ARG, "ham or tuning is NULL");
+  t->reg_col = h->cfg.reg_col ? 1 : 0;
+  t->reg_plane = h->cfg.reg_plane ? 1 : 0;
+  t->plane_variant = h->cfg.plane_variant;
+  t->chunk = (int32_t)h->chunk;
+  t->gemm_blocks = h->gemm_target;
+  t->ms = 0.0;
+  return PW_OK;
+}
+
+pw_status pw_ham_set_tuning(pw_ham* h, const pw_tuning* t) {
+  if (!h || !t) return fail(nullptr, PW_ERR_INVALID_ARG, "ham or tuning is NULL");
+  if ((t->reg_col != 0 && t->reg_col != 1) || (t->reg_plane != 0 && t->reg_plane != 1) ||
+      (t->plane_variant != 0 && t->plane_variant != 1))
+    return fail(h->ctx, PW_ERR_INVALID_ARG, "reg_col, reg_plane and plane_variant are 0 or 1");
+  if (t->reg_col && !h->reg_col_ok)
+    return fail(h->ctx, PW_ERR_UNSUPPORTED, "no register column kernel for this N3");
+  if (t->reg_plane && !h->reg_plane_ok)
+    return fail(h->ctx, PW_ERR_UNSUPPORTED, "no register plane kernel for this (N1, N2)");
+  if (t->plane_variant == 1 && (!t->reg_plane || !h->narrow_ok))
+    return fail(h->ctx, PW_ERR_UNSUPPORTED, "no 8-lane plane variant for this (N1, N2)");
+  if (t->chunk < 1 || t->chunk > h->chunk_alloc)
+    return fail(h->ctx, PW_ERR_INVALID_ARG,
+                "chunk outside [1, " + std::to_string(h->chunk_alloc) + "]");
+  if (t->gemm_blocks < 1 || t->gemm_blocks > 2048)
+    return fail(h->ctx, PW_ERR_INVALID_ARG, "gemm_blocks outside [1, 2048]");
+  h->cfg.reg_col = t->reg_col != 0;
+  h->cfg.reg_plane = t->reg_plane != 0;
+  h->cfg.plane_variant = t->plane_variant;
+  h->chunk = t->chunk;
+  h->gemm_target = t->gemm_blocks;
+  return PW_OK;
+}
+
+
+pw_status pw_ham_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, pw_tuning* best,
+                          pw_tuning* initial) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  if (!best) return fail(h->ctx, PW_ERR_INVALID_ARG, "best is NULL");
+  pw_status st;
+  if ((st = check_hot(h, prec, nb)) != PW_OK) return st;
+  if (reps < 1 || reps > 100) return fail(h->ctx, PW_ERR_INVALID_ARG, "reps outside [1, 100]");
+  pw_ctx* c = h->ctx;
+  HIPCHK(c, hipSetDevice(c->device));
+  const bool timing = c->timing;
+  c->timing = false;
+  struct Restore {
+    pw_ctx* c;
+    bool t;
+    ~Restore() { c->timing = t; }
+  } restore{c, timing};
+  // operands: zero input, scratch output
+  pw_ham scratch;
+  scratch.ctx = c;
+  void* in = nullptr;
+  void* out = nullptr;
+  const size_t elem = prec == PW_FP64 ? sizeof(cplx) : sizeof(float2);
+  if (prec == PW_FP64) {
+    in = h->blk;
+    cplx* o = nullptr;
+    if ((st = dalloc(&scratch, &o, (size_t)(h->npw * nb))) != PW_OK) return st;
+    out = o;
+  } else {
+    in = h->blk32[0];
+    out = h->blk32[1];
+  }
+  struct FreeScratch {
+    pw_ham* s;
+    ~FreeScratch() { free_ham(s); }
+  } free_scratch{&scratch};
+  HIPCHK(c, hipMemsetAsync(in, 0, (size_t)(h->npw * nb) * elem, c->stream));
+
+  pw_tuning cur;
+  pw_ham_get_tuning(h, &cur);
+  double cur_ms = 0.0;
+  if ((st = time_apply(h, prec, nb, in, out, reps, &cur_ms)) != PW_OK) return st;
+  if (initial) {
+    *initial = cur;
+    initial->ms = cur_ms;
+  }
+  auto try_one = [&](pw_tuning t) -> pw_status {
+    pw_status s2 = pw_ham_set_tuning(h, &t);
+    if (s2 != PW_OK) return s2;
+    double ms = 0.0;
+    if ((s2 = time_apply(h, prec, nb, in, out, reps, &ms)) != PW_OK) return s2;
+    if (ms < cur_ms) {
+      cur = t;
+      cur_ms = ms;
+    }
+    return pw_ham_set_tuning(h, &cur);
+  };
+  // 1) FFT kernel families
+  for (int rc = 0; rc <= (h->reg_col_ok ? 1 : 0); ++rc)
+    for (int rp = 0; rp <= (h->reg_plane_ok ? 1 : 0); ++rp)
+      for (int pv = 0; pv <= ((rp && h->narrow_ok) ? 1 : 0); ++pv) {
+        pw_tuning t = cur;
+        t.reg_col = rc;
+        t.reg_plane = rp;
+        t.plane_variant = pv;
+        if (t.reg_col == cur.reg_col && t.reg_plane == cur.reg_plane &&
+            t.plane_variant == cur.plane_variant)
+          continue;
+        if ((st = try_one(t)) != PW_OK) return st;
+      }
+  // 2) bands per FFT launch
+  const int64_t cmax = std::min<int64_t>(h->chunk_alloc, nb);
+  for (int64_t ch = cmax; ch >= 1 && ch >= cmax / 8; ch /= 2) {
+    if (ch == cur.chunk) continue;
+    pw_tuning t = cur;
+    t.chunk = (int32_t)ch;
+    if ((st = try_one(t)) != PW_OK) return st;
+  }
+  // 3) split-K parallelism of the projector product
+  if (h->nproj > 0)
+    for (int g : {2048, 1024, 512, 256}) {
+      if (g == cur.gemm_blocks) continue;
+      pw_tuning t = cur;
+      t.gemm_blocks = g;
+      if ((st = try_one(t)) != PW_OK) return st;
+    }
+  *best = cur;
+  best->ms = cur_ms;
+  return PW_OK;
+}
+
+// ---------------------------------------------------------------------------
 // batched subspace iteration
 // ---------------------------------------------------------------------------
 pw_status pw_batch_destroy(pw_batch* b) {
@@ -1164,7 +1337,7 @@ pw_status pw_batch_start(pw_batch* b) {
   if (!b) return fail(nullptr, PW_ERR_INVALID_ARG, "batch is NULL");
   pw_status st;
   if ((st = batch_enter(b)) != PW_OK) return st;
-  if ((st = batch_issue(b, false)) != PW_OK) return st;
+  if ((st = batch_issue(b, false, false)) != PW_OK) return st;
   return batch_leave(b);
 }
 
@@ -1176,7 +1349,7 @@ pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
   if ((st = batch_enter(b)) != PW_OK) return st;
   if (use_graph && !b->exec) {
     HIPCHK(c, hipStreamBeginCapture(b->s0, hipStreamCaptureModeThreadLocal));
-    st = batch_issue(b, true);
+    st = batch_issue(b, true, true);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->s0, &g);
     if (st != PW_OK) {
@@ -1192,7 +1365,7 @@ pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
   }
   for (int32_t t = 0; t < iters; ++t) {
     if (use_graph) HIPCHK(c, hipGraphLaunch(b->exec, b->s0));
-    else if ((st = batch_issue(b, true)) != PW_OK) return st;
+    else if ((st = batch_issue(b, true, false)) != PW_OK) return st;
   }
   return batch_leave(b);
 }

@@ -122,7 +122,7 @@ size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k);
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
                           cplx* work, hipStream_t s, double beta = 0.0,
-                          const double* alpha_dev = nullptr);
+                          const double* alpha_dev = nullptr, int target_blocks = 2048);
 hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
                           hipStream_t s);
@@ -133,7 +133,7 @@ size_t gemm_cn32_work_elems(int64_t m, int64_t n, int64_t k, int bf16);
 hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
                             const double* rowscale, float2* work, hipStream_t s,
-                            const double* alpha_dev = nullptr);
+                            const double* alpha_dev = nullptr, int target_blocks = 2048);
 hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
                             int64_t ldc, hipStream_t s);

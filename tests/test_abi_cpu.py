@@ -62,22 +62,35 @@ def test_invalid_arguments_without_device(lib):
     assert b"NULL" in lib.pw_last_error(None)
 
 
-def test_desc_layout_matches_header(tmp_path):
-    """The ctypes mirror of pw_ham_desc has the C compiler's offsets (checked with gcc)."""
+def _c_layout(tmp_path, ctype, struct):
+    """Offsets and size of a C struct of pw.h as gcc lays it out."""
     import shutil
     import subprocess
-    from paper_2507_08578_amd._lib import PwHamDesc
     gcc = shutil.which("gcc")
     if gcc is None:
         pytest.skip("gcc not available")
-    fields = [f[0] for f in PwHamDesc._fields_]
-    src = tmp_path / "off.c"
+    fields = [f[0] for f in struct._fields_]
+    src = tmp_path / f"off_{ctype}.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "pw.h"\nint main(void){\n' +
-                   "".join(f'printf("%zu\\n", offsetof(pw_ham_desc, {f}));\n' for f in fields) +
-                   'printf("%zu\\n", sizeof(pw_ham_desc));\nreturn 0;}\n')
-    exe = tmp_path / "off"
+                   "".join(f'printf("%zu\\n", offsetof({ctype}, {f}));\n' for f in fields) +
+                   f'printf("%zu\\n", sizeof({ctype}));\nreturn 0;}}\n')
+    exe = tmp_path / f"off_{ctype}"
     subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
+    return fields, out
+
+
+def test_desc_layout_matches_header(tmp_path):
+    """The ctypes mirror of pw_ham_desc has the C compiler's offsets (checked with gcc)."""
+    from paper_2507_08578_amd._lib import PwHamDesc
+    fields, out = _c_layout(tmp_path, "pw_ham_desc", PwHamDesc)
     assert out[:-1] == [getattr(PwHamDesc, f).offset for f in fields]
     assert out[-1] == ctypes.sizeof(PwHamDesc)
+
+
+def test_tuning_layout_matches_header(tmp_path):
+    from paper_2507_08578_amd._lib import PwTuning
+    fields, out = _c_layout(tmp_path, "pw_tuning", PwTuning)
+    assert out[:-1] == [getattr(PwTuning, f).offset for f in fields]
+    assert out[-1] == ctypes.sizeof(PwTuning)
