@@ -65,24 +65,57 @@ def make_workload(name):
 BATCHED = ("C2", "C4")
 
 
+COUNTER_FILES = {   # (config, precision, stage) -> committed rocprofv3 counter summary
+    ("C5", "fp32", "fft_plane"): "profiles/c5_plane_fp32_counters.md",
+}
+KERNEL_SOURCES = ("paper_2507_08578_amd/csrc/fft_reg.hip", "paper_2507_08578_amd/csrc/fft_common.h")
+
+
+def measured_traffic(config, prec, stage, bands_per_launch):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary,
+    or None when there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    rel = COUNTER_FILES.get((config, prec, stage))
+    if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    vals = {}
+    for line in open(os.path.join(ROOT, rel)):
+        if ":" in line and not line.startswith(("#", "|", "`")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if vals.get("kernel_source_sha1") != h.hexdigest() or "traffic_bytes_per_band" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_band"]) * bands_per_launch
+
+
 def fft_flops(n):
     import math
     return 5.0 * n * math.log2(n)
 
 
-def roofline(stages, steps, applies, w, ham, nb, prec):
+def roofline(stages, steps, w, ham, nb, prec, config=None):
     """Dominant single-kernel stage of the filter path against its bound.
 
-    nonlocal (k_gemm_nn: H psi += P C): MFMA, 8 npw nproj nb flop per launch.
+    The stages of the precision being reported are used (the low-precision
+    path times its FP32 / BF16 kernels under their own stage ids; its
+    Rayleigh-Ritz product stays FP64 and is not counted here).
+    nonlocal (H psi += P C): MFMA, 8 npw nproj nb flop per launch.
     fft_plane: vector ALU, per band and z-plane 2 (xr 5 N2 log2 N2 + N2 5 N1 log2 N1)
                + 2 N1 N2 flop (the V product), per launch x bands in the launch.
     fft_col_inv / fft_col_fwd: HBM, (npw + ncols N3) / (ncols N3 + 2 npw) elements per band.
     """
     N1, N2, N3 = w.box
     ncols, xr = ham.ncolumns, ham.extent1
+    lp = prec != "fp64"
+    sfx = "_lp" if lp else ""
+    applies = w.degree - 1 if lp else w.degree     # H*psi products of this precision per step
     elem = 16 if prec == "fp64" else 8
-    cand = {k: v for k, v in stages.items()
-            if k in ("nonlocal", "fft_plane", "fft_col_inv", "fft_col_fwd") and v[1] > 0}
+    cand = {k[:len(k) - len(sfx)] if sfx else k: v for k, v in stages.items()
+            if k in (f"nonlocal{sfx}", f"fft_plane{sfx}", f"fft_col_inv{sfx}", f"fft_col_fwd{sfx}")
+            and v[1] > 0}
     dom = max(cand, key=lambda k: cand[k][0])
     total_ms, launches = cand[dom]
     avg_ms = total_ms / launches
@@ -93,7 +126,7 @@ def roofline(stages, steps, applies, w, ham, nb, prec):
         peak = PEAK["fp64_mfma" if prec == "fp64" else ("bf16_mfma" if prec == "bf16" else "fp32_mfma")]
         ach = fl / (avg_ms * 1e-3) / 1e12
         return {"kernel": "k_gemm_nn (H psi += P C)", "bound": "mfma", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "avg_launch_ms": avg_ms,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "avg_launch_ms": avg_ms,
                 "per_launch": f"8*npw*nproj*nb = {fl:.4g} flop"}
     if dom == "fft_plane":
         per_band = N3 * (2 * (xr * fft_flops(N2) + N2 * fft_flops(N1)) + 2.0 * N1 * N2)
@@ -102,6 +135,7 @@ def roofline(stages, steps, applies, w, ham, nb, prec):
         ach = fl / (avg_ms * 1e-3) / 1e12
         return {"kernel": "k_plane_reg (N2/N1 transforms x V per z-plane)", "bound": "alu",
                 "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": measured_traffic(config, prec, dom, bands_per_launch),
                 "avg_launch_ms": avg_ms,
                 "per_launch": f"{per_band:.4g} flop/band (5 N log2 N per transform) x "
                               f"{bands_per_launch:.0f} bands",
@@ -110,7 +144,7 @@ def roofline(stages, steps, applies, w, ham, nb, prec):
     per_band = elem * ((w.npw + ncols * N3) if dom == "fft_col_inv" else (ncols * N3 + 2 * w.npw))
     ach = per_band * bands_per_launch / (avg_ms * 1e-3) / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-            "frac": ach / PEAK["hbm_gbs"], "avg_launch_ms": avg_ms,
+            "frac": ach / PEAK["hbm_gbs"], "traffic": None, "avg_launch_ms": avg_ms,
             "per_launch": f"{per_band:.4g} B/band x {bands_per_launch:.0f} bands"}
 
 
@@ -180,16 +214,20 @@ def batch_roofline(stages, items, prec, degree):
     """Dominant kernel of a directly issued batch iteration (per-branch HIP
     events; concurrent branches overlap, so durations include sharing)."""
     elem = 16 if prec == "fp64" else 8
-    cand = {k: v for k, v in stages.items()
-            if k in ("nonlocal", "proj", "fft_plane", "fft_col_inv", "fft_col_fwd") and v[1] > 0}
+    sfx = "_lp" if prec != "fp64" else ""
+    cand = {k[:len(k) - len(sfx)] if sfx else k: v for k, v in stages.items()
+            if k in tuple(n + sfx for n in ("nonlocal", "proj", "fft_plane", "fft_col_inv",
+                                            "fft_col_fwd")) and v[1] > 0}
     dom = max(cand, key=lambda k: cand[k][0])
     total_ms, launches = cand[dom]
-    # one iteration: degree-1 filter products (prec) + 1 Rayleigh-Ritz product (fp64)
+    # one iteration: degree-1 filter products in the filter precision (the
+    # Rayleigh-Ritz product of the mixed path is FP64 and timed elsewhere)
     units = []
     for w, ham in items:
         N1, N2, N3 = w.box
         nc, xr = ham.ncolumns, ham.extent1
-        for e, napp in ((elem, degree - 1), (16, 1)):
+        pairs = ((elem, degree - 1),) if sfx else ((elem, degree),)
+        for e, napp in pairs:
             if dom == "fft_col_inv":
                 units.append(e * (w.npw + nc * N3) * w.nb * napp)
             elif dom == "fft_col_fwd":
@@ -201,7 +239,7 @@ def batch_roofline(stages, items, prec, degree):
     total_bytes = sum(units)
     ach = total_bytes / (total_ms * 1e-3) / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-            "frac": ach / PEAK["hbm_gbs"], "avg_launch_ms": total_ms / launches,
+            "frac": ach / PEAK["hbm_gbs"], "traffic": None, "avg_launch_ms": total_ms / launches,
             "per_launch": f"algorithmic bytes of all {len(items)} items over one iteration "
                           f"({total_bytes:.4g} B) / summed kernel time",
             "note": "latency-bound configuration: kernels of concurrent branches overlap"}
@@ -231,7 +269,8 @@ def run_batch(args):
                   "apply_ms_default_sum": sum(r["default_ms"] for r in res),
                   "apply_ms_tuned_sum": sum(r["ms"] for r in res),
                   "choices": sorted({json.dumps({k: r[k] for k in ("reg_col", "reg_plane",
-                                                                   "plane_variant", "chunk",
+                                                                   "plane_variant",
+                                                                   "plane_variant32", "chunk",
                                                                    "gemm_blocks")})
                                      for r in res}),
                   "tuning_s": time.perf_counter() - t0}
@@ -316,12 +355,13 @@ def run_batch(args):
                                      "speedup_batch_over_per_item": dt64 / dt}
         out["eig_diff_vs_fp64_Ha"] = d
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_items(ws, args.cpu_bands or 16)
+        out["cpu_baseline"] = cpu_baseline_items(ws, args.cpu_bands or 32)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_items(ws, nb_each):
-    """Oracle H*psi on nb_each bands of every item, timed on the host."""
+def cpu_baseline_items(ws, nb_each, min_s=10.0, max_reps=10000):
+    """Oracle H*psi on nb_each bands of every item, timed on the host; the
+    pass over all items is repeated until at least min_s seconds have run."""
     import oracle
     import synth
     try:
@@ -334,14 +374,31 @@ def cpu_baseline_items(ws, nb_each):
     Xs = [synth.start_block(w.npw, min(nb_each, w.nb), 7).T for w in ws]
     oracle.apply_h(hs[0], Xs[0][:, :1])
     t0 = time.perf_counter()
-    n = 0
-    for h, X in zip(hs, Xs):
-        oracle.apply_h(h, X)
-        n += X.shape[1]
-    dt = time.perf_counter() - t0
+    n = reps = 0
+    while True:
+        for h, X in zip(hs, Xs):
+            oracle.apply_h(h, X)
+            n += X.shape[1]
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s or reps >= max_reps:
+            break
     return {"value": n / dt, "unit": UNIT, "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} bands ({min(nb_each, max(w.nb for w in ws))} per item) of one FP64 "
-                      f"oracle H*psi over all {len(ws)} items, {dt:.2f} s"}
+            "sample": f"{reps} passes of one FP64 oracle H*psi on {min(nb_each, max(w.nb for w in ws))}"
+                      f" bands of each of the {len(ws)} items ({n} band applies), {dt:.1f} s"}
+
+
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """A plain device-to-device copy of known size: the reference that scales
+    the HBM byte counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": reps}),
+          flush=True)
 
 
 def main():
@@ -358,10 +415,14 @@ def main():
     ap.add_argument("--streams", type=int, default=8, help="batch branches (C2, C4)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing alternatives")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.calibrate_copy:
+        return calibrate_copy()
     if args.config in BATCHED:
         return run_batch(args)
 
@@ -396,7 +457,7 @@ def main():
     if mixed and not args.no_compare:
         tune("fp64")
         ref = run_path(pw, ctx, ham, w, X0, b, "fp64", args.steps, args.warmup)
-    roof = roofline(res["stages"], args.steps, res["applies"], w, ham, nb, args.precision)
+    roof = roofline(res["stages"], args.steps, w, ham, nb, args.precision, args.config)
     dtype = "f64" if not mixed else ("f32+f64" if args.precision == "fp32" else "bf16/f32+f64")
     out = {
         "metric": METRIC, "value": res["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,

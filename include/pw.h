@@ -198,7 +198,9 @@ pw_status pw_upper_bound(pw_ham* ham, double* b_host);
 typedef struct {
   int32_t reg_col;        /* 1: register-resident column kernels (N3 in the fast set)       */
   int32_t reg_plane;      /* 1: register-resident plane kernel (N1 = N2 in the fast set)     */
-  int32_t plane_variant;  /* 0: lane groups of up to 16 lanes; 1: up to 8 (N1 = 48, 64, 96)  */
+  int32_t plane_variant;  /* FP64 plane kernel: 0 lane groups of up to 16 lanes; 1 up to 8
+                             (N1 = N2 = 48, 64, 96)                                        */
+  int32_t plane_variant32;/* FP32 plane kernel, the same choice (1 also for 120, 128, 144, 160) */
   int32_t chunk;          /* bands per FFT launch, [1, the handle's buffer]                  */
   int32_t gemm_blocks;    /* split-K target block count of P^H psi, [1, 2048]                */
   double ms;              /* pw_ham_autotune: median time of one H*psi of nb bands           */
@@ -314,7 +316,13 @@ typedef enum {
   PW_STAGE_ROTATE = 7,       /* Y U^{-1}, Y Q, W Q                                         */
   PW_STAGE_EIGH = 8,         /* dense Hermitian eigensolver                                */
   PW_STAGE_MISC = 9,         /* residuals, copies, reductions                              */
-  PW_STAGE_COUNT = 10
+  /* the same H*psi stages run in FP32 / BF16 (low-precision filter path) */
+  PW_STAGE_FFT_COL_INV_LP = 10,
+  PW_STAGE_FFT_PLANE_LP = 11,
+  PW_STAGE_FFT_COL_FWD_LP = 12,
+  PW_STAGE_PROJ_LP = 13,
+  PW_STAGE_NONLOCAL_LP = 14,
+  PW_STAGE_COUNT = 15
 } pw_stage;
 
 pw_status pw_ctx_set_timing(pw_ctx* ctx, int enable);

@@ -280,7 +280,8 @@ class Hamiltonian:
         return b.value
 
     # --- launch-shape tuning ---
-    _TUNING_KEYS = ("reg_col", "reg_plane", "plane_variant", "chunk", "gemm_blocks")
+    _TUNING_KEYS = ("reg_col", "reg_plane", "plane_variant", "plane_variant32", "chunk",
+                    "gemm_blocks")
 
     def get_tuning(self) -> dict:
         t = _lib.PwTuning()

@@ -21,7 +21,8 @@ c_int = ctypes.c_int
 PW_OK = 0
 PW_FP64, PW_FP32, PW_BF16 = 0, 1, 2
 STAGES = ["fft_col_inv", "fft_plane", "fft_col_fwd", "proj", "nonlocal", "gram", "chol",
-          "rotate", "eigh", "misc"]
+          "rotate", "eigh", "misc", "fft_col_inv_lp", "fft_plane_lp", "fft_col_fwd_lp", "proj_lp",
+          "nonlocal_lp"]
 
 
 class PwHamDesc(ctypes.Structure):
@@ -44,7 +45,7 @@ class PwHamDesc(ctypes.Structure):
 class PwTuning(ctypes.Structure):
     """pw_tuning (include/pw.h)."""
     _fields_ = [("reg_col", c_int32), ("reg_plane", c_int32), ("plane_variant", c_int32),
-                ("chunk", c_int32), ("gemm_blocks", c_int32), ("ms", c_double)]
+                ("plane_variant32", c_int32), ("chunk", c_int32), ("gemm_blocks", c_int32), ("ms", c_double)]
 
 
 SIGNATURES = {

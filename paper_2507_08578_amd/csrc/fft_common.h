@@ -276,18 +276,20 @@ __device__ __forceinline__ void dft_reg(C* v) {
 //   M = 1, 2 : quad_perm [1,0,3,2] / [2,3,0,1]
 //   M = 4    : row_half_mirror (i -> 7-i) then quad_perm [3,2,1,0]  (7 - (i^3) = i^4)
 //   M = 8    : row_ror:8
+// Every lane's source lies inside its own row for these patterns, so the
+// "old" operand is never used (bound_ctrl set: no initialising move).
 // Larger masks fall back to ds_bpermute.
 template <int M>
 __device__ __forceinline__ int xor_lane_i32(int v) {
   if constexpr (M == 1) {
-    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
   } else if constexpr (M == 2) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
   } else if constexpr (M == 4) {
-    const int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
-    return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, false);
+    const int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);
+    return __builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, true);
   } else if constexpr (M == 8) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);
   } else {
     return __shfl_xor(v, M);
   }
@@ -328,12 +330,16 @@ __device__ __forceinline__ int brev(int b) {
 // Per-lane twiddles of a length-N = G R transform for lane b of its group,
 // loaded once and shared by both directions (all exp(-2 pi i t/N) values):
 //   k[q-1] = exp(-2 pi i b q / N), q = 1..R-1      (between registers and lanes)
-//   st[s]  = exp(-2 pi i (b mod h) / (2h)), h = 2^s (cross-lane stage of span h)
+//   w[s]   = exp(-2 pi i (b mod h) / (2h)) on the upper lane of a stage-s pair
+//            (b & h set, h = 2^s) and exactly 1 on the lower lane
+//   sg[s]  = -1 on the upper lane, +1 on the lower lane
+// so that both lanes of a pair run the same instructions (no divergence).
 template <int R, int G, class C>
 struct LaneTw {
   static constexpr int kStages = (G > 1) ? __builtin_ctz(G) : 1;
   C k[R > 1 ? R - 1 : 1];
-  C st[kStages];
+  C w[kStages];
+  real_t<C> sg[kStages];
   __device__ __forceinline__ void load(int b, const C* __restrict__ tw) {
     constexpr int N = R * G;
     if constexpr (G > 1) {
@@ -342,7 +348,9 @@ struct LaneTw {
 #pragma unroll
       for (int s = 0; s < kStages; ++s) {
         const int h = 1 << s;
-        st[s] = tw[(b & (h - 1)) * (N / (2 * h))];
+        const bool up = (b & h) != 0;
+        w[s] = up ? tw[(b & (h - 1)) * (N / (2 * h))] : mkc<C>(1.0, 0.0);
+        sg[s] = up ? (real_t<C>)-1 : (real_t<C>)1;
       }
     }
   }
@@ -356,29 +364,43 @@ struct LaneTw {
 // forward  (-):  in : v[k1] = Z[k1 + R brev(b)]    (the backward's layout)
 //                out: v[a]  = X'[G a + b]
 // The forward is the exact adjoint of the backward, stage by stage.
+//
+// Decimation-in-frequency stage of span h (backward), pair (lo, up):
+//   lo <- lo + up,   up <- (lo - up) conj(w)
+// each lane forms p + sg v from its own value v and its partner's p, then
+// multiplies by conj(w) (exactly 1 on the lower lane).
 template <int R, int G, int SI, class C>
 __device__ __forceinline__ void dif_stages(C* v, int b, const LaneTw<R, G, C>& t) {
   if constexpr (SI >= 0) {
     constexpr int h = 1 << SI;
-    const bool up = (b & h) != 0;
+    const real_t<C> sg = t.sg[SI];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const C p = xor_lane<h>(v[r]);
-      v[r] = up ? conj_mul(csub(p, v[r]), t.st[SI]) : cadd(v[r], p);
+      C u;
+      u.x = p.x + sg * v[r].x;
+      u.y = p.y + sg * v[r].y;
+      v[r] = conj_mul(u, t.w[SI]);
     }
     dif_stages<R, G, SI - 1>(v, b, t);
   }
 }
 
+// Decimation-in-time stage of span h (forward), pair (lo, up):
+//   lo <- lo + w up,   up <- lo - w up
+// each lane scales its own value by w (1 on the lower lane), exchanges, and
+// forms p + sg x.
 template <int R, int G, int SI, class C>
 __device__ __forceinline__ void dit_stages(C* v, int b, const LaneTw<R, G, C>& t) {
   if constexpr (SI < LaneTw<R, G, C>::kStages) {
     constexpr int h = 1 << SI;
-    const bool up = (b & h) != 0;
+    const real_t<C> sg = t.sg[SI];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const C p = xor_lane<h>(v[r]);
-      v[r] = up ? csub(p, cmul(t.st[SI], v[r])) : cadd(v[r], cmul(t.st[SI], p));
+      const C x = cmul(t.w[SI], v[r]);
+      const C p = xor_lane<h>(x);
+      v[r].x = p.x + sg * x.x;
+      v[r].y = p.y + sg * x.y;
     }
     dit_stages<R, G, SI + 1>(v, b, t);
   }

@@ -323,6 +323,7 @@ bool fft_choose_config(const BoxPlan& p, size_t lds_limit, FftLaunchCfg* cfg) {
   cfg->reg_col = fft_reg_col_supported(p.n3);
   cfg->reg_plane = fft_reg_plane_supported(p, lds_limit);
   cfg->plane_variant = 0;
+  cfg->plane_variant32 = 0;
   return true;
 }
 
@@ -377,7 +378,7 @@ hipError_t launch_fft_plane(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, c
 }
 hipError_t launch_fft_plane32(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const float* vscaled,
                               float2* T, hipStream_t s) {
-  if (cfg.reg_plane) return launch_fft_plane_reg32(p, cfg.plane_variant, nb, vscaled, T, s);
+  if (cfg.reg_plane) return launch_fft_plane_reg32(p, cfg.plane_variant32, nb, vscaled, T, s);
   return plane_generic<float2>(p, cfg, nb, vscaled, T, s);
 }
 

@@ -211,8 +211,10 @@ int plane_reg_threads(const BoxPlan& p, int gmax) {
 }
 
 #define PW_FAST_SIZES(X) X(24) X(32) X(36) X(48) X(64) X(72) X(96) X(120) X(128) X(144) X(160)
-// sizes whose 8-lane variant differs from the 16-lane one and fits the registers
-#define PW_NARROW_SIZES(X) X(48) X(64) X(96)
+// sizes whose 8-lane variant differs from the 16-lane one and fits the
+// registers: FP64, and FP32 (half the registers per value)
+#define PW_NARROW_SIZES64(X) X(48) X(64) X(96)
+#define PW_NARROW_SIZES32(X) X(48) X(64) X(96) X(120) X(128) X(144) X(160)
 
 }  // namespace
 
@@ -223,9 +225,13 @@ bool fft_reg_col_supported(int n3) {
   return false;
 }
 
-bool fft_reg_plane_narrow(const BoxPlan& p) {
+bool fft_reg_plane_narrow(const BoxPlan& p, bool fp32) {
 #define CASE(N) if (p.n1 == N && p.n2 == N) return true;
-  PW_NARROW_SIZES(CASE)
+  if (fp32) {
+    PW_NARROW_SIZES32(CASE)
+  } else {
+    PW_NARROW_SIZES64(CASE)
+  }
 #undef CASE
   return false;
 }
@@ -298,7 +304,11 @@ hipError_t plane_reg(const BoxPlan& p, int variant, int nb, const real_t<C>* vsc
                          tw1, tw2, vscaled, T);                                                \
       return hipGetLastError();                                                                \
     }
-    PW_NARROW_SIZES(CASE)
+    if constexpr (sizeof(C) == sizeof(double2)) {
+      PW_NARROW_SIZES64(CASE)
+    } else {
+      PW_NARROW_SIZES32(CASE)
+    }
 #undef CASE
     return hipErrorInvalidValue;
   }
@@ -329,7 +339,11 @@ hipError_t set_plane_lds(size_t bytes) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
     if (e != hipSuccess) return e;                                                           \
   }
-  PW_NARROW_SIZES(CASE)
+  if constexpr (sizeof(C) == sizeof(double2)) {
+    PW_NARROW_SIZES64(CASE)
+  } else {
+    PW_NARROW_SIZES32(CASE)
+  }
 #undef CASE
   return hipSuccess;
 }

@@ -57,7 +57,7 @@ struct pw_ham {
   int64_t chunk = 0;         // bands per FFT launch (tunable, <= chunk_alloc)
   int64_t chunk_alloc = 0;   // bands the FFT work buffer holds
   int gemm_target = 2048;    // split-K target block count of the projector product (tunable)
-  bool reg_col_ok = false, reg_plane_ok = false, narrow_ok = false;
+  bool reg_col_ok = false, reg_plane_ok = false, narrow_ok = false, narrow32_ok = false;
   std::vector<void*> allocs;
   double* kin = nullptr;
   double* vscaled = nullptr;
@@ -259,7 +259,7 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
   if (h->nproj > 0) {
-    StageScope sc(c, PW_STAGE_PROJ);
+    StageScope sc(c, PW_STAGE_PROJ_LP);
     HIPCHK(c, launch_gemm_cn32(bf16, h->nproj, nb, h->npw, alpha, h->proj32, h->npw, in, ldin,
                                h->cprj32, h->nproj, h->ekb_dev, h->work32, s, coef,
                                h->gemm_target));
@@ -268,22 +268,22 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
   for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
     const int nc = (int)std::min<int64_t>(h->chunk, nb - c0);
     {
-      StageScope sc(c, PW_STAGE_FFT_COL_INV);
+      StageScope sc(c, PW_STAGE_FFT_COL_INV_LP);
       HIPCHK(c, launch_fft_col_inv32(h->plan, h->cfg, nc, in + c0 * ldin, ldin, h->T32, s));
     }
     {
-      StageScope sc(c, PW_STAGE_FFT_PLANE);
+      StageScope sc(c, PW_STAGE_FFT_PLANE_LP);
       HIPCHK(c, launch_fft_plane32(h->plan, h->cfg, nc, h->vs32, h->T32, s));
     }
     {
-      StageScope sc(c, PW_STAGE_FFT_COL_FWD);
+      StageScope sc(c, PW_STAGE_FFT_COL_FWD_LP);
       HIPCHK(c, launch_fft_col_fwd32(h->plan, h->cfg, nc, h->T32, h->kin32, in + c0 * ldin, ldin,
                                      prev ? prev + c0 * ldprev : nullptr, ldprev, out + c0 * ldout,
                                      ldout, ep, s));
     }
   }
   if (h->nproj > 0) {
-    StageScope sc(c, PW_STAGE_NONLOCAL);
+    StageScope sc(c, PW_STAGE_NONLOCAL_LP);
     HIPCHK(c, launch_gemm_nn32(bf16, h->npw, nb, h->nproj, 1.0, h->proj32, h->npw, h->cprj32,
                                h->nproj, 1.0, out, ldout, s));
   }
@@ -782,7 +782,8 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   h->chunk_alloc = h->chunk;
   h->reg_col_ok = h->cfg.reg_col;
   h->reg_plane_ok = h->cfg.reg_plane;
-  h->narrow_ok = h->cfg.reg_plane && fft_reg_plane_narrow(P);
+  h->narrow_ok = h->cfg.reg_plane && fft_reg_plane_narrow(P, false);
+  h->narrow32_ok = h->cfg.reg_plane && fft_reg_plane_narrow(P, true);
   TRY(dalloc(h, &h->T, per_band * h->chunk));
   if (h->nproj > 0) TRY(dalloc(h, &h->cprj, (size_t)(h->nproj * h->nb_max)));
   size_t wmax = 0;
@@ -1078,6 +1079,7 @@ pw_status pw_ham_get_tuning(const pw_ham* h, pw_tuning* t) {
   t->reg_col = h->cfg.reg_col ? 1 : 0;
   t->reg_plane = h->cfg.reg_plane ? 1 : 0;
   t->plane_variant = h->cfg.plane_variant;
+  t->plane_variant32 = h->cfg.plane_variant32;
   t->chunk = (int32_t)h->chunk;
   t->gemm_blocks = h->gemm_target;
   t->ms = 0.0;
@@ -1087,14 +1089,18 @@ pw_status pw_ham_get_tuning(const pw_ham* h, pw_tuning* t) {
 pw_status pw_ham_set_tuning(pw_ham* h, const pw_tuning* t) {
   if (!h || !t) return fail(nullptr, PW_ERR_INVALID_ARG, "ham or tuning is NULL");
   if ((t->reg_col != 0 && t->reg_col != 1) || (t->reg_plane != 0 && t->reg_plane != 1) ||
-      (t->plane_variant != 0 && t->plane_variant != 1))
-    return fail(h->ctx, PW_ERR_INVALID_ARG, "reg_col, reg_plane and plane_variant are 0 or 1");
+      (t->plane_variant != 0 && t->plane_variant != 1) ||
+      (t->plane_variant32 != 0 && t->plane_variant32 != 1))
+    return fail(h->ctx, PW_ERR_INVALID_ARG,
+                "reg_col, reg_plane, plane_variant and plane_variant32 are 0 or 1");
   if (t->reg_col && !h->reg_col_ok)
     return fail(h->ctx, PW_ERR_UNSUPPORTED, "no register column kernel for this N3");
   if (t->reg_plane && !h->reg_plane_ok)
     return fail(h->ctx, PW_ERR_UNSUPPORTED, "no register plane kernel for this (N1, N2)");
   if (t->plane_variant == 1 && (!t->reg_plane || !h->narrow_ok))
-    return fail(h->ctx, PW_ERR_UNSUPPORTED, "no 8-lane plane variant for this (N1, N2)");
+    return fail(h->ctx, PW_ERR_UNSUPPORTED, "no 8-lane FP64 plane variant for this (N1, N2)");
+  if (t->plane_variant32 == 1 && (!t->reg_plane || !h->narrow32_ok))
+    return fail(h->ctx, PW_ERR_UNSUPPORTED, "no 8-lane FP32 plane variant for this (N1, N2)");
   if (t->chunk < 1 || t->chunk > h->chunk_alloc)
     return fail(h->ctx, PW_ERR_INVALID_ARG,
                 "chunk outside [1, " + std::to_string(h->chunk_alloc) + "]");
@@ -1103,6 +1109,7 @@ pw_status pw_ham_set_tuning(pw_ham* h, const pw_tuning* t) {
   h->cfg.reg_col = t->reg_col != 0;
   h->cfg.reg_plane = t->reg_plane != 0;
   h->cfg.plane_variant = t->plane_variant;
+  h->cfg.plane_variant32 = t->plane_variant32;
   h->chunk = t->chunk;
   h->gemm_target = t->gemm_blocks;
   return PW_OK;
@@ -1165,16 +1172,20 @@ pw_status pw_ham_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, pw_
     }
     return pw_ham_set_tuning(h, &cur);
   };
-  // 1) FFT kernel families
+  // 1) FFT kernel families (the plane variant of the precision being tuned)
+  const bool lp = prec != PW_FP64;
+  const bool nok = lp ? h->narrow32_ok : h->narrow_ok;
   for (int rc = 0; rc <= (h->reg_col_ok ? 1 : 0); ++rc)
     for (int rp = 0; rp <= (h->reg_plane_ok ? 1 : 0); ++rp)
-      for (int pv = 0; pv <= ((rp && h->narrow_ok) ? 1 : 0); ++pv) {
+      for (int pv = 0; pv <= ((rp && nok) ? 1 : 0); ++pv) {
         pw_tuning t = cur;
         t.reg_col = rc;
         t.reg_plane = rp;
-        t.plane_variant = pv;
+        if (lp) t.plane_variant32 = pv;
+        else t.plane_variant = pv;
+        if (!rp) t.plane_variant = t.plane_variant32 = 0;
         if (t.reg_col == cur.reg_col && t.reg_plane == cur.reg_plane &&
-            t.plane_variant == cur.plane_variant)
+            t.plane_variant == cur.plane_variant && t.plane_variant32 == cur.plane_variant32)
           continue;
         if ((st = try_one(t)) != PW_OK) return st;
       }

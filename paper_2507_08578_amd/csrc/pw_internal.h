@@ -50,7 +50,8 @@ struct FftLaunchCfg {
   size_t col_lds, plane_lds;
   bool reg_col;             // register-resident column kernels available for N3
   bool reg_plane;           // register-resident plane kernel available for (N1, N2)
-  int plane_variant;        // register plane kernel: 0 = lane groups <= 16, 1 = <= 8
+  int plane_variant;        // FP64 register plane kernel: 0 = lane groups <= 16, 1 = <= 8
+  int plane_variant32;      // the same choice for the FP32 kernel
 };
 
 // Host-side choice of tiles and LDS sizes; returns false if this GPU's LDS
@@ -96,7 +97,7 @@ hipError_t fft_set_lds_limits(size_t bytes);
 // Register-resident variants (fft_reg.hip) for the box lengths they are built for.
 bool fft_reg_col_supported(int n3);
 bool fft_reg_plane_supported(const BoxPlan& p, size_t lds_limit);
-bool fft_reg_plane_narrow(const BoxPlan& p);   // an 8-lane plane variant exists
+bool fft_reg_plane_narrow(const BoxPlan& p, bool fp32);   // an 8-lane plane variant exists
 hipError_t fft_reg_set_lds_limits(size_t bytes);
 hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int64_t ldpsi, cplx* T,
                                   hipStream_t s);

@@ -17,11 +17,11 @@ pytestmark = pytest.mark.gpu
 def all_tunings(ham, nb):
     base = ham.get_tuning()
     out = []
-    for rc, rp, pv in itertools.product((0, 1), (0, 1), (0, 1)):
+    for rc, rp, pv, pv32 in itertools.product((0, 1), (0, 1), (0, 1), (0, 1)):
         for ch in sorted({base["chunk"], max(1, base["chunk"] // 2), 1}):
             for gb in (2048, 256):
-                out.append(dict(reg_col=rc, reg_plane=rp, plane_variant=pv, chunk=ch,
-                                gemm_blocks=gb))
+                out.append(dict(reg_col=rc, reg_plane=rp, plane_variant=pv, plane_variant32=pv32,
+                                chunk=ch, gemm_blocks=gb))
     return out
 
 
