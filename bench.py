@@ -278,12 +278,13 @@ def run_batch(args):
     bt = pw.Batch(ctx, hams, X0, degree=degree, filter_prec=args.precision,
                   nstreams=args.streams)
     bt.start()
-    bt.iterate(args.warmup, graph=True)
+    gmode = False if args.graph == "none" else args.graph
+    bt.iterate(args.warmup, graph=gmode)
     log("batch warmup done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        bt.iterate(1, graph=True)
+        bt.iterate(1, graph=gmode)
         log(f"batch step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -307,8 +308,9 @@ def run_batch(args):
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
                    "filter_precision": args.precision, "subspace_precision": "fp64",
                    "items": len(ws), "bands_total": bands, "streams": args.streams,
+                   "graph": args.graph,
                    "step": f"one iteration of every item: filter (degree {degree}, H*Y reused) "
-                           "+ Cholesky + Rayleigh-Ritz, replayed as one HIP graph"},
+                           "+ Cholesky + Rayleigh-Ritz, replayed from HIP graphs"},
         "filter_iter_ms": 1e3 * dt / args.steps,
         "max_resid": max_resid, "eigensolver_max_sweeps": sweeps,
         "roofline": roof,
@@ -413,6 +415,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=0, help="oracle band sample (0 = auto)")
     ap.add_argument("--streams", type=int, default=8, help="batch branches (C2, C4)")
+    ap.add_argument("--graph", default="per_stream", choices=["single", "per_stream", "none"],
+                    help="batch replay mode (C2, C4)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing alternatives")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -258,9 +258,12 @@ pw_status pw_batch_destroy(pw_batch* b);
  * synchronises and reports failures as pw_batch_iterate does. */
 pw_status pw_batch_start(pw_batch* b);
 /*
- * iters further iterations of every item.  use_graph != 0: replay the
- * captured graph (captured on first use); 0: issue the same kernels
- * directly on the batch's streams.  Ordered after prior work on the
+ * iters further iterations of every item.  use_graph 1: replay one
+ * captured graph holding every branch; 2: replay one captured graph per
+ * branch stream, each launched on its own stream (the branches then run
+ * concurrently whatever the graph executor does with independent nodes);
+ * 0: issue the same kernels directly on the batch's streams.  Graphs are
+ * captured on first use.  Ordered after prior work on the
  * context's stream and before later work on it.  Synchronises once at the
  * end and returns PW_ERR_NOT_POSDEF (Cholesky pivot), PW_ERR_NO_CONVERGENCE
  * (eigensolver sweep limit) or PW_ERR_INVALID_ARG (Ritz values not inside

@@ -369,8 +369,11 @@ class Batch:
         """Iteration 0: orthonormalise the start blocks, then Rayleigh-Ritz."""
         self.ctx.check(_LIB.pw_batch_start(self.handle))
 
-    def iterate(self, iters: int = 1, graph: bool = True):
-        self.ctx.check(_LIB.pw_batch_iterate(self.handle, int(iters), int(bool(graph))))
+    def iterate(self, iters: int = 1, graph=True):
+        """graph: True / "single" (one graph, a branch per stream), "per_stream"
+        (one graph per branch stream), False (kernels issued directly)."""
+        mode = {True: 1, "single": 1, "per_stream": 2, False: 0}[graph]
+        self.ctx.check(_LIB.pw_batch_iterate(self.handle, int(iters), mode))
 
     def max_sweeps(self) -> int:
         n = ctypes.c_int32()

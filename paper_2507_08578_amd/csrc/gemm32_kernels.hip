@@ -109,18 +109,41 @@ k_gemm_nn32(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restri
       f4zero(ar[a][b]);
       f4zero(ai[a][b]);
     }
-  for (int64_t k0 = 0; k0 < K; k0 += Kc) {
-    for (int e = tid; e < kBM * Kc; e += kThreads) {
+  constexpr int QA = kBM * Kc / kThreads, QB = kBN * Kc / kThreads;
+  static_assert(QA * kThreads == kBM * Kc && QB * kThreads == kBN * Kc, "tile split");
+  float2 ra[QA], rb[QB];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * kThreads;
       const int kk = e / kBM, ii = e - kk * kBM;
       const int64_t gi = i0 + ii, gk = k0 + kk;
-      As[kk * PA + ii] = (gi < M && gk < K) ? A[gi + gk * lda] : make_float2(0.f, 0.f);
+      ra[q] = (gi < M && gk < K) ? A[gi + gk * lda] : make_float2(0.f, 0.f);
     }
-    for (int e = tid; e < kBN * Kc; e += kThreads) {
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * kThreads;
       const int jj = e / Kc, kk = e - jj * Kc;
       const int64_t gk = k0 + kk, gj = j0 + jj;
-      Bs[kk * PB + jj] = (gk < K && gj < N) ? B[gk + gj * ldb] : make_float2(0.f, 0.f);
+      rb[q] = (gk < K && gj < N) ? B[gk + gj * ldb] : make_float2(0.f, 0.f);
+    }
+  };
+  fetch(0);
+  for (int64_t k0 = 0; k0 < K; k0 += Kc) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * kThreads;
+      const int kk = e / kBM, ii = e - kk * kBM;
+      As[kk * PA + ii] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * kThreads;
+      const int jj = e / Kc, kk = e - jj * Kc;
+      Bs[kk * PB + jj] = rb[q];
     }
     __syncthreads();
+    if (k0 + Kc < K) fetch(k0 + Kc);
     mfma_stage<MODE, false>(As, PA, Bs, PB, wi, wj, lane, ar, ai);
     __syncthreads();
   }
@@ -167,18 +190,41 @@ k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __res
       f4zero(ar[a][b]);
       f4zero(ai[a][b]);
     }
-  for (int64_t k0 = kb; k0 < ke; k0 += Kc) {
-    for (int e = tid; e < kBM * Kc; e += kThreads) {
+  constexpr int QA = kBM * Kc / kThreads, QB = kBN * Kc / kThreads;
+  static_assert(QA * kThreads == kBM * Kc && QB * kThreads == kBN * Kc, "tile split");
+  float2 ra[QA], rb[QB];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * kThreads;
       const int ii = e / Kc, kk = e - ii * Kc;
       const int64_t gi = i0 + ii, gk = k0 + kk;
-      As[kk * PA + ii] = (gi < M && gk < ke) ? A[gk + gi * lda] : make_float2(0.f, 0.f);
+      ra[q] = (gi < M && gk < ke) ? A[gk + gi * lda] : make_float2(0.f, 0.f);
     }
-    for (int e = tid; e < kBN * Kc; e += kThreads) {
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * kThreads;
       const int jj = e / Kc, kk = e - jj * Kc;
       const int64_t gj = j0 + jj, gk = k0 + kk;
-      Bs[kk * PB + jj] = (gj < N && gk < ke) ? B[gk + gj * ldb] : make_float2(0.f, 0.f);
+      rb[q] = (gj < N && gk < ke) ? B[gk + gj * ldb] : make_float2(0.f, 0.f);
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += Kc) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * kThreads;
+      const int ii = e / Kc, kk = e - ii * Kc;
+      As[kk * PA + ii] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * kThreads;
+      const int jj = e / Kc, kk = e - jj * Kc;
+      Bs[kk * PB + jj] = rb[q];
     }
     __syncthreads();
+    if (k0 + Kc < ke) fetch(k0 + Kc);
     mfma_stage<MODE, true>(As, PA, Bs, PB, wi, wj, lane, ar, ai);
     __syncthreads();
   }

@@ -49,18 +49,42 @@ k_gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict_
       acci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     }
   const int lr = lane & 15, lk = lane >> 4;
-  for (int64_t k0 = 0; k0 < K; k0 += kKcNN) {
-    for (int e = tid; e < kBM * kKcNN; e += kThreads) {
+  // global -> register prefetch of the next K stage overlaps this stage's MFMAs
+  constexpr int QA = kBM * kKcNN / kThreads, QB = kBN * kKcNN / kThreads;
+  static_assert(QA * kThreads == kBM * kKcNN && QB * kThreads == kBN * kKcNN, "tile split");
+  cplx ra[QA], rb[QB];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * kThreads;
       const int kk = e / kBM, ii = e - kk * kBM;
       const int64_t gi = i0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < M && gk < K) ? A[gi + gk * lda] : make_double2(0.0, 0.0);
+      ra[q] = (gi < M && gk < K) ? A[gi + gk * lda] : make_double2(0.0, 0.0);
     }
-    for (int e = tid; e < kBN * kKcNN; e += kThreads) {
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * kThreads;
       const int jj = e / kKcNN, kk = e - jj * kKcNN;
       const int64_t gk = k0 + kk, gj = j0 + jj;
-      Bs[kk][jj] = (gk < K && gj < N) ? B[gk + gj * ldb] : make_double2(0.0, 0.0);
+      rb[q] = (gk < K && gj < N) ? B[gk + gj * ldb] : make_double2(0.0, 0.0);
+    }
+  };
+  fetch(0);
+  for (int64_t k0 = 0; k0 < K; k0 += kKcNN) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * kThreads;
+      const int kk = e / kBM, ii = e - kk * kBM;
+      As[kk][ii] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * kThreads;
+      const int jj = e / kKcNN, kk = e - jj * kKcNN;
+      Bs[kk][jj] = rb[q];
     }
     __syncthreads();
+    if (k0 + kKcNN < K) fetch(k0 + kKcNN);
 #pragma unroll
     for (int ks = 0; ks < kKcNN; ks += 4) {
       cplx a[2], b[2];
@@ -121,18 +145,41 @@ k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
       acci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     }
   const int lr = lane & 15, lk = lane >> 4;
-  for (int64_t k0 = kb; k0 < ke; k0 += kKcCN) {
-    for (int e = tid; e < kBM * kKcCN; e += kThreads) {
+  constexpr int QA = kBM * kKcCN / kThreads, QB = kBN * kKcCN / kThreads;
+  static_assert(QA * kThreads == kBM * kKcCN && QB * kThreads == kBN * kKcCN, "tile split");
+  cplx ra[QA], rb[QB];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * kThreads;
       const int ii = e / kKcCN, kk = e - ii * kKcCN;
       const int64_t gi = i0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < M && gk < ke) ? A[gk + gi * lda] : make_double2(0.0, 0.0);
+      ra[q] = (gi < M && gk < ke) ? A[gk + gi * lda] : make_double2(0.0, 0.0);
     }
-    for (int e = tid; e < kBN * kKcCN; e += kThreads) {
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * kThreads;
       const int jj = e / kKcCN, kk = e - jj * kKcCN;
       const int64_t gj = j0 + jj, gk = k0 + kk;
-      Bs[kk][jj] = (gj < N && gk < ke) ? B[gk + gj * ldb] : make_double2(0.0, 0.0);
+      rb[q] = (gj < N && gk < ke) ? B[gk + gj * ldb] : make_double2(0.0, 0.0);
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kKcCN) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = tid + q * kThreads;
+      const int ii = e / kKcCN, kk = e - ii * kKcCN;
+      As[kk][ii] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int e = tid + q * kThreads;
+      const int jj = e / kKcCN, kk = e - jj * kKcCN;
+      Bs[kk][jj] = rb[q];
     }
     __syncthreads();
+    if (k0 + kKcCN < ke) fetch(k0 + kKcCN);
 #pragma unroll
     for (int ks = 0; ks < kKcCN; ks += 4) {
       cplx a[2], b[2];

@@ -109,8 +109,10 @@ struct pw_batch {
   std::vector<hipStream_t> streams;
   hipStream_t s0 = nullptr;         // graph launch / fork-join stream
   std::vector<hipEvent_t> ev;       // [0] ctx->s0, [1] s0->ctx, [2] fork, [3 + k] join of stream k
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;        // mode 1: one graph, a branch per stream
   hipGraphExec_t exec = nullptr;
+  std::vector<hipGraph_t> sgraph;    // mode 2: one graph per stream
+  std::vector<hipGraphExec_t> sexec;
   std::vector<void*> allocs;
   int* flags_dev = nullptr;         // 4 per item
   int* flags_host = nullptr;        // pinned copy
@@ -430,21 +432,43 @@ pw_status batch_ortho_rr(BatchItem& it) {
 
 // One iteration of every item, forked from s0 over the batch streams and
 // joined back (also the body of the captured graph).
-pw_status batch_issue(pw_batch* b, bool filter, bool capturing) {
+// The items of branch stream k, one after another, on that stream.
+pw_status batch_issue_stream(pw_batch* b, size_t k, bool filter, bool capturing) {
   pw_ctx* c = b->ctx;
-  HIPCHK(c, hipEventRecord(b->ev[2], b->s0));
-  for (hipStream_t st : b->streams) HIPCHK(c, hipStreamWaitEvent(st, b->ev[2], 0));
   for (BatchItem& it : b->items) {
-    StreamSwap sw(c, b->streams[it.stream], capturing);
+    if ((size_t)it.stream != k) continue;
+    StreamSwap sw(c, b->streams[k], capturing);
     pw_status st;
     if (filter && (st = batch_filter(b, it)) != PW_OK) return st;
     if ((st = batch_ortho_rr(it)) != PW_OK) return st;
   }
+  return PW_OK;
+}
+
+pw_status batch_fork(pw_batch* b) {
+  pw_ctx* c = b->ctx;
+  HIPCHK(c, hipEventRecord(b->ev[2], b->s0));
+  for (hipStream_t st : b->streams) HIPCHK(c, hipStreamWaitEvent(st, b->ev[2], 0));
+  return PW_OK;
+}
+
+pw_status batch_join(pw_batch* b) {
+  pw_ctx* c = b->ctx;
   for (size_t k = 0; k < b->streams.size(); ++k) {
     HIPCHK(c, hipEventRecord(b->ev[3 + k], b->streams[k]));
     HIPCHK(c, hipStreamWaitEvent(b->s0, b->ev[3 + k], 0));
   }
   return PW_OK;
+}
+
+// One iteration of every item, forked from s0 over the batch streams and
+// joined back (also the body of the single captured graph).
+pw_status batch_issue(pw_batch* b, bool filter, bool capturing) {
+  pw_status st;
+  if ((st = batch_fork(b)) != PW_OK) return st;
+  for (size_t k = 0; k < b->streams.size(); ++k)
+    if ((st = batch_issue_stream(b, k, filter, capturing)) != PW_OK) return st;
+  return batch_join(b);
 }
 
 // Reads the flags of all items (synchronises s0) and reports the first failure.
@@ -1199,7 +1223,7 @@ pw_status pw_ham_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, pw_
   }
   // 3) split-K parallelism of the projector product
   if (h->nproj > 0)
-    for (int g : {2048, 1024, 512, 256}) {
+    for (int g : {2048, 1024, 512, 256, 64, 1}) {
       if (g == cur.gemm_blocks) continue;
       pw_tuning t = cur;
       t.gemm_blocks = g;
@@ -1220,6 +1244,10 @@ pw_status pw_batch_destroy(pw_batch* b) {
   for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipGraphExec_t e : b->sexec)
+    if (e) (void)hipGraphExecDestroy(e);
+  for (hipGraph_t g : b->sgraph)
+    if (g) (void)hipGraphDestroy(g);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   if (b->s0) (void)hipStreamDestroy(b->s0);
@@ -1355,10 +1383,12 @@ pw_status pw_batch_start(pw_batch* b) {
 pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
   if (!b) return fail(nullptr, PW_ERR_INVALID_ARG, "batch is NULL");
   if (iters < 0) return fail(b->ctx, PW_ERR_INVALID_ARG, "iters < 0");
+  if (use_graph < 0 || use_graph > 2)
+    return fail(b->ctx, PW_ERR_INVALID_ARG, "use_graph must be 0, 1 or 2");
   pw_ctx* c = b->ctx;
   pw_status st;
   if ((st = batch_enter(b)) != PW_OK) return st;
-  if (use_graph && !b->exec) {
+  if (use_graph == 1 && !b->exec) {
     HIPCHK(c, hipStreamBeginCapture(b->s0, hipStreamCaptureModeThreadLocal));
     st = batch_issue(b, true, true);
     hipGraph_t g = nullptr;
@@ -1374,9 +1404,33 @@ pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
     b->graph = g;
     HIPCHK(c, hipGraphInstantiateWithFlags(&b->exec, b->graph, 0));
   }
+  if (use_graph == 2 && b->sexec.empty()) {
+    const size_t ns = b->streams.size();
+    b->sgraph.assign(ns, nullptr);
+    b->sexec.assign(ns, nullptr);
+    for (size_t k = 0; k < ns; ++k) {
+      HIPCHK(c, hipStreamBeginCapture(b->streams[k], hipStreamCaptureModeThreadLocal));
+      st = batch_issue_stream(b, k, true, true);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(b->streams[k], &g);
+      b->sgraph[k] = g;
+      if (st != PW_OK) return st;
+      if (e != hipSuccess)
+        return fail(c, PW_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      HIPCHK(c, hipGraphInstantiateWithFlags(&b->sexec[k], g, 0));
+    }
+  }
   for (int32_t t = 0; t < iters; ++t) {
-    if (use_graph) HIPCHK(c, hipGraphLaunch(b->exec, b->s0));
-    else if ((st = batch_issue(b, true, false)) != PW_OK) return st;
+    if (use_graph == 1) {
+      HIPCHK(c, hipGraphLaunch(b->exec, b->s0));
+    } else if (use_graph == 2) {
+      if ((st = batch_fork(b)) != PW_OK) return st;
+      for (size_t k = 0; k < b->streams.size(); ++k)
+        HIPCHK(c, hipGraphLaunch(b->sexec[k], b->streams[k]));
+      if ((st = batch_join(b)) != PW_OK) return st;
+    } else if ((st = batch_issue(b, true, false)) != PW_OK) {
+      return st;
+    }
   }
   return batch_leave(b);
 }

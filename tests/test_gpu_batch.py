@@ -58,7 +58,8 @@ def test_batch_matches_per_item_path(pw, ctx):
         assert np.abs(to_host(bt.resid[i]) - st.resid_history[-1]).max() < 1e-9
 
 
-def test_graph_replays_equal_direct_issue(pw, ctx):
+@pytest.mark.parametrize("mode", ["single", "per_stream"])
+def test_graph_replays_equal_direct_issue(pw, ctx, mode):
     """Graph replays, with unrelated eager work and host reads between them,
     give the same bits as the same iteration issued directly."""
     import torch
@@ -69,7 +70,7 @@ def test_graph_replays_equal_direct_issue(pw, ctx):
     ga.start()
     gb.start()
     for t in range(4):
-        ga.iterate(1, graph=True)
+        ga.iterate(1, graph=mode)
         junk = torch.randn(1 << 16, device="cuda").sum()
         gb.iterate(1, graph=False)
         torch.cuda.synchronize()
