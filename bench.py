@@ -415,7 +415,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=0, help="oracle band sample (0 = auto)")
     ap.add_argument("--streams", type=int, default=8, help="batch branches (C2, C4)")
-    ap.add_argument("--graph", default="per_stream", choices=["single", "per_stream", "none"],
+    ap.add_argument("--graph", default="fused", choices=["single", "per_stream", "fused", "none"],
                     help="batch replay mode (C2, C4)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing alternatives")

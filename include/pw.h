@@ -262,8 +262,12 @@ pw_status pw_batch_start(pw_batch* b);
  * captured graph holding every branch; 2: replay one captured graph per
  * branch stream, each launched on its own stream (the branches then run
  * concurrently whatever the graph executor does with independent nodes);
- * 0: issue the same kernels directly on the batch's streams.  Graphs are
- * captured on first use.  Ordered after prior work on the
+ * 3: fused — items with the same FFT box share every launch (one kernel per
+ * stage for the whole group, the items' sizes and buffers read from device
+ * descriptors; needs each handle's FFT buffer to hold all nb bands), one
+ * graph replayed; 0: issue the per-item kernels directly on the batch's
+ * streams.  Graphs are captured on first use.  All modes compute the same
+ * arithmetic item by item.  Ordered after prior work on the
  * context's stream and before later work on it.  Synchronises once at the
  * end and returns PW_ERR_NOT_POSDEF (Cholesky pivot), PW_ERR_NO_CONVERGENCE
  * (eigensolver sweep limit) or PW_ERR_INVALID_ARG (Ritz values not inside

@@ -73,8 +73,8 @@ __global__ void k_check_finite(int64_t n, const double* __restrict__ x, int* fla
 }
 
 // A <- (A + A^H)/2
-__global__ void k_hermitize(int64_t n, cplx* a, int64_t lda) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void hermitize_body(int64_t n, cplx* a, int64_t lda, int bx_) {
+  const int64_t idx = (int64_t)bx_ * blockDim.x + threadIdx.x;
   if (idx >= n * n) return;
   const int64_t j = idx / n, i = idx - j * n;
   if (i > j) return;
@@ -88,12 +88,23 @@ __global__ void k_hermitize(int64_t n, cplx* a, int64_t lda) {
   a[j + i * lda] = cconj(avg);
 }
 
-__global__ void k_copy_block(int64_t rows, int64_t cols, const cplx* __restrict__ src, int64_t lds,
-                             cplx* __restrict__ dst, int64_t ldd) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void 
+k_hermitize(int64_t n, cplx* a, int64_t lda) {
+  hermitize_body(n, a, lda, blockIdx.x);
+}
+
+__device__ __forceinline__ void copy_block_body(int64_t rows, int64_t cols, const cplx* __restrict__ src, int64_t lds,
+                             cplx* __restrict__ dst, int64_t ldd, int bx_) {
+  const int64_t idx = (int64_t)bx_ * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const int64_t j = idx / rows, i = idx - j * rows;
   dst[i + j * ldd] = src[i + j * lds];
+}
+
+__global__ void 
+k_copy_block(int64_t rows, int64_t cols, const cplx* __restrict__ src, int64_t lds,
+                             cplx* __restrict__ dst, int64_t ldd) {
+  copy_block_body(rows, cols, src, lds, dst, ldd, blockIdx.x);
 }
 
 __global__ void k_scale_rows_cols(int64_t n, const double* __restrict__ d, cplx* a, int64_t lda) {
@@ -103,10 +114,10 @@ __global__ void k_scale_rows_cols(int64_t n, const double* __restrict__ d, cplx*
   a[i + j * lda] = cscale(a[i + j * lda], d[i] * d[j]);
 }
 
-__global__ void k_axpby_block(int64_t npw, int64_t nb, double a, const cplx* x, int64_t ldx,
+__device__ __forceinline__ void axpby_block_body(int64_t npw, int64_t nb, double a, const cplx* x, int64_t ldx,
                               double b, const cplx* y, int64_t ldy, cplx* out, int64_t ldo,
-                              const double* __restrict__ coef) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                              const double* __restrict__ coef, int bx_) {
+  const int64_t idx = (int64_t)bx_ * blockDim.x + threadIdx.x;
   if (idx >= npw * nb) return;
   if (coef) {
     a = coef[0];
@@ -117,11 +128,17 @@ __global__ void k_axpby_block(int64_t npw, int64_t nb, double a, const cplx* x, 
   out[i + j * ldo] = make_double2(a * u.x + b * v.x, a * u.y + b * v.y);
 }
 
-__global__ void __launch_bounds__(256)
-k_residuals(int64_t npw, const cplx* __restrict__ W, int64_t ldw, const cplx* __restrict__ Y,
-            int64_t ldy, const double* __restrict__ lam, double* __restrict__ resid) {
+__global__ void 
+k_axpby_block(int64_t npw, int64_t nb, double a, const cplx* x, int64_t ldx,
+                              double b, const cplx* y, int64_t ldy, cplx* out, int64_t ldo,
+                              const double* __restrict__ coef) {
+  axpby_block_body(npw, nb, a, x, ldx, b, y, ldy, out, ldo, coef, blockIdx.x);
+}
+
+__device__ __forceinline__ void residuals_body(int64_t npw, const cplx* __restrict__ W, int64_t ldw, const cplx* __restrict__ Y,
+            int64_t ldy, const double* __restrict__ lam, double* __restrict__ resid, int bx_) {
   __shared__ double red[256];
-  const int64_t b = blockIdx.x;
+  const int64_t b = bx_;
   const double l = lam[b];
   const cplx* w = W + b * ldw;
   const cplx* y = Y + b * ldy;
@@ -139,12 +156,18 @@ k_residuals(int64_t npw, const cplx* __restrict__ W, int64_t ldw, const cplx* __
   if (threadIdx.x == 0) resid[b] = sqrt(red[0]);
 }
 
+__global__ void __launch_bounds__(256) 
+k_residuals(int64_t npw, const cplx* __restrict__ W, int64_t ldw, const cplx* __restrict__ Y,
+            int64_t ldy, const double* __restrict__ lam, double* __restrict__ resid) {
+  residuals_body(npw, W, ldw, Y, ldy, lam, resid, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Blocked Cholesky (S = U^H U) for large n: per diagonal block of kb <= 64
 // one workgroup factors it in LDS and inverts the factor; the row panel and
 // the trailing update are matrix products (k_gemm_cn) issued by the host.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_chol_init(int n, const cplx* __restrict__ A, int64_t lda,
+__device__ __forceinline__ void chol_init_body(int n, const cplx* __restrict__ A, int64_t lda,
                                                     double* tol, int* status) {
   __shared__ double red[1024];
   double m = 0.0;
@@ -161,11 +184,16 @@ __global__ void __launch_bounds__(1024) k_chol_init(int n, const cplx* __restric
   }
 }
 
+__global__ void __launch_bounds__(1024) 
+k_chol_init(int n, const cplx* __restrict__ A, int64_t lda,
+                                                    double* tol, int* status) {
+  chol_init_body(n, A, lda, tol, status);
+}
+
 // Factor the kb x kb diagonal block at A(k0, k0) (upper triangle read),
 // write U back (zeros below its diagonal) and U^{-1} to dinv (ld kb).  A
 // pivot at or below tol records k0 + p in status unless an earlier block did.
-__global__ void __launch_bounds__(256)
-k_chol_diag(int kb, int k0, cplx* __restrict__ A, int64_t lda, cplx* __restrict__ dinv,
+__device__ __forceinline__ void chol_diag_body(int kb, int k0, cplx* __restrict__ A, int64_t lda, cplx* __restrict__ dinv,
             const double* __restrict__ tol, int* status) {
   extern __shared__ cplx sm[];
   const int trs = kb + 1;
@@ -238,6 +266,12 @@ k_chol_diag(int kb, int k0, cplx* __restrict__ A, int64_t lda, cplx* __restrict_
     const int j = idx / kb, i = idx - j * kb;
     dinv[i + j * kb] = x[i + j * trs];
   }
+}
+
+__global__ void __launch_bounds__(256) 
+k_chol_diag(int kb, int k0, cplx* __restrict__ A, int64_t lda, cplx* __restrict__ dinv,
+            const double* __restrict__ tol, int* status) {
+  chol_diag_body(kb, k0, A, lda, dinv, tol, status);
 }
 
 __global__ void k_zero_lower(int n, cplx* A, int64_t lda) {
@@ -333,8 +367,7 @@ constexpr int kMaxSweeps = 40;
 __device__ __forceinline__ double jac_tol(int n) { return fmax(1e-15, 2.2e-16 * n); }
 
 // Whole Jacobi solve in LDS for n <= 64.
-__global__ void __launch_bounds__(kJacThreads)
-k_jacobi_small(int n, const cplx* __restrict__ Ain, int64_t lda, double* __restrict__ w,
+__device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict__ Ain, int64_t lda, double* __restrict__ w,
                cplx* __restrict__ Q, int64_t ldq, int* sweeps_out) {
   extern __shared__ cplx sm[];
   const int n2 = n + (n & 1);
@@ -462,6 +495,12 @@ k_jacobi_small(int n, const cplx* __restrict__ Ain, int64_t lda, double* __restr
     Q[i + (int64_t)rank_[j] * ldq] = v[i + j * n];
   }
   if (tid == 0) sweeps_out[0] = done ? sweeps : -1;
+}
+
+__global__ void 
+k_jacobi_small(int n, const cplx* __restrict__ Ain, int64_t lda, double* __restrict__ w,
+               cplx* __restrict__ Q, int64_t ldq, int* sweeps_out) {
+  jacobi_small_body(n, Ain, lda, w, Q, ldq, sweeps_out);
 }
 
 // Rounds for n > 64 run in "position space": the n2 x n2 matrix (n2 = n
@@ -610,29 +649,41 @@ __global__ void __launch_bounds__(1024) k_offnorm(int n, const cplx* __restrict_
 // ---------------------------------------------------------------------------
 // precision conversions for the low-precision filter path
 // ---------------------------------------------------------------------------
-__global__ void k_block_to_f32(int64_t rows, int64_t cols, const cplx* __restrict__ x, int64_t ldx,
-                               float2* __restrict__ y, int64_t ldy) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void block_to_f32_body(int64_t rows, int64_t cols, const cplx* __restrict__ x, int64_t ldx,
+                               float2* __restrict__ y, int64_t ldy, int bx_) {
+  const int64_t idx = (int64_t)bx_ * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const int64_t j = idx / rows, i = idx - j * rows;
   const cplx v = x[i + j * ldx];
   y[i + j * ldy] = make_float2((float)v.x, (float)v.y);
 }
 
-__global__ void k_block_to_f64(int64_t rows, int64_t cols, const float2* __restrict__ x, int64_t ldx,
-                               cplx* __restrict__ y, int64_t ldy) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void 
+k_block_to_f32(int64_t rows, int64_t cols, const cplx* __restrict__ x, int64_t ldx,
+                               float2* __restrict__ y, int64_t ldy) {
+  block_to_f32_body(rows, cols, x, ldx, y, ldy, blockIdx.x);
+}
+
+__device__ __forceinline__ void block_to_f64_body(int64_t rows, int64_t cols, const float2* __restrict__ x, int64_t ldx,
+                               cplx* __restrict__ y, int64_t ldy, int bx_) {
+  const int64_t idx = (int64_t)bx_ * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const int64_t j = idx / rows, i = idx - j * rows;
   const float2 v = x[i + j * ldx];
   y[i + j * ldy] = make_double2((double)v.x, (double)v.y);
 }
 
+__global__ void 
+k_block_to_f64(int64_t rows, int64_t cols, const float2* __restrict__ x, int64_t ldx,
+                               cplx* __restrict__ y, int64_t ldy) {
+  block_to_f64_body(rows, cols, x, ldx, y, ldy, blockIdx.x);
+}
+
 // out = fp32(a x + b y), x and y FP64
-__global__ void k_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx* __restrict__ x,
+__device__ __forceinline__ void axpby_to_f32_body(int64_t rows, int64_t cols, double a, const cplx* __restrict__ x,
                                int64_t ldx, double b, const cplx* __restrict__ y, int64_t ldy,
-                               float2* __restrict__ out, int64_t ldo, const double* __restrict__ coef) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                               float2* __restrict__ out, int64_t ldo, const double* __restrict__ coef, int bx_) {
+  const int64_t idx = (int64_t)bx_ * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   if (coef) {
     a = coef[0];
@@ -641,6 +692,13 @@ __global__ void k_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx*
   const int64_t j = idx / rows, i = idx - j * rows;
   const cplx u = x[i + j * ldx], v = y[i + j * ldy];
   out[i + j * ldo] = make_float2((float)(a * u.x + b * v.x), (float)(a * u.y + b * v.y));
+}
+
+__global__ void 
+k_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx* __restrict__ x,
+                               int64_t ldx, double b, const cplx* __restrict__ y, int64_t ldy,
+                               float2* __restrict__ out, int64_t ldo, const double* __restrict__ coef) {
+  axpby_to_f32_body(rows, cols, a, x, ldx, b, y, ldy, out, ldo, coef, blockIdx.x);
 }
 
 __global__ void k_real_to_f32(int64_t n, const double* __restrict__ src, double scale,
@@ -660,9 +718,9 @@ __global__ void k_tw_to_f32(int n, const cplx* __restrict__ src, float2* __restr
 //   i = 0: alpha = s/e, beta = -s c/e, gamma = 0            (s = e/(a0 - c))
 //   i > 0: s' = 1/(2/s_0 - s), alpha = 2 s'/e, beta = -alpha c, gamma = -s s'; s = s'
 // If a0 < a < b fails, every step becomes the identity and flag[0] is set.
-__global__ void k_cheb_coef(const double* __restrict__ eig, int nb, const double* __restrict__ upper,
+__device__ __forceinline__ void cheb_coef_body(const double* __restrict__ eig, int nb, const double* __restrict__ upper,
                             int degree, double* __restrict__ coef, int* flag) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (threadIdx.x != 0) return;
   const double a = eig[nb - 1], a0 = eig[0], b = upper[0];
   if (!(a0 < a && a < b)) {
     for (int i = 0; i < degree; ++i) {
@@ -689,17 +747,94 @@ __global__ void k_cheb_coef(const double* __restrict__ eig, int nb, const double
   }
 }
 
+__global__ void 
+k_cheb_coef(const double* __restrict__ eig, int nb, const double* __restrict__ upper,
+                            int degree, double* __restrict__ coef, int* flag) {
+  cheb_coef_body(eig, nb, upper, degree, coef, flag);
+}
+
 // Sticky per-item failure flags of a batched iteration:
 // flags[0] = first failing Cholesky pivot + 1, flags[1] = eigensolver hit the
 // sweep limit, flags[2] = bad filter interval (set by k_cheb_coef),
 // flags[3] = largest sweep count seen.
-__global__ void k_batch_flags(const int* __restrict__ chol_status, const int* __restrict__ sweeps,
+__device__ __forceinline__ void batch_flags_body(const int* __restrict__ chol_status, const int* __restrict__ sweeps,
                               int* flags) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (threadIdx.x != 0) return;
   if (chol_status && chol_status[0] >= 0 && flags[0] == 0) flags[0] = chol_status[0] + 1;
   const int sw = sweeps[0];
   if (sw < 0) flags[1] = 1;
   else if (sw > flags[3]) flags[3] = sw;
+}
+
+__global__ void 
+k_batch_flags(const int* __restrict__ chol_status, const int* __restrict__ sweeps,
+                              int* flags) {
+  batch_flags_body(chol_status, sweeps, flags);
+}
+
+// ---- fused-batch steps: item = blockIdx.y for the element-wise steps (x covers
+// the largest item), blockIdx.x for the one-workgroup steps
+__global__ void kb_cheb_coef(const ItemDev* __restrict__ D, int degree) {
+  const ItemDev& d = D[blockIdx.x];
+  cheb_coef_body(d.eig, d.nb, d.upper, degree, d.coef, d.flags + 2);
+}
+
+// first filter step from W = H Y: FP64 blk, or FP32 b32[1]
+__global__ void kb_filter_first(const ItemDev* __restrict__ D, int fp32) {
+  const ItemDev& d = D[blockIdx.y];
+  if (fp32)
+    axpby_to_f32_body(d.npw, d.nb, 0.0, d.hy, d.npw, 0.0, d.y, d.npw, d.b32[1], d.npw, d.coef,
+                      blockIdx.x);
+  else
+    axpby_block_body(d.npw, d.nb, 0.0, d.hy, d.npw, 0.0, d.y, d.npw, d.blk, d.npw, d.coef,
+                     blockIdx.x);
+}
+
+__global__ void kb_to_f32(const ItemDev* __restrict__ D) {
+  const ItemDev& d = D[blockIdx.y];
+  block_to_f32_body(d.npw, d.nb, d.y, d.npw, d.b32[0], d.npw, blockIdx.x);
+}
+
+__global__ void kb_to_f64(const ItemDev* __restrict__ D, int sel) {
+  const ItemDev& d = D[blockIdx.y];
+  block_to_f64_body(d.npw, d.nb, item_blk32(d, sel), d.npw, d.y, d.npw, blockIdx.x);
+}
+
+__global__ void kb_copy(const ItemDev* __restrict__ D, int sel_src, int sel_dst) {
+  const ItemDev& d = D[blockIdx.y];
+  copy_block_body(d.npw, d.nb, item_blk64(d, sel_src), d.npw, item_blk64(d, sel_dst), d.npw,
+                  blockIdx.x);
+}
+
+__global__ void kb_hermitize(const ItemDev* __restrict__ D) {
+  const ItemDev& d = D[blockIdx.y];
+  hermitize_body(d.nb, d.sub0, d.nb, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) kb_chol_init(const ItemDev* __restrict__ D) {
+  const ItemDev& d = D[blockIdx.x];
+  chol_init_body(d.nb, d.sub0, d.nb, d.dtol, d.status);
+}
+
+__global__ void __launch_bounds__(256) kb_chol_diag(const ItemDev* __restrict__ D) {
+  const ItemDev& d = D[blockIdx.x];
+  chol_diag_body(d.nb, 0, d.sub0, d.nb, d.dinv, d.dtol, d.status);
+}
+
+__global__ void __launch_bounds__(kJacThreads) kb_jacobi(const ItemDev* __restrict__ D) {
+  const ItemDev& d = D[blockIdx.x];
+  jacobi_small_body(d.nb, d.sub0, d.nb, d.eig, d.sub1, d.nb, d.sweeps);
+}
+
+__global__ void __launch_bounds__(256) kb_residuals(const ItemDev* __restrict__ D) {
+  const ItemDev& d = D[blockIdx.y];
+  if ((int)blockIdx.x >= d.nb) return;
+  residuals_body(d.npw, d.hy, d.npw, d.y, d.npw, d.eig, d.resid, blockIdx.x);
+}
+
+__global__ void kb_flags(const ItemDev* __restrict__ D) {
+  const ItemDev& d = D[blockIdx.x];
+  batch_flags_body(d.status, d.sweeps, d.flags);
 }
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -839,7 +974,8 @@ size_t heev_work_bytes(int64_t n) {
 }
 
 hipError_t heev_set_lds_limit(size_t bytes) {
-  const void* fns[2] = {(const void*)k_jacobi_small, (const void*)k_chol_diag};
+  const void* fns[4] = {(const void*)k_jacobi_small, (const void*)k_chol_diag,
+                        (const void*)kb_jacobi, (const void*)kb_chol_diag};
   for (const void* f : fns) {
     hipFuncAttributes at;
     hipError_t e = hipFuncGetAttributes(&at, f);
@@ -920,5 +1056,51 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
   hipLaunchKernelGGL(k_jacobi_scatter, dim3(nblocks(n * n, 256)), dim3(256), 0, s, (int)n, (int)n2,
                      rounds, (const cplx*)A0, (const cplx*)V0, (const int*)dev_int, w, q, ldq);
   *sweeps_done = conv ? sw : -1;
+  return hipGetLastError();
+}
+
+// ---- fused-batch step launchers (npw_nb_max = max over items of npw * nb)
+hipError_t launch_fused_dense(FusedStep step, int nitems, int64_t npw_nb_max, int nb_max,
+                              const ItemDev* D, int arg0, int arg1, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  const dim3 ew(nblocks(npw_nb_max, 256), nitems);
+  switch (step) {
+    case FS_CHEB_COEF:
+      hipLaunchKernelGGL(kb_cheb_coef, dim3(nitems), dim3(64), 0, s, D, arg0);
+      break;
+    case FS_FILTER_FIRST:
+      hipLaunchKernelGGL(kb_filter_first, ew, dim3(256), 0, s, D, arg0);
+      break;
+    case FS_TO_F32:
+      hipLaunchKernelGGL(kb_to_f32, ew, dim3(256), 0, s, D);
+      break;
+    case FS_TO_F64:
+      hipLaunchKernelGGL(kb_to_f64, ew, dim3(256), 0, s, D, arg0);
+      break;
+    case FS_COPY:
+      hipLaunchKernelGGL(kb_copy, ew, dim3(256), 0, s, D, arg0, arg1);
+      break;
+    case FS_HERMITIZE:
+      hipLaunchKernelGGL(kb_hermitize, dim3(nblocks((int64_t)nb_max * nb_max, 256), nitems),
+                         dim3(256), 0, s, D);
+      break;
+    case FS_CHOL_INIT:
+      hipLaunchKernelGGL(kb_chol_init, dim3(nitems), dim3(1024), 0, s, D);
+      break;
+    case FS_CHOL_DIAG:
+      hipLaunchKernelGGL(kb_chol_diag, dim3(nitems), dim3(256),
+                         (size_t)2 * nb_max * (nb_max + 1) * sizeof(cplx), s, D);
+      break;
+    case FS_JACOBI:
+      hipLaunchKernelGGL(kb_jacobi, dim3(nitems), dim3(kJacThreads),
+                         (size_t)(2 * nb_max * nb_max) * sizeof(cplx), s, D);
+      break;
+    case FS_RESIDUALS:
+      hipLaunchKernelGGL(kb_residuals, dim3(nb_max, nitems), dim3(256), 0, s, D);
+      break;
+    case FS_FLAGS:
+      hipLaunchKernelGGL(kb_flags, dim3(nitems), dim3(64), 0, s, D);
+      break;
+  }
   return hipGetLastError();
 }

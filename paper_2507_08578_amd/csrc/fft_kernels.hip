@@ -118,13 +118,12 @@ PlanArgs plan_args(const BoxPlan& p) {
   return a;
 }
 
-template <class C>
-__global__ void __launch_bounds__(kThreads)
-k_col_inv(PlanArgs P, int ct, const C* __restrict__ psi, int64_t ldpsi, C* __restrict__ T) {
+template <class C, class PL>
+__device__ __forceinline__ void col_inv_body(const PL& P, int ct, const C* __restrict__ psi,
+                                             int64_t ldpsi, C* __restrict__ T, int cb, int b) {
   extern __shared__ __align__(16) char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
-  const int c0 = blockIdx.x * ct;
-  const int b = blockIdx.y;
+  const int c0 = cb * ct;
   const int ncl = min(ct, P.ncols - c0);
   const int trs = P.n3 + 1;
   for (int i = threadIdx.x; i < ncl * trs; i += blockDim.x) lds[i] = czero<C>();
@@ -144,15 +143,19 @@ k_col_inv(PlanArgs P, int ct, const C* __restrict__ psi, int64_t ldpsi, C* __res
 
 template <class C>
 __global__ void __launch_bounds__(kThreads)
-k_plane(PlanArgs P, int rb, const real_t<C>* __restrict__ v, C* __restrict__ T) {
+k_col_inv(PlanArgs P, int ct, const C* __restrict__ psi, int64_t ldpsi, C* __restrict__ T) {
+  col_inv_body<C>(P, ct, psi, ldpsi, T, blockIdx.x, blockIdx.y);
+}
+
+template <class C, class PL>
+__device__ __forceinline__ void plane_body(const PL& P, int rb, const real_t<C>* __restrict__ v,
+                                           C* __restrict__ T, int j3, int b) {
   extern __shared__ __align__(16) char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
   const int trse = P.n2 + 1;
   const int trsr = P.n1 + 1;
   C* E = lds;
   C* Rw = lds + P.xr * trse;
-  const int j3 = blockIdx.x;
-  const int b = blockIdx.y;
   C* tp = T + (size_t)b * P.n3 * P.ncols + (size_t)j3 * P.ncols;
   for (int i = threadIdx.x; i < P.xr * trse; i += blockDim.x) E[i] = czero<C>();
   __syncthreads();
@@ -188,9 +191,17 @@ k_plane(PlanArgs P, int rb, const real_t<C>* __restrict__ v, C* __restrict__ T) 
 
 template <class C>
 __global__ void __launch_bounds__(kThreads)
-k_col_fwd(PlanArgs P, int ct, const C* __restrict__ T, const real_t<C>* __restrict__ kin,
-          const C* in, int64_t ldin, const C* prev, int64_t ldprev, C* out, int64_t ldout,
-          double alpha_d, double beta_d, double gamma_d, const double* __restrict__ coef) {
+k_plane(PlanArgs P, int rb, const real_t<C>* __restrict__ v, C* __restrict__ T) {
+  plane_body<C>(P, rb, v, T, blockIdx.x, blockIdx.y);
+}
+
+template <class C, class PL>
+__device__ __forceinline__ void col_fwd_body(const PL& P, int ct, const C* __restrict__ T,
+                                             const real_t<C>* __restrict__ kin, const C* in,
+                                             int64_t ldin, const C* prev, int64_t ldprev, C* out,
+                                             int64_t ldout, double alpha_d, double beta_d,
+                                             double gamma_d, const double* __restrict__ coef,
+                                             int cb, int b) {
   using Rl = real_t<C>;
   extern __shared__ __align__(16) char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
@@ -200,8 +211,7 @@ k_col_fwd(PlanArgs P, int ct, const C* __restrict__ T, const real_t<C>* __restri
     gamma_d = coef[2];
   }
   const Rl alpha = (Rl)alpha_d, beta = (Rl)beta_d, gamma = (Rl)gamma_d;
-  const int c0 = blockIdx.x * ct;
-  const int b = blockIdx.y;
+  const int c0 = cb * ct;
   const int ncl = min(ct, P.ncols - c0);
   const int trs = P.n3 + 1;
   const C* srcT = T + (size_t)b * P.n3 * P.ncols + c0;
@@ -230,6 +240,70 @@ k_col_fwd(PlanArgs P, int ct, const C* __restrict__ T, const real_t<C>* __restri
     }
     outb[g] = val;
   }
+}
+
+template <class C>
+__global__ void __launch_bounds__(kThreads)
+k_col_fwd(PlanArgs P, int ct, const C* __restrict__ T, const real_t<C>* __restrict__ kin,
+          const C* in, int64_t ldin, const C* prev, int64_t ldprev, C* out, int64_t ldout,
+          double alpha_d, double beta_d, double gamma_d, const double* __restrict__ coef) {
+  col_fwd_body<C>(P, ct, T, kin, in, ldin, prev, ldprev, out, ldout, alpha_d, beta_d, gamma_d,
+                  coef, blockIdx.x, blockIdx.y);
+}
+
+// ---- fused-batch variants (item = blockIdx.z; tiles from the item's descriptor)
+template <class C>
+__device__ __forceinline__ C* gen_block(const ItemDev& d, int sel);
+template <>
+__device__ __forceinline__ double2* gen_block<double2>(const ItemDev& d, int sel) {
+  return item_blk64(d, sel);
+}
+template <>
+__device__ __forceinline__ float2* gen_block<float2>(const ItemDev& d, int sel) {
+  return item_blk32(d, sel);
+}
+template <class C>
+__device__ __forceinline__ C* gen_T(const ItemDev& d);
+template <>
+__device__ __forceinline__ double2* gen_T<double2>(const ItemDev& d) { return d.T; }
+template <>
+__device__ __forceinline__ float2* gen_T<float2>(const ItemDev& d) { return d.T32; }
+
+template <class C>
+__global__ void __launch_bounds__(kThreads)
+kb_col_inv(const ItemDev* __restrict__ D, int sel_in) {
+  const ItemDev& d = D[blockIdx.z];
+  if ((int)blockIdx.y >= d.nb || (int)blockIdx.x * d.col_tile >= d.plan.ncols) return;
+  col_inv_body<C>(d.plan, d.col_tile, gen_block<C>(d, sel_in), d.npw, gen_T<C>(d), blockIdx.x,
+                  blockIdx.y);
+}
+
+template <class C>
+__global__ void __launch_bounds__(kThreads)
+kb_plane(const ItemDev* __restrict__ D) {
+  const ItemDev& d = D[blockIdx.z];
+  if ((int)blockIdx.y >= d.nb || (int)blockIdx.x >= d.plan.n3) return;
+  if constexpr (sizeof(C) == sizeof(double2))
+    plane_body<C>(d.plan, d.plane_rows, d.vs, gen_T<C>(d), blockIdx.x, blockIdx.y);
+  else
+    plane_body<C>(d.plan, d.plane_rows, d.vs32, gen_T<C>(d), blockIdx.x, blockIdx.y);
+}
+
+template <class C>
+__global__ void __launch_bounds__(kThreads)
+kb_col_fwd(const ItemDev* __restrict__ D, int sel_in, int sel_out, int sel_prev, double alpha,
+           double beta, double gamma, int coef_step) {
+  const ItemDev& d = D[blockIdx.z];
+  if ((int)blockIdx.y >= d.nb || (int)blockIdx.x * d.col_tile >= d.plan.ncols) return;
+  const double* coef = coef_step >= 0 ? d.coef + 3 * coef_step : nullptr;
+  if constexpr (sizeof(C) == sizeof(double2))
+    col_fwd_body<C>(d.plan, d.col_tile, gen_T<C>(d), d.kin, gen_block<C>(d, sel_in), d.npw,
+                    gen_block<C>(d, sel_prev), d.npw, gen_block<C>(d, sel_out), d.npw, alpha, beta,
+                    gamma, coef, blockIdx.x, blockIdx.y);
+  else
+    col_fwd_body<C>(d.plan, d.col_tile, gen_T<C>(d), d.kin32, gen_block<C>(d, sel_in), d.npw,
+                    gen_block<C>(d, sel_prev), d.npw, gen_block<C>(d, sel_out), d.npw, alpha, beta,
+                    gamma, coef, blockIdx.x, blockIdx.y);
 }
 
 int max_butterflies(const FftAxis& ax) {
@@ -399,11 +473,51 @@ hipError_t launch_fft_col_fwd32(const BoxPlan& p, const FftLaunchCfg& cfg, int n
   return col_fwd_generic<float2>(p, cfg, nb, T, kin, in, ldin, prev, ldprev, out, ldout, ep, s);
 }
 
+hipError_t launch_fused_col_inv(const FusedFft& f, bool fp32, const ItemDev* D, int sel_in,
+                                hipStream_t s) {
+  if (f.reg_col) return launch_fused_col_inv_reg(f, fp32, D, sel_in, s);
+  dim3 grid(f.col_blocks, f.nb_max, f.nitems);
+  if (fp32)
+    hipLaunchKernelGGL(kb_col_inv<float2>, grid, dim3(kThreads), f.col_lds, s, D, sel_in);
+  else
+    hipLaunchKernelGGL(kb_col_inv<double2>, grid, dim3(kThreads), f.col_lds, s, D, sel_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_plane(const FusedFft& f, bool fp32, const ItemDev* D, hipStream_t s) {
+  if (f.reg_plane) return launch_fused_plane_reg(f, fp32, D, s);
+  dim3 grid(f.n3_max, f.nb_max, f.nitems);
+  if (fp32)
+    hipLaunchKernelGGL(kb_plane<float2>, grid, dim3(kThreads), f.plane_lds, s, D);
+  else
+    hipLaunchKernelGGL(kb_plane<double2>, grid, dim3(kThreads), f.plane_lds, s, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_col_fwd(const FusedFft& f, bool fp32, const ItemDev* D, int sel_in,
+                                int sel_out, int sel_prev, double alpha, double beta, double gamma,
+                                int coef_step, hipStream_t s) {
+  if (f.reg_col)
+    return launch_fused_col_fwd_reg(f, fp32, D, sel_in, sel_out, sel_prev, alpha, beta, gamma,
+                                    coef_step, s);
+  dim3 grid(f.col_blocks, f.nb_max, f.nitems);
+  if (fp32)
+    hipLaunchKernelGGL(kb_col_fwd<float2>, grid, dim3(kThreads), f.col_lds, s, D, sel_in, sel_out,
+                       sel_prev, alpha, beta, gamma, coef_step);
+  else
+    hipLaunchKernelGGL(kb_col_fwd<double2>, grid, dim3(kThreads), f.col_lds, s, D, sel_in, sel_out,
+                       sel_prev, alpha, beta, gamma, coef_step);
+  return hipGetLastError();
+}
+
 // Dynamic LDS above the default limit must be opted into per kernel.
 hipError_t fft_set_lds_limits(size_t bytes) {
-  const void* fns[6] = {(const void*)k_col_inv<double2>, (const void*)k_plane<double2>,
-                        (const void*)k_col_fwd<double2>, (const void*)k_col_inv<float2>,
-                        (const void*)k_plane<float2>, (const void*)k_col_fwd<float2>};
+  const void* fns[12] = {(const void*)k_col_inv<double2>, (const void*)k_plane<double2>,
+                         (const void*)k_col_fwd<double2>, (const void*)k_col_inv<float2>,
+                         (const void*)k_plane<float2>, (const void*)k_col_fwd<float2>,
+                         (const void*)kb_col_inv<double2>, (const void*)kb_plane<double2>,
+                         (const void*)kb_col_fwd<double2>, (const void*)kb_col_inv<float2>,
+                         (const void*)kb_plane<float2>, (const void*)kb_col_fwd<float2>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;

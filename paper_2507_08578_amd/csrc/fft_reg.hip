@@ -20,13 +20,12 @@ constexpr int kColThreads = 256;
 constexpr int kPlaneMaxThreads = 512;
 
 template <int N3, class C>
-__global__ void __launch_bounds__(kColThreads)
-k_col_inv_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ psi, int64_t ldpsi,
-              C* __restrict__ T) {
+__device__ __forceinline__ void col_inv_reg_body(const BoxPlan& P, const C* __restrict__ tw3,
+                                                 const C* __restrict__ psi, int64_t ldpsi,
+                                                 C* __restrict__ T, int cb, int b) {
   constexpr int G = lane_group(N3), R = N3 / G, CT = kColThreads / G, TRS = N3 + 1;
   __shared__ C tile[CT * TRS];
-  const int c0 = blockIdx.x * CT;
-  const int b = blockIdx.y;
+  const int c0 = cb * CT;
   const int ncl = min(CT, P.ncols - c0);
   for (int i = threadIdx.x; i < CT * TRS; i += blockDim.x) tile[i] = czero<C>();
   __syncthreads();
@@ -58,10 +57,19 @@ k_col_inv_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ psi, i
 
 template <int N3, class C>
 __global__ void __launch_bounds__(kColThreads)
-k_col_fwd_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ T,
-              const real_t<C>* __restrict__ kin, const C* in, int64_t ldin, const C* prev,
-              int64_t ldprev, C* out, int64_t ldout, double alpha_d, double beta_d,
-              double gamma_d, const double* __restrict__ coef) {
+k_col_inv_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ psi, int64_t ldpsi,
+              C* __restrict__ T) {
+  col_inv_reg_body<N3, C>(P, tw3, psi, ldpsi, T, blockIdx.x, blockIdx.y);
+}
+
+template <int N3, class C>
+__device__ __forceinline__ void col_fwd_reg_body(const BoxPlan& P, const C* __restrict__ tw3,
+                                                 const C* __restrict__ T,
+                                                 const real_t<C>* __restrict__ kin, const C* in,
+                                                 int64_t ldin, const C* prev, int64_t ldprev,
+                                                 C* out, int64_t ldout, double alpha_d,
+                                                 double beta_d, double gamma_d,
+                                                 const double* __restrict__ coef, int cb, int b) {
   using Rl = real_t<C>;
   constexpr int G = lane_group(N3), R = N3 / G, CT = kColThreads / G, TRS = N3 + 1;
   __shared__ C tile[CT * TRS];
@@ -71,8 +79,7 @@ k_col_fwd_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ T,
     gamma_d = coef[2];
   }
   const Rl alpha = (Rl)alpha_d, beta = (Rl)beta_d, gamma = (Rl)gamma_d;
-  const int c0 = blockIdx.x * CT;
-  const int b = blockIdx.y;
+  const int c0 = cb * CT;
   const int ncl = min(CT, P.ncols - c0);
   const C* srcT = T + (size_t)b * N3 * P.ncols + c0;
   for (int i = threadIdx.x; i < ncl * N3; i += blockDim.x) {
@@ -115,18 +122,27 @@ k_col_fwd_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ T,
   }
 }
 
+template <int N3, class C>
+__global__ void __launch_bounds__(kColThreads)
+k_col_fwd_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ T,
+              const real_t<C>* __restrict__ kin, const C* in, int64_t ldin, const C* prev,
+              int64_t ldprev, C* out, int64_t ldout, double alpha_d, double beta_d,
+              double gamma_d, const double* __restrict__ coef) {
+  col_fwd_reg_body<N3, C>(P, tw3, T, kin, in, ldin, prev, ldprev, out, ldout, alpha_d, beta_d,
+                          gamma_d, coef, blockIdx.x, blockIdx.y);
+}
+
 template <int N1, int N2, int GMAX, class C>
-__global__ void __launch_bounds__(kPlaneMaxThreads)
-k_plane_reg(BoxPlan P, const C* __restrict__ tw1, const C* __restrict__ tw2,
-            const real_t<C>* __restrict__ vs, C* __restrict__ T) {
+__device__ __forceinline__ void plane_reg_body(const BoxPlan& P, const C* __restrict__ tw1,
+                                               const C* __restrict__ tw2,
+                                               const real_t<C>* __restrict__ vs,
+                                               C* __restrict__ T, int j3, int b) {
   constexpr int G1 = lane_group(N1, GMAX), R1 = N1 / G1;
   constexpr int G2 = lane_group(N2, GMAX), R2 = N2 / G2;
   constexpr int TRS = N2 + 1;
   extern __shared__ __align__(16) char lds_raw[];
   C* E = reinterpret_cast<C*>(lds_raw);                            // xr x TRS
   int* slot = reinterpret_cast<int*>(E + (size_t)P.xr * TRS);      // N1 entries
-  const int j3 = blockIdx.x;
-  const int b = blockIdx.y;
   const int tid = threadIdx.x, nt = blockDim.x;
   C* tp = T + (size_t)b * P.n3 * P.ncols + (size_t)j3 * P.ncols;
   for (int i = tid; i < P.xr * TRS; i += nt) E[i] = czero<C>();
@@ -197,6 +213,83 @@ k_plane_reg(BoxPlan P, const C* __restrict__ tw1, const C* __restrict__ tw2,
   }
   __syncthreads();
   for (int c = tid; c < P.ncols; c += nt) tp[c] = E[P.col_e[c] * TRS + P.col_m2[c]];
+}
+
+template <int N1, int N2, int GMAX, class C>
+__global__ void __launch_bounds__(kPlaneMaxThreads)
+k_plane_reg(BoxPlan P, const C* __restrict__ tw1, const C* __restrict__ tw2,
+            const real_t<C>* __restrict__ vs, C* __restrict__ T) {
+  plane_reg_body<N1, N2, GMAX, C>(P, tw1, tw2, vs, T, blockIdx.x, blockIdx.y);
+}
+
+// ---- fused-batch variants: item = blockIdx.z, all items share the box lengths
+template <class C>
+__device__ __forceinline__ const C* tw_of(const FftAxis& ax);
+template <>
+__device__ __forceinline__ const double2* tw_of<double2>(const FftAxis& ax) { return ax.tw; }
+template <>
+__device__ __forceinline__ const float2* tw_of<float2>(const FftAxis& ax) { return ax.tw32; }
+
+template <class C>
+__device__ __forceinline__ C* item_block(const ItemDev& d, int sel);
+template <>
+__device__ __forceinline__ double2* item_block<double2>(const ItemDev& d, int sel) {
+  return item_blk64(d, sel);
+}
+template <>
+__device__ __forceinline__ float2* item_block<float2>(const ItemDev& d, int sel) {
+  return item_blk32(d, sel);
+}
+template <class C>
+__device__ __forceinline__ C* item_T(const ItemDev& d);
+template <>
+__device__ __forceinline__ double2* item_T<double2>(const ItemDev& d) { return d.T; }
+template <>
+__device__ __forceinline__ float2* item_T<float2>(const ItemDev& d) { return d.T32; }
+template <class C>
+__device__ __forceinline__ const real_t<C>* item_kin(const ItemDev& d);
+template <>
+__device__ __forceinline__ const double* item_kin<double2>(const ItemDev& d) { return d.kin; }
+template <>
+__device__ __forceinline__ const float* item_kin<float2>(const ItemDev& d) { return d.kin32; }
+template <class C>
+__device__ __forceinline__ const real_t<C>* item_vs(const ItemDev& d);
+template <>
+__device__ __forceinline__ const double* item_vs<double2>(const ItemDev& d) { return d.vs; }
+template <>
+__device__ __forceinline__ const float* item_vs<float2>(const ItemDev& d) { return d.vs32; }
+
+template <int N3, class C>
+__global__ void __launch_bounds__(kColThreads)
+kb_col_inv_reg(const ItemDev* __restrict__ D, int sel_in) {
+  constexpr int CT = kColThreads / lane_group(N3);
+  const ItemDev& d = D[blockIdx.z];
+  if ((int)blockIdx.y >= d.nb || (int)blockIdx.x * CT >= d.plan.ncols) return;
+  col_inv_reg_body<N3, C>(d.plan, tw_of<C>(d.plan.ax3), item_block<C>(d, sel_in), d.npw,
+                          item_T<C>(d), blockIdx.x, blockIdx.y);
+}
+
+template <int N3, class C>
+__global__ void __launch_bounds__(kColThreads)
+kb_col_fwd_reg(const ItemDev* __restrict__ D, int sel_in, int sel_out, int sel_prev, double alpha,
+               double beta, double gamma, int coef_step) {
+  constexpr int CT = kColThreads / lane_group(N3);
+  const ItemDev& d = D[blockIdx.z];
+  if ((int)blockIdx.y >= d.nb || (int)blockIdx.x * CT >= d.plan.ncols) return;
+  col_fwd_reg_body<N3, C>(d.plan, tw_of<C>(d.plan.ax3), item_T<C>(d), item_kin<C>(d),
+                          item_block<C>(d, sel_in), d.npw, item_block<C>(d, sel_prev), d.npw,
+                          item_block<C>(d, sel_out), d.npw, alpha, beta, gamma,
+                          coef_step >= 0 ? d.coef + 3 * coef_step : nullptr, blockIdx.x,
+                          blockIdx.y);
+}
+
+template <int N1, int N2, int GMAX, class C>
+__global__ void __launch_bounds__(kPlaneMaxThreads)
+kb_plane_reg(const ItemDev* __restrict__ D) {
+  const ItemDev& d = D[blockIdx.z];
+  if ((int)blockIdx.y >= d.nb || (int)blockIdx.x >= d.plan.n3) return;
+  plane_reg_body<N1, N2, GMAX, C>(d.plan, tw_of<C>(d.plan.ax1), tw_of<C>(d.plan.ax2),
+                                  item_vs<C>(d), item_T<C>(d), blockIdx.x, blockIdx.y);
 }
 
 size_t plane_reg_lds(const BoxPlan& p, size_t elem) {
@@ -330,6 +423,9 @@ hipError_t set_plane_lds(size_t bytes) {
     hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N, 16, C>,                \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
     if (e != hipSuccess) return e;                                                           \
+    e = hipFuncSetAttribute((const void*)kb_plane_reg<N, N, 16, C>,                          \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);         \
+    if (e != hipSuccess) return e;                                                           \
   }
   PW_FAST_SIZES(CASE)
 #undef CASE
@@ -337,6 +433,9 @@ hipError_t set_plane_lds(size_t bytes) {
   {                                                                                          \
     hipError_t e = hipFuncSetAttribute((const void*)k_plane_reg<N, N, 8, C>,                 \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
+    if (e != hipSuccess) return e;                                                           \
+    e = hipFuncSetAttribute((const void*)kb_plane_reg<N, N, 8, C>,                           \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);         \
     if (e != hipSuccess) return e;                                                           \
   }
   if constexpr (sizeof(C) == sizeof(double2)) {
@@ -349,6 +448,90 @@ hipError_t set_plane_lds(size_t bytes) {
 }
 
 }  // namespace
+
+namespace {
+template <class C>
+hipError_t fused_col_inv_reg(const FusedFft& f, const ItemDev* D, int sel_in, hipStream_t s) {
+#define CASE(N)                                                                             \
+  if (f.n3 == N) {                                                                          \
+    constexpr int CT = kColThreads / lane_group(N);                                         \
+    dim3 grid((f.ncols_max + CT - 1) / CT, f.nb_max, f.nitems);                             \
+    hipLaunchKernelGGL((kb_col_inv_reg<N, C>), grid, dim3(kColThreads), 0, s, D, sel_in);   \
+    return hipGetLastError();                                                               \
+  }
+  PW_FAST_SIZES(CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+template <class C>
+hipError_t fused_col_fwd_reg(const FusedFft& f, const ItemDev* D, int sel_in, int sel_out,
+                             int sel_prev, double alpha, double beta, double gamma, int coef_step,
+                             hipStream_t s) {
+#define CASE(N)                                                                              \
+  if (f.n3 == N) {                                                                           \
+    constexpr int CT = kColThreads / lane_group(N);                                          \
+    dim3 grid((f.ncols_max + CT - 1) / CT, f.nb_max, f.nitems);                              \
+    hipLaunchKernelGGL((kb_col_fwd_reg<N, C>), grid, dim3(kColThreads), 0, s, D, sel_in,      \
+                       sel_out, sel_prev, alpha, beta, gamma, coef_step);                     \
+    return hipGetLastError();                                                                \
+  }
+  PW_FAST_SIZES(CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+template <class C>
+hipError_t fused_plane_reg(const FusedFft& f, int variant, const ItemDev* D, hipStream_t s) {
+  BoxPlan shape{};
+  shape.n1 = f.n1;
+  shape.n2 = f.n2;
+  shape.n3 = f.n3;
+  shape.xr = f.xr_max;
+  const size_t lds = plane_reg_lds(shape, sizeof(C));
+  const int threads = plane_reg_threads(shape, variant == 1 ? 8 : 16);
+  dim3 grid(f.n3_max, f.nb_max, f.nitems);
+  if (variant == 1) {
+#define CASE(N)                                                                               \
+    if (f.n1 == N && f.n2 == N) {                                                             \
+      hipLaunchKernelGGL((kb_plane_reg<N, N, 8, C>), grid, dim3(threads), lds, s, D);         \
+      return hipGetLastError();                                                               \
+    }
+    if constexpr (sizeof(C) == sizeof(double2)) {
+      PW_NARROW_SIZES64(CASE)
+    } else {
+      PW_NARROW_SIZES32(CASE)
+    }
+#undef CASE
+    return hipErrorInvalidValue;
+  }
+#define CASE(N)                                                                               \
+  if (f.n1 == N && f.n2 == N) {                                                               \
+    hipLaunchKernelGGL((kb_plane_reg<N, N, 16, C>), grid, dim3(threads), lds, s, D);          \
+    return hipGetLastError();                                                                 \
+  }
+  PW_FAST_SIZES(CASE)
+#undef CASE
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_fused_col_inv_reg(const FusedFft& f, bool fp32, const ItemDev* D, int sel_in,
+                                    hipStream_t s) {
+  return fp32 ? fused_col_inv_reg<float2>(f, D, sel_in, s) : fused_col_inv_reg<double2>(f, D, sel_in, s);
+}
+hipError_t launch_fused_col_fwd_reg(const FusedFft& f, bool fp32, const ItemDev* D, int sel_in,
+                                    int sel_out, int sel_prev, double alpha, double beta,
+                                    double gamma, int coef_step, hipStream_t s) {
+  return fp32 ? fused_col_fwd_reg<float2>(f, D, sel_in, sel_out, sel_prev, alpha, beta, gamma,
+                                          coef_step, s)
+              : fused_col_fwd_reg<double2>(f, D, sel_in, sel_out, sel_prev, alpha, beta, gamma,
+                                           coef_step, s);
+}
+hipError_t launch_fused_plane_reg(const FusedFft& f, bool fp32, const ItemDev* D, hipStream_t s) {
+  return fp32 ? fused_plane_reg<float2>(f, f.plane_variant32, D, s)
+              : fused_plane_reg<double2>(f, f.plane_variant, D, s);
+}
 
 hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int64_t ldpsi, cplx* T,
                                   hipStream_t s) {

@@ -90,17 +90,18 @@ __device__ __forceinline__ void mfma_stage(const float2* As, int pa, const float
 
 // C = alpha A B + beta C; A m x k (lda), B k x n (ldb), complex64 column-major.
 template <int MODE>
-__global__ void __launch_bounds__(kThreads)
-k_gemm_nn32(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restrict__ A,
-            int64_t lda, const float2* __restrict__ B, int64_t ldb, float beta,
-            float2* __restrict__ C, int64_t ldc) {
+__device__ __forceinline__ void gemm_nn32_body(int64_t M, int64_t N, int64_t K, float alpha,
+                                               const float2* __restrict__ A, int64_t lda,
+                                               const float2* __restrict__ B, int64_t ldb,
+                                               float beta, float2* __restrict__ C, int64_t ldc,
+                                               int bx, int by) {
   constexpr int Kc = KC<MODE>::value;
   constexpr int PA = kBM, PB = kBN + 1;
   __shared__ float2 As[Kc * PA];
   __shared__ float2 Bs[Kc * PB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const int64_t i0 = (int64_t)blockIdx.y * kBM, j0 = (int64_t)blockIdx.x * kBN;
+  const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
   f4 ar[2][2], ai[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -168,19 +169,28 @@ k_gemm_nn32(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restri
       }
 }
 
-// Partial (split z over K) A^H B; A k x m (lda), B k x n (ldb); out ld = M.
 template <int MODE>
 __global__ void __launch_bounds__(kThreads)
-k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __restrict__ A,
-            int64_t lda, const float2* __restrict__ B, int64_t ldb, float2* __restrict__ out) {
+k_gemm_nn32(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restrict__ A,
+            int64_t lda, const float2* __restrict__ B, int64_t ldb, float beta,
+            float2* __restrict__ C, int64_t ldc) {
+  gemm_nn32_body<MODE>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
+}
+
+// Partial (split z over K) A^H B; A k x m (lda), B k x n (ldb); out ld = M.
+template <int MODE>
+__device__ __forceinline__ void gemm_cn32_body(int64_t M, int64_t N, int64_t K, int64_t ksplit,
+                                               const float2* __restrict__ A, int64_t lda,
+                                               const float2* __restrict__ B, int64_t ldb,
+                                               float2* __restrict__ out, int bx, int by, int bz) {
   constexpr int Kc = KC<MODE>::value;
   constexpr int PA = kBM + 1, PB = kBN + 1;
   __shared__ float2 As[Kc * PA];
   __shared__ float2 Bs[Kc * PB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const int64_t i0 = (int64_t)blockIdx.y * kBM, j0 = (int64_t)blockIdx.x * kBN;
-  const int64_t kb = (int64_t)blockIdx.z * ksplit;
+  const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
+  const int64_t kb = (int64_t)bz * ksplit;
   const int64_t ke = min(K, kb + ksplit);
   f4 ar[2][2], ai[2][2];
 #pragma unroll
@@ -228,7 +238,7 @@ k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __res
     mfma_stage<MODE, true>(As, PA, Bs, PB, wi, wj, lane, ar, ai);
     __syncthreads();
   }
-  float2* o = out + (int64_t)blockIdx.z * M * N;
+  float2* o = out + (int64_t)bz * M * N;
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
@@ -242,13 +252,21 @@ k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __res
       }
 }
 
+template <int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __restrict__ A,
+            int64_t lda, const float2* __restrict__ B, int64_t ldb, float2* __restrict__ out) {
+  gemm_cn32_body<MODE>(M, N, K, ksplit, A, lda, B, ldb, out, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M] (FP64 sum, fixed order), rounded.
-__global__ void k_splitk_reduce32(int64_t M, int64_t N, int nsplit, const float2* __restrict__ work,
-                                  double alpha, const double* __restrict__ alpha_dev,
-                                  const double* __restrict__ rowscale, float2* __restrict__ C,
-                                  int64_t ldc) {
+__device__ __forceinline__ void splitk_reduce32_body(int64_t M, int64_t N, int nsplit,
+                                                     const float2* __restrict__ work, double alpha,
+                                                     const double* __restrict__ alpha_dev,
+                                                     const double* __restrict__ rowscale,
+                                                     float2* __restrict__ C, int64_t ldc, int bx) {
   if (alpha_dev) alpha = alpha_dev[0];
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = (int64_t)bx * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const int64_t j = idx / M, i = idx - j * M;
   double re = 0.0, im = 0.0;
@@ -261,25 +279,67 @@ __global__ void k_splitk_reduce32(int64_t M, int64_t N, int nsplit, const float2
   C[i + j * ldc] = make_float2((float)(s * re), (float)(s * im));
 }
 
+__global__ void k_splitk_reduce32(int64_t M, int64_t N, int nsplit, const float2* __restrict__ work,
+                                  double alpha, const double* __restrict__ alpha_dev,
+                                  const double* __restrict__ rowscale, float2* __restrict__ C,
+                                  int64_t ldc) {
+  splitk_reduce32_body(M, N, nsplit, work, alpha, alpha_dev, rowscale, C, ldc, blockIdx.x);
+}
+
 struct SplitPlan {
   int64_t tiles_m, tiles_n, nsplit, ksplit;
 };
 
 template <int MODE>
-SplitPlan split_plan32(int64_t m, int64_t n, int64_t k, int target) {
+__host__ __device__ inline SplitPlan split_plan32(int64_t m, int64_t n, int64_t k, int target) {
   constexpr int Kc = KC<MODE>::value;
   SplitPlan p;
   p.tiles_m = (m + kBM - 1) / kBM;
   p.tiles_n = (n + kBN - 1) / kBN;
   const int64_t tiles = p.tiles_m * p.tiles_n;
   int64_t want = (target + tiles - 1) / tiles;
-  const int64_t maxs = std::max<int64_t>(1, (k + Kc * 8 - 1) / (Kc * 8));
-  want = std::max<int64_t>(1, std::min(want, maxs));
+  const int64_t maxs = (k + Kc * 8 - 1) / (Kc * 8) > 1 ? (k + Kc * 8 - 1) / (Kc * 8) : 1;
+  want = want < maxs ? want : maxs;
+  if (want < 1) want = 1;
   int64_t ks = (k + want - 1) / want;
   ks = ((ks + Kc - 1) / Kc) * Kc;
-  p.ksplit = std::max<int64_t>(ks, Kc);
-  p.nsplit = std::max<int64_t>(1, (k + p.ksplit - 1) / p.ksplit);
+  p.ksplit = ks > Kc ? ks : Kc;
+  p.nsplit = (k + p.ksplit - 1) / p.ksplit;
+  if (p.nsplit < 1) p.nsplit = 1;
   return p;
+}
+
+// ---- fused-batch products (FP32 / bf16 operands): P^H X into work32, reduced into
+// cprj32; X += P cprj32
+template <int MODE>
+__global__ void __launch_bounds__(kThreads)
+kb_gemm_cn32(const ItemDev* __restrict__ D, int sel_b, int nsplit_max) {
+  const int item = blockIdx.z / nsplit_max, zs = blockIdx.z - item * nsplit_max;
+  const ItemDev& d = D[item];
+  if (d.nproj <= 0) return;
+  const SplitPlan p = split_plan32<MODE>(d.nproj, d.nb, d.npw, d.gemm_target);
+  if (zs >= p.nsplit || (int64_t)blockIdx.y >= p.tiles_m || (int64_t)blockIdx.x >= p.tiles_n) return;
+  gemm_cn32_body<MODE>(d.nproj, d.nb, d.npw, p.ksplit, d.proj32, d.npw, item_blk32(d, sel_b), d.npw,
+                       d.work32, blockIdx.x, blockIdx.y, zs);
+}
+
+template <int MODE>
+__global__ void kb_splitk_reduce32(const ItemDev* __restrict__ D, double alpha, int coef_step) {
+  const ItemDev& d = D[blockIdx.y];
+  if (d.nproj <= 0) return;
+  const SplitPlan p = split_plan32<MODE>(d.nproj, d.nb, d.npw, d.gemm_target);
+  const double* alpha_dev = coef_step >= 0 ? d.coef + 3 * coef_step : nullptr;
+  splitk_reduce32_body(d.nproj, d.nb, (int)p.nsplit, d.work32, alpha, alpha_dev, d.ekb, d.cprj32,
+                       d.nproj, blockIdx.x);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kThreads)
+kb_gemm_nn32(const ItemDev* __restrict__ D, int sel_c) {
+  const ItemDev& d = D[blockIdx.z];
+  if (d.nproj <= 0 || (int64_t)blockIdx.y * kBM >= d.npw || (int64_t)blockIdx.x * kBN >= d.nb) return;
+  gemm_nn32_body<MODE>(d.npw, d.nb, d.nproj, 1.f, d.proj32, d.npw, d.cprj32, d.nproj, 1.f,
+                       item_blk32(d, sel_c), d.npw, blockIdx.x, blockIdx.y);
 }
 
 }  // namespace
@@ -324,5 +384,41 @@ hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double al
   else
     hipLaunchKernelGGL(k_gemm_nn32<MODE_F32>, grid, dim3(kThreads), 0, s, m, n, k, (float)alpha, A,
                        lda, B, ldb, (float)beta, C, ldc);
+  return hipGetLastError();
+}
+
+int fused_cn32_nsplit(int bf16, int64_t npw, int64_t nb, int64_t nproj, int target) {
+  const SplitPlan p = bf16 ? split_plan32<MODE_BF16>(nproj, nb, npw, target)
+                           : split_plan32<MODE_F32>(nproj, nb, npw, target);
+  return (int)p.nsplit;
+}
+
+hipError_t launch_fused_gemm_cn32(int bf16, int nitems, int64_t m_max, int64_t n_max,
+                                  int nsplit_max, const ItemDev* D, int sel_b, double alpha,
+                                  int coef_step, hipStream_t s) {
+  if (nitems <= 0 || m_max <= 0 || n_max <= 0) return hipSuccess;
+  dim3 grid((n_max + kBN - 1) / kBN, (m_max + kBM - 1) / kBM, nitems * nsplit_max);
+  if (bf16)
+    hipLaunchKernelGGL(kb_gemm_cn32<MODE_BF16>, grid, dim3(kThreads), 0, s, D, sel_b, nsplit_max);
+  else
+    hipLaunchKernelGGL(kb_gemm_cn32<MODE_F32>, grid, dim3(kThreads), 0, s, D, sel_b, nsplit_max);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 rgrid((m_max * n_max + 255) / 256, nitems);
+  if (bf16)
+    hipLaunchKernelGGL(kb_splitk_reduce32<MODE_BF16>, rgrid, dim3(256), 0, s, D, alpha, coef_step);
+  else
+    hipLaunchKernelGGL(kb_splitk_reduce32<MODE_F32>, rgrid, dim3(256), 0, s, D, alpha, coef_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_gemm_nn32(int bf16, int nitems, int64_t m_max, int64_t n_max,
+                                  const ItemDev* D, int sel_c, hipStream_t s) {
+  if (nitems <= 0 || m_max <= 0 || n_max <= 0) return hipSuccess;
+  dim3 grid((n_max + kBN - 1) / kBN, (m_max + kBM - 1) / kBM, nitems);
+  if (bf16)
+    hipLaunchKernelGGL(kb_gemm_nn32<MODE_BF16>, grid, dim3(kThreads), 0, s, D, sel_c);
+  else
+    hipLaunchKernelGGL(kb_gemm_nn32<MODE_F32>, grid, dim3(kThreads), 0, s, D, sel_c);
   return hipGetLastError();
 }

@@ -32,14 +32,15 @@ __device__ __forceinline__ void cmfma(d4& re, d4& im, double ar, double ai, doub
 }
 
 // C = alpha A B + beta C; A m x k (lda), B k x n (ldb), column-major.
-__global__ void __launch_bounds__(kThreads)
-k_gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict__ A, int64_t lda,
-          const cplx* __restrict__ B, int64_t ldb, double beta, cplx* __restrict__ C, int64_t ldc) {
+__device__ __forceinline__ void gemm_nn_body(int64_t M, int64_t N, int64_t K, double alpha,
+                                             const cplx* __restrict__ A, int64_t lda,
+                                             const cplx* __restrict__ B, int64_t ldb, double beta,
+                                             cplx* __restrict__ C, int64_t ldc, int bx, int by) {
   __shared__ cplx As[kKcNN][kBM];
   __shared__ cplx Bs[kKcNN][kBN + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const int64_t i0 = (int64_t)blockIdx.y * kBM, j0 = (int64_t)blockIdx.x * kBN;
+  const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
   d4 accr[2][2], acci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -121,20 +122,28 @@ k_gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict_
       }
 }
 
+__global__ void __launch_bounds__(kThreads)
+k_gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict__ A, int64_t lda,
+          const cplx* __restrict__ B, int64_t ldb, double beta, cplx* __restrict__ C, int64_t ldc) {
+  gemm_nn_body(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
+}
+
 // Partial or final C = alpha diag(rowscale) A^H B over K range [kb, ke) of split z.
 // A k x m (lda), B k x n (ldb).  Output at out + z*zstride, leading dim ldo.
-__global__ void __launch_bounds__(kThreads)
-k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
-          const double* __restrict__ alpha_dev, const double* __restrict__ rowscale,
-          const cplx* __restrict__ A, int64_t lda, const cplx* __restrict__ B, int64_t ldb,
-          double beta, cplx* __restrict__ out, int64_t ldo, int64_t zstride) {
+__device__ __forceinline__ void gemm_cn_body(int64_t M, int64_t N, int64_t K, int64_t ksplit,
+                                             double alpha, const double* __restrict__ alpha_dev,
+                                             const double* __restrict__ rowscale,
+                                             const cplx* __restrict__ A, int64_t lda,
+                                             const cplx* __restrict__ B, int64_t ldb, double beta,
+                                             cplx* __restrict__ out, int64_t ldo, int64_t zstride,
+                                             int bx, int by, int bz) {
   if (alpha_dev) alpha = alpha_dev[0];
   __shared__ cplx As[kKcCN][kBM + 1];
   __shared__ cplx Bs[kKcCN][kBN + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const int64_t i0 = (int64_t)blockIdx.y * kBM, j0 = (int64_t)blockIdx.x * kBN;
-  const int64_t kb = (int64_t)blockIdx.z * ksplit;
+  const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
+  const int64_t kb = (int64_t)bz * ksplit;
   const int64_t ke = min(K, kb + ksplit);
   d4 accr[2][2], acci[2][2];
 #pragma unroll
@@ -196,7 +205,7 @@ k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
     }
     __syncthreads();
   }
-  cplx* o = out + (int64_t)blockIdx.z * zstride;
+  cplx* o = out + (int64_t)bz * zstride;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -218,13 +227,24 @@ k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
       }
 }
 
+__global__ void __launch_bounds__(kThreads)
+k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
+          const double* __restrict__ alpha_dev, const double* __restrict__ rowscale,
+          const cplx* __restrict__ A, int64_t lda, const cplx* __restrict__ B, int64_t ldb,
+          double beta, cplx* __restrict__ out, int64_t ldo, int64_t zstride) {
+  gemm_cn_body(M, N, K, ksplit, alpha, alpha_dev, rowscale, A, lda, B, ldb, beta, out, ldo, zstride,
+               blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M], z in fixed order.
-__global__ void k_splitk_reduce(int64_t M, int64_t N, int nsplit, const cplx* __restrict__ work,
-                                double alpha, const double* __restrict__ alpha_dev,
-                                const double* __restrict__ rowscale, double beta,
-                                cplx* __restrict__ C, int64_t ldc) {
+__device__ __forceinline__ void splitk_reduce_body(int64_t M, int64_t N, int nsplit,
+                                                   const cplx* __restrict__ work, double alpha,
+                                                   const double* __restrict__ alpha_dev,
+                                                   const double* __restrict__ rowscale,
+                                                   double beta, cplx* __restrict__ C, int64_t ldc,
+                                                   int bx) {
   if (alpha_dev) alpha = alpha_dev[0];
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = (int64_t)bx * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const int64_t j = idx / M, i = idx - j * M;
   double re = 0.0, im = 0.0;
@@ -243,24 +263,121 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int nsplit, const cplx* __
   C[i + j * ldc] = v;
 }
 
+__global__ void k_splitk_reduce(int64_t M, int64_t N, int nsplit, const cplx* __restrict__ work,
+                                double alpha, const double* __restrict__ alpha_dev,
+                                const double* __restrict__ rowscale, double beta,
+                                cplx* __restrict__ C, int64_t ldc) {
+  splitk_reduce_body(M, N, nsplit, work, alpha, alpha_dev, rowscale, beta, C, ldc, blockIdx.x);
+}
+
 struct SplitPlan {
   int64_t tiles_m, tiles_n, nsplit, ksplit;
 };
 
-SplitPlan split_plan(int64_t m, int64_t n, int64_t k, int target) {
+__host__ __device__ inline SplitPlan split_plan(int64_t m, int64_t n, int64_t k, int target) {
   SplitPlan p;
   p.tiles_m = (m + kBM - 1) / kBM;
   p.tiles_n = (n + kBN - 1) / kBN;
   const int64_t tiles = p.tiles_m * p.tiles_n;
   int64_t want = (target + tiles - 1) / tiles;
-  const int64_t maxs = std::max<int64_t>(1, (k + kKcCN * 8 - 1) / (kKcCN * 8));
-  want = std::max<int64_t>(1, std::min(want, maxs));
+  const int64_t maxs = (k + kKcCN * 8 - 1) / (kKcCN * 8) > 1 ? (k + kKcCN * 8 - 1) / (kKcCN * 8) : 1;
+  want = want < maxs ? want : maxs;
+  if (want < 1) want = 1;
   int64_t ks = (k + want - 1) / want;
   ks = ((ks + kKcCN - 1) / kKcCN) * kKcCN;
-  p.ksplit = std::max<int64_t>(ks, kKcCN);
+  p.ksplit = ks > kKcCN ? ks : kKcCN;
   p.nsplit = (k + p.ksplit - 1) / p.ksplit;
   if (p.nsplit < 1) p.nsplit = 1;
   return p;
+}
+
+// ---- fused-batch products (item from the launch's z or y coordinate)
+struct CnArgs {
+  int64_t M, N, K;
+  const cplx* A;
+  int64_t lda;
+  const cplx* B;
+  int64_t ldb;
+  cplx* C;
+  int64_t ldc;
+  const double* rowscale;
+  int target;
+};
+
+__device__ __forceinline__ CnArgs fused_cn_args(const ItemDev& d, int op, int sel_b) {
+  CnArgs a;
+  a.B = item_blk64(d, sel_b);
+  a.ldb = d.npw;
+  a.K = d.npw;
+  a.lda = d.npw;
+  if (op == GOP_PROJ) {
+    a.M = d.nproj;
+    a.N = d.nb;
+    a.A = d.proj;
+    a.C = d.cprj;
+    a.ldc = d.nproj;
+    a.rowscale = d.ekb;
+    a.target = d.gemm_target;
+  } else {
+    a.M = d.nb;
+    a.N = d.nb;
+    a.A = d.y;
+    a.C = d.sub0;
+    a.ldc = d.nb;
+    a.rowscale = nullptr;
+    a.target = kTargetBlocks;
+  }
+  return a;
+}
+
+__global__ void __launch_bounds__(kThreads)
+kb_gemm_cn(const ItemDev* __restrict__ D, int op, int sel_b, double alpha, int coef_step,
+           int nsplit_max) {
+  const int item = blockIdx.z / nsplit_max, zs = blockIdx.z - item * nsplit_max;
+  const ItemDev& d = D[item];
+  const CnArgs a = fused_cn_args(d, op, sel_b);
+  if (a.M <= 0 || a.N <= 0) return;
+  const SplitPlan p = split_plan(a.M, a.N, a.K, a.target);
+  if (zs >= p.nsplit || (int64_t)blockIdx.y >= p.tiles_m || (int64_t)blockIdx.x >= p.tiles_n) return;
+  const double* alpha_dev = coef_step >= 0 ? d.coef + 3 * coef_step : nullptr;
+  if (p.nsplit == 1)
+    gemm_cn_body(a.M, a.N, a.K, p.ksplit, alpha, alpha_dev, a.rowscale, a.A, a.lda, a.B, a.ldb, 0.0,
+                 a.C, a.ldc, 0, blockIdx.x, blockIdx.y, 0);
+  else
+    gemm_cn_body(a.M, a.N, a.K, p.ksplit, 1.0, nullptr, nullptr, a.A, a.lda, a.B, a.ldb, 0.0,
+                 d.gemm_work, a.M, a.M * a.N, blockIdx.x, blockIdx.y, zs);
+}
+
+__global__ void kb_splitk_reduce(const ItemDev* __restrict__ D, int op, int sel_b, double alpha,
+                                 int coef_step) {
+  const ItemDev& d = D[blockIdx.y];
+  const CnArgs a = fused_cn_args(d, op, sel_b);
+  if (a.M <= 0 || a.N <= 0) return;
+  const SplitPlan p = split_plan(a.M, a.N, a.K, a.target);
+  if (p.nsplit == 1) return;
+  const double* alpha_dev = coef_step >= 0 ? d.coef + 3 * coef_step : nullptr;
+  splitk_reduce_body(a.M, a.N, (int)p.nsplit, d.gemm_work, alpha, alpha_dev, a.rowscale, 0.0, a.C,
+                     a.ldc, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kThreads)
+kb_gemm_nn(const ItemDev* __restrict__ D, int op, int sel_a, int sel_c) {
+  const ItemDev& d = D[blockIdx.z];
+  int64_t M = d.npw, N = d.nb, K;
+  const cplx* A;
+  const cplx* B;
+  int64_t ldb;
+  cplx* C;
+  double beta;
+  if (op == GOP_NONLOCAL) {
+    K = d.nproj; A = d.proj; B = d.cprj; ldb = d.nproj; C = item_blk64(d, sel_c); beta = 1.0;
+  } else if (op == GOP_TRSM) {
+    K = d.nb; A = d.y; B = d.dinv; ldb = d.nb; C = d.blk; beta = 0.0;
+  } else {
+    K = d.nb; A = item_blk64(d, sel_a); B = d.sub1; ldb = d.nb; C = d.blk; beta = 0.0;
+  }
+  if (K <= 0 || (int64_t)blockIdx.y * kBM >= M || (int64_t)blockIdx.x * kBN >= N) return;
+  gemm_nn_body(M, N, K, 1.0, A, d.npw, B, ldb, beta, C, d.npw, blockIdx.x, blockIdx.y);
 }
 
 }  // namespace
@@ -302,5 +419,33 @@ hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const c
   dim3 grid((n + kBN - 1) / kBN, (m + kBM - 1) / kBM, 1);
   hipLaunchKernelGGL(k_gemm_nn, grid, dim3(kThreads), 0, s, m, n, k, alpha, A, lda, B, ldb, beta,
                      C, ldc);
+  return hipGetLastError();
+}
+
+int fused_cn_nsplit(int op, int64_t npw, int64_t nb, int64_t nproj, int target) {
+  const SplitPlan p = op == GOP_PROJ ? split_plan(nproj, nb, npw, target)
+                                     : split_plan(nb, nb, npw, kTargetBlocks);
+  return (int)p.nsplit;
+}
+
+hipError_t launch_fused_gemm_cn(int nitems, int64_t m_max, int64_t n_max, int nsplit_max,
+                                const ItemDev* D, int op, int sel_b, double alpha, int coef_step,
+                                hipStream_t s) {
+  if (nitems <= 0 || m_max <= 0 || n_max <= 0) return hipSuccess;
+  dim3 grid((n_max + kBN - 1) / kBN, (m_max + kBM - 1) / kBM, nitems * nsplit_max);
+  hipLaunchKernelGGL(kb_gemm_cn, grid, dim3(kThreads), 0, s, D, op, sel_b, alpha, coef_step,
+                     nsplit_max);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nsplit_max == 1) return e;
+  dim3 rgrid((m_max * n_max + 255) / 256, nitems);
+  hipLaunchKernelGGL(kb_splitk_reduce, rgrid, dim3(256), 0, s, D, op, sel_b, alpha, coef_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_gemm_nn(int nitems, int64_t m_max, int64_t n_max, const ItemDev* D, int op,
+                                int sel_a, int sel_c, hipStream_t s) {
+  if (nitems <= 0 || m_max <= 0 || n_max <= 0) return hipSuccess;
+  dim3 grid((n_max + kBN - 1) / kBN, (m_max + kBM - 1) / kBM, nitems);
+  hipLaunchKernelGGL(kb_gemm_nn, grid, dim3(kThreads), 0, s, D, op, sel_a, sel_c);
   return hipGetLastError();
 }

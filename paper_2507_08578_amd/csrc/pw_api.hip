@@ -113,6 +113,16 @@ struct pw_batch {
   hipGraphExec_t exec = nullptr;
   std::vector<hipGraph_t> sgraph;    // mode 2: one graph per stream
   std::vector<hipGraphExec_t> sexec;
+  struct Group {                     // mode 3: items fused per box, one launch per stage
+    FusedFft f{};
+    ItemDev* D = nullptr;            // device descriptors of the group's items
+    int nitems = 0, nb_max = 0, nproj_max = 0;
+    int64_t npw_max = 0, npw_nb_max = 0;
+    int nsplit_proj = 1, nsplit_gram = 1, nsplit_proj32 = 1;
+  };
+  std::vector<Group> groups;
+  hipGraph_t fgraph = nullptr;
+  hipGraphExec_t fexec = nullptr;
   std::vector<void*> allocs;
   int* flags_dev = nullptr;         // 4 per item
   int* flags_host = nullptr;        // pinned copy
@@ -468,6 +478,204 @@ pw_status batch_issue(pw_batch* b, bool filter, bool capturing) {
   if ((st = batch_fork(b)) != PW_OK) return st;
   for (size_t k = 0; k < b->streams.size(); ++k)
     if ((st = batch_issue_stream(b, k, filter, capturing)) != PW_OK) return st;
+  return batch_join(b);
+}
+
+// ---- fused mode: items grouped by box, every stage one launch per group ----
+// Builds the groups and their device descriptors (once).
+pw_status fused_setup(pw_batch* b) {
+  pw_ctx* c = b->ctx;
+  if (!b->groups.empty()) return PW_OK;
+  std::map<std::vector<int>, std::vector<int>> bybox;
+  for (size_t i = 0; i < b->items.size(); ++i) {
+    const pw_ham* h = b->items[i].h;
+    if (h->chunk_alloc < b->items[i].nb)
+      return fail(c, PW_ERR_UNSUPPORTED,
+                  "fused batch: item " + std::to_string(i) + " FFT buffer holds fewer than nb bands");
+    // items share a group when they use the same FFT kernels (register
+    // kernels are compiled per length; the generic ones take any box)
+    const bool rc = h->reg_col_ok, rp = h->reg_plane_ok;
+    bybox[{rc ? h->plan.n3 : -1, rp ? h->plan.n1 : -1, rp ? h->plan.n2 : -1}].push_back((int)i);
+  }
+  for (auto& kv : bybox) {
+    pw_batch::Group g;
+    const std::vector<int>& ids = kv.second;
+    const pw_ham* h0 = b->items[ids[0]].h;
+    FusedFft& f = g.f;
+    f.n1 = h0->plan.n1;
+    f.n2 = h0->plan.n2;
+    f.n3 = h0->plan.n3;
+    f.nitems = (int)ids.size();
+    f.reg_col = h0->reg_col_ok;
+    f.reg_plane = h0->reg_plane_ok;
+    f.plane_variant = 0;
+    f.plane_variant32 = 0;
+    f.col_lds = 0;
+    f.plane_lds = 0;
+    f.col_blocks = 0;
+    f.nb_max = f.ncols_max = f.xr_max = f.n3_max = 0;
+    for (int i : ids) {
+      const pw_ham* h = b->items[i].h;
+      f.nb_max = std::max<int>(f.nb_max, (int)b->items[i].nb);
+      f.ncols_max = std::max(f.ncols_max, h->plan.ncols);
+      f.xr_max = std::max(f.xr_max, h->plan.xr);
+      f.n3_max = std::max(f.n3_max, h->plan.n3);
+      f.col_blocks = std::max(f.col_blocks, (h->plan.ncols + h->cfg.col_tile - 1) / h->cfg.col_tile);
+      f.col_lds = std::max(f.col_lds, h->cfg.col_lds);
+      f.plane_lds = std::max(f.plane_lds, h->cfg.plane_lds);
+      g.nproj_max = std::max<int>(g.nproj_max, (int)h->nproj);
+      g.npw_max = std::max(g.npw_max, h->npw);
+      g.npw_nb_max = std::max(g.npw_nb_max, h->npw * b->items[i].nb);
+      g.nsplit_proj = std::max(g.nsplit_proj,
+                               fused_cn_nsplit(GOP_PROJ, h->npw, b->items[i].nb, h->nproj,
+                                               h->gemm_target));
+      g.nsplit_gram = std::max(g.nsplit_gram,
+                               fused_cn_nsplit(GOP_GRAM, h->npw, b->items[i].nb, h->nproj,
+                                               h->gemm_target));
+      if (b->prec != PW_FP64)
+        g.nsplit_proj32 = std::max(g.nsplit_proj32,
+                                   fused_cn32_nsplit(b->prec == PW_BF16, h->npw, b->items[i].nb,
+                                                     h->nproj, h->gemm_target));
+    }
+    g.nitems = f.nitems;
+    g.nb_max = f.nb_max;
+    std::vector<ItemDev> host(ids.size());
+    for (size_t q = 0; q < ids.size(); ++q) {
+      const BatchItem& it = b->items[ids[q]];
+      const pw_ham* h = it.h;
+      ItemDev& d = host[q];
+      d.plan = h->plan;
+      d.npw = (int)h->npw;
+      d.nb = (int)it.nb;
+      d.nproj = (int)h->nproj;
+      d.gemm_target = h->gemm_target;
+      d.col_tile = h->cfg.col_tile;
+      d.plane_rows = h->cfg.plane_rows;
+      d.y = it.y;
+      d.hy = it.hy;
+      d.blk = h->blk;
+      d.b32[0] = h->blk32[0];
+      d.b32[1] = h->blk32[1];
+      d.T = h->T;
+      d.T32 = h->T32;
+      d.kin = h->kin;
+      d.vs = h->vscaled;
+      d.kin32 = h->kin32;
+      d.vs32 = h->vs32;
+      d.proj = h->proj;
+      d.proj32 = h->proj32;
+      d.ekb = h->ekb_dev;
+      d.cprj = h->cprj;
+      d.cprj32 = h->cprj32;
+      d.gemm_work = h->gemm_work;
+      d.work32 = h->work32;
+      d.sub0 = h->sub0;
+      d.sub1 = h->sub1;
+      d.dinv = h->dinv;
+      d.dtol = h->dtol;
+      d.status = h->status_dev;
+      d.eig = it.eig;
+      d.resid = it.resid;
+      d.coef = it.coef;
+      d.upper = it.upper;
+      d.flags = it.flags;
+      d.sweeps = it.sweeps;
+    }
+    void* dev = nullptr;
+    hipError_t e = hipMalloc(&dev, host.size() * sizeof(ItemDev));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, PW_ERR_OOM, "fused batch: descriptor allocation failed");
+    }
+    b->allocs.push_back(dev);
+    HIPCHK(c, hipMemcpy(dev, host.data(), host.size() * sizeof(ItemDev), hipMemcpyHostToDevice));
+    g.D = static_cast<ItemDev*>(dev);
+    b->groups.push_back(g);
+  }
+  return PW_OK;
+}
+
+// One fused H application: out = alpha (H in) + beta in + gamma prev.
+pw_status fused_apply(pw_ctx* c, const pw_batch::Group& g, int prec, int in, int out, int prev,
+                      double alpha, double beta, double gamma, int coef_step, hipStream_t s) {
+  const bool lp = prec != PW_FP64;
+  const int bf16 = prec == PW_BF16;
+  if (g.nproj_max > 0) {
+    if (lp)
+      HIPCHK(c, launch_fused_gemm_cn32(bf16, g.nitems, g.nproj_max, g.nb_max, g.nsplit_proj32, g.D,
+                                       in, alpha, coef_step, s));
+    else
+      HIPCHK(c, launch_fused_gemm_cn(g.nitems, g.nproj_max, g.nb_max, g.nsplit_proj, g.D, GOP_PROJ,
+                                     in, alpha, coef_step, s));
+  }
+  HIPCHK(c, launch_fused_col_inv(g.f, lp, g.D, in, s));
+  HIPCHK(c, launch_fused_plane(g.f, lp, g.D, s));
+  HIPCHK(c, launch_fused_col_fwd(g.f, lp, g.D, in, out, prev, alpha, beta, gamma, coef_step, s));
+  if (g.nproj_max > 0) {
+    if (lp) HIPCHK(c, launch_fused_gemm_nn32(bf16, g.nitems, g.npw_max, g.nb_max, g.D, out, s));
+    else HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_NONLOCAL, 0, out, s));
+  }
+  return PW_OK;
+}
+
+// One iteration (filter, Cholesky, Rayleigh-Ritz) of every item of a group.
+pw_status fused_iteration(pw_batch* b, const pw_batch::Group& g, hipStream_t s) {
+  pw_ctx* c = b->ctx;
+  const int m = b->degree;
+  const int64_t ew = g.npw_nb_max;
+  pw_status st;
+  HIPCHK(c, launch_fused_dense(FS_CHEB_COEF, g.nitems, ew, g.nb_max, g.D, m, 0, s));
+  if (b->prec == PW_FP64) {
+    const int buf[2] = {SEL_Y, SEL_BLK};
+    HIPCHK(c, launch_fused_dense(FS_FILTER_FIRST, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+    for (int i = 2; i <= m; ++i) {
+      const int cur = buf[(i - 1) & 1], nxt = buf[i & 1];
+      if ((st = fused_apply(c, g, PW_FP64, cur, nxt, nxt, 0.0, 0.0, 0.0, i - 1, s)) != PW_OK)
+        return st;
+    }
+    if (m & 1) HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_Y, s));
+  } else {
+    const int buf[2] = {SEL_B32A, SEL_B32B};
+    HIPCHK(c, launch_fused_dense(FS_TO_F32, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+    HIPCHK(c, launch_fused_dense(FS_FILTER_FIRST, g.nitems, ew, g.nb_max, g.D, 1, 0, s));
+    for (int i = 2; i <= m; ++i) {
+      const int cur = buf[(i - 1) & 1], nxt = buf[i & 1];
+      if ((st = fused_apply(c, g, b->prec, cur, nxt, nxt, 0.0, 0.0, 0.0, i - 1, s)) != PW_OK)
+        return st;
+    }
+    HIPCHK(c, launch_fused_dense(FS_TO_F64, g.nitems, ew, g.nb_max, g.D, buf[m & 1], 0, s));
+  }
+  // Cholesky orthonormalisation (one diagonal block: nb <= 64)
+  HIPCHK(c, launch_fused_gemm_cn(g.nitems, g.nb_max, g.nb_max, g.nsplit_gram, g.D, GOP_GRAM, SEL_Y,
+                                 1.0, -1, s));
+  HIPCHK(c, launch_fused_dense(FS_HERMITIZE, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  HIPCHK(c, launch_fused_dense(FS_CHOL_INIT, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  HIPCHK(c, launch_fused_dense(FS_CHOL_DIAG, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_TRSM, 0, 0, s));
+  HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_Y, s));
+  // Rayleigh-Ritz, FP64
+  if ((st = fused_apply(c, g, PW_FP64, SEL_Y, SEL_HY, SEL_NONE, 1.0, 0.0, 0.0, -1, s)) != PW_OK)
+    return st;
+  HIPCHK(c, launch_fused_gemm_cn(g.nitems, g.nb_max, g.nb_max, g.nsplit_gram, g.D, GOP_GRAM, SEL_HY,
+                                 1.0, -1, s));
+  HIPCHK(c, launch_fused_dense(FS_HERMITIZE, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  HIPCHK(c, launch_fused_dense(FS_JACOBI, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_ROT, SEL_Y, 0, s));
+  HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_Y, s));
+  HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_ROT, SEL_HY, 0, s));
+  HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_HY, s));
+  HIPCHK(c, launch_fused_dense(FS_RESIDUALS, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  HIPCHK(c, launch_fused_dense(FS_FLAGS, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  return PW_OK;
+}
+
+// All groups, forked over the batch streams and joined back.
+pw_status fused_issue(pw_batch* b) {
+  pw_status st;
+  if ((st = batch_fork(b)) != PW_OK) return st;
+  for (size_t gi = 0; gi < b->groups.size(); ++gi)
+    if ((st = fused_iteration(b, b->groups[gi], b->streams[gi % b->streams.size()])) != PW_OK)
+      return st;
   return batch_join(b);
 }
 
@@ -1244,6 +1452,8 @@ pw_status pw_batch_destroy(pw_batch* b) {
   for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->fexec) (void)hipGraphExecDestroy(b->fexec);
+  if (b->fgraph) (void)hipGraphDestroy(b->fgraph);
   for (hipGraphExec_t e : b->sexec)
     if (e) (void)hipGraphExecDestroy(e);
   for (hipGraph_t g : b->sgraph)
@@ -1383,8 +1593,8 @@ pw_status pw_batch_start(pw_batch* b) {
 pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
   if (!b) return fail(nullptr, PW_ERR_INVALID_ARG, "batch is NULL");
   if (iters < 0) return fail(b->ctx, PW_ERR_INVALID_ARG, "iters < 0");
-  if (use_graph < 0 || use_graph > 2)
-    return fail(b->ctx, PW_ERR_INVALID_ARG, "use_graph must be 0, 1 or 2");
+  if (use_graph < 0 || use_graph > 3)
+    return fail(b->ctx, PW_ERR_INVALID_ARG, "use_graph must be 0, 1, 2 or 3");
   pw_ctx* c = b->ctx;
   pw_status st;
   if ((st = batch_enter(b)) != PW_OK) return st;
@@ -1420,8 +1630,27 @@ pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
       HIPCHK(c, hipGraphInstantiateWithFlags(&b->sexec[k], g, 0));
     }
   }
+  if (use_graph == 3 && !b->fexec) {
+    if ((st = fused_setup(b)) != PW_OK) return st;
+    HIPCHK(c, hipStreamBeginCapture(b->s0, hipStreamCaptureModeThreadLocal));
+    st = fused_issue(b);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->s0, &g);
+    if (st != PW_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(c, PW_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    b->fgraph = g;
+    HIPCHK(c, hipGraphInstantiateWithFlags(&b->fexec, b->fgraph, 0));
+  }
   for (int32_t t = 0; t < iters; ++t) {
-    if (use_graph == 1) {
+    if (use_graph == 3) {
+      HIPCHK(c, hipGraphLaunch(b->fexec, b->s0));
+    } else if (use_graph == 1) {
       HIPCHK(c, hipGraphLaunch(b->exec, b->s0));
     } else if (use_graph == 2) {
       if ((st = batch_fork(b)) != PW_OK) return st;

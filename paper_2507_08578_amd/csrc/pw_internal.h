@@ -42,6 +42,76 @@ struct BoxPlan {
 };
 
 // ---------------------------------------------------------------------------
+// Fused batches: one launch per stage covers every item; each item's sizes,
+// plan and buffers are read from an array of ItemDev in device memory
+// (indexed by the launch's item coordinate).  Block buffers have ld = npw.
+// ---------------------------------------------------------------------------
+struct ItemDev {
+  BoxPlan plan;
+  int npw, nb, nproj, gemm_target;
+  int col_tile, plane_rows;            // generic FFT kernels' tiles of this item's box
+  cplx* y;                             // complex128 blocks
+  cplx* hy;
+  cplx* blk;
+  float2* b32[2];                      // complex64 blocks of the low-precision filter
+  cplx* T;                             // FFT intermediates (all nb bands)
+  float2* T32;
+  const double* kin;
+  const double* vs;                    // V / N_box
+  const float* kin32;
+  const float* vs32;
+  const cplx* proj;
+  const float2* proj32;
+  const double* ekb;
+  cplx* cprj;
+  float2* cprj32;
+  cplx* gemm_work;
+  float2* work32;
+  cplx* sub0;                          // nb x nb, ld nb
+  cplx* sub1;
+  cplx* dinv;
+  double* dtol;
+  int* status;
+  double* eig;
+  double* resid;
+  double* coef;                        // 3 per filter step
+  double* upper;
+  int* flags;
+  int* sweeps;
+};
+
+// Matrix products of the fused launches (FP64 unless noted):
+//   GOP_PROJ     cprj = alpha diag(E_KB) P^H X        (X = block sel_b; FP32 variant: cprj32)
+//   GOP_GRAM     sub0 = Y^H X                         (X = block sel_b)
+//   GOP_NONLOCAL X += P cprj                          (X = block sel_c; FP32 variant: cprj32)
+//   GOP_TRSM     blk = Y dinv                         (one diagonal block: nb <= 64)
+//   GOP_ROT      blk = X sub1                         (X = block sel_a)
+enum GemmOp : int { GOP_PROJ = 0, GOP_GRAM = 1, GOP_NONLOCAL = 2, GOP_TRSM = 3, GOP_ROT = 4 };
+
+// Block selectors of the fused launches.
+enum BlockSel : int { SEL_Y = 0, SEL_HY = 1, SEL_BLK = 2, SEL_B32A = 3, SEL_B32B = 4, SEL_NONE = 5 };
+
+__device__ __forceinline__ cplx* item_blk64(const ItemDev& d, int s) {
+  return s == SEL_Y ? d.y : s == SEL_HY ? d.hy : s == SEL_BLK ? d.blk : nullptr;
+}
+__device__ __forceinline__ float2* item_blk32(const ItemDev& d, int s) {
+  return s == SEL_B32A ? d.b32[0] : s == SEL_B32B ? d.b32[1] : nullptr;
+}
+
+// Host-side launch shape of one fused group.  Items of a group share the FFT
+// kernel family: register column kernels need one N3, the register plane
+// kernel one N1 = N2; the generic kernels take every length from the item.
+struct FusedFft {
+  int n1, n2, n3;                      // the shared lengths (register kernels)
+  int n3_max;                          // plane grid
+  int nitems, nb_max, ncols_max, xr_max;
+  bool reg_col, reg_plane;
+  int plane_variant, plane_variant32;
+  int col_blocks;                      // generic column grid: max over items of ceil(ncols / tile)
+  size_t col_lds, plane_lds;           // generic kernels, largest item
+};
+
+// ---------------------------------------------------------------------------
 // Launch helpers (defined in the .hip files), all enqueue on `s`.
 // ---------------------------------------------------------------------------
 struct FftLaunchCfg {
@@ -90,6 +160,49 @@ hipError_t launch_fft_col_fwd32(const BoxPlan& p, const FftLaunchCfg& cfg, int n
                                 const float* kin, const float2* in, int64_t ldin, const float2* prev,
                                 int64_t ldprev, float2* out, int64_t ldout, const Epilogue& ep,
                                 hipStream_t s);
+
+// Fused-batch FFT stages over the items D[0 .. f.nitems) (block selectors as in BlockSel;
+// coef_step >= 0 reads the epilogue coefficients from item.coef + 3 coef_step).
+hipError_t launch_fused_col_inv(const FusedFft& f, bool fp32, const ItemDev* D, int sel_in,
+                                hipStream_t s);
+hipError_t launch_fused_plane(const FusedFft& f, bool fp32, const ItemDev* D, hipStream_t s);
+hipError_t launch_fused_col_fwd(const FusedFft& f, bool fp32, const ItemDev* D, int sel_in,
+                                int sel_out, int sel_prev, double alpha, double beta, double gamma,
+                                int coef_step, hipStream_t s);
+hipError_t launch_fused_col_inv_reg(const FusedFft& f, bool fp32, const ItemDev* D, int sel_in,
+                                    hipStream_t s);
+hipError_t launch_fused_plane_reg(const FusedFft& f, bool fp32, const ItemDev* D, hipStream_t s);
+hipError_t launch_fused_col_fwd_reg(const FusedFft& f, bool fp32, const ItemDev* D, int sel_in,
+                                    int sel_out, int sel_prev, double alpha, double beta,
+                                    double gamma, int coef_step, hipStream_t s);
+
+// Fused-batch products over items D[0 .. nitems) (see GemmOp).  m_max / n_max
+// bound the output tiles of any item; nsplit_max the split count of any item.
+hipError_t launch_fused_gemm_cn(int nitems, int64_t m_max, int64_t n_max, int nsplit_max,
+                                const ItemDev* D, int op, int sel_b, double alpha, int coef_step,
+                                hipStream_t s);
+hipError_t launch_fused_gemm_nn(int nitems, int64_t m_max, int64_t n_max, const ItemDev* D, int op,
+                                int sel_a, int sel_c, hipStream_t s);
+// the split count the fused GOP_PROJ / GOP_GRAM product uses for one item
+int fused_cn_nsplit(int op, int64_t npw, int64_t nb, int64_t nproj, int target);
+hipError_t launch_fused_gemm_cn32(int bf16, int nitems, int64_t m_max, int64_t n_max,
+                                  int nsplit_max, const ItemDev* D, int sel_b, double alpha,
+                                  int coef_step, hipStream_t s);
+hipError_t launch_fused_gemm_nn32(int bf16, int nitems, int64_t m_max, int64_t n_max,
+                                  const ItemDev* D, int sel_c, hipStream_t s);
+int fused_cn32_nsplit(int bf16, int64_t npw, int64_t nb, int64_t nproj, int target);
+
+// Fused-batch subspace and filter steps (one launch over all items):
+//   FS_CHEB_COEF (arg0 = degree), FS_FILTER_FIRST (arg0 = 1: FP32 b32[1], 0: FP64 blk),
+//   FS_TO_F32 (y -> b32[0]), FS_TO_F64 (b32[arg0 - SEL_B32A] -> y), FS_COPY (arg0 -> arg1),
+//   FS_HERMITIZE (sub0), FS_CHOL_INIT / FS_CHOL_DIAG (sub0 -> U, dinv; nb <= 64),
+//   FS_JACOBI (sub0 -> eig, sub1; nb <= 64), FS_RESIDUALS, FS_FLAGS.
+enum FusedStep : int {
+  FS_CHEB_COEF, FS_FILTER_FIRST, FS_TO_F32, FS_TO_F64, FS_COPY, FS_HERMITIZE, FS_CHOL_INIT,
+  FS_CHOL_DIAG, FS_JACOBI, FS_RESIDUALS, FS_FLAGS
+};
+hipError_t launch_fused_dense(FusedStep step, int nitems, int64_t npw_nb_max, int nb_max,
+                              const ItemDev* D, int arg0, int arg1, hipStream_t s);
 
 // Allow `bytes` of dynamic LDS for the FFT kernels (above the default cap).
 hipError_t fft_set_lds_limits(size_t bytes);

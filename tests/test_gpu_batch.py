@@ -168,3 +168,25 @@ def test_batch_rank_deficient_start(pw, ctx):
     with pytest.raises(pw.PWError) as e:
         bt.start()
     assert e.value.status == 5 and "item 1" in str(e.value) and "pivot 6" in str(e.value)
+
+
+@pytest.mark.parametrize("cfg,prec", [("C2", "fp64"), ("C4", "fp64"), ("C4", "fp32")])
+def test_fused_equals_per_item_kernels(pw, ctx, cfg, prec):
+    """Fused mode (one launch per stage for all items of a box; register and
+    generic FFT kernels, several box groups for C4) gives the same bits as
+    the per-item kernels issued directly."""
+    ws = synth.config_c2()[:6] if cfg == "C2" else synth.config_c4()[:10]
+    lp = prec != "fp64"
+    X0 = [to_dev(synth.start_block(w.npw, w.nb, 700 + i)) for i, w in enumerate(ws)]
+    res = {}
+    for mode in ("fused", False):
+        hams = [pw.Hamiltonian.from_workload(ctx, w, nb_max=w.nb, low_prec=lp) for w in ws]
+        bt = pw.Batch(ctx, hams, X0, degree=8, filter_prec=prec, nstreams=4)
+        bt.start()
+        bt.iterate(3, graph=mode)
+        res[mode] = ([to_host(e) for e in bt.eig], [to_host(y) for y in bt.Y],
+                     [to_host(r) for r in bt.resid])
+    for i in range(len(ws)):
+        assert np.array_equal(res["fused"][0][i], res[False][0][i]), i
+        assert np.array_equal(res["fused"][1][i], res[False][1][i]), i
+        assert np.array_equal(res["fused"][2][i], res[False][2][i]), i
