@@ -366,6 +366,15 @@ constexpr int kMaxSweeps = 40;
 
 __device__ __forceinline__ double jac_tol(int n) { return fmax(1e-15, 2.2e-16 * n); }
 
+// Workgroup size of the one-workgroup solve: one thread per 2x2 block of a
+// round (h^2, h = ceil(n/2)), a power of two in [64, 1024].
+inline int jac_threads(int n) {
+  const int h = (n + 1) / 2;
+  int t = 64;
+  while (t < h * h && t < kJacThreads) t *= 2;
+  return t;
+}
+
 // Whole Jacobi solve in LDS for n <= 64.
 __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict__ Ain, int64_t lda, double* __restrict__ w,
                cplx* __restrict__ Q, int64_t ldq, int* sweeps_out) {
@@ -389,18 +398,21 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
   __syncthreads();
   int sweeps = 0;
   for (; sweeps < kMaxSweeps; ++sweeps) {
-    // convergence test before the sweep
-    double off = 0.0, tot = 0.0;
-    for (int idx = tid; idx < n * n; idx += nt) {
-      const int j = idx / n, i = idx - j * n;
-      const double m2 = cabs2(a[idx]);
-      tot += m2;
-      if (i != j) off += m2;
+    // convergence test before the sweep: 64 fixed partial sums, so the
+    // summation order does not depend on the workgroup size
+    if (tid < 64) {
+      double off = 0.0, tot = 0.0;
+      for (int idx = tid; idx < n * n; idx += 64) {
+        const int j = idx / n, i = idx - j * n;
+        const double m2 = cabs2(a[idx]);
+        tot += m2;
+        if (i != j) off += m2;
+      }
+      red[tid] = off;
+      red2[tid] = tot;
     }
-    red[tid] = off;
-    red2[tid] = tot;
     __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
+    for (int s = 32; s > 0; s >>= 1) {
       if (tid < s) {
         red[tid] += red[tid + s];
         red2[tid] += red2[tid + s];
@@ -991,8 +1003,8 @@ hipError_t launch_heev_small_async(int64_t n, const cplx* a, int64_t lda, double
                                    int64_t ldq, int* sweeps_dev, hipStream_t s) {
   if (n > kJacSmallMax) return hipErrorInvalidValue;
   const size_t lds = (size_t)(2 * n * n) * sizeof(cplx);
-  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(kJacThreads), lds, s, (int)n, a, lda, w, q, ldq,
-                     sweeps_dev);
+  hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(jac_threads((int)n)), lds, s, (int)n, a, lda, w,
+                     q, ldq, sweeps_dev);
   return hipGetLastError();
 }
 
@@ -1006,8 +1018,8 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
   double* dstat = reinterpret_cast<double*>(base + stat_off);
   if (n <= kJacSmallMax) {
     const size_t lds = (size_t)(2 * n * n) * sizeof(cplx);
-    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(kJacThreads), lds, s, (int)n, (const cplx*)a,
-                       lda, w, q, ldq, dev_int);
+    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(jac_threads((int)n)), lds, s, (int)n,
+                       (const cplx*)a, lda, w, q, ldq, dev_int);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int hs = 0;
@@ -1092,7 +1104,7 @@ hipError_t launch_fused_dense(FusedStep step, int nitems, int64_t npw_nb_max, in
                          (size_t)2 * nb_max * (nb_max + 1) * sizeof(cplx), s, D);
       break;
     case FS_JACOBI:
-      hipLaunchKernelGGL(kb_jacobi, dim3(nitems), dim3(kJacThreads),
+      hipLaunchKernelGGL(kb_jacobi, dim3(nitems), dim3(jac_threads(nb_max)),
                          (size_t)(2 * nb_max * nb_max) * sizeof(cplx), s, D);
       break;
     case FS_RESIDUALS:

@@ -303,7 +303,7 @@ int plane_reg_threads(const BoxPlan& p, int gmax) {
   return std::min(t, kPlaneMaxThreads);
 }
 
-#define PW_FAST_SIZES(X) X(24) X(32) X(36) X(48) X(64) X(72) X(96) X(120) X(128) X(144) X(160)
+#define PW_FAST_SIZES(X) X(24) X(30) X(32) X(36) X(48) X(64) X(72) X(96) X(120) X(128) X(144) X(160)
 // sizes whose 8-lane variant differs from the 16-lane one and fits the
 // registers: FP64, and FP32 (half the registers per value)
 #define PW_NARROW_SIZES64(X) X(48) X(64) X(96)

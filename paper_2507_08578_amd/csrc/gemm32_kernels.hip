@@ -298,7 +298,8 @@ __host__ __device__ inline SplitPlan split_plan32(int64_t m, int64_t n, int64_t 
   p.tiles_n = (n + kBN - 1) / kBN;
   const int64_t tiles = p.tiles_m * p.tiles_n;
   int64_t want = (target + tiles - 1) / tiles;
-  const int64_t maxs = (k + Kc * 8 - 1) / (Kc * 8) > 1 ? (k + Kc * 8 - 1) / (Kc * 8) : 1;
+  // at least two K stages per split (short splits keep small products latency-light)
+  const int64_t maxs = (k + Kc * 2 - 1) / (Kc * 2) > 1 ? (k + Kc * 2 - 1) / (Kc * 2) : 1;
   want = want < maxs ? want : maxs;
   if (want < 1) want = 1;
   int64_t ks = (k + want - 1) / want;

@@ -280,7 +280,8 @@ __host__ __device__ inline SplitPlan split_plan(int64_t m, int64_t n, int64_t k,
   p.tiles_n = (n + kBN - 1) / kBN;
   const int64_t tiles = p.tiles_m * p.tiles_n;
   int64_t want = (target + tiles - 1) / tiles;
-  const int64_t maxs = (k + kKcCN * 8 - 1) / (kKcCN * 8) > 1 ? (k + kKcCN * 8 - 1) / (kKcCN * 8) : 1;
+  // at least two K stages per split (short splits keep small products latency-light)
+  const int64_t maxs = (k + kKcCN * 2 - 1) / (kKcCN * 2) > 1 ? (k + kKcCN * 2 - 1) / (kKcCN * 2) : 1;
   want = want < maxs ? want : maxs;
   if (want < 1) want = 1;
   int64_t ks = (k + want - 1) / want;
@@ -393,7 +394,11 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
                           int target) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (target < 1 || target > kTargetBlocks) target = kTargetBlocks;
-  const SplitPlan p = split_plan(m, n, k, target);
+  SplitPlan p = split_plan(m, n, k, target);
+  if (!work) {   // no workspace: one split over the whole K range
+    p.nsplit = 1;
+    p.ksplit = k > 0 ? k : 1;
+  }
   if (p.nsplit == 1) {
     dim3 grid(p.tiles_n, p.tiles_m, 1);
     hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, alpha, alpha_dev,

@@ -333,7 +333,7 @@ hipError_t chol_blocked(int64_t n, cplx* a, int64_t lda, cplx* dinv, cplx* panel
     e = launch_chol_diag(kbk, (int)k0, a, lda, dk, tol, status, s);
     if (e != hipSuccess || m == 0) break;
     cplx* row = a + k0 + (k0 + kbk) * lda;                       // U[k, k+1:]
-    // row <- U_kk^{-H} A[k, k+1:]  (K = kbk <= 64: one split, no workspace)
+    // row <- U_kk^{-H} A[k, k+1:]  (no workspace: the product is not split)
     e = launch_gemm_cn(kbk, m, kbk, 1.0, dk, kbk, row, lda, panel, kbk, nullptr, nullptr, s);
     if (e == hipSuccess) e = launch_copy_block(kbk, m, panel, kbk, row, lda, s);
     // A[k+1:, k+1:] -= row^H row

@@ -230,7 +230,8 @@ hipError_t launch_fft_col_fwd_reg32(const BoxPlan& p, int nb, const float2* T, c
                                     hipStream_t s);
 
 // Split-K C = alpha diag(rowscale) A^H B + beta C (see pw_gemm_cn).  `work`
-// holds splits*m*n cplx; rowscale (m doubles on device) may be null.
+// holds splits*m*n cplx (gemm_cn_work_elems); with work == null the product
+// is not split.  rowscale (m doubles on device) may be null.
 size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k);
 // alpha_dev (may be null): device scalar read in place of alpha.
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,

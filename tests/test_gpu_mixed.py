@@ -104,10 +104,10 @@ def test_low_precision_errors(pw, ctx):
     assert e.value.status == 2
 
 
-@pytest.mark.parametrize("cell", [0, 2, 7])
+@pytest.mark.parametrize("cell", [0, 2, 7, 3])
 def test_apply_fp32_uneven_box(pw, ctx, cell):
-    """Strained C4 cells: boxes that are not cubic or not of a register-kernel
-    length (e.g. 30 x 30 x 24) run the generic FP32 LDS kernels."""
+    """Strained C4 cells: boxes whose planes are not square (32 x 36 x 32,
+    24 x 30 x 30) run the generic FP32 plane kernel."""
     w = synth.config_c4()[cell]
     for prec, tol in (("fp32", 2e-6), ("bf16", 2e-2)):
         err = apply_err(pw, ctx, w, 8, prec, seed=cell)

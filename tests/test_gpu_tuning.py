@@ -55,7 +55,7 @@ def test_every_accepted_tuning_matches_oracle(pw, ctx, which):
 
 
 def test_set_tuning_rejects(pw, ctx):
-    w = synth.config_c4()[2]                 # box 30 x 30 x 24: no register plane kernel
+    w = synth.config_c4()[0]                 # box 32 x 36 x 32: no register plane kernel
     ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=8)
     with pytest.raises(pw.PWError) as e:
         ham.set_tuning({"reg_plane": 1})
