@@ -203,6 +203,7 @@ typedef struct {
   int32_t plane_variant32;/* FP32 plane kernel, the same choice (1 also for 120, 128, 144, 160) */
   int32_t chunk;          /* bands per FFT launch, [1, the handle's buffer]                  */
   int32_t gemm_blocks;    /* split-K target block count of P^H psi, [1, 2048]                */
+  int32_t nn_tile;        /* tall products P C, Y Q, Y U^-1: 0 64x64, 1 128x64 workgroup tiles */
   double ms;              /* pw_ham_autotune: median time of one H*psi of nb bands           */
 } pw_tuning;
 
@@ -211,7 +212,8 @@ pw_status pw_ham_get_tuning(const pw_ham* ham, pw_tuning* t);
 pw_status pw_ham_set_tuning(pw_ham* ham, const pw_tuning* t);
 /*
  * Coordinate search over (1) the FFT kernel families, (2) the band chunk,
- * (3) the split-K block count, each step keeping the fastest; every
+ * (3) the split-K block count, (4) the tile of the tall products, each step
+ * keeping the fastest; every
  * candidate timed as the median of reps H*psi applications of nb bands in
  * precision prec (after one warm-up) with HIP events on the context's
  * stream.  Leaves the handle at *best; *initial (may be NULL) receives the

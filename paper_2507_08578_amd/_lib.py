@@ -45,7 +45,8 @@ class PwHamDesc(ctypes.Structure):
 class PwTuning(ctypes.Structure):
     """pw_tuning (include/pw.h)."""
     _fields_ = [("reg_col", c_int32), ("reg_plane", c_int32), ("plane_variant", c_int32),
-                ("plane_variant32", c_int32), ("chunk", c_int32), ("gemm_blocks", c_int32), ("ms", c_double)]
+                ("plane_variant32", c_int32), ("chunk", c_int32), ("gemm_blocks", c_int32),
+                ("nn_tile", c_int32), ("ms", c_double)]
 
 
 SIGNATURES = {

@@ -33,27 +33,28 @@ struct KC {
 
 __device__ __forceinline__ void f4zero(f4& a) { a = f4{0.f, 0.f, 0.f, 0.f}; }
 
-// One complex K-stage of MFMAs for a wave's 2x2 sub-tiles.  As/Bs are LDS
+// One complex K-stage of MFMAs for a wave's TM x TN sub-tiles.  As/Bs are LDS
 // tiles [k][i] / [k][j] (row pitch pa/pb in float2); conjA negates Im(A).
-template <int MODE, bool CONJA>
+template <int MODE, bool CONJA, int TM = 2, int TN = 2>
 __device__ __forceinline__ void mfma_stage(const float2* As, int pa, const float2* Bs, int pb,
-                                           int wi, int wj, int lane, f4 (&ar)[2][2],
-                                           f4 (&ai)[2][2]) {
+                                           int wi, int wj, int lane, f4 (&ar)[TM][TN],
+                                           f4 (&ai)[TM][TN]) {
   const int lr = lane & 15, lk = lane >> 4;
   if constexpr (MODE == MODE_F32) {
 #pragma unroll
     for (int ks = 0; ks < KC<MODE>::value; ks += 4) {
-      float2 a[2], b[2];
+      float2 a[TM], b[TN];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = As[(ks + lk) * pa + wi * 32 + t * 16 + lr];
-        b[t] = Bs[(ks + lk) * pb + wj * 32 + t * 16 + lr];
+      for (int t = 0; t < TM; ++t) {
+        a[t] = As[(ks + lk) * pa + wi * 16 * TM + t * 16 + lr];
         if (CONJA) a[t].y = -a[t].y;
       }
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
+      for (int t = 0; t < TN; ++t) b[t] = Bs[(ks + lk) * pb + wj * 16 * TN + t * 16 + lr];
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj) {
+      for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TN; ++tj) {
           ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti].x, b[tj].x, ar[ti][tj], 0, 0, 0);
           ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[ti].y, b[tj].y, ar[ti][tj], 0, 0, 0);
           ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti].x, b[tj].y, ai[ti][tj], 0, 0, 0);
@@ -61,25 +62,31 @@ __device__ __forceinline__ void mfma_stage(const float2* As, int pa, const float
         }
     }
   } else {
-    bf8 are[2], aim[2], anim[2], bre[2], bim[2];
+    bf8 are[TM], aim[TM], anim[TM], bre[TN], bim[TN];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < TM; ++t) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        float2 a = As[(8 * lk + e) * pa + wi * 32 + t * 16 + lr];
+        float2 a = As[(8 * lk + e) * pa + wi * 16 * TM + t * 16 + lr];
         if (CONJA) a.y = -a.y;
-        const float2 b = Bs[(8 * lk + e) * pb + wj * 32 + t * 16 + lr];
         are[t][e] = (__bf16)a.x;
         aim[t][e] = (__bf16)a.y;
         anim[t][e] = (__bf16)(-a.y);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float2 b = Bs[(8 * lk + e) * pb + wj * 16 * TN + t * 16 + lr];
         bre[t][e] = (__bf16)b.x;
         bim[t][e] = (__bf16)b.y;
       }
     }
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
+      for (int tj = 0; tj < TN; ++tj) {
         ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(are[ti], bre[tj], ar[ti][tj], 0, 0, 0);
         ar[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anim[ti], bim[tj], ar[ti][tj], 0, 0, 0);
         ai[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(are[ti], bim[tj], ai[ti][tj], 0, 0, 0);
@@ -89,35 +96,37 @@ __device__ __forceinline__ void mfma_stage(const float2* As, int pa, const float
 }
 
 // C = alpha A B + beta C; A m x k (lda), B k x n (ldb), complex64 column-major.
-template <int MODE>
-__device__ __forceinline__ void gemm_nn32_body(int64_t M, int64_t N, int64_t K, float alpha,
+// Workgroup tile (32 TM) x (32 TN), 4 waves in 2 x 2.
+template <int MODE, int TM, int TN>
+__device__ __forceinline__ void gemm_nn32_tile(int64_t M, int64_t N, int64_t K, float alpha,
                                                const float2* __restrict__ A, int64_t lda,
                                                const float2* __restrict__ B, int64_t ldb,
                                                float beta, float2* __restrict__ C, int64_t ldc,
                                                int bx, int by) {
   constexpr int Kc = KC<MODE>::value;
-  constexpr int PA = kBM, PB = kBN + 1;
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int PA = BM, PB = BN + 1;
   __shared__ float2 As[Kc * PA];
   __shared__ float2 Bs[Kc * PB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
-  f4 ar[2][2], ai[2][2];
+  const int64_t i0 = (int64_t)by * BM, j0 = (int64_t)bx * BN;
+  f4 ar[TM][TN], ai[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < TN; ++b) {
       f4zero(ar[a][b]);
       f4zero(ai[a][b]);
     }
-  constexpr int QA = kBM * Kc / kThreads, QB = kBN * Kc / kThreads;
-  static_assert(QA * kThreads == kBM * Kc && QB * kThreads == kBN * Kc, "tile split");
+  constexpr int QA = BM * Kc / kThreads, QB = BN * Kc / kThreads;
+  static_assert(QA * kThreads == BM * Kc && QB * kThreads == BN * Kc, "tile split");
   float2 ra[QA], rb[QB];
   auto fetch = [&](int64_t k0) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = tid + q * kThreads;
-      const int kk = e / kBM, ii = e - kk * kBM;
+      const int kk = e / BM, ii = e - kk * BM;
       const int64_t gi = i0 + ii, gk = k0 + kk;
       ra[q] = (gi < M && gk < K) ? A[gi + gk * lda] : make_float2(0.f, 0.f);
     }
@@ -134,7 +143,7 @@ __device__ __forceinline__ void gemm_nn32_body(int64_t M, int64_t N, int64_t K, 
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = tid + q * kThreads;
-      const int kk = e / kBM, ii = e - kk * kBM;
+      const int kk = e / BM, ii = e - kk * BM;
       As[kk * PA + ii] = ra[q];
     }
 #pragma unroll
@@ -145,18 +154,18 @@ __device__ __forceinline__ void gemm_nn32_body(int64_t M, int64_t N, int64_t K, 
     }
     __syncthreads();
     if (k0 + Kc < K) fetch(k0 + Kc);
-    mfma_stage<MODE, false>(As, PA, Bs, PB, wi, wj, lane, ar, ai);
+    mfma_stage<MODE, false, TM, TN>(As, PA, Bs, PB, wi, wj, lane, ar, ai);
     __syncthreads();
   }
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < TN; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + wi * 32 + ti * 16 + 4 * lk + r;
-        const int64_t j = j0 + wj * 32 + tj * 16 + lr;
+        const int64_t i = i0 + wi * 16 * TM + ti * 16 + 4 * lk + r;
+        const int64_t j = j0 + wj * 16 * TN + tj * 16 + lr;
         if (i < M && j < N) {
           float2 v = make_float2(alpha * ar[ti][tj][r], alpha * ai[ti][tj][r]);
           if (beta != 0.f) {
@@ -170,11 +179,28 @@ __device__ __forceinline__ void gemm_nn32_body(int64_t M, int64_t N, int64_t K, 
 }
 
 template <int MODE>
+__device__ __forceinline__ void gemm_nn32_body(int64_t M, int64_t N, int64_t K, float alpha,
+                                               const float2* __restrict__ A, int64_t lda,
+                                               const float2* __restrict__ B, int64_t ldb,
+                                               float beta, float2* __restrict__ C, int64_t ldc,
+                                               int bx, int by) {
+  gemm_nn32_tile<MODE, 2, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
+}
+
+template <int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_gemm_nn32(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restrict__ A,
             int64_t lda, const float2* __restrict__ B, int64_t ldb, float beta,
             float2* __restrict__ C, int64_t ldc) {
   gemm_nn32_body<MODE>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kThreads)
+k_gemm_nn32_tall(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restrict__ A,
+                 int64_t lda, const float2* __restrict__ B, int64_t ldb, float beta,
+                 float2* __restrict__ C, int64_t ldc) {
+  gemm_nn32_tile<MODE, 4, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
 }
 
 // Partial (split z over K) A^H B; A k x m (lda), B k x n (ldb); out ld = M.
@@ -376,8 +402,18 @@ hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double al
 
 hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
-                            int64_t ldc, hipStream_t s) {
+                            int64_t ldc, hipStream_t s, int tile) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  if (tile == 1) {
+    dim3 grid((n + kBN - 1) / kBN, (m + 2 * kBM - 1) / (2 * kBM), 1);
+    if (bf16)
+      hipLaunchKernelGGL(k_gemm_nn32_tall<MODE_BF16>, grid, dim3(kThreads), 0, s, m, n, k,
+                         (float)alpha, A, lda, B, ldb, (float)beta, C, ldc);
+    else
+      hipLaunchKernelGGL(k_gemm_nn32_tall<MODE_F32>, grid, dim3(kThreads), 0, s, m, n, k,
+                         (float)alpha, A, lda, B, ldb, (float)beta, C, ldc);
+    return hipGetLastError();
+  }
   dim3 grid((n + kBN - 1) / kBN, (m + kBM - 1) / kBM, 1);
   if (bf16)
     hipLaunchKernelGGL(k_gemm_nn32<MODE_BF16>, grid, dim3(kThreads), 0, s, m, n, k, (float)alpha, A,

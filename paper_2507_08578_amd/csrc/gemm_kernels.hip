@@ -32,84 +32,87 @@ __device__ __forceinline__ void cmfma(d4& re, d4& im, double ar, double ai, doub
 }
 
 // C = alpha A B + beta C; A m x k (lda), B k x n (ldb), column-major.
-__device__ __forceinline__ void gemm_nn_body(int64_t M, int64_t N, int64_t K, double alpha,
+// Workgroup tile (32 TM) x (32 TN): 4 waves in 2 x 2, each (16 TM) x (16 TN)
+// built from TM x TN MFMA tiles; K staged KC complex at a time.
+template <int TM, int TN, int KC>
+__device__ __forceinline__ void gemm_nn_tile(int64_t M, int64_t N, int64_t K, double alpha,
                                              const cplx* __restrict__ A, int64_t lda,
                                              const cplx* __restrict__ B, int64_t ldb, double beta,
                                              cplx* __restrict__ C, int64_t ldc, int bx, int by) {
-  __shared__ cplx As[kKcNN][kBM];
-  __shared__ cplx Bs[kKcNN][kBN + 1];
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  __shared__ cplx As[KC][BM];
+  __shared__ cplx Bs[KC][BN + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
-  d4 accr[2][2], acci[2][2];
+  const int64_t i0 = (int64_t)by * BM, j0 = (int64_t)bx * BN;
+  d4 accr[TM][TN], acci[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < TN; ++b) {
       accr[a][b] = d4{0.0, 0.0, 0.0, 0.0};
       acci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     }
   const int lr = lane & 15, lk = lane >> 4;
   // global -> register prefetch of the next K stage overlaps this stage's MFMAs
-  constexpr int QA = kBM * kKcNN / kThreads, QB = kBN * kKcNN / kThreads;
-  static_assert(QA * kThreads == kBM * kKcNN && QB * kThreads == kBN * kKcNN, "tile split");
+  constexpr int QA = BM * KC / kThreads, QB = BN * KC / kThreads;
+  static_assert(QA * kThreads == BM * KC && QB * kThreads == BN * KC, "tile split");
   cplx ra[QA], rb[QB];
   auto fetch = [&](int64_t k0) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = tid + q * kThreads;
-      const int kk = e / kBM, ii = e - kk * kBM;
+      const int kk = e / BM, ii = e - kk * BM;
       const int64_t gi = i0 + ii, gk = k0 + kk;
       ra[q] = (gi < M && gk < K) ? A[gi + gk * lda] : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int e = tid + q * kThreads;
-      const int jj = e / kKcNN, kk = e - jj * kKcNN;
+      const int jj = e / KC, kk = e - jj * KC;
       const int64_t gk = k0 + kk, gj = j0 + jj;
       rb[q] = (gk < K && gj < N) ? B[gk + gj * ldb] : make_double2(0.0, 0.0);
     }
   };
   fetch(0);
-  for (int64_t k0 = 0; k0 < K; k0 += kKcNN) {
+  for (int64_t k0 = 0; k0 < K; k0 += KC) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = tid + q * kThreads;
-      const int kk = e / kBM, ii = e - kk * kBM;
+      const int kk = e / BM, ii = e - kk * BM;
       As[kk][ii] = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int e = tid + q * kThreads;
-      const int jj = e / kKcNN, kk = e - jj * kKcNN;
+      const int jj = e / KC, kk = e - jj * KC;
       Bs[kk][jj] = rb[q];
     }
     __syncthreads();
-    if (k0 + kKcNN < K) fetch(k0 + kKcNN);
+    if (k0 + KC < K) fetch(k0 + KC);
 #pragma unroll
-    for (int ks = 0; ks < kKcNN; ks += 4) {
-      cplx a[2], b[2];
+    for (int ks = 0; ks < KC; ks += 4) {
+      cplx a[TM], b[TN];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = As[ks + lk][wi * 32 + t * 16 + lr];
-        b[t] = Bs[ks + lk][wj * 32 + t * 16 + lr];
-      }
+      for (int t = 0; t < TM; ++t) a[t] = As[ks + lk][wi * 16 * TM + t * 16 + lr];
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
+      for (int t = 0; t < TN; ++t) b[t] = Bs[ks + lk][wj * 16 * TN + t * 16 + lr];
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
+      for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TN; ++tj)
           cmfma(accr[ti][tj], acci[ti][tj], a[ti].x, a[ti].y, b[tj].x, b[tj].y);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < TM; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < TN; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + wi * 32 + ti * 16 + lk + 4 * r;
-        const int64_t j = j0 + wj * 32 + tj * 16 + lr;
+        const int64_t i = i0 + wi * 16 * TM + ti * 16 + lk + 4 * r;
+        const int64_t j = j0 + wj * 16 * TN + tj * 16 + lr;
         if (i < M && j < N) {
           cplx v = make_double2(alpha * accr[ti][tj][r], alpha * acci[ti][tj][r]);
           if (beta != 0.0) {
@@ -122,10 +125,25 @@ __device__ __forceinline__ void gemm_nn_body(int64_t M, int64_t N, int64_t K, do
       }
 }
 
+__device__ __forceinline__ void gemm_nn_body(int64_t M, int64_t N, int64_t K, double alpha,
+                                             const cplx* __restrict__ A, int64_t lda,
+                                             const cplx* __restrict__ B, int64_t ldb, double beta,
+                                             cplx* __restrict__ C, int64_t ldc, int bx, int by) {
+  gemm_nn_tile<2, 2, kKcNN>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict__ A, int64_t lda,
           const cplx* __restrict__ B, int64_t ldb, double beta, cplx* __restrict__ C, int64_t ldc) {
   gemm_nn_body(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
+}
+
+// 128 x 64 workgroup tiles for tall products (M = plane waves)
+__global__ void __launch_bounds__(kThreads)
+k_gemm_nn_tall(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict__ A,
+               int64_t lda, const cplx* __restrict__ B, int64_t ldb, double beta,
+               cplx* __restrict__ C, int64_t ldc) {
+  gemm_nn_tile<4, 2, kKcNN>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
 }
 
 // Partial or final C = alpha diag(rowscale) A^H B over K range [kb, ke) of split z.
@@ -419,8 +437,14 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
 
 hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
-                          hipStream_t s) {
+                          hipStream_t s, int tile) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  if (tile == 1) {
+    dim3 grid((n + kBN - 1) / kBN, (m + 2 * kBM - 1) / (2 * kBM), 1);
+    hipLaunchKernelGGL(k_gemm_nn_tall, grid, dim3(kThreads), 0, s, m, n, k, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
+    return hipGetLastError();
+  }
   dim3 grid((n + kBN - 1) / kBN, (m + kBM - 1) / kBM, 1);
   hipLaunchKernelGGL(k_gemm_nn, grid, dim3(kThreads), 0, s, m, n, k, alpha, A, lda, B, ldb, beta,
                      C, ldc);

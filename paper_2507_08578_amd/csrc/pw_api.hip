@@ -57,6 +57,7 @@ struct pw_ham {
   int64_t chunk = 0;         // bands per FFT launch (tunable, <= chunk_alloc)
   int64_t chunk_alloc = 0;   // bands the FFT work buffer holds
   int gemm_target = 2048;    // split-K target block count of the projector product (tunable)
+  int nn_tile = 0;           // workgroup tile of the tall products P C, Y Q, Y U^-1 (tunable)
   bool reg_col_ok = false, reg_plane_ok = false, narrow_ok = false, narrow32_ok = false;
   std::vector<void*> allocs;
   double* kin = nullptr;
@@ -257,7 +258,7 @@ pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* o
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_NONLOCAL);
     HIPCHK(c, launch_gemm_nn(h->npw, nb, h->nproj, 1.0, h->proj, h->npw, h->cprj, h->nproj, 1.0,
-                             out, ldout, s));
+                             out, ldout, s, h->nn_tile));
   }
   return PW_OK;
 }
@@ -297,7 +298,7 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_NONLOCAL_LP);
     HIPCHK(c, launch_gemm_nn32(bf16, h->npw, nb, h->nproj, 1.0, h->proj32, h->npw, h->cprj32,
-                               h->nproj, 1.0, out, ldout, s));
+                               h->nproj, 1.0, out, ldout, s, h->nn_tile));
   }
   return PW_OK;
 }
@@ -306,7 +307,8 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
 pw_status rotate_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, const cplx* m) {
   pw_ctx* c = h->ctx;
   StageScope sc(c, PW_STAGE_ROTATE);
-  HIPCHK(c, launch_gemm_nn(h->npw, nb, nb, 1.0, y, ld, m, nb, 0.0, h->blk, h->npw, c->stream));
+  HIPCHK(c, launch_gemm_nn(h->npw, nb, nb, 1.0, y, ld, m, nb, 0.0, h->blk, h->npw, c->stream,
+                           h->nn_tile));
   HIPCHK(c, launch_copy_block(h->npw, nb, h->blk, h->npw, y, ld, c->stream));
   return PW_OK;
 }
@@ -347,16 +349,17 @@ hipError_t chol_blocked(int64_t n, cplx* a, int64_t lda, cplx* dinv, cplx* panel
 // y <- y U^{-1} for a rows x n block (ld), by column blocks J:
 // y[:, J] = (y[:, J] - y[:, <J] U[<J, J]) U_JJ^{-1}.  tmp: rows x kb.
 hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* u, int64_t ldu,
-                      const cplx* dinv, cplx* tmp, hipStream_t s) {
+                      const cplx* dinv, cplx* tmp, hipStream_t s, int tile = 0) {
   const int kb = kCholBlock;
   hipError_t e = hipSuccess;
   for (int64_t j0 = 0; j0 < n && e == hipSuccess; j0 += kb) {
     const int kbj = (int)std::min<int64_t>(kb, n - j0);
     if (j0 > 0)
-      e = launch_gemm_nn(rows, kbj, j0, -1.0, y, ld, u + j0 * ldu, ldu, 1.0, y + j0 * ld, ld, s);
+      e = launch_gemm_nn(rows, kbj, j0, -1.0, y, ld, u + j0 * ldu, ldu, 1.0, y + j0 * ld, ld, s,
+                         tile);
     if (e == hipSuccess)
       e = launch_gemm_nn(rows, kbj, kbj, 1.0, y + j0 * ld, ld, dinv + (j0 / kb) * kb * kb, kbj, 0.0,
-                         tmp, rows, s);
+                         tmp, rows, s, tile);
     if (e == hipSuccess) e = launch_copy_block(rows, kbj, tmp, rows, y + j0 * ld, ld, s);
   }
   return e;
@@ -1213,9 +1216,10 @@ pw_status pw_orthonormalize(pw_ham* h, pw_prec gram_prec, int64_t nb, void* yv, 
                 "Gram matrix not positive definite at pivot " + std::to_string(status));
   {
     StageScope sc(c, PW_STAGE_ROTATE);
-    HIPCHK(c, trsm_right(h->npw, nb, y, ld, h->sub0, nb, h->dinv, h->blk, s));
+    HIPCHK(c, trsm_right(h->npw, nb, y, ld, h->sub0, nb, h->dinv, h->blk, s, h->nn_tile));
     if (hyv)
-      HIPCHK(c, trsm_right(h->npw, nb, static_cast<cplx*>(hyv), ldhy, h->sub0, nb, h->dinv, h->blk, s));
+      HIPCHK(c, trsm_right(h->npw, nb, static_cast<cplx*>(hyv), ldhy, h->sub0, nb, h->dinv, h->blk, s,
+                           h->nn_tile));
   }
   return PW_OK;
 }
@@ -1314,6 +1318,7 @@ pw_status pw_ham_get_tuning(const pw_ham* h, pw_tuning* t) {
   t->plane_variant32 = h->cfg.plane_variant32;
   t->chunk = (int32_t)h->chunk;
   t->gemm_blocks = h->gemm_target;
+  t->nn_tile = h->nn_tile;
   t->ms = 0.0;
   return PW_OK;
 }
@@ -1338,12 +1343,14 @@ pw_status pw_ham_set_tuning(pw_ham* h, const pw_tuning* t) {
                 "chunk outside [1, " + std::to_string(h->chunk_alloc) + "]");
   if (t->gemm_blocks < 1 || t->gemm_blocks > 2048)
     return fail(h->ctx, PW_ERR_INVALID_ARG, "gemm_blocks outside [1, 2048]");
+  if (t->nn_tile != 0 && t->nn_tile != 1) return fail(h->ctx, PW_ERR_INVALID_ARG, "nn_tile is 0 or 1");
   h->cfg.reg_col = t->reg_col != 0;
   h->cfg.reg_plane = t->reg_plane != 0;
   h->cfg.plane_variant = t->plane_variant;
   h->cfg.plane_variant32 = t->plane_variant32;
   h->chunk = t->chunk;
   h->gemm_target = t->gemm_blocks;
+  h->nn_tile = t->nn_tile;
   return PW_OK;
 }
 
@@ -1437,6 +1444,12 @@ pw_status pw_ham_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, pw_
       t.gemm_blocks = g;
       if ((st = try_one(t)) != PW_OK) return st;
     }
+  // 4) workgroup tile of the tall products
+  if (h->nproj > 0) {
+    pw_tuning t = cur;
+    t.nn_tile = 1 - cur.nn_tile;
+    if ((st = try_one(t)) != PW_OK) return st;
+  }
   *best = cur;
   best->ms = cur_ms;
   return PW_OK;

@@ -238,9 +238,10 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
                           cplx* work, hipStream_t s, double beta = 0.0,
                           const double* alpha_dev = nullptr, int target_blocks = 2048);
+// tile 0: 64 x 64 workgroup tiles; 1: 128 x 64 (tall products)
 hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
-                          hipStream_t s);
+                          hipStream_t s, int tile = 0);
 
 // Low-precision products (gemm32_kernels.hip): complex64 operands, FP32
 // accumulation; bf16 != 0 rounds the MFMA operands to bfloat16.
@@ -251,7 +252,7 @@ hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double al
                             const double* alpha_dev = nullptr, int target_blocks = 2048);
 hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
-                            int64_t ldc, hipStream_t s);
+                            int64_t ldc, hipStream_t s, int tile = 0);
 
 // Precision conversions
 hipError_t launch_block_to_f32(int64_t rows, int64_t cols, const cplx* x, int64_t ldx, float2* y,
