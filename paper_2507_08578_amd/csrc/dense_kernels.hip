@@ -315,19 +315,22 @@ __device__ __forceinline__ void rr_pair(int r, int k, int n2, int* p, int* q) {
 // Rotation J = [[cs, sn ph], [-sn conj(ph), cs]] with J^H [[a, c], [conj c, b]] J diagonal:
 // tau = (b - a)/(2|c|), t = sign(tau)/(|tau| + sqrt(1 + tau^2)), cs = 1/sqrt(1+t^2), sn = t cs;
 // new diagonal a - t|c|, b + t|c|.
+// (Matrix entries here are O(1) Hamiltonian elements: |c| is formed without
+// the overflow guard of hypot.)
 __device__ __forceinline__ Rot make_rot(double a, double b, cplx c) {
   Rot R;
-  const double mag = hypot(c.x, c.y);
+  const double mag = sqrt(c.x * c.x + c.y * c.y);
   if (!(mag > DBL_MIN)) {
     R.cs = 1.0; R.sn = 0.0; R.t = 0.0; R.ph = make_double2(1.0, 0.0); R.on = false;
     return R;
   }
-  const double tau = (b - a) / (2.0 * mag);
+  const double rmag = 1.0 / mag;
+  const double tau = 0.5 * (b - a) * rmag;
   const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
   R.cs = 1.0 / sqrt(1.0 + t * t);
   R.sn = t * R.cs;
   R.t = t * mag;
-  R.ph = make_double2(c.x / mag, c.y / mag);
+  R.ph = make_double2(c.x * rmag, c.y * rmag);
   R.on = true;
   return R;
 }
@@ -384,6 +387,7 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
   cplx* a = sm;               // n x n, ld n
   cplx* v = sm + n * n;       // n x n
   __shared__ Rot rots[kJacSmallMax / 2];
+  __shared__ int pp[kJacSmallMax / 2], pq[kJacSmallMax / 2];   // this round's pairs
   __shared__ double red[kJacThreads];
   __shared__ double red2[kJacThreads];
   __shared__ int done;
@@ -429,15 +433,15 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
       if (tid < h) {
         int p, q;
         rr_pair(r, tid, n2, &p, &q);
+        pp[tid] = p;
+        pq[tid] = q;
         if (q < n) rots[tid] = make_rot(a[p + p * n].x, a[q + q * n].x, a[p + q * n]);
         else rots[tid] = make_rot(0.0, 0.0, make_double2(0.0, 0.0));
       }
       __syncthreads();
       for (int idx = tid; idx < h * h; idx += nt) {
         const int P = idx / h, Qb = idx - P * h;
-        int p1, q1, p2, q2;
-        rr_pair(r, P, n2, &p1, &q1);
-        rr_pair(r, Qb, n2, &p2, &q2);
+        const int p1 = pp[P], q1 = pq[P], p2 = pp[Qb], q2 = pq[Qb];
         const Rot& RP = rots[P];
         const Rot& RQ = rots[Qb];
         if (q1 >= n || q2 >= n) {
@@ -479,8 +483,7 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
       }
       for (int idx = tid; idx < n * h; idx += nt) {
         const int Qb = idx / n, i = idx - Qb * n;
-        int p2, q2;
-        rr_pair(r, Qb, n2, &p2, &q2);
+        const int p2 = pp[Qb], q2 = pq[Qb];
         if (q2 >= n || !rots[Qb].on) continue;
         cplx x1 = v[i + p2 * n], x2 = v[i + q2 * n];
         rot_row(rots[Qb], &x1, &x2);
