@@ -200,7 +200,8 @@ typedef struct {
   int32_t reg_plane;      /* 1: register-resident plane kernel (N1 = N2 in the fast set)     */
   int32_t plane_variant;  /* FP64 plane kernel: 0 lane groups of up to 16 lanes; 1 up to 8
                              (N1 = N2 = 48, 64, 96)                                        */
-  int32_t plane_variant32;/* FP32 plane kernel, the same choice (1 also for 120, 128, 144, 160) */
+  int32_t plane_variant32;/* FP32 plane kernel: 0, 1 as above (1 also for 120, 128, 144, 160);
+                             2 transforms exchanged through LDS (N1 = N2 = 144)            */
   int32_t chunk;          /* bands per FFT launch, [1, the handle's buffer]                  */
   int32_t gemm_blocks;    /* split-K target block count of P^H psi, [1, 2048]                */
   int32_t nn_tile;        /* tall products P C, Y Q, Y U^-1: 0 64x64, 1 128x64 workgroup tiles */

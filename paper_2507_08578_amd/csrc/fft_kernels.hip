@@ -452,6 +452,7 @@ hipError_t launch_fft_plane(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, c
 }
 hipError_t launch_fft_plane32(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const float* vscaled,
                               float2* T, hipStream_t s) {
+  if (cfg.reg_plane && cfg.plane_variant32 == 2) return launch_fft_plane_ls32(p, nb, vscaled, T, s);
   if (cfg.reg_plane) return launch_fft_plane_reg32(p, cfg.plane_variant32, nb, vscaled, T, s);
   return plane_generic<float2>(p, cfg, nb, vscaled, T, s);
 }

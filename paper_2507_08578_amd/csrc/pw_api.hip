@@ -59,6 +59,7 @@ struct pw_ham {
   int gemm_target = 2048;    // split-K target block count of the projector product (tunable)
   int nn_tile = 0;           // workgroup tile of the tall products P C, Y Q, Y U^-1 (tunable)
   bool reg_col_ok = false, reg_plane_ok = false, narrow_ok = false, narrow32_ok = false;
+  bool ls32_ok = false;      // FP32 plane kernel with LDS exchanges (square P^2 planes)
   std::vector<void*> allocs;
   double* kin = nullptr;
   double* vscaled = nullptr;
@@ -803,6 +804,7 @@ pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
   e = fft_set_lds_limits(c->lds_limit);
   if (e == hipSuccess) e = fft_reg_set_lds_limits(c->lds_limit);
   if (e == hipSuccess) e = heev_set_lds_limit(c->lds_limit);
+  if (e == hipSuccess) e = fft_ls_set_lds_limit(c->lds_limit);
   if (e != hipSuccess) {
     (void)hipHostFree(pin);
     delete c;
@@ -1019,6 +1021,7 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   h->reg_plane_ok = h->cfg.reg_plane;
   h->narrow_ok = h->cfg.reg_plane && fft_reg_plane_narrow(P, false);
   h->narrow32_ok = h->cfg.reg_plane && fft_reg_plane_narrow(P, true);
+  h->ls32_ok = h->cfg.reg_plane && fft_plane_ls_supported(P, ctx->lds_limit);
   TRY(dalloc(h, &h->T, per_band * h->chunk));
   if (h->nproj > 0) TRY(dalloc(h, &h->cprj, (size_t)(h->nproj * h->nb_max)));
   size_t wmax = 0;
@@ -1327,9 +1330,9 @@ pw_status pw_ham_set_tuning(pw_ham* h, const pw_tuning* t) {
   if (!h || !t) return fail(nullptr, PW_ERR_INVALID_ARG, "ham or tuning is NULL");
   if ((t->reg_col != 0 && t->reg_col != 1) || (t->reg_plane != 0 && t->reg_plane != 1) ||
       (t->plane_variant != 0 && t->plane_variant != 1) ||
-      (t->plane_variant32 != 0 && t->plane_variant32 != 1))
+      (t->plane_variant32 < 0 || t->plane_variant32 > 2))
     return fail(h->ctx, PW_ERR_INVALID_ARG,
-                "reg_col, reg_plane, plane_variant and plane_variant32 are 0 or 1");
+                "reg_col, reg_plane and plane_variant are 0 or 1, plane_variant32 0, 1 or 2");
   if (t->reg_col && !h->reg_col_ok)
     return fail(h->ctx, PW_ERR_UNSUPPORTED, "no register column kernel for this N3");
   if (t->reg_plane && !h->reg_plane_ok)
@@ -1338,6 +1341,8 @@ pw_status pw_ham_set_tuning(pw_ham* h, const pw_tuning* t) {
     return fail(h->ctx, PW_ERR_UNSUPPORTED, "no 8-lane FP64 plane variant for this (N1, N2)");
   if (t->plane_variant32 == 1 && (!t->reg_plane || !h->narrow32_ok))
     return fail(h->ctx, PW_ERR_UNSUPPORTED, "no 8-lane FP32 plane variant for this (N1, N2)");
+  if (t->plane_variant32 == 2 && (!t->reg_plane || !h->ls32_ok))
+    return fail(h->ctx, PW_ERR_UNSUPPORTED, "no LDS-exchange FP32 plane kernel for this (N1, N2)");
   if (t->chunk < 1 || t->chunk > h->chunk_alloc)
     return fail(h->ctx, PW_ERR_INVALID_ARG,
                 "chunk outside [1, " + std::to_string(h->chunk_alloc) + "]");
@@ -1414,9 +1419,11 @@ pw_status pw_ham_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, pw_
   // 1) FFT kernel families (the plane variant of the precision being tuned)
   const bool lp = prec != PW_FP64;
   const bool nok = lp ? h->narrow32_ok : h->narrow_ok;
+  const bool lsok = lp && h->ls32_ok;
   for (int rc = 0; rc <= (h->reg_col_ok ? 1 : 0); ++rc)
     for (int rp = 0; rp <= (h->reg_plane_ok ? 1 : 0); ++rp)
-      for (int pv = 0; pv <= ((rp && nok) ? 1 : 0); ++pv) {
+      for (int pv = 0; pv <= (rp ? 2 : 0); ++pv) {
+        if ((pv == 1 && !nok) || (pv == 2 && !lsok)) continue;
         pw_tuning t = cur;
         t.reg_col = rc;
         t.reg_plane = rp;

@@ -121,7 +121,7 @@ struct FftLaunchCfg {
   bool reg_col;             // register-resident column kernels available for N3
   bool reg_plane;           // register-resident plane kernel available for (N1, N2)
   int plane_variant;        // FP64 register plane kernel: 0 = lane groups <= 16, 1 = <= 8
-  int plane_variant32;      // the same choice for the FP32 kernel
+  int plane_variant32;      // FP32: 0 / 1 as above, 2 = LDS-exchange kernel (fft_ls.hip)
 };
 
 // Host-side choice of tiles and LDS sizes; returns false if this GPU's LDS
@@ -212,6 +212,12 @@ bool fft_reg_col_supported(int n3);
 bool fft_reg_plane_supported(const BoxPlan& p, size_t lds_limit);
 bool fft_reg_plane_narrow(const BoxPlan& p, bool fp32);   // an 8-lane plane variant exists
 hipError_t fft_reg_set_lds_limits(size_t bytes);
+// FP32 plane kernel with LDS exchanges for N1 = N2 = 144 (fft_ls.hip).
+size_t fft_plane_ls_lds(const BoxPlan& p);
+bool fft_plane_ls_supported(const BoxPlan& p, size_t lds_limit);
+hipError_t launch_fft_plane_ls32(const BoxPlan& p, int nb, const float* vscaled, float2* T,
+                                 hipStream_t s);
+hipError_t fft_ls_set_lds_limit(size_t bytes);
 hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int64_t ldpsi, cplx* T,
                                   hipStream_t s);
 hipError_t launch_fft_plane_reg(const BoxPlan& p, int variant, int nb, const double* vscaled,

@@ -113,3 +113,25 @@ def test_apply_fp32_uneven_box(pw, ctx, cell):
         err = apply_err(pw, ctx, w, 8, prec, seed=cell)
         print(f"C4 cell {cell} box {w.box} {prec} H*psi relative error {err:.3e}")
         assert err < tol
+
+
+def test_apply_fp32_lds_exchange_plane_c5(pw, ctx):
+    """144^3 box (C5 cell, local part): the FP32 plane kernel with LDS
+    exchanges (plane_variant32 = 2) against the lane-shuffle kernel and the
+    FP64 oracle, on a ragged block of 21 bands."""
+    import torch
+    w = synth.config_c5(nb=21, with_proj=False)
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=21, low_prec=True)
+    X0 = synth.start_block(w.npw, 21, 4)
+    X = to_dev(X0).to(torch.complex64)
+    ham.set_tuning({"plane_variant32": 0})
+    H0 = to_host(ham.apply_h(X, prec="fp32")).astype(np.complex128)
+    ham.set_tuning({"plane_variant32": 2})
+    H2 = to_host(ham.apply_h(X, prec="fp32")).astype(np.complex128)
+    d = rel_err(H2, H0)
+    print(f"LDS-exchange vs lane-shuffle FP32 plane kernel: relative difference {d:.3e}")
+    assert d < 1e-6
+    oh = oracle.OracleHam.from_workload(w)
+    for b in (0, 20):
+        ref = oracle.apply_h(oh, X0[b:b + 1].astype(np.complex64).T).T
+        assert rel_err(H2[b:b + 1], ref) < 2e-6, b

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 def all_tunings(ham, nb):
     base = ham.get_tuning()
     out = []
-    for rc, rp, pv, pv32 in itertools.product((0, 1), (0, 1), (0, 1), (0, 1)):
+    for rc, rp, pv, pv32 in itertools.product((0, 1), (0, 1), (0, 1), (0, 1, 2)):
         for ch in sorted({base["chunk"], max(1, base["chunk"] // 2), 1}):
             for gb in (2048, 256):
                 out.append(dict(reg_col=rc, reg_plane=rp, plane_variant=pv, plane_variant32=pv32,
