@@ -7,10 +7,10 @@
 //           outputs X[k1 + P k2] in natural order.
 // Step 1 of a forward transform takes exactly the layout step 2 of a
 // backward one leaves, so a row goes backward, x V/N_box, forward without
-// leaving the registers except for the two exchanges.  The N2 transforms of
-// the extent columns run in place in the plane's extent array E (the
-// positions a lane writes in step 1 are the ones it read); the N1 rows use
-// a per-group exchange buffer.  Lanes of one group always sit in one
+// leaving the registers except for the two exchanges.  Every exchange goes
+// through a per-group buffer whose rows are padded so that the step-2 reads
+// fall in distinct banks; the N2 transforms of the extent columns read and
+// write the plane's extent array E in natural order.  Lanes of one group always sit in one
 // wavefront, whose LDS operations execute in order, so the exchanges need
 // only a compiler-level wavefront fence.
 #include "fft_common.h"
@@ -19,8 +19,11 @@ using namespace pwfft;
 
 namespace {
 
-constexpr int kLsWaves = 10;
-constexpr int kLsThreads = kLsWaves * 64;
+// Up to 16 wavefronts per workgroup; the launch takes as many as the LDS
+// budget leaves room for after the extent array (each wavefront adds the
+// exchange buffers of its 64 / P groups).
+constexpr int kLsMaxWaves = 16;
+constexpr int kLsMinWaves = 4;
 
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -35,58 +38,78 @@ __device__ __forceinline__ void ls_twiddle(float2 (&v)[P], const float2 (&w)[P -
   for (int k = 1; k < P; ++k) v[k] = S > 0 ? conj_mul(v[k], w[k - 1]) : cmul(v[k], w[k - 1]);
 }
 
-// In-place transform (sign S) of the length-P^2 sequence seq[0 .. P^2) in LDS
-// by the P lanes of a group (lane lb): natural order in, natural order out.
-template <int P, int S>
-__device__ __forceinline__ void ls_fft_inplace(float2* seq, int lb, const float2 (&w)[P - 1]) {
-  float2 v[P];
-#pragma unroll
-  for (int a = 0; a < P; ++a) v[a] = seq[P * a + lb];
-  dft_reg<P, S>(v);
-  ls_twiddle<P, S>(v, w);
-#pragma unroll
-  for (int k = 0; k < P; ++k) seq[P * k + lb] = v[k];
-  wave_lds_fence();
-#pragma unroll
-  for (int b = 0; b < P; ++b) v[b] = seq[P * lb + b];
-  dft_reg<P, S>(v);
-  wave_lds_fence();
-#pragma unroll
-  for (int k = 0; k < P; ++k) seq[lb + P * k] = v[k];
-  wave_lds_fence();
-}
+// Exchange buffer of one group: the P x P intermediate, row k at offset
+// P k + k / 4.  The extra entry every fourth row spreads the rows a group
+// reads column-wise in step 2 (lane r reads row r) over distinct LDS banks.
+template <int P>
+__host__ __device__ constexpr int ls_row_off(int k) { return P * k + k / 4; }
+template <int P>
+__host__ __device__ constexpr int ls_buf_len() { return ls_row_off<P>(P - 1) + P; }
+// Distance between the buffers of neighbouring groups: one entry more than a
+// buffer, so the five groups of a wavefront start on staggered banks.
+template <int P>
+__host__ __device__ constexpr int ls_buf_stride() { return ls_buf_len<P>() + 1; }
 
-// Transform (sign S) of the sequence whose element P a + lb sits in v[a] of
-// lane lb; the exchange goes through buf (P^2 entries).  Result: v[k] holds
-// element lb + P k.
+// Step 1 on v (the P values x[P a + lb] of lane lb): P-point DFT, twiddle,
+// store row-wise into buf; step 2: lane lb reads intermediate row lb and
+// transforms it.  Result: v[k] holds element lb + P k.
 template <int P, int S>
 __device__ __forceinline__ void ls_fft_regs(float2 (&v)[P], float2* buf, int lb,
                                             const float2 (&w)[P - 1]) {
   dft_reg<P, S>(v);
   ls_twiddle<P, S>(v, w);
 #pragma unroll
-  for (int k = 0; k < P; ++k) buf[P * k + lb] = v[k];
+  for (int k = 0; k < P; ++k) buf[ls_row_off<P>(k) + lb] = v[k];
   wave_lds_fence();
+  const float2* row = buf + ls_row_off<P>(lb);
 #pragma unroll
-  for (int b = 0; b < P; ++b) v[b] = buf[P * lb + b];
+  for (int b = 0; b < P; ++b) v[b] = row[b];
   dft_reg<P, S>(v);
   wave_lds_fence();
 }
+
+// Transform (sign S) of the length-P^2 sequence seq[0 .. P^2) in LDS by the P
+// lanes of a group, through the group's exchange buffer: natural order in,
+// natural order out.
+template <int P, int S>
+__device__ __forceinline__ void ls_fft_seq(float2* seq, float2* buf, int lb,
+                                           const float2 (&w)[P - 1]) {
+  float2 v[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) v[a] = seq[P * a + lb];
+  ls_fft_regs<P, S>(v, buf, lb, w);
+#pragma unroll
+  for (int k = 0; k < P; ++k) seq[lb + P * k] = v[k];
+}
+
+// Columns handled together by the groups of one wavefront are kColSpacing
+// apart in E: 12 x (P^2 + 1) complex entries is 24 dwords past a multiple of
+// 64 banks, so the groups' contiguous 24-dword slices tile the banks.
+constexpr int kColSpacing = 12;
 
 template <int P>
 __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* __restrict__ tw,
                                               const float* __restrict__ vs, float2* __restrict__ T,
                                               int j3, int b) {
-  constexpr int N = P * P, TRS = N + 1, GPW = 64 / P;
+  constexpr int N = P * P, TRS = N + 1, GPW = 64 / P, XS = ls_buf_stride<P>();
   extern __shared__ __align__(16) char lds_raw[];
   float2* E = reinterpret_cast<float2*>(lds_raw);                      // xr x TRS
-  float2* X = E + (size_t)Pl.xr * TRS;                                 // groups x N
-  int* slot = reinterpret_cast<int*>(X + (size_t)kLsWaves * GPW * N);  // N
   const int tid = threadIdx.x, nt = blockDim.x;
+  float2* X = E + (size_t)Pl.xr * TRS;                                 // groups x N
+  int* slot = reinterpret_cast<int*>(X + (size_t)(nt >> 6) * GPW * XS);  // N
   const int wave = tid >> 6, lw = tid & 63;
   const int gw = lw / P, lb = lw - gw * P;
   const bool act = gw < GPW;
-  const int grp = wave * GPW + gw, ngr = (nt >> 6) * GPW;
+  const int nw = nt >> 6;
+  const int grp = wave * GPW + gw;
+  float2* buf = X + (size_t)grp * XS;
+  // Work items are dealt in tasks of GPW items, one per group of the
+  // wavefront that takes the task, spaced so that the groups' LDS accesses
+  // fall on different banks.  Rows: task t holds rows t + rstride gw.
+  // Extent columns: tasks come in rounds of kColSpacing, task t of round r
+  // holds columns r kColSpacing GPW + t + kColSpacing gw.
+  const int rstride = (N + GPW - 1) / GPW;
+  const int ctasks = kColSpacing * ((Pl.xr + kColSpacing * GPW - 1) / (kColSpacing * GPW));
   float2* tp = T + (size_t)b * Pl.n3 * Pl.ncols + (size_t)j3 * Pl.ncols;
   for (int i = tid; i < Pl.xr * TRS; i += nt) E[i] = czero<float2>();
   for (int i = tid; i < N; i += nt) slot[i] = -1;
@@ -99,16 +122,20 @@ __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* _
   for (int k = 1; k < P; ++k) w[k - 1] = tw[(lb * k) % N];
   // backward along N2 on every extent column
   if (act)
-    for (int e = grp; e < Pl.xr; e += ngr) ls_fft_inplace<P, +1>(E + e * TRS, lb, w);
+    for (int t = wave; t < ctasks; t += nw) {
+      const int e = (t / kColSpacing) * (kColSpacing * GPW) + t % kColSpacing + kColSpacing * gw;
+      if (e < Pl.xr) ls_fft_seq<P, +1>(E + e * TRS, buf, lb, w);
+    }
   __syncthreads();
   // rows: backward along N1, x V/N_box, forward along N1
   if (act) {
     int sl[P];   // extent slot of positions P a + lb (the same set on output: lb + P k)
 #pragma unroll
     for (int a = 0; a < P; ++a) sl[a] = slot[P * a + lb];
-    float2* buf = X + (size_t)grp * N;
     const float* vp = vs + (size_t)j3 * N * N;
-    for (int row = grp; row < N; row += ngr) {
+    for (int t = wave; t < rstride; t += nw) {
+      const int row = t + rstride * gw;
+      if (row >= N) continue;
       float2 v[P];
 #pragma unroll
       for (int a = 0; a < P; ++a) v[a] = sl[a] >= 0 ? E[sl[a] * TRS + row] : czero<float2>();
@@ -126,13 +153,16 @@ __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* _
   __syncthreads();
   // forward along N2
   if (act)
-    for (int e = grp; e < Pl.xr; e += ngr) ls_fft_inplace<P, -1>(E + e * TRS, lb, w);
+    for (int t = wave; t < ctasks; t += nw) {
+      const int e = (t / kColSpacing) * (kColSpacing * GPW) + t % kColSpacing + kColSpacing * gw;
+      if (e < Pl.xr) ls_fft_seq<P, -1>(E + e * TRS, buf, lb, w);
+    }
   __syncthreads();
   for (int c = tid; c < Pl.ncols; c += nt) tp[c] = E[Pl.col_e[c] * TRS + Pl.col_m2[c]];
 }
 
 template <int P>
-__global__ void __launch_bounds__(kLsThreads)
+__global__ void __launch_bounds__(kLsMaxWaves * 64)
 k_plane_ls(BoxPlan Pl, const float2* __restrict__ tw, const float* __restrict__ vs,
            float2* __restrict__ T) {
   plane_ls_body<P>(Pl, tw, vs, T, blockIdx.x, blockIdx.y);
@@ -140,27 +170,41 @@ k_plane_ls(BoxPlan Pl, const float2* __restrict__ tw, const float* __restrict__ 
 
 constexpr int kLsP = 12;   // N1 = N2 = 144
 
-}  // namespace
+size_t g_ls_lds_limit = 64 * 1024;
 
-size_t fft_plane_ls_lds(const BoxPlan& p) {
+size_t ls_lds_bytes(const BoxPlan& p, int waves) {
   constexpr int N = kLsP * kLsP, GPW = 64 / kLsP;
-  return (size_t)p.xr * (N + 1) * sizeof(float2) + (size_t)kLsWaves * GPW * N * sizeof(float2) +
-         (size_t)N * sizeof(int);
+  return (size_t)p.xr * (N + 1) * sizeof(float2) +
+         (size_t)waves * GPW * ls_buf_stride<kLsP>() * sizeof(float2) + (size_t)N * sizeof(int);
 }
 
+// the most wavefronts whose buffers fit next to this plan's extent array
+int ls_waves(const BoxPlan& p, size_t lds_limit) {
+  int w = kLsMaxWaves;
+  while (w >= kLsMinWaves && ls_lds_bytes(p, w) > lds_limit) --w;
+  return w;
+}
+
+}  // namespace
+
+size_t fft_plane_ls_lds(const BoxPlan& p) { return ls_lds_bytes(p, ls_waves(p, g_ls_lds_limit)); }
+
 bool fft_plane_ls_supported(const BoxPlan& p, size_t lds_limit) {
-  return p.n1 == kLsP * kLsP && p.n2 == kLsP * kLsP && fft_plane_ls_lds(p) <= lds_limit;
+  return p.n1 == kLsP * kLsP && p.n2 == kLsP * kLsP && ls_waves(p, lds_limit) >= kLsMinWaves;
 }
 
 hipError_t launch_fft_plane_ls32(const BoxPlan& p, int nb, const float* vscaled, float2* T,
                                  hipStream_t s) {
-  if (p.n1 != kLsP * kLsP || p.n2 != p.n1 || p.ax1.tw32 == nullptr) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_plane_ls<kLsP>, dim3(p.n3, nb), dim3(kLsThreads), fft_plane_ls_lds(p), s, p,
-                     p.ax1.tw32, vscaled, T);
+  const int waves = ls_waves(p, g_ls_lds_limit);
+  if (p.n1 != kLsP * kLsP || p.n2 != p.n1 || p.ax1.tw32 == nullptr || waves < kLsMinWaves)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_plane_ls<kLsP>, dim3(p.n3, nb), dim3(waves * 64), ls_lds_bytes(p, waves), s,
+                     p, p.ax1.tw32, vscaled, T);
   return hipGetLastError();
 }
 
 hipError_t fft_ls_set_lds_limit(size_t bytes) {
+  g_ls_lds_limit = bytes;
   return hipFuncSetAttribute((const void*)k_plane_ls<kLsP>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
