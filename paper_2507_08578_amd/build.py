@@ -27,6 +27,11 @@ CFLAGS = [
 ]
 
 
+# per-source extra flags: the LDS-exchange FFT feeds literal zeros into its
+# pruned transforms, and folding x + 0 -> x needs signed zeros ignored
+FILE_FLAGS = {"fft_ls.hip": ["-fno-signed-zeros"]}
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -36,7 +41,8 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [hipcc(), *CFLAGS, "-I", os.path.join(HERE, "..", "include"), "-c", src, "-o", obj]
+    extra = FILE_FLAGS.get(os.path.basename(src), [])
+    cmd = [hipcc(), *CFLAGS, *extra, "-I", os.path.join(HERE, "..", "include"), "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{res.stdout}\n{res.stderr}")

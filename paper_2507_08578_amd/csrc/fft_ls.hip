@@ -50,12 +50,25 @@ __host__ __device__ constexpr int ls_buf_len() { return ls_row_off<P>(P - 1) + P
 template <int P>
 __host__ __device__ constexpr int ls_buf_stride() { return ls_buf_len<P>() + 1; }
 
+// Index a of the P values a lane holds lies in the outer quarters of the
+// sequence: P a + lb in [0, N/4) or [3N/4, N), i.e. centred index in [-N/4, N/4).
+template <int P>
+__host__ __device__ constexpr bool ls_quarter(int a) { return a < P / 4 || a >= P - P / 4; }
+
 // Step 1 on v (the P values x[P a + lb] of lane lb): P-point DFT, twiddle,
 // store row-wise into buf; step 2: lane lb reads intermediate row lb and
-// transforms it.  Result: v[k] holds element lb + P k.
-template <int P, int S>
+// transforms it.  Result: v[k] holds element lb + P k.  ZIN: the input is
+// zero outside the outer quarters (those v[a] are not read; the DFT folds the
+// zeros away).  Callers that use only the outer-quarter outputs leave the
+// rest unused and the compiler drops their arithmetic.
+template <int P, int S, bool ZIN = false>
 __device__ __forceinline__ void ls_fft_regs(float2 (&v)[P], float2* buf, int lb,
                                             const float2 (&w)[P - 1]) {
+  if constexpr (ZIN) {
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+      if (!ls_quarter<P>(a)) v[a] = czero<float2>();
+  }
   dft_reg<P, S>(v);
   ls_twiddle<P, S>(v, w);
 #pragma unroll
@@ -70,16 +83,19 @@ __device__ __forceinline__ void ls_fft_regs(float2 (&v)[P], float2* buf, int lb,
 
 // Transform (sign S) of the length-P^2 sequence seq[0 .. P^2) in LDS by the P
 // lanes of a group, through the group's exchange buffer: natural order in,
-// natural order out.
-template <int P, int S>
+// natural order out.  ZIN: input zero outside the outer quarters; QOUT: only
+// the outer-quarter outputs are written.
+template <int P, int S, bool ZIN, bool QOUT>
 __device__ __forceinline__ void ls_fft_seq(float2* seq, float2* buf, int lb,
                                            const float2 (&w)[P - 1]) {
   float2 v[P];
 #pragma unroll
-  for (int a = 0; a < P; ++a) v[a] = seq[P * a + lb];
-  ls_fft_regs<P, S>(v, buf, lb, w);
+  for (int a = 0; a < P; ++a)
+    if (!ZIN || ls_quarter<P>(a)) v[a] = seq[P * a + lb];
+  ls_fft_regs<P, S, ZIN>(v, buf, lb, w);
 #pragma unroll
-  for (int k = 0; k < P; ++k) seq[lb + P * k] = v[k];
+  for (int k = 0; k < P; ++k)
+    if (!QOUT || ls_quarter<P>(k)) seq[lb + P * k] = v[k];
 }
 
 // Columns handled together by the groups of one wavefront are kColSpacing
@@ -87,7 +103,11 @@ __device__ __forceinline__ void ls_fft_seq(float2* seq, float2* buf, int lb,
 // 64 banks, so the groups' contiguous 24-dword slices tile the banks.
 constexpr int kColSpacing = 12;
 
-template <int P>
+// Q: every sphere point's centred m1 and m2 lie in [-N/4, N/4) (always so
+// when the box holds the density's sphere), which prunes the transforms:
+// the backward N2 and N1 passes start from data zero outside the outer
+// quarters, the forward ones are needed only there.
+template <int P, bool Q>
 __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* __restrict__ tw,
                                               const float* __restrict__ vs, float2* __restrict__ T,
                                               int j3, int b) {
@@ -111,7 +131,16 @@ __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* _
   const int rstride = (N + GPW - 1) / GPW;
   const int ctasks = kColSpacing * ((Pl.xr + kColSpacing * GPW - 1) / (kColSpacing * GPW));
   float2* tp = T + (size_t)b * Pl.n3 * Pl.ncols + (size_t)j3 * Pl.ncols;
-  for (int i = tid; i < Pl.xr * TRS; i += nt) E[i] = czero<float2>();
+  if constexpr (Q) {
+    // the backward N2 pass reads only the outer quarters of each column
+    constexpr int H = N / 4;
+    for (int i = tid; i < Pl.xr * 2 * H; i += nt) {
+      const int e = i / (2 * H), j = i - e * (2 * H);
+      E[e * TRS + (j < H ? j : j + N - 2 * H)] = czero<float2>();
+    }
+  } else {
+    for (int i = tid; i < Pl.xr * TRS; i += nt) E[i] = czero<float2>();
+  }
   for (int i = tid; i < N; i += nt) slot[i] = -1;
   __syncthreads();
   for (int e = tid; e < Pl.xr; e += nt) slot[Pl.ext_m1[e]] = e;
@@ -124,7 +153,7 @@ __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* _
   if (act)
     for (int t = wave; t < ctasks; t += nw) {
       const int e = (t / kColSpacing) * (kColSpacing * GPW) + t % kColSpacing + kColSpacing * gw;
-      if (e < Pl.xr) ls_fft_seq<P, +1>(E + e * TRS, buf, lb, w);
+      if (e < Pl.xr) ls_fft_seq<P, +1, Q, false>(E + e * TRS, buf, lb, w);
     }
   __syncthreads();
   // rows: backward along N1, x V/N_box, forward along N1
@@ -138,8 +167,9 @@ __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* _
       if (row >= N) continue;
       float2 v[P];
 #pragma unroll
-      for (int a = 0; a < P; ++a) v[a] = sl[a] >= 0 ? E[sl[a] * TRS + row] : czero<float2>();
-      ls_fft_regs<P, +1>(v, buf, lb, w);
+      for (int a = 0; a < P; ++a)
+        if (!Q || ls_quarter<P>(a)) v[a] = sl[a] >= 0 ? E[sl[a] * TRS + row] : czero<float2>();
+      ls_fft_regs<P, +1, Q>(v, buf, lb, w);
       const float* vr = vp + (size_t)row * N + lb;
 #pragma unroll
       for (int k = 0; k < P; ++k) v[k] = cscale(v[k], vr[P * k]);
@@ -147,7 +177,7 @@ __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* _
       // v[k] holds position lb + P k: slot sl[k]
 #pragma unroll
       for (int k = 0; k < P; ++k)
-        if (sl[k] >= 0) E[sl[k] * TRS + row] = v[k];
+        if ((!Q || ls_quarter<P>(k)) && sl[k] >= 0) E[sl[k] * TRS + row] = v[k];
     }
   }
   __syncthreads();
@@ -155,17 +185,17 @@ __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* _
   if (act)
     for (int t = wave; t < ctasks; t += nw) {
       const int e = (t / kColSpacing) * (kColSpacing * GPW) + t % kColSpacing + kColSpacing * gw;
-      if (e < Pl.xr) ls_fft_seq<P, -1>(E + e * TRS, buf, lb, w);
+      if (e < Pl.xr) ls_fft_seq<P, -1, false, Q>(E + e * TRS, buf, lb, w);
     }
   __syncthreads();
   for (int c = tid; c < Pl.ncols; c += nt) tp[c] = E[Pl.col_e[c] * TRS + Pl.col_m2[c]];
 }
 
-template <int P>
+template <int P, bool Q>
 __global__ void __launch_bounds__(kLsMaxWaves * 64)
 k_plane_ls(BoxPlan Pl, const float2* __restrict__ tw, const float* __restrict__ vs,
            float2* __restrict__ T) {
-  plane_ls_body<P>(Pl, tw, vs, T, blockIdx.x, blockIdx.y);
+  plane_ls_body<P, Q>(Pl, tw, vs, T, blockIdx.x, blockIdx.y);
 }
 
 constexpr int kLsP = 12;   // N1 = N2 = 144
@@ -198,13 +228,20 @@ hipError_t launch_fft_plane_ls32(const BoxPlan& p, int nb, const float* vscaled,
   const int waves = ls_waves(p, g_ls_lds_limit);
   if (p.n1 != kLsP * kLsP || p.n2 != p.n1 || p.ax1.tw32 == nullptr || waves < kLsMinWaves)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_plane_ls<kLsP>, dim3(p.n3, nb), dim3(waves * 64), ls_lds_bytes(p, waves), s,
-                     p, p.ax1.tw32, vscaled, T);
+  if (p.quarter12)
+    hipLaunchKernelGGL((k_plane_ls<kLsP, true>), dim3(p.n3, nb), dim3(waves * 64),
+                       ls_lds_bytes(p, waves), s, p, p.ax1.tw32, vscaled, T);
+  else
+    hipLaunchKernelGGL((k_plane_ls<kLsP, false>), dim3(p.n3, nb), dim3(waves * 64),
+                       ls_lds_bytes(p, waves), s, p, p.ax1.tw32, vscaled, T);
   return hipGetLastError();
 }
 
 hipError_t fft_ls_set_lds_limit(size_t bytes) {
   g_ls_lds_limit = bytes;
-  return hipFuncSetAttribute((const void*)k_plane_ls<kLsP>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_plane_ls<kLsP, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_plane_ls<kLsP, true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }

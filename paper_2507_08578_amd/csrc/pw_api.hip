@@ -927,6 +927,11 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
     ext = tmp;
   }
   P.xr = (int)ext.size();
+  P.quarter12 = 1;
+  for (int c = 0; c < P.ncols; ++c) {
+    const int a1 = center(col_m1[c], P.n1), a2 = center(col_m2v[c], P.n2);
+    if (4 * a1 < -P.n1 || 4 * a1 >= P.n1 || 4 * a2 < -P.n2 || 4 * a2 >= P.n2) P.quarter12 = 0;
+  }
   std::vector<int> slot(P.n1, -1);
   for (int e = 0; e < P.xr; ++e) slot[ext[e]] = e;
   std::vector<int> col_e(P.ncols);
@@ -1022,6 +1027,7 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   h->narrow_ok = h->cfg.reg_plane && fft_reg_plane_narrow(P, false);
   h->narrow32_ok = h->cfg.reg_plane && fft_reg_plane_narrow(P, true);
   h->ls32_ok = h->cfg.reg_plane && fft_plane_ls_supported(P, ctx->lds_limit);
+  if (h->ls32_ok) h->cfg.plane_variant32 = 2;   // the faster FP32 plane kernel where it applies
   TRY(dalloc(h, &h->T, per_band * h->chunk));
   if (h->nproj > 0) TRY(dalloc(h, &h->cprj, (size_t)(h->nproj * h->nb_max)));
   size_t wmax = 0;

@@ -38,6 +38,7 @@ struct BoxPlan {
   int* pt_col;              // npw: column of the k-th point (column order)
   int* pt_m3;               // npw: box index m3 of the k-th point (column order)
   int* ext_m1;              // xr: box index m1 of extent slot e
+  int quarter12;            // 1: every point's centred m1 and m2 lie in [-N/4, N/4)
   FftAxis ax1, ax2, ax3;
 };
 

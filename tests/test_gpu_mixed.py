@@ -115,12 +115,18 @@ def test_apply_fp32_uneven_box(pw, ctx, cell):
         assert err < tol
 
 
-def test_apply_fp32_lds_exchange_plane_c5(pw, ctx):
+@pytest.mark.parametrize("shape", ["quarter", "wide"])
+def test_apply_fp32_lds_exchange_plane_c5(pw, ctx, shape):
     """144^3 box (C5 cell, local part): the FP32 plane kernel with LDS
     exchanges (plane_variant32 = 2) against the lane-shuffle kernel and the
-    FP64 oracle, on a ragged block of 21 bands."""
+    FP64 oracle, on a ragged block of 21 bands.  "quarter": C5 at 20 Ha, the
+    sphere (|m| <= 31) lies inside the outer quarters of every axis and the
+    kernel prunes its transforms; "wide": the cell stretched 6% along a2 at
+    25 Ha, m2 reaches +-36 and the transforms run whole."""
     import torch
-    w = synth.config_c5(nb=21, with_proj=False)
+    strain, ecut = ((0.0, 0.0, 0.0), 20.0) if shape == "quarter" else ((0.0, 0.06, 0.0), 25.0)
+    w = synth.make_workload("C5", synth.diamond_cell(reps=(3, 3, 3), strain=strain), (0.0, 0.0, 0.0),
+                            ecut, (144, 144, 144), "sp", nb=21, degree=12, iters=1, with_proj=False)
     ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=21, low_prec=True)
     X0 = synth.start_block(w.npw, 21, 4)
     X = to_dev(X0).to(torch.complex64)
@@ -129,7 +135,7 @@ def test_apply_fp32_lds_exchange_plane_c5(pw, ctx):
     ham.set_tuning({"plane_variant32": 2})
     H2 = to_host(ham.apply_h(X, prec="fp32")).astype(np.complex128)
     d = rel_err(H2, H0)
-    print(f"LDS-exchange vs lane-shuffle FP32 plane kernel: relative difference {d:.3e}")
+    print(f"{shape}: LDS-exchange vs lane-shuffle FP32 plane kernel: relative difference {d:.3e}")
     assert d < 1e-6
     oh = oracle.OracleHam.from_workload(w)
     for b in (0, 20):
