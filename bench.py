@@ -65,26 +65,41 @@ def make_workload(name):
 BATCHED = ("C2", "C4")
 
 
-COUNTER_FILES = {   # (config, precision, stage) -> committed rocprofv3 counter summary
-    ("C5", "fp32", "fft_plane"): "profiles/c5_plane_fp32_counters.md",
+# (config, precision, stage, kernel) -> committed rocprofv3 counter summary and
+# the sources whose hash it records
+COUNTER_FILES = {
+    ("C5", "fp32", "fft_plane", "k_plane_reg"): (
+        "profiles/c5_plane_fp32_counters.md",
+        ("paper_2507_08578_amd/csrc/fft_reg.hip", "paper_2507_08578_amd/csrc/fft_common.h")),
+    ("C5", "fp32", "fft_plane", "k_plane_ls"): (
+        "profiles/c5_plane_ls_fp32_counters.md",
+        ("paper_2507_08578_amd/csrc/fft_ls.hip", "paper_2507_08578_amd/csrc/fft_common.h")),
 }
-KERNEL_SOURCES = ("paper_2507_08578_amd/csrc/fft_reg.hip", "paper_2507_08578_amd/csrc/fft_common.h")
 
 
-def measured_traffic(config, prec, stage, bands_per_launch):
+def plane_kernel(ham, prec):
+    """Name of the plane kernel the handle's tuning selects for this precision."""
+    t = ham.get_tuning()
+    if prec != "fp64" and t["reg_plane"] and t["plane_variant32"] == 2:
+        return "k_plane_ls"
+    return "k_plane_reg" if t["reg_plane"] else "k_plane"
+
+
+def measured_traffic(config, prec, stage, kernel, bands_per_launch):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary,
     or None when there is none or the kernel sources changed since it was taken."""
     import hashlib
-    rel = COUNTER_FILES.get((config, prec, stage))
-    if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
+    entry = COUNTER_FILES.get((config, prec, stage, kernel))
+    if entry is None or not os.path.exists(os.path.join(ROOT, entry[0])):
         return None
+    rel, sources = entry
     vals = {}
     for line in open(os.path.join(ROOT, rel)):
         if ":" in line and not line.startswith(("#", "|", "`")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     h = hashlib.sha1()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if vals.get("kernel_source_sha1") != h.hexdigest() or "traffic_bytes_per_band" not in vals:
         return None
@@ -104,7 +119,9 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
     Rayleigh-Ritz product stays FP64 and is not counted here).
     nonlocal (H psi += P C): MFMA, 8 npw nproj nb flop per launch.
     fft_plane: vector ALU, per band and z-plane 2 (xr 5 N2 log2 N2 + N2 5 N1 log2 N1)
-               + 2 N1 N2 flop (the V product), per launch x bands in the launch.
+               + 2 N1 N2 flop (the V product), per launch x bands in the launch
+               (full-length transforms: a kernel that prunes the zero inputs and
+               unused outputs does less arithmetic than this count).
     fft_col_inv / fft_col_fwd: HBM, (npw + ncols N3) / (ncols N3 + 2 npw) elements per band.
     """
     N1, N2, N3 = w.box
@@ -133,9 +150,10 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
         fl = per_band * bands_per_launch
         peak = PEAK["fp64_valu" if prec == "fp64" else "fp32_valu"]
         ach = fl / (avg_ms * 1e-3) / 1e12
-        return {"kernel": "k_plane_reg (N2/N1 transforms x V per z-plane)", "bound": "alu",
+        kname = plane_kernel(ham, prec)
+        return {"kernel": f"{kname} (N2/N1 transforms x V per z-plane)", "bound": "alu",
                 "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                "traffic": measured_traffic(config, prec, dom, bands_per_launch),
+                "traffic": measured_traffic(config, prec, dom, kname, bands_per_launch),
                 "avg_launch_ms": avg_ms,
                 "per_launch": f"{per_band:.4g} flop/band (5 N log2 N per transform) x "
                               f"{bands_per_launch:.0f} bands",
@@ -457,11 +475,12 @@ def main():
 
     tune(args.precision)
     res = run_path(pw, ctx, ham, w, X0, b, args.precision, args.steps, args.warmup)
+    # (before the FP64 run retunes the handle: the roofline names the kernels just timed)
+    roof = roofline(res["stages"], args.steps, w, ham, nb, args.precision, args.config)
     ref = None
     if mixed and not args.no_compare:
         tune("fp64")
         ref = run_path(pw, ctx, ham, w, X0, b, "fp64", args.steps, args.warmup)
-    roof = roofline(res["stages"], args.steps, w, ham, nb, args.precision, args.config)
     dtype = "f64" if not mixed else ("f32+f64" if args.precision == "fp32" else "bf16/f32+f64")
     out = {
         "metric": METRIC, "value": res["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,

@@ -548,47 +548,97 @@ __device__ __forceinline__ Rot pos_rot(const cplx* A, int P, int n2) {
   return make_rot(A[p + (int64_t)p * n2].x, A[q + (int64_t)q * n2].x, A[p + (int64_t)q * n2]);
 }
 
-// A: n2 x n2 (ld n2), V: n x n2 (ld n).  Threads [0, h*h) own 2x2 blocks of A
-// (consecutive threads walk down a block column), [h*h, h*h + n*h) own V row pairs.
-__global__ void k_jacobi_round(int n, int n2, const cplx* __restrict__ Ai, cplx* __restrict__ Ao,
-                               const cplx* __restrict__ Vi, cplx* __restrict__ Vo) {
+// Rotation of the pair at positions (2P, 2P+1) in one round, as applied to
+// the rows of V (cs = 1, sn = 0 when the pair does not rotate).
+struct RotV {
+  double cs, sn, phx, phy;
+};
+
+// One round on A (n2 x n2, ld n2): thread (P, Qb) owns the 2x2 block at
+// positions (2P, 2Qb); consecutive threads walk down a block column.  The
+// diagonal-block threads record their pair's rotation in rot[P].
+__global__ void k_jacobi_round(int n2, const cplx* __restrict__ Ai, cplx* __restrict__ Ao,
+                               RotV* __restrict__ rot) {
   const int h = n2 / 2;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nblk = (int64_t)h * h;
-  if (idx < nblk) {
-    const int Qb = (int)(idx / h), P = (int)(idx - (int64_t)Qb * h);
-    const Rot RP = pos_rot(Ai, P, n2);
-    const Rot RQ = pos_rot(Ai, Qb, n2);
-    const int r0 = 2 * P, c0 = 2 * Qb;
-    cplx x11 = Ai[r0 + (int64_t)c0 * n2], x21 = Ai[r0 + 1 + (int64_t)c0 * n2];
-    cplx x12 = Ai[r0 + (int64_t)(c0 + 1) * n2], x22 = Ai[r0 + 1 + (int64_t)(c0 + 1) * n2];
-    if (P == Qb) {
-      if (RP.on) {
-        x11 = make_double2(x11.x - RP.t, 0.0);
-        x22 = make_double2(x22.x + RP.t, 0.0);
-        x12 = make_double2(0.0, 0.0);
-        x21 = make_double2(0.0, 0.0);
-      }
-    } else if (RP.on || RQ.on) {
-      rot_block(RP, RQ, &x11, &x12, &x21, &x22);
-    }
-    const int nr0 = jac_next_pos(r0, n2), nr1 = jac_next_pos(r0 + 1, n2);
-    const int nc0 = jac_next_pos(c0, n2), nc1 = jac_next_pos(c0 + 1, n2);
-    Ao[nr0 + (int64_t)nc0 * n2] = x11;
-    Ao[nr1 + (int64_t)nc0 * n2] = x21;
-    Ao[nr0 + (int64_t)nc1 * n2] = x12;
-    Ao[nr1 + (int64_t)nc1 * n2] = x22;
-    return;
-  }
-  const int64_t vi = idx - nblk;
-  if (vi >= (int64_t)n * h) return;
-  const int Qb = (int)(vi / n), i = (int)(vi - (int64_t)Qb * n);
+  if (idx >= (int64_t)h * h) return;
+  const int Qb = (int)(idx / h), P = (int)(idx - (int64_t)Qb * h);
+  const Rot RP = pos_rot(Ai, P, n2);
   const Rot RQ = pos_rot(Ai, Qb, n2);
-  const int c0 = 2 * Qb;
-  cplx x1 = Vi[i + (int64_t)c0 * n], x2 = Vi[i + (int64_t)(c0 + 1) * n];
-  if (RQ.on) rot_row(RQ, &x1, &x2);
-  Vo[i + (int64_t)jac_next_pos(c0, n2) * n] = x1;
-  Vo[i + (int64_t)jac_next_pos(c0 + 1, n2) * n] = x2;
+  const int r0 = 2 * P, c0 = 2 * Qb;
+  cplx x11 = Ai[r0 + (int64_t)c0 * n2], x21 = Ai[r0 + 1 + (int64_t)c0 * n2];
+  cplx x12 = Ai[r0 + (int64_t)(c0 + 1) * n2], x22 = Ai[r0 + 1 + (int64_t)(c0 + 1) * n2];
+  if (P == Qb) {
+    RotV rv;
+    rv.cs = RP.cs;
+    rv.sn = RP.sn;
+    rv.phx = RP.ph.x;
+    rv.phy = RP.ph.y;
+    rot[P] = rv;
+    if (RP.on) {
+      x11 = make_double2(x11.x - RP.t, 0.0);
+      x22 = make_double2(x22.x + RP.t, 0.0);
+      x12 = make_double2(0.0, 0.0);
+      x21 = make_double2(0.0, 0.0);
+    }
+  } else if (RP.on || RQ.on) {
+    rot_block(RP, RQ, &x11, &x12, &x21, &x22);
+  }
+  const int nr0 = jac_next_pos(r0, n2), nr1 = jac_next_pos(r0 + 1, n2);
+  const int nc0 = jac_next_pos(c0, n2), nc1 = jac_next_pos(c0 + 1, n2);
+  Ao[nr0 + (int64_t)nc0 * n2] = x11;
+  Ao[nr1 + (int64_t)nc0 * n2] = x21;
+  Ao[nr0 + (int64_t)nc1 * n2] = x12;
+  Ao[nr1 + (int64_t)nc1 * n2] = x22;
+}
+
+// V (n x n2, ld n, columns in position space) <- V G_0 G_1 ... G_{nr-1}: the
+// rotations of nr consecutive rounds (rot: nr x h, round-major) applied to R
+// rows of V per workgroup, staged in LDS (two n2 x R buffers, element (row r,
+// position c) at c R + r).  Rows are independent under V <- V G, so the
+// whole sweep runs without a grid-wide step; each element sees the same
+// operations as a per-round update.
+template <int R>
+__global__ void __launch_bounds__(1024)
+k_jacobi_v_rounds(int n, int n2, int nr, const RotV* __restrict__ rot, cplx* __restrict__ V) {
+  extern __shared__ cplx vbuf[];
+  cplx* b0 = vbuf;
+  cplx* b1 = vbuf + (size_t)n2 * R;
+  const int i0 = blockIdx.x * R, h = n2 / 2;
+  for (int e = threadIdx.x; e < n2 * R; e += blockDim.x) {
+    const int c = e / R, r = e - c * R;
+    b0[e] = (i0 + r < n) ? V[(i0 + r) + (int64_t)c * n] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int rr = 0; rr < nr; ++rr) {
+    const RotV* rp = rot + (int64_t)rr * h;
+    for (int P = threadIdx.x; P < h; P += blockDim.x) {
+      const RotV q = rp[P];
+      Rot Q;
+      Q.cs = q.cs;
+      Q.sn = q.sn;
+      Q.t = 0.0;
+      Q.ph = make_double2(q.phx, q.phy);
+      Q.on = true;
+      const int c0 = 2 * P, c1 = 2 * P + 1;
+      const int d0 = jac_next_pos(c0, n2), d1 = jac_next_pos(c1, n2);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        cplx x1 = b0[c0 * R + r], x2 = b0[c1 * R + r];
+        rot_row(Q, &x1, &x2);
+        b1[d0 * R + r] = x1;
+        b1[d1 * R + r] = x2;
+      }
+    }
+    __syncthreads();
+    cplx* t = b0;
+    b0 = b1;
+    b1 = t;
+  }
+  for (int e = threadIdx.x; e < n2 * R; e += blockDim.x) {
+    const int c = e / R, r = e - c * R;
+    if (i0 + r < n) V[(i0 + r) + (int64_t)c * n] = b0[e];
+  }
 }
 
 // A0 = [a 0; 0 0] (n2 x n2), V0 = [I 0] (n x n2)
@@ -981,7 +1031,18 @@ hipError_t launch_identity(int64_t n, cplx* a, int64_t lda, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Work layout for n > 64: A0, A1 (n2 x n2), V0, V1 (n x n2), n ints of ranks,
+static size_t g_heev_lds_limit = 64 * 1024;
+
+// rows of V per workgroup in the per-sweep V update: as many (4, 2, 1) as
+// two n2-long LDS buffers allow; 0 if not even one row fits
+static int jac_v_rows(int64_t n2) {
+  for (int r = 4; r >= 1; r /= 2)
+    if ((size_t)2 * n2 * r * sizeof(cplx) <= g_heev_lds_limit) return r;
+  return 0;
+}
+
+// Work layout for n > 64: A0, A1 (n2 x n2), V (n x n2), a sweep of rotations
+// (in a second n x n2 slot), n ints of ranks,
 // then two 16-byte aligned doubles.
 size_t heev_work_bytes(int64_t n) {
   const int64_t n2 = n + (n & 1);
@@ -989,8 +1050,11 @@ size_t heev_work_bytes(int64_t n) {
 }
 
 hipError_t heev_set_lds_limit(size_t bytes) {
-  const void* fns[4] = {(const void*)k_jacobi_small, (const void*)k_chol_diag,
-                        (const void*)kb_jacobi, (const void*)kb_chol_diag};
+  g_heev_lds_limit = bytes;
+  const void* fns[7] = {(const void*)k_jacobi_small, (const void*)k_chol_diag,
+                        (const void*)kb_jacobi, (const void*)kb_chol_diag,
+                        (const void*)k_jacobi_v_rounds<4>, (const void*)k_jacobi_v_rounds<2>,
+                        (const void*)k_jacobi_v_rounds<1>};
   for (const void* f : fns) {
     hipFuncAttributes at;
     hipError_t e = hipFuncGetAttributes(&at, f);
@@ -1032,17 +1096,22 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
     *sweeps_done = hs;
     return e;
   }
+  if (jac_v_rows(n2) == 0) return hipErrorInvalidValue;   // a row of V must fit in LDS
   cplx* A0 = reinterpret_cast<cplx*>(base);
   cplx* A1 = A0 + n2 * n2;
   cplx* V0 = A1 + n2 * n2;
-  cplx* V1 = V0 + n * n2;
+  // one sweep's rotations ((n2 - 1) rounds x n2/2 pairs x 32 B) in the second
+  // V-sized slot of the layout (n2 (n2 - 1) 16 B <= n n2 16 B)
+  RotV* rots = reinterpret_cast<RotV*>(V0 + n * n2);
   hipLaunchKernelGGL(k_jacobi_init, dim3(nblocks(n2 * n2 + n * n2, 256)), dim3(256), 0, s, (int)n,
                      (int)n2, (const cplx*)a, lda, A0, V0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t h = n2 / 2;
-  const int64_t threads = h * h + n * h;
   const double tl = std::max(1e-15, 2.2e-16 * (double)n);
+  const int vrows = jac_v_rows(n2);
+  const size_t vlds = (size_t)2 * n2 * vrows * sizeof(cplx);
+  const int vthreads = (int)std::min<int64_t>(1024, ((h + 63) / 64) * 64);
   int sw = 0, rounds = 0;
   bool conv = false;
   for (; sw <= kMaxSweeps; ++sw) {
@@ -1057,12 +1126,21 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
     }
     if (sw == kMaxSweeps) break;
     for (int r = 0; r < n2 - 1; ++r) {
-      hipLaunchKernelGGL(k_jacobi_round, dim3(nblocks(threads, 256)), dim3(256), 0, s, (int)n,
-                         (int)n2, (const cplx*)A0, A1, (const cplx*)V0, V1);
+      hipLaunchKernelGGL(k_jacobi_round, dim3(nblocks(h * h, 256)), dim3(256), 0, s, (int)n2,
+                         (const cplx*)A0, A1, rots + (int64_t)r * h);
       std::swap(A0, A1);
-      std::swap(V0, V1);
       ++rounds;
     }
+    const dim3 vgrid((unsigned)((n + vrows - 1) / vrows));
+    if (vrows == 4)
+      hipLaunchKernelGGL(k_jacobi_v_rounds<4>, vgrid, dim3(vthreads), vlds, s, (int)n, (int)n2,
+                         (int)(n2 - 1), (const RotV*)rots, V0);
+    else if (vrows == 2)
+      hipLaunchKernelGGL(k_jacobi_v_rounds<2>, vgrid, dim3(vthreads), vlds, s, (int)n, (int)n2,
+                         (int)(n2 - 1), (const RotV*)rots, V0);
+    else
+      hipLaunchKernelGGL(k_jacobi_v_rounds<1>, vgrid, dim3(vthreads), vlds, s, (int)n, (int)n2,
+                         (int)(n2 - 1), (const RotV*)rots, V0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
