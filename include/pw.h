@@ -299,8 +299,9 @@ pw_status pw_gemm_nn(pw_ctx* ctx, int64_t m, int64_t n, int64_t k, double alpha_
                      const void* a_dev, int64_t lda, const void* b_dev, int64_t ldb,
                      double beta_re, void* c_dev, int64_t ldc);
 /* Hermitian eigendecomposition a = Q diag(w) Q^H (n x n, lda) by cyclic
- * Jacobi: a is destroyed, q_dev (n x n, ldq) receives Q, w_dev ascending.
- * Synchronises.  NO_CONVERGENCE after the sweep limit. */
+ * Jacobi (n > 64: block Jacobi over blocks of 32, one inner sweep per block
+ * pair): a is destroyed, q_dev (n x n, ldq) receives Q, w_dev ascending.
+ * Synchronises once per sweep.  NO_CONVERGENCE after the sweep limit. */
 pw_status pw_heev(pw_ctx* ctx, int64_t n, void* a_dev, int64_t lda, double* w_dev,
                   void* q_dev, int64_t ldq);
 /* Upper Cholesky factor in place: a = U^H U (upper triangle of a read and

@@ -8,8 +8,9 @@
 //  * heev      : cyclic two-sided Jacobi with the round-robin (circle)
 //                ordering: in each round all n/2 disjoint pairs rotate at
 //                once, A <- G^H A G, V <- V G.  For n <= 64 the whole solve
-//                runs in one workgroup with A and V in LDS; larger n run one
-//                kernel per round in position space (pairs adjacent).
+//                runs in one workgroup with A and V in LDS; larger n run a
+//                block Jacobi whose block pairs take one such sweep each in
+//                LDS, applied to A and V as tiled products.
 #include "pw_internal.h"
 
 #include <algorithm>
@@ -312,22 +313,44 @@ __device__ __forceinline__ void rr_pair(int r, int k, int n2, int* p, int* q) {
   *q = max(a, b);
 }
 
+// 1/sqrt(x) and 1/x for x > 0 (normal): the hardware estimate refined by two
+// Newton steps (each doubles the correct bits), much shorter dependency
+// chains than the correctly rounded sequences; about 1 ulp.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+
 // Rotation J = [[cs, sn ph], [-sn conj(ph), cs]] with J^H [[a, c], [conj c, b]] J diagonal:
 // tau = (b - a)/(2|c|), t = sign(tau)/(|tau| + sqrt(1 + tau^2)), cs = 1/sqrt(1+t^2), sn = t cs;
-// new diagonal a - t|c|, b + t|c|.
-// (Matrix entries here are O(1) Hamiltonian elements: |c| is formed without
-// the overflow guard of hypot.)
+// new diagonal a - t|c|, b + t|c|.  |c| below 1e-150 (|c|^2 near the
+// denormal range) counts as zero: no rotation.  (Matrix entries here are
+// O(1) Hamiltonian elements.)
 __device__ __forceinline__ Rot make_rot(double a, double b, cplx c) {
   Rot R;
-  const double mag = sqrt(c.x * c.x + c.y * c.y);
-  if (!(mag > DBL_MIN)) {
+  const double m2 = c.x * c.x + c.y * c.y;
+  if (!(m2 > 1e-300)) {
     R.cs = 1.0; R.sn = 0.0; R.t = 0.0; R.ph = make_double2(1.0, 0.0); R.on = false;
     return R;
   }
-  const double rmag = 1.0 / mag;
+  const double rmag = rsqrt_nr(m2);
+  const double mag = m2 * rmag;
   const double tau = 0.5 * (b - a) * rmag;
-  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  R.cs = 1.0 / sqrt(1.0 + t * t);
+  const double at = fabs(tau);
+  // for |tau| > 1e100, sqrt(1 + tau^2) = |tau| to working precision
+  const double u = 1.0 + tau * tau;
+  const double root = at > 1e100 ? at : u * rsqrt_nr(u);
+  const double t = copysign(rcp_nr(at + root), tau);
+  R.cs = rsqrt_nr(1.0 + t * t);
   R.sn = t * R.cs;
   R.t = t * mag;
   R.ph = make_double2(c.x * rmag, c.y * rmag);
@@ -384,8 +407,11 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
   extern __shared__ cplx sm[];
   const int n2 = n + (n & 1);
   const int h = n2 / 2;
-  cplx* a = sm;               // n x n, ld n
-  cplx* v = sm + n * n;       // n x n
+  // A with an odd leading dimension: the 2x2 blocks a round updates sit in
+  // columns n + 1 entries apart, which spreads them over the LDS banks
+  const int la = n + 1;
+  cplx* a = sm;               // n x n, ld la
+  cplx* v = sm + n * la;      // n x n, ld n
   __shared__ Rot rots[kJacSmallMax / 2];
   __shared__ int pp[kJacSmallMax / 2], pq[kJacSmallMax / 2];   // this round's pairs
   __shared__ double red[kJacThreads];
@@ -395,7 +421,7 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int idx = tid; idx < n * n; idx += nt) {
     const int j = idx / n, i = idx - j * n;
-    a[idx] = Ain[i + (int64_t)j * lda];
+    a[i + j * la] = Ain[i + (int64_t)j * lda];
     v[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   if (tid == 0) done = 0;
@@ -408,7 +434,7 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
       double off = 0.0, tot = 0.0;
       for (int idx = tid; idx < n * n; idx += 64) {
         const int j = idx / n, i = idx - j * n;
-        const double m2 = cabs2(a[idx]);
+        const double m2 = cabs2(a[i + j * la]);
         tot += m2;
         if (i != j) off += m2;
       }
@@ -435,7 +461,7 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
         rr_pair(r, tid, n2, &p, &q);
         pp[tid] = p;
         pq[tid] = q;
-        if (q < n) rots[tid] = make_rot(a[p + p * n].x, a[q + q * n].x, a[p + q * n]);
+        if (q < n) rots[tid] = make_rot(a[p + p * la].x, a[q + q * la].x, a[p + q * la]);
         else rots[tid] = make_rot(0.0, 0.0, make_double2(0.0, 0.0));
       }
       __syncthreads();
@@ -447,39 +473,39 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
         if (q1 >= n || q2 >= n) {
           // pairs holding the padding index rotate nothing; update the real rows/cols only
           if (q1 < n && RP.on) {   // Q pair is (p2, pad): column p2 only
-            cplx x1 = a[p1 + p2 * n], x2 = a[q1 + p2 * n];
+            cplx x1 = a[p1 + p2 * la], x2 = a[q1 + p2 * la];
             cplx y1 = x1, y2 = x2;
             // Jp^H [x1; x2]
             const cplx p12 = cscale(RP.ph, -RP.sn), p21 = cscale(cconj(RP.ph), RP.sn);
             y1 = cadd(cscale(x1, RP.cs), cmul(p12, x2));
             y2 = cadd(cmul(p21, x1), cscale(x2, RP.cs));
-            a[p1 + p2 * n] = y1;
-            a[q1 + p2 * n] = y2;
+            a[p1 + p2 * la] = y1;
+            a[q1 + p2 * la] = y2;
           } else if (q2 < n && RQ.on) {   // P pair is (p1, pad): row p1 only
-            cplx x1 = a[p1 + p2 * n], x2 = a[p1 + q2 * n];
+            cplx x1 = a[p1 + p2 * la], x2 = a[p1 + q2 * la];
             rot_row(RQ, &x1, &x2);
-            a[p1 + p2 * n] = x1;
-            a[p1 + q2 * n] = x2;
+            a[p1 + p2 * la] = x1;
+            a[p1 + q2 * la] = x2;
           }
           continue;
         }
         if (P == Qb) {
           if (RP.on) {
-            const double ap = a[p1 + p1 * n].x, aq = a[q1 + q1 * n].x;
-            a[p1 + p1 * n] = make_double2(ap - RP.t, 0.0);
-            a[q1 + q1 * n] = make_double2(aq + RP.t, 0.0);
-            a[p1 + q1 * n] = make_double2(0.0, 0.0);
-            a[q1 + p1 * n] = make_double2(0.0, 0.0);
+            const double ap = a[p1 + p1 * la].x, aq = a[q1 + q1 * la].x;
+            a[p1 + p1 * la] = make_double2(ap - RP.t, 0.0);
+            a[q1 + q1 * la] = make_double2(aq + RP.t, 0.0);
+            a[p1 + q1 * la] = make_double2(0.0, 0.0);
+            a[q1 + p1 * la] = make_double2(0.0, 0.0);
           }
           continue;
         }
         if (!RP.on && !RQ.on) continue;
-        cplx x11 = a[p1 + p2 * n], x12 = a[p1 + q2 * n], x21 = a[q1 + p2 * n], x22 = a[q1 + q2 * n];
+        cplx x11 = a[p1 + p2 * la], x12 = a[p1 + q2 * la], x21 = a[q1 + p2 * la], x22 = a[q1 + q2 * la];
         rot_block(RP, RQ, &x11, &x12, &x21, &x22);
-        a[p1 + p2 * n] = x11;
-        a[p1 + q2 * n] = x12;
-        a[q1 + p2 * n] = x21;
-        a[q1 + q2 * n] = x22;
+        a[p1 + p2 * la] = x11;
+        a[p1 + q2 * la] = x12;
+        a[q1 + p2 * la] = x21;
+        a[q1 + q2 * la] = x22;
       }
       for (int idx = tid; idx < n * h; idx += nt) {
         const int Qb = idx / n, i = idx - Qb * n;
@@ -495,16 +521,16 @@ __device__ __forceinline__ void jacobi_small_body(int n, const cplx* __restrict_
   }
   // sort ascending (rank by value, ties by index) and write out
   for (int i = tid; i < n; i += nt) {
-    const double di = a[i + i * n].x;
+    const double di = a[i + i * la].x;
     int rk = 0;
     for (int j = 0; j < n; ++j) {
-      const double dj = a[j + j * n].x;
+      const double dj = a[j + j * la].x;
       if (dj < di || (dj == di && j < i)) ++rk;
     }
     rank_[i] = rk;
   }
   __syncthreads();
-  for (int i = tid; i < n; i += nt) w[rank_[i]] = a[i + i * n].x;
+  for (int i = tid; i < n; i += nt) w[rank_[i]] = a[i + i * la].x;
   for (int idx = tid; idx < n * n; idx += nt) {
     const int j = idx / n, i = idx - j * n;
     Q[i + (int64_t)rank_[j] * ldq] = v[i + j * n];
@@ -518,126 +544,196 @@ k_jacobi_small(int n, const cplx* __restrict__ Ain, int64_t lda, double* __restr
   jacobi_small_body(n, Ain, lda, w, Q, ldq, sweeps_out);
 }
 
-// Rounds for n > 64 run in "position space": the n2 x n2 matrix (n2 = n
-// rounded up to even, padding row/column zero) is stored so that the pair k
-// of every round occupies positions (2k, 2k+1).  Position 0 holds a fixed
-// player; positions 1..n2-1 are the slots of a circle (odd position 2s+1 is
-// slot s < n2/2, even position 2(n2-1-s) is slot s >= n2/2) and after every
-// round each circle player moves to the next slot.  This is the circle-method
-// ordering, so n2-1 rounds meet every pair once; each round reads contiguous
-// 2x2 blocks and writes them to the players' next positions (ping-pong).
-__device__ __forceinline__ int jac_next_pos(int pos, int n2) {
-  if (pos == 0) return 0;
-  const int h = n2 / 2;
-  const int slot = (pos & 1) ? (pos - 1) / 2 : n2 - 1 - pos / 2;
-  const int ns = (slot + 1 == n2 - 1) ? 0 : slot + 1;
-  return ns < h ? 2 * ns + 1 : 2 * (n2 - 1 - ns);
+// n > 64: block Jacobi.  The matrix (padded with zero rows and columns to
+// n2p, a multiple of 2 kBJ) is cut into blocks of kBJ indices; an outer
+// round pairs the blocks by the circle method and, for every pair (I, J) at
+// once, runs one cyclic Jacobi sweep on the 2 kBJ x 2 kBJ sub-problem
+// A[I u J, I u J] in LDS, accumulating its rotations in a unitary Q_k; then
+// A <- G^H A G and V <- V G with G the block-diagonal product of the Q_k, as
+// two tiled products.  Every index pair meets in each outer sweep (pairs
+// inside a block in every round), so the outer sweeps converge like cyclic
+// Jacobi, with 3 launches per outer round instead of one per scalar round.
+// Padding indices have zero rows and columns and never rotate.
+constexpr int kBJ = 16;           // block size
+constexpr int kBJS = 2 * kBJ;     // sub-problem size
+constexpr int kBJTile = 64;       // row / column tile of the update products
+constexpr int kBJThreads = 1024;  // workgroup of the update products
+
+// global index of sub-problem index i of block pair (I, J)
+__device__ __forceinline__ int bj_index(int i, int I, int J) {
+  return i < kBJ ? I * kBJ + i : J * kBJ + (i - kBJ);
 }
 
-// Position of player p after r rounds (player p starts at position p).
-__device__ __forceinline__ int jac_pos_after(int p, int r, int n2) {
-  if (p == 0) return 0;
-  const int h = n2 / 2;
-  const int slot0 = (p & 1) ? (p - 1) / 2 : n2 - 1 - p / 2;
-  const int ns = (int)(((int64_t)slot0 + r) % (n2 - 1));
-  return ns < h ? 2 * ns + 1 : 2 * (n2 - 1 - ns);
-}
-
-__device__ __forceinline__ Rot pos_rot(const cplx* A, int P, int n2) {
-  const int p = 2 * P, q = 2 * P + 1;
-  return make_rot(A[p + (int64_t)p * n2].x, A[q + (int64_t)q * n2].x, A[p + (int64_t)q * n2]);
-}
-
-// Rotation of the pair at positions (2P, 2P+1) in one round, as applied to
-// the rows of V (cs = 1, sn = 0 when the pair does not rotate).
-struct RotV {
-  double cs, sn, phx, phy;
-};
-
-// One round on A (n2 x n2, ld n2): thread (P, Qb) owns the 2x2 block at
-// positions (2P, 2Qb); consecutive threads walk down a block column.  The
-// diagonal-block threads record their pair's rotation in rot[P].
-__global__ void k_jacobi_round(int n2, const cplx* __restrict__ Ai, cplx* __restrict__ Ao,
-                               RotV* __restrict__ rot) {
-  const int h = n2 / 2;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)h * h) return;
-  const int Qb = (int)(idx / h), P = (int)(idx - (int64_t)Qb * h);
-  const Rot RP = pos_rot(Ai, P, n2);
-  const Rot RQ = pos_rot(Ai, Qb, n2);
-  const int r0 = 2 * P, c0 = 2 * Qb;
-  cplx x11 = Ai[r0 + (int64_t)c0 * n2], x21 = Ai[r0 + 1 + (int64_t)c0 * n2];
-  cplx x12 = Ai[r0 + (int64_t)(c0 + 1) * n2], x22 = Ai[r0 + 1 + (int64_t)(c0 + 1) * n2];
-  if (P == Qb) {
-    RotV rv;
-    rv.cs = RP.cs;
-    rv.sn = RP.sn;
-    rv.phx = RP.ph.x;
-    rv.phy = RP.ph.y;
-    rot[P] = rv;
-    if (RP.on) {
-      x11 = make_double2(x11.x - RP.t, 0.0);
-      x22 = make_double2(x22.x + RP.t, 0.0);
-      x12 = make_double2(0.0, 0.0);
-      x21 = make_double2(0.0, 0.0);
-    }
-  } else if (RP.on || RQ.on) {
-    rot_block(RP, RQ, &x11, &x12, &x21, &x22);
-  }
-  const int nr0 = jac_next_pos(r0, n2), nr1 = jac_next_pos(r0 + 1, n2);
-  const int nc0 = jac_next_pos(c0, n2), nc1 = jac_next_pos(c0 + 1, n2);
-  Ao[nr0 + (int64_t)nc0 * n2] = x11;
-  Ao[nr1 + (int64_t)nc0 * n2] = x21;
-  Ao[nr0 + (int64_t)nc1 * n2] = x12;
-  Ao[nr1 + (int64_t)nc1 * n2] = x22;
-}
-
-// V (n x n2, ld n, columns in position space) <- V G_0 G_1 ... G_{nr-1}: the
-// rotations of nr consecutive rounds (rot: nr x h, round-major) applied to R
-// rows of V per workgroup, staged in LDS (two n2 x R buffers, element (row r,
-// position c) at c R + r).  Rows are independent under V <- V G, so the
-// whole sweep runs without a grid-wide step; each element sees the same
-// operations as a per-round update.
-template <int R>
-__global__ void __launch_bounds__(1024)
-k_jacobi_v_rounds(int n, int n2, int nr, const RotV* __restrict__ rot, cplx* __restrict__ V) {
-  extern __shared__ cplx vbuf[];
-  cplx* b0 = vbuf;
-  cplx* b1 = vbuf + (size_t)n2 * R;
-  const int i0 = blockIdx.x * R, h = n2 / 2;
-  for (int e = threadIdx.x; e < n2 * R; e += blockDim.x) {
-    const int c = e / R, r = e - c * R;
-    b0[e] = (i0 + r < n) ? V[(i0 + r) + (int64_t)c * n] : make_double2(0.0, 0.0);
+// One sweep on each block pair of outer round r (workgroup k: pair k);
+// Qout[k] (kBJS x kBJS, column-major) receives the accumulated rotations.
+// Each inner round: kBJ threads form the rotations, then four threads per
+// 2x2 block of A (one output element each) and two per row pair of V.  The
+// threads sharing a block are adjacent lanes of one wavefront, whose LDS
+// reads all complete before its writes, so they may update it in place.
+constexpr int kBJInnerThreads = 4 * kBJ * kBJ;
+static_assert(2 * kBJS * kBJ == kBJInnerThreads, "V row pairs: two threads each");
+__global__ void __launch_bounds__(kBJInnerThreads)
+k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout) {
+  __shared__ cplx a[kBJS * (kBJS + 1)];   // ld kBJS + 1 (odd: spreads the LDS banks)
+  __shared__ cplx v[kBJS * kBJS];
+  __shared__ Rot rots[kBJ];
+  __shared__ int pp[kBJ], pq[kBJ];
+  constexpr int LA = kBJS + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int I, J;
+  rr_pair(r, blockIdx.x, n2p / kBJ, &I, &J);
+  for (int idx = tid; idx < kBJS * kBJS; idx += nt) {
+    const int j = idx / kBJS, i = idx - j * kBJS;
+    a[i + j * LA] = A[bj_index(i, I, J) + (int64_t)bj_index(j, I, J) * n2p];
+    v[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  for (int rr = 0; rr < nr; ++rr) {
-    const RotV* rp = rot + (int64_t)rr * h;
-    for (int P = threadIdx.x; P < h; P += blockDim.x) {
-      const RotV q = rp[P];
-      Rot Q;
-      Q.cs = q.cs;
-      Q.sn = q.sn;
-      Q.t = 0.0;
-      Q.ph = make_double2(q.phx, q.phy);
-      Q.on = true;
-      const int c0 = 2 * P, c1 = 2 * P + 1;
-      const int d0 = jac_next_pos(c0, n2), d1 = jac_next_pos(c1, n2);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        cplx x1 = b0[c0 * R + r], x2 = b0[c1 * R + r];
-        rot_row(Q, &x1, &x2);
-        b1[d0 * R + r] = x1;
-        b1[d1 * R + r] = x2;
+  const int blk = tid >> 2, er = (tid >> 1) & 1, ec = tid & 1;   // block, output row / column
+  const int P = blk / kBJ, Qb = blk - P * kBJ;
+  const int vp = tid >> 1, vf = tid & 1;                          // V row pair, output column
+  const int vQ = vp / kBJS, vi = vp - vQ * kBJS;
+  for (int rr = 0; rr < kBJS - 1; ++rr) {
+    if (tid < kBJ) {
+      int p, q;
+      rr_pair(rr, tid, kBJS, &p, &q);
+      pp[tid] = p;
+      pq[tid] = q;
+      rots[tid] = make_rot(a[p + p * LA].x, a[q + q * LA].x, a[p + q * LA]);
+    }
+    __syncthreads();
+    {
+      const Rot& RP = rots[P];
+      const Rot& RQ = rots[Qb];
+      const int p1 = pp[P], q1 = pq[P], p2 = pp[Qb], q2 = pq[Qb];
+      const int row = er ? q1 : p1, col = ec ? q2 : p2;
+      if (P == Qb) {
+        if (RP.on) {
+          cplx out = make_double2(0.0, 0.0);
+          if (er == ec) out = make_double2(a[row + row * LA].x + (er ? RP.t : -RP.t), 0.0);
+          a[row + col * LA] = out;
+        }
+      } else if (RP.on || RQ.on) {
+        const cplx x11 = a[p1 + p2 * LA], x12 = a[p1 + q2 * LA];
+        const cplx x21 = a[q1 + p2 * LA], x22 = a[q1 + q2 * LA];
+        // column ec of M = X Jq, Jq = [[cs, sn ph], [-sn conj(ph), cs]]
+        const cplx q12 = cscale(RQ.ph, RQ.sn), q21 = cscale(cconj(RQ.ph), -RQ.sn);
+        cplx m1, m2;
+        if (ec == 0) {
+          m1 = cadd(cscale(x11, RQ.cs), cmul(x12, q21));
+          m2 = cadd(cscale(x21, RQ.cs), cmul(x22, q21));
+        } else {
+          m1 = cadd(cmul(x11, q12), cscale(x12, RQ.cs));
+          m2 = cadd(cmul(x21, q12), cscale(x22, RQ.cs));
+        }
+        // row er of Jp^H M, Jp^H = [[cs, -sn ph], [sn conj(ph), cs]]
+        const cplx out = er == 0 ? cadd(cscale(m1, RP.cs), cmul(cscale(RP.ph, -RP.sn), m2))
+                                 : cadd(cmul(cscale(cconj(RP.ph), RP.sn), m1), cscale(m2, RP.cs));
+        a[row + col * LA] = out;
+      }
+    }
+    {
+      const Rot& RV = rots[vQ];
+      if (RV.on) {
+        const int p2 = pp[vQ], q2 = pq[vQ];
+        const cplx x1 = v[vi + p2 * kBJS], x2 = v[vi + q2 * kBJS];
+        // (x1, x2) <- (x1, x2) J
+        const cplx out = vf == 0 ? cadd(cscale(x1, RV.cs), cmul(x2, cscale(cconj(RV.ph), -RV.sn)))
+                                 : cadd(cmul(x1, cscale(RV.ph, RV.sn)), cscale(x2, RV.cs));
+        v[vi + (vf ? q2 : p2) * kBJS] = out;
       }
     }
     __syncthreads();
-    cplx* t = b0;
-    b0 = b1;
-    b1 = t;
   }
-  for (int e = threadIdx.x; e < n2 * R; e += blockDim.x) {
-    const int c = e / R, r = e - c * R;
-    if (i0 + r < n) V[(i0 + r) + (int64_t)c * n] = b0[e];
+  cplx* qo = Qout + (int64_t)blockIdx.x * kBJS * kBJS;
+  for (int idx = tid; idx < kBJS * kBJS; idx += nt) qo[idx] = v[idx];
+}
+
+// A[idx_k, tile] <- Q_k^H A[idx_k, tile] for block pair k = blockIdx.y of
+// outer round r and the kBJTile-column tile blockIdx.x (in place: the
+// workgroup stages its whole tile before writing it).  Thread: row i, columns
+// jg + t kBJThreads / kBJS.
+__global__ void __launch_bounds__(kBJThreads)
+k_bj_rows(int n2p, int r, cplx* __restrict__ A, const cplx* __restrict__ Qk) {
+  __shared__ cplx T[kBJS * kBJTile];    // [m + j kBJS]: A[idx_k[m], c0 + j]
+  __shared__ cplx QH[kBJS * kBJS];      // [i + m kBJS]: conj(Q[m][i])
+  constexpr int G = kBJThreads / kBJS, NJ = kBJTile / G;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int I, J;
+  rr_pair(r, blockIdx.y, n2p / kBJ, &I, &J);
+  const cplx* Q = Qk + (int64_t)blockIdx.y * kBJS * kBJS;
+  const int64_t c0 = (int64_t)blockIdx.x * kBJTile;
+  for (int idx = tid; idx < kBJS * kBJTile; idx += nt) {
+    const int j = idx / kBJS, m = idx - j * kBJS;
+    T[idx] = A[bj_index(m, I, J) + (c0 + j) * n2p];
+  }
+  for (int idx = tid; idx < kBJS * kBJS; idx += nt) {
+    const int m = idx / kBJS, i = idx - m * kBJS;
+    QH[idx] = cconj(Q[m + i * kBJS]);
+  }
+  __syncthreads();
+  const int i = tid % kBJS, jg = tid / kBJS;
+  cplx acc[NJ];
+#pragma unroll
+  for (int t = 0; t < NJ; ++t) acc[t] = make_double2(0.0, 0.0);
+#pragma unroll 4
+  for (int m = 0; m < kBJS; ++m) {
+    const cplx q = QH[i + m * kBJS];
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+      const cplx x = T[m + (jg + t * G) * kBJS];
+      acc[t].x += q.x * x.x - q.y * x.y;
+      acc[t].y += q.x * x.y + q.y * x.x;
+    }
+  }
+  const int gi = bj_index(i, I, J);
+#pragma unroll
+  for (int t = 0; t < NJ; ++t) A[gi + (c0 + jg + t * G) * n2p] = acc[t];
+}
+
+// X[tile, idx_k] <- X[tile, idx_k] Q_k for the kBJTile-row tiles of A (n2p
+// rows, ld n2p; tiles blockIdx.x < n2p / kBJTile) and then of V (n rows,
+// ld n).  Thread: row i, columns jg + t kBJThreads / kBJTile.
+__global__ void __launch_bounds__(kBJThreads)
+k_bj_cols(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
+          const cplx* __restrict__ Qk) {
+  __shared__ cplx T[kBJTile * kBJS];    // [i + m kBJTile]: X[r0 + i, idx_k[m]]
+  __shared__ cplx Q[kBJS * kBJS];       // [m + j kBJS]
+  constexpr int G = kBJThreads / kBJTile, NJ = kBJS / G;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int I, J;
+  rr_pair(r, blockIdx.y, n2p / kBJ, &I, &J);
+  const cplx* Qg = Qk + (int64_t)blockIdx.y * kBJS * kBJS;
+  const int atiles = n2p / kBJTile;
+  const bool onA = (int)blockIdx.x < atiles;
+  cplx* X = onA ? A : V;
+  const int64_t ld = onA ? n2p : n;
+  const int rows = onA ? n2p : n;
+  const int r0 = (onA ? (int)blockIdx.x : (int)blockIdx.x - atiles) * kBJTile;
+  for (int idx = tid; idx < kBJTile * kBJS; idx += nt) {
+    const int m = idx / kBJTile, i = idx - m * kBJTile;
+    T[idx] = (r0 + i < rows) ? X[(r0 + i) + (int64_t)bj_index(m, I, J) * ld]
+                             : make_double2(0.0, 0.0);
+  }
+  for (int idx = tid; idx < kBJS * kBJS; idx += nt) Q[idx] = Qg[idx];
+  __syncthreads();
+  const int i = tid % kBJTile, jg = tid / kBJTile;
+  cplx acc[NJ];
+#pragma unroll
+  for (int t = 0; t < NJ; ++t) acc[t] = make_double2(0.0, 0.0);
+#pragma unroll 4
+  for (int m = 0; m < kBJS; ++m) {
+    const cplx x = T[i + m * kBJTile];
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+      const cplx q = Q[m + (jg + t * G) * kBJS];
+      acc[t].x += x.x * q.x - x.y * q.y;
+      acc[t].y += x.x * q.y + x.y * q.x;
+    }
+  }
+  if (r0 + i < rows) {
+#pragma unroll
+    for (int t = 0; t < NJ; ++t)
+      X[(r0 + i) + (int64_t)bj_index(jg + t * G, I, J) * ld] = acc[t];
   }
 }
 
@@ -657,32 +753,28 @@ __global__ void k_jacobi_init(int n, int n2, const cplx* __restrict__ a, int64_t
   V0[vi] = make_double2(i == j ? 1.0 : 0.0, 0.0);
 }
 
-// Rank of player p's eigenvalue (ties by player index), players 0..n-1.
-__global__ void k_jacobi_rank(int n, int n2, int rounds, const cplx* __restrict__ A,
-                              int* __restrict__ rank) {
+// Rank of index p's eigenvalue among 0..n-1 (ties by index).
+__global__ void k_jacobi_rank(int n, int ld, const cplx* __restrict__ A, int* __restrict__ rank) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const int sp = jac_pos_after(p, rounds, n2);
-  const double dp = A[sp + (int64_t)sp * n2].x;
+  const double dp = A[p + (int64_t)p * ld].x;
   int rk = 0;
   for (int q = 0; q < n; ++q) {
-    const int sq = jac_pos_after(q, rounds, n2);
-    const double dq = A[sq + (int64_t)sq * n2].x;
+    const double dq = A[q + (int64_t)q * ld].x;
     if (dq < dp || (dq == dp && q < p)) ++rk;
   }
   rank[p] = rk;
 }
 
-__global__ void k_jacobi_scatter(int n, int n2, int rounds, const cplx* __restrict__ A,
+__global__ void k_jacobi_scatter(int n, int ld, const cplx* __restrict__ A,
                                  const cplx* __restrict__ V, const int* __restrict__ rank,
                                  double* __restrict__ w, cplx* __restrict__ Q, int64_t ldq) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
   const int p = (int)(idx / n), i = (int)(idx - (int64_t)p * n);
-  const int sp = jac_pos_after(p, rounds, n2);
   const int rp = rank[p];
-  Q[i + (int64_t)rp * ldq] = V[i + (int64_t)sp * n];
-  if (i == 0) w[rp] = A[sp + (int64_t)sp * n2].x;
+  Q[i + (int64_t)rp * ldq] = V[i + (int64_t)p * n];
+  if (i == 0) w[rp] = A[p + (int64_t)p * ld].x;
 }
 
 __global__ void __launch_bounds__(1024) k_offnorm(int n, const cplx* __restrict__ A, double* out) {
@@ -1031,30 +1123,21 @@ hipError_t launch_identity(int64_t n, cplx* a, int64_t lda, hipStream_t s) {
   return hipGetLastError();
 }
 
-static size_t g_heev_lds_limit = 64 * 1024;
+// padded size: a multiple of the update tiles (and so of 2 kBJ)
+static int64_t bj_padded(int64_t n) { return (n + kBJTile - 1) / kBJTile * kBJTile; }
 
-// rows of V per workgroup in the per-sweep V update: as many (4, 2, 1) as
-// two n2-long LDS buffers allow; 0 if not even one row fits
-static int jac_v_rows(int64_t n2) {
-  for (int r = 4; r >= 1; r /= 2)
-    if ((size_t)2 * n2 * r * sizeof(cplx) <= g_heev_lds_limit) return r;
-  return 0;
-}
-
-// Work layout for n > 64: A0, A1 (n2 x n2), V (n x n2), a sweep of rotations
-// (in a second n x n2 slot), n ints of ranks,
-// then two 16-byte aligned doubles.
+// Work layout for n > 64: A (n2p x n2p), V (n x n2p), the block pairs'
+// unitaries (n2p / kBJS of kBJS x kBJS), n ints of ranks, then two 16-byte
+// aligned doubles.
 size_t heev_work_bytes(int64_t n) {
-  const int64_t n2 = n + (n & 1);
-  return (size_t)(2 * n2 * n2 + 2 * n * n2) * sizeof(cplx) + (size_t)(n + 8) * sizeof(int) + 64;
+  const int64_t n2p = bj_padded(n);
+  return (size_t)(n2p * n2p + n * n2p + n2p * kBJS) * sizeof(cplx) + (size_t)(n + 8) * sizeof(int) +
+         64;
 }
 
 hipError_t heev_set_lds_limit(size_t bytes) {
-  g_heev_lds_limit = bytes;
-  const void* fns[7] = {(const void*)k_jacobi_small, (const void*)k_chol_diag,
-                        (const void*)kb_jacobi, (const void*)kb_chol_diag,
-                        (const void*)k_jacobi_v_rounds<4>, (const void*)k_jacobi_v_rounds<2>,
-                        (const void*)k_jacobi_v_rounds<1>};
+  const void* fns[4] = {(const void*)k_jacobi_small, (const void*)k_chol_diag,
+                        (const void*)kb_jacobi, (const void*)kb_chol_diag};
   for (const void* f : fns) {
     hipFuncAttributes at;
     hipError_t e = hipFuncGetAttributes(&at, f);
@@ -1069,7 +1152,7 @@ hipError_t heev_set_lds_limit(size_t bytes) {
 hipError_t launch_heev_small_async(int64_t n, const cplx* a, int64_t lda, double* w, cplx* q,
                                    int64_t ldq, int* sweeps_dev, hipStream_t s) {
   if (n > kJacSmallMax) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(2 * n * n) * sizeof(cplx);
+  const size_t lds = (size_t)(n * (2 * n + 1)) * sizeof(cplx);
   hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(jac_threads((int)n)), lds, s, (int)n, a, lda, w,
                      q, ldq, sweeps_dev);
   return hipGetLastError();
@@ -1077,14 +1160,14 @@ hipError_t launch_heev_small_async(int64_t n, const cplx* a, int64_t lda, double
 
 hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int64_t ldq, void* work,
                        double* host_scratch, int* sweeps_done, hipStream_t s) {
-  const int64_t n2 = n + (n & 1);
+  const int64_t n2p = bj_padded(n);
   char* base = static_cast<char*>(work);
-  const size_t mat_bytes = (size_t)(2 * n2 * n2 + 2 * n * n2) * sizeof(cplx);
+  const size_t mat_bytes = (size_t)(n2p * n2p + n * n2p + n2p * kBJS) * sizeof(cplx);
   int* dev_int = reinterpret_cast<int*>(base + mat_bytes);
   const size_t stat_off = (mat_bytes + (size_t)(n + 8) * sizeof(int) + 15) & ~(size_t)15;
   double* dstat = reinterpret_cast<double*>(base + stat_off);
   if (n <= kJacSmallMax) {
-    const size_t lds = (size_t)(2 * n * n) * sizeof(cplx);
+    const size_t lds = (size_t)(n * (2 * n + 1)) * sizeof(cplx);
     hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(jac_threads((int)n)), lds, s, (int)n,
                        (const cplx*)a, lda, w, q, ldq, dev_int);
     hipError_t e = hipGetLastError();
@@ -1096,26 +1179,20 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
     *sweeps_done = hs;
     return e;
   }
-  if (jac_v_rows(n2) == 0) return hipErrorInvalidValue;   // a row of V must fit in LDS
-  cplx* A0 = reinterpret_cast<cplx*>(base);
-  cplx* A1 = A0 + n2 * n2;
-  cplx* V0 = A1 + n2 * n2;
-  // one sweep's rotations ((n2 - 1) rounds x n2/2 pairs x 32 B) in the second
-  // V-sized slot of the layout (n2 (n2 - 1) 16 B <= n n2 16 B)
-  RotV* rots = reinterpret_cast<RotV*>(V0 + n * n2);
-  hipLaunchKernelGGL(k_jacobi_init, dim3(nblocks(n2 * n2 + n * n2, 256)), dim3(256), 0, s, (int)n,
-                     (int)n2, (const cplx*)a, lda, A0, V0);
+  cplx* A = reinterpret_cast<cplx*>(base);
+  cplx* V = A + n2p * n2p;
+  cplx* Qk = V + n * n2p;
+  hipLaunchKernelGGL(k_jacobi_init, dim3(nblocks(n2p * n2p + n * n2p, 256)), dim3(256), 0, s,
+                     (int)n, (int)n2p, (const cplx*)a, lda, A, V);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t h = n2 / 2;
+  const int nblk = (int)(n2p / kBJ), npair = nblk / 2;
+  const int atiles = (int)(n2p / kBJTile), vtiles = (int)((n + kBJTile - 1) / kBJTile);
   const double tl = std::max(1e-15, 2.2e-16 * (double)n);
-  const int vrows = jac_v_rows(n2);
-  const size_t vlds = (size_t)2 * n2 * vrows * sizeof(cplx);
-  const int vthreads = (int)std::min<int64_t>(1024, ((h + 63) / 64) * 64);
-  int sw = 0, rounds = 0;
+  int sw = 0;
   bool conv = false;
   for (; sw <= kMaxSweeps; ++sw) {
-    hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, s, (int)n2, (const cplx*)A0, dstat);
+    hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, s, (int)n2p, (const cplx*)A, dstat);
     e = hipMemcpyAsync(host_scratch, dstat, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
@@ -1125,29 +1202,21 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
       break;
     }
     if (sw == kMaxSweeps) break;
-    for (int r = 0; r < n2 - 1; ++r) {
-      hipLaunchKernelGGL(k_jacobi_round, dim3(nblocks(h * h, 256)), dim3(256), 0, s, (int)n2,
-                         (const cplx*)A0, A1, rots + (int64_t)r * h);
-      std::swap(A0, A1);
-      ++rounds;
+    for (int r = 0; r < nblk - 1; ++r) {
+      hipLaunchKernelGGL(k_bj_inner, dim3(npair), dim3(kBJInnerThreads), 0, s, (int)n2p, r,
+                         (const cplx*)A, Qk);
+      hipLaunchKernelGGL(k_bj_rows, dim3(atiles, npair), dim3(kBJThreads), 0, s, (int)n2p, r, A,
+                         (const cplx*)Qk);
+      hipLaunchKernelGGL(k_bj_cols, dim3(atiles + vtiles, npair), dim3(kBJThreads), 0, s, (int)n,
+                         (int)n2p, r, A, V, (const cplx*)Qk);
     }
-    const dim3 vgrid((unsigned)((n + vrows - 1) / vrows));
-    if (vrows == 4)
-      hipLaunchKernelGGL(k_jacobi_v_rounds<4>, vgrid, dim3(vthreads), vlds, s, (int)n, (int)n2,
-                         (int)(n2 - 1), (const RotV*)rots, V0);
-    else if (vrows == 2)
-      hipLaunchKernelGGL(k_jacobi_v_rounds<2>, vgrid, dim3(vthreads), vlds, s, (int)n, (int)n2,
-                         (int)(n2 - 1), (const RotV*)rots, V0);
-    else
-      hipLaunchKernelGGL(k_jacobi_v_rounds<1>, vgrid, dim3(vthreads), vlds, s, (int)n, (int)n2,
-                         (int)(n2 - 1), (const RotV*)rots, V0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_jacobi_rank, dim3(nblocks(n, 256)), dim3(256), 0, s, (int)n, (int)n2, rounds,
-                     (const cplx*)A0, dev_int);
-  hipLaunchKernelGGL(k_jacobi_scatter, dim3(nblocks(n * n, 256)), dim3(256), 0, s, (int)n, (int)n2,
-                     rounds, (const cplx*)A0, (const cplx*)V0, (const int*)dev_int, w, q, ldq);
+  hipLaunchKernelGGL(k_jacobi_rank, dim3(nblocks(n, 256)), dim3(256), 0, s, (int)n, (int)n2p,
+                     (const cplx*)A, dev_int);
+  hipLaunchKernelGGL(k_jacobi_scatter, dim3(nblocks(n * n, 256)), dim3(256), 0, s, (int)n, (int)n2p,
+                     (const cplx*)A, (const cplx*)V, (const int*)dev_int, w, q, ldq);
   *sweeps_done = conv ? sw : -1;
   return hipGetLastError();
 }
@@ -1186,7 +1255,7 @@ hipError_t launch_fused_dense(FusedStep step, int nitems, int64_t npw_nb_max, in
       break;
     case FS_JACOBI:
       hipLaunchKernelGGL(kb_jacobi, dim3(nitems), dim3(jac_threads(nb_max)),
-                         (size_t)(2 * nb_max * nb_max) * sizeof(cplx), s, D);
+                         (size_t)(nb_max * (2 * nb_max + 1)) * sizeof(cplx), s, D);
       break;
     case FS_RESIDUALS:
       hipLaunchKernelGGL(kb_residuals, dim3(nb_max, nitems), dim3(256), 0, s, D);

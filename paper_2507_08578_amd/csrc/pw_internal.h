@@ -302,7 +302,8 @@ hipError_t launch_chol_diag(int kb, int k0, cplx* a, int64_t lda, cplx* dinv, co
                             int* status, hipStream_t s);
 hipError_t launch_zero_lower(int64_t n, cplx* a, int64_t lda, hipStream_t s);
 hipError_t launch_identity(int64_t n, cplx* a, int64_t lda, hipStream_t s);
-// Cyclic Jacobi eigensolver of a Hermitian n x n matrix (a is destroyed):
+// Cyclic Jacobi eigensolver of a Hermitian n x n matrix (a is destroyed;
+// n > 64: block Jacobi, sub-problems and unitaries of 64 x 64 in LDS):
 // w ascending, q = eigenvectors.  work: heev_work_bytes(n) device bytes;
 // host_scratch: >= 4 doubles of pinned host memory.  Synchronises the stream
 // once per sweep.  *sweeps_done = sweeps used, or -1 if not converged.
