@@ -204,7 +204,8 @@ typedef struct {
                              2 transforms exchanged through LDS (N1 = N2 = 144)            */
   int32_t chunk;          /* bands per FFT launch, [1, the handle's buffer]                  */
   int32_t gemm_blocks;    /* split-K target block count of P^H psi, [1, 2048]                */
-  int32_t nn_tile;        /* tall products P C, Y Q, Y U^-1: 0 64x64, 1 128x64 workgroup tiles */
+  int32_t nn_tile;        /* tall FP64 products P C, Y Q, Y U^-1: 0 64x64, 1 128x64 tiles    */
+  int32_t nn_tile32;      /* the same choice for the FP32 / BF16 product P C                 */
   double ms;              /* pw_ham_autotune: median time of one H*psi of nb bands           */
 } pw_tuning;
 

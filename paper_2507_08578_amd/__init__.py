@@ -281,7 +281,7 @@ class Hamiltonian:
 
     # --- launch-shape tuning ---
     _TUNING_KEYS = ("reg_col", "reg_plane", "plane_variant", "plane_variant32", "chunk",
-                    "gemm_blocks", "nn_tile")
+                    "gemm_blocks", "nn_tile", "nn_tile32")
 
     def get_tuning(self) -> dict:
         t = _lib.PwTuning()

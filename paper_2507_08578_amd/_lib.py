@@ -46,7 +46,7 @@ class PwTuning(ctypes.Structure):
     """pw_tuning (include/pw.h)."""
     _fields_ = [("reg_col", c_int32), ("reg_plane", c_int32), ("plane_variant", c_int32),
                 ("plane_variant32", c_int32), ("chunk", c_int32), ("gemm_blocks", c_int32),
-                ("nn_tile", c_int32), ("ms", c_double)]
+                ("nn_tile", c_int32), ("nn_tile32", c_int32), ("ms", c_double)]
 
 
 SIGNATURES = {

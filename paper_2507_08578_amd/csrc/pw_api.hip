@@ -57,7 +57,8 @@ struct pw_ham {
   int64_t chunk = 0;         // bands per FFT launch (tunable, <= chunk_alloc)
   int64_t chunk_alloc = 0;   // bands the FFT work buffer holds
   int gemm_target = 2048;    // split-K target block count of the projector product (tunable)
-  int nn_tile = 0;           // workgroup tile of the tall products P C, Y Q, Y U^-1 (tunable)
+  int nn_tile = 0;           // workgroup tile of the tall FP64 products P C, Y Q, Y U^-1 (tunable)
+  int nn_tile32 = 0;         // the same for the FP32 / BF16 product P C (tunable)
   bool reg_col_ok = false, reg_plane_ok = false, narrow_ok = false, narrow32_ok = false;
   bool ls32_ok = false;      // FP32 plane kernel with LDS exchanges (square P^2 planes)
   std::vector<void*> allocs;
@@ -299,7 +300,7 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_NONLOCAL_LP);
     HIPCHK(c, launch_gemm_nn32(bf16, h->npw, nb, h->nproj, 1.0, h->proj32, h->npw, h->cprj32,
-                               h->nproj, 1.0, out, ldout, s, h->nn_tile));
+                               h->nproj, 1.0, out, ldout, s, h->nn_tile32));
   }
   return PW_OK;
 }
@@ -1328,6 +1329,7 @@ pw_status pw_ham_get_tuning(const pw_ham* h, pw_tuning* t) {
   t->chunk = (int32_t)h->chunk;
   t->gemm_blocks = h->gemm_target;
   t->nn_tile = h->nn_tile;
+  t->nn_tile32 = h->nn_tile32;
   t->ms = 0.0;
   return PW_OK;
 }
@@ -1354,7 +1356,8 @@ pw_status pw_ham_set_tuning(pw_ham* h, const pw_tuning* t) {
                 "chunk outside [1, " + std::to_string(h->chunk_alloc) + "]");
   if (t->gemm_blocks < 1 || t->gemm_blocks > 2048)
     return fail(h->ctx, PW_ERR_INVALID_ARG, "gemm_blocks outside [1, 2048]");
-  if (t->nn_tile != 0 && t->nn_tile != 1) return fail(h->ctx, PW_ERR_INVALID_ARG, "nn_tile is 0 or 1");
+  if ((t->nn_tile != 0 && t->nn_tile != 1) || (t->nn_tile32 != 0 && t->nn_tile32 != 1))
+    return fail(h->ctx, PW_ERR_INVALID_ARG, "nn_tile and nn_tile32 are 0 or 1");
   h->cfg.reg_col = t->reg_col != 0;
   h->cfg.reg_plane = t->reg_plane != 0;
   h->cfg.plane_variant = t->plane_variant;
@@ -1362,6 +1365,7 @@ pw_status pw_ham_set_tuning(pw_ham* h, const pw_tuning* t) {
   h->chunk = t->chunk;
   h->gemm_target = t->gemm_blocks;
   h->nn_tile = t->nn_tile;
+  h->nn_tile32 = t->nn_tile32;
   return PW_OK;
 }
 
@@ -1457,10 +1461,13 @@ pw_status pw_ham_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, pw_
       t.gemm_blocks = g;
       if ((st = try_one(t)) != PW_OK) return st;
     }
-  // 4) workgroup tile of the tall products
+  // 4) workgroup tile of the tall product P C of the precision being tuned
   if (h->nproj > 0) {
     pw_tuning t = cur;
-    t.nn_tile = 1 - cur.nn_tile;
+    if (lp)
+      t.nn_tile32 = 1 - cur.nn_tile32;
+    else
+      t.nn_tile = 1 - cur.nn_tile;
     if ((st = try_one(t)) != PW_OK) return st;
   }
   *best = cur;

@@ -21,9 +21,10 @@ def all_tunings(ham, nb):
         for ch in sorted({base["chunk"], max(1, base["chunk"] // 2), 1}):
             for gb in (2048, 256):
                 out.append(dict(reg_col=rc, reg_plane=rp, plane_variant=pv, plane_variant32=pv32,
-                                chunk=ch, gemm_blocks=gb, nn_tile=0))
+                                chunk=ch, gemm_blocks=gb, nn_tile=0, nn_tile32=0))
     out.append(dict(base, nn_tile=1))
-    out.append(dict(base, nn_tile=1, gemm_blocks=1))
+    out.append(dict(base, nn_tile32=1))
+    out.append(dict(base, nn_tile=1, nn_tile32=1, gemm_blocks=1))
     return out
 
 
@@ -63,7 +64,7 @@ def test_set_tuning_rejects(pw, ctx):
         ham.set_tuning({"reg_plane": 1})
     assert e.value.status == 2
     for bad in ({"chunk": 0}, {"chunk": 10 ** 6}, {"gemm_blocks": 4096}, {"reg_col": 2},
-                {"nn_tile": 2}):
+                {"nn_tile": 2}, {"nn_tile32": -1}):
         with pytest.raises(pw.PWError) as e:
             ham.set_tuning(bad)
         assert e.value.status == 1, bad
