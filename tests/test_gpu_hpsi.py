@@ -105,6 +105,27 @@ def test_c5_full_block_sampled(pw, ctx):
     torch.cuda.empty_cache()
 
 
+def test_c5_fp32_full_block_sampled(pw, ctx):
+    """C5 FP32 H*psi at its full size in the mixed benchmark's launch
+    configuration (LDS-exchange plane kernel, 77-band chunks, so a ragged last
+    chunk of 50; 128 x 64 tiles for P C; split-K over 2048 blocks); sampled
+    bands, including both sides of a chunk boundary, against the oracle."""
+    import torch
+    w = synth.config_c5()
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=512, low_prec=True)
+    ham.set_tuning({"reg_col": 1, "reg_plane": 1, "plane_variant32": 2, "chunk": 77,
+                    "gemm_blocks": 2048, "nn_tile32": 1})
+    X0 = synth.start_block(w.npw, 512, 0).astype(np.complex64)
+    HX = ham.apply_h(to_dev(X0), prec="fp32")
+    oh = oracle.OracleHam.from_workload(w)
+    for b in (0, 76, 77, 462, 511):
+        ref = oracle.apply_h(oh, X0[b:b + 1].astype(np.complex128).T).T
+        err = rel_err(to_host(HX[b:b + 1]).astype(np.complex128), ref)
+        assert err < 2e-6, (b, err)
+    del HX
+    torch.cuda.empty_cache()
+
+
 def test_hermiticity_and_determinism(pw, ctx):
     w = synth.config_c1()
     ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=2)
@@ -130,6 +151,9 @@ def test_argument_errors(pw, ctx):
     with pytest.raises(pw.PWError) as e:
         ham.apply_h(X4, X4)                              # in place is not allowed
     assert e.value.status == 1
+    with pytest.raises(pw.PWError) as e:
+        ham.apply_h(X[:0])                               # an empty block is rejected, not ignored
+    assert e.value.status == 1 and "nb = 0" in str(e.value)
     vloc = torch.from_numpy(w.vloc).cuda()
     with pytest.raises(pw.PWError) as e:                 # radix 7 unsupported
         pw.Hamiltonian(ctx, w.miller, w.recip, w.kred, (28, 24, 24),
