@@ -73,7 +73,8 @@ __global__ void k_check_finite(int64_t n, const double* __restrict__ x, int* fla
   if (i < n && !isfinite(x[i])) atomicOr(flag, 1);
 }
 
-// A <- (A + A^H)/2
+// The Hermitian matrix from its upper triangle: A[j][i] = conj(A[i][j]) for
+// i < j, real diagonal (the lower triangle is not read).
 __device__ __forceinline__ void hermitize_body(int64_t n, cplx* a, int64_t lda, int bx_) {
   const int64_t idx = (int64_t)bx_ * blockDim.x + threadIdx.x;
   if (idx >= n * n) return;
@@ -83,10 +84,7 @@ __device__ __forceinline__ void hermitize_body(int64_t n, cplx* a, int64_t lda, 
     a[i + j * lda].y = 0.0;
     return;
   }
-  const cplx u = a[i + j * lda], l = a[j + i * lda];
-  const cplx avg = make_double2(0.5 * (u.x + l.x), 0.5 * (u.y - l.y));
-  a[i + j * lda] = avg;
-  a[j + i * lda] = cconj(avg);
+  a[j + i * lda] = cconj(a[i + j * lda]);
 }
 
 __global__ void 

@@ -147,14 +147,16 @@ k_gemm_nn_tall(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __rest
 }
 
 // Partial or final C = alpha diag(rowscale) A^H B over K range [kb, ke) of split z.
-// A k x m (lda), B k x n (ldb).  Output at out + z*zstride, leading dim ldo.
+// A k x m (lda), B k x n (ldb).  Element (i, j) goes to out + z*zstride at
+// (i - oi0) + (j - oj0) ldo.
 __device__ __forceinline__ void gemm_cn_body(int64_t M, int64_t N, int64_t K, int64_t ksplit,
                                              double alpha, const double* __restrict__ alpha_dev,
                                              const double* __restrict__ rowscale,
                                              const cplx* __restrict__ A, int64_t lda,
                                              const cplx* __restrict__ B, int64_t ldb, double beta,
                                              cplx* __restrict__ out, int64_t ldo, int64_t zstride,
-                                             int bx, int by, int bz) {
+                                             int bx, int by, int bz, int64_t oi0 = 0,
+                                             int64_t oj0 = 0) {
   if (alpha_dev) alpha = alpha_dev[0];
   __shared__ cplx As[kKcCN][kBM + 1];
   __shared__ cplx Bs[kKcCN][kBN + 1];
@@ -236,11 +238,11 @@ __device__ __forceinline__ void gemm_cn_body(int64_t M, int64_t N, int64_t K, in
           const double s = alpha * (rowscale ? rowscale[i] : 1.0);
           cplx v = make_double2(s * accr[ti][tj][r], s * acci[ti][tj][r]);
           if (beta != 0.0) {
-            const cplx c = o[i + j * ldo];
+            const cplx c = o[(i - oi0) + (j - oj0) * ldo];
             v.x += beta * c.x;
             v.y += beta * c.y;
           }
-          o[i + j * ldo] = v;
+          o[(i - oi0) + (j - oj0) * ldo] = v;
         }
       }
 }
@@ -249,7 +251,8 @@ __global__ void __launch_bounds__(kThreads)
 k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
           const double* __restrict__ alpha_dev, const double* __restrict__ rowscale,
           const cplx* __restrict__ A, int64_t lda, const cplx* __restrict__ B, int64_t ldb,
-          double beta, cplx* __restrict__ out, int64_t ldo, int64_t zstride) {
+          double beta, cplx* __restrict__ out, int64_t ldo, int64_t zstride, int upper) {
+  if (upper && blockIdx.y > blockIdx.x) return;   // tile strictly below the diagonal
   gemm_cn_body(M, N, K, ksplit, alpha, alpha_dev, rowscale, A, lda, B, ldb, beta, out, ldo, zstride,
                blockIdx.x, blockIdx.y, blockIdx.z);
 }
@@ -286,6 +289,47 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int nsplit, const cplx* __
                                 const double* __restrict__ rowscale, double beta,
                                 cplx* __restrict__ C, int64_t ldc) {
   splitk_reduce_body(M, N, nsplit, work, alpha, alpha_dev, rowscale, beta, C, ldc, blockIdx.x);
+}
+
+// Hermitian products (M = N): only the nact = T (T + 1) / 2 tiles on and
+// above the diagonal (T = ceil(M / 64)), enumerated column by column,
+// t = bx (bx + 1) / 2 + by for by <= bx.  Split partials are packed per
+// active tile: work[(z nact + t) 4096 + ii + 64 jj].
+__device__ __forceinline__ void upper_tile(int t, int* by, int* bx) {
+  int c = 0;
+  while ((c + 1) * (c + 2) / 2 <= t) ++c;
+  *bx = c;
+  *by = t - c * (c + 1) / 2;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_gemm_cn_upper(int64_t M, int64_t K, int64_t ksplit, int nact, const cplx* __restrict__ A,
+                int64_t lda, const cplx* __restrict__ B, int64_t ldb, cplx* __restrict__ work) {
+  int by, bx;
+  upper_tile(blockIdx.x, &by, &bx);
+  gemm_cn_body(M, M, K, ksplit, 1.0, nullptr, nullptr, A, lda, B, ldb, 0.0,
+               work + (int64_t)blockIdx.x * kBM * kBN, kBM, (int64_t)nact * kBM * kBN, bx, by,
+               blockIdx.z, (int64_t)by * kBM, (int64_t)bx * kBN);
+}
+
+// C[i + j ldc] = alpha sum_z (packed partials), fixed order, for the
+// elements of the active tiles; the rest of C is not written.
+__global__ void k_splitk_reduce_upper(int64_t M, int nsplit, int nact, const cplx* __restrict__ work,
+                                      double alpha, cplx* __restrict__ C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * M) return;
+  const int64_t j = idx / M, i = idx - j * M;
+  const int by = (int)(i / kBM), bx = (int)(j / kBN);
+  if (by > bx) return;
+  const int64_t t = (int64_t)bx * (bx + 1) / 2 + by;
+  const int64_t loc = (i - (int64_t)by * kBM) + (j - (int64_t)bx * kBN) * kBM;
+  double re = 0.0, im = 0.0;
+  for (int z = 0; z < nsplit; ++z) {
+    const cplx w = work[((int64_t)z * nact + t) * kBM * kBN + loc];
+    re += w.x;
+    im += w.y;
+  }
+  C[i + j * ldc] = make_double2(alpha * re, alpha * im);
 }
 
 struct SplitPlan {
@@ -409,10 +453,34 @@ size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k) {
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
                           cplx* work, hipStream_t s, double beta, const double* alpha_dev,
-                          int target) {
+                          int target, int upper) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  if (upper && (m != n || kBM != kBN || rowscale || alpha_dev || beta != 0.0))
+    return hipErrorInvalidValue;
   if (target < 1 || target > kTargetBlocks) target = kTargetBlocks;
   SplitPlan p = split_plan(m, n, k, target);
+  const int64_t T = (m + kBM - 1) / kBM, nact = T * (T + 1) / 2;
+  if (T == 1) upper = 0;   // a single tile: nothing to skip
+  // packed splits that fit the workspace the full product would use (p.nsplit m n)
+  const int64_t cap = p.nsplit * m * n / (nact * kBM * kBN);
+  if (upper && work && p.nsplit > 1 && cap >= 1) {
+    // as many splits as fill ~target blocks with the active tiles
+    const int64_t maxs = (k + kKcCN * 2 - 1) / (kKcCN * 2) > 1 ? (k + kKcCN * 2 - 1) / (kKcCN * 2) : 1;
+    int64_t want = (target + nact - 1) / nact;
+    want = std::min(want, std::min(maxs, cap));
+    if (want < 1) want = 1;
+    int64_t ks = (k + want - 1) / want;
+    ks = ((ks + kKcCN - 1) / kKcCN) * kKcCN;
+    ks = std::max<int64_t>(ks, kKcCN);
+    const int64_t ns = (k + ks - 1) / ks;
+    hipLaunchKernelGGL(k_gemm_cn_upper, dim3((unsigned)nact, 1, (unsigned)ns), dim3(kThreads), 0, s,
+                       m, k, ks, (int)nact, A, lda, B, ldb, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_splitk_reduce_upper, dim3((unsigned)((m * m + 255) / 256)), dim3(256), 0, s,
+                       m, (int)ns, (int)nact, (const cplx*)work, alpha, C, ldc);
+    return hipGetLastError();
+  }
   if (!work) {   // no workspace: one split over the whole K range
     p.nsplit = 1;
     p.ksplit = k > 0 ? k : 1;
@@ -420,13 +488,13 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
   if (p.nsplit == 1) {
     dim3 grid(p.tiles_n, p.tiles_m, 1);
     hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, alpha, alpha_dev,
-                       rowscale, A, lda, B, ldb, beta, C, ldc, (int64_t)0);
+                       rowscale, A, lda, B, ldb, beta, C, ldc, (int64_t)0, upper);
     return hipGetLastError();
   }
   dim3 grid(p.tiles_n, p.tiles_m, p.nsplit);
   hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, 1.0,
                      (const double*)nullptr, (const double*)nullptr, A, lda, B, ldb, 0.0, work, m,
-                     m * n);
+                     m * n, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = m * n;

@@ -428,14 +428,14 @@ pw_status batch_ortho_rr(BatchItem& it) {
   hipStream_t s = c->stream;
   const int64_t nb = it.nb, npw = h->npw;
   HIPCHK(c, launch_gemm_cn(nb, nb, npw, 1.0, it.y, npw, it.y, npw, h->sub0, nb, nullptr,
-                           h->gemm_work, s));
+                           h->gemm_work, s, 0.0, nullptr, 2048, 1));
   HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
   HIPCHK(c, chol_blocked(nb, h->sub0, nb, h->dinv, h->panel, h->dtol, h->status_dev, s));
   HIPCHK(c, trsm_right(npw, nb, it.y, npw, h->sub0, nb, h->dinv, h->blk, s));
   pw_status st = ham_apply(h, nb, it.y, npw, it.hy, npw, 1.0, 0.0, 0.0, nullptr, 0);
   if (st != PW_OK) return st;
   HIPCHK(c, launch_gemm_cn(nb, nb, npw, 1.0, it.y, npw, it.hy, npw, h->sub0, nb, nullptr,
-                           h->gemm_work, s));
+                           h->gemm_work, s, 0.0, nullptr, 2048, 1));
   HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
   HIPCHK(c, launch_heev_small_async(nb, h->sub0, nb, it.eig, h->sub1, nb, it.sweeps, s));
   if ((st = rotate_block(h, nb, it.y, npw, h->sub1)) != PW_OK) return st;
@@ -1211,7 +1211,9 @@ pw_status pw_orthonormalize(pw_ham* h, pw_prec gram_prec, int64_t nb, void* yv, 
   cplx* y = static_cast<cplx*>(yv);
   {
     StageScope sc(c, PW_STAGE_GRAM);
-    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, y, ld, h->sub0, nb, nullptr, h->gemm_work, s));
+    // Hermitian: the tiles on and above the diagonal, then mirrored
+    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, y, ld, h->sub0, nb, nullptr, h->gemm_work, s,
+                             0.0, nullptr, 2048, 1));
     HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
   }
   {
@@ -1253,7 +1255,7 @@ pw_status pw_rayleigh_ritz(pw_ham* h, int64_t nb, void* yv, int64_t ld, void* hy
   {
     StageScope sc(c, PW_STAGE_GRAM);
     HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, hy, ldhy, h->sub0, nb, nullptr,
-                             h->gemm_work, s));
+                             h->gemm_work, s, 0.0, nullptr, 2048, 1));
     HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
   }
   int sweeps = 0;

@@ -244,7 +244,9 @@ size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k);
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
                           cplx* work, hipStream_t s, double beta = 0.0,
-                          const double* alpha_dev = nullptr, int target_blocks = 2048);
+                          const double* alpha_dev = nullptr, int target_blocks = 2048,
+                          int upper = 0);   // 1 (m == n, Hermitian result): only the 64 x 64
+                                            // tiles on and above the diagonal are formed
 // tile 0: 64 x 64 workgroup tiles; 1: 128 x 64 (tall products)
 hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
@@ -278,6 +280,7 @@ hipError_t launch_kinetic(int64_t npw, const int* miller, const double* recip9, 
                           double* kin, hipStream_t s);
 hipError_t launch_scale_copy(int64_t n, const double* src, double scale, double* dst, hipStream_t s);
 hipError_t launch_max_reduce(int64_t n, const double* x, double* out1, hipStream_t s);
+// a <- its upper triangle mirrored: a[j][i] = conj(a[i][j]) for i < j, Im a[i][i] = 0
 hipError_t launch_hermitize(int64_t n, cplx* a, int64_t lda, hipStream_t s);
 hipError_t launch_copy_block(int64_t rows, int64_t cols, const cplx* src, int64_t lds, cplx* dst,
                              int64_t ldd, hipStream_t s);
