@@ -71,6 +71,9 @@ COUNTER_FILES = {
     ("C5", "fp32", "fft_plane", "k_plane_reg"): (
         "profiles/c5_plane_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/fft_reg.hip", "paper_2507_08578_amd/csrc/fft_common.h")),
+    ("C5", "fp32", "proj", "gemm"): (
+        "profiles/c5_gemm_fp32_counters.md",
+        ("paper_2507_08578_amd/csrc/gemm32_kernels.hip",)),
     ("C5", "fp32", "fft_plane", "k_plane_ls"): (
         "profiles/c5_plane_ls_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/fft_ls.hip", "paper_2507_08578_amd/csrc/fft_common.h")),
@@ -117,7 +120,8 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
     The stages of the precision being reported are used (the low-precision
     path times its FP32 / BF16 kernels under their own stage ids; its
     Rayleigh-Ritz product stays FP64 and is not counted here).
-    nonlocal (H psi += P C): MFMA, 8 npw nproj nb flop per launch.
+    proj (P^H psi, split-K + reduce) and nonlocal (H psi += P C): MFMA,
+               8 npw nproj nb flop per launch.
     fft_plane: vector ALU, per band and z-plane 2 (xr 5 N2 log2 N2 + N2 5 N1 log2 N1)
                + 2 N1 N2 flop (the V product), per launch x bands in the launch
                (full-length transforms: a kernel that prunes the zero inputs and
@@ -131,19 +135,28 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
     applies = w.degree - 1 if lp else w.degree     # H*psi products of this precision per step
     elem = 16 if prec == "fp64" else 8
     cand = {k[:len(k) - len(sfx)] if sfx else k: v for k, v in stages.items()
-            if k in (f"nonlocal{sfx}", f"fft_plane{sfx}", f"fft_col_inv{sfx}", f"fft_col_fwd{sfx}")
+            if k in (f"proj{sfx}", f"nonlocal{sfx}", f"fft_plane{sfx}", f"fft_col_inv{sfx}",
+                     f"fft_col_fwd{sfx}")
             and v[1] > 0}
     dom = max(cand, key=lambda k: cand[k][0])
     total_ms, launches = cand[dom]
     avg_ms = total_ms / launches
     # bands per launch: the FFT kernels run once per band chunk and application
     bands_per_launch = nb * steps * applies / launches
-    if dom == "nonlocal":
+    if dom in ("proj", "nonlocal"):
         fl = 8.0 * w.npw * w.nproj * nb
         peak = PEAK["fp64_mfma" if prec == "fp64" else ("bf16_mfma" if prec == "bf16" else "fp32_mfma")]
         ach = fl / (avg_ms * 1e-3) / 1e12
-        return {"kernel": "k_gemm_nn (H psi += P C)", "bound": "mfma", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "avg_launch_ms": avg_ms,
+        mode = "" if prec == "fp64" else ("<F32>" if prec == "fp32" else "<BF16>")
+        sx = "" if prec == "fp64" else "32"
+        if dom == "proj":
+            kname = f"k_gemm_cn{sx}{mode} + k_splitk_reduce{sx} (P^H psi, split-K, KB scale)"
+        else:
+            tall = ham.get_tuning()["nn_tile" if prec == "fp64" else "nn_tile32"] == 1
+            kname = f"k_gemm_nn{sx}{'_tall' if tall else ''}{mode} (H psi += P C)"
+        return {"kernel": kname, "bound": "mfma", "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": measured_traffic(config, prec, dom, "gemm", 1), "avg_launch_ms": avg_ms,
                 "per_launch": f"8*npw*nproj*nb = {fl:.4g} flop"}
     if dom == "fft_plane":
         per_band = N3 * (2 * (xr * fft_flops(N2) + N2 * fft_flops(N1)) + 2.0 * N1 * N2)

@@ -15,6 +15,8 @@
 // only a compiler-level wavefront fence.
 #include "fft_common.h"
 
+#include <algorithm>
+
 using namespace pwfft;
 
 namespace {
@@ -103,15 +105,26 @@ __device__ __forceinline__ void ls_fft_seq(float2* seq, float2* buf, int lb,
 // 64 banks, so the groups' contiguous 24-dword slices tile the banks.
 constexpr int kColSpacing = 12;
 
+// Columns of the sphere per thread kept in registers from one plane to the
+// next (the next plane's are loaded while the current one is transformed);
+// plans with more columns load the rest directly.
+constexpr int kLsPre = 4;
+
 // Q: every sphere point's centred m1 and m2 lie in [-N/4, N/4) (always so
 // when the box holds the density's sphere), which prunes the transforms:
 // the backward N2 and N1 passes start from data zero outside the outer
 // quarters, the forward ones are needed only there.
+//
+// Persistent: workgroup g takes planes L = g, g + G, ... of the n3 x nb
+// (z-plane, band) planes, L = b n3 + j3.
 template <int P, bool Q>
-__device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* __restrict__ tw,
-                                              const float* __restrict__ vs, float2* __restrict__ T,
-                                              int j3, int b) {
+__global__ void __launch_bounds__(kLsMaxWaves * 64)
+k_plane_ls(BoxPlan Pl, const float2* __restrict__ tw, const float* __restrict__ vs,
+           float2* __restrict__ T, int nplanes) {
   constexpr int N = P * P, TRS = N + 1, GPW = 64 / P, XS = ls_buf_stride<P>();
+  // the unpruned transforms need the registers: no prefetch there
+  constexpr int KP = Q ? kLsPre : 0;
+  constexpr int KPA = KP > 0 ? KP : 1;
   extern __shared__ __align__(16) char lds_raw[];
   float2* E = reinterpret_cast<float2*>(lds_raw);                      // xr x TRS
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -130,77 +143,106 @@ __device__ __forceinline__ void plane_ls_body(const BoxPlan& Pl, const float2* _
   // holds columns r kColSpacing GPW + t + kColSpacing gw.
   const int rstride = (N + GPW - 1) / GPW;
   const int ctasks = kColSpacing * ((Pl.xr + kColSpacing * GPW - 1) / (kColSpacing * GPW));
-  float2* tp = T + (size_t)b * Pl.n3 * Pl.ncols + (size_t)j3 * Pl.ncols;
-  if constexpr (Q) {
-    // the backward N2 pass reads only the outer quarters of each column
-    constexpr int H = N / 4;
-    for (int i = tid; i < Pl.xr * 2 * H; i += nt) {
-      const int e = i / (2 * H), j = i - e * (2 * H);
-      E[e * TRS + (j < H ? j : j + N - 2 * H)] = czero<float2>();
-    }
-  } else {
-    for (int i = tid; i < Pl.xr * TRS; i += nt) E[i] = czero<float2>();
-  }
+  const int64_t plane_elems = Pl.ncols;
+  // per plane invariants: extent slots, twiddles, this thread's column positions in E
   for (int i = tid; i < N; i += nt) slot[i] = -1;
   __syncthreads();
   for (int e = tid; e < Pl.xr; e += nt) slot[Pl.ext_m1[e]] = e;
-  for (int c = tid; c < Pl.ncols; c += nt) E[Pl.col_e[c] * TRS + Pl.col_m2[c]] = tp[c];
-  __syncthreads();
+  int cpos[KPA];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int c = tid + k * nt;
+    cpos[k] = c < Pl.ncols ? Pl.col_e[c] * TRS + Pl.col_m2[c] : 0;
+  }
   float2 w[P - 1];
 #pragma unroll
   for (int k = 1; k < P; ++k) w[k - 1] = tw[(lb * k) % N];
-  // backward along N2 on every extent column
-  if (act)
-    for (int t = wave; t < ctasks; t += nw) {
-      const int e = (t / kColSpacing) * (kColSpacing * GPW) + t % kColSpacing + kColSpacing * gw;
-      if (e < Pl.xr) ls_fft_seq<P, +1, Q, false>(E + e * TRS, buf, lb, w);
+  // plane L's block of T: band b = L / n3, z-plane j3 = L % n3, i.e. offset L ncols
+  float2 pre[KPA];
+  auto fetch = [&](int L) {
+    if (L < nplanes) {
+      const float2* tq = T + (size_t)L * plane_elems;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const int c = tid + k * nt;
+        if (c < Pl.ncols) pre[k] = tq[c];
+      }
     }
-  __syncthreads();
-  // rows: backward along N1, x V/N_box, forward along N1
-  if (act) {
-    int sl[P];   // extent slot of positions P a + lb (the same set on output: lb + P k)
-#pragma unroll
-    for (int a = 0; a < P; ++a) sl[a] = slot[P * a + lb];
-    const float* vp = vs + (size_t)j3 * N * N;
-    for (int t = wave; t < rstride; t += nw) {
-      const int row = t + rstride * gw;
-      if (row >= N) continue;
-      float2 v[P];
-#pragma unroll
-      for (int a = 0; a < P; ++a)
-        if (!Q || ls_quarter<P>(a)) v[a] = sl[a] >= 0 ? E[sl[a] * TRS + row] : czero<float2>();
-      ls_fft_regs<P, +1, Q>(v, buf, lb, w);
-      const float* vr = vp + (size_t)row * N + lb;
-#pragma unroll
-      for (int k = 0; k < P; ++k) v[k] = cscale(v[k], vr[P * k]);
-      ls_fft_regs<P, -1>(v, buf, lb, w);
-      // v[k] holds position lb + P k: slot sl[k]
-#pragma unroll
-      for (int k = 0; k < P; ++k)
-        if ((!Q || ls_quarter<P>(k)) && sl[k] >= 0) E[sl[k] * TRS + row] = v[k];
+  };
+  fetch(blockIdx.x);
+  for (int L = blockIdx.x; L < nplanes; L += gridDim.x) {
+    const int j3 = L % Pl.n3;
+    float2* tp = T + (size_t)L * plane_elems;
+    __syncthreads();   // the previous plane's gather is done with E
+    if constexpr (Q) {
+      // the backward N2 pass reads only the outer quarters of each column
+      constexpr int H = N / 4;
+      for (int i = tid; i < Pl.xr * 2 * H; i += nt) {
+        const int e = i / (2 * H), j = i - e * (2 * H);
+        E[e * TRS + (j < H ? j : j + N - 2 * H)] = czero<float2>();
+      }
+    } else {
+      for (int i = tid; i < Pl.xr * TRS; i += nt) E[i] = czero<float2>();
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      if (tid + k * nt < Pl.ncols) E[cpos[k]] = pre[k];
+    for (int c = tid + KP * nt; c < Pl.ncols; c += nt)
+      E[Pl.col_e[c] * TRS + Pl.col_m2[c]] = tp[c];
+    __syncthreads();
+    fetch(L + gridDim.x);   // next plane's columns, in flight during the transforms
+    // backward along N2 on every extent column
+    if (act)
+      for (int t = wave; t < ctasks; t += nw) {
+        const int e = (t / kColSpacing) * (kColSpacing * GPW) + t % kColSpacing + kColSpacing * gw;
+        if (e < Pl.xr) ls_fft_seq<P, +1, Q, false>(E + e * TRS, buf, lb, w);
+      }
+    __syncthreads();
+    // rows: backward along N1, x V/N_box, forward along N1
+    if (act) {
+      int sl[P];   // extent slot of positions P a + lb (the same set on output: lb + P k)
+#pragma unroll
+      for (int a = 0; a < P; ++a) sl[a] = slot[P * a + lb];
+      const float* vp = vs + (size_t)j3 * N * N;
+      for (int t = wave; t < rstride; t += nw) {
+        const int row = t + rstride * gw;
+        if (row >= N) continue;
+        float2 v[P];
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+          if (!Q || ls_quarter<P>(a)) v[a] = sl[a] >= 0 ? E[sl[a] * TRS + row] : czero<float2>();
+        ls_fft_regs<P, +1, Q>(v, buf, lb, w);
+        const float* vr = vp + (size_t)row * N + lb;
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = cscale(v[k], vr[P * k]);
+        ls_fft_regs<P, -1>(v, buf, lb, w);
+        // v[k] holds position lb + P k: slot sl[k]
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+          if ((!Q || ls_quarter<P>(k)) && sl[k] >= 0) E[sl[k] * TRS + row] = v[k];
+      }
+    }
+    __syncthreads();
+    // forward along N2
+    if (act)
+      for (int t = wave; t < ctasks; t += nw) {
+        const int e = (t / kColSpacing) * (kColSpacing * GPW) + t % kColSpacing + kColSpacing * gw;
+        if (e < Pl.xr) ls_fft_seq<P, -1, false, Q>(E + e * TRS, buf, lb, w);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      if (tid + k * nt < Pl.ncols) tp[tid + k * nt] = E[cpos[k]];
+    for (int c = tid + KP * nt; c < Pl.ncols; c += nt)
+      tp[c] = E[Pl.col_e[c] * TRS + Pl.col_m2[c]];
   }
-  __syncthreads();
-  // forward along N2
-  if (act)
-    for (int t = wave; t < ctasks; t += nw) {
-      const int e = (t / kColSpacing) * (kColSpacing * GPW) + t % kColSpacing + kColSpacing * gw;
-      if (e < Pl.xr) ls_fft_seq<P, -1, false, Q>(E + e * TRS, buf, lb, w);
-    }
-  __syncthreads();
-  for (int c = tid; c < Pl.ncols; c += nt) tp[c] = E[Pl.col_e[c] * TRS + Pl.col_m2[c]];
-}
-
-template <int P, bool Q>
-__global__ void __launch_bounds__(kLsMaxWaves * 64)
-k_plane_ls(BoxPlan Pl, const float2* __restrict__ tw, const float* __restrict__ vs,
-           float2* __restrict__ T) {
-  plane_ls_body<P, Q>(Pl, tw, vs, T, blockIdx.x, blockIdx.y);
 }
 
 constexpr int kLsP = 12;   // N1 = N2 = 144
 
 size_t g_ls_lds_limit = 64 * 1024;
+int g_ls_cus = 256;   // compute units of the device (set with the LDS limit)
 
 size_t ls_lds_bytes(const BoxPlan& p, int waves) {
   constexpr int N = kLsP * kLsP, GPW = 64 / kLsP;
@@ -228,17 +270,29 @@ hipError_t launch_fft_plane_ls32(const BoxPlan& p, int nb, const float* vscaled,
   const int waves = ls_waves(p, g_ls_lds_limit);
   if (p.n1 != kLsP * kLsP || p.n2 != p.n1 || p.ax1.tw32 == nullptr || waves < kLsMinWaves)
     return hipErrorInvalidValue;
+  if (nb <= 0) return hipSuccess;
+  // persistent grid: as many workgroups as are resident at once (LDS: one
+  // per CU at C5 sizes; VGPRs: at most 16 wavefronts per CU)
+  const size_t lds = ls_lds_bytes(p, waves);
+  const int per_cu = std::max(1, std::min((int)(g_ls_lds_limit / lds), 16 / waves));
+  const int64_t nplanes = (int64_t)p.n3 * nb;
+  const int grid = (int)std::min<int64_t>(nplanes, (int64_t)g_ls_cus * per_cu);
   if (p.quarter12)
-    hipLaunchKernelGGL((k_plane_ls<kLsP, true>), dim3(p.n3, nb), dim3(waves * 64),
-                       ls_lds_bytes(p, waves), s, p, p.ax1.tw32, vscaled, T);
+    hipLaunchKernelGGL((k_plane_ls<kLsP, true>), dim3(grid), dim3(waves * 64), lds, s, p,
+                       p.ax1.tw32, vscaled, T, (int)nplanes);
   else
-    hipLaunchKernelGGL((k_plane_ls<kLsP, false>), dim3(p.n3, nb), dim3(waves * 64),
-                       ls_lds_bytes(p, waves), s, p, p.ax1.tw32, vscaled, T);
+    hipLaunchKernelGGL((k_plane_ls<kLsP, false>), dim3(grid), dim3(waves * 64), lds, s, p,
+                       p.ax1.tw32, vscaled, T, (int)nplanes);
   return hipGetLastError();
 }
 
 hipError_t fft_ls_set_lds_limit(size_t bytes) {
   g_ls_lds_limit = bytes;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      cus > 0)
+    g_ls_cus = cus;
   hipError_t e = hipFuncSetAttribute((const void*)k_plane_ls<kLsP, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;

@@ -187,20 +187,41 @@ __device__ __forceinline__ void gemm_nn32_body(int64_t M, int64_t N, int64_t K, 
   gemm_nn32_tile<MODE, 2, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
 }
 
+// Workgroups are dealt round-robin over the device's XCDs (each with its own
+// L2), block L to XCD L % kXcds.  The launches below use 1D grids whose block
+// order keeps the blocks that share operand tiles on one XCD and close in
+// time, so those tiles come from that XCD's L2 rather than from HBM.
+constexpr int kXcds = 8;
+
+// Tall products: the tiles_n column tiles of a row panel on one XCD in a row
+// (the panel's rows of A are read once); grid kXcds * tiles_n * ceil(tiles_m / kXcds).
+__device__ __forceinline__ bool xcd_panel_tile(int L, int tiles_m, int tiles_n, int* bx, int* by) {
+  const int x = L % kXcds, slot = L / kXcds;
+  const int panel = x + kXcds * (slot / tiles_n);
+  if (panel >= tiles_m) return false;
+  *by = panel;
+  *bx = slot % tiles_n;
+  return true;
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_gemm_nn32(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restrict__ A,
             int64_t lda, const float2* __restrict__ B, int64_t ldb, float beta,
-            float2* __restrict__ C, int64_t ldc) {
-  gemm_nn32_body<MODE>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
+            float2* __restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
+  int bx, by;
+  if (!xcd_panel_tile(blockIdx.x, tiles_m, tiles_n, &bx, &by)) return;
+  gemm_nn32_body<MODE>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
 }
 
 template <int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_gemm_nn32_tall(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restrict__ A,
                  int64_t lda, const float2* __restrict__ B, int64_t ldb, float beta,
-                 float2* __restrict__ C, int64_t ldc) {
-  gemm_nn32_tile<MODE, 4, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
+                 float2* __restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
+  int bx, by;
+  if (!xcd_panel_tile(blockIdx.x, tiles_m, tiles_n, &bx, &by)) return;
+  gemm_nn32_tile<MODE, 4, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
 }
 
 // Partial (split z over K) A^H B; A k x m (lda), B k x n (ldb); out ld = M.
@@ -278,11 +299,30 @@ __device__ __forceinline__ void gemm_cn32_body(int64_t M, int64_t N, int64_t K, 
       }
 }
 
+// Split-K products: all tiles of one K split on one XCD in a row; they stream
+// the same K range of both operands together, so each K stage is fetched
+// once per XCD.  Grid kXcds * tiles_m * tiles_n * ceil(nsplit / kXcds).
+__device__ __forceinline__ bool xcd_split_tile(int L, int tiles_m, int tiles_n, int nsplit,
+                                               int* bx, int* by, int* bz) {
+  const int x = L % kXcds, slot = L / kXcds;
+  const int per = tiles_m * tiles_n;
+  const int z = x + kXcds * (slot / per);
+  if (z >= nsplit) return false;
+  const int r = slot % per;
+  *by = r / tiles_n;
+  *bx = r % tiles_n;
+  *bz = z;
+  return true;
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __restrict__ A,
-            int64_t lda, const float2* __restrict__ B, int64_t ldb, float2* __restrict__ out) {
-  gemm_cn32_body<MODE>(M, N, K, ksplit, A, lda, B, ldb, out, blockIdx.x, blockIdx.y, blockIdx.z);
+            int64_t lda, const float2* __restrict__ B, int64_t ldb, float2* __restrict__ out,
+            int tiles_m, int tiles_n, int nsplit) {
+  int bx, by, bz;
+  if (!xcd_split_tile(blockIdx.x, tiles_m, tiles_n, nsplit, &bx, &by, &bz)) return;
+  gemm_cn32_body<MODE>(M, N, K, ksplit, A, lda, B, ldb, out, bx, by, bz);
 }
 
 // C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M] (FP64 sum, fixed order), rounded.
@@ -327,6 +367,7 @@ __host__ __device__ inline SplitPlan split_plan32(int64_t m, int64_t n, int64_t 
   // at least two K stages per split (short splits keep small products latency-light)
   const int64_t maxs = (k + Kc * 2 - 1) / (Kc * 2) > 1 ? (k + Kc * 2 - 1) / (Kc * 2) : 1;
   want = want < maxs ? want : maxs;
+  if (want >= 2 * kXcds) want -= want % kXcds;   // whole rounds of splits over the XCDs
   if (want < 1) want = 1;
   int64_t ks = (k + want - 1) / want;
   ks = ((ks + Kc - 1) / Kc) * Kc;
@@ -385,13 +426,13 @@ hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double al
   if (target < 1 || target > kTargetBlocks) target = kTargetBlocks;
   const SplitPlan p = bf16 ? split_plan32<MODE_BF16>(m, n, k, target)
                            : split_plan32<MODE_F32>(m, n, k, target);
-  dim3 grid(p.tiles_n, p.tiles_m, p.nsplit);
+  const dim3 grid((unsigned)(kXcds * p.tiles_m * p.tiles_n * ((p.nsplit + kXcds - 1) / kXcds)));
   if (bf16)
     hipLaunchKernelGGL(k_gemm_cn32<MODE_BF16>, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, A, lda,
-                       B, ldb, work);
+                       B, ldb, work, (int)p.tiles_m, (int)p.tiles_n, (int)p.nsplit);
   else
     hipLaunchKernelGGL(k_gemm_cn32<MODE_F32>, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, A, lda,
-                       B, ldb, work);
+                       B, ldb, work, (int)p.tiles_m, (int)p.tiles_n, (int)p.nsplit);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = m * n;
@@ -404,23 +445,26 @@ hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double al
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
                             int64_t ldc, hipStream_t s, int tile) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  const int tn = (int)((n + kBN - 1) / kBN);
   if (tile == 1) {
-    dim3 grid((n + kBN - 1) / kBN, (m + 2 * kBM - 1) / (2 * kBM), 1);
+    const int tm = (int)((m + 2 * kBM - 1) / (2 * kBM));
+    const dim3 grid((unsigned)(kXcds * tn * ((tm + kXcds - 1) / kXcds)));
     if (bf16)
       hipLaunchKernelGGL(k_gemm_nn32_tall<MODE_BF16>, grid, dim3(kThreads), 0, s, m, n, k,
-                         (float)alpha, A, lda, B, ldb, (float)beta, C, ldc);
+                         (float)alpha, A, lda, B, ldb, (float)beta, C, ldc, tm, tn);
     else
       hipLaunchKernelGGL(k_gemm_nn32_tall<MODE_F32>, grid, dim3(kThreads), 0, s, m, n, k,
-                         (float)alpha, A, lda, B, ldb, (float)beta, C, ldc);
+                         (float)alpha, A, lda, B, ldb, (float)beta, C, ldc, tm, tn);
     return hipGetLastError();
   }
-  dim3 grid((n + kBN - 1) / kBN, (m + kBM - 1) / kBM, 1);
+  const int tm = (int)((m + kBM - 1) / kBM);
+  const dim3 grid((unsigned)(kXcds * tn * ((tm + kXcds - 1) / kXcds)));
   if (bf16)
     hipLaunchKernelGGL(k_gemm_nn32<MODE_BF16>, grid, dim3(kThreads), 0, s, m, n, k, (float)alpha, A,
-                       lda, B, ldb, (float)beta, C, ldc);
+                       lda, B, ldb, (float)beta, C, ldc, tm, tn);
   else
     hipLaunchKernelGGL(k_gemm_nn32<MODE_F32>, grid, dim3(kThreads), 0, s, m, n, k, (float)alpha, A,
-                       lda, B, ldb, (float)beta, C, ldc);
+                       lda, B, ldb, (float)beta, C, ldc, tm, tn);
   return hipGetLastError();
 }
 
