@@ -132,18 +132,48 @@ __device__ __forceinline__ void gemm_nn_body(int64_t M, int64_t N, int64_t K, do
   gemm_nn_tile<2, 2, kKcNN>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
 }
 
+// Workgroups are dealt round-robin over the device's XCDs (each with its own
+// L2), block L to XCD L % kXcds.  The launches use 1D grids whose block order
+// keeps the blocks that share operand tiles on one XCD and close in time.
+constexpr int kXcds = 8;
+
+// the tiles_n column tiles of a row panel on one XCD in a row;
+// grid kXcds * tiles_n * ceil(tiles_m / kXcds)
+__device__ __forceinline__ bool xcd_panel_tile(int L, int tiles_m, int tiles_n, int* bx, int* by) {
+  const int x = L % kXcds, slot = L / kXcds;
+  const int panel = x + kXcds * (slot / tiles_n);
+  if (panel >= tiles_m) return false;
+  *by = panel;
+  *bx = slot % tiles_n;
+  return true;
+}
+
+// all `per` tiles of one K split on one XCD in a row;
+// grid kXcds * per * ceil(nsplit / kXcds); returns the tile index within the split
+__device__ __forceinline__ bool xcd_split(int L, int per, int nsplit, int* tile, int* z) {
+  const int x = L % kXcds, slot = L / kXcds;
+  *z = x + kXcds * (slot / per);
+  *tile = slot % per;
+  return *z < nsplit;
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_gemm_nn(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict__ A, int64_t lda,
-          const cplx* __restrict__ B, int64_t ldb, double beta, cplx* __restrict__ C, int64_t ldc) {
-  gemm_nn_body(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
+          const cplx* __restrict__ B, int64_t ldb, double beta, cplx* __restrict__ C, int64_t ldc,
+          int tiles_m, int tiles_n) {
+  int bx, by;
+  if (!xcd_panel_tile(blockIdx.x, tiles_m, tiles_n, &bx, &by)) return;
+  gemm_nn_body(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
 }
 
 // 128 x 64 workgroup tiles for tall products (M = plane waves)
 __global__ void __launch_bounds__(kThreads)
 k_gemm_nn_tall(int64_t M, int64_t N, int64_t K, double alpha, const cplx* __restrict__ A,
                int64_t lda, const cplx* __restrict__ B, int64_t ldb, double beta,
-               cplx* __restrict__ C, int64_t ldc) {
-  gemm_nn_tile<4, 2, kKcNN>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.x, blockIdx.y);
+               cplx* __restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
+  int bx, by;
+  if (!xcd_panel_tile(blockIdx.x, tiles_m, tiles_n, &bx, &by)) return;
+  gemm_nn_tile<4, 2, kKcNN>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
 }
 
 // Partial or final C = alpha diag(rowscale) A^H B over K range [kb, ke) of split z.
@@ -257,6 +287,17 @@ k_gemm_cn(int64_t M, int64_t N, int64_t K, int64_t ksplit, double alpha,
                blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// split partials of A^H B into work (ld M, split stride M N), XCD-grouped 1D grid
+__global__ void __launch_bounds__(kThreads)
+k_gemm_cn_split(int64_t M, int64_t N, int64_t K, int64_t ksplit, const cplx* __restrict__ A,
+                int64_t lda, const cplx* __restrict__ B, int64_t ldb, cplx* __restrict__ work,
+                int tiles_m, int tiles_n, int nsplit) {
+  int t, z;
+  if (!xcd_split(blockIdx.x, tiles_m * tiles_n, nsplit, &t, &z)) return;
+  gemm_cn_body(M, N, K, ksplit, 1.0, nullptr, nullptr, A, lda, B, ldb, 0.0, work, M, M * N,
+               t % tiles_n, t / tiles_n, z);
+}
+
 // C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M], z in fixed order.
 __device__ __forceinline__ void splitk_reduce_body(int64_t M, int64_t N, int nsplit,
                                                    const cplx* __restrict__ work, double alpha,
@@ -303,13 +344,15 @@ __device__ __forceinline__ void upper_tile(int t, int* by, int* bx) {
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_gemm_cn_upper(int64_t M, int64_t K, int64_t ksplit, int nact, const cplx* __restrict__ A,
-                int64_t lda, const cplx* __restrict__ B, int64_t ldb, cplx* __restrict__ work) {
-  int by, bx;
-  upper_tile(blockIdx.x, &by, &bx);
+k_gemm_cn_upper(int64_t M, int64_t K, int64_t ksplit, int nact, int nsplit,
+                const cplx* __restrict__ A, int64_t lda, const cplx* __restrict__ B, int64_t ldb,
+                cplx* __restrict__ work) {
+  int t, z, by, bx;
+  if (!xcd_split(blockIdx.x, nact, nsplit, &t, &z)) return;
+  upper_tile(t, &by, &bx);
   gemm_cn_body(M, M, K, ksplit, 1.0, nullptr, nullptr, A, lda, B, ldb, 0.0,
-               work + (int64_t)blockIdx.x * kBM * kBN, kBM, (int64_t)nact * kBM * kBN, bx, by,
-               blockIdx.z, (int64_t)by * kBM, (int64_t)bx * kBN);
+               work + (int64_t)t * kBM * kBN, kBM, (int64_t)nact * kBM * kBN, bx, by, z,
+               (int64_t)by * kBM, (int64_t)bx * kBN);
 }
 
 // C[i + j ldc] = alpha sum_z (packed partials), fixed order, for the
@@ -345,6 +388,7 @@ __host__ __device__ inline SplitPlan split_plan(int64_t m, int64_t n, int64_t k,
   // at least two K stages per split (short splits keep small products latency-light)
   const int64_t maxs = (k + kKcCN * 2 - 1) / (kKcCN * 2) > 1 ? (k + kKcCN * 2 - 1) / (kKcCN * 2) : 1;
   want = want < maxs ? want : maxs;
+  if (want >= 2 * kXcds) want -= want % kXcds;   // whole rounds of splits over the XCDs
   if (want < 1) want = 1;
   int64_t ks = (k + want - 1) / want;
   ks = ((ks + kKcCN - 1) / kKcCN) * kKcCN;
@@ -468,13 +512,14 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
     const int64_t maxs = (k + kKcCN * 2 - 1) / (kKcCN * 2) > 1 ? (k + kKcCN * 2 - 1) / (kKcCN * 2) : 1;
     int64_t want = (target + nact - 1) / nact;
     want = std::min(want, std::min(maxs, cap));
+    if (want >= 2 * kXcds) want -= want % kXcds;
     if (want < 1) want = 1;
     int64_t ks = (k + want - 1) / want;
     ks = ((ks + kKcCN - 1) / kKcCN) * kKcCN;
     ks = std::max<int64_t>(ks, kKcCN);
     const int64_t ns = (k + ks - 1) / ks;
-    hipLaunchKernelGGL(k_gemm_cn_upper, dim3((unsigned)nact, 1, (unsigned)ns), dim3(kThreads), 0, s,
-                       m, k, ks, (int)nact, A, lda, B, ldb, work);
+    hipLaunchKernelGGL(k_gemm_cn_upper, dim3((unsigned)(kXcds * nact * ((ns + kXcds - 1) / kXcds))),
+                       dim3(kThreads), 0, s, m, k, ks, (int)nact, (int)ns, A, lda, B, ldb, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_splitk_reduce_upper, dim3((unsigned)((m * m + 255) / 256)), dim3(256), 0, s,
@@ -491,10 +536,9 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
                        rowscale, A, lda, B, ldb, beta, C, ldc, (int64_t)0, upper);
     return hipGetLastError();
   }
-  dim3 grid(p.tiles_n, p.tiles_m, p.nsplit);
-  hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, 1.0,
-                     (const double*)nullptr, (const double*)nullptr, A, lda, B, ldb, 0.0, work, m,
-                     m * n, 0);
+  const dim3 grid((unsigned)(kXcds * p.tiles_m * p.tiles_n * ((p.nsplit + kXcds - 1) / kXcds)));
+  hipLaunchKernelGGL(k_gemm_cn_split, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, A, lda, B, ldb,
+                     work, (int)p.tiles_m, (int)p.tiles_n, (int)p.nsplit);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = m * n;
@@ -507,15 +551,18 @@ hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const c
                           const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,
                           hipStream_t s, int tile) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  const int tn = (int)((n + kBN - 1) / kBN);
   if (tile == 1) {
-    dim3 grid((n + kBN - 1) / kBN, (m + 2 * kBM - 1) / (2 * kBM), 1);
+    const int tm = (int)((m + 2 * kBM - 1) / (2 * kBM));
+    const dim3 grid((unsigned)(kXcds * tn * ((tm + kXcds - 1) / kXcds)));
     hipLaunchKernelGGL(k_gemm_nn_tall, grid, dim3(kThreads), 0, s, m, n, k, alpha, A, lda, B, ldb,
-                       beta, C, ldc);
+                       beta, C, ldc, tm, tn);
     return hipGetLastError();
   }
-  dim3 grid((n + kBN - 1) / kBN, (m + kBM - 1) / kBM, 1);
+  const int tm = (int)((m + kBM - 1) / kBM);
+  const dim3 grid((unsigned)(kXcds * tn * ((tm + kXcds - 1) / kXcds)));
   hipLaunchKernelGGL(k_gemm_nn, grid, dim3(kThreads), 0, s, m, n, k, alpha, A, lda, B, ldb, beta,
-                     C, ldc);
+                     C, ldc, tm, tn);
   return hipGetLastError();
 }
 
