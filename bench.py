@@ -104,7 +104,11 @@ def measured_traffic(config, prec, stage, kernel, bands_per_launch):
     h = hashlib.sha1()
     for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if vals.get("kernel_source_sha1") != h.hexdigest() or "traffic_bytes_per_band" not in vals:
+    if vals.get("kernel_source_sha1") != h.hexdigest():
+        return None
+    if "traffic_bytes_per_launch" in vals:
+        return float(vals["traffic_bytes_per_launch"])
+    if "traffic_bytes_per_band" not in vals:
         return None
     return float(vals["traffic_bytes_per_band"]) * bands_per_launch
 
