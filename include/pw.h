@@ -44,7 +44,7 @@ extern "C" {
 typedef enum {
   PW_OK = 0,
   PW_ERR_INVALID_ARG = 1,   /* null pointer, size or leading dimension out of range   */
-  PW_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement             */
+  PW_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement            */
   PW_ERR_HIP = 3,           /* a HIP runtime call failed (message has the HIP string)  */
   PW_ERR_OOM = 4,           /* device allocation failed                                */
   PW_ERR_NOT_POSDEF = 5,    /* Gram matrix not numerically positive definite           */
