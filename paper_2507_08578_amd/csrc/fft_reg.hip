@@ -29,12 +29,24 @@ __device__ __forceinline__ void col_inv_reg_body(const BoxPlan& P, const C* __re
   const int ncl = min(CT, P.ncols - c0);
   for (int i = threadIdx.x; i < CT * TRS; i += blockDim.x) tile[i] = czero<C>();
   __syncthreads();
-  const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
   const C* src = psi + (size_t)b * ldpsi;
-  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
-    tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]] = src[P.pt_perm[k]];
-  __syncthreads();
   const int grp = threadIdx.x / G, lb = threadIdx.x % G;
+  if (P.runs) {
+    // one lane group per column: its points are consecutive in psi and in m3
+    if (grp < ncl) {
+      const int c = c0 + grp, ks = P.col_start[c], len = P.col_start[c + 1] - ks;
+      const int lo = P.col_m3lo[c];
+      for (int j = lb; j < len; j += G) {
+        const int m = lo + j;
+        tile[grp * TRS + (m < 0 ? m + N3 : m)] = src[ks + j];
+      }
+    }
+  } else {
+    const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
+    for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
+      tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]] = src[P.pt_perm[k]];
+  }
+  __syncthreads();
   if (grp < ncl) {
     C v[R];
     C* col = tile + grp * TRS;
@@ -101,13 +113,10 @@ __device__ __forceinline__ void col_fwd_reg_body(const BoxPlan& P, const C* __re
     for (int a = 0; a < R; ++a) col[G * a + lb] = v[a];
   }
   __syncthreads();
-  const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
   const C* inb = in + (size_t)b * ldin;
   C* outb = out + (size_t)b * ldout;
   const C* prevb = prev ? prev + (size_t)b * ldprev : nullptr;
-  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-    const int g = P.pt_perm[k];
-    const C loc = tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]];
+  auto emit = [&](int g, const C& loc) {
     const C x = inb[g];
     const Rl t = kin[g];
     C val;
@@ -119,6 +128,21 @@ __device__ __forceinline__ void col_fwd_reg_body(const BoxPlan& P, const C* __re
       val.y += gamma * p.y;
     }
     outb[g] = val;
+  };
+  if (P.runs) {
+    // one lane group per column: its points are consecutive in psi and in m3
+    if (grp < ncl) {
+      const int c = c0 + grp, ks = P.col_start[c], len = P.col_start[c + 1] - ks;
+      const int lo = P.col_m3lo[c];
+      for (int j = lb; j < len; j += G) {
+        const int m = lo + j;
+        emit(ks + j, tile[grp * TRS + (m < 0 ? m + N3 : m)]);
+      }
+    }
+  } else {
+    const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
+    for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
+      emit(P.pt_perm[k], tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]]);
   }
 }
 

@@ -907,14 +907,19 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
     if (bx != by) return bx < by;
     return center(m3[x], P.n3) < center(m3[y], P.n3);
   });
-  std::vector<int> col_start, col_m1, col_m2v, pt_col(npw), pt_m3(npw);
+  std::vector<int> col_start, col_m1, col_m2v, col_m3lo, pt_col(npw), pt_m3(npw);
+  P.runs = 1;
   for (int64_t k = 0; k < npw; ++k) {
     const int g = order[k];
     if (k == 0 || m1[g] != m1[order[k - 1]] || m2[g] != m2[order[k - 1]]) {
       col_start.push_back((int)k);
       col_m1.push_back(m1[g]);
       col_m2v.push_back(m2[g]);
+      col_m3lo.push_back(center(m3[g], P.n3));
+    } else if (center(m3[g], P.n3) != center(m3[order[k - 1]], P.n3) + 1) {
+      P.runs = 0;   // a gap along N3 inside a column
     }
+    if (g != (int)k) P.runs = 0;   // not in column order
     pt_col[k] = (int)col_start.size() - 1;
     pt_m3[k] = m3[g];
   }
@@ -961,6 +966,7 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   TRY(upload_int(&P.pt_perm, order));
   TRY(upload_int(&P.pt_col, pt_col));
   TRY(upload_int(&P.pt_m3, pt_m3));
+  TRY(upload_int(&P.col_m3lo, col_m3lo));
   TRY(upload_int(&P.ext_m1, ext));
   // twiddles
   FftAxis* axes[3] = {&P.ax1, &P.ax2, &P.ax3};

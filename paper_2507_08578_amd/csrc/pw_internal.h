@@ -39,6 +39,12 @@ struct BoxPlan {
   int* pt_m3;               // npw: box index m3 of the k-th point (column order)
   int* ext_m1;              // xr: box index m1 of extent slot e
   int quarter12;            // 1: every point's centred m1 and m2 lie in [-N/4, N/4)
+  // 1: the caller's order is the column order (pt_perm is the identity); a
+  // column's points then hold consecutive centred m3 from col_m3lo[c] up
+  // (the sphere is convex along N3), so the column kernels need no per-point
+  // index arrays
+  int runs;
+  int* col_m3lo;            // ncols: centred m3 of the column's first point
   FftAxis ax1, ax2, ax3;
 };
 
