@@ -775,11 +775,17 @@ __global__ void k_jacobi_scatter(int n, int ld, const cplx* __restrict__ A,
   if (i == 0) w[rp] = A[p + (int64_t)p * ld].x;
 }
 
-__global__ void __launch_bounds__(1024) k_offnorm(int n, const cplx* __restrict__ A, double* out) {
-  __shared__ double r1[1024], r2[1024];
+// Squared off-diagonal and total Frobenius norms of A (n x n), in two fixed-
+// order stages: kOffParts workgroups sum interleaved slices into part[2 w],
+// part[2 w + 1]; one workgroup adds the parts.
+constexpr int kOffParts = 256;
+__global__ void __launch_bounds__(256) k_offnorm_part(int n, const cplx* __restrict__ A,
+                                                      double* __restrict__ part) {
+  __shared__ double r1[256], r2[256];
   double off = 0.0, tot = 0.0;
   const int64_t nn = (int64_t)n * n;
-  for (int64_t idx = threadIdx.x; idx < nn; idx += blockDim.x) {
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < nn;
+       idx += (int64_t)kOffParts * 256) {
     const int64_t j = idx / n, i = idx - j * n;
     const double m2 = cabs2(A[idx]);
     tot += m2;
@@ -788,7 +794,26 @@ __global__ void __launch_bounds__(1024) k_offnorm(int n, const cplx* __restrict_
   r1[threadIdx.x] = off;
   r2[threadIdx.x] = tot;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      r1[threadIdx.x] += r1[threadIdx.x + s];
+      r2[threadIdx.x] += r2[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r1[0];
+    part[2 * blockIdx.x + 1] = r2[0];
+  }
+}
+
+__global__ void __launch_bounds__(kOffParts) k_offnorm_final(const double* __restrict__ part,
+                                                            double* __restrict__ out) {
+  __shared__ double r1[kOffParts], r2[kOffParts];
+  r1[threadIdx.x] = part[2 * threadIdx.x];
+  r2[threadIdx.x] = part[2 * threadIdx.x + 1];
+  __syncthreads();
+  for (int s = kOffParts / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
       r1[threadIdx.x] += r1[threadIdx.x + s];
       r2[threadIdx.x] += r2[threadIdx.x + s];
@@ -1130,7 +1155,7 @@ static int64_t bj_padded(int64_t n) { return (n + kBJTile - 1) / kBJTile * kBJTi
 size_t heev_work_bytes(int64_t n) {
   const int64_t n2p = bj_padded(n);
   return (size_t)(n2p * n2p + n * n2p + n2p * kBJS) * sizeof(cplx) + (size_t)(n + 8) * sizeof(int) +
-         64;
+         64 + 2 * kOffParts * sizeof(double);
 }
 
 hipError_t heev_set_lds_limit(size_t bytes) {
@@ -1164,6 +1189,7 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
   int* dev_int = reinterpret_cast<int*>(base + mat_bytes);
   const size_t stat_off = (mat_bytes + (size_t)(n + 8) * sizeof(int) + 15) & ~(size_t)15;
   double* dstat = reinterpret_cast<double*>(base + stat_off);
+  double* dpart = dstat + 2;   // kOffParts pairs of partial norms
   if (n <= kJacSmallMax) {
     const size_t lds = (size_t)(n * (2 * n + 1)) * sizeof(cplx);
     hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(jac_threads((int)n)), lds, s, (int)n,
@@ -1190,7 +1216,9 @@ hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int6
   int sw = 0;
   bool conv = false;
   for (; sw <= kMaxSweeps; ++sw) {
-    hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, s, (int)n2p, (const cplx*)A, dstat);
+    hipLaunchKernelGGL(k_offnorm_part, dim3(kOffParts), dim3(256), 0, s, (int)n2p, (const cplx*)A,
+                       dpart);
+    hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(kOffParts), 0, s, (const double*)dpart, dstat);
     e = hipMemcpyAsync(host_scratch, dstat, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
