@@ -13,5 +13,5 @@ from .pw_oracle import (  # noqa: F401
     kinetic, scatter_to_box, gather_from_box, fft_backward, fft_forward,
     dft_backward_direct, dft_forward_direct, apply_local, apply_nonlocal, apply_h,
     dense_h, upper_bound, cheb_filter, cheb_filter_closed_form, orthonormalize,
-    rayleigh_ritz, chfsi, OracleHam,
+    rayleigh_ritz, chfsi, OracleHam, cell_volume, density, density_at,
 )

@@ -303,3 +303,45 @@ def chfsi(ham: OracleHam, X0: np.ndarray, degree: int, iters: int,
         eigs.append(lam)
         res.append(r)
     return ChfsiResult(eig_history=eigs, resid_history=res, Y=Y, upper=b)
+
+
+# ----------------------------------------------------------------------------
+# Electron density of a block of bands (section 2.4, Eq. nandtau; the
+# band-and-k sum of Eq. extfpmd_density in section 2.3, without its
+# free-electron term N_ext / Omega)
+# ----------------------------------------------------------------------------
+
+def cell_volume(ham: OracleHam) -> float:
+    """Omega = (2 pi)^3 / |det B| for reciprocal rows b_i (a_i . b_j = 2 pi delta_ij)."""
+    return float((2.0 * np.pi) ** 3 / abs(np.linalg.det(ham.recip)))
+
+
+def density(ham: OracleHam, psi: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """n(r_j) = sum_b w_b |psi_b(r_j)|^2 at the box points r_j = (j1/N1, j2/N2, j3/N3) A.
+
+    psi_b(r) = Omega^{-1/2} sum_G c_b(G) e^{i(k+G).r}: a band whose
+    coefficients have unit norm holds one electron in the cell, and the
+    factor e^{ik.r} has modulus one, so |psi_b(r_j)|^2 is
+    |fft_backward(scatter(c_b))[j]|^2 / Omega.  w_b is the band's occupation
+    times its k-point weight.  Returns shape (N3, N2, N1).
+    """
+    grid = fft_backward(scatter_to_box(ham, np.asarray(psi, dtype=np.complex128)))
+    dens = np.zeros(grid.shape[1:], dtype=np.float64)
+    for b in range(grid.shape[0]):
+        dens += float(w[b]) * np.abs(grid[b]) ** 2
+    return dens / cell_volume(ham)
+
+
+def density_at(ham: OracleHam, psi: np.ndarray, w: np.ndarray, points: np.ndarray) -> np.ndarray:
+    """n at selected box points, each summed directly over the sphere:
+    psi_b(r_j) = Omega^{-1/2} sum_g c_b(g) exp(2 pi i sum_i n_i(g) j_i / N_i).
+    points: (P, 3) integer (j1, j2, j3).  For full-size blocks the box never
+    has to exist."""
+    N = np.asarray(ham.box, dtype=np.float64)
+    n = ham.miller.astype(np.float64)
+    out = np.empty(len(points))
+    for p, j in enumerate(np.asarray(points)):
+        phase = np.exp(2j * np.pi * (n @ (np.asarray(j, dtype=np.float64) / N)))
+        amp = phase @ np.asarray(psi, dtype=np.complex128)      # (nb,)
+        out[p] = float(np.sum(np.asarray(w, dtype=np.float64) * np.abs(amp) ** 2))
+    return out / cell_volume(ham)
