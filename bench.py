@@ -204,6 +204,68 @@ def cpu_baseline(w, nb_sample, seed=0):
                       f"(numpy FFT + BLAS), {dt:.2f} s"}
 
 
+def density_leg(ctx, ham, w, X0, steps, warmup):
+    """Electron density of the resident block (section 2.4, Eq. nandtau), every
+    band with occupation 2: `steps` pw_density calls timed after `warmup`.
+    Roofline of its plane kernel (vector ALU, FP64): per band and z-plane
+    xr 5 N2 log2 N2 + N2 5 N1 log2 N1 + 4 N1 N2 flop (the two backward
+    transforms, w |.|^2 added), x bands per launch, over the kernel's average
+    launch time; charge = (Omega / N_box) sum_j n(r_j) against
+    sum_b w_b |c_b|^2 (Parseval) as a check of the timed result."""
+    import torch
+    nb = X0.shape[0]
+    wt = torch.full((nb,), 2.0, dtype=torch.float64, device="cuda")
+    rho = ham.density(X0, wt)
+    for _ in range(warmup):
+        ham.density(X0, wt, rho=rho)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.reset_timing()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ham.density(X0, wt, rho=rho)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    N1, N2, N3 = w.box
+    xr = ham.extent1
+    total, launches = st["density"]
+    avg_ms = total / launches
+    bands_per_launch = nb * steps / launches
+    per_band = N3 * (xr * fft_flops(N2) + N2 * fft_flops(N1) + 4.0 * N1 * N2)
+    ach = per_band * bands_per_launch / (avg_ms * 1e-3) / 1e12
+    reg = N1 == N2 and N1 in (24, 30, 32, 36, 48, 64, 72, 96, 120, 128, 144, 160)
+    kname = f"k_density_reg<{N1},16>" if reg else "k_density_plane"
+    charge = w.cell.volume / (N1 * N2 * N3) * float(rho.sum().item())
+    ref_charge = 2.0 * float((X0.abs() ** 2).sum().item())
+    return {"ms_per_call": 1e3 * dt, "nb": nb, "value": nb / dt, "unit": "band densities/s",
+            "stages_ms_per_call": {k: v[0] / steps for k, v in st.items() if v[1]},
+            "charge_rel_err": abs(charge - ref_charge) / ref_charge,
+            "roofline": {"kernel": f"{kname} (N2/N1 backward transforms, w |psi|^2 summed)",
+                         "bound": "alu", "achieved": ach, "peak": PEAK["fp64_valu"],
+                         "unit": "TFLOP/s", "frac": ach / PEAK["fp64_valu"], "traffic": None,
+                         "avg_launch_ms": avg_ms,
+                         "per_launch": f"{per_band:.4g} flop/band x {bands_per_launch:.0f} bands"}}
+
+
+def cpu_density_baseline(w, nb_sample, seed=0):
+    """Oracle density (numpy FFT per band) on nb_sample bands, timed on the host."""
+    import numpy as np
+    import oracle
+    import synth
+    oh = oracle.OracleHam.from_workload(w)
+    X = synth.start_block(w.npw, nb_sample, seed).T
+    wt = np.full(nb_sample, 2.0)
+    oracle.density(oh, X[:, :1], wt[:1])          # first-touch
+    t0 = time.perf_counter()
+    oracle.density(oh, X, wt)
+    dt = time.perf_counter() - t0
+    return {"value": nb_sample / dt, "unit": "band densities/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nb_sample} bands of the FP64 oracle density on {w.name} "
+                      f"(numpy FFT, one thread), {dt:.2f} s"}
+
+
 def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup):
     """Iteration 0 + warmup + timed steps from X0; returns timings and the last Ritz values."""
     import torch
@@ -448,6 +510,8 @@ def main():
                     help="filter precision of the reported path (subspace steps are FP64)")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the electron-density measurement")
     ap.add_argument("--cpu-bands", type=int, default=0, help="oracle band sample (0 = auto)")
     ap.add_argument("--streams", type=int, default=8, help="batch branches (C2, C4)")
     ap.add_argument("--graph", default="fused", choices=["single", "per_stream", "fused", "none"],
@@ -521,6 +585,12 @@ def main():
                             "stages_ms_per_step": {k: v[0] / args.steps
                                                    for k, v in ref["stages"].items()}}
         out["eig_diff_vs_fp64_Ha"] = d
+    if not args.no_density:
+        log("electron density")
+        out["density"] = density_leg(ctx, ham, w, X0, args.steps, args.warmup)
+        if not args.no_cpu_baseline:
+            nbd = {"C1": 512, "C3": 32, "C5": 16}[args.config]
+            out["density"]["cpu_baseline"] = cpu_density_baseline(w, nbd)
     if not args.no_cpu_baseline:
         nbs = args.cpu_bands or {"C1": 2048, "C3": 64, "C5": 160}[args.config]
         log(f"cpu baseline: oracle H*psi on {nbs} bands")

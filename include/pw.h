@@ -147,6 +147,33 @@ pw_status pw_apply_h(pw_ham* ham, pw_prec prec, int64_t nb, const void* psi_dev,
                      void* hpsi_dev, int64_t ldh);
 
 /*
+ * Electron density of a block of bands (section 2.4, Eq. nandtau; the band
+ * sum of Eq. extfpmd_density in section 2.3, without its free-electron
+ * term N_ext / Omega, which the caller adds):
+ *   rho(r_j) [+]= (1/Omega) sum_b w_b |F_bwd(scatter psi_b)(r_j)|^2,
+ * F_bwd the unnormalised e^{+2 pi i m.j/N} transform of pw_apply_h, Omega =
+ * (2 pi)^3 / |det B| from the handle's reciprocal lattice; a band with unit
+ * coefficient norm then holds one electron in the cell.
+ *   psi_dev  DEVICE, npw x nb complex128, column-major, leading dim ldpsi >= npw
+ *            (may be NULL when nb = 0).
+ *   w_dev    DEVICE, nb float64: occupation times k-point weight of each band
+ *            (any sign; may be NULL when nb = 0).
+ *   rho_dev  DEVICE, N1*N2*N3 float64, layout [N3][N2][N1] (N1 fastest, as
+ *            vloc).  accumulate = 0: overwritten (nb = 0 writes zeros);
+ *            1: the block's density is added (sums over k-points).  Must not
+ *            overlap psi_dev or w_dev.
+ * 0 <= nb <= nb_max.  FP64 throughout.  Deterministic: every sum runs in an
+ * order fixed by the handle (bands in chunks, partial sums per band group
+ * added in group order).  The first call allocates the handle's partial-sum
+ * array (a few x N1 N2 N3 float64; freed with the handle); later calls
+ * allocate nothing.  Enqueued on the context's stream; returns without
+ * synchronising.  Errors: INVALID_ARG (nb out of range, NULL pointers,
+ * ld < npw, accumulate not 0/1, singular lattice), OOM, HIP.
+ */
+pw_status pw_density(pw_ham* ham, int64_t nb, const void* psi_dev, int64_t ldpsi,
+                     const double* w_dev, double* rho_dev, int32_t accumulate);
+
+/*
  * Chebyshev filter of degree m >= 1 (section 5.1; the paper cites the
  * filter without formulas, this is the textbook scaled three-term form):
  *   y <- p_m(H) y,  p_m(t) = T_m((t-c)/e) / T_m((a0-c)/e),  c=(a+b)/2, e=(b-a)/2,
@@ -334,7 +361,9 @@ typedef enum {
   PW_STAGE_FFT_COL_FWD_LP = 12,
   PW_STAGE_PROJ_LP = 13,
   PW_STAGE_NONLOCAL_LP = 14,
-  PW_STAGE_COUNT = 15
+  PW_STAGE_DENSITY = 15,     /* density planes: N2/N1 backward, w |.|^2 summed (the final
+                                sum of the band groups' partials counts under MISC)      */
+  PW_STAGE_COUNT = 16
 } pw_stage;
 
 pw_status pw_ctx_set_timing(pw_ctx* ctx, int enable);

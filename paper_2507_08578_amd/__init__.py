@@ -241,6 +241,28 @@ class Hamiltonian:
         self.ctx.check(_LIB.pw_apply_h(self.handle, pr, psi.shape[0], p, ldp, o, ldo))
         return out
 
+    def density(self, psi, w, rho=None, accumulate=False):
+        """rho(r_j) [+]= (1/Omega) sum_b w_b |psi_b(r_j)|^2 on the box, float64 (N3, N2, N1).
+
+        psi: complex128 block (nb, npw); w: float64 CUDA tensor of nb weights
+        (occupation x k-point weight); accumulate adds to rho instead of
+        overwriting it."""
+        import torch
+        p, ldp = _block_args(psi, self.npw, "psi")
+        nb = psi.shape[0]
+        if (not isinstance(w, torch.Tensor) or not w.is_cuda or w.dtype != torch.float64
+                or w.dim() != 1 or w.shape[0] != nb or not w.is_contiguous()):
+            raise TypeError(f"w must be a contiguous float64 CUDA tensor of {nb} weights")
+        N1, N2, N3 = self.box
+        if rho is None:
+            rho = torch.empty((N3, N2, N1), dtype=torch.float64, device=psi.device)
+        if (not isinstance(rho, torch.Tensor) or not rho.is_cuda or rho.dtype != torch.float64
+                or not rho.is_contiguous() or rho.numel() != N1 * N2 * N3):
+            raise TypeError(f"rho must be a contiguous float64 CUDA tensor of {N1 * N2 * N3} values")
+        self.ctx.check(_LIB.pw_density(self.handle, nb, p, ldp, ctypes.c_void_p(w.data_ptr()),
+                                       ctypes.c_void_p(rho.data_ptr()), int(bool(accumulate))))
+        return rho
+
     def cheb_filter(self, y, degree: int, a: float, b: float, a0: float, hx=None, prec="fp64"):
         """y <- p_m(H) y in place (complex128 block; prec selects the internal arithmetic)."""
         p, ld = _block_args(y, self.npw, "y")

@@ -22,7 +22,7 @@ PW_OK = 0
 PW_FP64, PW_FP32, PW_BF16 = 0, 1, 2
 STAGES = ["fft_col_inv", "fft_plane", "fft_col_fwd", "proj", "nonlocal", "gram", "chol",
           "rotate", "eigh", "misc", "fft_col_inv_lp", "fft_plane_lp", "fft_col_fwd_lp", "proj_lp",
-          "nonlocal_lp"]
+          "nonlocal_lp", "density"]
 
 
 class PwHamDesc(ctypes.Structure):
@@ -59,6 +59,7 @@ SIGNATURES = {
     "pw_ham_destroy": (c_int, [c_void_p]),
     "pw_ham_info": (c_int, [c_void_p] + [ctypes.POINTER(c_int64)] * 5),
     "pw_apply_h": (c_int, [c_void_p, c_int, c_int64, c_void_p, c_int64, c_void_p, c_int64]),
+    "pw_density": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int32]),
     "pw_cheb_filter": (c_int, [c_void_p, c_int, c_int32, c_double, c_double, c_double, c_int64,
                                c_void_p, c_int64, c_void_p, c_int64]),
     "pw_orthonormalize": (c_int, [c_void_p, c_int, c_int64, c_void_p, c_int64, c_void_p, c_int64]),

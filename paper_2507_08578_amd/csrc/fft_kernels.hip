@@ -195,6 +195,57 @@ k_plane(PlanArgs P, int rb, const real_t<C>* __restrict__ v, C* __restrict__ T) 
   plane_body<C>(P, rb, v, T, blockIdx.x, blockIdx.y);
 }
 
+// Electron density, any box (section 2.4, Eq. nandtau): for z-plane j3 and
+// band group g, the backward N2 and N1 transforms of the chunk's bands
+// b = g, g + ngroup, ... as in plane_body, w_b |.|^2 added to the group's
+// partial array part[g][j3][j2][j1].  Element i of a row batch belongs to
+// thread i mod blockDim for every band, so each element has one writer.
+__global__ void __launch_bounds__(kThreads)
+k_density_plane(PlanArgs P, int rb, const double2* __restrict__ T, int nbc,
+                const double* __restrict__ w, int ngroup, double* __restrict__ part, int add) {
+  extern __shared__ __align__(16) char lds_raw[];
+  double2* E = reinterpret_cast<double2*>(lds_raw);
+  const int trse = P.n2 + 1, trsr = P.n1 + 1;
+  double2* Rw = E + P.xr * trse;
+  const int j3 = blockIdx.x, g = blockIdx.y;
+  double* pp = part + ((size_t)g * P.n3 + j3) * P.n2 * P.n1;
+  if (g >= nbc && !add) {   // a group without bands in the first chunk starts from zero
+    for (int i = threadIdx.x; i < P.n2 * P.n1; i += blockDim.x) pp[i] = 0.0;
+    return;
+  }
+  bool fresh = !add;
+  for (int b = g; b < nbc; b += ngroup) {
+    const double2* tp = T + ((size_t)b * P.n3 + j3) * P.ncols;
+    __syncthreads();
+    for (int i = threadIdx.x; i < P.xr * trse; i += blockDim.x) E[i] = czero<double2>();
+    __syncthreads();
+    for (int c = threadIdx.x; c < P.ncols; c += blockDim.x)
+      E[P.col_e[c] * trse + P.col_m2[c]] = tp[c];
+    __syncthreads();
+    fft_lds<+1>(E, P.xr, trse, P.ax2);
+    const double wb = w[b];
+    for (int r0 = 0; r0 < P.n2; r0 += rb) {
+      const int nr = min(rb, P.n2 - r0);
+      for (int i = threadIdx.x; i < nr * trsr; i += blockDim.x) Rw[i] = czero<double2>();
+      __syncthreads();
+      for (int i = threadIdx.x; i < nr * P.xr; i += blockDim.x) {
+        const int r = i / P.xr, e = i - r * P.xr;
+        Rw[r * trsr + P.ext_m1[e]] = E[e * trse + r0 + r];
+      }
+      __syncthreads();
+      fft_lds<+1>(Rw, nr, trsr, P.ax1);
+      for (int i = threadIdx.x; i < nr * P.n1; i += blockDim.x) {
+        const int r = i / P.n1, j1 = i - r * P.n1;
+        const double2 v = Rw[r * trsr + j1];
+        double* d = pp + (size_t)(r0 + r) * P.n1 + j1;
+        *d = (fresh ? 0.0 : *d) + wb * (v.x * v.x + v.y * v.y);
+      }
+      __syncthreads();
+    }
+    fresh = false;
+  }
+}
+
 template <class C, class PL>
 __device__ __forceinline__ void col_fwd_body(const PL& P, int ct, const C* __restrict__ T,
                                              const real_t<C>* __restrict__ kin, const C* in,
@@ -434,6 +485,14 @@ hipError_t col_fwd_generic(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, co
 
 }  // namespace
 
+hipError_t launch_density_planes_gen(const BoxPlan& p, const FftLaunchCfg& cfg, int nbc,
+                                     const cplx* T, const double* w, int ngroup, double* part,
+                                     int add, hipStream_t s) {
+  hipLaunchKernelGGL(k_density_plane, dim3(p.n3, ngroup), dim3(kThreads), cfg.plane_lds, s,
+                     plan_args(p), cfg.plane_rows, T, nbc, w, ngroup, part, add);
+  return hipGetLastError();
+}
+
 hipError_t launch_fft_col_inv(const BoxPlan& p, const FftLaunchCfg& cfg, int nb, const cplx* psi,
                               int64_t ldpsi, cplx* T, hipStream_t s) {
   if (cfg.reg_col) return launch_fft_col_inv_reg(p, nb, psi, ldpsi, T, s);
@@ -513,12 +572,13 @@ hipError_t launch_fused_col_fwd(const FusedFft& f, bool fp32, const ItemDev* D, 
 
 // Dynamic LDS above the default limit must be opted into per kernel.
 hipError_t fft_set_lds_limits(size_t bytes) {
-  const void* fns[12] = {(const void*)k_col_inv<double2>, (const void*)k_plane<double2>,
+  const void* fns[13] = {(const void*)k_col_inv<double2>, (const void*)k_plane<double2>,
                          (const void*)k_col_fwd<double2>, (const void*)k_col_inv<float2>,
                          (const void*)k_plane<float2>, (const void*)k_col_fwd<float2>,
                          (const void*)kb_col_inv<double2>, (const void*)kb_plane<double2>,
                          (const void*)kb_col_fwd<double2>, (const void*)kb_col_inv<float2>,
-                         (const void*)kb_plane<float2>, (const void*)kb_col_fwd<float2>};
+                         (const void*)kb_plane<float2>, (const void*)kb_col_fwd<float2>,
+                         (const void*)k_density_plane};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;

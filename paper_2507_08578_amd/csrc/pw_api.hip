@@ -28,6 +28,7 @@ struct pw_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   size_t lds_limit = 0;
+  int cus = 256;              // compute units of the device
   bool timing = false;
   std::vector<EventPair> pending;
   std::vector<hipEvent_t> pool;
@@ -88,6 +89,10 @@ struct pw_ham {
   float2* cprj32 = nullptr;
   float2* work32 = nullptr;
   float2* blk32[2] = {nullptr, nullptr};
+  // electron density (allocated by the first pw_density call)
+  double omega = 0.0;        // cell volume (2 pi)^3 / |det B|
+  double* rho_part = nullptr;
+  int rho_groups = 0;
 };
 
 struct BatchItem {
@@ -795,6 +800,12 @@ pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->lds_limit = (size_t)lds;
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        cus > 0)
+      c->cus = cus;
+  }
   void* pin = nullptr;
   e = hipHostMalloc(&pin, 64 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -806,6 +817,7 @@ pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
   if (e == hipSuccess) e = fft_reg_set_lds_limits(c->lds_limit);
   if (e == hipSuccess) e = heev_set_lds_limit(c->lds_limit);
   if (e == hipSuccess) e = fft_ls_set_lds_limit(c->lds_limit);
+  if (e == hipSuccess) e = density_set_lds_limit(c->lds_limit);
   if (e != hipSuccess) {
     (void)hipHostFree(pin);
     delete c;
@@ -994,6 +1006,13 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
     TRY(dalloc(h, &h->kin, (size_t)npw));
     HIPCHK(ctx, launch_kinetic(npw, dm, d->recip, d->kpt, h->kin, s));
   }
+  {
+    const double* B = d->recip;
+    const double det = B[0] * (B[4] * B[8] - B[5] * B[7]) - B[1] * (B[3] * B[8] - B[5] * B[6]) +
+                       B[2] * (B[3] * B[7] - B[4] * B[6]);
+    const double two_pi = 6.283185307179586476925286766559;
+    h->omega = det != 0.0 ? two_pi * two_pi * two_pi / std::fabs(det) : 0.0;
+  }
   // V scaled by 1/N_box; maxima for the spectral bound
   const int64_t nbox = (int64_t)P.n1 * P.n2 * P.n3;
   TRY(dalloc(h, &h->vscaled, (size_t)nbox));
@@ -1128,6 +1147,57 @@ pw_status pw_apply_h(pw_ham* h, pw_prec prec, int64_t nb, const void* psi, int64
                        static_cast<float2*>(hpsi), ldh, 1.0, 0.0, 0.0, nullptr, 0);
   return ham_apply(h, nb, static_cast<const cplx*>(psi), ldpsi, static_cast<cplx*>(hpsi), ldh, 1.0,
                    0.0, 0.0, nullptr, 0);
+}
+
+pw_status pw_density(pw_ham* h, int64_t nb, const void* psi, int64_t ldpsi, const double* w,
+                     double* rho, int32_t accumulate) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  pw_ctx* c = h->ctx;
+  if (nb < 0 || nb > h->nb_max)
+    return fail(c, PW_ERR_INVALID_ARG,
+                "nb = " + std::to_string(nb) + " outside [0, nb_max = " + std::to_string(h->nb_max) +
+                    "]");
+  if (!rho) return fail(c, PW_ERR_INVALID_ARG, "rho is NULL");
+  if (accumulate != 0 && accumulate != 1)
+    return fail(c, PW_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+  pw_status st;
+  if (nb > 0) {
+    if ((st = check_block(h, psi, ldpsi, "psi")) != PW_OK) return st;
+    if (!w) return fail(c, PW_ERR_INVALID_ARG, "w is NULL");
+  }
+  if (!(h->omega > 0.0) || !std::isfinite(h->omega))
+    return fail(c, PW_ERR_INVALID_ARG, "the reciprocal lattice is singular");
+  HIPCHK(c, hipSetDevice(c->device));
+  const BoxPlan& P = h->plan;
+  const int64_t nbox = (int64_t)P.n1 * P.n2 * P.n3;
+  const bool reg = density_reg_supported(P, c->lds_limit);
+  if (!h->rho_part) {
+    // about four workgroups per compute unit over the z-planes (and row
+    // parts), at least one band per group and chunk
+    const int64_t per = (int64_t)P.n3 * (reg ? density_row_parts(P) : 1);
+    const int64_t want = (4 * (int64_t)c->cus + per - 1) / per;
+    const int groups = (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, h->chunk_alloc}));
+    if ((st = dalloc(h, &h->rho_part, (size_t)groups * nbox)) != PW_OK) return st;
+    h->rho_groups = groups;
+  }
+  hipStream_t s = c->stream;
+  const cplx* in = static_cast<const cplx*>(psi);
+  for (int64_t c0 = 0; c0 < nb; c0 += h->chunk_alloc) {
+    const int nc = (int)std::min<int64_t>(h->chunk_alloc, nb - c0);
+    {
+      StageScope sc(c, PW_STAGE_FFT_COL_INV);
+      HIPCHK(c, launch_fft_col_inv(P, h->cfg, nc, in + c0 * ldpsi, ldpsi, h->T, s));
+    }
+    StageScope sc(c, PW_STAGE_DENSITY);
+    HIPCHK(c, reg ? launch_density_planes_reg(P, nc, h->T, w + c0, h->rho_groups, h->rho_part,
+                                              c0 > 0, s)
+                  : launch_density_planes_gen(P, h->cfg, nc, h->T, w + c0, h->rho_groups,
+                                              h->rho_part, c0 > 0, s));
+  }
+  StageScope sc(c, PW_STAGE_MISC);
+  HIPCHK(c, launch_density_reduce(nbox, nb > 0 ? h->rho_groups : 0, h->rho_part, 1.0 / h->omega,
+                                  rho, accumulate, s));
+  return PW_OK;
 }
 
 pw_status pw_cheb_filter(pw_ham* h, pw_prec prec, int32_t degree, double a, double b, double a0,

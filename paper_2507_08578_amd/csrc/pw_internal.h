@@ -225,6 +225,18 @@ bool fft_plane_ls_supported(const BoxPlan& p, size_t lds_limit);
 hipError_t launch_fft_plane_ls32(const BoxPlan& p, int nb, const float* vscaled, float2* T,
                                  hipStream_t s);
 hipError_t fft_ls_set_lds_limit(size_t bytes);
+
+// Electron density (density.hip; generic form in fft_kernels.hip)
+hipError_t launch_density_planes_reg(const BoxPlan& p, int nbc, const cplx* T, const double* w,
+                                     int ngroup, double* part, int add, hipStream_t s);
+hipError_t launch_density_planes_gen(const BoxPlan& p, const FftLaunchCfg& cfg, int nbc,
+                                     const cplx* T, const double* w, int ngroup, double* part,
+                                     int add, hipStream_t s);
+hipError_t launch_density_reduce(int64_t nbox, int ngroup, const double* part, double scale,
+                                 double* rho, int accumulate, hipStream_t s);
+bool density_reg_supported(const BoxPlan& p, size_t lds_limit);
+int density_row_parts(const BoxPlan& p);   // workgroups per (plane, band group), register kernel
+hipError_t density_set_lds_limit(size_t bytes);
 hipError_t launch_fft_col_inv_reg(const BoxPlan& p, int nb, const cplx* psi, int64_t ldpsi, cplx* T,
                                   hipStream_t s);
 hipError_t launch_fft_plane_reg(const BoxPlan& p, int variant, int nb, const double* vscaled,
