@@ -589,7 +589,7 @@ def main():
         log("electron density")
         out["density"] = density_leg(ctx, ham, w, X0, args.steps, args.warmup)
         if not args.no_cpu_baseline:
-            nbd = {"C1": 512, "C3": 32, "C5": 16}[args.config]
+            nbd = {"C1": 2048, "C3": 256, "C5": 64}[args.config]
             out["density"]["cpu_baseline"] = cpu_density_baseline(w, nbd)
     if not args.no_cpu_baseline:
         nbs = args.cpu_bands or {"C1": 2048, "C3": 64, "C5": 160}[args.config]
