@@ -71,8 +71,11 @@ COUNTER_FILES = {
     ("C5", "fp32", "fft_plane", "k_plane_reg"): (
         "profiles/c5_plane_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/fft_reg.hip", "paper_2507_08578_amd/csrc/fft_common.h")),
-    ("C5", "fp32", "proj", "gemm"): (
+    ("C5", "fp32", "proj", "k_gemm_cn32"): (
         "profiles/c5_gemm_fp32_counters.md",
+        ("paper_2507_08578_amd/csrc/gemm32_kernels.hip",)),
+    ("C5", "fp32", "nonlocal", "k_gemm_nn32_tall"): (
+        "profiles/c5_gemm_nn32_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/gemm32_kernels.hip",)),
     ("C5", "fp32", "fft_plane", "k_plane_ls"): (
         "profiles/c5_plane_ls_fp32_counters.md",
@@ -149,19 +152,31 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
     bands_per_launch = nb * steps * applies / launches
     if dom in ("proj", "nonlocal"):
         fl = 8.0 * w.npw * w.nproj * nb
-        peak = PEAK["fp64_mfma" if prec == "fp64" else ("bf16_mfma" if prec == "bf16" else "fp32_mfma")]
+        # the matrix cores' own dtype: FP64; FP32 for P C; bf16 for P^H psi in the
+        # FP32 path (FP32 operands as three bf16 terms, six MFMA products per real
+        # product) and for both products in the bf16 path
+        on_bf16 = prec == "bf16" or (prec == "fp32" and dom == "proj")
+        peak = PEAK["fp64_mfma" if prec == "fp64" else ("bf16_mfma" if on_bf16 else "fp32_mfma")]
         ach = fl / (avg_ms * 1e-3) / 1e12
         mode = "" if prec == "fp64" else ("<F32>" if prec == "fp32" else "<BF16>")
         sx = "" if prec == "fp64" else "32"
+        extra = {}
         if dom == "proj":
+            key = f"k_gemm_cn{sx}"
             kname = f"k_gemm_cn{sx}{mode} + k_splitk_reduce{sx} (P^H psi, split-K, KB scale)"
+            if prec == "fp32":
+                kname += "; FP32 operands split into three bf16 terms, bf16 MFMA"
+                extra = {"executed_mfma_flop_per_launch": 6.0 * fl,
+                         "executed_TFLOPs": 6.0 * ach, "executed_frac": 6.0 * ach / peak}
         else:
             tall = ham.get_tuning()["nn_tile" if prec == "fp64" else "nn_tile32"] == 1
-            kname = f"k_gemm_nn{sx}{'_tall' if tall else ''}{mode} (H psi += P C)"
-        return {"kernel": kname, "bound": "mfma", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak,
-                "traffic": measured_traffic(config, prec, dom, "gemm", 1), "avg_launch_ms": avg_ms,
-                "per_launch": f"8*npw*nproj*nb = {fl:.4g} flop"}
+            key = f"k_gemm_nn{sx}{'_tall' if tall else ''}"
+            kname = f"{key}{mode} (H psi += P C)"
+        return dict({"kernel": kname, "bound": "mfma", "achieved": ach, "peak": peak,
+                     "unit": "TFLOP/s", "frac": ach / peak,
+                     "traffic": measured_traffic(config, prec, dom, key, 1),
+                     "avg_launch_ms": avg_ms,
+                     "per_launch": f"8*npw*nproj*nb = {fl:.4g} flop"}, **extra)
     if dom == "fft_plane":
         per_band = N3 * (2 * (xr * fft_flops(N2) + N2 * fft_flops(N1)) + 2.0 * N1 * N2)
         fl = per_band * bands_per_launch

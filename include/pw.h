@@ -22,8 +22,11 @@
  *    complex64 for PW_FP32 / PW_BF16; every other entry point takes
  *    complex128 blocks whatever its internal precision.
  *  - Precision of a call: PW_FP64 everything in FP64.  PW_FP32: FFT route in
- *    FP32, projector products on FP32 MFMA.  PW_BF16: FFT route in FP32,
- *    projector products with bfloat16 operands.  Both accumulate in FP32.
+ *    FP32, projector products with FP32 operands: P C on FP32 MFMA, P^H psi
+ *    on the bf16 MFMA with every operand split exactly into three bfloat16
+ *    terms (six term products per real product; the accuracy of FP32
+ *    products).  PW_BF16: FFT route in FP32, projector products with
+ *    bfloat16 operands.  All accumulate in FP32.
  *  - Pointers named *_dev are device memory on the context's device, owned by
  *    the caller; the library never frees them.  Pointers named *_host are host
  *    memory read during the call only.
@@ -230,7 +233,7 @@ typedef struct {
   int32_t plane_variant32;/* FP32 plane kernel: 0, 1 as above (1 also for 120, 128, 144, 160);
                              2 transforms exchanged through LDS (N1 = N2 = 144)            */
   int32_t chunk;          /* bands per FFT launch, [1, the handle's buffer]                  */
-  int32_t gemm_blocks;    /* split-K target block count of P^H psi, [1, 2048]                */
+  int32_t gemm_blocks;    /* split-K target block count of P^H psi, [1, 4096] (FP64: <= 2048) */
   int32_t nn_tile;        /* tall FP64 products P C, Y Q, Y U^-1: 0 64x64, 1 128x64 tiles    */
   int32_t nn_tile32;      /* the same choice for the FP32 / BF16 product P C                 */
   double ms;              /* pw_ham_autotune: median time of one H*psi of nb bands           */

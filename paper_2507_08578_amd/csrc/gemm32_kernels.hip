@@ -3,7 +3,12 @@
 // non-local expansion H psi += P c of section 5.2, Eq. ham-nl, applied to
 // complex64 blocks).
 //
-//   MODE_F32 : v_mfma_f32_16x16x4f32, operands FP32.
+//   MODE_F32 : P C (gemm_nn32): v_mfma_f32_16x16x4f32, operands FP32.
+//              P^H psi (gemm_cn32): every FP32 operand split exactly into three
+//              bfloat16 terms when its tile is staged in LDS, products on
+//              v_mfma_f32_16x16x32_bf16 (six term products per real product,
+//              FP32 accumulation: the accuracy of FP32 products at 6/16 of
+//              the FP32 MFMA time).
 //   MODE_BF16: v_mfma_f32_16x16x32_bf16, operands rounded to bfloat16
 //              (round to nearest even) when the MFMA operands are formed from
 //              the FP32 tiles staged in LDS.
@@ -23,7 +28,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 namespace {
 
 constexpr int kBM = 64, kBN = 64, kThreads = 256;
-constexpr int kTargetBlocks = 2048;
+constexpr int kTargetBlocks = 4096;
 enum { MODE_F32 = 0, MODE_BF16 = 1 };
 
 template <int MODE>
@@ -224,12 +229,159 @@ k_gemm_nn32_tall(int64_t M, int64_t N, int64_t K, float alpha, const float2* __r
   gemm_nn32_tile<MODE, 4, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
 }
 
+// ---- P^H psi with FP32 operands on the bf16 matrix cores.
+// x = h + m + l, h = bf16(x), m = bf16(x - h), l = bf16(x - h - m): both
+// differences are exact in FP32, and the three terms hold x's 24 significant
+// bits (bf16 has FP32's exponent range).  x y is formed from the six term
+// products of weight >= 2^-16 (h h, h m, m h, h l, l h, m m); the dropped
+// ones are below 2^-24 |x y|.
+constexpr int kB3K = 32;                    // complex K per LDS stage
+constexpr int kB3Pitch = kB3K + 8;          // bf16 per LDS row (80 B: rows spread over the banks)
+constexpr int kB3Plane = 64 * kB3Pitch;     // one (term, part) plane of a 64-row operand tile
+
+__device__ __forceinline__ f4 mfma6(const bf8 (&x)[3], const bf8 (&y)[3], f4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[2], y[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[1], y[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[1], acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[0], acc, 0, 0, 0);
+}
+
+// Split two consecutive-K complex values of one operand row and store the
+// six bf16 pairs (term t, part re/im) at row `row`, K offset kq (even).
+__device__ __forceinline__ void b3_store2(__bf16* L, int row, int kq, float4 v) {
+  const float x[2][2] = {{v.x, v.z}, {v.y, v.w}};   // [re, im][k, k + 1]
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+    bf2 h, m, l;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const __bf16 xh = (__bf16)x[c][e];
+      const float r = x[c][e] - (float)xh;
+      const __bf16 xm = (__bf16)r;
+      h[e] = xh;
+      m[e] = xm;
+      l[e] = (__bf16)(r - (float)xm);
+    }
+    *reinterpret_cast<bf2*>(L + (0 * 2 + c) * kB3Plane + row * kB3Pitch + kq) = h;
+    *reinterpret_cast<bf2*>(L + (1 * 2 + c) * kB3Plane + row * kB3Pitch + kq) = m;
+    *reinterpret_cast<bf2*>(L + (2 * 2 + c) * kB3Plane + row * kB3Pitch + kq) = l;
+  }
+}
+
+// Fragment of 16 rows (from row r0) for the 16x16x32 bf16 layout: lane
+// (lr, lk) takes K values 8 lk .. 8 lk + 7 of row r0 + lr, for each term.
+__device__ __forceinline__ void b3_frag(const __bf16* L, int c, int r0, int lr, int lk, bf8 (&f)[3]) {
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+    f[t] = *reinterpret_cast<const bf8*>(L + (t * 2 + c) * kB3Plane + (r0 + lr) * kB3Pitch + 8 * lk);
+}
+
+// Partial (split z over K) A^H B as gemm_cn32_body, FP32 operands in three
+// bf16 terms.  Each operand tile (64 rows x 32 K) is staged as 1024 pairs of
+// consecutive-K values: pair p = tid + 256 q (q < 4) is row p / 16, K 2 (p % 16),
+// so the 16-byte loads of a wavefront cover four whole 256-byte row runs.
+__device__ __forceinline__ void gemm_cn32_b3_body(int64_t M, int64_t N, int64_t K, int64_t ksplit,
+                                                  const float2* __restrict__ A, int64_t lda,
+                                                  const float2* __restrict__ B, int64_t ldb,
+                                                  float2* __restrict__ out, int bx, int by, int bz) {
+  __shared__ __align__(16) __bf16 LA[6 * kB3Plane];
+  __shared__ __align__(16) __bf16 LB[6 * kB3Plane];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
+  const int64_t kb = (int64_t)bz * ksplit;
+  const int64_t ke = min(K, kb + ksplit);
+  const int kq = (tid & 15) * 2;
+  // acc[0] = Re(conj(a) b) = ar br + ai bi, acc[1] = ar bi, acc[2] = ai br
+  f4 acc[3][2][2];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) f4zero(acc[q][a][b]);
+  float4 ra[4], rb[4];
+  // (k, k + 1) of one row (columns of odd length are only 8-byte aligned)
+  auto pair = [&](const float2* __restrict__ X, int64_t ld, int64_t row, int64_t rows,
+                  int64_t gk) -> float4 {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float2* src = X + gk + row * ld;
+    if (row < rows && gk < ke) {
+      const float2 a = src[0];
+      v.x = a.x;
+      v.y = a.y;
+    }
+    if (row < rows && gk + 1 < ke) {
+      const float2 b = src[1];
+      v.z = b.x;
+      v.w = b.y;
+    }
+    return v;
+  };
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = (tid >> 4) + 16 * q;
+      ra[q] = pair(A, lda, i0 + r, M, k0 + kq);
+      rb[q] = pair(B, ldb, j0 + r, N, k0 + kq);
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kB3K) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      b3_store2(LA, (tid >> 4) + 16 * q, kq, ra[q]);
+      b3_store2(LB, (tid >> 4) + 16 * q, kq, rb[q]);
+    }
+    __syncthreads();
+    if (k0 + kB3K < ke) fetch(k0 + kB3K);
+    bf8 a[2][2][3], b[2][2][3];   // [tile][re, im][term]
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        b3_frag(LA, c, wi * 32 + t * 16, lr, lk, a[t][c]);
+        b3_frag(LB, c, wj * 32 + t * 16, lr, lk, b[t][c]);
+      }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        acc[0][ti][tj] = mfma6(a[ti][0], b[tj][0], acc[0][ti][tj]);
+        acc[0][ti][tj] = mfma6(a[ti][1], b[tj][1], acc[0][ti][tj]);
+        acc[1][ti][tj] = mfma6(a[ti][0], b[tj][1], acc[1][ti][tj]);
+        acc[2][ti][tj] = mfma6(a[ti][1], b[tj][0], acc[2][ti][tj]);
+      }
+    __syncthreads();
+  }
+  float2* o = out + (int64_t)bz * M * N;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wi * 32 + ti * 16 + 4 * lk + r;
+        const int64_t j = j0 + wj * 32 + tj * 16 + lr;
+        if (i < M && j < N)
+          o[i + j * M] = make_float2(acc[0][ti][tj][r], acc[1][ti][tj][r] - acc[2][ti][tj][r]);
+      }
+}
+
 // Partial (split z over K) A^H B; A k x m (lda), B k x n (ldb); out ld = M.
 template <int MODE>
 __device__ __forceinline__ void gemm_cn32_body(int64_t M, int64_t N, int64_t K, int64_t ksplit,
                                                const float2* __restrict__ A, int64_t lda,
                                                const float2* __restrict__ B, int64_t ldb,
                                                float2* __restrict__ out, int bx, int by, int bz) {
+  if constexpr (MODE == MODE_F32) {
+    gemm_cn32_b3_body(M, N, K, ksplit, A, lda, B, ldb, out, bx, by, bz);
+    return;
+  }
   constexpr int Kc = KC<MODE>::value;
   constexpr int PA = kBM + 1, PB = kBN + 1;
   __shared__ float2 As[Kc * PA];
@@ -358,7 +510,7 @@ struct SplitPlan {
 
 template <int MODE>
 __host__ __device__ inline SplitPlan split_plan32(int64_t m, int64_t n, int64_t k, int target) {
-  constexpr int Kc = KC<MODE>::value;
+  constexpr int Kc = 32;   // complex K per LDS stage of both P^H psi kernels
   SplitPlan p;
   p.tiles_m = (m + kBM - 1) / kBM;
   p.tiles_n = (n + kBN - 1) / kBN;

@@ -379,6 +379,14 @@ struct SplitPlan {
   int64_t tiles_m, tiles_n, nsplit, ksplit;
 };
 
+// The handle's split-K target as the FP64 products use it: values outside
+// [1, kTargetBlocks] (the FP32 products accept more) mean kTargetBlocks, as in
+// launch_gemm_cn, so fused and per-item launches split alike and stay within
+// the workspace sized for kTargetBlocks.
+__host__ __device__ inline int fp64_target(int target) {
+  return (target < 1 || target > kTargetBlocks) ? kTargetBlocks : target;
+}
+
 __host__ __device__ inline SplitPlan split_plan(int64_t m, int64_t n, int64_t k, int target) {
   SplitPlan p;
   p.tiles_m = (m + kBM - 1) / kBM;
@@ -424,7 +432,7 @@ __device__ __forceinline__ CnArgs fused_cn_args(const ItemDev& d, int op, int se
     a.C = d.cprj;
     a.ldc = d.nproj;
     a.rowscale = d.ekb;
-    a.target = d.gemm_target;
+    a.target = fp64_target(d.gemm_target);
   } else {
     a.M = d.nb;
     a.N = d.nb;
@@ -567,7 +575,7 @@ hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const c
 }
 
 int fused_cn_nsplit(int op, int64_t npw, int64_t nb, int64_t nproj, int target) {
-  const SplitPlan p = op == GOP_PROJ ? split_plan(nproj, nb, npw, target)
+  const SplitPlan p = op == GOP_PROJ ? split_plan(nproj, nb, npw, fp64_target(target))
                                      : split_plan(nb, nb, npw, kTargetBlocks);
   return (int)p.nsplit;
 }

@@ -57,7 +57,8 @@ struct pw_ham {
   int64_t npw = 0, nproj = 0, nb_max = 0;
   int64_t chunk = 0;         // bands per FFT launch (tunable, <= chunk_alloc)
   int64_t chunk_alloc = 0;   // bands the FFT work buffer holds
-  int gemm_target = 2048;    // split-K target block count of the projector product (tunable)
+  int gemm_target = 4096;    // split-K target block count of the projector product (tunable;
+                             // the FP64 product caps it at 2048)
   int nn_tile = 0;           // workgroup tile of the tall FP64 products P C, Y Q, Y U^-1 (tunable)
   int nn_tile32 = 0;         // the same for the FP32 / BF16 product P C (tunable)
   bool reg_col_ok = false, reg_plane_ok = false, narrow_ok = false, narrow32_ok = false;
@@ -1432,8 +1433,8 @@ pw_status pw_ham_set_tuning(pw_ham* h, const pw_tuning* t) {
   if (t->chunk < 1 || t->chunk > h->chunk_alloc)
     return fail(h->ctx, PW_ERR_INVALID_ARG,
                 "chunk outside [1, " + std::to_string(h->chunk_alloc) + "]");
-  if (t->gemm_blocks < 1 || t->gemm_blocks > 2048)
-    return fail(h->ctx, PW_ERR_INVALID_ARG, "gemm_blocks outside [1, 2048]");
+  if (t->gemm_blocks < 1 || t->gemm_blocks > 4096)
+    return fail(h->ctx, PW_ERR_INVALID_ARG, "gemm_blocks outside [1, 4096]");
   if ((t->nn_tile != 0 && t->nn_tile != 1) || (t->nn_tile32 != 0 && t->nn_tile32 != 1))
     return fail(h->ctx, PW_ERR_INVALID_ARG, "nn_tile and nn_tile32 are 0 or 1");
   h->cfg.reg_col = t->reg_col != 0;
@@ -1533,7 +1534,7 @@ pw_status pw_ham_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, pw_
   }
   // 3) split-K parallelism of the projector product
   if (h->nproj > 0)
-    for (int g : {2048, 1024, 512, 256, 64, 1}) {
+    for (int g : {4096, 2048, 1024, 512, 256, 64, 1}) {
       if (g == cur.gemm_blocks) continue;
       pw_tuning t = cur;
       t.gemm_blocks = g;

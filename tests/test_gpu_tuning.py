@@ -19,7 +19,7 @@ def all_tunings(ham, nb):
     out = []
     for rc, rp, pv, pv32 in itertools.product((0, 1), (0, 1), (0, 1), (0, 1, 2)):
         for ch in sorted({base["chunk"], max(1, base["chunk"] // 2), 1}):
-            for gb in (2048, 256):
+            for gb in (4096, 2048, 256):
                 out.append(dict(reg_col=rc, reg_plane=rp, plane_variant=pv, plane_variant32=pv32,
                                 chunk=ch, gemm_blocks=gb, nn_tile=0, nn_tile32=0))
     out.append(dict(base, nn_tile=1))
@@ -63,7 +63,7 @@ def test_set_tuning_rejects(pw, ctx):
     with pytest.raises(pw.PWError) as e:
         ham.set_tuning({"reg_plane": 1})
     assert e.value.status == 2
-    for bad in ({"chunk": 0}, {"chunk": 10 ** 6}, {"gemm_blocks": 4096}, {"reg_col": 2},
+    for bad in ({"chunk": 0}, {"chunk": 10 ** 6}, {"gemm_blocks": 4097}, {"reg_col": 2},
                 {"nn_tile": 2}, {"nn_tile32": -1}):
         with pytest.raises(pw.PWError) as e:
             ham.set_tuning(bad)
