@@ -74,7 +74,7 @@ COUNTER_FILES = {
     ("C5", "fp32", "proj", "k_gemm_cn32"): (
         "profiles/c5_gemm_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/gemm32_kernels.hip",)),
-    ("C5", "fp32", "nonlocal", "k_gemm_nn32_tall"): (
+    ("C5", "fp32", "nonlocal", "k_gemm_nn32_b3"): (
         "profiles/c5_gemm_nn32_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/gemm32_kernels.hip",)),
     ("C5", "fp32", "fft_plane", "k_plane_ls"): (
@@ -152,10 +152,10 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
     bands_per_launch = nb * steps * applies / launches
     if dom in ("proj", "nonlocal"):
         fl = 8.0 * w.npw * w.nproj * nb
-        # the matrix cores' own dtype: FP64; FP32 for P C; bf16 for P^H psi in the
-        # FP32 path (FP32 operands as three bf16 terms, six MFMA products per real
-        # product) and for both products in the bf16 path
-        on_bf16 = prec == "bf16" or (prec == "fp32" and dom == "proj")
+        # the matrix cores' own dtype: FP64, or bf16 (the FP32 path's products take
+        # their FP32 operands as three bf16 terms, six MFMA products per real
+        # product; the bf16 path rounds its operands to bf16)
+        on_bf16 = prec in ("bf16", "fp32")
         peak = PEAK["fp64_mfma" if prec == "fp64" else ("bf16_mfma" if on_bf16 else "fp32_mfma")]
         ach = fl / (avg_ms * 1e-3) / 1e12
         mode = "" if prec == "fp64" else ("<F32>" if prec == "fp32" else "<BF16>")
@@ -168,6 +168,12 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
                 kname += "; FP32 operands split into three bf16 terms, bf16 MFMA"
                 extra = {"executed_mfma_flop_per_launch": 6.0 * fl,
                          "executed_TFLOPs": 6.0 * ach, "executed_frac": 6.0 * ach / peak}
+        elif prec == "fp32":
+            key = "k_gemm_nn32_b3"
+            kname = ("k_gemm_nn32_b3 (H psi += P C; P as a stored three-term bf16 copy, "
+                     "C split per tile, bf16 MFMA)")
+            extra = {"executed_mfma_flop_per_launch": 6.0 * fl,
+                     "executed_TFLOPs": 6.0 * ach, "executed_frac": 6.0 * ach / peak}
         else:
             tall = ham.get_tuning()["nn_tile" if prec == "fp64" else "nn_tile32"] == 1
             key = f"k_gemm_nn{sx}{'_tall' if tall else ''}"
@@ -183,7 +189,13 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
         peak = PEAK["fp64_valu" if prec == "fp64" else "fp32_valu"]
         ach = fl / (avg_ms * 1e-3) / 1e12
         kname = plane_kernel(ham, prec)
-        return {"kernel": f"{kname} (N2/N1 transforms x V per z-plane)", "bound": "alu",
+        extra = {}
+        if prec != "fp64":
+            # 157.3 counts packed FP32 (two FMAs per lane and instruction); the
+            # kernels are built without packed-FP32 code, so 78.6 is what they can issue
+            extra = {"peak_unpacked_fp32": PEAK["fp64_valu"],
+                     "frac_unpacked_fp32": ach / PEAK["fp64_valu"]}
+        return {**extra, "kernel": f"{kname} (N2/N1 transforms x V per z-plane)", "bound": "alu",
                 "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                 "traffic": measured_traffic(config, prec, dom, kname, bands_per_launch),
                 "avg_launch_ms": avg_ms,

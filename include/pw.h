@@ -22,11 +22,11 @@
  *    complex64 for PW_FP32 / PW_BF16; every other entry point takes
  *    complex128 blocks whatever its internal precision.
  *  - Precision of a call: PW_FP64 everything in FP64.  PW_FP32: FFT route in
- *    FP32, projector products with FP32 operands: P C on FP32 MFMA, P^H psi
- *    on the bf16 MFMA with every operand split exactly into three bfloat16
- *    terms (six term products per real product; the accuracy of FP32
- *    products).  PW_BF16: FFT route in FP32, projector products with
- *    bfloat16 operands.  All accumulate in FP32.
+ *    FP32, projector products with FP32 operands on the bf16 MFMA, every
+ *    operand split exactly into three bfloat16 terms (six term products per
+ *    real product; the accuracy of FP32 products).  PW_BF16: FFT route in
+ *    FP32, projector products with bfloat16 operands.  All accumulate in
+ *    FP32.
  *  - Pointers named *_dev are device memory on the context's device, owned by
  *    the caller; the library never frees them.  Pointers named *_host are host
  *    memory read during the call only.
@@ -110,7 +110,9 @@ const char* pw_last_error(const pw_ctx* ctx);
  *            workspaces are sized for it at creation so hot calls allocate
  *            nothing.
  *   low_prec 0: FP64 only.  1: also build the FP32 copies (projectors,
- *            V/N_box, kinetic energies, twiddles) and complex64 workspaces
+ *            V/N_box, kinetic energies, twiddles), the projectors' three-term
+ *            bf16 split (projector index contiguous; 1.5x the FP32 copy's
+ *            size; read by the FP32 P C) and complex64 workspaces
  *            that PW_FP32 / PW_BF16 calls need (cubic boxes of the lengths
  *            with register-resident FFT kernels; else UNSUPPORTED).
  */

@@ -451,6 +451,160 @@ __device__ __forceinline__ void gemm_cn32_body(int64_t M, int64_t N, int64_t K, 
       }
 }
 
+// ---- P C with FP32 operands on the bf16 matrix cores.  P is a constant of
+// the handle, so its three-term split is formed once (k_split3_t), transposed
+// so that the contraction index (projector) is contiguous:
+//   P3[(t 2 + c) rows kp + i kp + k]  (term t < 3, part c = re / im, plane
+//   wave i, projector k < kp = nproj rounded up to 8; zero for k >= nproj).
+// C is split per stage as the P^H psi kernel splits its operands.
+
+// out = alpha P C + beta out on a 64 x 64 tile (by: plane waves, bx: bands).
+// Thread tid stages P3 row tid / 4, projectors 8 (tid % 4) .. + 7 of each of
+// the six planes (16-byte loads), and four consecutive-projector pairs of C.
+__device__ __forceinline__ void gemm_nn32_b3_body(int64_t M, int64_t N, int64_t K, float alpha,
+                                                  const __bf16* __restrict__ P3, int kp,
+                                                  const float2* __restrict__ B, int64_t ldb,
+                                                  float beta, float2* __restrict__ C, int64_t ldc,
+                                                  int bx, int by) {
+  __shared__ __align__(16) __bf16 LA[6 * kB3Plane];
+  __shared__ __align__(16) __bf16 LB[6 * kB3Plane];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
+  const int arow = tid >> 2, acol = (tid & 3) * 8, kq = (tid & 15) * 2;
+  const int64_t gi = i0 + arow;
+  // acc[0] = ar br, acc[1] = ai bi, acc[2] = ar bi + ai br
+  f4 acc[3][2][2];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) f4zero(acc[q][a][b]);
+  bf8 pa[6];
+  float4 rb[4];
+  auto fetch = [&](int64_t k0) {
+    const int64_t kk = k0 + acol;   // a multiple of 8, as kp: the whole 8-run is inside or outside
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      bf8 z;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
+      pa[q] = (gi < M && kk < kp)
+                  ? *reinterpret_cast<const bf8*>(P3 + (int64_t)q * M * kp + gi * kp + kk)
+                  : z;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t col = j0 + (tid >> 4) + 16 * q, gk = k0 + kq;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (col < N && gk < K) {
+        const float2 a = B[gk + col * ldb];
+        v.x = a.x;
+        v.y = a.y;
+      }
+      if (col < N && gk + 1 < K) {
+        const float2 b = B[gk + 1 + col * ldb];
+        v.z = b.x;
+        v.w = b.y;
+      }
+      rb[q] = v;
+    }
+  };
+  fetch(0);
+  for (int64_t k0 = 0; k0 < K; k0 += kB3K) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      *reinterpret_cast<bf8*>(LA + q * kB3Plane + arow * kB3Pitch + acol) = pa[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b3_store2(LB, (tid >> 4) + 16 * q, kq, rb[q]);
+    __syncthreads();
+    if (k0 + kB3K < K) fetch(k0 + kB3K);
+    bf8 a[2][2][3], b[2][2][3];   // [tile][re, im][term]
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        b3_frag(LA, c, wi * 32 + t * 16, lr, lk, a[t][c]);
+        b3_frag(LB, c, wj * 32 + t * 16, lr, lk, b[t][c]);
+      }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        acc[0][ti][tj] = mfma6(a[ti][0], b[tj][0], acc[0][ti][tj]);
+        acc[1][ti][tj] = mfma6(a[ti][1], b[tj][1], acc[1][ti][tj]);
+        acc[2][ti][tj] = mfma6(a[ti][0], b[tj][1], acc[2][ti][tj]);
+        acc[2][ti][tj] = mfma6(a[ti][1], b[tj][0], acc[2][ti][tj]);
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wi * 32 + ti * 16 + 4 * lk + r;
+        const int64_t j = j0 + wj * 32 + tj * 16 + lr;
+        if (i < M && j < N) {
+          float2 v = make_float2(alpha * (acc[0][ti][tj][r] - acc[1][ti][tj][r]),
+                                 alpha * acc[2][ti][tj][r]);
+          if (beta != 0.f) {
+            const float2 c = C[i + j * ldc];
+            v.x += beta * c.x;
+            v.y += beta * c.y;
+          }
+          C[i + j * ldc] = v;
+        }
+      }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_gemm_nn32_b3(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __restrict__ P3, int kp,
+               const float2* __restrict__ B, int64_t ldb, float beta, float2* __restrict__ C,
+               int64_t ldc, int tiles_m, int tiles_n) {
+  int bx, by;
+  if (!xcd_panel_tile(blockIdx.x, tiles_m, tiles_n, &bx, &by)) return;
+  gemm_nn32_b3_body(M, N, K, alpha, P3, kp, B, ldb, beta, C, ldc, bx, by);
+}
+
+// P3 from P (rows x nk, ld ldp) through 64 x 64 LDS tiles: reads run along
+// the plane waves, writes along the projectors.
+__global__ void __launch_bounds__(256)
+k_split3_t(int64_t rows, int nk, int kp, const float2* __restrict__ P, int64_t ldp,
+           __bf16* __restrict__ P3) {
+  __shared__ float2 t[64][65];
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int k0 = blockIdx.y * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int kk = e >> 6, ii = e & 63;
+    const int64_t i = i0 + ii;
+    const int k = k0 + kk;
+    t[kk][ii] = (i < rows && k < nk) ? P[i + (int64_t)k * ldp] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int ii = e >> 6, kk = e & 63;
+    const int64_t i = i0 + ii;
+    const int k = k0 + kk;
+    if (i < rows && k < kp) {
+      const float2 v = t[kk][ii];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const float x = c == 0 ? v.x : v.y;
+        const __bf16 h = (__bf16)x;
+        const float r = x - (float)h;
+        const __bf16 m = (__bf16)r;
+        P3[(int64_t)(0 * 2 + c) * rows * kp + i * kp + k] = h;
+        P3[(int64_t)(1 * 2 + c) * rows * kp + i * kp + k] = m;
+        P3[(int64_t)(2 * 2 + c) * rows * kp + i * kp + k] = (__bf16)(r - (float)m);
+      }
+    }
+  }
+}
+
 // Split-K products: all tiles of one K split on one XCD in a row; they stream
 // the same K range of both operands together, so each K stage is fetched
 // once per XCD.  Grid kXcds * tiles_m * tiles_n * ceil(nsplit / kXcds).
@@ -558,8 +712,12 @@ __global__ void __launch_bounds__(kThreads)
 kb_gemm_nn32(const ItemDev* __restrict__ D, int sel_c) {
   const ItemDev& d = D[blockIdx.z];
   if (d.nproj <= 0 || (int64_t)blockIdx.y * kBM >= d.npw || (int64_t)blockIdx.x * kBN >= d.nb) return;
-  gemm_nn32_body<MODE>(d.npw, d.nb, d.nproj, 1.f, d.proj32, d.npw, d.cprj32, d.nproj, 1.f,
-                       item_blk32(d, sel_c), d.npw, blockIdx.x, blockIdx.y);
+  if constexpr (MODE == MODE_F32)
+    gemm_nn32_b3_body(d.npw, d.nb, d.nproj, 1.f, reinterpret_cast<const __bf16*>(d.proj3), d.kp3,
+                      d.cprj32, d.nproj, 1.f, item_blk32(d, sel_c), d.npw, blockIdx.x, blockIdx.y);
+  else
+    gemm_nn32_body<MODE>(d.npw, d.nb, d.nproj, 1.f, d.proj32, d.npw, d.cprj32, d.nproj, 1.f,
+                         item_blk32(d, sel_c), d.npw, blockIdx.x, blockIdx.y);
 }
 
 }  // namespace
@@ -595,9 +753,17 @@ hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double al
 
 hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
-                            int64_t ldc, hipStream_t s, int tile) {
+                            int64_t ldc, hipStream_t s, int tile, const uint16_t* a3, int kp3) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const int tn = (int)((n + kBN - 1) / kBN);
+  if (!bf16 && a3) {
+    const int tm = (int)((m + kBM - 1) / kBM);
+    const dim3 grid((unsigned)(kXcds * tn * ((tm + kXcds - 1) / kXcds)));
+    hipLaunchKernelGGL(k_gemm_nn32_b3, grid, dim3(kThreads), 0, s, m, n, k, (float)alpha,
+                       reinterpret_cast<const __bf16*>(a3), kp3, B, ldb, (float)beta, C, ldc, tm,
+                       tn);
+    return hipGetLastError();
+  }
   if (tile == 1) {
     const int tm = (int)((m + 2 * kBM - 1) / (2 * kBM));
     const dim3 grid((unsigned)(kXcds * tn * ((tm + kXcds - 1) / kXcds)));
@@ -653,5 +819,14 @@ hipError_t launch_fused_gemm_nn32(int bf16, int nitems, int64_t m_max, int64_t n
     hipLaunchKernelGGL(kb_gemm_nn32<MODE_BF16>, grid, dim3(kThreads), 0, s, D, sel_c);
   else
     hipLaunchKernelGGL(kb_gemm_nn32<MODE_F32>, grid, dim3(kThreads), 0, s, D, sel_c);
+  return hipGetLastError();
+}
+
+hipError_t launch_split3_t(int64_t rows, int nk, int kp, const float2* P, int64_t ldp, uint16_t* P3,
+                           hipStream_t s) {
+  if (rows <= 0 || kp <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((kp + 63) / 64));
+  hipLaunchKernelGGL(k_split3_t, grid, dim3(256), 0, s, rows, nk, kp, P, ldp,
+                     reinterpret_cast<__bf16*>(P3));
   return hipGetLastError();
 }

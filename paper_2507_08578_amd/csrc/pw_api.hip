@@ -86,6 +86,8 @@ struct pw_ham {
   float* kin32 = nullptr;
   float* vs32 = nullptr;
   float2* proj32 = nullptr;
+  uint16_t* proj3 = nullptr;   // proj32 as three bf16 terms, projector-contiguous (FP32 P C)
+  int kp3 = 0;
   float2* T32 = nullptr;
   float2* cprj32 = nullptr;
   float2* work32 = nullptr;
@@ -306,7 +308,7 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_NONLOCAL_LP);
     HIPCHK(c, launch_gemm_nn32(bf16, h->npw, nb, h->nproj, 1.0, h->proj32, h->npw, h->cprj32,
-                               h->nproj, 1.0, out, ldout, s, h->nn_tile32));
+                               h->nproj, 1.0, out, ldout, s, h->nn_tile32, h->proj3, h->kp3));
   }
   return PW_OK;
 }
@@ -575,6 +577,8 @@ pw_status fused_setup(pw_batch* b) {
       d.vs32 = h->vs32;
       d.proj = h->proj;
       d.proj32 = h->proj32;
+      d.proj3 = h->proj3;
+      d.kp3 = h->kp3;
       d.ekb = h->ekb_dev;
       d.cprj = h->cprj;
       d.cprj32 = h->cprj32;
@@ -1091,6 +1095,9 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
     if (h->nproj > 0) {
       TRY(dalloc(h, &h->proj32, (size_t)(npw * h->nproj)));
       HIPCHK(ctx, launch_block_to_f32(npw, h->nproj, h->proj, npw, h->proj32, npw, s));
+      h->kp3 = (int)((h->nproj + 7) / 8 * 8);
+      TRY(dalloc(h, &h->proj3, (size_t)6 * npw * h->kp3));
+      HIPCHK(ctx, launch_split3_t(npw, (int)h->nproj, h->kp3, h->proj32, npw, h->proj3, s));
       TRY(dalloc(h, &h->cprj32, (size_t)(h->nproj * h->nb_max)));
       size_t w32 = 1;
       for (int64_t nb = 1; nb <= h->nb_max; ++nb)

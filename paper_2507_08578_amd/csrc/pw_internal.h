@@ -69,6 +69,8 @@ struct ItemDev {
   const float* vs32;
   const cplx* proj;
   const float2* proj32;
+  const uint16_t* proj3;               // three-term bf16 copy of proj32, projector-contiguous
+  int kp3;                             // its padded projector count (multiple of 8)
   const double* ekb;
   cplx* cprj;
   float2* cprj32;
@@ -277,9 +279,16 @@ hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double al
                             int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
                             const double* rowscale, float2* work, hipStream_t s,
                             const double* alpha_dev = nullptr, int target_blocks = 2048);
+// FP32 (bf16 = 0) with a3 given: P C from the three-term bf16 copy a3 of A
+// (launch_split3_t layout, kp3 = padded k); tile then has no effect.
 hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
-                            int64_t ldc, hipStream_t s, int tile = 0);
+                            int64_t ldc, hipStream_t s, int tile = 0, const uint16_t* a3 = nullptr,
+                            int kp3 = 0);
+// a3[(t 2 + c) rows kp + i kp + k] = term t of part c of P[i + k ldp] split
+// into three bf16 terms (zero for nk <= k < kp; kp a multiple of 8).
+hipError_t launch_split3_t(int64_t rows, int nk, int kp, const float2* P, int64_t ldp, uint16_t* P3,
+                           hipStream_t s);
 
 // Precision conversions
 hipError_t launch_block_to_f32(int64_t rows, int64_t cols, const cplx* x, int64_t ldx, float2* y,
