@@ -32,27 +32,32 @@ constexpr int kDensThreads = 512;
 // split between two (N = 160: three) workgroups, each repeating the plane's
 // N2 transforms.
 constexpr int dens_parts(int n) { return n >= 160 ? 3 : n >= 128 ? 2 : 1; }
+// Rows of every part but the last (which takes the rest): whole rounds of the
+// 32 lane groups where that helps (N = 144: 64 + 80 rows, five rounds where
+// 72 + 72 took six).
+constexpr int dens_split(int n) { return n == 144 ? 64 : (n + dens_parts(n) - 1) / dens_parts(n); }
 
 // Register plane kernel for N1 = N2 = N: each length-N transform in the
 // registers of one lane group (pwfft::lane_fft_bwd); E[e][m2] in LDS holds
 // the plane's extent columns between the two axes.  Workgroup (j3, g NH + h)
-// takes row part h (rows h NR .. h NR + NR - 1) of the bands of group g.  A
-// thread owns rows h NR + grp + k NGR (k < RPT) and N1 outputs
-// base .. base + R - 1 of each: the same elements for every band, so its
-// sums stay in registers.
+// takes row part h (rows h S .. h S + S - 1, the last part up to N - 1) of
+// the bands of group g.  A thread owns rows h S + grp + k NGR (k < RPT) of its
+// part and N1 outputs base .. base + R - 1 of each: the same elements for
+// every band, so its sums stay in registers.
 template <int N, int GMAX>
 __global__ void __launch_bounds__(kDensThreads)
 k_density_reg(BoxPlan P, const double2* __restrict__ tw, const double2* __restrict__ T, int nbc,
               const double* __restrict__ w, int ngroup, double* __restrict__ part, int add) {
   constexpr int G = lane_group(N, GMAX), R = N / G, TRS = N + 1;
-  constexpr int NH = dens_parts(N), NR = (N + NH - 1) / NH;
+  constexpr int NH = dens_parts(N), S = dens_split(N), NL = N - (NH - 1) * S;   // last part: NL rows
+  constexpr int NR = S > NL ? S : NL;                                            // largest part
   constexpr int NGR = kDensThreads / G, RPT = (NR + NGR - 1) / NGR;
   extern __shared__ __align__(16) char lds_raw[];
   double2* E = reinterpret_cast<double2*>(lds_raw);                   // xr x TRS
   int* slot = reinterpret_cast<int*>(E + (size_t)P.xr * TRS);         // N entries
   const int tid = threadIdx.x, j3 = blockIdx.x, g = blockIdx.y / NH, h = blockIdx.y % NH;
   const int grp = tid / G, lb = tid % G, base = R * brev<G>(lb);
-  const int row0 = h * NR, row1 = min(N, row0 + NR);
+  const int row0 = h * S, row1 = h == NH - 1 ? N : row0 + S;
   for (int i = tid; i < N; i += kDensThreads) slot[i] = -1;
   __syncthreads();
   for (int e = tid; e < P.xr; e += kDensThreads) slot[P.ext_m1[e]] = e;
