@@ -224,7 +224,8 @@ pw_status pw_upper_bound(pw_ham* ham, double* b_host);
 /* ---------------------------------------------------------------------------
  * Launch-shape tuning of H*psi.  A handle starts with the register-resident
  * FFT kernels where they exist, the largest band chunk its buffer holds and
- * 2048 target blocks for the split-K projector product; pw_ham_autotune
+ * 4096 target blocks for the split-K projector product (the FP64 product
+ * uses at most 2048); pw_ham_autotune
  * times alternatives on the device and keeps the fastest.
  * ------------------------------------------------------------------------- */
 typedef struct {

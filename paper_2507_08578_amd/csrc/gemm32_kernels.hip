@@ -3,12 +3,14 @@
 // non-local expansion H psi += P c of section 5.2, Eq. ham-nl, applied to
 // complex64 blocks).
 //
-//   MODE_F32 : P C (gemm_nn32): v_mfma_f32_16x16x4f32, operands FP32.
-//              P^H psi (gemm_cn32): every FP32 operand split exactly into three
-//              bfloat16 terms when its tile is staged in LDS, products on
-//              v_mfma_f32_16x16x32_bf16 (six term products per real product,
-//              FP32 accumulation: the accuracy of FP32 products at 6/16 of
-//              the FP32 MFMA time).
+//   MODE_F32 : FP32 operands, each split exactly into three bfloat16 terms,
+//              products on v_mfma_f32_16x16x32_bf16 (six term products per
+//              real product, FP32 accumulation: the accuracy of FP32 products
+//              at 6/16 of the FP32 MFMA time).  P^H psi (gemm_cn32) splits
+//              both operands when their tiles are staged in LDS; P C
+//              (gemm_nn32_b3) reads P's terms from a copy made once per
+//              handle and splits C per stage.  Without that copy P C runs on
+//              v_mfma_f32_16x16x4f32 with FP32 operands.
 //   MODE_BF16: v_mfma_f32_16x16x32_bf16, operands rounded to bfloat16
 //              (round to nearest even) when the MFMA operands are formed from
 //              the FP32 tiles staged in LDS.
