@@ -77,6 +77,9 @@ COUNTER_FILES = {
     ("C5", "fp32", "nonlocal", "k_gemm_nn32_b3"): (
         "profiles/c5_gemm_nn32_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/gemm32_kernels.hip",)),
+    ("C5", "fp64", "density", "k_density_reg"): (
+        "profiles/c5_density_counters.md",
+        ("paper_2507_08578_amd/csrc/density.hip", "paper_2507_08578_amd/csrc/fft_common.h")),
     ("C5", "fp32", "fft_plane", "k_plane_ls"): (
         "profiles/c5_plane_ls_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/fft_ls.hip", "paper_2507_08578_amd/csrc/fft_common.h")),
@@ -231,7 +234,7 @@ def cpu_baseline(w, nb_sample, seed=0):
                       f"(numpy FFT + BLAS), {dt:.2f} s"}
 
 
-def density_leg(ctx, ham, w, X0, steps, warmup):
+def density_leg(ctx, ham, w, X0, steps, warmup, config=None):
     """Electron density of the resident block (section 2.4, Eq. nandtau), every
     band with occupation 2: `steps` pw_density calls timed after `warmup`.
     Roofline of its plane kernel (vector ALU, FP64): per band and z-plane
@@ -271,7 +274,9 @@ def density_leg(ctx, ham, w, X0, steps, warmup):
             "charge_rel_err": abs(charge - ref_charge) / ref_charge,
             "roofline": {"kernel": f"{kname} (N2/N1 backward transforms, w |psi|^2 summed)",
                          "bound": "alu", "achieved": ach, "peak": PEAK["fp64_valu"],
-                         "unit": "TFLOP/s", "frac": ach / PEAK["fp64_valu"], "traffic": None,
+                         "unit": "TFLOP/s", "frac": ach / PEAK["fp64_valu"],
+                         "traffic": measured_traffic(config, "fp64", "density", "k_density_reg",
+                                                     bands_per_launch) if reg else None,
                          "avg_launch_ms": avg_ms,
                          "per_launch": f"{per_band:.4g} flop/band x {bands_per_launch:.0f} bands"}}
 
@@ -614,7 +619,7 @@ def main():
         out["eig_diff_vs_fp64_Ha"] = d
     if not args.no_density:
         log("electron density")
-        out["density"] = density_leg(ctx, ham, w, X0, args.steps, args.warmup)
+        out["density"] = density_leg(ctx, ham, w, X0, args.steps, args.warmup, args.config)
         if not args.no_cpu_baseline:
             nbd = {"C1": 2048, "C3": 256, "C5": 64}[args.config]
             out["density"]["cpu_baseline"] = cpu_density_baseline(w, nbd)
