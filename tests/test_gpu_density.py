@@ -33,6 +33,7 @@ def _c4_cell(box):
 
 CASES = {
     "C1-24^3": lambda: synth.config_c1(),                # register kernel, one row part
+    "C2-k13": lambda: synth.config_c2()[13],             # shifted k-point (k enters only the sphere)
     "C4-30x30x24": lambda: _c4_cell((30, 30, 24)),       # register kernel, odd lane groups
     "C4-32x36x32": lambda: _c4_cell((32, 36, 32)),       # N1 != N2: generic LDS kernel
 }
