@@ -34,6 +34,16 @@ def test_apply_c1(pw, ctx, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("bf16", 2e-2)])
+def test_apply_c2_kpoint(pw, ctx, prec, tol):
+    """A shifted k-point, k = (1/2, 1/2, 1/2): kinetic energies and projector
+    phases of a non-Gamma point (complex projector tables in both products)."""
+    w = synth.config_c2()[13]
+    err = apply_err(pw, ctx, w, 16, prec, seed=3)
+    print(f"C2 k13 {prec} H*psi relative error {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("bf16", 2e-2)])
 def test_apply_c3(pw, ctx, prec, tol):
     err = apply_err(pw, ctx, synth.config_c3(), 8, prec)
     print(f"C3 {prec} H*psi relative error {err:.3e}")
