@@ -261,8 +261,8 @@ pw_status pw_ham_autotune(pw_ham* ham, pw_prec prec, int64_t nb, int32_t reps, p
 /* ---------------------------------------------------------------------------
  * Batched subspace iteration over independent Hamiltonians (k-points of one
  * cell, or separate cells), section 5.1's Chebyshev-filtered iteration run
- * for many small problems at once (section 5.4 notes that k-points are
- * independent and are the first level of parallelism).
+ * for many small problems at once (section 5.3 notes that the equations
+ * are trivially parallel over k-points, the first level of distribution).
  *
  * One iteration of item i: filter coefficients are computed ON THE DEVICE
  * from the item's current Ritz values (a = largest, a0 = smallest) and its

@@ -34,6 +34,7 @@ import dataclasses
 from typing import List, Optional
 
 import numpy as np
+import scipy.fft
 import scipy.linalg
 
 
@@ -93,15 +94,18 @@ def gather_from_box(ham: OracleHam, box: np.ndarray) -> np.ndarray:
 
 
 def fft_backward(box: np.ndarray) -> np.ndarray:
-    """X(r_j) = sum_m X[m] exp(+2 pi i m.j / N) over the last three axes (unnormalised)."""
+    """X(r_j) = sum_m X[m] exp(+2 pi i m.j / N) over the last three axes (unnormalised).
+
+    Evaluated by pocketfft (scipy.fft) on every host core (workers=-1); the
+    direct O(N^2) sums below pin it."""
     nbox = box.shape[-1] * box.shape[-2] * box.shape[-3]
-    return np.fft.ifftn(box, axes=(-3, -2, -1)) * nbox
+    return scipy.fft.ifftn(box, axes=(-3, -2, -1), workers=-1) * nbox
 
 
 def fft_forward(grid: np.ndarray) -> np.ndarray:
     """X[m] = (1/N_box) sum_j X(r_j) exp(-2 pi i m.j / N) over the last three axes."""
     nbox = grid.shape[-1] * grid.shape[-2] * grid.shape[-3]
-    return np.fft.fftn(grid, axes=(-3, -2, -1)) / nbox
+    return scipy.fft.fftn(grid, axes=(-3, -2, -1), workers=-1) / nbox
 
 
 def _dft_matrix(N: int, sign: int) -> np.ndarray:
@@ -263,10 +267,13 @@ def orthonormalize(Y: np.ndarray, HY: Optional[np.ndarray] = None):
     return Yn, HYn
 
 
-def rayleigh_ritz(ham: OracleHam, Y: np.ndarray):
+def rayleigh_ritz(ham: OracleHam, Y: np.ndarray, W: Optional[np.ndarray] = None):
     """W = H Y; Hs = (Y^H W + (Y^H W)^H)/2; Hs = Q diag(lam) Q^H (ascending);
-    Y <- Y Q; W <- W Q; r_b = ||W_b - lam_b Y_b||_2.  Y must be orthonormal."""
-    W = apply_h(ham, Y)
+    Y <- Y Q; W <- W Q; r_b = ||W_b - lam_b Y_b||_2.  Y must be orthonormal.
+    W, if given, is H Y already formed by apply_h (e.g. band by band for a
+    block whose whole FFT box would not fit in host memory)."""
+    if W is None:
+        W = apply_h(ham, Y)
     Hs = Y.conj().T @ W
     Hs = 0.5 * (Hs + Hs.conj().T)
     lam, Q = np.linalg.eigh(Hs)

@@ -212,6 +212,13 @@ bool ranges_overlap(const void* a, int64_t lda, const void* b, int64_t ldb, int6
   return a0 < b1 && b0 < a1;
 }
 
+// byte spans [a, a + abytes) and [b, b + bbytes) intersect
+bool spans_overlap(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
+  const char* a0 = static_cast<const char*>(a);
+  const char* b0 = static_cast<const char*>(b);
+  return abytes > 0 && bbytes > 0 && a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
 pw_status check_block(pw_ham* h, const void* p, int64_t ld, const char* name) {
   if (!p) return fail(h->ctx, PW_ERR_INVALID_ARG, std::string(name) + " is NULL");
   if (ld < h->npw)
@@ -1175,9 +1182,17 @@ pw_status pw_density(pw_ham* h, int64_t nb, const void* psi, int64_t ldpsi, cons
   }
   if (!(h->omega > 0.0) || !std::isfinite(h->omega))
     return fail(c, PW_ERR_INVALID_ARG, "the reciprocal lattice is singular");
-  HIPCHK(c, hipSetDevice(c->device));
   const BoxPlan& P = h->plan;
   const int64_t nbox = (int64_t)P.n1 * P.n2 * P.n3;
+  const int64_t rho_bytes = nbox * (int64_t)sizeof(double);
+  if (nb > 0) {
+    const int64_t psi_bytes = ((nb - 1) * ldpsi + h->npw) * (int64_t)sizeof(cplx);
+    if (spans_overlap(rho, rho_bytes, psi, psi_bytes))
+      return fail(c, PW_ERR_INVALID_ARG, "rho and psi overlap");
+    if (spans_overlap(rho, rho_bytes, w, nb * (int64_t)sizeof(double)))
+      return fail(c, PW_ERR_INVALID_ARG, "rho and w overlap");
+  }
+  HIPCHK(c, hipSetDevice(c->device));
   const bool reg = density_reg_supported(P, c->lds_limit);
   if (!h->rho_part) {
     // about four workgroups per compute unit over the z-planes (and row

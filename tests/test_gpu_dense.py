@@ -41,7 +41,7 @@ def hpd(rng, n, cond=1e3):
     return (Q * d) @ Q.conj().T
 
 
-@pytest.mark.parametrize("n", [1, 16, 64, 100, 160, 200])
+@pytest.mark.parametrize("n", [1, 16, 64, 100, 160, 200, 256, 511, 512])
 def test_potrf_inv(ctx, n):
     rng = np.random.default_rng(n)
     S = hpd(rng, n)
@@ -53,6 +53,22 @@ def test_potrf_inv(ctx, n):
     assert np.abs(U @ X - np.eye(n)).max() < 1e-11
     L = np.linalg.cholesky(S)                          # LAPACK: S = L L^H, U = L^H
     assert np.abs(U - L.conj().T).max() < 1e-11 * np.abs(L).max()
+
+
+@pytest.mark.parametrize("n,cond", [(512, 1e8), (512, 1e12), (160, 1e12)])
+def test_potrf_inv_ill_conditioned(ctx, n, cond):
+    """Gram matrices of a filtered block are ill-conditioned (the filter
+    amplifies the wanted directions by large factors): backward error of the
+    factor and of its inverse at the sizes of the C3 and C5 blocks."""
+    rng = np.random.default_rng(int(n + np.log10(cond)))
+    S = hpd(rng, n, cond)
+    Ud, Xd = ctx.potrf_inv(to_dev(S.T.copy()))
+    U, X = to_host(Ud).T, to_host(Xd).T
+    assert np.abs(U.conj().T @ U - S).max() < 1e-13 * n * np.abs(S).max()
+    # U X = I up to the conditioning of U (sqrt(cond))
+    assert np.abs(U @ X - np.eye(n)).max() < 1e-15 * n * np.sqrt(cond)
+    L = np.linalg.cholesky(S)
+    assert np.abs(U - L.conj().T).max() < 1e-15 * n * cond * np.abs(L).max()
 
 
 def test_potrf_not_posdef(pw, ctx):

@@ -103,6 +103,14 @@ def test_density_rejects_bad_arguments(pw, ctx):
     with pytest.raises(TypeError):
         ham.density(X[:4], torch.ones(4, dtype=torch.float64, device="cuda"),
                     rho=torch.zeros(7, dtype=torch.float64, device="cuda"))     # rho size
+    # rho sharing memory with psi or with w
+    nbox = 24 ** 3
+    big = torch.zeros(nbox + 16, dtype=torch.float64, device="cuda")
+    psi_alias = big[:8 * w.npw].view(torch.complex128).view(4, w.npw)
+    with pytest.raises(pw.PWError, match="rho and psi overlap"):
+        ham.density(psi_alias, torch.ones(4, dtype=torch.float64, device="cuda"), rho=big[:nbox])
+    with pytest.raises(pw.PWError, match="rho and w overlap"):
+        ham.density(X[:4], big[nbox - 2:nbox + 2], rho=big[:nbox])
 
 
 def test_c5_full_block_sampled_and_charge(pw, ctx):

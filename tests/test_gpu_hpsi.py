@@ -1,6 +1,7 @@
 """H*psi on the GPU (pw_apply_h) against the FP64 oracle, element by element.
 
-Tolerance: relative Frobenius error <= 1e-12 (the stated FP64 target is
+Tolerance: 1e-12 on both the largest element-wise error (relative to the
+largest reference element) and the relative Frobenius error (the stated FP64 target is
 1e-10; both sides evaluate the same sums in FP64, so only rounding order
 differs).
 """

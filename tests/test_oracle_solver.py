@@ -108,6 +108,71 @@ def test_upper_bound_is_an_upper_bound(c1_dense):
     assert b - lam[-1] < 2.0              # and not uselessly loose
 
 
+def _max_kinetic_cubic(w):
+    """max over the sphere of 1/2 |k + G|^2 for a cubic cell of edge a, from the
+    integer Miller indices alone: |k + G|^2 = (2 pi / a)^2 |n + k|^2."""
+    a = float(w.cell.A[0, 0])
+    assert np.allclose(w.cell.A, a * np.eye(3))
+    n = w.miller.astype(np.float64) + np.asarray(w.kred)
+    return 0.5 * (2.0 * np.pi / a) ** 2 * float(np.max(np.sum(n * n, axis=1)))
+
+
+def _ham_with(w, vloc=None, proj=None, ekb=None):
+    return oracle.OracleHam(miller=w.miller, recip=w.recip, kred=w.kred, box=w.box,
+                            vloc=w.vloc if vloc is None else vloc,
+                            proj=w.proj if proj is None else proj,
+                            ekb=w.ekb if ekb is None else ekb)
+
+
+@pytest.mark.parametrize("kred", [(0.0, 0.0, 0.0), (0.5, 0.5, 0.5), (0.1, -0.3, 0.2)])
+def test_upper_bound_terms_closed_forms(kred):
+    """The Weyl bound b = max T + max V + lambda_max(D+^1/2 P^H P D+^1/2) pinned term by
+    term, each against a formula the oracle does not use:
+      * empty lattice (V = 0, no projectors): b = max 1/2 |k+G|^2 from the Miller indices;
+      * constant V = V0: b = max T + V0 (also for negative V0);
+      * one projector p with energy E > 0: b = max T + max V + E ||p||^2 (rank one);
+      * a projector with E < 0 adds nothing (D+ clamps it);
+      * several projectors: the last term equals lambda_max of the explicit npw x npw
+        matrix P D+ P^H (same non-zero spectrum as D+^1/2 P^H P D+^1/2)."""
+    w = synth.make_workload("ub", synth.diamond_cell(), kred, 8.0, (24, 24, 24), "s", 4, 8, 1)
+    tmax = _max_kinetic_cubic(w)
+    none = np.zeros((0, w.npw), dtype=np.complex128)
+    zero_v = np.zeros_like(w.vloc)
+    assert abs(oracle.upper_bound(_ham_with(w, vloc=zero_v, proj=none, ekb=np.zeros(0)))
+               - tmax) < 1e-12 * tmax
+    for v0 in (0.7, -1.3):
+        b = oracle.upper_bound(_ham_with(w, vloc=np.full_like(w.vloc, v0), proj=none,
+                                         ekb=np.zeros(0)))
+        assert abs(b - (tmax + v0)) < 1e-12 * tmax
+    vmax = float(w.vloc.max())
+    p = w.proj[3:4]
+    b = oracle.upper_bound(_ham_with(w, proj=p, ekb=np.array([0.8])))
+    pn2 = float(np.sum(np.abs(p) ** 2))
+    assert abs(b - (tmax + vmax + 0.8 * pn2)) < 1e-12 * b
+    b = oracle.upper_bound(_ham_with(w, proj=p, ekb=np.array([-0.8])))
+    assert abs(b - (tmax + vmax)) < 1e-12 * b
+    ekb = np.array([0.5, 0.25, -0.4, 1.5, 0.0, 0.5, 0.75, 0.1])
+    b = oracle.upper_bound(_ham_with(w, ekb=ekb))
+    P = w.proj.T                                           # (npw, nproj)
+    M = (P * np.maximum(ekb, 0.0)[None, :]) @ P.conj().T   # npw x npw, Hermitian PSD
+    lam_nl = float(np.linalg.eigvalsh(M)[-1])
+    assert abs(b - (tmax + vmax + lam_nl)) < 1e-11 * b
+
+
+def test_upper_bound_planted_mistakes_fail():
+    """Dropping any term of the bound, or taking min V for max V, changes b on C1
+    by more than the tolerance of the pins above (so those pins would catch it)."""
+    w = synth.config_c1()
+    b = oracle.upper_bound(_ham_with(w))
+    tmax = _max_kinetic_cubic(w)
+    P = w.proj.T
+    lam_nl = float(np.linalg.eigvalsh((P * w.ekb[None, :]) @ P.conj().T)[-1])
+    vmax, vmin = float(w.vloc.max()), float(w.vloc.min())
+    assert abs(b - (tmax + vmax + lam_nl)) < 1e-11 * b
+    for wrong in (vmax + lam_nl, tmax + lam_nl, tmax + vmax, tmax + vmin + lam_nl):
+        assert abs(b - wrong) > 1e-3
+
+
 def test_chfsi_converges_to_exact_c1(c1_dense):
     """C1 with a 24-vector block: the lowest 16 Ritz values reach the exact spectrum."""
     w, ham, lam, U = c1_dense
