@@ -15,3 +15,8 @@ from .pw_oracle import (  # noqa: F401
     dense_h, upper_bound, cheb_filter, cheb_filter_closed_form, orthonormalize,
     rayleigh_ritz, chfsi, OracleHam, cell_volume, density, density_at,
 )
+from . import eigensolvers  # noqa: F401,E402
+from .eigensolvers import (  # noqa: F401,E402
+    teter_factor, band_kinetic, precondition, block_bounds, lobpcg, line_step, rmm_diis,
+    LobpcgResult, RmmDiisResult,
+)
