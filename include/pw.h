@@ -32,7 +32,13 @@
  *    memory read during the call only.
  *  - Every kernel is enqueued on the stream given to pw_ctx_create.  Calls
  *    return once the work is enqueued, except where a description says the
- *    call synchronises (it then waits for that stream only).
+ *    call synchronises (it then waits for that stream only).  The hot calls
+ *    (pw_apply_h, pw_cheb_filter, pw_orthonormalize, pw_rayleigh_ritz,
+ *    pw_lobpcg, pw_rmm_diis, pw_density after its first call) never
+ *    synchronise and never allocate, so a sequence of them can be captured
+ *    into a HIP graph; failures only the device can see (a Cholesky pivot,
+ *    the eigensolver's sweep limit) are recorded on the device and reported
+ *    by pw_ctx_check.
  *  - A context is not thread-safe; separate contexts are independent.
  */
 #ifndef PW_H
@@ -81,6 +87,29 @@ pw_status pw_ctx_destroy(pw_ctx* ctx);
  * next call on it.  pw_last_error(NULL) returns the last error of calls that
  * had no valid context. */
 const char* pw_last_error(const pw_ctx* ctx);
+
+/*
+ * Deferred status of the hot calls.  A failure that only the device can see
+ * -- a Cholesky pivot at or below the threshold (PW_ERR_NOT_POSDEF), the
+ * dense eigensolver reaching its sweep limit (PW_ERR_NO_CONVERGENCE) -- is
+ * written to a status word of the context by the kernels themselves; the
+ * first one since the last check is kept, later ones are dropped, and the
+ * outputs of the failing call and of every later call that used them are
+ * unspecified.  pw_ctx_check synchronises the context's stream, returns that
+ * status (PW_OK if none), names the call and the pivot in pw_last_error, and
+ * clears the word.  Callers that read results back once per iteration
+ * check once per iteration.
+ */
+pw_status pw_ctx_check(pw_ctx* ctx);
+
+/*
+ * Sweep limit of the dense Hermitian eigensolver inside the hot calls
+ * (pw_rayleigh_ritz and the subspace steps of pw_lobpcg / pw_rmm_diis), in
+ * [1, 40]; default 24.  For n > 64 the solver issues that many outer sweeps
+ * with the convergence test on the device; sweeps after convergence return
+ * at once.  Reaching the limit is reported by pw_ctx_check.
+ */
+pw_status pw_ctx_set_sweep_limit(pw_ctx* ctx, int32_t max_sweeps);
 
 /*
  * Description of H at one k-point (section 5.2, Eq. ham-nl, norm-conserving
@@ -196,10 +225,10 @@ pw_status pw_cheb_filter(pw_ham* ham, pw_prec prec, int32_t degree, double a, do
  * Cholesky orthonormalisation (section 5.4): S = Y^H Y = U^H U (U upper,
  * positive diagonal), Y <- Y U^{-1}; if hy_dev != NULL, HY <- HY U^{-1} too.
  * U is factored in diagonal blocks of 64; Y U^{-1} is a blocked right-side
- * triangular solve (no explicit inverse).
- * gram_prec: PW_FP64 only in this version.  Synchronises (reads the
- * factorisation status).  PW_ERR_NOT_POSDEF when a squared pivot is at or
- * below nb * eps * max_i S_ii; the message names the pivot.
+ * triangular solve (no explicit inverse).  y_dev and hy_dev must not overlap.
+ * gram_prec: PW_FP64 (else PW_ERR_UNSUPPORTED).  Does not synchronise: a
+ * squared pivot at or below nb * eps * max_i S_ii is reported by
+ * pw_ctx_check as PW_ERR_NOT_POSDEF naming the pivot.
  */
 pw_status pw_orthonormalize(pw_ham* ham, pw_prec gram_prec, int64_t nb, void* y_dev, int64_t ld,
                             void* hy_dev, int64_t ldhy);
@@ -209,7 +238,10 @@ pw_status pw_orthonormalize(pw_ham* ham, pw_prec gram_prec, int64_t nb, void* y_
  * Hs = (Y^H W + (Y^H W)^H)/2; Hs = Q diag(lambda) Q^H with lambda ascending;
  * Y <- Y Q; W <- W Q; resid_b = ||W_b - lambda_b Y_b||_2.  Y must be
  * orthonormal.  eig_dev (nb doubles) and resid_dev (nb doubles, may be NULL)
- * are device memory.  Synchronises (eigensolver convergence test).
+ * are device memory.  The eigensolve is cyclic Jacobi (one workgroup in LDS
+ * for nb <= 64, block Jacobi above) with its convergence test on the device;
+ * does not synchronise.  Reaching the sweep limit (pw_ctx_set_sweep_limit)
+ * is reported by pw_ctx_check as PW_ERR_NO_CONVERGENCE.
  */
 pw_status pw_rayleigh_ritz(pw_ham* ham, int64_t nb, void* y_dev, int64_t ld, void* hy_dev,
                            int64_t ldhy, double* eig_dev, double* resid_dev);
@@ -333,9 +365,10 @@ pw_status pw_gemm_nn(pw_ctx* ctx, int64_t m, int64_t n, int64_t k, double alpha_
                      const void* a_dev, int64_t lda, const void* b_dev, int64_t ldb,
                      double beta_re, void* c_dev, int64_t ldc);
 /* Hermitian eigendecomposition a = Q diag(w) Q^H (n x n, lda) by cyclic
- * Jacobi (n > 64: block Jacobi over blocks of 32, one inner sweep per block
- * pair): a is destroyed, q_dev (n x n, ldq) receives Q, w_dev ascending.
- * Synchronises once per sweep.  NO_CONVERGENCE after the sweep limit. */
+ * Jacobi (n > 64: block Jacobi over blocks of 16 indices, one inner sweep per
+ * block pair and round): a is read only, q_dev (n x n, ldq) receives Q,
+ * w_dev ascending.  Allocates its workspace, synchronises once at the end;
+ * NO_CONVERGENCE after 40 sweeps. */
 pw_status pw_heev(pw_ctx* ctx, int64_t n, void* a_dev, int64_t lda, double* w_dev,
                   void* q_dev, int64_t ldq);
 /* Upper Cholesky factor in place: a = U^H U (upper triangle of a read and
@@ -377,7 +410,7 @@ pw_status pw_ctx_set_timing(pw_ctx* ctx, int enable);
 pw_status pw_ctx_stage_time(pw_ctx* ctx, int stage, double* total_ms, int64_t* launches);
 pw_status pw_ctx_reset_timing(pw_ctx* ctx);
 /* Sweeps used by the last dense Hermitian eigensolve on this context
- * (-1 if it hit the sweep limit). */
+ * (-1 if it hit the sweep limit).  Synchronises. */
 pw_status pw_ctx_last_sweeps(const pw_ctx* ctx, int* sweeps);
 
 #ifdef __cplusplus

@@ -86,6 +86,14 @@ class Context:
     def check(self, status: int):
         _check(status, self.handle)
 
+    def check_status(self):
+        """Wait for the context's stream and raise the first failure the hot
+        calls recorded on the device since the last check (pw_ctx_check)."""
+        self.check(_LIB.pw_ctx_check(self.handle))
+
+    def set_sweep_limit(self, max_sweeps: int):
+        self.check(_LIB.pw_ctx_set_sweep_limit(self.handle, int(max_sweeps)))
+
     # --- stage timing ---
     def set_timing(self, enable: bool):
         self.check(_LIB.pw_ctx_set_timing(self.handle, int(enable)))
@@ -274,16 +282,21 @@ class Hamiltonian:
                                            float(b), float(a0), y.shape[0], p, ld, hp, ldh))
         return y
 
-    def orthonormalize(self, y, hy=None):
+    def orthonormalize(self, y, hy=None, gram_prec="fp64", check=True):
+        """Cholesky orthonormalisation in place.  check: wait and raise a
+        failing pivot now (pw_ctx_check); False leaves it to a later check."""
         p, ld = _block_args(y, self.npw, "y")
         if hy is not None:
             hp, ldh = _block_args(hy, self.npw, "hy")
         else:
             hp, ldh = None, 0
-        self.ctx.check(_LIB.pw_orthonormalize(self.handle, PW_FP64, y.shape[0], p, ld, hp, ldh))
+        self.ctx.check(_LIB.pw_orthonormalize(self.handle, _prec(gram_prec), y.shape[0], p, ld,
+                                              hp, ldh))
+        if check:
+            self.ctx.check_status()
         return y
 
-    def rayleigh_ritz(self, y, hy, eig, resid=None):
+    def rayleigh_ritz(self, y, hy, eig, resid=None, check=True):
         import torch
         p, ld = _block_args(y, self.npw, "y")
         hp, ldh = _block_args(hy, self.npw, "hy")
@@ -294,6 +307,8 @@ class Hamiltonian:
         self.ctx.check(_LIB.pw_rayleigh_ritz(self.handle, y.shape[0], p, ld, hp, ldh,
                                              eig.data_ptr(),
                                              resid.data_ptr() if resid is not None else None))
+        if check:
+            self.ctx.check_status()
         return eig
 
     def upper_bound(self) -> float:

@@ -6,8 +6,9 @@ later iteration filters with a = largest Ritz value, a0 = smallest,
 b = the spectral upper bound, then orthonormalises (Cholesky) and runs
 Rayleigh-Ritz.  With reuse_hx the W = H Y left by Rayleigh-Ritz serves as
 the filter's first product (H (Y Q) = (H Y) Q, exact up to rounding).
-The only host reads per iteration are the Ritz values that set the next
-filter interval.
+The only host reads per iteration are the deferred status of the
+orthonormalisation and Rayleigh-Ritz (pw_ctx_check) and the Ritz values that
+set the next filter interval.
 """
 from __future__ import annotations
 
@@ -41,8 +42,9 @@ def chfsi(ham, X0, degree: int, iters: int, upper: Optional[float] = None,
     resid = torch.empty(nb, dtype=torch.float64, device=Y.device)
     b = ham.upper_bound() if upper is None else float(upper)
     st = ChfsiState(Y=Y, HY=HY, eig=eig, resid=resid, upper=b)
-    ham.orthonormalize(Y)
-    ham.rayleigh_ritz(Y, HY, eig, resid)
+    ham.orthonormalize(Y, check=False)
+    ham.rayleigh_ritz(Y, HY, eig, resid, check=False)
+    ham.ctx.check_status()
     st.applies += 1
     lam = eig.cpu()
     if record:
@@ -55,8 +57,9 @@ def chfsi(ham, X0, degree: int, iters: int, upper: Optional[float] = None,
         ham.cheb_filter(Y, degree, float(lam[-1]), b, float(lam[0]), hx=HY if reuse_hx else None,
                         prec=fp)
         st.applies += degree - 1 if reuse_hx else degree
-        ham.orthonormalize(Y)
-        ham.rayleigh_ritz(Y, HY, eig, resid)
+        ham.orthonormalize(Y, check=False)
+        ham.rayleigh_ritz(Y, HY, eig, resid, check=False)
+        ham.ctx.check_status()
         st.applies += 1
         lam = eig.cpu()
         if record:

@@ -386,7 +386,7 @@ __device__ __forceinline__ void rot_row(const Rot& Q, cplx* vp, cplx* vq) {
 
 constexpr int kJacSmallMax = 64;
 constexpr int kJacThreads = 1024;
-constexpr int kMaxSweeps = 40;
+constexpr int kMaxSweeps = kHeevMaxSweeps;
 
 __device__ __forceinline__ double jac_tol(int n) { return fmax(1e-15, 2.2e-16 * n); }
 
@@ -550,8 +550,11 @@ k_jacobi_small(int n, const cplx* __restrict__ Ain, int64_t lda, double* __restr
 // A <- G^H A G and V <- V G with G the block-diagonal product of the Q_k, as
 // two tiled products.  Every index pair meets in each outer sweep (pairs
 // inside a block in every round), so the outer sweeps converge like cyclic
-// Jacobi, with 3 launches per outer round instead of one per scalar round.
-// Padding indices have zero rows and columns and never rotate.
+// Jacobi, with 2 launches per outer round instead of one per scalar round.
+// Padding indices have zero rows and columns and never rotate.  The
+// convergence test runs on the device before every outer sweep; once it
+// passes, conv[0] is set and every later launch of the solve returns at
+// once, so a fixed number of sweeps can be issued with no host read.
 constexpr int kBJ = 16;           // block size
 constexpr int kBJS = 2 * kBJ;     // sub-problem size
 constexpr int kBJTile = 64;       // row / column tile of the update products
@@ -571,7 +574,9 @@ __device__ __forceinline__ int bj_index(int i, int I, int J) {
 constexpr int kBJInnerThreads = 4 * kBJ * kBJ;
 static_assert(2 * kBJS * kBJ == kBJInnerThreads, "V row pairs: two threads each");
 __global__ void __launch_bounds__(kBJInnerThreads)
-k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout) {
+k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout,
+           const int* __restrict__ conv) {
+  if (conv[0]) return;
   __shared__ cplx a[kBJS * (kBJS + 1)];   // ld kBJS + 1 (odd: spreads the LDS banks)
   __shared__ cplx v[kBJS * kBJS];
   __shared__ Rot rots[kBJ];
@@ -646,99 +651,122 @@ k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout) 
   for (int idx = tid; idx < kBJS * kBJS; idx += nt) qo[idx] = v[idx];
 }
 
-// A[idx_k, tile] <- Q_k^H A[idx_k, tile] for block pair k = blockIdx.y of
-// outer round r and the kBJTile-column tile blockIdx.x (in place: the
-// workgroup stages its whole tile before writing it).  Thread: row i, columns
-// jg + t kBJThreads / kBJS.
-__global__ void __launch_bounds__(kBJThreads)
-k_bj_rows(int n2p, int r, cplx* __restrict__ A, const cplx* __restrict__ Qk) {
-  __shared__ cplx T[kBJS * kBJTile];    // [m + j kBJS]: A[idx_k[m], c0 + j]
-  __shared__ cplx QH[kBJS * kBJS];      // [i + m kBJS]: conj(Q[m][i])
-  constexpr int G = kBJThreads / kBJS, NJ = kBJTile / G;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  int I, J;
-  rr_pair(r, blockIdx.y, n2p / kBJ, &I, &J);
-  const cplx* Q = Qk + (int64_t)blockIdx.y * kBJS * kBJS;
-  const int64_t c0 = (int64_t)blockIdx.x * kBJTile;
-  for (int idx = tid; idx < kBJS * kBJTile; idx += nt) {
-    const int j = idx / kBJS, m = idx - j * kBJS;
-    T[idx] = A[bj_index(m, I, J) + (c0 + j) * n2p];
-  }
-  for (int idx = tid; idx < kBJS * kBJS; idx += nt) {
-    const int m = idx / kBJS, i = idx - m * kBJS;
-    QH[idx] = cconj(Q[m + i * kBJS]);
-  }
-  __syncthreads();
-  const int i = tid % kBJS, jg = tid / kBJS;
-  cplx acc[NJ];
-#pragma unroll
-  for (int t = 0; t < NJ; ++t) acc[t] = make_double2(0.0, 0.0);
-#pragma unroll 4
-  for (int m = 0; m < kBJS; ++m) {
-    const cplx q = QH[i + m * kBJS];
-#pragma unroll
-    for (int t = 0; t < NJ; ++t) {
-      const cplx x = T[m + (jg + t * G) * kBJS];
-      acc[t].x += q.x * x.x - q.y * x.y;
-      acc[t].y += q.x * x.y + q.y * x.x;
+// Two-sided update of outer round r.  Workgroup w < npair^2 takes the
+// sub-block of A on block pair p = w / npair (rows) and block pair q =
+// w % npair (columns): A[idx_p, idx_q] <- Q_p^H A[idx_p, idx_q] Q_q, both
+// products in LDS.  Workgroup npair^2 + t npair + q takes kBJTile rows of V
+// from row t kBJTile: V[rows, idx_q] <- V[rows, idx_q] Q_q.  Each workgroup
+// reads and writes only its own elements, so the update is in place.
+constexpr int kBJUThreads = 256;
+__global__ void __launch_bounds__(kBJUThreads)
+k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
+            const cplx* __restrict__ Qk, const int* __restrict__ conv) {
+  if (conv[0]) return;
+  constexpr int LX = kBJS + 1;                         // odd row pitch of the A sub-block
+  __shared__ cplx sm[(kBJS + 1) * kBJS + 2 * kBJS * kBJS];
+  const int tid = threadIdx.x;
+  const int nblk = n2p / kBJ, npair = nblk / 2;
+  const int w = blockIdx.x;
+  if (w < npair * npair) {
+    const int p = w / npair, q = w - p * npair;
+    int Ip, Jp, Iq, Jq;
+    rr_pair(r, p, nblk, &Ip, &Jp);
+    rr_pair(r, q, nblk, &Iq, &Jq);
+    cplx* X = sm;                       // [i + j LX]
+    cplx* Qp = sm + LX * kBJS;          // [m + i kBJS] = Q_p(m, i)
+    cplx* Qq = Qp + kBJS * kBJS;
+    const cplx* gp = Qk + (int64_t)p * kBJS * kBJS;
+    const cplx* gq = Qk + (int64_t)q * kBJS * kBJS;
+    for (int idx = tid; idx < kBJS * kBJS; idx += kBJUThreads) {
+      const int j = idx / kBJS, i = idx - j * kBJS;
+      X[i + j * LX] = A[bj_index(i, Ip, Jp) + (int64_t)bj_index(j, Iq, Jq) * n2p];
+      Qp[idx] = gp[idx];
+      Qq[idx] = gq[idx];
     }
-  }
-  const int gi = bj_index(i, I, J);
+    __syncthreads();
+    constexpr int NJ = kBJS * kBJS / kBJUThreads;      // outputs per thread
+    constexpr int G = kBJUThreads / kBJS;
+    const int i = tid % kBJS, jg = tid / kBJS;
+    cplx acc[NJ];
 #pragma unroll
-  for (int t = 0; t < NJ; ++t) A[gi + (c0 + jg + t * G) * n2p] = acc[t];
-}
-
-// X[tile, idx_k] <- X[tile, idx_k] Q_k for the kBJTile-row tiles of A (n2p
-// rows, ld n2p; tiles blockIdx.x < n2p / kBJTile) and then of V (n rows,
-// ld n).  Thread: row i, columns jg + t kBJThreads / kBJTile.
-__global__ void __launch_bounds__(kBJThreads)
-k_bj_cols(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
-          const cplx* __restrict__ Qk) {
-  __shared__ cplx T[kBJTile * kBJS];    // [i + m kBJTile]: X[r0 + i, idx_k[m]]
-  __shared__ cplx Q[kBJS * kBJS];       // [m + j kBJS]
-  constexpr int G = kBJThreads / kBJTile, NJ = kBJS / G;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  int I, J;
-  rr_pair(r, blockIdx.y, n2p / kBJ, &I, &J);
-  const cplx* Qg = Qk + (int64_t)blockIdx.y * kBJS * kBJS;
-  const int atiles = n2p / kBJTile;
-  const bool onA = (int)blockIdx.x < atiles;
-  cplx* X = onA ? A : V;
-  const int64_t ld = onA ? n2p : n;
-  const int rows = onA ? n2p : n;
-  const int r0 = (onA ? (int)blockIdx.x : (int)blockIdx.x - atiles) * kBJTile;
-  for (int idx = tid; idx < kBJTile * kBJS; idx += nt) {
-    const int m = idx / kBJTile, i = idx - m * kBJTile;
-    T[idx] = (r0 + i < rows) ? X[(r0 + i) + (int64_t)bj_index(m, I, J) * ld]
-                             : make_double2(0.0, 0.0);
+    for (int t = 0; t < NJ; ++t) acc[t] = make_double2(0.0, 0.0);
+    // T = Q_p^H X
+    for (int m = 0; m < kBJS; ++m) {
+      const cplx qh = cconj(Qp[m + i * kBJS]);
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) {
+        const cplx x = X[m + (jg + t * G) * LX];
+        acc[t].x += qh.x * x.x - qh.y * x.y;
+        acc[t].y += qh.x * x.y + qh.y * x.x;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) X[i + (jg + t * G) * LX] = acc[t];
+    __syncthreads();
+    // out = T Q_q
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) acc[t] = make_double2(0.0, 0.0);
+    for (int m = 0; m < kBJS; ++m) {
+      const cplx x = X[i + m * LX];
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) {
+        const cplx qv = Qq[m + (jg + t * G) * kBJS];
+        acc[t].x += x.x * qv.x - x.y * qv.y;
+        acc[t].y += x.x * qv.y + x.y * qv.x;
+      }
+    }
+    const int gi = bj_index(i, Ip, Jp);
+#pragma unroll
+    for (int t = 0; t < NJ; ++t)
+      A[gi + (int64_t)bj_index(jg + t * G, Iq, Jq) * n2p] = acc[t];
+    return;
   }
-  for (int idx = tid; idx < kBJS * kBJS; idx += nt) Q[idx] = Qg[idx];
+  const int v = w - npair * npair;
+  const int tile = v / npair, q = v - tile * npair;
+  int Iq, Jq;
+  rr_pair(r, q, nblk, &Iq, &Jq);
+  const int r0 = tile * kBJTile;
+  cplx* T = sm;                         // [i + m kBJTile]: V[r0 + i, idx_q[m]]
+  cplx* Qq = sm + kBJTile * kBJS;       // [m + j kBJS]
+  const cplx* gq = Qk + (int64_t)q * kBJS * kBJS;
+  for (int idx = tid; idx < kBJTile * kBJS; idx += kBJUThreads) {
+    const int m = idx / kBJTile, i = idx - m * kBJTile;
+    T[idx] = (r0 + i < n) ? V[(r0 + i) + (int64_t)bj_index(m, Iq, Jq) * n] : make_double2(0.0, 0.0);
+  }
+  for (int idx = tid; idx < kBJS * kBJS; idx += kBJUThreads) Qq[idx] = gq[idx];
   __syncthreads();
+  constexpr int G = kBJUThreads / kBJTile, NJ = kBJS / G;
   const int i = tid % kBJTile, jg = tid / kBJTile;
   cplx acc[NJ];
 #pragma unroll
   for (int t = 0; t < NJ; ++t) acc[t] = make_double2(0.0, 0.0);
-#pragma unroll 4
   for (int m = 0; m < kBJS; ++m) {
     const cplx x = T[i + m * kBJTile];
 #pragma unroll
     for (int t = 0; t < NJ; ++t) {
-      const cplx q = Q[m + (jg + t * G) * kBJS];
-      acc[t].x += x.x * q.x - x.y * q.y;
-      acc[t].y += x.x * q.y + x.y * q.x;
+      const cplx qv = Qq[m + (jg + t * G) * kBJS];
+      acc[t].x += x.x * qv.x - x.y * qv.y;
+      acc[t].y += x.x * qv.y + x.y * qv.x;
     }
   }
-  if (r0 + i < rows) {
+  if (r0 + i < n) {
 #pragma unroll
     for (int t = 0; t < NJ; ++t)
-      X[(r0 + i) + (int64_t)bj_index(jg + t * G, I, J) * ld] = acc[t];
+      V[(r0 + i) + (int64_t)bj_index(jg + t * G, Iq, Jq) * n] = acc[t];
   }
 }
+static_assert(kBJTile * kBJS + kBJS * kBJS <= (kBJS + 1) * kBJS + 2 * kBJS * kBJS,
+              "the update workgroup's LDS also holds a V tile and its unitary");
 
 // A0 = [a 0; 0 0] (n2 x n2), V0 = [I 0] (n x n2)
 __global__ void k_jacobi_init(int n, int n2, const cplx* __restrict__ a, int64_t lda,
-                              cplx* __restrict__ A0, cplx* __restrict__ V0) {
+                              cplx* __restrict__ A0, cplx* __restrict__ V0, int* __restrict__ conv) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx == 0) {
+    conv[0] = 0;   // converged
+    conv[1] = 0;   // sweeps when it converged
+  }
   const int64_t na = (int64_t)n2 * n2;
   if (idx < na) {
     const int j = (int)(idx / n2), i = (int)(idx - (int64_t)j * n2);
@@ -752,8 +780,10 @@ __global__ void k_jacobi_init(int n, int n2, const cplx* __restrict__ a, int64_t
 }
 
 // Rank of index p's eigenvalue among 0..n-1 (ties by index).
-__global__ void k_jacobi_rank(int n, int ld, const cplx* __restrict__ A, int* __restrict__ rank) {
+__global__ void k_jacobi_rank(int n, int ld, const cplx* __restrict__ A, int* __restrict__ rank,
+                              const int* __restrict__ conv, int* __restrict__ sweeps_out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) sweeps_out[0] = conv[0] ? conv[1] : -1;
   if (p >= n) return;
   const double dp = A[p + (int64_t)p * ld].x;
   int rk = 0;
@@ -780,7 +810,9 @@ __global__ void k_jacobi_scatter(int n, int ld, const cplx* __restrict__ A,
 // part[2 w + 1]; one workgroup adds the parts.
 constexpr int kOffParts = 256;
 __global__ void __launch_bounds__(256) k_offnorm_part(int n, const cplx* __restrict__ A,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part,
+                                                      const int* __restrict__ conv) {
+  if (conv[0]) return;
   __shared__ double r1[256], r2[256];
   double off = 0.0, tot = 0.0;
   const int64_t nn = (int64_t)n * n;
@@ -807,8 +839,12 @@ __global__ void __launch_bounds__(256) k_offnorm_part(int n, const cplx* __restr
   }
 }
 
+// ... and sets conv = {1, sweep} when off <= tol2 * total (the test that
+// precedes outer sweep `sweep`).
 __global__ void __launch_bounds__(kOffParts) k_offnorm_final(const double* __restrict__ part,
-                                                            double* __restrict__ out) {
+                                                            double tol2, int sweep,
+                                                            int* __restrict__ conv) {
+  if (conv[0]) return;
   __shared__ double r1[kOffParts], r2[kOffParts];
   r1[threadIdx.x] = part[2 * threadIdx.x];
   r2[threadIdx.x] = part[2 * threadIdx.x + 1];
@@ -820,9 +856,9 @@ __global__ void __launch_bounds__(kOffParts) k_offnorm_final(const double* __res
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    out[0] = r1[0];
-    out[1] = r2[0];
+  if (threadIdx.x == 0 && r1[0] <= tol2 * r2[0]) {
+    conv[1] = sweep;
+    conv[0] = 1;
   }
 }
 
@@ -1181,69 +1217,90 @@ hipError_t launch_heev_small_async(int64_t n, const cplx* a, int64_t lda, double
   return hipGetLastError();
 }
 
-hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int64_t ldq, void* work,
-                       double* host_scratch, int* sweeps_done, hipStream_t s) {
+hipError_t launch_heev_async(int64_t n, const cplx* a, int64_t lda, double* w, cplx* q,
+                             int64_t ldq, void* work, int* sweeps_dev, int max_sweeps,
+                             hipStream_t s) {
+  if (n <= kJacSmallMax) return launch_heev_small_async(n, a, lda, w, q, ldq, sweeps_dev, s);
+  if (max_sweeps < 1 || max_sweeps > kMaxSweeps) return hipErrorInvalidValue;
   const int64_t n2p = bj_padded(n);
   char* base = static_cast<char*>(work);
   const size_t mat_bytes = (size_t)(n2p * n2p + n * n2p + n2p * kBJS) * sizeof(cplx);
-  int* dev_int = reinterpret_cast<int*>(base + mat_bytes);
+  int* rank = reinterpret_cast<int*>(base + mat_bytes);
+  int* conv = rank + n;                  // {converged, sweeps}
   const size_t stat_off = (mat_bytes + (size_t)(n + 8) * sizeof(int) + 15) & ~(size_t)15;
-  double* dstat = reinterpret_cast<double*>(base + stat_off);
-  double* dpart = dstat + 2;   // kOffParts pairs of partial norms
-  if (n <= kJacSmallMax) {
-    const size_t lds = (size_t)(n * (2 * n + 1)) * sizeof(cplx);
-    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(jac_threads((int)n)), lds, s, (int)n,
-                       (const cplx*)a, lda, w, q, ldq, dev_int);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    int hs = 0;
-    e = hipMemcpyAsync(&hs, dev_int, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(s);
-    *sweeps_done = hs;
-    return e;
-  }
+  double* dpart = reinterpret_cast<double*>(base + stat_off) + 2;   // kOffParts pairs
   cplx* A = reinterpret_cast<cplx*>(base);
   cplx* V = A + n2p * n2p;
   cplx* Qk = V + n * n2p;
   hipLaunchKernelGGL(k_jacobi_init, dim3(nblocks(n2p * n2p + n * n2p, 256)), dim3(256), 0, s,
-                     (int)n, (int)n2p, (const cplx*)a, lda, A, V);
+                     (int)n, (int)n2p, a, lda, A, V, conv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nblk = (int)(n2p / kBJ), npair = nblk / 2;
-  const int atiles = (int)(n2p / kBJTile), vtiles = (int)((n + kBJTile - 1) / kBJTile);
+  const int vtiles = (int)((n + kBJTile - 1) / kBJTile);
+  const unsigned ugrid = (unsigned)(npair * npair + vtiles * npair);
   const double tl = std::max(1e-15, 2.2e-16 * (double)n);
-  int sw = 0;
-  bool conv = false;
-  for (; sw <= kMaxSweeps; ++sw) {
+  for (int sw = 0; sw <= max_sweeps; ++sw) {
     hipLaunchKernelGGL(k_offnorm_part, dim3(kOffParts), dim3(256), 0, s, (int)n2p, (const cplx*)A,
-                       dpart);
-    hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(kOffParts), 0, s, (const double*)dpart, dstat);
-    e = hipMemcpyAsync(host_scratch, dstat, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    if (host_scratch[0] <= tl * tl * host_scratch[1]) {
-      conv = true;
-      break;
-    }
-    if (sw == kMaxSweeps) break;
+                       dpart, (const int*)conv);
+    hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(kOffParts), 0, s, (const double*)dpart,
+                       tl * tl, sw, conv);
+    if (sw == max_sweeps) break;
     for (int r = 0; r < nblk - 1; ++r) {
       hipLaunchKernelGGL(k_bj_inner, dim3(npair), dim3(kBJInnerThreads), 0, s, (int)n2p, r,
-                         (const cplx*)A, Qk);
-      hipLaunchKernelGGL(k_bj_rows, dim3(atiles, npair), dim3(kBJThreads), 0, s, (int)n2p, r, A,
-                         (const cplx*)Qk);
-      hipLaunchKernelGGL(k_bj_cols, dim3(atiles + vtiles, npair), dim3(kBJThreads), 0, s, (int)n,
-                         (int)n2p, r, A, V, (const cplx*)Qk);
+                         (const cplx*)A, Qk, (const int*)conv);
+      hipLaunchKernelGGL(k_bj_update, dim3(ugrid), dim3(kBJUThreads), 0, s, (int)n, (int)n2p, r, A,
+                         V, (const cplx*)Qk, (const int*)conv);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_jacobi_rank, dim3(nblocks(n, 256)), dim3(256), 0, s, (int)n, (int)n2p,
-                     (const cplx*)A, dev_int);
+                     (const cplx*)A, rank, (const int*)conv, sweeps_dev);
   hipLaunchKernelGGL(k_jacobi_scatter, dim3(nblocks(n * n, 256)), dim3(256), 0, s, (int)n, (int)n2p,
-                     (const cplx*)A, (const cplx*)V, (const int*)dev_int, w, q, ldq);
-  *sweeps_done = conv ? sw : -1;
+                     (const cplx*)A, (const cplx*)V, (const int*)rank, w, q, ldq);
+  return hipGetLastError();
+}
+
+hipError_t launch_heev(int64_t n, const cplx* a, int64_t lda, double* w, cplx* q, int64_t ldq,
+                       void* work, int* sweeps_dev, int* host_scratch, int* sweeps_done,
+                       hipStream_t s) {
+  hipError_t e = launch_heev_async(n, a, lda, w, q, ldq, work, sweeps_dev, kMaxSweeps, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(host_scratch, sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) *sweeps_done = host_scratch[0];
+  return e;
+}
+
+// First failure since the last clear wins: rec = {status, op, info}.
+__global__ void k_status_record(const int* __restrict__ chol_status, const int* __restrict__ sweeps,
+                                int op, int* __restrict__ rec) {
+  if (threadIdx.x != 0 || rec[0] != 0) return;
+  if (chol_status && chol_status[0] >= 0) {
+    rec[0] = 5;   // PW_ERR_NOT_POSDEF
+    rec[1] = op;
+    rec[2] = chol_status[0];
+  } else if (sweeps && sweeps[0] < 0) {
+    rec[0] = 7;   // PW_ERR_NO_CONVERGENCE
+    rec[1] = op;
+    rec[2] = 0;
+  }
+}
+
+__global__ void k_fill_int(int n, int v, int* __restrict__ p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_status_record(const int* chol_status, const int* sweeps, int op, int* rec,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_status_record, dim3(1), dim3(64), 0, s, chol_status, sweeps, op, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int n, int v, int* p, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, n, v, p);
   return hipGetLastError();
 }
 

@@ -35,7 +35,11 @@ struct pw_ctx {
   double acc_ms[PW_STAGE_COUNT] = {0};
   int64_t launches[PW_STAGE_COUNT] = {0};
   double* pinned = nullptr;   // small pinned host scratch (64 doubles)
-  int last_sweeps = 0;        // sweeps of the last dense eigensolve
+  // deferred status of the hot calls on the device: [0..2] = {status, op,
+  // info} of the first failure since the last pw_ctx_check, [4] = sweeps of
+  // the last dense eigensolve (-1: sweep limit reached)
+  int* rec_dev = nullptr;
+  int max_sweeps = 24;        // sweep limit of the block eigensolver in hot calls
   int refs = 1;               // the caller's handle + one per live ham / batch
 
   hipEvent_t get_event() {
@@ -331,11 +335,23 @@ pw_status rotate_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, const cplx* m
 }
 
 pw_status heev_status(pw_ctx* c, int sweeps) {
-  c->last_sweeps = sweeps;
   if (sweeps < 0)
     return fail(c, PW_ERR_NO_CONVERGENCE, "Jacobi eigensolver did not converge in its sweep limit");
   return PW_OK;
 }
+
+// Hot calls that record a deferred status (pw_ctx_check names them).
+enum DeferredOp { kOpOrtho = 1, kOpRayleighRitz = 2, kOpLobpcg = 3, kOpRmmDiis = 4 };
+const char* op_name(int op) {
+  switch (op) {
+    case kOpOrtho: return "pw_orthonormalize";
+    case kOpRayleighRitz: return "pw_rayleigh_ritz";
+    case kOpLobpcg: return "pw_lobpcg";
+    case kOpRmmDiis: return "pw_rmm_diis";
+  }
+  return "a hot call";
+}
+int* sweeps_slot(pw_ctx* c) { return c->rec_dev + 4; }
 
 // Blocked upper Cholesky a = U^H U in place (upper triangle read; blocks
 // below the diagonal are left with scratch values).  dinv receives the
@@ -380,6 +396,62 @@ hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* 
     if (e == hipSuccess) e = launch_copy_block(rows, kbj, tmp, rows, y + j0 * ld, ld, s);
   }
   return e;
+}
+
+// Cholesky orthonormalisation of a block (Gram in FP64, blocked Cholesky,
+// Y <- Y U^{-1} and, if hy is given, HY <- HY U^{-1}); a failing pivot goes
+// to the context's deferred status under op.  No host synchronisation.
+pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op) {
+  pw_ctx* c = h->ctx;
+  hipStream_t s = c->stream;
+  {
+    StageScope sc(c, PW_STAGE_GRAM);
+    // Hermitian: the tiles on and above the diagonal, then mirrored
+    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, y, ld, h->sub0, nb, nullptr, h->gemm_work, s,
+                             0.0, nullptr, 2048, 1));
+    HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_CHOL);
+    HIPCHK(c, chol_blocked(nb, h->sub0, nb, h->dinv, h->panel, h->dtol, h->status_dev, s));
+    HIPCHK(c, launch_status_record(h->status_dev, nullptr, op, c->rec_dev, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_ROTATE);
+    HIPCHK(c, trsm_right(h->npw, nb, y, ld, h->sub0, nb, h->dinv, h->blk, s, h->nn_tile));
+    if (hy)
+      HIPCHK(c, trsm_right(h->npw, nb, hy, ldhy, h->sub0, nb, h->dinv, h->blk, s, h->nn_tile));
+  }
+  return PW_OK;
+}
+
+// The subspace part of Rayleigh-Ritz for Y orthonormal and W = H Y given:
+// Hs = Y^H W (Hermitian part), Hs = Q diag(eig) Q^H, Y <- Y Q, W <- W Q,
+// resid_b = ||W_b - eig_b Y_b|| (if resid); eigensolver status deferred.
+pw_status subspace_rr(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, double* eig,
+                      double* resid, int op) {
+  pw_ctx* c = h->ctx;
+  hipStream_t s = c->stream;
+  {
+    StageScope sc(c, PW_STAGE_GRAM);
+    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, hy, ldhy, h->sub0, nb, nullptr,
+                             h->gemm_work, s, 0.0, nullptr, 2048, 1));
+    HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_EIGH);
+    HIPCHK(c, launch_heev_async(nb, h->sub0, nb, eig, h->sub1, nb, h->heev_work, sweeps_slot(c),
+                                c->max_sweeps, s));
+    HIPCHK(c, launch_status_record(nullptr, sweeps_slot(c), op, c->rec_dev, s));
+  }
+  pw_status st;
+  if ((st = rotate_block(h, nb, y, ld, h->sub1)) != PW_OK) return st;
+  if ((st = rotate_block(h, nb, hy, ldhy, h->sub1)) != PW_OK) return st;
+  if (resid) {
+    StageScope sc(c, PW_STAGE_MISC);
+    HIPCHK(c, launch_residuals(h->npw, nb, hy, ldhy, y, ld, eig, resid, s));
+  }
+  return PW_OK;
 }
 
 // Runs the hot-path helpers of one context on another stream (untimed while
@@ -825,15 +897,27 @@ pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
     return fail(nullptr, PW_ERR_OOM, "pinned host scratch allocation failed");
   }
   c->pinned = static_cast<double*>(pin);
-  e = fft_set_lds_limits(c->lds_limit);
+  void* rec = nullptr;
+  e = hipMalloc(&rec, 8 * sizeof(int));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(pin);
+    delete c;
+    return fail(nullptr, PW_ERR_OOM, "status word allocation failed");
+  }
+  c->rec_dev = static_cast<int*>(rec);
+  e = launch_fill_int(8, 0, c->rec_dev, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = fft_set_lds_limits(c->lds_limit);
   if (e == hipSuccess) e = fft_reg_set_lds_limits(c->lds_limit);
   if (e == hipSuccess) e = heev_set_lds_limit(c->lds_limit);
   if (e == hipSuccess) e = fft_ls_set_lds_limit(c->lds_limit);
   if (e == hipSuccess) e = density_set_lds_limit(c->lds_limit);
   if (e != hipSuccess) {
+    (void)hipFree(rec);
     (void)hipHostFree(pin);
     delete c;
-    return fail(nullptr, PW_ERR_HIP, std::string("LDS opt-in: ") + hipGetErrorString(e));
+    return fail(nullptr, PW_ERR_HIP, std::string("context set-up: ") + hipGetErrorString(e));
   }
   *out = c;
   return PW_OK;
@@ -852,6 +936,7 @@ void ctx_release(pw_ctx* ctx) {
   }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->rec_dev) (void)hipFree(ctx->rec_dev);
   delete ctx;
 }
 }  // namespace
@@ -1302,37 +1387,15 @@ pw_status pw_orthonormalize(pw_ham* h, pw_prec gram_prec, int64_t nb, void* yv, 
   if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
   pw_status st;
   if ((st = check_hot(h, gram_prec, nb)) != PW_OK) return st;
+  if (gram_prec != PW_FP64)
+    return fail(h->ctx, PW_ERR_UNSUPPORTED, "the Gram matrix is formed in FP64 only");
   if ((st = check_block(h, yv, ld, "y")) != PW_OK) return st;
   if (hyv && (st = check_block(h, hyv, ldhy, "hy")) != PW_OK) return st;
+  if (hyv && ranges_overlap(yv, ld, hyv, ldhy, h->npw, nb))
+    return fail(h->ctx, PW_ERR_INVALID_ARG, "y and hy overlap");
   pw_ctx* c = h->ctx;
   HIPCHK(c, hipSetDevice(c->device));
-  hipStream_t s = c->stream;
-  cplx* y = static_cast<cplx*>(yv);
-  {
-    StageScope sc(c, PW_STAGE_GRAM);
-    // Hermitian: the tiles on and above the diagonal, then mirrored
-    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, y, ld, h->sub0, nb, nullptr, h->gemm_work, s,
-                             0.0, nullptr, 2048, 1));
-    HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
-  }
-  {
-    StageScope sc(c, PW_STAGE_CHOL);
-    HIPCHK(c, chol_blocked(nb, h->sub0, nb, h->dinv, h->panel, h->dtol, h->status_dev, s));
-  }
-  int status = 0;
-  HIPCHK(c, hipMemcpyAsync(&status, h->status_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
-  if (status >= 0)
-    return fail(c, PW_ERR_NOT_POSDEF,
-                "Gram matrix not positive definite at pivot " + std::to_string(status));
-  {
-    StageScope sc(c, PW_STAGE_ROTATE);
-    HIPCHK(c, trsm_right(h->npw, nb, y, ld, h->sub0, nb, h->dinv, h->blk, s, h->nn_tile));
-    if (hyv)
-      HIPCHK(c, trsm_right(h->npw, nb, static_cast<cplx*>(hyv), ldhy, h->sub0, nb, h->dinv, h->blk, s,
-                           h->nn_tile));
-  }
-  return PW_OK;
+  return ortho_block(h, nb, static_cast<cplx*>(yv), ld, static_cast<cplx*>(hyv), ldhy, kOpOrtho);
 }
 
 pw_status pw_rayleigh_ritz(pw_ham* h, int64_t nb, void* yv, int64_t ld, void* hyv, int64_t ldhy,
@@ -1347,29 +1410,10 @@ pw_status pw_rayleigh_ritz(pw_ham* h, int64_t nb, void* yv, int64_t ld, void* hy
     return fail(h->ctx, PW_ERR_INVALID_ARG, "y and hy overlap");
   pw_ctx* c = h->ctx;
   HIPCHK(c, hipSetDevice(c->device));
-  hipStream_t s = c->stream;
   cplx* y = static_cast<cplx*>(yv);
   cplx* hy = static_cast<cplx*>(hyv);
   if ((st = ham_apply(h, nb, y, ld, hy, ldhy, 1.0, 0.0, 0.0, nullptr, 0)) != PW_OK) return st;
-  {
-    StageScope sc(c, PW_STAGE_GRAM);
-    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, hy, ldhy, h->sub0, nb, nullptr,
-                             h->gemm_work, s, 0.0, nullptr, 2048, 1));
-    HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
-  }
-  int sweeps = 0;
-  {
-    StageScope sc(c, PW_STAGE_EIGH);
-    HIPCHK(c, launch_heev(nb, h->sub0, nb, eig, h->sub1, nb, h->heev_work, c->pinned, &sweeps, s));
-  }
-  if ((st = heev_status(c, sweeps)) != PW_OK) return st;
-  if ((st = rotate_block(h, nb, y, ld, h->sub1)) != PW_OK) return st;
-  if ((st = rotate_block(h, nb, hy, ldhy, h->sub1)) != PW_OK) return st;
-  if (resid) {
-    StageScope sc(c, PW_STAGE_MISC);
-    HIPCHK(c, launch_residuals(h->npw, nb, hy, ldhy, y, ld, eig, resid, s));
-  }
-  return PW_OK;
+  return subspace_rr(h, nb, y, ld, hy, ldhy, eig, resid, kOpRayleighRitz);
 }
 
 pw_status pw_upper_bound(pw_ham* h, double* b_host) {
@@ -1405,7 +1449,9 @@ pw_status pw_upper_bound(pw_ham* h, double* b_host) {
     if (e == hipSuccess) e = launch_scale_rows_cols(m, sq, M, m, s);
     if (e == hipSuccess) e = launch_hermitize(m, M, m, s);
     int sweeps = 0;
-    if (e == hipSuccess) e = launch_heev(m, M, m, w, Q, m, hw, c->pinned, &sweeps, s);
+    if (e == hipSuccess)
+      e = launch_heev(m, M, m, w, Q, m, hw, sweeps_slot(c), reinterpret_cast<int*>(c->pinned),
+                      &sweeps, s);
     double wmax = 0.0;
     if (e == hipSuccess) e = hipMemcpyAsync(&wmax, w + (m - 1), sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1852,9 +1898,8 @@ pw_status pw_heev(pw_ctx* c, int64_t n, void* a, int64_t lda, double* w, void* q
   pw_status st = dalloc(&tmp, &hw, heev_work_bytes(n));
   if (st != PW_OK) return st;
   int sweeps = 0;
-  hipError_t e = launch_heev(n, static_cast<cplx*>(a), lda, w, static_cast<cplx*>(q), ldq, hw,
-                             c->pinned, &sweeps, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipError_t e = launch_heev(n, static_cast<const cplx*>(a), lda, w, static_cast<cplx*>(q), ldq, hw,
+                             sweeps_slot(c), reinterpret_cast<int*>(c->pinned), &sweeps, c->stream);
   free_ham(&tmp);
   if (e != hipSuccess) return fail(c, PW_ERR_HIP, hipGetErrorString(e));
   return heev_status(c, sweeps);
@@ -1936,8 +1981,42 @@ pw_status pw_ctx_stage_time(pw_ctx* c, int stage, double* total_ms, int64_t* lau
 
 pw_status pw_ctx_last_sweeps(const pw_ctx* c, int* sweeps) {
   if (!c || !sweeps) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx or sweeps is NULL");
-  *sweeps = c->last_sweeps;
+  pw_ctx* m = const_cast<pw_ctx*>(c);
+  HIPCHK(m, hipSetDevice(m->device));
+  int* hs = reinterpret_cast<int*>(m->pinned) + 8;
+  HIPCHK(m, hipMemcpyAsync(hs, sweeps_slot(m), sizeof(int), hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(m, hipStreamSynchronize(m->stream));
+  *sweeps = hs[0];
   return PW_OK;
+}
+
+pw_status pw_ctx_set_sweep_limit(pw_ctx* c, int32_t max_sweeps) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (max_sweeps < 1 || max_sweeps > kHeevMaxSweeps)
+    return fail(c, PW_ERR_INVALID_ARG,
+                "sweep limit must be in [1, " + std::to_string(kHeevMaxSweeps) + "]");
+  c->max_sweeps = max_sweeps;
+  return PW_OK;
+}
+
+pw_status pw_ctx_check(pw_ctx* c) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  HIPCHK(c, hipSetDevice(c->device));
+  int* hr = reinterpret_cast<int*>(c->pinned) + 16;
+  HIPCHK(c, hipMemcpyAsync(hr, c->rec_dev, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int code = hr[0], op = hr[1], info = hr[2];
+  if (code == 0) return PW_OK;
+  HIPCHK(c, launch_fill_int(4, 0, c->rec_dev, c->stream));
+  if (code == PW_ERR_NOT_POSDEF)
+    return fail(c, PW_ERR_NOT_POSDEF,
+                std::string(op_name(op)) + ": Gram matrix not positive definite at pivot " +
+                    std::to_string(info));
+  if (code == PW_ERR_NO_CONVERGENCE)
+    return fail(c, PW_ERR_NO_CONVERGENCE,
+                std::string(op_name(op)) + ": Jacobi eigensolver reached its limit of " +
+                    std::to_string(c->max_sweeps) + " sweeps");
+  return fail(c, (pw_status)code, std::string(op_name(op)) + ": device-side failure");
 }
 
 pw_status pw_ctx_reset_timing(pw_ctx* c) {

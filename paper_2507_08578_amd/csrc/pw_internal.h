@@ -332,18 +332,33 @@ hipError_t launch_chol_diag(int kb, int k0, cplx* a, int64_t lda, cplx* dinv, co
                             int* status, hipStream_t s);
 hipError_t launch_zero_lower(int64_t n, cplx* a, int64_t lda, hipStream_t s);
 hipError_t launch_identity(int64_t n, cplx* a, int64_t lda, hipStream_t s);
-// Cyclic Jacobi eigensolver of a Hermitian n x n matrix (a is destroyed;
-// n > 64: block Jacobi, sub-problems and unitaries of 64 x 64 in LDS):
-// w ascending, q = eigenvectors.  work: heev_work_bytes(n) device bytes;
-// host_scratch: >= 4 doubles of pinned host memory.  Synchronises the stream
-// once per sweep.  *sweeps_done = sweeps used, or -1 if not converged.
+// Cyclic Jacobi eigensolver of a Hermitian n x n matrix (n > 64: block
+// Jacobi over blocks of 16, one LDS sweep per block pair and round): w
+// ascending, q = eigenvectors; a is read only.  work: heev_work_bytes(n)
+// device bytes.  launch_heev_async issues at most max_sweeps outer sweeps
+// (in [1, 40]) with the convergence test on the device and reads nothing
+// back: sweeps_dev[0] = sweeps used, or -1 if the limit was reached.
 size_t heev_work_bytes(int64_t n);
 // n <= 64 only: the whole solve in one workgroup, no host synchronisation;
 // sweeps_dev[0] = sweeps used or -1.
 hipError_t launch_heev_small_async(int64_t n, const cplx* a, int64_t lda, double* w, cplx* q,
                                    int64_t ldq, int* sweeps_dev, hipStream_t s);
 hipError_t heev_set_lds_limit(size_t bytes);
-hipError_t launch_heev(int64_t n, cplx* a, int64_t lda, double* w, cplx* q, int64_t ldq, void* work,
-                       double* host_scratch, int* sweeps_done, hipStream_t s);
+hipError_t launch_heev_async(int64_t n, const cplx* a, int64_t lda, double* w, cplx* q,
+                             int64_t ldq, void* work, int* sweeps_dev, int max_sweeps,
+                             hipStream_t s);
+// The same with the largest sweep limit, then waits for the stream and
+// returns the sweep count (or -1) in *sweeps_done (host_scratch: one int of
+// pinned host memory).
+hipError_t launch_heev(int64_t n, const cplx* a, int64_t lda, double* w, cplx* q, int64_t ldq,
+                       void* work, int* sweeps_dev, int* host_scratch, int* sweeps_done,
+                       hipStream_t s);
+constexpr int kHeevMaxSweeps = 40;
+// Deferred status: rec = {status, op, info}; the first failure since the
+// last clear is kept (chol_status[0] >= 0: NOT_POSDEF at that pivot;
+// sweeps[0] < 0: NO_CONVERGENCE).  Either pointer may be null.
+hipError_t launch_status_record(const int* chol_status, const int* sweeps, int op, int* rec,
+                                hipStream_t s);
+hipError_t launch_fill_int(int n, int v, int* p, hipStream_t s);
 hipError_t launch_residuals(int64_t npw, int64_t nb, const cplx* W, int64_t ldw, const cplx* Y,
                             int64_t ldy, const double* lam, double* resid, hipStream_t s);

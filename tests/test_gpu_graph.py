@@ -1,0 +1,123 @@
+"""The single-k hot calls neither synchronise nor allocate, so one whole
+Chebyshev-filtered iteration -- filter reusing H Y, Cholesky
+orthonormalisation, Rayleigh-Ritz, the shape of the benchmarked step -- can
+be captured into one HIP graph.  Replays must equal the same calls issued
+directly, bit for bit, with unrelated eager work between replays.  Failures
+only the device sees (a Cholesky pivot, the eigensolver's sweep limit) come
+back through the context's deferred status.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(pw, nb, seed):
+    import torch
+    w = synth.config_c1()
+    s = torch.cuda.Stream()
+    ctx = pw.Context(0, stream=s)
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=nb)
+    with torch.cuda.stream(s):
+        Y = to_dev(synth.start_block(w.npw, nb, seed))
+        HY = torch.empty_like(Y)
+        eig = torch.empty(nb, dtype=torch.float64, device="cuda")
+        res = torch.empty_like(eig)
+    s.synchronize()
+    return ctx, ham, s, Y, HY, eig, res
+
+
+@pytest.mark.parametrize("nb", [16, 96])   # one-workgroup eigensolver; block Jacobi (n > 64)
+def test_iteration_graph_replay_is_bit_identical(pw, nb):
+    import torch
+    ctx, ham, s, Y, HY, eig, res = _state(pw, nb, seed=3)
+    with torch.cuda.stream(s):
+        ham.orthonormalize(Y, check=False)
+        ham.rayleigh_ritz(Y, HY, eig, res, check=False)
+    ctx.check_status()
+    lam = eig.cpu().numpy()
+    a, a0, b = float(lam[-1]), float(lam[0]), ham.upper_bound()
+    with torch.cuda.stream(s):
+        Y0, HY0 = Y.clone(), HY.clone()
+
+    def step():
+        ham.cheb_filter(Y, 8, a, b, a0, hx=HY)
+        ham.orthonormalize(Y, check=False)
+        ham.rayleigh_ritz(Y, HY, eig, res, check=False)
+
+    with torch.cuda.stream(s):
+        step()
+    ctx.check_status()
+    ref = [t.clone() for t in (Y, HY, eig, res)]
+    assert np.all(np.diff(ref[2].cpu().numpy()) >= 0)
+
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        Y.copy_(Y0)
+        HY.copy_(HY0)
+    s.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        step()
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            Y.copy_(Y0)
+            HY.copy_(HY0)
+            eig.zero_()
+            res.zero_()
+            g.replay()
+        junk = torch.randn(4096, 64, device="cuda") @ torch.randn(64, 64, device="cuda")
+        torch.cuda.synchronize()
+        del junk
+        ctx.check_status()
+        for got, want, name in zip((Y, HY, eig, res), ref, ("Y", "HY", "eig", "resid")):
+            assert torch.equal(got, want), (rep, name)
+
+
+def test_deferred_not_posdef_then_cleared(pw):
+    import torch
+    ctx, ham, s, Y, HY, eig, res = _state(pw, 8, seed=1)
+    with torch.cuda.stream(s):
+        Y[5].copy_(Y[2])
+        ham.orthonormalize(Y, check=False)          # enqueued; returns without a status
+    with pytest.raises(pw.PWError) as e:
+        ctx.check_status()
+    assert e.value.status == 5 and "pw_orthonormalize" in str(e.value) and "pivot 5" in str(e.value)
+    ctx.check_status()                               # the word was cleared
+
+
+def test_deferred_sweep_limit(pw):
+    """A random 96 x 96 subspace matrix cannot be diagonalised in one Jacobi
+    sweep: with the limit at 1 the device reports NO_CONVERGENCE; at the
+    default limit the same call succeeds."""
+    import torch
+    ctx, ham, s, Y, HY, eig, res = _state(pw, 96, seed=2)
+    with torch.cuda.stream(s):
+        ham.orthonormalize(Y, check=False)
+        Y1 = Y.clone()
+    ctx.check_status()
+    ctx.set_sweep_limit(1)
+    with torch.cuda.stream(s):
+        ham.rayleigh_ritz(Y, HY, eig, res, check=False)
+    with pytest.raises(pw.PWError) as e:
+        ctx.check_status()
+    assert e.value.status == 7 and "pw_rayleigh_ritz" in str(e.value)
+    ctx.set_sweep_limit(24)
+    with torch.cuda.stream(s):
+        Y.copy_(Y1)
+        ham.rayleigh_ritz(Y, HY, eig, res, check=False)
+    ctx.check_status()
+    assert 1 < ctx.last_sweeps() <= 24
+    with pytest.raises(pw.PWError):
+        ctx.set_sweep_limit(0)
+
+
+def test_low_precision_gram_is_refused(pw, ctx):
+    w = synth.config_c1()
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=8, low_prec=True)
+    Y = to_dev(synth.start_block(w.npw, 8, 0))
+    with pytest.raises(pw.PWError) as e:
+        ham.orthonormalize(Y, gram_prec="bf16")
+    assert e.value.status == 2
