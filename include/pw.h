@@ -247,6 +247,75 @@ pw_status pw_rayleigh_ritz(pw_ham* ham, int64_t nb, void* y_dev, int64_t ld, voi
                            int64_t ldhy, double* eig_dev, double* resid_dev);
 
 /*
+ * One pass of block LOBPCG (section 5.1: the locally optimal block
+ * preconditioned conjugate-gradient solver measured beside Chebyshev
+ * filtering, with its block count nblock_lobpcg and line count nline; the
+ * paper names it without its steps, this is Knyazev's method applied to
+ * blocks of bands in turn).  All FP64.
+ *   The nb bands of y_dev are orthonormalised (Cholesky), then split into
+ *   nblock contiguous blocks (sizes differ by at most one, larger first).
+ *   Block j: made orthogonal to the blocks below it (already updated),
+ *   orthonormalised, Rayleigh-Ritzed; then nline times
+ *     R = H X - X Lambda,  W = K R (Teter-Payne-Allan preconditioner:
+ *       K_gb = k(T_g / Ekin_b), k(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4),
+ *       Ekin_b = <x_b|T|x_b>/<x_b|x_b>),
+ *     W orthogonal to the lower blocks and to X, columns normalised,
+ *     orthonormalised; H W formed (the only H application of the line);
+ *     P (from the second line on) orthogonal to X and W with H P alongside,
+ *     normalised, orthonormalised;
+ *     Rayleigh-Ritz on V = [X, W, P]: Hs = V^H (H V), Hs Z = Z Theta;
+ *     X <- V Z[:, :m], P <- V[:, m:] Z[m:, :m], H X and H P by the same
+ *     products, Lambda <- Theta[:m].
+ *   Finally one Rayleigh-Ritz over all nb bands with the carried H X:
+ *   y_dev <- Ritz vectors, hy_dev <- H y, eig_dev (nb, ascending), resid_dev
+ *   (nb, may be NULL) = ||H y_b - eig_b y_b||.
+ * hist_dev (may be NULL): (nline + 1) x nb doubles, hist[t nb + b] = the
+ * Ritz value of band b after line t of its block (t = 0: the block's first
+ * Rayleigh-Ritz).  1 <= nblock <= nb <= nb_max, 1 <= nline <= 1000; y and hy
+ * must not overlap.  The first call (and a later one with a larger block or
+ * nb) allocates the solver's workspace on the handle (two pairs of
+ * npw x 3m blocks, m = ceil(nb / nblock), plus (3m)^2 matrices); other calls
+ * allocate nothing.  Never synchronises; Cholesky and eigensolver failures
+ * are reported by pw_ctx_check.
+ */
+pw_status pw_lobpcg(pw_ham* ham, int64_t nb, int32_t nblock, int32_t nline, void* y_dev,
+                    int64_t ld, void* hy_dev, int64_t ldhy, double* eig_dev, double* resid_dev,
+                    double* hist_dev);
+
+/*
+ * One RMM-DIIS pass (section 5.4: residual minimisation with direct
+ * inversion in the iterative subspace; no orthogonalisation during the band
+ * updates, one full-band Cholesky orthonormalisation and one subspace
+ * rotation per call; the paper cites Kresse and Furthmuller for the steps).
+ * Every band b of y_dev (normally Ritz vectors of an earlier solver) on its
+ * own, all FP64:
+ *   psi^0 = y_b; R(psi) = H psi - e(psi) psi, e(psi) = <psi|H psi>/<psi|psi>;
+ *   K = the Teter-Payne-Allan preconditioner of pw_lobpcg with Ekin_b of psi^0;
+ *   lam = the step minimising the Rayleigh quotient on span{psi^0, K R^0}
+ *     (the lowest vector c of the 2 x 2 pencil, lam = c_1 / c_0; 0 when the
+ *     two vectors are numerically dependent);  psi^1 = psi^0 + lam K R^0;
+ *   for M = 1 .. ndiis - 1: alpha = the lowest vector of the pencil
+ *     <R^i|R^j> alpha = e <psi^i|psi^j> alpha (i, j <= M; directions of the
+ *     overlap matrix at or below 1e-12 of its largest eigenvalue dropped;
+ *     alpha normalised so that alpha^H <psi|psi> alpha = 1 and sum alpha_i is
+ *     real and non-negative);  psi^{M+1} = sum alpha_i psi^i
+ *     + lam K sum alpha_i R^i;
+ *   then y <- psi^ndiis, orthonormalised (Cholesky, H y carried), and one
+ *   Rayleigh-Ritz with the carried H y: y_dev, hy_dev, eig_dev, resid_dev as
+ *   in pw_lobpcg.
+ * hy_valid = 1: hy_dev holds H y_dev on entry (e.g. from the previous
+ * Rayleigh-Ritz) and the first application is skipped; 0: it is formed.
+ * band_resid_dev (may be NULL): (ndiis + 1) x nb doubles, ||R^M_b|| /
+ * ||psi^M_b|| for M = 0..ndiis.  1 <= ndiis <= 8; H is applied ndiis + 1
+ * times (ndiis with hy_valid).  Workspace (2 (ndiis + 1) + 3 blocks of
+ * npw x nb) allocated by the first call and by a later one with a larger nb
+ * or ndiis.  Never synchronises; failures via pw_ctx_check.
+ */
+pw_status pw_rmm_diis(pw_ham* ham, int64_t nb, int32_t ndiis, void* y_dev, int64_t ld,
+                      void* hy_dev, int64_t ldhy, int32_t hy_valid, double* eig_dev,
+                      double* resid_dev, double* band_resid_dev);
+
+/*
  * Upper bound of the spectrum of H used as the filter's upper edge b:
  * max_g T_g + max_r V(r) + lambda_max(D+^1/2 P^H P D+^1/2), D+ = max(E_KB, 0)
  * (each term bounds its operator from above).  Synchronises.

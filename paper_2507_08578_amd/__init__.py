@@ -311,6 +311,45 @@ class Hamiltonian:
             self.ctx.check_status()
         return eig
 
+    @staticmethod
+    def _dvec(t, n, name):
+        import torch
+        if t is None:
+            return None
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and t.numel() >= n):
+            raise TypeError(f"{name} must be a contiguous float64 CUDA tensor of >= {n} elements")
+        return t.data_ptr()
+
+    def lobpcg(self, y, hy, eig, resid=None, nblock: int = 1, nline: int = 4, hist=None,
+               check=True):
+        """One block-LOBPCG pass in place (pw_lobpcg): y <- Ritz vectors, hy <- H y.
+        hist (optional): float64 tensor of (nline + 1) * nb Ritz values per line."""
+        p, ld = _block_args(y, self.npw, "y")
+        hp, ldh = _block_args(hy, self.npw, "hy")
+        nb = y.shape[0]
+        self.ctx.check(_LIB.pw_lobpcg(self.handle, nb, int(nblock), int(nline), p, ld, hp, ldh,
+                                      self._dvec(eig, nb, "eig"), self._dvec(resid, nb, "resid"),
+                                      self._dvec(hist, (int(nline) + 1) * nb, "hist")))
+        if check:
+            self.ctx.check_status()
+        return eig
+
+    def rmm_diis(self, y, hy, eig, resid=None, ndiis: int = 3, hy_valid=False, band_resid=None,
+                 check=True):
+        """One RMM-DIIS pass in place (pw_rmm_diis): y <- Ritz vectors, hy <- H y.
+        band_resid (optional): float64 tensor of (ndiis + 1) * nb relative residuals."""
+        p, ld = _block_args(y, self.npw, "y")
+        hp, ldh = _block_args(hy, self.npw, "hy")
+        nb = y.shape[0]
+        self.ctx.check(_LIB.pw_rmm_diis(self.handle, nb, int(ndiis), p, ld, hp, ldh,
+                                        int(bool(hy_valid)), self._dvec(eig, nb, "eig"),
+                                        self._dvec(resid, nb, "resid"),
+                                        self._dvec(band_resid, (int(ndiis) + 1) * nb, "band_resid")))
+        if check:
+            self.ctx.check_status()
+        return eig
+
     def upper_bound(self) -> float:
         b = ctypes.c_double()
         self.ctx.check(_LIB.pw_upper_bound(self.handle, ctypes.byref(b)))

@@ -66,6 +66,10 @@ SIGNATURES = {
     "pw_rayleigh_ritz": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                  c_void_p]),
     "pw_upper_bound": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
+    "pw_lobpcg": (c_int, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64,
+                          c_void_p, c_void_p, c_void_p]),
+    "pw_rmm_diis": (c_int, [c_void_p, c_int64, c_int32, c_void_p, c_int64, c_void_p, c_int64,
+                            c_int32, c_void_p, c_void_p, c_void_p]),
     "pw_gemm_cn": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,
                            c_void_p, c_int64, c_void_p, c_int64]),
     "pw_gemm_nn": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_double, c_void_p, c_int64,

@@ -5,7 +5,7 @@
 //   pw_cheb_filter    section 5.1 (Chebyshev filtering, textbook scaled recurrence)
 //   pw_orthonormalize section 5.4 (full-band Cholesky orthogonalisation)
 //   pw_rayleigh_ritz  section 5.1 (Rayleigh-Ritz subspace diagonalisation)
-#include "pw_internal.h"
+#include "pw_handles.h"
 
 #include <algorithm>
 #include <cmath>
@@ -17,90 +17,6 @@
 #include <vector>
 
 #define PW_VERSION "0.1.0"
-
-struct EventPair {
-  hipEvent_t a, b;
-  int stage;
-};
-
-struct pw_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  size_t lds_limit = 0;
-  int cus = 256;              // compute units of the device
-  bool timing = false;
-  std::vector<EventPair> pending;
-  std::vector<hipEvent_t> pool;
-  double acc_ms[PW_STAGE_COUNT] = {0};
-  int64_t launches[PW_STAGE_COUNT] = {0};
-  double* pinned = nullptr;   // small pinned host scratch (64 doubles)
-  // deferred status of the hot calls on the device: [0..2] = {status, op,
-  // info} of the first failure since the last pw_ctx_check, [4] = sweeps of
-  // the last dense eigensolve (-1: sweep limit reached)
-  int* rec_dev = nullptr;
-  int max_sweeps = 24;        // sweep limit of the block eigensolver in hot calls
-  int refs = 1;               // the caller's handle + one per live ham / batch
-
-  hipEvent_t get_event() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-};
-
-struct pw_ham {
-  pw_ctx* ctx = nullptr;
-  BoxPlan plan{};
-  FftLaunchCfg cfg{};
-  int64_t npw = 0, nproj = 0, nb_max = 0;
-  int64_t chunk = 0;         // bands per FFT launch (tunable, <= chunk_alloc)
-  int64_t chunk_alloc = 0;   // bands the FFT work buffer holds
-  int gemm_target = 4096;    // split-K target block count of the projector product (tunable;
-                             // the FP64 product caps it at 2048)
-  int nn_tile = 0;           // workgroup tile of the tall FP64 products P C, Y Q, Y U^-1 (tunable)
-  int nn_tile32 = 0;         // the same for the FP32 / BF16 product P C (tunable)
-  bool reg_col_ok = false, reg_plane_ok = false, narrow_ok = false, narrow32_ok = false;
-  bool ls32_ok = false;      // FP32 plane kernel with LDS exchanges (square P^2 planes)
-  std::vector<void*> allocs;
-  double* kin = nullptr;
-  double* vscaled = nullptr;
-  double vmax = 0.0, kmax = 0.0;
-  const cplx* proj = nullptr;
-  double* ekb_dev = nullptr;
-  std::vector<double> ekb;
-  cplx* T = nullptr;
-  cplx* cprj = nullptr;
-  cplx* gemm_work = nullptr;
-  cplx* blk = nullptr;
-  cplx* sub0 = nullptr;
-  cplx* sub1 = nullptr;
-  void* heev_work = nullptr;
-  int* status_dev = nullptr;
-  cplx* dinv = nullptr;     // inverses of the Cholesky diagonal blocks
-  cplx* panel = nullptr;    // kb x nb_max row panel
-  double* dtol = nullptr;   // pivot threshold
-  // low-precision filter path (allocated when desc->low_prec != 0)
-  bool low_prec = false;
-  float* kin32 = nullptr;
-  float* vs32 = nullptr;
-  float2* proj32 = nullptr;
-  uint16_t* proj3 = nullptr;   // proj32 as three bf16 terms, projector-contiguous (FP32 P C)
-  int kp3 = 0;
-  float2* T32 = nullptr;
-  float2* cprj32 = nullptr;
-  float2* work32 = nullptr;
-  float2* blk32[2] = {nullptr, nullptr};
-  // electron density (allocated by the first pw_density call)
-  double omega = 0.0;        // cell volume (2 pi)^3 / |det B|
-  double* rho_part = nullptr;
-  int rho_groups = 0;
-};
 
 struct BatchItem {
   pw_ham* h = nullptr;
@@ -144,7 +60,7 @@ struct pw_batch {
   int max_sweeps = 0;
 };
 
-namespace {
+namespace pwi {
 
 thread_local std::string g_err;
 
@@ -154,50 +70,11 @@ pw_status fail(pw_ctx* c, pw_status s, const std::string& msg) {
   return s;
 }
 
-#define HIPCHK(ctx, expr)                                                                    \
-  do {                                                                                       \
-    hipError_t e_ = (expr);                                                                  \
-    if (e_ != hipSuccess)                                                                    \
-      return fail((ctx), PW_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
-  } while (0)
-
-struct StageScope {
-  pw_ctx* c;
-  int stage;
-  hipEvent_t a = nullptr;
-  StageScope(pw_ctx* ctx, int st) : c(ctx), stage(st) {
-    if (c->timing) {
-      a = c->get_event();
-      if (a) (void)hipEventRecord(a, c->stream);
-    }
-  }
-  ~StageScope() {
-    if (c->timing && a) {
-      hipEvent_t b = c->get_event();
-      if (b) {
-        (void)hipEventRecord(b, c->stream);
-        c->pending.push_back({a, b, stage});
-      } else {
-        c->pool.push_back(a);
-      }
-    }
-  }
-};
-
-template <class T>
-pw_status dalloc(pw_ham* h, T** p, size_t count) {
-  *p = nullptr;
-  if (count == 0) return PW_OK;
-  void* q = nullptr;
-  hipError_t e = hipMalloc(&q, count * sizeof(T));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(h->ctx, PW_ERR_OOM,
-                "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
-  }
-  h->allocs.push_back(q);
-  *p = static_cast<T*>(q);
-  return PW_OK;
+void dfree(pw_ham* h, void* p) {
+  auto it = std::find(h->allocs.begin(), h->allocs.end(), p);
+  if (it == h->allocs.end()) return;
+  (void)hipFree(p);
+  h->allocs.erase(it);
 }
 
 void free_ham(pw_ham* h) {
@@ -208,7 +85,7 @@ void free_ham(pw_ham* h) {
 inline int center(int m, int n) { return m <= n / 2 ? m : m - n; }
 
 bool ranges_overlap(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t rows,
-                    int64_t cols, int64_t elem = (int64_t)sizeof(cplx)) {
+                    int64_t cols, int64_t elem) {
   const char* a0 = static_cast<const char*>(a);
   const char* a1 = a0 + ((cols - 1) * lda + rows) * elem;
   const char* b0 = static_cast<const char*>(b);
@@ -250,7 +127,7 @@ pw_status check_hot(pw_ham* h, pw_prec prec, int64_t nb) {
 // prev is read whenever it is non-null.
 pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* out, int64_t ldout,
                     double alpha, double beta, double gamma, const cplx* prev, int64_t ldprev,
-                    const double* coef = nullptr) {
+                    const double* coef) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
   if (h->nproj > 0) {
@@ -340,8 +217,6 @@ pw_status heev_status(pw_ctx* c, int sweeps) {
   return PW_OK;
 }
 
-// Hot calls that record a deferred status (pw_ctx_check names them).
-enum DeferredOp { kOpOrtho = 1, kOpRayleighRitz = 2, kOpLobpcg = 3, kOpRmmDiis = 4 };
 const char* op_name(int op) {
   switch (op) {
     case kOpOrtho: return "pw_orthonormalize";
@@ -351,7 +226,6 @@ const char* op_name(int op) {
   }
   return "a hot call";
 }
-int* sweeps_slot(pw_ctx* c) { return c->rec_dev + 4; }
 
 // Blocked upper Cholesky a = U^H U in place (upper triangle read; blocks
 // below the diagonal are left with scratch values).  dinv receives the
@@ -382,7 +256,7 @@ hipError_t chol_blocked(int64_t n, cplx* a, int64_t lda, cplx* dinv, cplx* panel
 // y <- y U^{-1} for a rows x n block (ld), by column blocks J:
 // y[:, J] = (y[:, J] - y[:, <J] U[<J, J]) U_JJ^{-1}.  tmp: rows x kb.
 hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* u, int64_t ldu,
-                      const cplx* dinv, cplx* tmp, hipStream_t s, int tile = 0) {
+                      const cplx* dinv, cplx* tmp, hipStream_t s, int tile) {
   const int kb = kCholBlock;
   hipError_t e = hipSuccess;
   for (int64_t j0 = 0; j0 < n && e == hipSuccess; j0 += kb) {
@@ -844,7 +718,8 @@ pw_status time_apply(pw_ham* h, pw_prec prec, int64_t nb, void* in, void* out, i
   *ms = v[v.size() / 2];
   return PW_OK;
 }
-}  // namespace
+}  // namespace pwi
+using namespace pwi;
 
 extern "C" {
 
