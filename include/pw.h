@@ -440,6 +440,21 @@ pw_status pw_gemm_nn(pw_ctx* ctx, int64_t m, int64_t n, int64_t k, double alpha_
  * NO_CONVERGENCE after 40 sweeps. */
 pw_status pw_heev(pw_ctx* ctx, int64_t n, void* a_dev, int64_t lda, double* w_dev,
                   void* q_dev, int64_t ldq);
+/*
+ * pw_heev for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same eigensolver and the same results as pw_heev, with its workspace
+ * in a static device array of 9 MiB that every call on the device shares
+ * (held by each GPU the library runs on until the process ends).  n <= 512
+ * (INVALID_ARG above); a is read only.  Does not allocate and does not
+ * synchronise: the sweep count goes to pw_ctx_last_sweeps and a sweep-limit
+ * failure (40 sweeps) to pw_ctx_check.  Calls that overlap on one device
+ * (from several contexts or streams) race on the shared array; calls on one
+ * context's stream are ordered and safe.
+ */
+pw_status pw_heev_noalloc(pw_ctx* ctx, int64_t n, const void* a_dev, int64_t lda, double* w_dev,
+                          void* q_dev, int64_t ldq);
+
 /* Upper Cholesky factor in place: a = U^H U (upper triangle of a read and
  * overwritten; strictly lower part set to 0); then ainv_dev (n x n, ldi)
  * receives U^{-1} (upper, zeros below), formed as I U^{-1} by the same

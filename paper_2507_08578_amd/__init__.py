@@ -149,6 +149,22 @@ class Context:
                                 Q.data_ptr(), Q.stride(0)))
         return w, Q
 
+    def heev_noalloc(self, A, w=None, Q=None, check=True):
+        """pw_heev_noalloc: the same eigensolver with its workspace in the
+        library's static device array (n <= 512).  w, Q: optional outputs
+        (float64 (n,), complex128 (n, n) CUDA tensors); A is not modified."""
+        import torch
+        n = A.shape[0]
+        if w is None:
+            w = torch.empty(n, dtype=torch.float64, device=A.device)
+        if Q is None:
+            Q = torch.empty((n, n), dtype=torch.complex128, device=A.device)
+        self.check(_LIB.pw_heev_noalloc(self.handle, n, A.data_ptr(), A.stride(0), w.data_ptr(),
+                                        Q.data_ptr(), Q.stride(0)))
+        if check:
+            self.check_status()
+        return w, Q
+
     def potrf_inv(self, S):
         """Upper Cholesky S = U^H U and U^{-1}, column-major tensors (n, n)."""
         import torch

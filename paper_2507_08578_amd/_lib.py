@@ -76,6 +76,7 @@ SIGNATURES = {
                            c_void_p, c_int64, c_double, c_void_p, c_int64]),
     "pw_heev": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int64]),
     "pw_potrf_inv": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64]),
+    "pw_heev_noalloc": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_int64]),
     "pw_ctx_set_timing": (c_int, [c_void_p, c_int]),
     "pw_ctx_stage_time": (c_int, [c_void_p, c_int, ctypes.POINTER(c_double),
                                   ctypes.POINTER(c_int64)]),

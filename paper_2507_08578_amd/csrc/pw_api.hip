@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -60,7 +61,34 @@ struct pw_batch {
   int max_sweeps = 0;
 };
 
+// Workspace of pw_heev_noalloc: one static device array per GPU, large
+// enough for the block-Jacobi work of a 512 x 512 problem.  Host code never
+// uses the symbol itself (on the host it is only a stand-in): pw_ctx_create
+// resolves each device's own address of it once, with that device current,
+// and every later use goes through that address.
+constexpr size_t kScratchBytes = (size_t)9 << 20;
+constexpr int kScratchHeevMax = 512;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace pwi {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved once per device).
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 thread_local std::string g_err;
 
@@ -223,6 +251,7 @@ const char* op_name(int op) {
     case kOpRayleighRitz: return "pw_rayleigh_ritz";
     case kOpLobpcg: return "pw_lobpcg";
     case kOpRmmDiis: return "pw_rmm_diis";
+    case kOpHeev: return "pw_heev_noalloc";
   }
   return "a hot call";
 }
@@ -781,7 +810,9 @@ pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
     return fail(nullptr, PW_ERR_OOM, "status word allocation failed");
   }
   c->rec_dev = static_cast<int*>(rec);
-  e = launch_fill_int(8, 0, c->rec_dev, c->stream);
+  e = scratch_address(device, &c->scratch);
+  if (e == hipSuccess && heev_work_bytes(kScratchHeevMax) > kScratchBytes) e = hipErrorInvalidValue;
+  if (e == hipSuccess) e = launch_fill_int(8, 0, c->rec_dev, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess) e = fft_set_lds_limits(c->lds_limit);
   if (e == hipSuccess) e = fft_reg_set_lds_limits(c->lds_limit);
@@ -1778,6 +1809,26 @@ pw_status pw_heev(pw_ctx* c, int64_t n, void* a, int64_t lda, double* w, void* q
   free_ham(&tmp);
   if (e != hipSuccess) return fail(c, PW_ERR_HIP, hipGetErrorString(e));
   return heev_status(c, sweeps);
+}
+
+pw_status pw_heev_noalloc(pw_ctx* c, int64_t n, const void* a, int64_t lda, double* w, void* q,
+                          int64_t ldq) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (n < 1 || !a || !w || !q || lda < n || ldq < n)
+    return fail(c, PW_ERR_INVALID_ARG, "pw_heev_noalloc: bad sizes or pointers");
+  if (n > kScratchHeevMax || heev_work_bytes(n) > kScratchBytes)
+    return fail(c, PW_ERR_INVALID_ARG,
+                "pw_heev_noalloc: n = " + std::to_string(n) + " exceeds its static workspace (n <= " +
+                    std::to_string(kScratchHeevMax) + ")");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  {
+    StageScope sc(c, PW_STAGE_EIGH);
+    HIPCHK(c, launch_heev_async(n, static_cast<const cplx*>(a), lda, w, static_cast<cplx*>(q), ldq,
+                                c->scratch, sweeps_slot(c), kHeevMaxSweeps, s));
+    HIPCHK(c, launch_status_record(nullptr, sweeps_slot(c), kOpHeev, c->rec_dev, s));
+  }
+  return PW_OK;
 }
 
 pw_status pw_potrf_inv(pw_ctx* c, int64_t n, void* a, int64_t lda, void* ainv, int64_t ldi) {

@@ -30,6 +30,7 @@ struct pw_ctx {
   // the last dense eigensolve (-1: sweep limit reached)
   int* rec_dev = nullptr;
   int max_sweeps = 24;        // sweep limit of the block eigensolver in hot calls
+  void* scratch = nullptr;    // this device's address of the static workspace of pw_heev_noalloc
   int refs = 1;               // the caller's handle + one per live ham / batch
 
   hipEvent_t get_event() {
@@ -198,7 +199,7 @@ pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* o
                     const double* coef = nullptr);
 pw_status rotate_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, const cplx* m);
 // Hot calls that record a deferred status (pw_ctx_check names them).
-enum DeferredOp { kOpOrtho = 1, kOpRayleighRitz = 2, kOpLobpcg = 3, kOpRmmDiis = 4 };
+enum DeferredOp { kOpOrtho = 1, kOpRayleighRitz = 2, kOpLobpcg = 3, kOpRmmDiis = 4, kOpHeev = 5 };
 const char* op_name(int op);
 inline int* sweeps_slot(pw_ctx* c) { return c->rec_dev + 4; }
 hipError_t chol_blocked(int64_t n, cplx* a, int64_t lda, cplx* dinv, cplx* panel, double* tol,
