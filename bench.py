@@ -14,10 +14,14 @@ JSON line for the mixed path with the FP64 figures and the Ritz-value
 difference between the two trajectories beside it.
 
   value        band*H*psi applications per second over the timed steps
-  ms_per_step  filter-iteration time
+  ms_per_step  filter-iteration time (no stage events in the timed steps)
   roofline     dominant kernel vs its roofline, from HIP events recorded by
-               the library on its own stream over the timed steps
+               the library on its own stream over a few further steps
   cpu_baseline the FP64 oracle's H*psi timed on the host on a band sample
+
+Beside the headline the same line carries the FP64 path (with its own
+roofline), LOBPCG and RMM-DIIS passes on the same block, the electron
+density, and (default C5 run) the batched C2 (FP64) and C4 (mixed) forms.
 """
 from __future__ import annotations
 
@@ -213,16 +217,39 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
             "per_launch": f"{per_band:.4g} B/band x {bands_per_launch:.0f} bands"}
 
 
+def host_cpu():
+    """CPU model string and the threads the oracle uses: BLAS threads for
+    its matrix products, scipy.fft workers (every CPU the OS reports) for
+    its transforms."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        blas_threads = max([p.get("num_threads", 1) for p in blas] or [1])
+    except Exception:
+        blas_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    fft_workers = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:
+        affinity = fft_workers
+    return {"cpu_model": model, "blas_threads": int(blas_threads), "fft_workers": int(fft_workers),
+            "cpus_allowed": int(affinity)}
+
+
 def cpu_baseline(w, nb_sample, seed=0):
     """Oracle H*psi on nb_sample bands of the same workload, timed on the host."""
     import oracle
     import synth
-    try:
-        from threadpoolctl import threadpool_info
-        blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
-        threads = max([p.get("num_threads", 1) for p in blas] or [1])
-    except Exception:
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    hc = host_cpu()
+    threads = min(max(hc["blas_threads"], hc["fft_workers"]), hc["cpus_allowed"])
     oh = oracle.OracleHam.from_workload(w)
     X = synth.start_block(w.npw, nb_sample, seed).T
     oracle.apply_h(oh, X[:, :1])                 # first-touch
@@ -231,7 +258,7 @@ def cpu_baseline(w, nb_sample, seed=0):
     dt = time.perf_counter() - t0
     return {"value": nb_sample / dt, "unit": UNIT, "cores": int(threads), "kind": "oracle",
             "sample": f"{nb_sample} bands of one FP64 oracle H*psi on {w.name} "
-                      f"(numpy FFT + BLAS), {dt:.2f} s"}
+                      f"(scipy FFT + BLAS), {dt:.2f} s", **hc}
 
 
 def density_leg(ctx, ham, w, X0, steps, warmup, config=None):
@@ -293,37 +320,42 @@ def cpu_density_baseline(w, nb_sample, seed=0):
     t0 = time.perf_counter()
     oracle.density(oh, X, wt)
     dt = time.perf_counter() - t0
-    return {"value": nb_sample / dt, "unit": "band densities/s", "cores": 1, "kind": "oracle",
+    hc = host_cpu()
+    return {"value": nb_sample / dt, "unit": "band densities/s",
+            "cores": min(hc["fft_workers"], hc["cpus_allowed"]), "kind": "oracle",
             "sample": f"{nb_sample} bands of the FP64 oracle density on {w.name} "
-                      f"(numpy FFT, one thread), {dt:.2f} s"}
+                      f"(scipy FFT on all workers), {dt:.2f} s", **hc}
 
 
-def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup):
-    """Iteration 0 + warmup + timed steps from X0; returns timings and the last Ritz values."""
+def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup, stage_steps):
+    """Iteration 0 + warmup + timed steps from X0 (no stage events in the timed
+    steps), then stage_steps more steps with per-stage HIP events for the
+    roofline.  The only host reads per step are the deferred status and the
+    Ritz values (and the eigensolver's sweep count)."""
     import torch
     nb = w.nb
     Y = X0.clone()
     HY = torch.empty_like(Y)
     eig = torch.empty(nb, dtype=torch.float64, device="cuda")
     resid = torch.empty(nb, dtype=torch.float64, device="cuda")
-    ham.orthonormalize(Y)
-    ham.rayleigh_ritz(Y, HY, eig, resid)
+    ham.orthonormalize(Y, check=False)
+    ham.rayleigh_ritz(Y, HY, eig, resid, check=False)
+    ctx.check_status()
     lam = eig.cpu()
     sweeps = []
 
     def step():
         nonlocal lam
         ham.cheb_filter(Y, w.degree, float(lam[-1]), b, float(lam[0]), hx=HY, prec=prec)
-        ham.orthonormalize(Y)
-        ham.rayleigh_ritz(Y, HY, eig, resid)
-        sweeps.append(ctx.last_sweeps())
+        ham.orthonormalize(Y, check=False)
+        ham.rayleigh_ritz(Y, HY, eig, resid, check=False)
+        ctx.check_status()
         lam = eig.cpu()
+        sweeps.append(ctx.last_sweeps())
 
     for i in range(warmup):
         step()
         log(f"{prec}: warmup {i + 1}/{warmup} done")
-    ctx.set_timing(True)
-    ctx.reset_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -331,12 +363,82 @@ def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup):
         log(f"{prec}: step {i + 1}/{steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ctx.set_timing(True)
+    ctx.reset_timing()
+    for i in range(stage_steps):
+        step()
+    torch.cuda.synchronize()
     stages = ctx.stage_times()
     ctx.set_timing(False)
+    log(f"{prec}: {stage_steps} stage-timed steps done")
     applies = w.degree                       # (degree - 1) filter products + 1 in Rayleigh-Ritz
     return {"ms_per_step": 1e3 * dt / steps, "value": applies * nb * steps / dt,
-            "stages": stages, "applies": applies, "lam": lam.numpy().copy(),
-            "max_resid": float(resid.max().cpu()), "sweeps": sweeps}
+            "stages": stages, "stage_steps": stage_steps, "applies": applies,
+            "lam": lam.numpy().copy(), "max_resid": float(resid.max().cpu()), "sweeps": sweeps,
+            "Y": Y, "HY": HY}
+
+
+def lobpcg_leg(ctx, ham, w, X0, passes, nblock=4, nline=4):
+    """Block LOBPCG (pw_lobpcg; the paper's run settings nblock_lobpcg = 4,
+    nline = 4) from the random start block: one untimed pass (allocates the
+    solver's workspace), then `passes` timed passes continuing the same
+    iteration.  H*psi applications per pass: nb (nline + 1)."""
+    import torch
+    nb = w.nb
+    Y = X0.clone()
+    HY = torch.empty_like(Y)
+    eig = torch.empty(nb, dtype=torch.float64, device="cuda")
+    res = torch.empty_like(eig)
+    ham.lobpcg(Y, HY, eig, res, nblock=nblock, nline=nline)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(passes):
+        ham.lobpcg(Y, HY, eig, res, nblock=nblock, nline=nline, check=False)
+        ctx.check_status()
+        log(f"lobpcg: pass {i + 1}/{passes} done")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / passes
+    ctx.set_timing(True)
+    ctx.reset_timing()
+    ham.lobpcg(Y, HY, eig, res, nblock=nblock, nline=nline)
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    applies = nb * (nline + 1)
+    return {"ms_per_pass": 1e3 * dt, "value": applies / dt, "unit": UNIT,
+            "nblock": nblock, "nline": nline, "applies_per_pass": applies,
+            "max_resid": float(res.max().cpu()), "lowest_ritz_Ha": float(eig[0].cpu()),
+            "stages_ms_per_pass": {k: v[0] for k, v in st.items() if v[1]}}
+
+
+def rmm_leg(ctx, ham, w, Y0, HY0, passes, ndiis=3):
+    """RMM-DIIS (pw_rmm_diis) from the Ritz vectors the FP64 filter path left
+    (H Y carried in): `passes` timed passes; H*psi applications per pass:
+    nb ndiis.  Residuals before and after say what the passes bought."""
+    import torch
+    nb = w.nb
+    Y, HY = Y0.clone(), HY0.clone()
+    eig = torch.empty(nb, dtype=torch.float64, device="cuda")
+    res = torch.empty_like(eig)
+    before = None
+    # one untimed pass allocates the solver's workspace
+    Yw, HYw = Y.clone(), HY.clone()
+    ham.rmm_diis(Yw, HYw, eig, res, ndiis=ndiis, hy_valid=True)
+    del Yw, HYw
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(passes):
+        ham.rmm_diis(Y, HY, eig, res, ndiis=ndiis, hy_valid=True, check=False)
+        ctx.check_status()
+        if before is None:
+            before = float(res.max().cpu())
+        log(f"rmm-diis: pass {i + 1}/{passes} done")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / passes
+    applies = nb * ndiis
+    return {"ms_per_pass": 1e3 * dt, "value": applies / dt, "unit": UNIT, "ndiis": ndiis,
+            "applies_per_pass": applies, "max_resid_after_first_pass": before,
+            "max_resid_after_last_pass": float(res.max().cpu()),
+            "start": "Ritz vectors and H Y of the FP64 filter path's last iteration"}
 
 
 def batch_roofline(stages, items, prec, degree):
@@ -375,8 +477,22 @@ def batch_roofline(stages, items, prec, degree):
 
 
 def run_batch(args):
+    print(json.dumps(batch_leg(args.config, args.precision, args.steps, args.warmup, args.streams,
+                               args.graph, args.no_autotune, args.no_compare,
+                               args.no_cpu_baseline, args.cpu_bands)), flush=True)
+
+
+def batch_leg(config, precision, steps, warmup, streams=8, graph="fused", no_autotune=False,
+              no_compare=False, no_cpu_baseline=False, cpu_bands=0):
     """C2 / C4: all items in one pw_batch (graph replays), against the plain
-    FP64 per-item path (host-driven iterations, one item after another)."""
+    FP64 per-item path (host-driven iterations, one item after another).
+    The roofline comes from one more iteration of the same fused launches
+    issued without the graph, each stage timed with HIP events."""
+    import argparse as _ap
+    args = _ap.Namespace(config=config, precision=precision, steps=steps, warmup=warmup,
+                         streams=streams, graph=graph, no_autotune=no_autotune,
+                         no_compare=no_compare, no_cpu_baseline=no_cpu_baseline,
+                         cpu_bands=cpu_bands)
     import numpy as np
     import torch
     import synth
@@ -420,13 +536,16 @@ def run_batch(args):
     lam_batch = bt.eigenvalues()
     sweeps = bt.max_sweeps()
     max_resid = max(float(r.max().cpu()) for r in bt.resid)
-    # one directly issued, stage-timed iteration for the roofline
+    # one more iteration of the timed launches issued without the graph, stage-timed
     ctx.set_timing(True)
     ctx.reset_timing()
-    bt.iterate(1, graph=False)
+    bt.iterate(1, graph="fused_direct" if gmode == "fused" else False)
     stages = ctx.stage_times()
     ctx.set_timing(False)
     roof = batch_roofline(stages, list(zip(ws, hams)), args.precision, degree)
+    roof["timed_launches"] = ("the fused launches (one per stage for all items of a box), "
+                              "issued directly with per-stage HIP events"
+                              if gmode == "fused" else "per-item kernels issued directly")
     value = bands * degree * args.steps / dt
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -467,8 +586,9 @@ def run_batch(args):
             for st in states:
                 h, Y, HY, eig, res, lam, b = st
                 h.cheb_filter(Y, degree, float(lam[-1]), b, float(lam[0]), hx=HY)
-                h.orthonormalize(Y)
-                h.rayleigh_ritz(Y, HY, eig, res)
+                h.orthonormalize(Y, check=False)
+                h.rayleigh_ritz(Y, HY, eig, res, check=False)
+                ctx.check_status()
                 st[5] = eig.cpu()
 
         for _ in range(args.warmup):
@@ -487,7 +607,7 @@ def run_batch(args):
         out["eig_diff_vs_fp64_Ha"] = d
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_items(ws, args.cpu_bands or 32)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def cpu_baseline_items(ws, nb_each, min_s=10.0, max_reps=10000):
@@ -495,12 +615,8 @@ def cpu_baseline_items(ws, nb_each, min_s=10.0, max_reps=10000):
     pass over all items is repeated until at least min_s seconds have run."""
     import oracle
     import synth
-    try:
-        from threadpoolctl import threadpool_info
-        blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
-        threads = max([p.get("num_threads", 1) for p in blas] or [1])
-    except Exception:
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    hc = host_cpu()
+    threads = min(max(hc["blas_threads"], hc["fft_workers"]), hc["cpus_allowed"])
     hs = [oracle.OracleHam.from_workload(w) for w in ws]
     Xs = [synth.start_block(w.npw, min(nb_each, w.nb), 7).T for w in ws]
     oracle.apply_h(hs[0], Xs[0][:, :1])
@@ -516,7 +632,7 @@ def cpu_baseline_items(ws, nb_each, min_s=10.0, max_reps=10000):
             break
     return {"value": n / dt, "unit": UNIT, "cores": int(threads), "kind": "oracle",
             "sample": f"{reps} passes of one FP64 oracle H*psi on {min(nb_each, max(w.nb for w in ws))}"
-                      f" bands of each of the {len(ws)} items ({n} band applies), {dt:.1f} s"}
+                      f" bands of each of the {len(ws)} items ({n} band applies), {dt:.1f} s", **hc}
 
 
 def calibrate_copy(nbytes=1 << 30, reps=3):
@@ -552,6 +668,12 @@ def main():
                     help="keep the default launch shapes instead of timing alternatives")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--stage-steps", type=int, default=3,
+                    help="extra stage-timed steps after the timed ones (roofline, stage split)")
+    ap.add_argument("--no-solvers", action="store_true",
+                    help="skip the LOBPCG and RMM-DIIS legs")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched C2 / C4 legs of the default run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
@@ -587,13 +709,15 @@ def main():
         log(f"autotune {prec}: {r}")
 
     tune(args.precision)
-    res = run_path(pw, ctx, ham, w, X0, b, args.precision, args.steps, args.warmup)
+    ss = max(1, args.stage_steps)
+    res = run_path(pw, ctx, ham, w, X0, b, args.precision, args.steps, args.warmup, ss)
     # (before the FP64 run retunes the handle: the roofline names the kernels just timed)
-    roof = roofline(res["stages"], args.steps, w, ham, nb, args.precision, args.config)
+    roof = roofline(res["stages"], ss, w, ham, nb, args.precision, args.config)
     ref = None
     if mixed and not args.no_compare:
         tune("fp64")
-        ref = run_path(pw, ctx, ham, w, X0, b, "fp64", args.steps, args.warmup)
+        ref = run_path(pw, ctx, ham, w, X0, b, "fp64", args.steps, args.warmup, ss)
+        ref_roof = roofline(ref["stages"], ss, w, ham, nb, "fp64", args.config)
     dtype = "f64" if not mixed else ("f32+f64" if args.precision == "fp32" else "bf16/f32+f64")
     out = {
         "metric": METRIC, "value": res["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -607,16 +731,26 @@ def main():
         "max_resid": res["max_resid"],
         "eigensolver_sweeps": res["sweeps"],
         "roofline": roof,
-        "stages_ms_per_step": {k: v[0] / args.steps for k, v in res["stages"].items()},
+        "stages_ms_per_step": {k: v[0] / ss for k, v in res["stages"].items()},
+        "stage_timing": f"{ss} further steps with per-stage HIP events after the timed steps "
+                        "(the timed steps record no events)",
         "autotune": tunings or None,
     }
     if ref is not None:
         d = float(abs(res["lam"] - ref["lam"]).max())
         out["fp64_path"] = {"ms_per_step": ref["ms_per_step"], "value": ref["value"],
                             "speedup_mixed_over_fp64": ref["ms_per_step"] / res["ms_per_step"],
-                            "stages_ms_per_step": {k: v[0] / args.steps
+                            "max_resid": ref["max_resid"], "roofline": ref_roof,
+                            "stages_ms_per_step": {k: v[0] / ss
                                                    for k, v in ref["stages"].items()}}
         out["eig_diff_vs_fp64_Ha"] = d
+    if not args.no_solvers:
+        log("LOBPCG")
+        out["lobpcg"] = lobpcg_leg(ctx, ham, w, X0, passes=2 if args.config == "C5" else 4)
+        src = ref if ref is not None else res
+        log("RMM-DIIS")
+        out["rmm_diis"] = rmm_leg(ctx, ham, w, src["Y"], src["HY"], passes=3)
+        out["rmm_diis"]["chfsi_fp64_iteration_ms"] = src["ms_per_step"]
     if not args.no_density:
         log("electron density")
         out["density"] = density_leg(ctx, ham, w, X0, args.steps, args.warmup, args.config)
@@ -627,6 +761,17 @@ def main():
         nbs = args.cpu_bands or {"C1": 2048, "C3": 64, "C5": 160}[args.config]
         log(f"cpu baseline: oracle H*psi on {nbs} bands")
         out["cpu_baseline"] = cpu_baseline(w, nbs)
+    if args.config == "C5" and not args.no_batched:
+        # the batched forms, measured by every default run (each its own line's
+        # fields; the headline above is C5)
+        del res, ref
+        ham.close()
+        torch.cuda.empty_cache()
+        out["batched"] = {}
+        for cfg, prec in (("C2", "fp64"), ("C4", "fp32")):
+            log(f"batched leg {cfg} ({prec})")
+            out["batched"][cfg] = batch_leg(cfg, prec, min(args.steps, 10), max(1, args.warmup),
+                                            no_cpu_baseline=args.no_cpu_baseline, cpu_bands=16)
     print(json.dumps(out), flush=True)
 
 

@@ -403,17 +403,19 @@ pw_status pw_batch_start(pw_batch* b);
  * 3: fused — items with the same FFT box share every launch (one kernel per
  * stage for the whole group, the items' sizes and buffers read from device
  * descriptors; needs each handle's FFT buffer to hold all nb bands), one
- * graph replayed; 0: issue the per-item kernels directly on the batch's
- * streams.  Graphs are captured on first use.  All modes compute the same
+ * graph replayed; 4: the launches of mode 3 issued directly, without a
+ * graph (with stage timing on, each stage is timed on its group's stream);
+ * 0: issue the per-item kernels directly on the batch's streams.  Graphs
+ * are captured on first use.  All modes compute the same
  * arithmetic item by item.  Ordered after prior work on the
  * context's stream and before later work on it.  Synchronises once at the
  * end and returns PW_ERR_NOT_POSDEF (Cholesky pivot), PW_ERR_NO_CONVERGENCE
  * (eigensolver sweep limit) or PW_ERR_INVALID_ARG (Ritz values not inside
  * a0 < a < b: that item's filter became the identity) for the first item
  * that failed in any of the iterations; pw_last_error names it.
- * With stage timing on, directly issued iterations are timed per stage on
- * the branch streams (kernels of concurrent branches overlap, so stage sums
- * exceed wall time); graph replays are not timed.
+ * With stage timing on, directly issued iterations (modes 0 and 4) are
+ * timed per stage on the branch streams (kernels of concurrent branches
+ * overlap, so stage sums can exceed wall time); graph replays are not timed.
  */
 pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph);
 /* Largest number of Jacobi sweeps any item used in the last start/iterate. */

@@ -464,8 +464,11 @@ class Batch:
     def iterate(self, iters: int = 1, graph=True):
         """graph: True / "single" (one graph, a branch per stream), "per_stream"
         (one graph per branch stream), "fused" (one launch per stage for all
-        items of a box, replayed from a graph), False (kernels issued directly)."""
-        mode = {True: 1, "single": 1, "per_stream": 2, "fused": 3, False: 0}[graph]
+        items of a box, replayed from a graph), "fused_direct" (the same
+        launches issued without a graph; stage-timed when timing is on),
+        False (per-item kernels issued directly)."""
+        mode = {True: 1, "single": 1, "per_stream": 2, "fused": 3, "fused_direct": 4,
+                False: 0}[graph]
         self.ctx.check(_LIB.pw_batch_iterate(self.handle, int(iters), mode))
 
     def max_sweeps(self) -> int:

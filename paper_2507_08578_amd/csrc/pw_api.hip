@@ -597,7 +597,9 @@ pw_status fused_apply(pw_ctx* c, const pw_batch::Group& g, int prec, int in, int
                       double alpha, double beta, double gamma, int coef_step, hipStream_t s) {
   const bool lp = prec != PW_FP64;
   const int bf16 = prec == PW_BF16;
+  const int lps = lp ? PW_STAGE_FFT_COL_INV_LP - PW_STAGE_FFT_COL_INV : 0;
   if (g.nproj_max > 0) {
+    StageScope sc(c, PW_STAGE_PROJ + lps);
     if (lp)
       HIPCHK(c, launch_fused_gemm_cn32(bf16, g.nitems, g.nproj_max, g.nb_max, g.nsplit_proj32, g.D,
                                        in, alpha, coef_step, s));
@@ -605,10 +607,20 @@ pw_status fused_apply(pw_ctx* c, const pw_batch::Group& g, int prec, int in, int
       HIPCHK(c, launch_fused_gemm_cn(g.nitems, g.nproj_max, g.nb_max, g.nsplit_proj, g.D, GOP_PROJ,
                                      in, alpha, coef_step, s));
   }
-  HIPCHK(c, launch_fused_col_inv(g.f, lp, g.D, in, s));
-  HIPCHK(c, launch_fused_plane(g.f, lp, g.D, s));
-  HIPCHK(c, launch_fused_col_fwd(g.f, lp, g.D, in, out, prev, alpha, beta, gamma, coef_step, s));
+  {
+    StageScope sc(c, PW_STAGE_FFT_COL_INV + lps);
+    HIPCHK(c, launch_fused_col_inv(g.f, lp, g.D, in, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_FFT_PLANE + lps);
+    HIPCHK(c, launch_fused_plane(g.f, lp, g.D, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_FFT_COL_FWD + lps);
+    HIPCHK(c, launch_fused_col_fwd(g.f, lp, g.D, in, out, prev, alpha, beta, gamma, coef_step, s));
+  }
   if (g.nproj_max > 0) {
+    StageScope sc(c, PW_STAGE_NONLOCAL + lps);
     if (lp) HIPCHK(c, launch_fused_gemm_nn32(bf16, g.nitems, g.npw_max, g.nb_max, g.D, out, s));
     else HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_NONLOCAL, 0, out, s));
   }
@@ -643,36 +655,61 @@ pw_status fused_iteration(pw_batch* b, const pw_batch::Group& g, hipStream_t s) 
     HIPCHK(c, launch_fused_dense(FS_TO_F64, g.nitems, ew, g.nb_max, g.D, buf[m & 1], 0, s));
   }
   // Cholesky orthonormalisation (one diagonal block: nb <= 64)
-  HIPCHK(c, launch_fused_gemm_cn(g.nitems, g.nb_max, g.nb_max, g.nsplit_gram, g.D, GOP_GRAM, SEL_Y,
-                                 1.0, -1, s));
-  HIPCHK(c, launch_fused_dense(FS_HERMITIZE, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
-  HIPCHK(c, launch_fused_dense(FS_CHOL_INIT, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
-  HIPCHK(c, launch_fused_dense(FS_CHOL_DIAG, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
-  HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_TRSM, 0, 0, s));
-  HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_Y, s));
+  {
+    StageScope sc(c, PW_STAGE_GRAM);
+    HIPCHK(c, launch_fused_gemm_cn(g.nitems, g.nb_max, g.nb_max, g.nsplit_gram, g.D, GOP_GRAM, SEL_Y,
+                                   1.0, -1, s));
+    HIPCHK(c, launch_fused_dense(FS_HERMITIZE, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_CHOL);
+    HIPCHK(c, launch_fused_dense(FS_CHOL_INIT, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+    HIPCHK(c, launch_fused_dense(FS_CHOL_DIAG, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_ROTATE);
+    HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_TRSM, 0, 0, s));
+    HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_Y, s));
+  }
   // Rayleigh-Ritz, FP64
   if ((st = fused_apply(c, g, PW_FP64, SEL_Y, SEL_HY, SEL_NONE, 1.0, 0.0, 0.0, -1, s)) != PW_OK)
     return st;
-  HIPCHK(c, launch_fused_gemm_cn(g.nitems, g.nb_max, g.nb_max, g.nsplit_gram, g.D, GOP_GRAM, SEL_HY,
-                                 1.0, -1, s));
-  HIPCHK(c, launch_fused_dense(FS_HERMITIZE, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
-  HIPCHK(c, launch_fused_dense(FS_JACOBI, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
-  HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_ROT, SEL_Y, 0, s));
-  HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_Y, s));
-  HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_ROT, SEL_HY, 0, s));
-  HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_HY, s));
-  HIPCHK(c, launch_fused_dense(FS_RESIDUALS, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
-  HIPCHK(c, launch_fused_dense(FS_FLAGS, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  {
+    StageScope sc(c, PW_STAGE_GRAM);
+    HIPCHK(c, launch_fused_gemm_cn(g.nitems, g.nb_max, g.nb_max, g.nsplit_gram, g.D, GOP_GRAM, SEL_HY,
+                                   1.0, -1, s));
+    HIPCHK(c, launch_fused_dense(FS_HERMITIZE, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_EIGH);
+    HIPCHK(c, launch_fused_dense(FS_JACOBI, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_ROTATE);
+    HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_ROT, SEL_Y, 0, s));
+    HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_Y, s));
+    HIPCHK(c, launch_fused_gemm_nn(g.nitems, g.npw_max, g.nb_max, g.D, GOP_ROT, SEL_HY, 0, s));
+    HIPCHK(c, launch_fused_dense(FS_COPY, g.nitems, ew, g.nb_max, g.D, SEL_BLK, SEL_HY, s));
+  }
+  {
+    StageScope sc(c, PW_STAGE_MISC);
+    HIPCHK(c, launch_fused_dense(FS_RESIDUALS, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+    HIPCHK(c, launch_fused_dense(FS_FLAGS, g.nitems, ew, g.nb_max, g.D, 0, 0, s));
+  }
   return PW_OK;
 }
 
 // All groups, forked over the batch streams and joined back.
-pw_status fused_issue(pw_batch* b) {
+// With stage timing on and not capturing, every stage is bracketed by HIP
+// events on its group's stream.
+pw_status fused_issue(pw_batch* b, bool capturing) {
   pw_status st;
   if ((st = batch_fork(b)) != PW_OK) return st;
-  for (size_t gi = 0; gi < b->groups.size(); ++gi)
-    if ((st = fused_iteration(b, b->groups[gi], b->streams[gi % b->streams.size()])) != PW_OK)
-      return st;
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    hipStream_t gs = b->streams[gi % b->streams.size()];
+    StreamSwap sw(b->ctx, gs, capturing);
+    if ((st = fused_iteration(b, b->groups[gi], gs)) != PW_OK) return st;
+  }
   return batch_join(b);
 }
 
@@ -1679,8 +1716,8 @@ pw_status pw_batch_start(pw_batch* b) {
 pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
   if (!b) return fail(nullptr, PW_ERR_INVALID_ARG, "batch is NULL");
   if (iters < 0) return fail(b->ctx, PW_ERR_INVALID_ARG, "iters < 0");
-  if (use_graph < 0 || use_graph > 3)
-    return fail(b->ctx, PW_ERR_INVALID_ARG, "use_graph must be 0, 1, 2 or 3");
+  if (use_graph < 0 || use_graph > 4)
+    return fail(b->ctx, PW_ERR_INVALID_ARG, "use_graph must be in [0, 4]");
   pw_ctx* c = b->ctx;
   pw_status st;
   if ((st = batch_enter(b)) != PW_OK) return st;
@@ -1716,10 +1753,10 @@ pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
       HIPCHK(c, hipGraphInstantiateWithFlags(&b->sexec[k], g, 0));
     }
   }
+  if (use_graph >= 3 && b->groups.empty() && (st = fused_setup(b)) != PW_OK) return st;
   if (use_graph == 3 && !b->fexec) {
-    if ((st = fused_setup(b)) != PW_OK) return st;
     HIPCHK(c, hipStreamBeginCapture(b->s0, hipStreamCaptureModeThreadLocal));
-    st = fused_issue(b);
+    st = fused_issue(b, true);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->s0, &g);
     if (st != PW_OK) {
@@ -1736,6 +1773,8 @@ pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
   for (int32_t t = 0; t < iters; ++t) {
     if (use_graph == 3) {
       HIPCHK(c, hipGraphLaunch(b->fexec, b->s0));
+    } else if (use_graph == 4) {
+      if ((st = fused_issue(b, false)) != PW_OK) return st;
     } else if (use_graph == 1) {
       HIPCHK(c, hipGraphLaunch(b->exec, b->s0));
     } else if (use_graph == 2) {

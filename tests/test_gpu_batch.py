@@ -179,14 +179,22 @@ def test_fused_equals_per_item_kernels(pw, ctx, cfg, prec):
     lp = prec != "fp64"
     X0 = [to_dev(synth.start_block(w.npw, w.nb, 700 + i)) for i, w in enumerate(ws)]
     res = {}
-    for mode in ("fused", False):
+    for mode in ("fused", "fused_direct", False):
         hams = [pw.Hamiltonian.from_workload(ctx, w, nb_max=w.nb, low_prec=lp) for w in ws]
         bt = pw.Batch(ctx, hams, X0, degree=8, filter_prec=prec, nstreams=4)
         bt.start()
+        if mode == "fused_direct":          # stage-timed direct issue of the fused launches
+            ctx.set_timing(True)
+            ctx.reset_timing()
         bt.iterate(3, graph=mode)
+        if mode == "fused_direct":
+            st = ctx.stage_times()
+            ctx.set_timing(False)
+            assert st["fft_plane_lp" if lp else "fft_plane"][1] > 0 and st["eigh"][1] > 0
         res[mode] = ([to_host(e) for e in bt.eig], [to_host(y) for y in bt.Y],
                      [to_host(r) for r in bt.resid])
-    for i in range(len(ws)):
-        assert np.array_equal(res["fused"][0][i], res[False][0][i]), i
-        assert np.array_equal(res["fused"][1][i], res[False][1][i]), i
-        assert np.array_equal(res["fused"][2][i], res[False][2][i]), i
+    for mode in ("fused", "fused_direct"):
+        for i in range(len(ws)):
+            assert np.array_equal(res[mode][0][i], res[False][0][i]), (mode, i)
+            assert np.array_equal(res[mode][1][i], res[False][1][i]), (mode, i)
+            assert np.array_equal(res[mode][2][i], res[False][2][i]), (mode, i)
