@@ -327,7 +327,7 @@ def cpu_density_baseline(w, nb_sample, seed=0):
                       f"(scipy FFT on all workers), {dt:.2f} s", **hc}
 
 
-def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup, stage_steps):
+def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup, stage_steps, gram_prec="fp64"):
     """Iteration 0 + warmup + timed steps from X0 (no stage events in the timed
     steps), then stage_steps more steps with per-stage HIP events for the
     roofline.  The only host reads per step are the deferred status and the
@@ -344,23 +344,28 @@ def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup, stage_steps):
     lam = eig.cpu()
     sweeps = []
 
+    it = [0]
+
     def step():
         nonlocal lam
-        ham.cheb_filter(Y, w.degree, float(lam[-1]), b, float(lam[0]), hx=HY, prec=prec)
-        ham.orthonormalize(Y, check=False)
+        it[0] += 1
+        fp = prec(it[0]) if callable(prec) else prec
+        ham.cheb_filter(Y, w.degree, float(lam[-1]), b, float(lam[0]), hx=HY, prec=fp)
+        ham.orthonormalize(Y, gram_prec=gram_prec, check=False)
         ham.rayleigh_ritz(Y, HY, eig, resid, check=False)
         ctx.check_status()
         lam = eig.cpu()
         sweeps.append(ctx.last_sweeps())
 
+    name = "ladder" if callable(prec) else prec
     for i in range(warmup):
         step()
-        log(f"{prec}: warmup {i + 1}/{warmup} done")
+        log(f"{name}: warmup {i + 1}/{warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         step()
-        log(f"{prec}: step {i + 1}/{steps} done")
+        log(f"{name}: step {i + 1}/{steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.set_timing(True)
@@ -370,7 +375,7 @@ def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup, stage_steps):
     torch.cuda.synchronize()
     stages = ctx.stage_times()
     ctx.set_timing(False)
-    log(f"{prec}: {stage_steps} stage-timed steps done")
+    log(f"{name}: {stage_steps} stage-timed steps done")
     applies = w.degree                       # (degree - 1) filter products + 1 in Rayleigh-Ritz
     return {"ms_per_step": 1e3 * dt / steps, "value": applies * nb * steps / dt,
             "stages": stages, "stage_steps": stage_steps, "applies": applies,
@@ -670,6 +675,8 @@ def main():
                     help="only run a 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--stage-steps", type=int, default=3,
                     help="extra stage-timed steps after the timed ones (roofline, stage split)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the bf16->FP32 ladder and low-precision Gram runs")
     ap.add_argument("--no-solvers", action="store_true",
                     help="skip the LOBPCG and RMM-DIIS legs")
     ap.add_argument("--no-batched", action="store_true",
@@ -744,6 +751,29 @@ def main():
                             "stages_ms_per_step": {k: v[0] / ss
                                                    for k, v in ref["stages"].items()}}
         out["eig_diff_vs_fp64_Ha"] = d
+    if ref is not None and args.precision == "fp32" and not args.no_variants:
+        # the other mixed forms over the same number of iterations from the same
+        # start: the bf16 -> FP32 filter ladder, and the low-precision first
+        # Gram pass (Cholesky QR twice); each against the FP64 trajectory
+        total = args.warmup + args.steps + ss
+        switch = max(1, int(0.6 * total))
+        lad = run_path(pw, ctx, ham, w, X0, b, lambda t: "bf16" if t <= switch else "fp32",
+                       args.steps, args.warmup, ss)
+        out["ladder_bf16_fp32"] = {
+            "ms_per_step": lad["ms_per_step"], "value": lad["value"],
+            "schedule": f"bf16 projector operands for iterations 1..{switch}, FP32 after "
+                        f"({total} iterations in all)",
+            "eig_diff_vs_fp64_Ha": float(abs(lad["lam"] - ref["lam"]).max()),
+            "max_resid": lad["max_resid"]}
+        del lad
+        gq = run_path(pw, ctx, ham, w, X0, b, "fp32", args.steps, args.warmup, ss, gram_prec="bf16")
+        out["gram_bf16_cholqr2"] = {
+            "ms_per_step": gq["ms_per_step"], "value": gq["value"],
+            "form": "FP32 filter; orthonormalisation with a bf16 Gram pass then the FP64 pass",
+            "eig_diff_vs_fp64_Ha": float(abs(gq["lam"] - ref["lam"]).max()),
+            "gram_ms_per_step": gq["stages"]["gram"][0] / ss,
+            "max_resid": gq["max_resid"]}
+        del gq
     if not args.no_solvers:
         log("LOBPCG")
         out["lobpcg"] = lobpcg_leg(ctx, ham, w, X0, passes=2 if args.config == "C5" else 4)

@@ -226,9 +226,15 @@ pw_status pw_cheb_filter(pw_ham* ham, pw_prec prec, int32_t degree, double a, do
  * positive diagonal), Y <- Y U^{-1}; if hy_dev != NULL, HY <- HY U^{-1} too.
  * U is factored in diagonal blocks of 64; Y U^{-1} is a blocked right-side
  * triangular solve (no explicit inverse).  y_dev and hy_dev must not overlap.
- * gram_prec: PW_FP64 (else PW_ERR_UNSUPPORTED).  Does not synchronise: a
- * squared pivot at or below nb * eps * max_i S_ii is reported by
- * pw_ctx_check as PW_ERR_NOT_POSDEF naming the pivot.
+ * gram_prec PW_FP64: one pass.  PW_FP32 / PW_BF16 (handle made with
+ * low_prec, else UNSUPPORTED): the overlap product in low precision -- S1
+ * from a complex64 copy of Y on the matrix cores (FP32: three-term bf16
+ * split operands; BF16: bf16 operands; FP32 accumulation) -- factored and
+ * applied in FP64, then the FP64 pass above on the result (Cholesky QR
+ * twice), so the final block is orthonormal to FP64 accuracy whatever S1's
+ * precision.  Does not synchronise: a squared pivot at or below
+ * nb * eps * max_i S_ii (either pass) is reported by pw_ctx_check as
+ * PW_ERR_NOT_POSDEF naming the pivot.
  */
 pw_status pw_orthonormalize(pw_ham* ham, pw_prec gram_prec, int64_t nb, void* y_dev, int64_t ld,
                             void* hy_dev, int64_t ldhy);

@@ -29,11 +29,13 @@ class ChfsiState:
 
 
 def chfsi(ham, X0, degree: int, iters: int, upper: Optional[float] = None,
-          reuse_hx: bool = True, record: bool = True, filter_prec="fp64",
+          reuse_hx: bool = True, record: bool = True, filter_prec="fp64", gram_prec="fp64",
           callback: Optional[Callable[[int, ChfsiState], None]] = None) -> ChfsiState:
     """filter_prec: "fp64", "fp32", "bf16", or a callable t -> precision for
-    iteration t (a precision ladder, e.g. bf16 early and fp32 late).  The
-    orthonormalisation and Rayleigh-Ritz always run in FP64."""
+    iteration t (a precision ladder, e.g. bf16 early and fp32 late).
+    gram_prec: precision of the first Gram matrix of the orthonormalisation
+    ("fp32" / "bf16" add a low-precision Cholesky-QR pass before the FP64
+    one).  The factorisations and Rayleigh-Ritz always run in FP64."""
     import torch
     nb = X0.shape[0]
     Y = X0.clone()
@@ -57,7 +59,7 @@ def chfsi(ham, X0, degree: int, iters: int, upper: Optional[float] = None,
         ham.cheb_filter(Y, degree, float(lam[-1]), b, float(lam[0]), hx=HY if reuse_hx else None,
                         prec=fp)
         st.applies += degree - 1 if reuse_hx else degree
-        ham.orthonormalize(Y, check=False)
+        ham.orthonormalize(Y, gram_prec=gram_prec, check=False)
         ham.rayleigh_ritz(Y, HY, eig, resid, check=False)
         ham.ctx.check_status()
         st.applies += 1

@@ -301,19 +301,12 @@ hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* 
   return e;
 }
 
-// Cholesky orthonormalisation of a block (Gram in FP64, blocked Cholesky,
-// Y <- Y U^{-1} and, if hy is given, HY <- HY U^{-1}); a failing pivot goes
-// to the context's deferred status under op.  No host synchronisation.
-pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op) {
+// Blocked Cholesky of the Gram matrix in sub0 (S = U^H U), its failing
+// pivot recorded under op, then Y <- Y U^{-1} and, if hy is given,
+// HY <- HY U^{-1}.
+pw_status chol_and_solve(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
-  {
-    StageScope sc(c, PW_STAGE_GRAM);
-    // Hermitian: the tiles on and above the diagonal, then mirrored
-    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, y, ld, h->sub0, nb, nullptr, h->gemm_work, s,
-                             0.0, nullptr, 2048, 1));
-    HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
-  }
   {
     StageScope sc(c, PW_STAGE_CHOL);
     HIPCHK(c, chol_blocked(nb, h->sub0, nb, h->dinv, h->panel, h->dtol, h->status_dev, s));
@@ -326,6 +319,42 @@ pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int6
       HIPCHK(c, trsm_right(h->npw, nb, hy, ldhy, h->sub0, nb, h->dinv, h->blk, s, h->nn_tile));
   }
   return PW_OK;
+}
+
+// Cholesky orthonormalisation of a block: Gram in FP64, blocked Cholesky,
+// Y <- Y U^{-1} (and HY alike); a failing pivot goes to the context's
+// deferred status under op.  gram_prec FP32 / BF16: a first pass whose Gram
+// matrix is formed from a complex64 copy of Y on the bf16 matrix cores
+// (FP32: three-term split operands, FP32-accurate products; BF16: bf16
+// operands), factored in FP64 and applied in FP64, then the FP64 pass on
+// the nearly orthonormal result (Cholesky QR twice), so the low-precision
+// Gram matrix never decides the final orthonormality.  No host
+// synchronisation.
+pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op,
+                      pw_prec gram_prec) {
+  pw_ctx* c = h->ctx;
+  hipStream_t s = c->stream;
+  pw_status st;
+  if (gram_prec != PW_FP64) {
+    {
+      StageScope sc(c, PW_STAGE_GRAM);
+      HIPCHK(c, launch_block_to_f32(h->npw, nb, y, ld, h->blk32[0], h->npw, s));
+      HIPCHK(c, launch_gemm_cn32(gram_prec == PW_BF16, nb, nb, h->npw, 1.0, h->blk32[0], h->npw,
+                                 h->blk32[0], h->npw, h->gram32, nb, nullptr, h->work32, s, nullptr,
+                                 h->gemm_target));
+      HIPCHK(c, launch_block_to_f64(nb, nb, h->gram32, nb, h->sub0, nb, s));
+      HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
+    }
+    if ((st = chol_and_solve(h, nb, y, ld, hy, ldhy, op)) != PW_OK) return st;
+  }
+  {
+    StageScope sc(c, PW_STAGE_GRAM);
+    // Hermitian: the tiles on and above the diagonal, then mirrored
+    HIPCHK(c, launch_gemm_cn(nb, nb, h->npw, 1.0, y, ld, y, ld, h->sub0, nb, nullptr, h->gemm_work, s,
+                             0.0, nullptr, 2048, 1));
+    HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
+  }
+  return chol_and_solve(h, nb, y, ld, hy, ldhy, op);
 }
 
 // The subspace part of Rayleigh-Ritz for Y orthonormal and W = H Y given:
@@ -1134,11 +1163,17 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
       TRY(dalloc(h, &h->proj3, (size_t)6 * npw * h->kp3));
       HIPCHK(ctx, launch_split3_t(npw, (int)h->nproj, h->kp3, h->proj32, npw, h->proj3, s));
       TRY(dalloc(h, &h->cprj32, (size_t)(h->nproj * h->nb_max)));
+    }
+    {
+      // split-K partials of the FP32 / BF16 projections and Gram matrices
       size_t w32 = 1;
       for (int64_t nb = 1; nb <= h->nb_max; ++nb)
-        for (int bf = 0; bf < 2; ++bf)
-          w32 = std::max(w32, gemm_cn32_work_elems(h->nproj, nb, npw, bf));
+        for (int bf = 0; bf < 2; ++bf) {
+          if (h->nproj > 0) w32 = std::max(w32, gemm_cn32_work_elems(h->nproj, nb, npw, bf));
+          w32 = std::max(w32, gemm_cn32_work_elems(nb, nb, npw, bf));
+        }
       TRY(dalloc(h, &h->work32, w32));
+      TRY(dalloc(h, &h->gram32, (size_t)(h->nb_max * h->nb_max)));
     }
     const size_t per_band32 = (size_t)P.n3 * P.ncols;
     TRY(dalloc(h, &h->T32, per_band32 * h->chunk_alloc));
@@ -1330,15 +1365,14 @@ pw_status pw_orthonormalize(pw_ham* h, pw_prec gram_prec, int64_t nb, void* yv, 
   if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
   pw_status st;
   if ((st = check_hot(h, gram_prec, nb)) != PW_OK) return st;
-  if (gram_prec != PW_FP64)
-    return fail(h->ctx, PW_ERR_UNSUPPORTED, "the Gram matrix is formed in FP64 only");
   if ((st = check_block(h, yv, ld, "y")) != PW_OK) return st;
   if (hyv && (st = check_block(h, hyv, ldhy, "hy")) != PW_OK) return st;
   if (hyv && ranges_overlap(yv, ld, hyv, ldhy, h->npw, nb))
     return fail(h->ctx, PW_ERR_INVALID_ARG, "y and hy overlap");
   pw_ctx* c = h->ctx;
   HIPCHK(c, hipSetDevice(c->device));
-  return ortho_block(h, nb, static_cast<cplx*>(yv), ld, static_cast<cplx*>(hyv), ldhy, kOpOrtho);
+  return ortho_block(h, nb, static_cast<cplx*>(yv), ld, static_cast<cplx*>(hyv), ldhy, kOpOrtho,
+                     gram_prec);
 }
 
 pw_status pw_rayleigh_ritz(pw_ham* h, int64_t nb, void* yv, int64_t ld, void* hyv, int64_t ldhy,

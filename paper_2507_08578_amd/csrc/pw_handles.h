@@ -120,6 +120,7 @@ struct pw_ham {
   float2* T32 = nullptr;
   float2* cprj32 = nullptr;
   float2* work32 = nullptr;
+  float2* gram32 = nullptr;    // nb_max^2 low-precision Gram matrix
   float2* blk32[2] = {nullptr, nullptr};
   // electron density (allocated by the first pw_density call)
   double omega = 0.0;        // cell volume (2 pi)^3 / |det B|
@@ -206,7 +207,8 @@ hipError_t chol_blocked(int64_t n, cplx* a, int64_t lda, cplx* dinv, cplx* panel
                         int* status, hipStream_t s);
 hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* u, int64_t ldu,
                       const cplx* dinv, cplx* tmp, hipStream_t s, int tile = 0);
-pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op);
+pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op,
+                      pw_prec gram_prec = PW_FP64);
 pw_status subspace_rr(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, double* eig,
                       double* resid, int op);
 

@@ -114,9 +114,9 @@ def test_deferred_sweep_limit(pw):
         ctx.set_sweep_limit(0)
 
 
-def test_low_precision_gram_is_refused(pw, ctx):
+def test_low_precision_gram_needs_low_prec_handle(pw, ctx):
     w = synth.config_c1()
-    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=8, low_prec=True)
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=8)          # FP64 only
     Y = to_dev(synth.start_block(w.npw, 8, 0))
     with pytest.raises(pw.PWError) as e:
         ham.orthonormalize(Y, gram_prec="bf16")

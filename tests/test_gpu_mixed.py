@@ -151,3 +151,39 @@ def test_apply_fp32_lds_exchange_plane_c5(pw, ctx, shape):
     for b in (0, 20):
         ref = oracle.apply_h(oh, X0[b:b + 1].astype(np.complex64).T).T
         assert rel_err(H2[b:b + 1], ref) < 2e-6, b
+
+
+@pytest.mark.parametrize("gram_prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("cfg,nb", [("C1", 16), ("C3", 160)])
+def test_orthonormalize_low_precision_gram(pw, ctx, gram_prec, cfg, nb):
+    """A first Cholesky-QR pass on a low-precision Gram matrix, then the FP64
+    pass: the result is the block's QR factor (positive R diagonal), as the
+    oracle's FP64 Cholesky QR gives, to FP64 accuracy; HY follows."""
+    w = synth.config_c1() if cfg == "C1" else synth.config_c3()
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=nb, low_prec=True)
+    oh = oracle.OracleHam.from_workload(w)
+    X0 = synth.start_block(w.npw, nb, 11)
+    HX0 = oracle.apply_h(oh, X0.T).T
+    Y, HY = to_dev(X0), to_dev(HX0)
+    ham.orthonormalize(Y, HY, gram_prec=gram_prec)
+    ry, rhy = oracle.orthonormalize(X0.T, HX0.T)
+    assert rel_err(to_host(Y), ry.T) < 1e-12
+    assert rel_err(to_host(HY), rhy.T) < 1e-12
+    y = to_host(Y)
+    assert np.abs(y.conj() @ y.T - np.eye(nb)).max() < 1e-13
+
+
+@pytest.mark.parametrize("gram_prec", ["fp32", "bf16"])
+def test_chfsi_low_precision_gram_tracks_fp64(pw, ctx, gram_prec):
+    """C1, 24 bands, 12 iterations with the low-precision first Gram pass:
+    Ritz values within 1e-8 Ha of the FP64 oracle's trajectory every
+    iteration (the filtered blocks are ill-conditioned, which a single
+    low-precision Cholesky QR would not survive at this accuracy)."""
+    w = synth.config_c1()
+    ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=24, low_prec=True)
+    oh = oracle.OracleHam.from_workload(w)
+    X0 = synth.start_block(w.npw, 24, 1)
+    st = pw.chfsi(ham, to_dev(X0), degree=8, iters=12, reuse_hx=True, gram_prec=gram_prec)
+    ores = oracle.chfsi(oh, X0.T, degree=8, iters=12, upper=st.upper)
+    d = max(np.abs(g - o).max() for g, o in zip(st.eig_history, ores.eig_history))
+    assert d < 1e-8, d
