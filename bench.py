@@ -755,6 +755,8 @@ def main():
         # the other mixed forms over the same number of iterations from the same
         # start: the bf16 -> FP32 filter ladder, and the low-precision first
         # Gram pass (Cholesky QR twice); each against the FP64 trajectory
+        if args.precision in tunings:
+            ham.set_tuning(tunings[args.precision])
         total = args.warmup + args.steps + ss
         switch = max(1, int(0.6 * total))
         lad = run_path(pw, ctx, ham, w, X0, b, lambda t: "bf16" if t <= switch else "fp32",
@@ -774,6 +776,8 @@ def main():
             "gram_ms_per_step": gq["stages"]["gram"][0] / ss,
             "max_resid": gq["max_resid"]}
         del gq
+        if "fp64" in tunings:
+            ham.set_tuning(tunings["fp64"])
     if not args.no_solvers:
         log("LOBPCG")
         out["lobpcg"] = lobpcg_leg(ctx, ham, w, X0, passes=2 if args.config == "C5" else 4)
