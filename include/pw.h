@@ -322,6 +322,24 @@ pw_status pw_rmm_diis(pw_ham* ham, int64_t nb, int32_t ndiis, void* y_dev, int64
                       double* resid_dev, double* band_resid_dev);
 
 /*
+ * Projections kept in memory (section 5.2: the coefficients c = <p_j|psi_b>,
+ * "cprj", stored for all bands so that every non-local operation is a
+ * matrix product, with no approximation).  pw_rayleigh_ritz, pw_lobpcg and
+ * pw_rmm_diis leave on the handle C = P^H Y for the Ritz vectors Y they
+ * return: C is taken from the projection products their H applications
+ * form anyway and carried through every later step by the same small
+ * matrices that change Y -- (P^H Y) U^{-1} after a Cholesky solve,
+ * (P^H Y) Q after a Rayleigh-Ritz rotation, C_B - C_X (X^H B) after a
+ * projection, column scalings -- an nproj x nb x nb product each, never
+ * P^H Y itself (nproj x npw x nb) again.  pw_ham_cprj copies the first nb
+ * columns to out_dev (nproj x nb complex128, column-major, ld ldc >=
+ * nproj; unscaled by the KB energies).  INVALID_ARG when the last such
+ * call returned fewer than nb vectors (or failed argument checks, or none
+ * ran).  nproj = 0: nothing is copied.  Enqueued; does not synchronise.
+ */
+pw_status pw_ham_cprj(pw_ham* ham, int64_t nb, void* out_dev, int64_t ldc);
+
+/*
  * Upper bound of the spectrum of H used as the filter's upper edge b:
  * max_g T_g + max_r V(r) + lambda_max(D+^1/2 P^H P D+^1/2), D+ = max(E_KB, 0)
  * (each term bounds its operator from above).  Synchronises.

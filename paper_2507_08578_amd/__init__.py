@@ -366,6 +366,17 @@ class Hamiltonian:
             self.ctx.check_status()
         return eig
 
+    def cprj(self, nb: int, out=None):
+        """Projections <p_j|y_b> of the Ritz vectors the last Rayleigh-Ritz,
+        LOBPCG or RMM-DIIS call returned (pw_ham_cprj): complex128 tensor
+        (nb, nproj), row b = band b."""
+        import torch
+        if out is None:
+            out = torch.empty((nb, max(self.nproj, 1)), dtype=torch.complex128, device="cuda")
+        self.ctx.check(_LIB.pw_ham_cprj(self.handle, int(nb), ctypes.c_void_p(out.data_ptr()),
+                                        out.stride(0)))
+        return out[:, :self.nproj]
+
     def upper_bound(self) -> float:
         b = ctypes.c_double()
         self.ctx.check(_LIB.pw_upper_bound(self.handle, ctypes.byref(b)))

@@ -66,6 +66,7 @@ SIGNATURES = {
     "pw_rayleigh_ritz": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                  c_void_p]),
     "pw_upper_bound": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
+    "pw_ham_cprj": (c_int, [c_void_p, c_int64, c_void_p, c_int64]),
     "pw_lobpcg": (c_int, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64,
                           c_void_p, c_void_p, c_void_p]),
     "pw_rmm_diis": (c_int, [c_void_p, c_int64, c_int32, c_void_p, c_int64, c_void_p, c_int64,

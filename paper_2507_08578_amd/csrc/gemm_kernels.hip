@@ -298,13 +298,15 @@ k_gemm_cn_split(int64_t M, int64_t N, int64_t K, int64_t ksplit, const cplx* __r
                t % tiles_n, t / tiles_n, z);
 }
 
-// C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M], z in fixed order.
+// C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M], z in fixed order;
+// Craw (may be null) also receives alpha sum_z work[z][i + j M] (ld ldraw).
 __device__ __forceinline__ void splitk_reduce_body(int64_t M, int64_t N, int nsplit,
                                                    const cplx* __restrict__ work, double alpha,
                                                    const double* __restrict__ alpha_dev,
                                                    const double* __restrict__ rowscale,
                                                    double beta, cplx* __restrict__ C, int64_t ldc,
-                                                   int bx) {
+                                                   int bx, cplx* __restrict__ Craw = nullptr,
+                                                   int64_t ldraw = 0) {
   if (alpha_dev) alpha = alpha_dev[0];
   const int64_t idx = (int64_t)bx * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
@@ -315,6 +317,7 @@ __device__ __forceinline__ void splitk_reduce_body(int64_t M, int64_t N, int nsp
     re += w.x;
     im += w.y;
   }
+  if (Craw) Craw[i + j * ldraw] = make_double2(alpha * re, alpha * im);
   const double s = alpha * (rowscale ? rowscale[i] : 1.0);
   cplx v = make_double2(s * re, s * im);
   if (beta != 0.0) {
@@ -328,8 +331,22 @@ __device__ __forceinline__ void splitk_reduce_body(int64_t M, int64_t N, int nsp
 __global__ void k_splitk_reduce(int64_t M, int64_t N, int nsplit, const cplx* __restrict__ work,
                                 double alpha, const double* __restrict__ alpha_dev,
                                 const double* __restrict__ rowscale, double beta,
-                                cplx* __restrict__ C, int64_t ldc) {
-  splitk_reduce_body(M, N, nsplit, work, alpha, alpha_dev, rowscale, beta, C, ldc, blockIdx.x);
+                                cplx* __restrict__ C, int64_t ldc, cplx* __restrict__ Craw,
+                                int64_t ldraw) {
+  splitk_reduce_body(M, N, nsplit, work, alpha, alpha_dev, rowscale, beta, C, ldc, blockIdx.x, Craw,
+                     ldraw);
+}
+
+// C[i + j ldc] = rowscale[i] R[i + j ldr] (the unsplit product's scaled copy)
+__global__ void k_rowscale_copy(int64_t M, int64_t N, const cplx* __restrict__ R, int64_t ldr,
+                                const double* __restrict__ rowscale, cplx* __restrict__ C,
+                                int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t j = idx / M, i = idx - j * M;
+  const cplx r = R[i + j * ldr];
+  const double sc = rowscale ? rowscale[i] : 1.0;
+  C[i + j * ldc] = make_double2(sc * r.x, sc * r.y);
 }
 
 // Hermitian products (M = N): only the nact = T (T + 1) / 2 tiles on and
@@ -505,10 +522,11 @@ size_t gemm_cn_work_elems(int64_t m, int64_t n, int64_t k) {
 hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
                           cplx* work, hipStream_t s, double beta, const double* alpha_dev,
-                          int target, int upper) {
+                          int target, int upper, cplx* craw, int64_t ldraw) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (upper && (m != n || kBM != kBN || rowscale || alpha_dev || beta != 0.0))
     return hipErrorInvalidValue;
+  if (craw && (upper || beta != 0.0 || ldraw < m)) return hipErrorInvalidValue;
   if (target < 1 || target > kTargetBlocks) target = kTargetBlocks;
   SplitPlan p = split_plan(m, n, k, target);
   const int64_t T = (m + kBM - 1) / kBM, nact = T * (T + 1) / 2;
@@ -540,6 +558,13 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
   }
   if (p.nsplit == 1) {
     dim3 grid(p.tiles_n, p.tiles_m, 1);
+    if (craw) {   // unscaled product first, then its row-scaled copy
+      hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, alpha, alpha_dev,
+                         (const double*)nullptr, A, lda, B, ldb, 0.0, craw, ldraw, (int64_t)0, 0);
+      hipLaunchKernelGGL(k_rowscale_copy, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, m,
+                         n, (const cplx*)craw, ldraw, rowscale, C, ldc);
+      return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_gemm_cn, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit, alpha, alpha_dev,
                        rowscale, A, lda, B, ldb, beta, C, ldc, (int64_t)0, upper);
     return hipGetLastError();
@@ -551,7 +576,8 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
   if (e != hipSuccess) return e;
   const int64_t tot = m * n;
   hipLaunchKernelGGL(k_splitk_reduce, dim3((tot + 255) / 256), dim3(256), 0, s, m, n,
-                     (int)p.nsplit, (const cplx*)work, alpha, alpha_dev, rowscale, beta, C, ldc);
+                     (int)p.nsplit, (const cplx*)work, alpha, alpha_dev, rowscale, beta, C, ldc, craw,
+                     ldraw);
   return hipGetLastError();
 }
 

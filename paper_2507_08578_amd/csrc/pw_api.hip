@@ -155,13 +155,14 @@ pw_status check_hot(pw_ham* h, pw_prec prec, int64_t nb) {
 // prev is read whenever it is non-null.
 pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* out, int64_t ldout,
                     double alpha, double beta, double gamma, const cplx* prev, int64_t ldprev,
-                    const double* coef) {
+                    const double* coef, cplx* craw) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_PROJ);
     HIPCHK(c, launch_gemm_cn(h->nproj, nb, h->npw, alpha, h->proj, h->npw, in, ldin, h->cprj,
-                             h->nproj, h->ekb_dev, h->gemm_work, s, 0.0, coef, h->gemm_target));
+                             h->nproj, h->ekb_dev, h->gemm_work, s, 0.0, coef, h->gemm_target, 0,
+                             craw, h->nproj));
   }
   const Epilogue ep{alpha, beta, gamma, coef};
   for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
@@ -304,7 +305,8 @@ hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* 
 // Blocked Cholesky of the Gram matrix in sub0 (S = U^H U), its failing
 // pivot recorded under op, then Y <- Y U^{-1} and, if hy is given,
 // HY <- HY U^{-1}.
-pw_status chol_and_solve(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op) {
+pw_status chol_and_solve(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op,
+                         cplx* cp) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
   {
@@ -317,6 +319,9 @@ pw_status chol_and_solve(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, i
     HIPCHK(c, trsm_right(h->npw, nb, y, ld, h->sub0, nb, h->dinv, h->blk, s, h->nn_tile));
     if (hy)
       HIPCHK(c, trsm_right(h->npw, nb, hy, ldhy, h->sub0, nb, h->dinv, h->blk, s, h->nn_tile));
+    // projections kept in memory: (P^H Y) U^{-1} = P^H (Y U^{-1}); h->cprj is free scratch here
+    if (cp && h->nproj > 0)
+      HIPCHK(c, trsm_right(h->nproj, nb, cp, h->nproj, h->sub0, nb, h->dinv, h->cprj, s, 0));
   }
   return PW_OK;
 }
@@ -331,7 +336,7 @@ pw_status chol_and_solve(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, i
 // Gram matrix never decides the final orthonormality.  No host
 // synchronisation.
 pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op,
-                      pw_prec gram_prec) {
+                      pw_prec gram_prec, cplx* cp) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
   pw_status st;
@@ -345,7 +350,7 @@ pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int6
       HIPCHK(c, launch_block_to_f64(nb, nb, h->gram32, nb, h->sub0, nb, s));
       HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
     }
-    if ((st = chol_and_solve(h, nb, y, ld, hy, ldhy, op)) != PW_OK) return st;
+    if ((st = chol_and_solve(h, nb, y, ld, hy, ldhy, op, cp)) != PW_OK) return st;
   }
   {
     StageScope sc(c, PW_STAGE_GRAM);
@@ -354,14 +359,14 @@ pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int6
                              0.0, nullptr, 2048, 1));
     HIPCHK(c, launch_hermitize(nb, h->sub0, nb, s));
   }
-  return chol_and_solve(h, nb, y, ld, hy, ldhy, op);
+  return chol_and_solve(h, nb, y, ld, hy, ldhy, op, cp);
 }
 
 // The subspace part of Rayleigh-Ritz for Y orthonormal and W = H Y given:
 // Hs = Y^H W (Hermitian part), Hs = Q diag(eig) Q^H, Y <- Y Q, W <- W Q,
 // resid_b = ||W_b - eig_b Y_b|| (if resid); eigensolver status deferred.
 pw_status subspace_rr(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, double* eig,
-                      double* resid, int op) {
+                      double* resid, int op, cplx* cp) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
   {
@@ -375,6 +380,13 @@ pw_status subspace_rr(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int6
     HIPCHK(c, launch_heev_async(nb, h->sub0, nb, eig, h->sub1, nb, h->heev_work, sweeps_slot(c),
                                 c->max_sweeps, s));
     HIPCHK(c, launch_status_record(nullptr, sweeps_slot(c), op, c->rec_dev, s));
+  }
+  if (cp && h->nproj > 0) {
+    // projections kept in memory: (P^H Y) Q = P^H (Y Q), an nproj x nb x nb product
+    StageScope sc(c, PW_STAGE_ROTATE);
+    HIPCHK(c, launch_gemm_nn(h->nproj, nb, nb, 1.0, cp, h->nproj, h->sub1, nb, 0.0, h->cprj, h->nproj,
+                             s, 0));
+    HIPCHK(c, launch_copy_block(h->nproj, nb, h->cprj, h->nproj, cp, h->nproj, s));
   }
   pw_status st;
   if ((st = rotate_block(h, nb, y, ld, h->sub1)) != PW_OK) return st;
@@ -1124,7 +1136,10 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   h->ls32_ok = h->cfg.reg_plane && fft_plane_ls_supported(P, ctx->lds_limit);
   if (h->ls32_ok) h->cfg.plane_variant32 = 2;   // the faster FP32 plane kernel where it applies
   TRY(dalloc(h, &h->T, per_band * h->chunk));
-  if (h->nproj > 0) TRY(dalloc(h, &h->cprj, (size_t)(h->nproj * h->nb_max)));
+  if (h->nproj > 0) {
+    TRY(dalloc(h, &h->cprj, (size_t)(h->nproj * h->nb_max)));
+    TRY(dalloc(h, &h->cprj_y, (size_t)(h->nproj * h->nb_max)));
+  }
   size_t wmax = 0;
   for (int64_t nb = 1; nb <= h->nb_max; ++nb) {
     if (h->nproj > 0) wmax = std::max(wmax, gemm_cn_work_elems(h->nproj, nb, npw));
@@ -1389,8 +1404,28 @@ pw_status pw_rayleigh_ritz(pw_ham* h, int64_t nb, void* yv, int64_t ld, void* hy
   HIPCHK(c, hipSetDevice(c->device));
   cplx* y = static_cast<cplx*>(yv);
   cplx* hy = static_cast<cplx*>(hyv);
-  if ((st = ham_apply(h, nb, y, ld, hy, ldhy, 1.0, 0.0, 0.0, nullptr, 0)) != PW_OK) return st;
-  return subspace_rr(h, nb, y, ld, hy, ldhy, eig, resid, kOpRayleighRitz);
+  h->cprj_nb = 0;
+  if ((st = ham_apply(h, nb, y, ld, hy, ldhy, 1.0, 0.0, 0.0, nullptr, 0, nullptr, h->cprj_y)) != PW_OK)
+    return st;
+  if ((st = subspace_rr(h, nb, y, ld, hy, ldhy, eig, resid, kOpRayleighRitz, h->cprj_y)) != PW_OK)
+    return st;
+  h->cprj_nb = nb;
+  return PW_OK;
+}
+
+pw_status pw_ham_cprj(pw_ham* h, int64_t nb, void* out, int64_t ldc) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  if (nb < 0 || nb > h->cprj_nb)
+    return fail(h->ctx, PW_ERR_INVALID_ARG,
+                "the handle holds the projections of " + std::to_string(h->cprj_nb) +
+                    " Ritz vectors, not " + std::to_string(nb));
+  if (h->nproj == 0 || nb == 0) return PW_OK;
+  if (!out || ldc < h->nproj) return fail(h->ctx, PW_ERR_INVALID_ARG, "out is NULL or ldc < nproj");
+  pw_ctx* c = h->ctx;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, launch_copy_block(h->nproj, nb, h->cprj_y, h->nproj, static_cast<cplx*>(out), ldc,
+                              c->stream));
+  return PW_OK;
 }
 
 pw_status pw_upper_bound(pw_ham* h, double* b_host) {

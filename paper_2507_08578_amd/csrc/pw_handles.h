@@ -58,6 +58,7 @@ struct LobpcgWork {
   double* lam = nullptr;              // m current Ritz values of the block
   double* ek = nullptr;               // m band kinetic energies
   void* heev = nullptr;
+  cplx* cv[2] = {nullptr, nullptr};   // P^H [X, W, P], nproj x 3m each
   std::vector<void*> mem;
 };
 
@@ -76,6 +77,8 @@ struct RmmWork {
   cplx* dots = nullptr;               // per band inner products of one launch
   cplx* lam = nullptr;                // per band trial step
   double* ek = nullptr;               // per band kinetic energy of psi^0
+  cplx* c0 = nullptr;                 // P^H psi^0, nproj x nb
+  cplx* cd = nullptr;                 // P^H K R^0
   std::vector<void*> mem;
 };
 
@@ -121,6 +124,10 @@ struct pw_ham {
   float2* cprj32 = nullptr;
   float2* work32 = nullptr;
   float2* gram32 = nullptr;    // nb_max^2 low-precision Gram matrix
+  // projections P^H Y of the Ritz vectors of the last Rayleigh-Ritz-type call
+  // (pw_rayleigh_ritz, pw_lobpcg, pw_rmm_diis), nproj x cprj_nb, ld nproj
+  cplx* cprj_y = nullptr;
+  int64_t cprj_nb = 0;
   float2* blk32[2] = {nullptr, nullptr};
   // electron density (allocated by the first pw_density call)
   double omega = 0.0;        // cell volume (2 pi)^3 / |det B|
@@ -195,9 +202,11 @@ pw_status check_block(pw_ham* h, const void* p, int64_t ld, const char* name);
 pw_status check_hot(pw_ham* h, pw_prec prec, int64_t nb);
 // out = alpha (H in) + beta in + gamma prev (FP64 blocks); coef (device,
 // may be null) overrides the scalars.
+// craw (may be null, nproj x nb, ld nproj) receives alpha P^H in, the
+// projections before the KB energies scale them.
 pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* out, int64_t ldout,
                     double alpha, double beta, double gamma, const cplx* prev, int64_t ldprev,
-                    const double* coef = nullptr);
+                    const double* coef = nullptr, cplx* craw = nullptr);
 pw_status rotate_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, const cplx* m);
 // Hot calls that record a deferred status (pw_ctx_check names them).
 enum DeferredOp { kOpOrtho = 1, kOpRayleighRitz = 2, kOpLobpcg = 3, kOpRmmDiis = 4, kOpHeev = 5 };
@@ -207,9 +216,11 @@ hipError_t chol_blocked(int64_t n, cplx* a, int64_t lda, cplx* dinv, cplx* panel
                         int* status, hipStream_t s);
 hipError_t trsm_right(int64_t rows, int64_t n, cplx* y, int64_t ld, const cplx* u, int64_t ldu,
                       const cplx* dinv, cplx* tmp, hipStream_t s, int tile = 0);
+// cp (may be null, nproj x nb, ld nproj): projections P^H Y carried along,
+// updated by the same triangular solves / rotation as Y (no product with P).
 pw_status ortho_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, int op,
-                      pw_prec gram_prec = PW_FP64);
+                      pw_prec gram_prec = PW_FP64, cplx* cp = nullptr);
 pw_status subspace_rr(pw_ham* h, int64_t nb, cplx* y, int64_t ld, cplx* hy, int64_t ldhy, double* eig,
-                      double* resid, int op);
+                      double* resid, int op, cplx* cp = nullptr);
 
 }  // namespace pwi

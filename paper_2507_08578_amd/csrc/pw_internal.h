@@ -265,8 +265,10 @@ hipError_t launch_gemm_cn(int64_t m, int64_t n, int64_t k, double alpha, const c
                           const cplx* B, int64_t ldb, cplx* C, int64_t ldc, const double* rowscale,
                           cplx* work, hipStream_t s, double beta = 0.0,
                           const double* alpha_dev = nullptr, int target_blocks = 2048,
-                          int upper = 0);   // 1 (m == n, Hermitian result): only the 64 x 64
+                          int upper = 0,    // 1 (m == n, Hermitian result): only the 64 x 64
                                             // tiles on and above the diagonal are formed
+                          cplx* craw = nullptr, int64_t ldraw = 0);  // also alpha A^H B without
+                                                                     // rowscale (beta = 0 only)
 // tile 0: 64 x 64 workgroup tiles; 1: 128 x 64 (tall products)
 hipError_t launch_gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const cplx* A, int64_t lda,
                           const cplx* B, int64_t ldb, double beta, cplx* C, int64_t ldc,

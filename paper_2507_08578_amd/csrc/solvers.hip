@@ -111,10 +111,11 @@ __global__ void k_precond(int64_t npw, const cplx* __restrict__ R, int64_t ldr,
   D[g + b * ldd] = zscale(R[g + b * ldr], teter(kin[g] / ek[b]));
 }
 
-// Column b of B (and of HB, if given) divided by ||B_b||.
+// Column b of B (and of HB and of the nc-row block CB, if given) divided by ||B_b||.
 __global__ void __launch_bounds__(kRed) k_normalize_cols(int64_t npw, cplx* __restrict__ B,
                                                          int64_t ldb, cplx* __restrict__ HB,
-                                                         int64_t ldhb) {
+                                                         int64_t ldhb, int64_t nc,
+                                                         cplx* __restrict__ CB, int64_t ldcb) {
   __shared__ double part[4];
   cplx* x = B + (int64_t)blockIdx.x * ldb;
   double v[1] = {0.0};
@@ -125,6 +126,10 @@ __global__ void __launch_bounds__(kRed) k_normalize_cols(int64_t npw, cplx* __re
   if (HB) {
     cplx* hx = HB + (int64_t)blockIdx.x * ldhb;
     for (int64_t g = threadIdx.x; g < npw; g += kRed) hx[g] = zscale(hx[g], s);
+  }
+  if (CB) {
+    cplx* cx = CB + (int64_t)blockIdx.x * ldcb;
+    for (int64_t g = threadIdx.x; g < nc; g += kRed) cx[g] = zscale(cx[g], s);
   }
 }
 
@@ -424,9 +429,11 @@ using namespace pwi;
 namespace {
 
 // B <- B - X (X^H B) and, if HB, HB <- HB - HX (X^H B): X has kx
-// orthonormal columns (ld ldx), B and HB m columns with ld npw.
+// orthonormal columns (ld ldx), B and HB m columns with ld npw.  With CB and
+// CX (projections of B and X, nproj rows): CB <- CB - CX (X^H B).
 pw_status remove_span(pw_ham* h, int64_t m, cplx* B, cplx* HB, int64_t kx, const cplx* X,
-                      int64_t ldx, const cplx* HX, int64_t ldhx, cplx* cbuf, cplx* work) {
+                      int64_t ldx, const cplx* HX, int64_t ldhx, cplx* cbuf, cplx* work,
+                      cplx* CB = nullptr, const cplx* CX = nullptr) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
   const int64_t npw = h->npw;
@@ -434,11 +441,15 @@ pw_status remove_span(pw_ham* h, int64_t m, cplx* B, cplx* HB, int64_t kx, const
   HIPCHK(c, launch_gemm_cn(kx, m, npw, 1.0, X, ldx, B, npw, cbuf, kx, nullptr, work, s));
   HIPCHK(c, launch_gemm_nn(npw, m, kx, -1.0, X, ldx, cbuf, kx, 1.0, B, npw, s, h->nn_tile));
   if (HB) HIPCHK(c, launch_gemm_nn(npw, m, kx, -1.0, HX, ldhx, cbuf, kx, 1.0, HB, npw, s, h->nn_tile));
+  if (CB && CX && h->nproj > 0)
+    HIPCHK(c, launch_gemm_nn(h->nproj, m, kx, -1.0, CX, h->nproj, cbuf, kx, 1.0, CB, h->nproj, s, 0));
   return PW_OK;
 }
 
-hipError_t normalize_cols(int64_t npw, int64_t m, cplx* B, cplx* HB, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize_cols, dim3((unsigned)m), dim3(kRed), 0, s, npw, B, npw, HB, npw);
+hipError_t normalize_cols(int64_t npw, int64_t m, cplx* B, cplx* HB, hipStream_t s,
+                          int64_t nc = 0, cplx* CB = nullptr) {
+  hipLaunchKernelGGL(k_normalize_cols, dim3((unsigned)m), dim3(kRed), 0, s, npw, B, npw, HB, npw,
+                     nc, CB, nc);
   return hipGetLastError();
 }
 
@@ -471,6 +482,11 @@ pw_status lobpcg_workspace(pw_ham* h, int64_t nb, int64_t m) {
   for (void* p : {(void*)w.s, (void*)w.z, (void*)w.c, (void*)w.work, (void*)w.theta, (void*)w.lam,
                   (void*)w.ek, (void*)hw})
     w.mem.push_back(p);
+  if (h->nproj > 0)
+    for (int i = 0; i < 2; ++i) {
+      if ((st = dalloc(h, &w.cv[i], (size_t)(h->nproj * k))) != PW_OK) return st;
+      w.mem.push_back(w.cv[i]);
+    }
   w.m = m;
   w.nb = nb;
   return PW_OK;
@@ -497,6 +513,13 @@ pw_status rmm_workspace(pw_ham* h, int64_t nb, int ndiis) {
   for (void* p : {(void*)w.psi, (void*)w.r, (void*)w.hcur, (void*)w.d, (void*)w.hd, (void*)w.amat,
                   (void*)w.bmat, (void*)w.coef, (void*)w.dots, (void*)w.lam, (void*)w.ek})
     w.mem.push_back(p);
+  if (h->nproj > 0) {
+    if ((st = dalloc(h, &w.c0, (size_t)(h->nproj * nb))) != PW_OK ||
+        (st = dalloc(h, &w.cd, (size_t)(h->nproj * nb))) != PW_OK)
+      return st;
+    w.mem.push_back(w.c0);
+    w.mem.push_back(w.cd);
+  }
   w.nb = nb;
   w.ndiis = ndiis;
   return PW_OK;
@@ -547,6 +570,8 @@ pw_status pw_lobpcg(pw_ham* h, int64_t nb, int32_t nblock, int32_t nline, void* 
   LobpcgWork& w = h->lob;
   cplx* y = static_cast<cplx*>(yv);
   cplx* hy = static_cast<cplx*>(hyv);
+  const int64_t np = h->nproj;
+  h->cprj_nb = 0;
   // X <- the orthonormalised start block
   if ((st = ortho_block(h, nb, y, ld, nullptr, 0, kOpLobpcg)) != PW_OK) return st;
   int64_t lo = 0;
@@ -556,6 +581,10 @@ pw_status pw_lobpcg(pw_ham* h, int64_t nb, int32_t nblock, int32_t nline, void* 
     cplx* HV = w.hv[0];
     cplx* V2 = w.v[1];
     cplx* HV2 = w.hv[1];
+    // projections P^H [X, W, P] (null without projectors): formed by the H
+    // applications, then carried through every later step of the block
+    cplx* CV = w.cv[0];
+    cplx* CV2 = w.cv[1];
     // X_j: orthogonal to the (updated) blocks below, orthonormal, Rayleigh-Ritz
     {
       StageScope sc(c, PW_STAGE_MISC);
@@ -566,8 +595,9 @@ pw_status pw_lobpcg(pw_ham* h, int64_t nb, int32_t nblock, int32_t nline, void* 
       if ((st = remove_span(h, m, V, nullptr, lo, y, ld, nullptr, 0, w.c, w.work)) != PW_OK) return st;
     }
     if ((st = ortho_block(h, m, V, npw, nullptr, 0, kOpLobpcg)) != PW_OK) return st;
-    if ((st = ham_apply(h, m, V, npw, HV, npw, 1.0, 0.0, 0.0, nullptr, 0)) != PW_OK) return st;
-    if ((st = subspace_rr(h, m, V, npw, HV, npw, w.lam, nullptr, kOpLobpcg)) != PW_OK) return st;
+    if ((st = ham_apply(h, m, V, npw, HV, npw, 1.0, 0.0, 0.0, nullptr, 0, nullptr, CV)) != PW_OK)
+      return st;
+    if ((st = subspace_rr(h, m, V, npw, HV, npw, w.lam, nullptr, kOpLobpcg, CV)) != PW_OK) return st;
     if (hist) HIPCHK(c, launch_scale_copy(m, w.lam, 1.0, hist + lo, s));
     bool have_p = false;
     for (int line = 0; line < nline; ++line) {
@@ -577,6 +607,9 @@ pw_status pw_lobpcg(pw_ham* h, int64_t nb, int32_t nblock, int32_t nline, void* 
       cplx* HW = HV + m * npw;
       cplx* P = V + 2 * m * npw;
       cplx* HP = HV + 2 * m * npw;
+      cplx* CX = CV;
+      cplx* CW = CV ? CV + m * np : nullptr;
+      cplx* CP = CV ? CV + 2 * m * np : nullptr;
       {
         StageScope sc(c, PW_STAGE_MISC);
         hipLaunchKernelGGL(k_band_kinetic, dim3((unsigned)m), dim3(kRed), 0, s, npw, (const cplx*)X,
@@ -596,15 +629,18 @@ pw_status pw_lobpcg(pw_ham* h, int64_t nb, int32_t nblock, int32_t nline, void* 
         HIPCHK(c, normalize_cols(npw, m, W, nullptr, s));
       }
       if ((st = ortho_block(h, m, W, npw, nullptr, 0, kOpLobpcg)) != PW_OK) return st;
-      if ((st = ham_apply(h, m, W, npw, HW, npw, 1.0, 0.0, 0.0, nullptr, 0)) != PW_OK) return st;
+      if ((st = ham_apply(h, m, W, npw, HW, npw, 1.0, 0.0, 0.0, nullptr, 0, nullptr, CW)) != PW_OK)
+        return st;
       if (have_p) {
         {
           StageScope sc(c, PW_STAGE_ROTATE);
-          if ((st = remove_span(h, m, P, HP, m, X, npw, HX, npw, w.c, w.work)) != PW_OK) return st;
-          if ((st = remove_span(h, m, P, HP, m, W, npw, HW, npw, w.c, w.work)) != PW_OK) return st;
-          HIPCHK(c, normalize_cols(npw, m, P, HP, s));
+          if ((st = remove_span(h, m, P, HP, m, X, npw, HX, npw, w.c, w.work, CP, CX)) != PW_OK)
+            return st;
+          if ((st = remove_span(h, m, P, HP, m, W, npw, HW, npw, w.c, w.work, CP, CW)) != PW_OK)
+            return st;
+          HIPCHK(c, normalize_cols(npw, m, P, HP, s, np, CP));
         }
-        if ((st = ortho_block(h, m, P, npw, HP, npw, kOpLobpcg)) != PW_OK) return st;
+        if ((st = ortho_block(h, m, P, npw, HP, npw, kOpLobpcg, PW_FP64, CP)) != PW_OK) return st;
       }
       const int64_t k = have_p ? 3 * m : 2 * m;
       {
@@ -628,10 +664,16 @@ pw_status pw_lobpcg(pw_ham* h, int64_t nb, int32_t nblock, int32_t nline, void* 
                                  V2 + 2 * m * npw, npw, s, h->nn_tile));
         HIPCHK(c, launch_gemm_nn(npw, m, k - m, 1.0, HV + m * npw, npw, w.z + m, k, 0.0,
                                  HV2 + 2 * m * npw, npw, s, h->nn_tile));
+        if (CV) {   // the same rotations of the projections, nproj rows
+          HIPCHK(c, launch_gemm_nn(np, m, k, 1.0, CV, np, w.z, k, 0.0, CV2, np, s, 0));
+          HIPCHK(c, launch_gemm_nn(np, m, k - m, 1.0, CV + m * np, np, w.z + m, k, 0.0,
+                                   CV2 + 2 * m * np, np, s, 0));
+        }
         HIPCHK(c, launch_scale_copy(m, w.theta, 1.0, w.lam, s));
       }
       std::swap(V, V2);
       std::swap(HV, HV2);
+      std::swap(CV, CV2);
       have_p = true;
       if (hist) HIPCHK(c, launch_scale_copy(m, w.lam, 1.0, hist + (int64_t)(line + 1) * nb + lo, s));
     }
@@ -639,11 +681,16 @@ pw_status pw_lobpcg(pw_ham* h, int64_t nb, int32_t nblock, int32_t nline, void* 
       StageScope sc(c, PW_STAGE_MISC);
       HIPCHK(c, launch_copy_block(npw, m, V, npw, y + lo * ld, ld, s));
       HIPCHK(c, launch_copy_block(npw, m, HV, npw, hy + lo * ldhy, ldhy, s));
+      if (CV) HIPCHK(c, launch_copy_block(np, m, CV, np, h->cprj_y + lo * np, np, s));
     }
     lo += m;
   }
-  // one Rayleigh-Ritz over all bands with the carried H X
-  return subspace_rr(h, nb, y, ld, hy, ldhy, eig, resid, kOpLobpcg);
+  // one Rayleigh-Ritz over all bands with the carried H X (and P^H X)
+  if ((st = subspace_rr(h, nb, y, ld, hy, ldhy, eig, resid, kOpLobpcg, np > 0 ? h->cprj_y : nullptr)) !=
+      PW_OK)
+    return st;
+  h->cprj_nb = nb;
+  return PW_OK;
 }
 
 pw_status pw_rmm_diis(pw_ham* h, int64_t nb, int32_t ndiis, void* yv, int64_t ld, void* hyv,
@@ -696,8 +743,17 @@ pw_status pw_rmm_diis(pw_ham* h, int64_t nb, int32_t ndiis, void* yv, int64_t ld
     HIPCHK(c, launch_copy_block(npw, nb, y, ld, P(0), npw, s));
     if (hy_valid) HIPCHK(c, launch_copy_block(npw, nb, hy, ldhy, w.hcur, npw, s));
   }
-  if (!hy_valid && (st = ham_apply(h, nb, P(0), npw, w.hcur, npw, 1.0, 0.0, 0.0, nullptr, 0)) != PW_OK)
+  const int64_t np = h->nproj;
+  h->cprj_nb = 0;
+  // projections of psi^0 (needed only when the pass ends on the line step)
+  if (!hy_valid &&
+      (st = ham_apply(h, nb, P(0), npw, w.hcur, npw, 1.0, 0.0, 0.0, nullptr, 0, nullptr, w.c0)) != PW_OK)
     return st;
+  if (hy_valid && ndiis == 1 && np > 0) {
+    StageScope sc(c, PW_STAGE_PROJ);
+    HIPCHK(c, launch_gemm_cn(np, nb, npw, 1.0, h->proj, npw, P(0), npw, w.c0, np, nullptr,
+                             h->gemm_work, s, 0.0, nullptr, h->gemm_target));
+  }
   {
     StageScope sc(c, PW_STAGE_MISC);
     hipLaunchKernelGGL(k_band_kinetic, dim3((unsigned)nb), dim3(kRed), 0, s, npw,
@@ -709,7 +765,8 @@ pw_status pw_rmm_diis(pw_ham* h, int64_t nb, int32_t ndiis, void* yv, int64_t ld
     HIPCHK(c, hipGetLastError());
     if ((st = store_row(0)) != PW_OK) return st;
   }
-  if ((st = ham_apply(h, nb, w.d, npw, w.hd, npw, 1.0, 0.0, 0.0, nullptr, 0)) != PW_OK) return st;
+  if ((st = ham_apply(h, nb, w.d, npw, w.hd, npw, 1.0, 0.0, 0.0, nullptr, 0, nullptr, w.cd)) != PW_OK)
+    return st;
   {
     StageScope sc(c, PW_STAGE_MISC);
     HIPCHK(c, band_dots(npw, nb, {P(0), w.d}, {P(0), w.d, w.hcur, w.hd}, npw, w.dots, s));
@@ -721,6 +778,9 @@ pw_status pw_rmm_diis(pw_ham* h, int64_t nb, int32_t ndiis, void* yv, int64_t ld
                        (const cplx*)w.hd, npw, (const cplx*)w.lam, w.hcur, npw);
     hipLaunchKernelGGL(k_rq_resid, dim3((unsigned)nb), dim3(kRed), 0, s, npw, (const cplx*)P(1), npw,
                        (const cplx*)w.hcur, npw, R(1), npw, bres(1));
+    if (ndiis == 1 && np > 0)   // P^H psi^1 = P^H psi^0 + lam P^H d
+      hipLaunchKernelGGL(k_axpy_band, band_grid(np, nb), dim3(256), 0, s, np, (const cplx*)w.c0, np,
+                         (const cplx*)w.cd, np, (const cplx*)w.lam, h->cprj_y, np);
     HIPCHK(c, hipGetLastError());
     if (ndiis > 1 && (st = store_row(1)) != PW_OK) return st;
   }
@@ -734,7 +794,8 @@ pw_status pw_rmm_diis(pw_ham* h, int64_t nb, int32_t ndiis, void* yv, int64_t ld
                          (const double*)h->kin, (const double*)w.ek, P(M + 1));
       HIPCHK(c, hipGetLastError());
     }
-    if ((st = ham_apply(h, nb, P(M + 1), npw, w.hcur, npw, 1.0, 0.0, 0.0, nullptr, 0)) != PW_OK)
+    if ((st = ham_apply(h, nb, P(M + 1), npw, w.hcur, npw, 1.0, 0.0, 0.0, nullptr, 0, nullptr,
+                        M + 1 == ndiis && np > 0 ? h->cprj_y : nullptr)) != PW_OK)
       return st;
     {
       StageScope sc(c, PW_STAGE_MISC);
@@ -750,8 +811,11 @@ pw_status pw_rmm_diis(pw_ham* h, int64_t nb, int32_t ndiis, void* yv, int64_t ld
     HIPCHK(c, launch_copy_block(npw, nb, P(ndiis), npw, y, ld, s));
     HIPCHK(c, launch_copy_block(npw, nb, w.hcur, npw, hy, ldhy, s));
   }
-  if ((st = ortho_block(h, nb, y, ld, hy, ldhy, kOpRmmDiis)) != PW_OK) return st;
-  return subspace_rr(h, nb, y, ld, hy, ldhy, eig, resid, kOpRmmDiis);
+  cplx* cp = np > 0 ? h->cprj_y : nullptr;
+  if ((st = ortho_block(h, nb, y, ld, hy, ldhy, kOpRmmDiis, PW_FP64, cp)) != PW_OK) return st;
+  if ((st = subspace_rr(h, nb, y, ld, hy, ldhy, eig, resid, kOpRmmDiis, cp)) != PW_OK) return st;
+  h->cprj_nb = nb;
+  return PW_OK;
 }
 
 }  // extern "C"
