@@ -383,6 +383,20 @@ pw_status pw_ham_set_tuning(pw_ham* ham, const pw_tuning* t);
 pw_status pw_ham_autotune(pw_ham* ham, pw_prec prec, int64_t nb, int32_t reps, pw_tuning* best,
                           pw_tuning* initial);
 
+/*
+ * pw_ham_autotune behind a tuning cache file: the handle's shape key (box,
+ * sphere columns and extent, npw, nproj, nb, precision) is looked up in the
+ * text file cache_path (one line per key: the key, then name=value for the
+ * eight tuning fields and ms); a hit whose tuning the handle accepts is
+ * applied without timing (*cached = 1, initial->ms = 0); otherwise the
+ * handle is tuned as by pw_ham_autotune (reps timings per candidate) and
+ * the line written (the file is rewritten through a temporary and renamed;
+ * not safe against concurrent writers).  cache_path NULL or "": no cache.
+ * initial and cached may be NULL.  Synchronises.
+ */
+pw_status pw_autotune(pw_ham* ham, pw_prec prec, int64_t nb, int32_t reps, const char* cache_path,
+                      pw_tuning* best, pw_tuning* initial, int32_t* cached);
+
 /* ---------------------------------------------------------------------------
  * Batched subspace iteration over independent Hamiltonians (k-points of one
  * cell, or separate cells), section 5.1's Chebyshev-filtered iteration run
@@ -442,6 +456,9 @@ pw_status pw_batch_start(pw_batch* b);
  * overlap, so stage sums can exceed wall time); graph replays are not timed.
  */
 pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph);
+/* The whole batched solve: pw_batch_start, then pw_batch_iterate(iters,
+ * use_graph).  Synchronises; failures as pw_batch_iterate. */
+pw_status pw_batch_chfsi(pw_batch* b, int32_t iters, int32_t use_graph);
 /* Largest number of Jacobi sweeps any item used in the last start/iterate. */
 pw_status pw_batch_max_sweeps(const pw_batch* b, int32_t* sweeps);
 

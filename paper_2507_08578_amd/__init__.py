@@ -400,38 +400,26 @@ class Hamiltonian:
         self.ctx.check(_LIB.pw_ham_set_tuning(self.handle, ctypes.byref(t)))
 
     def tuning_key(self, prec, nb: int) -> str:
-        """Shape key of the tuning cache: box, sphere columns and extent, npw, nproj, nb, prec."""
+        """Shape key of the tuning cache (as pw_autotune writes it): box, sphere
+        columns and extent, npw, nproj, nb, precision code."""
         N1, N2, N3 = self.box
         return (f"{N1}x{N2}x{N3}/cols{self.ncolumns}/xr{self.extent1}/npw{self.npw}/"
-                f"proj{self.nproj}/nb{nb}/{prec if isinstance(prec, str) else int(prec)}")
+                f"proj{self.nproj}/nb{nb}/{_prec(prec)}")
 
     def autotune(self, prec="fp64", nb: Optional[int] = None, reps: int = 3,
                  cache: Optional[str] = None) -> dict:
-        """Time launch-shape alternatives on the device and keep the fastest.
-        cache: path of a JSON file of earlier choices keyed by tuning_key();
-        a hit is applied without timing, a miss is tuned and stored."""
-        import json
-        import os
+        """Time launch-shape alternatives on the device and keep the fastest
+        (pw_autotune).  cache: path of the library's tuning cache file; a hit
+        is applied without timing, a miss is tuned and stored."""
         nb = int(nb or self.nb_max)
-        key = self.tuning_key(prec, nb)
-        table = {}
-        if cache and os.path.exists(cache):
-            with open(cache) as f:
-                table = json.load(f)
-            if key in table:
-                self.set_tuning(table[key])
-                return dict(table[key], cached=True)
         best, init = _lib.PwTuning(), _lib.PwTuning()
-        self.ctx.check(_LIB.pw_ham_autotune(self.handle, _prec(prec), nb, int(reps),
-                                            ctypes.byref(best), ctypes.byref(init)))
+        cached = ctypes.c_int32()
+        path = cache.encode() if cache else None
+        self.ctx.check(_LIB.pw_autotune(self.handle, _prec(prec), nb, int(reps), path,
+                                        ctypes.byref(best), ctypes.byref(init),
+                                        ctypes.byref(cached)))
         out = {k: getattr(best, k) for k in self._TUNING_KEYS}
-        out.update(ms=best.ms, default_ms=init.ms, cached=False)
-        if cache:
-            table[key] = {k: out[k] for k in self._TUNING_KEYS + ("ms", "default_ms")}
-            tmp = cache + ".tmp"
-            with open(tmp, "w") as f:
-                json.dump(table, f, indent=1, sort_keys=True)
-            os.replace(tmp, cache)
+        out.update(ms=best.ms, default_ms=init.ms, cached=bool(cached.value))
         return out
 
 
@@ -481,6 +469,13 @@ class Batch:
         mode = {True: 1, "single": 1, "per_stream": 2, "fused": 3, "fused_direct": 4,
                 False: 0}[graph]
         self.ctx.check(_LIB.pw_batch_iterate(self.handle, int(iters), mode))
+
+    def chfsi(self, iters: int, graph="fused"):
+        """The whole batched solve (pw_batch_chfsi): iteration 0, then iters
+        iterations in the given replay mode (as iterate)."""
+        mode = {True: 1, "single": 1, "per_stream": 2, "fused": 3, "fused_direct": 4,
+                False: 0}[graph]
+        self.ctx.check(_LIB.pw_batch_chfsi(self.handle, int(iters), mode))
 
     def max_sweeps(self) -> int:
         n = ctypes.c_int32()

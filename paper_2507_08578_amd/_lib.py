@@ -98,6 +98,10 @@ SIGNATURES = {
     "pw_batch_start": (c_int, [c_void_p]),
     "pw_batch_iterate": (c_int, [c_void_p, c_int32, c_int32]),
     "pw_batch_max_sweeps": (c_int, [c_void_p, ctypes.POINTER(c_int32)]),
+    "pw_batch_chfsi": (c_int, [c_void_p, c_int32, c_int32]),
+    "pw_autotune": (c_int, [c_void_p, c_int, c_int64, c_int32, ctypes.c_char_p,
+                            ctypes.POINTER(PwTuning), ctypes.POINTER(PwTuning),
+                            ctypes.POINTER(c_int32)]),
 }
 
 

@@ -11,8 +11,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdio>
+#include <fstream>
 #include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -1634,6 +1637,89 @@ pw_status pw_ham_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, pw_
   return PW_OK;
 }
 
+pw_status pw_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, const char* cache_path,
+                      pw_tuning* best, pw_tuning* initial, int32_t* cached) {
+  if (!h) return fail(nullptr, PW_ERR_INVALID_ARG, "ham is NULL");
+  if (!best) return fail(h->ctx, PW_ERR_INVALID_ARG, "best is NULL");
+  pw_status st;
+  if ((st = check_hot(h, prec, nb)) != PW_OK) return st;
+  // shape key: box, sphere columns and extent, npw, nproj, nb, precision
+  const BoxPlan& P = h->plan;
+  std::ostringstream ks;
+  ks << P.n1 << "x" << P.n2 << "x" << P.n3 << "/cols" << P.ncols << "/xr" << P.xr << "/npw"
+     << h->npw << "/proj" << h->nproj << "/nb" << nb << "/" << (int)prec;
+  const std::string key = ks.str();
+  static const char* names[8] = {"reg_col", "reg_plane", "plane_variant", "plane_variant32",
+                                 "chunk", "gemm_blocks", "nn_tile", "nn_tile32"};
+  auto fields = [](pw_tuning& t) {
+    int32_t* f[8] = {&t.reg_col, &t.reg_plane, &t.plane_variant, &t.plane_variant32,
+                     &t.chunk, &t.gemm_blocks, &t.nn_tile, &t.nn_tile32};
+    return std::vector<int32_t*>(f, f + 8);
+  };
+  std::vector<std::string> keep;
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream is(line);
+      std::string k;
+      if (!(is >> k)) continue;
+      if (k != key) {
+        keep.push_back(line);
+        continue;
+      }
+      pw_tuning t{};
+      pw_ham_get_tuning(h, &t);
+      int found = 0;
+      std::string tok;
+      while (is >> tok) {
+        const size_t eq = tok.find('=');
+        if (eq == std::string::npos) continue;
+        const std::string n = tok.substr(0, eq), v = tok.substr(eq + 1);
+        if (n == "ms") {
+          t.ms = std::atof(v.c_str());
+          continue;
+        }
+        auto f = fields(t);
+        for (int i = 0; i < 8; ++i)
+          if (n == names[i]) {
+            *f[i] = (int32_t)std::atoi(v.c_str());
+            ++found;
+          }
+      }
+      if (found == 8 && pw_ham_set_tuning(h, &t) == PW_OK) {
+        if (initial) {
+          *initial = t;
+          initial->ms = 0.0;
+        }
+        *best = t;
+        if (cached) *cached = 1;
+        return PW_OK;
+      }
+    }
+  }
+  if ((st = pw_ham_autotune(h, prec, nb, reps, best, initial)) != PW_OK) return st;
+  if (cached) *cached = 0;
+  if (cache_path && *cache_path) {
+    std::ostringstream line;
+    line << key;
+    pw_tuning t = *best;
+    auto f = fields(t);
+    for (int i = 0; i < 8; ++i) line << " " << names[i] << "=" << *f[i];
+    line << " ms=" << best->ms;
+    keep.push_back(line.str());
+    const std::string tmp = std::string(cache_path) + ".tmp";
+    {
+      std::ofstream out(tmp, std::ios::trunc);
+      for (const std::string& l : keep) out << l << "\n";
+      if (!out) return fail(h->ctx, PW_ERR_INVALID_ARG, "cannot write the tuning cache " + tmp);
+    }
+    if (std::rename(tmp.c_str(), cache_path) != 0)
+      return fail(h->ctx, PW_ERR_INVALID_ARG, std::string("cannot replace ") + cache_path);
+  }
+  return PW_OK;
+}
+
 // ---------------------------------------------------------------------------
 // batched subspace iteration
 // ---------------------------------------------------------------------------
@@ -1856,6 +1942,13 @@ pw_status pw_batch_iterate(pw_batch* b, int32_t iters, int32_t use_graph) {
     }
   }
   return batch_leave(b);
+}
+
+pw_status pw_batch_chfsi(pw_batch* b, int32_t iters, int32_t use_graph) {
+  if (!b) return fail(nullptr, PW_ERR_INVALID_ARG, "batch is NULL");
+  pw_status st;
+  if ((st = pw_batch_start(b)) != PW_OK) return st;
+  return pw_batch_iterate(b, iters, use_graph);
 }
 
 pw_status pw_batch_max_sweeps(const pw_batch* b, int32_t* sweeps) {

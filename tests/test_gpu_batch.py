@@ -84,8 +84,7 @@ def test_batch_c2_reaches_exact(pw, ctx):
     """20 iterations: the 12 lowest bands of every k-point hit the exact spectrum."""
     ws, hams, X0 = c2_items(pw, ctx, idx=[0, 4, 8, 17, 26])
     bt = pw.Batch(ctx, hams, X0, degree=8)
-    bt.start()
-    bt.iterate(20)
+    bt.chfsi(20, graph=True)                    # pw_batch_chfsi: start + 20 iterations
     for i, w in enumerate(ws):
         exact = np.linalg.eigvalsh(oracle.dense_h(oracle.OracleHam.from_workload(w)))
         err = np.abs(bt.eigenvalues()[i][:12] - exact[:12]).max()

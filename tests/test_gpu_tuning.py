@@ -2,7 +2,6 @@
 (to the FP64 bar against the oracle), the tuner keeps a valid choice, and the
 JSON cache replays it."""
 import itertools
-import json
 
 import numpy as np
 import pytest
@@ -74,13 +73,14 @@ def test_set_tuning_rejects(pw, ctx):
 def test_autotune_and_cache(pw, ctx, tmp_path, prec):
     w = synth.config_c1()
     ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=16, low_prec=True)
-    cache = str(tmp_path / "tune.json")
+    cache = str(tmp_path / "tune.txt")
     r = ham.autotune(prec, nb=16, reps=2, cache=cache)
     assert not r["cached"] and r["ms"] <= r["default_ms"] * 1.0001
     chosen = ham.get_tuning()
     assert all(chosen[k] == r[k] for k in chosen)
-    table = json.load(open(cache))
-    assert ham.tuning_key(prec, 16) in table
+    lines = open(cache).read().splitlines()
+    assert [ln.split()[0] for ln in lines] == [ham.tuning_key(prec, 16)]
+    assert all(f"{k}={chosen[k]}" in lines[0].split() for k in chosen)
     ham2 = pw.Hamiltonian.from_workload(ctx, w, nb_max=16, low_prec=True)
     r2 = ham2.autotune(prec, nb=16, cache=cache)
     assert r2["cached"] and ham2.get_tuning() == chosen
