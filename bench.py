@@ -675,6 +675,8 @@ def main():
                     help="only run a 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--stage-steps", type=int, default=3,
                     help="extra stage-timed steps after the timed ones (roofline, stage split)")
+    ap.add_argument("--overlap", action="store_true",
+                    help="run P^H psi on a second stream beside the FFT route")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the bf16->FP32 ladder and low-precision Gram runs")
     ap.add_argument("--no-solvers", action="store_true",
@@ -699,6 +701,7 @@ def main():
     nb = w.nb
     log(f"npw={w.npw} nproj={w.nproj} box={w.box} nb={nb} degree={w.degree}")
     ctx = pw.Context(0)
+    ctx.set_overlap(args.overlap)
     mixed = args.precision != "fp64"
     ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=nb, low_prec=mixed)
     X0 = torch.from_numpy(synth.start_block(w.npw, nb, 0)).cuda()
@@ -733,7 +736,8 @@ def main():
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
                    "filter_precision": args.precision, "subspace_precision": "fp64",
                    "step": f"filter (degree {w.degree}, H*Y reused) + Cholesky + Rayleigh-Ritz",
-                   "applies_per_step": res["applies"], "nb": nb},
+                   "applies_per_step": res["applies"], "nb": nb,
+                   "proj_overlap": args.overlap},
         "filter_iter_ms": res["ms_per_step"],
         "max_resid": res["max_resid"],
         "eigensolver_sweeps": res["sweeps"],

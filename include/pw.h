@@ -112,6 +112,18 @@ pw_status pw_ctx_check(pw_ctx* ctx);
 pw_status pw_ctx_set_sweep_limit(pw_ctx* ctx, int32_t max_sweeps);
 
 /*
+ * Concurrency inside H psi (default off): the projection product P^H psi
+ * runs on a second stream of the context, forked from and joined back to
+ * the context's stream by events, so it overlaps the FFT route of the same
+ * application; P C waits for both.  Results are bit-identical either way;
+ * graph capture sees the fork and join.  Off: everything on one stream
+ * (faster on the benchmarked cell, where the persistent plane kernel and
+ * the projection each fill the compute units).  Applies to calls issued on
+ * the context's own stream (not to a batch's branch streams).
+ */
+pw_status pw_ctx_set_overlap(pw_ctx* ctx, int32_t enable);
+
+/*
  * Description of H at one k-point (section 5.2, Eq. ham-nl, norm-conserving
  * case: h_{a,ij} diagonal).
  *   n[3]     FFT box N1, N2, N3.  Each N_i must be a product of the radices

@@ -91,6 +91,10 @@ class Context:
         calls recorded on the device since the last check (pw_ctx_check)."""
         self.check(_LIB.pw_ctx_check(self.handle))
 
+    def set_overlap(self, enable: bool):
+        """P^H psi on a second stream beside the FFT route (pw_ctx_set_overlap)."""
+        self.check(_LIB.pw_ctx_set_overlap(self.handle, int(bool(enable))))
+
     def set_sweep_limit(self, max_sweeps: int):
         self.check(_LIB.pw_ctx_set_sweep_limit(self.handle, int(max_sweeps)))
 

@@ -85,6 +85,7 @@ SIGNATURES = {
     "pw_ctx_last_sweeps": (c_int, [c_void_p, ctypes.POINTER(c_int)]),
     "pw_ctx_check": (c_int, [c_void_p]),
     "pw_ctx_set_sweep_limit": (c_int, [c_void_p, c_int32]),
+    "pw_ctx_set_overlap": (c_int, [c_void_p, c_int32]),
     "pw_ham_get_tuning": (c_int, [c_void_p, ctypes.POINTER(PwTuning)]),
     "pw_ham_set_tuning": (c_int, [c_void_p, ctypes.POINTER(PwTuning)]),
     "pw_ham_autotune": (c_int, [c_void_p, c_int, c_int64, c_int32, ctypes.POINTER(PwTuning),

@@ -161,12 +161,20 @@ pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* o
                     const double* coef, cplx* craw) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
+  const bool fork = h->nproj > 0 && c->overlap && c->stream == c->home;
   if (h->nproj > 0) {
-    StageScope sc(c, PW_STAGE_PROJ);
+    // P^H psi on the second stream, concurrent with the FFT route below
+    hipStream_t ps = fork ? c->aux : s;
+    if (fork) {
+      HIPCHK(c, hipEventRecord(c->ev_fork, s));
+      HIPCHK(c, hipStreamWaitEvent(ps, c->ev_fork, 0));
+    }
+    StageScope sc(c, PW_STAGE_PROJ, ps);
     HIPCHK(c, launch_gemm_cn(h->nproj, nb, h->npw, alpha, h->proj, h->npw, in, ldin, h->cprj,
-                             h->nproj, h->ekb_dev, h->gemm_work, s, 0.0, coef, h->gemm_target, 0,
+                             h->nproj, h->ekb_dev, h->gemm_work, ps, 0.0, coef, h->gemm_target, 0,
                              craw, h->nproj));
   }
+  if (fork) HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
   const Epilogue ep{alpha, beta, gamma, coef};
   for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
     const int nc = (int)std::min<int64_t>(h->chunk, nb - c0);
@@ -185,6 +193,7 @@ pw_status ham_apply(pw_ham* h, int64_t nb, const cplx* in, int64_t ldin, cplx* o
                                    ldout, ep, s));
     }
   }
+  if (fork) HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_NONLOCAL);
     HIPCHK(c, launch_gemm_nn(h->npw, nb, h->nproj, 1.0, h->proj, h->npw, h->cprj, h->nproj, 1.0,
@@ -201,12 +210,20 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
                       int64_t ldprev, const double* coef = nullptr) {
   pw_ctx* c = h->ctx;
   hipStream_t s = c->stream;
+  const bool fork = h->nproj > 0 && c->overlap && c->stream == c->home;
   if (h->nproj > 0) {
-    StageScope sc(c, PW_STAGE_PROJ_LP);
+    // P^H psi on the second stream, concurrent with the FFT route below
+    hipStream_t ps = fork ? c->aux : s;
+    if (fork) {
+      HIPCHK(c, hipEventRecord(c->ev_fork, s));
+      HIPCHK(c, hipStreamWaitEvent(ps, c->ev_fork, 0));
+    }
+    StageScope sc(c, PW_STAGE_PROJ_LP, ps);
     HIPCHK(c, launch_gemm_cn32(bf16, h->nproj, nb, h->npw, alpha, h->proj32, h->npw, in, ldin,
-                               h->cprj32, h->nproj, h->ekb_dev, h->work32, s, coef,
+                               h->cprj32, h->nproj, h->ekb_dev, h->work32, ps, coef,
                                h->gemm_target));
   }
+  if (fork) HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
   const Epilogue ep{alpha, beta, gamma, coef};
   for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
     const int nc = (int)std::min<int64_t>(h->chunk, nb - c0);
@@ -225,6 +242,7 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
                                      ldout, ep, s));
     }
   }
+  if (fork) HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_NONLOCAL_LP);
     HIPCHK(c, launch_gemm_nn32(bf16, h->npw, nb, h->nproj, 1.0, h->proj32, h->npw, h->cprj32,
@@ -891,7 +909,11 @@ pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
     return fail(nullptr, PW_ERR_OOM, "status word allocation failed");
   }
   c->rec_dev = static_cast<int*>(rec);
-  e = scratch_address(device, &c->scratch);
+  c->home = c->stream;
+  e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = scratch_address(device, &c->scratch);
   if (e == hipSuccess && heev_work_bytes(kScratchHeevMax) > kScratchBytes) e = hipErrorInvalidValue;
   if (e == hipSuccess) e = launch_fill_int(8, 0, c->rec_dev, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -901,6 +923,9 @@ pw_status pw_ctx_create(int device, void* hip_stream, pw_ctx** out) {
   if (e == hipSuccess) e = fft_ls_set_lds_limit(c->lds_limit);
   if (e == hipSuccess) e = density_set_lds_limit(c->lds_limit);
   if (e != hipSuccess) {
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     (void)hipFree(rec);
     (void)hipHostFree(pin);
     delete c;
@@ -922,8 +947,12 @@ void ctx_release(pw_ctx* ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->rec_dev) (void)hipFree(ctx->rec_dev);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   delete ctx;
 }
 }  // namespace
@@ -2123,6 +2152,13 @@ pw_status pw_ctx_set_sweep_limit(pw_ctx* c, int32_t max_sweeps) {
     return fail(c, PW_ERR_INVALID_ARG,
                 "sweep limit must be in [1, " + std::to_string(kHeevMaxSweeps) + "]");
   c->max_sweeps = max_sweeps;
+  return PW_OK;
+}
+
+pw_status pw_ctx_set_overlap(pw_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, PW_ERR_INVALID_ARG, "ctx is NULL");
+  if (enable != 0 && enable != 1) return fail(c, PW_ERR_INVALID_ARG, "enable must be 0 or 1");
+  c->overlap = enable != 0;
   return PW_OK;
 }
 

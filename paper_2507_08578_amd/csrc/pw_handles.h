@@ -15,7 +15,15 @@ struct EventPair {
 
 struct pw_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // where the library's work goes (the batch swaps it)
+  hipStream_t home = nullptr;     // the stream given at creation
+  // second stream for the projection product P^H psi, which then overlaps
+  // the FFT route of the same H*psi (fork / join by events); off by
+  // default: measured slower at C5, the persistent plane kernel and the
+  // projection both want whole compute units
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool overlap = false;
   std::string err;
   size_t lds_limit = 0;
   int cus = 256;              // compute units of the device
@@ -155,18 +163,20 @@ pw_status fail(pw_ctx* c, pw_status s, const std::string& msg);
 struct StageScope {
   pw_ctx* c;
   int stage;
+  hipStream_t s;
   hipEvent_t a = nullptr;
-  StageScope(pw_ctx* ctx, int st) : c(ctx), stage(st) {
+  StageScope(pw_ctx* ctx, int st, hipStream_t on = nullptr)
+      : c(ctx), stage(st), s(on ? on : ctx->stream) {
     if (c->timing) {
       a = c->get_event();
-      if (a) (void)hipEventRecord(a, c->stream);
+      if (a) (void)hipEventRecord(a, s);
     }
   }
   ~StageScope() {
     if (c->timing && a) {
       hipEvent_t b = c->get_event();
       if (b) {
-        (void)hipEventRecord(b, c->stream);
+        (void)hipEventRecord(b, s);
         c->pending.push_back({a, b, stage});
       } else {
         c->pool.push_back(a);

@@ -121,3 +121,23 @@ def test_low_precision_gram_needs_low_prec_handle(pw, ctx):
     with pytest.raises(pw.PWError) as e:
         ham.orthonormalize(Y, gram_prec="bf16")
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_overlap_is_bit_identical(pw, prec):
+    """P^H psi on the second stream (default) or on the context's stream:
+    the same kernels on the same data, so the same bits (C3, 160 bands, a
+    degree-8 filter reusing H Y, orthonormalisation, Rayleigh-Ritz)."""
+    import torch
+    w = synth.config_c3()
+    out = {}
+    for ov in (False, True):
+        ctx = pw.Context(0)
+        ctx.set_overlap(ov)
+        ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=160, low_prec=prec != "fp64")
+        st = pw.chfsi(ham, to_dev(synth.start_block(w.npw, 160, 2)), degree=8, iters=1,
+                      filter_prec=prec)
+        torch.cuda.synchronize()
+        out[ov] = (st.Y.clone(), st.HY.clone(), st.eig.clone())
+    for a, b in zip(out[False], out[True]):
+        assert torch.equal(a, b)
