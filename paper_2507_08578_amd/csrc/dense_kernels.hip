@@ -567,12 +567,12 @@ __device__ __forceinline__ int bj_index(int i, int I, int J) {
 
 // One sweep on each block pair of outer round r (workgroup k: pair k);
 // Qout[k] (kBJS x kBJS, column-major) receives the accumulated rotations.
-// Each inner round: kBJ threads form the rotations, then four threads per
-// 2x2 block of A (one output element each) and two per row pair of V.  The
-// threads sharing a block are adjacent lanes of one wavefront, whose LDS
-// reads all complete before its writes, so they may update it in place.
-constexpr int kBJInnerThreads = 4 * kBJ * kBJ;
-static_assert(2 * kBJS * kBJ == kBJInnerThreads, "V row pairs: two threads each");
+// Each inner round: kBJ threads form the rotations, then one thread per 2x2
+// block of A (kBJ^2 blocks: it reads the block's four entries once and
+// writes all four) and per two (row, pair) items of V.  Every entry belongs
+// to exactly one block or item, so the updates are in place.
+constexpr int kBJInnerThreads = kBJ * kBJ;
+static_assert(2 * kBJInnerThreads == kBJS * kBJ, "V (row, pair) items: two per thread");
 __global__ void __launch_bounds__(kBJInnerThreads)
 k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout,
            const int* __restrict__ conv) {
@@ -591,10 +591,7 @@ k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout,
     v[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  const int blk = tid >> 2, er = (tid >> 1) & 1, ec = tid & 1;   // block, output row / column
-  const int P = blk / kBJ, Qb = blk - P * kBJ;
-  const int vp = tid >> 1, vf = tid & 1;                          // V row pair, output column
-  const int vQ = vp / kBJS, vi = vp - vQ * kBJS;
+  const int P = tid / kBJ, Qb = tid - P * kBJ;   // this thread's 2x2 block of A
   for (int rr = 0; rr < kBJS - 1; ++rr) {
     if (tid < kBJ) {
       int p, q;
@@ -608,41 +605,34 @@ k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout,
       const Rot& RP = rots[P];
       const Rot& RQ = rots[Qb];
       const int p1 = pp[P], q1 = pq[P], p2 = pp[Qb], q2 = pq[Qb];
-      const int row = er ? q1 : p1, col = ec ? q2 : p2;
       if (P == Qb) {
         if (RP.on) {
-          cplx out = make_double2(0.0, 0.0);
-          if (er == ec) out = make_double2(a[row + row * LA].x + (er ? RP.t : -RP.t), 0.0);
-          a[row + col * LA] = out;
+          a[p1 + p1 * LA] = make_double2(a[p1 + p1 * LA].x - RP.t, 0.0);
+          a[q1 + q1 * LA] = make_double2(a[q1 + q1 * LA].x + RP.t, 0.0);
+          a[p1 + q1 * LA] = make_double2(0.0, 0.0);
+          a[q1 + p1 * LA] = make_double2(0.0, 0.0);
         }
       } else if (RP.on || RQ.on) {
-        const cplx x11 = a[p1 + p2 * LA], x12 = a[p1 + q2 * LA];
-        const cplx x21 = a[q1 + p2 * LA], x22 = a[q1 + q2 * LA];
-        // column ec of M = X Jq, Jq = [[cs, sn ph], [-sn conj(ph), cs]]
-        const cplx q12 = cscale(RQ.ph, RQ.sn), q21 = cscale(cconj(RQ.ph), -RQ.sn);
-        cplx m1, m2;
-        if (ec == 0) {
-          m1 = cadd(cscale(x11, RQ.cs), cmul(x12, q21));
-          m2 = cadd(cscale(x21, RQ.cs), cmul(x22, q21));
-        } else {
-          m1 = cadd(cmul(x11, q12), cscale(x12, RQ.cs));
-          m2 = cadd(cmul(x21, q12), cscale(x22, RQ.cs));
-        }
-        // row er of Jp^H M, Jp^H = [[cs, -sn ph], [sn conj(ph), cs]]
-        const cplx out = er == 0 ? cadd(cscale(m1, RP.cs), cmul(cscale(RP.ph, -RP.sn), m2))
-                                 : cadd(cmul(cscale(cconj(RP.ph), RP.sn), m1), cscale(m2, RP.cs));
-        a[row + col * LA] = out;
+        cplx x11 = a[p1 + p2 * LA], x12 = a[p1 + q2 * LA];
+        cplx x21 = a[q1 + p2 * LA], x22 = a[q1 + q2 * LA];
+        rot_block(RP, RQ, &x11, &x12, &x21, &x22);
+        a[p1 + p2 * LA] = x11;
+        a[p1 + q2 * LA] = x12;
+        a[q1 + p2 * LA] = x21;
+        a[q1 + q2 * LA] = x22;
       }
     }
-    {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int item = tid + h * kBJInnerThreads;
+      const int vQ = item / kBJS, vi = item - vQ * kBJS;
       const Rot& RV = rots[vQ];
       if (RV.on) {
         const int p2 = pp[vQ], q2 = pq[vQ];
-        const cplx x1 = v[vi + p2 * kBJS], x2 = v[vi + q2 * kBJS];
-        // (x1, x2) <- (x1, x2) J
-        const cplx out = vf == 0 ? cadd(cscale(x1, RV.cs), cmul(x2, cscale(cconj(RV.ph), -RV.sn)))
-                                 : cadd(cmul(x1, cscale(RV.ph, RV.sn)), cscale(x2, RV.cs));
-        v[vi + (vf ? q2 : p2) * kBJS] = out;
+        cplx x1 = v[vi + p2 * kBJS], x2 = v[vi + q2 * kBJS];
+        rot_row(RV, &x1, &x2);
+        v[vi + p2 * kBJS] = x1;
+        v[vi + q2 * kBJS] = x2;
       }
     }
     __syncthreads();
