@@ -233,14 +233,49 @@ struct Split {
   static constexpr int Q = R / P;
 };
 
-// R-point DFT in registers for R a product of 2, 3, 5 (mixed-radix
-// Cooley-Tukey, n = Q a + b, k = k1 + P k2, compile-time twiddles).
+constexpr int gcd_ce(int a, int b) { return b == 0 ? a : gcd_ce(b, a % b); }
+// x with (a x) mod m == 1, for gcd(a, m) == 1 and m >= 2
+constexpr int inv_mod_ce(int a, int m) {
+  int x = 1;
+  while ((a * x) % m != 1) ++x;
+  return x;
+}
+
+// R-point DFT in registers for R a product of 2, 3, 5.  R = P Q with
+// coprime factors: Good-Thomas prime-factor mapping, no twiddles --
+// input n = (Q a + P b) mod R, a P-point DFT over a for each b, then a
+// Q-point DFT over b for each k1, output k = (Q q' k1 + P p' k2) mod R with
+// q' = Q^-1 mod P, p' = P^-1 mod Q (W_R^{nk} = W_P^{a k1} W_Q^{b k2}).
+// Otherwise mixed-radix Cooley-Tukey, n = Q a + b, k = k1 + P k2, with
+// compile-time twiddles.
 template <int R, int S, class C>
 __device__ __forceinline__ void dft_reg(C* v) {
   if constexpr (R == 1) {
     return;
   } else if constexpr (R == 2 || R == 3 || R == 4 || R == 5 || R == 8) {
     dft_base<R, S>(v);
+  } else if constexpr (gcd_ce(Split<R>::P, Split<R>::Q) == 1) {
+    constexpr int P = Split<R>::P, Q = Split<R>::Q;
+    constexpr int qi = inv_mod_ce(Q % P, P), pi = inv_mod_ce(P % Q, Q);
+    C y[Q][P];
+#pragma unroll
+    for (int b = 0; b < Q; ++b) {
+      C u[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) u[a] = v[(Q * a + P * b) % R];
+      dft_reg<P, S>(u);
+#pragma unroll
+      for (int k1 = 0; k1 < P; ++k1) y[b][k1] = u[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+      C w[Q];
+#pragma unroll
+      for (int b = 0; b < Q; ++b) w[b] = y[b][k1];
+      dft_reg<Q, S>(w);
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) v[(Q * qi * k1 + P * pi * k2) % R] = w[k2];
+    }
   } else {
     constexpr int P = Split<R>::P, Q = Split<R>::Q;
     C y[Q][P];
