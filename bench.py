@@ -377,6 +377,8 @@ def run_path(pw, ctx, ham, w, X0, b, prec, steps, warmup, stage_steps, gram_prec
     ctx.set_timing(False)
     log(f"{name}: {stage_steps} stage-timed steps done")
     applies = w.degree                       # (degree - 1) filter products + 1 in Rayleigh-Ritz
+    log(f"{name}: {it[0]} iterations, Ritz values sum {float(lam.sum()):.15e} "
+        f"top {float(lam[-1]):.15e}")
     return {"ms_per_step": 1e3 * dt / steps, "value": applies * nb * steps / dt,
             "stages": stages, "stage_steps": stage_steps, "applies": applies,
             "lam": lam.numpy().copy(), "max_resid": float(resid.max().cpu()), "sweeps": sweeps,
@@ -770,6 +772,7 @@ def main():
             "schedule": f"bf16 projector operands for iterations 1..{switch}, FP32 after "
                         f"({total} iterations in all)",
             "eig_diff_vs_fp64_Ha": float(abs(lad["lam"] - ref["lam"]).max()),
+            "eig_diff_vs_fp32_Ha": float(abs(lad["lam"] - res["lam"]).max()),
             "max_resid": lad["max_resid"]}
         del lad
         gq = run_path(pw, ctx, ham, w, X0, b, "fp32", args.steps, args.warmup, ss, gram_prec="bf16")
@@ -777,6 +780,7 @@ def main():
             "ms_per_step": gq["ms_per_step"], "value": gq["value"],
             "form": "FP32 filter; orthonormalisation with a bf16 Gram pass then the FP64 pass",
             "eig_diff_vs_fp64_Ha": float(abs(gq["lam"] - ref["lam"]).max()),
+            "eig_diff_vs_fp32_Ha": float(abs(gq["lam"] - res["lam"]).max()),
             "gram_ms_per_step": gq["stages"]["gram"][0] / ss,
             "max_resid": gq["max_resid"]}
         del gq
