@@ -18,15 +18,21 @@
  *    pw_last_error() holds a message.
  *  - A block of nb wavefunctions is a column-major npw x nb complex matrix
  *    (band b occupies elements [b*ld, b*ld + npw)), ld >= npw, complex values
- *    interleaved (re, im).  pw_apply_h blocks are complex128 for PW_FP64 and
- *    complex64 for PW_FP32 / PW_BF16; every other entry point takes
- *    complex128 blocks whatever its internal precision.
+ *    interleaved (re, im).  pw_apply_h blocks are complex128 for PW_FP64,
+ *    complex64 for PW_FP32 and interleaved bfloat16 pairs (4 bytes per
+ *    element: a torch bfloat16 tensor of shape (nb, ld, 2)) for PW_BF16;
+ *    every other entry point takes complex128 blocks whatever its internal
+ *    precision.
  *  - Precision of a call: PW_FP64 everything in FP64.  PW_FP32: FFT route in
  *    FP32, projector products with FP32 operands on the bf16 MFMA, every
  *    operand split exactly into three bfloat16 terms (six term products per
- *    real product; the accuracy of FP32 products).  PW_BF16: FFT route in
- *    FP32, projector products with bfloat16 operands.  All accumulate in
- *    FP32.
+ *    real product; the accuracy of FP32 products).  PW_BF16: blocks stored
+ *    as bf16 pairs (loads widen to FP32, stores round to nearest even), FFT
+ *    route in FP32 (FP32 column intermediate), projector products with
+ *    bfloat16 operands (the block operand read straight from its bf16
+ *    storage); needs a box with the register column kernels (else
+ *    UNSUPPORTED).  All accumulate in FP32.  In a pw_batch, PW_BF16 runs
+ *    the filter on complex64 blocks with bfloat16 projector operands.
  *  - Pointers named *_dev are device memory on the context's device, owned by
  *    the caller; the library never frees them.  Pointers named *_host are host
  *    memory read during the call only.
@@ -228,7 +234,8 @@ pw_status pw_density(pw_ham* ham, int64_t nb, const void* psi_dev, int64_t ldpsi
  * hx_dev (may be NULL): H X already computed (e.g. by the previous
  * Rayleigh-Ritz); then only m-1 products are formed.
  * prec PW_FP32 / PW_BF16: y and hx stay complex128; the recurrence runs on
- * complex64 copies (y converted on entry, the result converted back).
+ * complex64 (FP32) or bf16-pair (BF16) copies (y converted on entry, the
+ * result converted back).
  */
 pw_status pw_cheb_filter(pw_ham* ham, pw_prec prec, int32_t degree, double a, double b, double a0,
                          int64_t nb, void* y_dev, int64_t ld, const void* hx_dev, int64_t ldhx);

@@ -48,6 +48,29 @@ def _prec(p) -> int:
     return int(p)
 
 
+def to_bf16_pairs(x):
+    """A complex block (nb, npw) as the bf16-pair storage of PW_BF16: a
+    bfloat16 tensor (nb, npw, 2), each part rounded to nearest even."""
+    import torch
+    return torch.view_as_real(x.to(torch.complex64)).to(torch.bfloat16).contiguous()
+
+
+def from_bf16_pairs(t):
+    """bf16-pair block (nb, npw, 2) -> complex64 (nb, npw), exactly."""
+    import torch
+    return torch.view_as_complex(t.to(torch.float32).contiguous())
+
+
+def _bf16_block_args(t, npw: int, name: str):
+    import torch
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.bfloat16
+            or t.dim() != 3 or t.shape[1] != npw or t.shape[2] != 2 or t.stride(2) != 1
+            or t.stride(1) != 2 or t.stride(0) % 2):
+        raise TypeError(f"{name} must be a bfloat16 CUDA tensor (nb, npw={npw}, 2) of "
+                        "interleaved (re, im) pairs, contiguous along npw")
+    return ctypes.c_void_p(t.data_ptr()), t.stride(0) // 2
+
+
 def _block_args(t, npw: int, name: str, complex64: bool = False):
     import torch
     want = torch.complex64 if complex64 else torch.complex128
@@ -258,14 +281,19 @@ class Hamiltonian:
 
     # --- hot path ---
     def apply_h(self, psi, out=None, prec="fp64"):
-        """H psi; complex128 blocks for fp64, complex64 blocks for fp32/bf16."""
+        """H psi; complex128 blocks for fp64, complex64 for fp32, bf16-pair
+        blocks (bfloat16 (nb, npw, 2), see to_bf16_pairs) for bf16."""
         import torch
         pr = _prec(prec)
-        c64 = pr != PW_FP64
-        p, ldp = _block_args(psi, self.npw, "psi", c64)
         if out is None:
             out = torch.empty_like(psi)
-        o, ldo = _block_args(out, self.npw, "out", c64)
+        if pr == PW_BF16:
+            p, ldp = _bf16_block_args(psi, self.npw, "psi")
+            o, ldo = _bf16_block_args(out, self.npw, "out")
+        else:
+            c64 = pr != PW_FP64
+            p, ldp = _block_args(psi, self.npw, "psi", c64)
+            o, ldo = _block_args(out, self.npw, "out", c64)
         self.ctx.check(_LIB.pw_apply_h(self.handle, pr, psi.shape[0], p, ldp, o, ldo))
         return out
 

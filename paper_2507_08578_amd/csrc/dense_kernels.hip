@@ -1132,6 +1132,62 @@ hipError_t launch_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx*
   return hipGetLastError();
 }
 
+__global__ void k_block_to_b16(int64_t rows, int64_t cols, const cplx* __restrict__ x, int64_t ldx,
+                               bf16c* __restrict__ y, int64_t ldy) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = idx - j * rows;
+  y[i + j * ldy] = st_c<bf16c>(x[i + j * ldx]);
+}
+
+__global__ void k_block_b16_to_f64(int64_t rows, int64_t cols, const bf16c* __restrict__ x,
+                                   int64_t ldx, cplx* __restrict__ y, int64_t ldy) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = idx - j * rows;
+  const float2 v = ld_c(x[i + j * ldx]);
+  y[i + j * ldy] = make_double2(v.x, v.y);
+}
+
+__global__ void k_axpby_to_b16(int64_t rows, int64_t cols, double a, const cplx* __restrict__ x,
+                               int64_t ldx, double b, const cplx* __restrict__ y, int64_t ldy,
+                               bf16c* __restrict__ out, int64_t ldo, const double* __restrict__ coef) {
+  if (coef) {
+    a = coef[0];
+    b = coef[1];
+  }
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t j = idx / rows, i = idx - j * rows;
+  const cplx u = x[i + j * ldx], v = y[i + j * ldy];
+  out[i + j * ldo] = st_c<bf16c>(make_double2(a * u.x + b * v.x, a * u.y + b * v.y));
+}
+
+hipError_t launch_block_to_b16(int64_t rows, int64_t cols, const cplx* x, int64_t ldx, bf16c* y,
+                               int64_t ldy, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_to_b16, dim3(nblocks(rows * cols, 256)), dim3(256), 0, s, rows, cols,
+                     x, ldx, y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_b16_to_f64(int64_t rows, int64_t cols, const bf16c* x, int64_t ldx, cplx* y,
+                                   int64_t ldy, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_b16_to_f64, dim3(nblocks(rows * cols, 256)), dim3(256), 0, s, rows,
+                     cols, x, ldx, y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby_to_b16(int64_t rows, int64_t cols, double a, const cplx* x, int64_t ldx,
+                               double b, const cplx* y, int64_t ldy, bf16c* out, int64_t ldo,
+                               hipStream_t s, const double* coef) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby_to_b16, dim3(nblocks(rows * cols, 256)), dim3(256), 0, s, rows, cols,
+                     a, x, ldx, b, y, ldy, out, ldo, coef);
+  return hipGetLastError();
+}
+
 hipError_t launch_real_to_f32(int64_t n, const double* src, double scale, float* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_real_to_f32, dim3(nblocks(n, 256)), dim3(256), 0, s, n, src, scale, dst);
   return hipGetLastError();

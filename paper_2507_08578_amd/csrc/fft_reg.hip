@@ -19,9 +19,10 @@ namespace {
 constexpr int kColThreads = 256;
 constexpr int kPlaneMaxThreads = 512;
 
-template <int N3, class C>
+// S: storage type of the block psi (C, or bf16 pairs widened on load).
+template <int N3, class C, class S = C>
 __device__ __forceinline__ void col_inv_reg_body(const BoxPlan& P, const C* __restrict__ tw3,
-                                                 const C* __restrict__ psi, int64_t ldpsi,
+                                                 const S* __restrict__ psi, int64_t ldpsi,
                                                  C* __restrict__ T, int cb, int b) {
   constexpr int G = lane_group(N3), R = N3 / G, CT = kColThreads / G, TRS = N3 + 1;
   __shared__ C tile[CT * TRS];
@@ -29,7 +30,7 @@ __device__ __forceinline__ void col_inv_reg_body(const BoxPlan& P, const C* __re
   const int ncl = min(CT, P.ncols - c0);
   for (int i = threadIdx.x; i < CT * TRS; i += blockDim.x) tile[i] = czero<C>();
   __syncthreads();
-  const C* src = psi + (size_t)b * ldpsi;
+  const S* src = psi + (size_t)b * ldpsi;
   const int grp = threadIdx.x / G, lb = threadIdx.x % G;
   if (P.runs) {
     // one lane group per column: its points are consecutive in psi and in m3
@@ -38,13 +39,13 @@ __device__ __forceinline__ void col_inv_reg_body(const BoxPlan& P, const C* __re
       const int lo = P.col_m3lo[c];
       for (int j = lb; j < len; j += G) {
         const int m = lo + j;
-        tile[grp * TRS + (m < 0 ? m + N3 : m)] = src[ks + j];
+        tile[grp * TRS + (m < 0 ? m + N3 : m)] = ld_c(src[ks + j]);
       }
     }
   } else {
     const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
     for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
-      tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]] = src[P.pt_perm[k]];
+      tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]] = ld_c(src[P.pt_perm[k]]);
   }
   __syncthreads();
   if (grp < ncl) {
@@ -67,19 +68,20 @@ __device__ __forceinline__ void col_inv_reg_body(const BoxPlan& P, const C* __re
   }
 }
 
-template <int N3, class C>
+template <int N3, class C, class S = C>
 __global__ void __launch_bounds__(kColThreads)
-k_col_inv_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ psi, int64_t ldpsi,
+k_col_inv_reg(BoxPlan P, const C* __restrict__ tw3, const S* __restrict__ psi, int64_t ldpsi,
               C* __restrict__ T) {
-  col_inv_reg_body<N3, C>(P, tw3, psi, ldpsi, T, blockIdx.x, blockIdx.y);
+  col_inv_reg_body<N3, C, S>(P, tw3, psi, ldpsi, T, blockIdx.x, blockIdx.y);
 }
 
-template <int N3, class C>
+// S: storage type of the blocks in, prev and out.
+template <int N3, class C, class S = C>
 __device__ __forceinline__ void col_fwd_reg_body(const BoxPlan& P, const C* __restrict__ tw3,
                                                  const C* __restrict__ T,
-                                                 const real_t<C>* __restrict__ kin, const C* in,
-                                                 int64_t ldin, const C* prev, int64_t ldprev,
-                                                 C* out, int64_t ldout, double alpha_d,
+                                                 const real_t<C>* __restrict__ kin, const S* in,
+                                                 int64_t ldin, const S* prev, int64_t ldprev,
+                                                 S* out, int64_t ldout, double alpha_d,
                                                  double beta_d, double gamma_d,
                                                  const double* __restrict__ coef, int cb, int b) {
   using Rl = real_t<C>;
@@ -113,21 +115,21 @@ __device__ __forceinline__ void col_fwd_reg_body(const BoxPlan& P, const C* __re
     for (int a = 0; a < R; ++a) col[G * a + lb] = v[a];
   }
   __syncthreads();
-  const C* inb = in + (size_t)b * ldin;
-  C* outb = out + (size_t)b * ldout;
-  const C* prevb = prev ? prev + (size_t)b * ldprev : nullptr;
+  const S* inb = in + (size_t)b * ldin;
+  S* outb = out + (size_t)b * ldout;
+  const S* prevb = prev ? prev + (size_t)b * ldprev : nullptr;
   auto emit = [&](int g, const C& loc) {
-    const C x = inb[g];
+    const C x = ld_c(inb[g]);
     const Rl t = kin[g];
     C val;
     val.x = alpha * (loc.x + t * x.x) + beta * x.x;
     val.y = alpha * (loc.y + t * x.y) + beta * x.y;
     if (prevb) {
-      const C p = prevb[g];
+      const C p = ld_c(prevb[g]);
       val.x += gamma * p.x;
       val.y += gamma * p.y;
     }
-    outb[g] = val;
+    outb[g] = st_c<S>(val);
   };
   if (P.runs) {
     // one lane group per column: its points are consecutive in psi and in m3
@@ -146,14 +148,14 @@ __device__ __forceinline__ void col_fwd_reg_body(const BoxPlan& P, const C* __re
   }
 }
 
-template <int N3, class C>
+template <int N3, class C, class S = C>
 __global__ void __launch_bounds__(kColThreads)
 k_col_fwd_reg(BoxPlan P, const C* __restrict__ tw3, const C* __restrict__ T,
-              const real_t<C>* __restrict__ kin, const C* in, int64_t ldin, const C* prev,
-              int64_t ldprev, C* out, int64_t ldout, double alpha_d, double beta_d,
+              const real_t<C>* __restrict__ kin, const S* in, int64_t ldin, const S* prev,
+              int64_t ldprev, S* out, int64_t ldout, double alpha_d, double beta_d,
               double gamma_d, const double* __restrict__ coef) {
-  col_fwd_reg_body<N3, C>(P, tw3, T, kin, in, ldin, prev, ldprev, out, ldout, alpha_d, beta_d,
-                          gamma_d, coef, blockIdx.x, blockIdx.y);
+  col_fwd_reg_body<N3, C, S>(P, tw3, T, kin, in, ldin, prev, ldprev, out, ldout, alpha_d, beta_d,
+                             gamma_d, coef, blockIdx.x, blockIdx.y);
 }
 
 template <int N1, int N2, int GMAX, class C>
@@ -371,13 +373,13 @@ const double2* axis_tw<double2>(const FftAxis& ax) { return ax.tw; }
 template <>
 const float2* axis_tw<float2>(const FftAxis& ax) { return ax.tw32; }
 
-template <class C>
-hipError_t col_inv_reg(const BoxPlan& p, int nb, const C* psi, int64_t ldpsi, C* T, hipStream_t s) {
+template <class C, class S = C>
+hipError_t col_inv_reg(const BoxPlan& p, int nb, const S* psi, int64_t ldpsi, C* T, hipStream_t s) {
 #define CASE(N)                                                                              \
   if (p.n3 == N) {                                                                           \
     constexpr int CT = kColThreads / lane_group(N);                                          \
     dim3 grid((p.ncols + CT - 1) / CT, nb);                                                  \
-    hipLaunchKernelGGL((k_col_inv_reg<N, C>), grid, dim3(kColThreads), 0, s, p,              \
+    hipLaunchKernelGGL((k_col_inv_reg<N, C, S>), grid, dim3(kColThreads), 0, s, p,           \
                        axis_tw<C>(p.ax3), psi, ldpsi, T);                                    \
     return hipGetLastError();                                                                \
   }
@@ -386,15 +388,15 @@ hipError_t col_inv_reg(const BoxPlan& p, int nb, const C* psi, int64_t ldpsi, C*
   return hipErrorInvalidValue;
 }
 
-template <class C>
-hipError_t col_fwd_reg(const BoxPlan& p, int nb, const C* T, const real_t<C>* kin, const C* in,
-                       int64_t ldin, const C* prev, int64_t ldprev, C* out, int64_t ldout,
+template <class C, class S = C>
+hipError_t col_fwd_reg(const BoxPlan& p, int nb, const C* T, const real_t<C>* kin, const S* in,
+                       int64_t ldin, const S* prev, int64_t ldprev, S* out, int64_t ldout,
                        const Epilogue& ep, hipStream_t s) {
 #define CASE(N)                                                                               \
   if (p.n3 == N) {                                                                            \
     constexpr int CT = kColThreads / lane_group(N);                                           \
     dim3 grid((p.ncols + CT - 1) / CT, nb);                                                   \
-    hipLaunchKernelGGL((k_col_fwd_reg<N, C>), grid, dim3(kColThreads), 0, s, p,               \
+    hipLaunchKernelGGL((k_col_fwd_reg<N, C, S>), grid, dim3(kColThreads), 0, s, p,            \
                        axis_tw<C>(p.ax3), T, kin, in, ldin, prev, ldprev, out, ldout, ep.alpha,  \
                        ep.beta, ep.gamma, ep.coef);                                           \
     return hipGetLastError();                                                                 \
@@ -576,6 +578,17 @@ hipError_t launch_fft_col_fwd_reg32(const BoxPlan& p, int nb, const float2* T, c
                                     int64_t ldprev, float2* out, int64_t ldout, const Epilogue& ep,
                                     hipStream_t s) {
   return col_fwd_reg<float2>(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, ep, s);
+}
+
+hipError_t launch_fft_col_inv_reg16(const BoxPlan& p, int nb, const bf16c* psi, int64_t ldpsi,
+                                    float2* T, hipStream_t s) {
+  return col_inv_reg<float2, bf16c>(p, nb, psi, ldpsi, T, s);
+}
+hipError_t launch_fft_col_fwd_reg16(const BoxPlan& p, int nb, const float2* T, const float* kin,
+                                    const bf16c* in, int64_t ldin, const bf16c* prev,
+                                    int64_t ldprev, bf16c* out, int64_t ldout, const Epilogue& ep,
+                                    hipStream_t s) {
+  return col_fwd_reg<float2, bf16c>(p, nb, T, kin, in, ldin, prev, ldprev, out, ldout, ep, s);
 }
 
 hipError_t launch_fft_plane_reg(const BoxPlan& p, int variant, int nb, const double* vscaled,

@@ -104,11 +104,11 @@ __device__ __forceinline__ void mfma_stage(const float2* As, int pa, const float
 
 // C = alpha A B + beta C; A m x k (lda), B k x n (ldb), complex64 column-major.
 // Workgroup tile (32 TM) x (32 TN), 4 waves in 2 x 2.
-template <int MODE, int TM, int TN>
+template <int MODE, int TM, int TN, class SC = float2>
 __device__ __forceinline__ void gemm_nn32_tile(int64_t M, int64_t N, int64_t K, float alpha,
                                                const float2* __restrict__ A, int64_t lda,
                                                const float2* __restrict__ B, int64_t ldb,
-                                               float beta, float2* __restrict__ C, int64_t ldc,
+                                               float beta, SC* __restrict__ C, int64_t ldc,
                                                int bx, int by) {
   constexpr int Kc = KC<MODE>::value;
   constexpr int BM = 32 * TM, BN = 32 * TN;
@@ -176,11 +176,11 @@ __device__ __forceinline__ void gemm_nn32_tile(int64_t M, int64_t N, int64_t K, 
         if (i < M && j < N) {
           float2 v = make_float2(alpha * ar[ti][tj][r], alpha * ai[ti][tj][r]);
           if (beta != 0.f) {
-            const float2 c = C[i + j * ldc];
+            const float2 c = ld_c(C[i + j * ldc]);
             v.x += beta * c.x;
             v.y += beta * c.y;
           }
-          C[i + j * ldc] = v;
+          C[i + j * ldc] = st_c<SC>(v);
         }
       }
 }
@@ -211,24 +211,24 @@ __device__ __forceinline__ bool xcd_panel_tile(int L, int tiles_m, int tiles_n, 
   return true;
 }
 
-template <int MODE>
+template <int MODE, class SC = float2>
 __global__ void __launch_bounds__(kThreads)
 k_gemm_nn32(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restrict__ A,
             int64_t lda, const float2* __restrict__ B, int64_t ldb, float beta,
-            float2* __restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
+            SC* __restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
   int bx, by;
   if (!xcd_panel_tile(blockIdx.x, tiles_m, tiles_n, &bx, &by)) return;
-  gemm_nn32_body<MODE>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
+  gemm_nn32_tile<MODE, 2, 2, SC>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
 }
 
-template <int MODE>
+template <int MODE, class SC = float2>
 __global__ void __launch_bounds__(kThreads)
 k_gemm_nn32_tall(int64_t M, int64_t N, int64_t K, float alpha, const float2* __restrict__ A,
                  int64_t lda, const float2* __restrict__ B, int64_t ldb, float beta,
-                 float2* __restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
+                 SC* __restrict__ C, int64_t ldc, int tiles_m, int tiles_n) {
   int bx, by;
   if (!xcd_panel_tile(blockIdx.x, tiles_m, tiles_n, &bx, &by)) return;
-  gemm_nn32_tile<MODE, 4, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
+  gemm_nn32_tile<MODE, 4, 2, SC>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bx, by);
 }
 
 // ---- P^H psi with FP32 operands on the bf16 matrix cores.
@@ -375,12 +375,13 @@ __device__ __forceinline__ void gemm_cn32_b3_body(int64_t M, int64_t N, int64_t 
 }
 
 // Partial (split z over K) A^H B; A k x m (lda), B k x n (ldb); out ld = M.
-template <int MODE>
+template <int MODE, class SB = float2>
 __device__ __forceinline__ void gemm_cn32_body(int64_t M, int64_t N, int64_t K, int64_t ksplit,
                                                const float2* __restrict__ A, int64_t lda,
-                                               const float2* __restrict__ B, int64_t ldb,
+                                               const SB* __restrict__ B, int64_t ldb,
                                                float2* __restrict__ out, int bx, int by, int bz) {
   if constexpr (MODE == MODE_F32) {
+    static_assert(sizeof(SB) == sizeof(float2), "FP32 operands only");
     gemm_cn32_b3_body(M, N, K, ksplit, A, lda, B, ldb, out, bx, by, bz);
     return;
   }
@@ -417,7 +418,7 @@ __device__ __forceinline__ void gemm_cn32_body(int64_t M, int64_t N, int64_t K, 
       const int e = tid + q * kThreads;
       const int jj = e / Kc, kk = e - jj * Kc;
       const int64_t gj = j0 + jj, gk = k0 + kk;
-      rb[q] = (gj < N && gk < ke) ? B[gk + gj * ldb] : make_float2(0.f, 0.f);
+      rb[q] = (gj < N && gk < ke) ? ld_c(B[gk + gj * ldb]) : make_float2(0.f, 0.f);
     }
   };
   if (kb < ke) fetch(kb);
@@ -623,14 +624,14 @@ __device__ __forceinline__ bool xcd_split_tile(int L, int tiles_m, int tiles_n, 
   return true;
 }
 
-template <int MODE>
+template <int MODE, class SB = float2>
 __global__ void __launch_bounds__(kThreads)
 k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __restrict__ A,
-            int64_t lda, const float2* __restrict__ B, int64_t ldb, float2* __restrict__ out,
+            int64_t lda, const SB* __restrict__ B, int64_t ldb, float2* __restrict__ out,
             int tiles_m, int tiles_n, int nsplit) {
   int bx, by, bz;
   if (!xcd_split_tile(blockIdx.x, tiles_m, tiles_n, nsplit, &bx, &by, &bz)) return;
-  gemm_cn32_body<MODE>(M, N, K, ksplit, A, lda, B, ldb, out, bx, by, bz);
+  gemm_cn32_body<MODE, SB>(M, N, K, ksplit, A, lda, B, ldb, out, bx, by, bz);
 }
 
 // C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M] (FP64 sum, fixed order), rounded.
@@ -750,6 +751,44 @@ hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double al
   const int64_t tot = m * n;
   hipLaunchKernelGGL(k_splitk_reduce32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, n,
                      (int)p.nsplit, (const float2*)work, alpha, alpha_dev, rowscale, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_cn32_s16(int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
+                                int64_t lda, const bf16c* B, int64_t ldb, float2* C, int64_t ldc,
+                                const double* rowscale, float2* work, hipStream_t s,
+                                const double* alpha_dev, int target) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (target < 1 || target > kTargetBlocks) target = kTargetBlocks;
+  const SplitPlan p = split_plan32<MODE_BF16>(m, n, k, target);
+  const dim3 grid((unsigned)(kXcds * p.tiles_m * p.tiles_n * ((p.nsplit + kXcds - 1) / kXcds)));
+  hipLaunchKernelGGL((k_gemm_cn32<MODE_BF16, bf16c>), grid, dim3(kThreads), 0, s, m, n, k,
+                     p.ksplit, A, lda, B, ldb, work, (int)p.tiles_m, (int)p.tiles_n,
+                     (int)p.nsplit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = m * n;
+  hipLaunchKernelGGL(k_splitk_reduce32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, n,
+                     (int)p.nsplit, (const float2*)work, alpha, alpha_dev, rowscale, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn32_s16(int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
+                                int64_t lda, const float2* B, int64_t ldb, double beta, bf16c* C,
+                                int64_t ldc, hipStream_t s, int tile) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int tn = (int)((n + kBN - 1) / kBN);
+  if (tile == 1) {
+    const int tm = (int)((m + 2 * kBM - 1) / (2 * kBM));
+    const dim3 grid((unsigned)(kXcds * tn * ((tm + kXcds - 1) / kXcds)));
+    hipLaunchKernelGGL((k_gemm_nn32_tall<MODE_BF16, bf16c>), grid, dim3(kThreads), 0, s, m, n, k,
+                       (float)alpha, A, lda, B, ldb, (float)beta, C, ldc, tm, tn);
+    return hipGetLastError();
+  }
+  const int tm = (int)((m + kBM - 1) / kBM);
+  const dim3 grid((unsigned)(kXcds * tn * ((tm + kXcds - 1) / kXcds)));
+  hipLaunchKernelGGL((k_gemm_nn32<MODE_BF16, bf16c>), grid, dim3(kThreads), 0, s, m, n, k,
+                     (float)alpha, A, lda, B, ldb, (float)beta, C, ldc, tm, tn);
   return hipGetLastError();
 }
 

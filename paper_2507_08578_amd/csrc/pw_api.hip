@@ -251,6 +251,50 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
   return PW_OK;
 }
 
+// H application on bf16-pair blocks: the register column kernels read and
+// write bf16 pairs (FP32 arithmetic, FP32 column intermediate), the
+// projector products take the block operand straight from bf16 storage
+// (bf16 MFMA operands, FP32 accumulation, complex64 cprj):
+// out = alpha (H in) + beta in + gamma prev, coef as in ham_apply.
+pw_status ham_apply16(pw_ham* h, int64_t nb, const bf16c* in, int64_t ldin, bf16c* out,
+                      int64_t ldout, double alpha, double beta, double gamma, const bf16c* prev,
+                      int64_t ldprev, const double* coef = nullptr) {
+  pw_ctx* c = h->ctx;
+  hipStream_t s = c->stream;
+  if (!h->reg_col_ok)
+    return fail(c, PW_ERR_UNSUPPORTED, "BF16 block storage needs the register column kernels");
+  if (h->nproj > 0) {
+    StageScope sc(c, PW_STAGE_PROJ_LP);
+    HIPCHK(c, launch_gemm_cn32_s16(h->nproj, nb, h->npw, alpha, h->proj32, h->npw, in, ldin,
+                                   h->cprj32, h->nproj, h->ekb_dev, h->work32, s, coef,
+                                   h->gemm_target));
+  }
+  const Epilogue ep{alpha, beta, gamma, coef};
+  for (int64_t c0 = 0; c0 < nb; c0 += h->chunk) {
+    const int nc = (int)std::min<int64_t>(h->chunk, nb - c0);
+    {
+      StageScope sc(c, PW_STAGE_FFT_COL_INV_LP);
+      HIPCHK(c, launch_fft_col_inv_reg16(h->plan, nc, in + c0 * ldin, ldin, h->T32, s));
+    }
+    {
+      StageScope sc(c, PW_STAGE_FFT_PLANE_LP);
+      HIPCHK(c, launch_fft_plane32(h->plan, h->cfg, nc, h->vs32, h->T32, s));
+    }
+    {
+      StageScope sc(c, PW_STAGE_FFT_COL_FWD_LP);
+      HIPCHK(c, launch_fft_col_fwd_reg16(h->plan, nc, h->T32, h->kin32, in + c0 * ldin, ldin,
+                                         prev ? prev + c0 * ldprev : nullptr, ldprev,
+                                         out + c0 * ldout, ldout, ep, s));
+    }
+  }
+  if (h->nproj > 0) {
+    StageScope sc(c, PW_STAGE_NONLOCAL_LP);
+    HIPCHK(c, launch_gemm_nn32_s16(h->npw, nb, h->nproj, 1.0, h->proj32, h->npw, h->cprj32,
+                                   h->nproj, 1.0, out, ldout, s, h->nn_tile32));
+  }
+  return PW_OK;
+}
+
 // In-place right multiplication of a block by the nb x nb matrix m (ld nb), via blk.
 pw_status rotate_block(pw_ham* h, int64_t nb, cplx* y, int64_t ld, const cplx* m) {
   pw_ctx* c = h->ctx;
@@ -830,11 +874,15 @@ pw_status time_apply(pw_ham* h, pw_prec prec, int64_t nb, void* in, void* out, i
   std::vector<double> v;
   for (int r = -1; r < reps; ++r) {
     HIPCHK(c, hipEventRecord(a.e, c->stream));
-    pw_status st = prec == PW_FP64
-                       ? ham_apply(h, nb, static_cast<const cplx*>(in), h->npw,
-                                   static_cast<cplx*>(out), h->npw, 1.0, 0.0, 0.0, nullptr, 0)
-                       : ham_apply32(h, prec == PW_BF16, nb, static_cast<const float2*>(in), h->npw,
-                                     static_cast<float2*>(out), h->npw, 1.0, 0.0, 0.0, nullptr, 0);
+    pw_status st =
+        prec == PW_FP64
+            ? ham_apply(h, nb, static_cast<const cplx*>(in), h->npw, static_cast<cplx*>(out), h->npw,
+                        1.0, 0.0, 0.0, nullptr, 0)
+        : prec == PW_BF16
+            ? ham_apply16(h, nb, static_cast<const bf16c*>(in), h->npw, static_cast<bf16c*>(out),
+                          h->npw, 1.0, 0.0, 0.0, nullptr, 0)
+            : ham_apply32(h, 0, nb, static_cast<const float2*>(in), h->npw,
+                          static_cast<float2*>(out), h->npw, 1.0, 0.0, 0.0, nullptr, 0);
     if (st != PW_OK) return st;
     HIPCHK(c, hipEventRecord(b.e, c->stream));
     HIPCHK(c, hipEventSynchronize(b.e));
@@ -1263,12 +1311,17 @@ pw_status pw_apply_h(pw_ham* h, pw_prec prec, int64_t nb, const void* psi, int64
   if ((st = check_hot(h, prec, nb)) != PW_OK) return st;
   if ((st = check_block(h, psi, ldpsi, "psi")) != PW_OK) return st;
   if ((st = check_block(h, hpsi, ldh, "hpsi")) != PW_OK) return st;
-  const int64_t elem = prec == PW_FP64 ? (int64_t)sizeof(cplx) : (int64_t)sizeof(float2);
+  const int64_t elem = prec == PW_FP64 ? (int64_t)sizeof(cplx)
+                     : prec == PW_FP32 ? (int64_t)sizeof(float2)
+                                       : (int64_t)sizeof(bf16c);
   if (ranges_overlap(psi, ldpsi, hpsi, ldh, h->npw, nb, elem))
     return fail(h->ctx, PW_ERR_INVALID_ARG, "psi and hpsi overlap");
   HIPCHK(h->ctx, hipSetDevice(h->ctx->device));
-  if (prec != PW_FP64)
-    return ham_apply32(h, prec == PW_BF16, nb, static_cast<const float2*>(psi), ldpsi,
+  if (prec == PW_BF16)
+    return ham_apply16(h, nb, static_cast<const bf16c*>(psi), ldpsi, static_cast<bf16c*>(hpsi), ldh,
+                       1.0, 0.0, 0.0, nullptr, 0);
+  if (prec == PW_FP32)
+    return ham_apply32(h, 0, nb, static_cast<const float2*>(psi), ldpsi,
                        static_cast<float2*>(hpsi), ldh, 1.0, 0.0, 0.0, nullptr, 0);
   return ham_apply(h, nb, static_cast<const cplx*>(psi), ldpsi, static_cast<cplx*>(hpsi), ldh, 1.0,
                    0.0, 0.0, nullptr, 0);
@@ -1349,6 +1402,35 @@ pw_status pw_cheb_filter(pw_ham* h, pw_prec prec, int32_t degree, double a, doub
   const double e = 0.5 * (b - a), c = 0.5 * (b + a);
   double sigma = e / (a0 - c);
   const double tau = 2.0 / sigma;
+  if (prec == PW_BF16) {
+    // the block enters and leaves in FP64; the recurrence runs on bf16-pair
+    // copies (in the memory of the complex64 work blocks)
+    bf16c* buf[2] = {reinterpret_cast<bf16c*>(h->blk32[0]), reinterpret_cast<bf16c*>(h->blk32[1])};
+    const int64_t l16 = h->npw;
+    hipStream_t s = h->ctx->stream;
+    {
+      StageScope sc(h->ctx, PW_STAGE_MISC);
+      HIPCHK(h->ctx, launch_block_to_b16(h->npw, nb, y, ld, buf[0], l16, s));
+      if (hx)
+        HIPCHK(h->ctx, launch_axpby_to_b16(h->npw, nb, sigma / e, hx, ldhx, -sigma * c / e, y, ld,
+                                           buf[1], l16, s));
+    }
+    if (!hx && (st = ham_apply16(h, nb, buf[0], l16, buf[1], l16, sigma / e, -sigma * c / e, 0.0,
+                                 nullptr, 0)) != PW_OK)
+      return st;
+    for (int i = 2; i <= degree; ++i) {
+      const double sn = 1.0 / (tau - sigma);
+      const int cur = (i - 1) & 1, nxt = i & 1;
+      const double al = 2.0 * sn / e;
+      if ((st = ham_apply16(h, nb, buf[cur], l16, buf[nxt], l16, al, -al * c, -sigma * sn, buf[nxt],
+                            l16)) != PW_OK)
+        return st;
+      sigma = sn;
+    }
+    StageScope sc(h->ctx, PW_STAGE_MISC);
+    HIPCHK(h->ctx, launch_block_b16_to_f64(h->npw, nb, buf[degree & 1], l16, y, ld, s));
+    return PW_OK;
+  }
   if (prec != PW_FP64) {
     // the block enters and leaves in FP64; the recurrence runs on complex64 copies
     const int bf16 = prec == PW_BF16;

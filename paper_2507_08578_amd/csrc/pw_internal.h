@@ -11,6 +11,41 @@
 
 typedef double2 cplx;   // interleaved (re, im), 16 bytes
 
+// A complex value stored as an interleaved pair of bfloat16 bit patterns
+// (the BF16 storage of pw_apply_h / pw_cheb_filter blocks; arithmetic
+// widens to FP32, stores round to nearest even).
+struct __attribute__((aligned(4))) bf16c {
+  uint16_t re, im;
+};
+
+// Loads and stores of block elements whose storage type may differ from the
+// arithmetic type: identity for complex128 / complex64, widening from and
+// rounding (to nearest even) to bf16 pairs.
+__device__ __forceinline__ double2 ld_c(const double2& v) { return v; }
+__device__ __forceinline__ float2 ld_c(const float2& v) { return v; }
+__device__ __forceinline__ float2 ld_c(const bf16c& v) {
+  return make_float2(__uint_as_float((uint32_t)v.re << 16), __uint_as_float((uint32_t)v.im << 16));
+}
+template <class S, class C>
+__device__ __forceinline__ S st_c(const C& v) {
+  return v;
+}
+template <>
+__device__ __forceinline__ bf16c st_c<bf16c, float2>(const float2& v) {
+  bf16c r;
+  r.re = __builtin_bit_cast(uint16_t, (__bf16)v.x);
+  r.im = __builtin_bit_cast(uint16_t, (__bf16)v.y);
+  return r;
+}
+template <>
+__device__ __forceinline__ bf16c st_c<bf16c, double2>(const double2& v) {   // one rounding
+  bf16c r;
+  r.re = __builtin_bit_cast(uint16_t, (__bf16)v.x);
+  r.im = __builtin_bit_cast(uint16_t, (__bf16)v.y);
+  return r;
+}
+
+
 // ---------------------------------------------------------------------------
 // FFT plan along one axis: N = product of radices, each in {2, 3, 4, 5, 8}.
 // ---------------------------------------------------------------------------
@@ -255,6 +290,14 @@ hipError_t launch_fft_col_fwd_reg32(const BoxPlan& p, int nb, const float2* T, c
                                     const float2* in, int64_t ldin, const float2* prev,
                                     int64_t ldprev, float2* out, int64_t ldout, const Epilogue& ep,
                                     hipStream_t s);
+// The same with the blocks (psi, in, prev, out) stored as bf16 pairs; FP32
+// arithmetic and FP32 column intermediate T.
+hipError_t launch_fft_col_inv_reg16(const BoxPlan& p, int nb, const bf16c* psi, int64_t ldpsi,
+                                    float2* T, hipStream_t s);
+hipError_t launch_fft_col_fwd_reg16(const BoxPlan& p, int nb, const float2* T, const float* kin,
+                                    const bf16c* in, int64_t ldin, const bf16c* prev,
+                                    int64_t ldprev, bf16c* out, int64_t ldout, const Epilogue& ep,
+                                    hipStream_t s);
 
 // Split-K C = alpha diag(rowscale) A^H B + beta C (see pw_gemm_cn).  `work`
 // holds splits*m*n cplx (gemm_cn_work_elems); with work == null the product
@@ -287,6 +330,16 @@ hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double al
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
                             int64_t ldc, hipStream_t s, int tile = 0, const uint16_t* a3 = nullptr,
                             int kp3 = 0);
+// bf16 operands with the block operand stored as bf16 pairs: A^H B with B a
+// bf16-pair block (split-K partials and result complex64, as launch_gemm_cn32
+// with bf16 = 1), and C (bf16 pairs) = alpha A B + beta C with A, B complex64.
+hipError_t launch_gemm_cn32_s16(int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
+                                int64_t lda, const bf16c* B, int64_t ldb, float2* C, int64_t ldc,
+                                const double* rowscale, float2* work, hipStream_t s,
+                                const double* alpha_dev = nullptr, int target_blocks = 2048);
+hipError_t launch_gemm_nn32_s16(int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
+                                int64_t lda, const float2* B, int64_t ldb, double beta, bf16c* C,
+                                int64_t ldc, hipStream_t s, int tile = 0);
 // a3[(t 2 + c) rows kp + i kp + k] = term t of part c of P[i + k ldp] split
 // into three bf16 terms (zero for nk <= k < kp; kp a multiple of 8).
 hipError_t launch_split3_t(int64_t rows, int nk, int kp, const float2* P, int64_t ldp, uint16_t* P3,
@@ -301,6 +354,15 @@ hipError_t launch_axpby_to_f32(int64_t rows, int64_t cols, double a, const cplx*
                                double b, const cplx* y, int64_t ldy, float2* out, int64_t ldo,
                                hipStream_t s, const double* coef = nullptr);
 hipError_t launch_real_to_f32(int64_t n, const double* src, double scale, float* dst, hipStream_t s);
+// complex128 <-> bf16-pair blocks (one rounding to nearest even; widening is exact)
+hipError_t launch_block_to_b16(int64_t rows, int64_t cols, const cplx* x, int64_t ldx, bf16c* y,
+                               int64_t ldy, hipStream_t s);
+hipError_t launch_block_b16_to_f64(int64_t rows, int64_t cols, const bf16c* x, int64_t ldx, cplx* y,
+                                   int64_t ldy, hipStream_t s);
+// out = a x + b y rounded to bf16 pairs (x, y complex128); coef overrides a, b
+hipError_t launch_axpby_to_b16(int64_t rows, int64_t cols, double a, const cplx* x, int64_t ldx,
+                               double b, const cplx* y, int64_t ldy, bf16c* out, int64_t ldo,
+                               hipStream_t s, const double* coef = nullptr);
 hipError_t launch_tw_to_f32(int n, const cplx* src, float2* dst, hipStream_t s);
 
 // Dense kernels (dense_kernels.hip)
