@@ -6,11 +6,12 @@
 //   MODE_F32 : FP32 operands, each split exactly into three bfloat16 terms,
 //              products on v_mfma_f32_16x16x32_bf16 (six term products per
 //              real product, FP32 accumulation: the accuracy of FP32 products
-//              at 6/16 of the FP32 MFMA time).  P^H psi (gemm_cn32) splits
-//              both operands when their tiles are staged in LDS; P C
-//              (gemm_nn32_b3) reads P's terms from a copy made once per
-//              handle and splits C per stage.  Without that copy P C runs on
-//              v_mfma_f32_16x16x4f32 with FP32 operands.
+//              at 6/16 of the FP32 MFMA time).  P^H psi (gemm_cn32_s3)
+//              and P C (gemm_nn32_s3) read P's terms from copies made once
+//              per handle; P^H psi splits psi per stage, and the reduction
+//              that forms C stores C's terms.  Gram matrices Y^H Y
+//              (gemm_cn32) split both operands per stage.  Without the copies
+//              P C runs on v_mfma_f32_16x16x4f32 with FP32 operands.
 //   MODE_BF16: v_mfma_f32_16x16x32_bf16, operands rounded to bfloat16
 //              (round to nearest even) when the MFMA operands are formed from
 //              the FP32 tiles staged in LDS.
@@ -250,6 +251,14 @@ __device__ __forceinline__ f4 mfma6(const bf8 (&x)[3], const bf8 (&y)[3], f4 acc
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[0], y[0], acc, 0, 0, 0);
 }
 
+// x = h + m + l as above (round to nearest even at each step).
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r = x - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
+}
+
 // Split two consecutive-K complex values of one operand row and store the
 // six bf16 pairs (term t, part re/im) at row `row`, K offset kq (even).
 __device__ __forceinline__ void b3_store2(__bf16* L, int row, int kq, float4 v) {
@@ -260,12 +269,11 @@ __device__ __forceinline__ void b3_store2(__bf16* L, int row, int kq, float4 v) 
     bf2 h, m, l;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const __bf16 xh = (__bf16)x[c][e];
-      const float r = x[c][e] - (float)xh;
-      const __bf16 xm = (__bf16)r;
+      __bf16 xh, xm, xl;
+      split3(x[c][e], xh, xm, xl);
       h[e] = xh;
       m[e] = xm;
-      l[e] = (__bf16)(r - (float)xm);
+      l[e] = xl;
     }
     *reinterpret_cast<bf2*>(L + (0 * 2 + c) * kB3Plane + row * kB3Pitch + kq) = h;
     *reinterpret_cast<bf2*>(L + (1 * 2 + c) * kB3Plane + row * kB3Pitch + kq) = m;
@@ -279,6 +287,50 @@ __device__ __forceinline__ void b3_frag(const __bf16* L, int c, int r0, int lr, 
 #pragma unroll
   for (int t = 0; t < 3; ++t)
     f[t] = *reinterpret_cast<const bf8*>(L + (t * 2 + c) * kB3Plane + (r0 + lr) * kB3Pitch + 8 * lk);
+}
+
+// ---- Stored three-term operands.  A matrix with R rows and contraction
+// length K is kept as chunks of 32 K values: chunk (r, s) holds row r, K
+// 32 s .. 32 s + 31, as six planes of 32 bf16 in the order q = 2 t + c (term
+// t, part c = re / im), 384 bytes; the chunks of a row follow each other:
+//   X3[((r nst + s) 6 + q) 32 + k % 32],  nst = ceil(K / 32).
+// Rows are padded to a multiple of 64 and K to 32 nst, with zeros, so the
+// 64-row x 32-K tiles of the products are read without bounds checks.
+constexpr int kS3Chunk = 6 * 32;   // bf16 per chunk
+
+__host__ __device__ inline int64_t s3_nst(int64_t k) { return (k + 31) / 32; }
+__host__ __device__ inline int64_t s3_rows(int64_t r) { return (r + 63) / 64 * 64; }
+__device__ __forceinline__ int64_t s3_index(int64_t r, int64_t k, int q, int64_t nst) {
+  return ((r * nst + (k >> 5)) * 6 + q) * 32 + (k & 31);
+}
+
+// Thread tid's part of a 64-row x 32-K tile: row tid / 4, K 8 (tid % 4) .. + 7
+// of the six planes (16-byte pieces of its chunk; `chunk` points at that K
+// offset of the row's current chunk).
+__device__ __forceinline__ void s3_load(const __bf16* __restrict__ chunk, bf8 (&v)[6]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) v[q] = *reinterpret_cast<const bf8*>(chunk + q * 32);
+}
+
+__device__ __forceinline__ void s3_put(__bf16* L, int row, int k8, const bf8 (&v)[6]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) *reinterpret_cast<bf8*>(L + q * kB3Plane + row * kB3Pitch + k8) = v[q];
+}
+
+// Eight consecutive-K complex values of one row, split into the six planes.
+__device__ __forceinline__ void s3_split8(const float2 (&x)[8], bf8 (&v)[6]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    __bf16 h, m, l;
+    split3(x[e].x, h, m, l);
+    v[0][e] = h;
+    v[2][e] = m;
+    v[4][e] = l;
+    split3(x[e].y, h, m, l);
+    v[1][e] = h;
+    v[3][e] = m;
+    v[5][e] = l;
+  }
 }
 
 // Partial (split z over K) A^H B as gemm_cn32_body, FP32 operands in three
@@ -338,6 +390,95 @@ __device__ __forceinline__ void gemm_cn32_b3_body(int64_t M, int64_t N, int64_t 
     for (int q = 0; q < 4; ++q) {
       b3_store2(LA, (tid >> 4) + 16 * q, kq, ra[q]);
       b3_store2(LB, (tid >> 4) + 16 * q, kq, rb[q]);
+    }
+    __syncthreads();
+    if (k0 + kB3K < ke) fetch(k0 + kB3K);
+    bf8 a[2][2][3], b[2][2][3];   // [tile][re, im][term]
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        b3_frag(LA, c, wi * 32 + t * 16, lr, lk, a[t][c]);
+        b3_frag(LB, c, wj * 32 + t * 16, lr, lk, b[t][c]);
+      }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        acc[0][ti][tj] = mfma6(a[ti][0], b[tj][0], acc[0][ti][tj]);
+        acc[0][ti][tj] = mfma6(a[ti][1], b[tj][1], acc[0][ti][tj]);
+        acc[1][ti][tj] = mfma6(a[ti][0], b[tj][1], acc[1][ti][tj]);
+        acc[2][ti][tj] = mfma6(a[ti][1], b[tj][0], acc[2][ti][tj]);
+      }
+    __syncthreads();
+  }
+  float2* o = out + (int64_t)bz * M * N;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wi * 32 + ti * 16 + 4 * lk + r;
+        const int64_t j = j0 + wj * 32 + tj * 16 + lr;
+        if (i < M && j < N)
+          o[i + j * M] = make_float2(acc[0][ti][tj][r], acc[1][ti][tj][r] - acc[2][ti][tj][r]);
+      }
+}
+
+// Partial (split z over K) A^H B with A given as its stored three-term copy
+// A3 (rows = the M columns of A, contraction K; the chunk layout above) and B
+// (K x N, ldb) complex64, split per stage: thread tid stages chunk row tid / 4
+// of A3 and column tid / 4 of B, K 8 (tid % 4) .. + 7 of the stage.  The same
+// products as gemm_cn32_b3_body in the same order, so the same result.
+// Columns j >= N are read from column N - 1 (they feed only outputs that are
+// not stored); K beyond ke reads zero from B.
+__device__ __forceinline__ void gemm_cn32_s3_body(int64_t M, int64_t N, int64_t K, int64_t ksplit,
+                                                  const __bf16* __restrict__ A3,
+                                                  const float2* __restrict__ B, int64_t ldb,
+                                                  float2* __restrict__ out, int bx, int by, int bz) {
+  __shared__ __align__(16) __bf16 LA[6 * kB3Plane];
+  __shared__ __align__(16) __bf16 LB[6 * kB3Plane];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int row = tid >> 2, k8 = (tid & 3) * 8;
+  const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
+  const int64_t kb = (int64_t)bz * ksplit;
+  const int64_t ke = min(K, kb + ksplit);
+  const int64_t nst = s3_nst(K);
+  f4 acc[3][2][2];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) f4zero(acc[q][a][b]);
+  const __bf16* pa = A3 + ((i0 + row) * nst + (kb >> 5)) * kS3Chunk + k8;
+  const int64_t col = min(j0 + row, N - 1);
+  const float2* pb = B + col * ldb + kb + k8;
+  bf8 ra[6];
+  float2 xb[8];
+  auto fetch = [&](int64_t k0) {
+    s3_load(pa, ra);
+    pa += kS3Chunk;
+    if (k0 + kB3K <= ke) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xb[e] = pb[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        xb[e] = k0 + k8 + e < ke ? pb[e] : make_float2(0.f, 0.f);
+    }
+    pb += kB3K;
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kB3K) {
+    s3_put(LA, row, k8, ra);
+    {
+      bf8 vb[6];
+      s3_split8(xb, vb);
+      s3_put(LB, row, k8, vb);
     }
     __syncthreads();
     if (k0 + kB3K < ke) fetch(k0 + kB3K);
@@ -454,29 +595,26 @@ __device__ __forceinline__ void gemm_cn32_body(int64_t M, int64_t N, int64_t K, 
       }
 }
 
-// ---- P C with FP32 operands on the bf16 matrix cores.  P is a constant of
-// the handle, so its three-term split is formed once (k_split3_t), transposed
-// so that the contraction index (projector) is contiguous:
-//   P3[(t 2 + c) rows kp + i kp + k]  (term t < 3, part c = re / im, plane
-//   wave i, projector k < kp = nproj rounded up to 8; zero for k >= nproj).
-// C is split per stage as the P^H psi kernel splits its operands.
+// ---- P C with FP32 operands on the bf16 matrix cores, both operands in
+// their stored three-term copies: A3 (rows = the M rows of P, contraction K)
+// and B3 (rows = the N columns of C, contraction K), formed once per handle
+// (P) and by the reduction that produces C.  Nothing is split or bounds-
+// checked in the K loop: every stage stages six 16-byte pieces of each.
 
-// out = alpha P C + beta out on a 64 x 64 tile (by: plane waves, bx: bands).
-// Thread tid stages P3 row tid / 4, projectors 8 (tid % 4) .. + 7 of each of
-// the six planes (16-byte loads), and four consecutive-projector pairs of C.
-__device__ __forceinline__ void gemm_nn32_b3_body(int64_t M, int64_t N, int64_t K, float alpha,
-                                                  const __bf16* __restrict__ P3, int kp,
-                                                  const float2* __restrict__ B, int64_t ldb,
-                                                  float beta, float2* __restrict__ C, int64_t ldc,
-                                                  int bx, int by) {
+// out = alpha P C + beta out on a 64 x 64 tile (by: rows of P, bx: columns of C).
+__device__ __forceinline__ void gemm_nn32_s3_body(int64_t M, int64_t N, int64_t K, float alpha,
+                                                  const __bf16* __restrict__ A3,
+                                                  const __bf16* __restrict__ B3, float beta,
+                                                  float2* __restrict__ C, int64_t ldc, int bx,
+                                                  int by) {
   __shared__ __align__(16) __bf16 LA[6 * kB3Plane];
   __shared__ __align__(16) __bf16 LB[6 * kB3Plane];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
   const int lr = lane & 15, lk = lane >> 4;
+  const int row = tid >> 2, k8 = (tid & 3) * 8;
   const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
-  const int arow = tid >> 2, acol = (tid & 3) * 8, kq = (tid & 15) * 2;
-  const int64_t gi = i0 + arow;
+  const int64_t nst = s3_nst(K);
   // acc[0] = ar br, acc[1] = ai bi, acc[2] = ar bi + ai br
   f4 acc[3][2][2];
 #pragma unroll
@@ -485,45 +623,21 @@ __device__ __forceinline__ void gemm_nn32_b3_body(int64_t M, int64_t N, int64_t 
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) f4zero(acc[q][a][b]);
-  bf8 pa[6];
-  float4 rb[4];
-  auto fetch = [&](int64_t k0) {
-    const int64_t kk = k0 + acol;   // a multiple of 8, as kp: the whole 8-run is inside or outside
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      bf8 z;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
-      pa[q] = (gi < M && kk < kp)
-                  ? *reinterpret_cast<const bf8*>(P3 + (int64_t)q * M * kp + gi * kp + kk)
-                  : z;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t col = j0 + (tid >> 4) + 16 * q, gk = k0 + kq;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (col < N && gk < K) {
-        const float2 a = B[gk + col * ldb];
-        v.x = a.x;
-        v.y = a.y;
-      }
-      if (col < N && gk + 1 < K) {
-        const float2 b = B[gk + 1 + col * ldb];
-        v.z = b.x;
-        v.w = b.y;
-      }
-      rb[q] = v;
-    }
-  };
-  fetch(0);
-  for (int64_t k0 = 0; k0 < K; k0 += kB3K) {
-#pragma unroll
-    for (int q = 0; q < 6; ++q)
-      *reinterpret_cast<bf8*>(LA + q * kB3Plane + arow * kB3Pitch + acol) = pa[q];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) b3_store2(LB, (tid >> 4) + 16 * q, kq, rb[q]);
+  const __bf16* pa = A3 + (i0 + row) * nst * kS3Chunk + k8;
+  const __bf16* pb = B3 + (j0 + row) * nst * kS3Chunk + k8;
+  bf8 ra[6], rb[6];
+  s3_load(pa, ra);
+  s3_load(pb, rb);
+  for (int64_t st = 0; st < nst; ++st) {
+    s3_put(LA, row, k8, ra);
+    s3_put(LB, row, k8, rb);
     __syncthreads();
-    if (k0 + kB3K < K) fetch(k0 + kB3K);
+    if (st + 1 < nst) {
+      pa += kS3Chunk;
+      pb += kS3Chunk;
+      s3_load(pa, ra);
+      s3_load(pb, rb);
+    }
     bf8 a[2][2][3], b[2][2][3];   // [tile][re, im][term]
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -565,46 +679,49 @@ __device__ __forceinline__ void gemm_nn32_b3_body(int64_t M, int64_t N, int64_t 
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_gemm_nn32_b3(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __restrict__ P3, int kp,
-               const float2* __restrict__ B, int64_t ldb, float beta, float2* __restrict__ C,
-               int64_t ldc, int tiles_m, int tiles_n) {
+k_gemm_nn32_s3(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __restrict__ A3,
+               const __bf16* __restrict__ B3, float beta, float2* __restrict__ C, int64_t ldc,
+               int tiles_m, int tiles_n) {
   int bx, by;
   if (!xcd_panel_tile(blockIdx.x, tiles_m, tiles_n, &bx, &by)) return;
-  gemm_nn32_b3_body(M, N, K, alpha, P3, kp, B, ldb, beta, C, ldc, bx, by);
+  gemm_nn32_s3_body(M, N, K, alpha, A3, B3, beta, C, ldc, bx, by);
 }
 
-// P3 from P (rows x nk, ld ldp) through 64 x 64 LDS tiles: reads run along
-// the plane waves, writes along the projectors.
+// The stored three-term copy X3 of a complex64 matrix X (R rows, contraction
+// K; element (r, k) at X[r sr + k sk]), all s3_rows(R) x 32 nst entries
+// written (zero padding included).  A workgroup per 64-row panel and K chunk
+// (grid-strided over the chunks), through LDS: reads run along whichever
+// index is contiguous in X, writes along K within the chunks.
 __global__ void __launch_bounds__(256)
-k_split3_t(int64_t rows, int nk, int kp, const float2* __restrict__ P, int64_t ldp,
-           __bf16* __restrict__ P3) {
-  __shared__ float2 t[64][65];
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int k0 = blockIdx.y * 64;
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int kk = e >> 6, ii = e & 63;
-    const int64_t i = i0 + ii;
-    const int k = k0 + kk;
-    t[kk][ii] = (i < rows && k < nk) ? P[i + (int64_t)k * ldp] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int ii = e >> 6, kk = e & 63;
-    const int64_t i = i0 + ii;
-    const int k = k0 + kk;
-    if (i < rows && k < kp) {
-      const float2 v = t[kk][ii];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const float x = c == 0 ? v.x : v.y;
-        const __bf16 h = (__bf16)x;
-        const float r = x - (float)h;
-        const __bf16 m = (__bf16)r;
-        P3[(int64_t)(0 * 2 + c) * rows * kp + i * kp + k] = h;
-        P3[(int64_t)(1 * 2 + c) * rows * kp + i * kp + k] = m;
-        P3[(int64_t)(2 * 2 + c) * rows * kp + i * kp + k] = (__bf16)(r - (float)m);
-      }
+k_split3_s3(int64_t R, int64_t K, const float2* __restrict__ X, int64_t sr, int64_t sk,
+            __bf16* __restrict__ X3) {
+  __shared__ float2 t[64][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int64_t nst = s3_nst(K);
+  for (int64_t s = blockIdx.y; s < nst; s += gridDim.y) {
+    const int64_t k0 = s * 32;
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      const int rr = sr == 1 ? (e & 63) : (e >> 5);
+      const int kk = sr == 1 ? (e >> 6) : (e & 31);
+      const int64_t r = r0 + rr, k = k0 + kk;
+      t[rr][kk] = (r < R && k < K) ? X[r * sr + k * sk] : make_float2(0.f, 0.f);
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+      const int rr = e >> 5, kk = e & 31;
+      const float2 v = t[rr][kk];
+      __bf16* o = X3 + ((r0 + rr) * nst + s) * kS3Chunk + kk;
+      __bf16 h, m, l;
+      split3(v.x, h, m, l);
+      o[0 * 32] = h;
+      o[2 * 32] = m;
+      o[4 * 32] = l;
+      split3(v.y, h, m, l);
+      o[1 * 32] = h;
+      o[3 * 32] = m;
+      o[5 * 32] = l;
+    }
+    __syncthreads();
   }
 }
 
@@ -634,12 +751,24 @@ k_gemm_cn32(int64_t M, int64_t N, int64_t K, int64_t ksplit, const float2* __res
   gemm_cn32_body<MODE, SB>(M, N, K, ksplit, A, lda, B, ldb, out, bx, by, bz);
 }
 
-// C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M] (FP64 sum, fixed order), rounded.
+__global__ void __launch_bounds__(kThreads)
+k_gemm_cn32_s3(int64_t M, int64_t N, int64_t K, int64_t ksplit, const __bf16* __restrict__ A3,
+               const float2* __restrict__ B, int64_t ldb, float2* __restrict__ out, int tiles_m,
+               int tiles_n, int nsplit) {
+  int bx, by, bz;
+  if (!xcd_split_tile(blockIdx.x, tiles_m, tiles_n, nsplit, &bx, &by, &bz)) return;
+  gemm_cn32_s3_body(M, N, K, ksplit, A3, B, ldb, out, bx, by, bz);
+}
+
+// C[i + j ldc] = alpha rowscale[i] sum_z work[z][i + j M] (FP64 sum, fixed order), rounded;
+// with c3, also the stored three-term copy of the rounded C^T (rows = the N
+// columns of C, contraction M: the B operand of gemm_nn32_s3_body).
 __device__ __forceinline__ void splitk_reduce32_body(int64_t M, int64_t N, int nsplit,
                                                      const float2* __restrict__ work, double alpha,
                                                      const double* __restrict__ alpha_dev,
                                                      const double* __restrict__ rowscale,
-                                                     float2* __restrict__ C, int64_t ldc, int bx) {
+                                                     float2* __restrict__ C, int64_t ldc,
+                                                     __bf16* __restrict__ c3, int bx) {
   if (alpha_dev) alpha = alpha_dev[0];
   const int64_t idx = (int64_t)bx * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
@@ -651,14 +780,27 @@ __device__ __forceinline__ void splitk_reduce32_body(int64_t M, int64_t N, int n
     im += w.y;
   }
   const double s = alpha * (rowscale ? rowscale[i] : 1.0);
-  C[i + j * ldc] = make_float2((float)(s * re), (float)(s * im));
+  const float2 v = make_float2((float)(s * re), (float)(s * im));
+  C[i + j * ldc] = v;
+  if (c3) {
+    __bf16* o = c3 + s3_index(j, i, 0, s3_nst(M));
+    __bf16 h, m, l;
+    split3(v.x, h, m, l);
+    o[0 * 32] = h;
+    o[2 * 32] = m;
+    o[4 * 32] = l;
+    split3(v.y, h, m, l);
+    o[1 * 32] = h;
+    o[3 * 32] = m;
+    o[5 * 32] = l;
+  }
 }
 
 __global__ void k_splitk_reduce32(int64_t M, int64_t N, int nsplit, const float2* __restrict__ work,
                                   double alpha, const double* __restrict__ alpha_dev,
                                   const double* __restrict__ rowscale, float2* __restrict__ C,
-                                  int64_t ldc) {
-  splitk_reduce32_body(M, N, nsplit, work, alpha, alpha_dev, rowscale, C, ldc, blockIdx.x);
+                                  int64_t ldc, __bf16* __restrict__ c3) {
+  splitk_reduce32_body(M, N, nsplit, work, alpha, alpha_dev, rowscale, C, ldc, c3, blockIdx.x);
 }
 
 struct SplitPlan {
@@ -696,8 +838,12 @@ kb_gemm_cn32(const ItemDev* __restrict__ D, int sel_b, int nsplit_max) {
   if (d.nproj <= 0) return;
   const SplitPlan p = split_plan32<MODE>(d.nproj, d.nb, d.npw, d.gemm_target);
   if (zs >= p.nsplit || (int64_t)blockIdx.y >= p.tiles_m || (int64_t)blockIdx.x >= p.tiles_n) return;
-  gemm_cn32_body<MODE>(d.nproj, d.nb, d.npw, p.ksplit, d.proj32, d.npw, item_blk32(d, sel_b), d.npw,
-                       d.work32, blockIdx.x, blockIdx.y, zs);
+  if constexpr (MODE == MODE_F32)
+    gemm_cn32_s3_body(d.nproj, d.nb, d.npw, p.ksplit, reinterpret_cast<const __bf16*>(d.proj3c),
+                      item_blk32(d, sel_b), d.npw, d.work32, blockIdx.x, blockIdx.y, zs);
+  else
+    gemm_cn32_body<MODE>(d.nproj, d.nb, d.npw, p.ksplit, d.proj32, d.npw, item_blk32(d, sel_b),
+                         d.npw, d.work32, blockIdx.x, blockIdx.y, zs);
 }
 
 template <int MODE>
@@ -707,7 +853,8 @@ __global__ void kb_splitk_reduce32(const ItemDev* __restrict__ D, double alpha, 
   const SplitPlan p = split_plan32<MODE>(d.nproj, d.nb, d.npw, d.gemm_target);
   const double* alpha_dev = coef_step >= 0 ? d.coef + 3 * coef_step : nullptr;
   splitk_reduce32_body(d.nproj, d.nb, (int)p.nsplit, d.work32, alpha, alpha_dev, d.ekb, d.cprj32,
-                       d.nproj, blockIdx.x);
+                       d.nproj, MODE == MODE_F32 ? reinterpret_cast<__bf16*>(d.cprj3) : nullptr,
+                       blockIdx.x);
 }
 
 template <int MODE>
@@ -716,8 +863,9 @@ kb_gemm_nn32(const ItemDev* __restrict__ D, int sel_c) {
   const ItemDev& d = D[blockIdx.z];
   if (d.nproj <= 0 || (int64_t)blockIdx.y * kBM >= d.npw || (int64_t)blockIdx.x * kBN >= d.nb) return;
   if constexpr (MODE == MODE_F32)
-    gemm_nn32_b3_body(d.npw, d.nb, d.nproj, 1.f, reinterpret_cast<const __bf16*>(d.proj3), d.kp3,
-                      d.cprj32, d.nproj, 1.f, item_blk32(d, sel_c), d.npw, blockIdx.x, blockIdx.y);
+    gemm_nn32_s3_body(d.npw, d.nb, d.nproj, 1.f, reinterpret_cast<const __bf16*>(d.proj3),
+                      reinterpret_cast<const __bf16*>(d.cprj3), 1.f, item_blk32(d, sel_c), d.npw,
+                      blockIdx.x, blockIdx.y);
   else
     gemm_nn32_body<MODE>(d.npw, d.nb, d.nproj, 1.f, d.proj32, d.npw, d.cprj32, d.nproj, 1.f,
                          item_blk32(d, sel_c), d.npw, blockIdx.x, blockIdx.y);
@@ -750,7 +898,28 @@ hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double al
   if (e != hipSuccess) return e;
   const int64_t tot = m * n;
   hipLaunchKernelGGL(k_splitk_reduce32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, n,
-                     (int)p.nsplit, (const float2*)work, alpha, alpha_dev, rowscale, C, ldc);
+                     (int)p.nsplit, (const float2*)work, alpha, alpha_dev, rowscale, C, ldc,
+                     (__bf16*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_cn32_s3(int64_t m, int64_t n, int64_t k, double alpha, const uint16_t* a3,
+                               const float2* B, int64_t ldb, float2* C, int64_t ldc,
+                               const double* rowscale, float2* work, hipStream_t s,
+                               const double* alpha_dev, int target, uint16_t* c3) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (target < 1 || target > kTargetBlocks) target = kTargetBlocks;
+  const SplitPlan p = split_plan32<MODE_F32>(m, n, k, target);
+  const dim3 grid((unsigned)(kXcds * p.tiles_m * p.tiles_n * ((p.nsplit + kXcds - 1) / kXcds)));
+  hipLaunchKernelGGL(k_gemm_cn32_s3, grid, dim3(kThreads), 0, s, m, n, k, p.ksplit,
+                     reinterpret_cast<const __bf16*>(a3), B, ldb, work, (int)p.tiles_m,
+                     (int)p.tiles_n, (int)p.nsplit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = m * n;
+  hipLaunchKernelGGL(k_splitk_reduce32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, n,
+                     (int)p.nsplit, (const float2*)work, alpha, alpha_dev, rowscale, C, ldc,
+                     reinterpret_cast<__bf16*>(c3));
   return hipGetLastError();
 }
 
@@ -769,7 +938,8 @@ hipError_t launch_gemm_cn32_s16(int64_t m, int64_t n, int64_t k, double alpha, c
   if (e != hipSuccess) return e;
   const int64_t tot = m * n;
   hipLaunchKernelGGL(k_splitk_reduce32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, n,
-                     (int)p.nsplit, (const float2*)work, alpha, alpha_dev, rowscale, C, ldc);
+                     (int)p.nsplit, (const float2*)work, alpha, alpha_dev, rowscale, C, ldc,
+                     (__bf16*)nullptr);
   return hipGetLastError();
 }
 
@@ -794,15 +964,16 @@ hipError_t launch_gemm_nn32_s16(int64_t m, int64_t n, int64_t k, double alpha, c
 
 hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
-                            int64_t ldc, hipStream_t s, int tile, const uint16_t* a3, int kp3) {
+                            int64_t ldc, hipStream_t s, int tile, const uint16_t* a3,
+                            const uint16_t* b3) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const int tn = (int)((n + kBN - 1) / kBN);
-  if (!bf16 && a3) {
+  if (!bf16 && a3 && b3) {
     const int tm = (int)((m + kBM - 1) / kBM);
     const dim3 grid((unsigned)(kXcds * tn * ((tm + kXcds - 1) / kXcds)));
-    hipLaunchKernelGGL(k_gemm_nn32_b3, grid, dim3(kThreads), 0, s, m, n, k, (float)alpha,
-                       reinterpret_cast<const __bf16*>(a3), kp3, B, ldb, (float)beta, C, ldc, tm,
-                       tn);
+    hipLaunchKernelGGL(k_gemm_nn32_s3, grid, dim3(kThreads), 0, s, m, n, k, (float)alpha,
+                       reinterpret_cast<const __bf16*>(a3), reinterpret_cast<const __bf16*>(b3),
+                       (float)beta, C, ldc, tm, tn);
     return hipGetLastError();
   }
   if (tile == 1) {
@@ -863,11 +1034,13 @@ hipError_t launch_fused_gemm_nn32(int bf16, int nitems, int64_t m_max, int64_t n
   return hipGetLastError();
 }
 
-hipError_t launch_split3_t(int64_t rows, int nk, int kp, const float2* P, int64_t ldp, uint16_t* P3,
-                           hipStream_t s) {
-  if (rows <= 0 || kp <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((kp + 63) / 64));
-  hipLaunchKernelGGL(k_split3_t, grid, dim3(256), 0, s, rows, nk, kp, P, ldp,
-                     reinterpret_cast<__bf16*>(P3));
+size_t split3_elems(int64_t rows, int64_t k) { return (size_t)(s3_rows(rows) * s3_nst(k) * kS3Chunk); }
+
+hipError_t launch_split3(int64_t rows, int64_t k, const float2* X, int64_t sr, int64_t sk,
+                         uint16_t* X3, hipStream_t s) {
+  if (rows <= 0 || k <= 0) return hipSuccess;
+  const dim3 grid((unsigned)(s3_rows(rows) / 64), (unsigned)std::min<int64_t>(s3_nst(k), 65535));
+  hipLaunchKernelGGL(k_split3_s3, grid, dim3(256), 0, s, rows, k, X, sr, sk,
+                     reinterpret_cast<__bf16*>(X3));
   return hipGetLastError();
 }

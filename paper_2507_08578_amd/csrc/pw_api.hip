@@ -219,9 +219,14 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
       HIPCHK(c, hipStreamWaitEvent(ps, c->ev_fork, 0));
     }
     StageScope sc(c, PW_STAGE_PROJ_LP, ps);
-    HIPCHK(c, launch_gemm_cn32(bf16, h->nproj, nb, h->npw, alpha, h->proj32, h->npw, in, ldin,
-                               h->cprj32, h->nproj, h->ekb_dev, h->work32, ps, coef,
-                               h->gemm_target));
+    if (bf16)
+      HIPCHK(c, launch_gemm_cn32(1, h->nproj, nb, h->npw, alpha, h->proj32, h->npw, in, ldin,
+                                 h->cprj32, h->nproj, h->ekb_dev, h->work32, ps, coef,
+                                 h->gemm_target));
+    else
+      HIPCHK(c, launch_gemm_cn32_s3(h->nproj, nb, h->npw, alpha, h->proj3c, in, ldin, h->cprj32,
+                                    h->nproj, h->ekb_dev, h->work32, ps, coef, h->gemm_target,
+                                    h->cprj3));
   }
   if (fork) HIPCHK(c, hipEventRecord(c->ev_join, c->aux));
   const Epilogue ep{alpha, beta, gamma, coef};
@@ -246,7 +251,7 @@ pw_status ham_apply32(pw_ham* h, int bf16, int64_t nb, const float2* in, int64_t
   if (h->nproj > 0) {
     StageScope sc(c, PW_STAGE_NONLOCAL_LP);
     HIPCHK(c, launch_gemm_nn32(bf16, h->npw, nb, h->nproj, 1.0, h->proj32, h->npw, h->cprj32,
-                               h->nproj, 1.0, out, ldout, s, h->nn_tile32, h->proj3, h->kp3));
+                               h->nproj, 1.0, out, ldout, s, h->nn_tile32, h->proj3, h->cprj3));
   }
   return PW_OK;
 }
@@ -666,7 +671,8 @@ pw_status fused_setup(pw_batch* b) {
       d.proj = h->proj;
       d.proj32 = h->proj32;
       d.proj3 = h->proj3;
-      d.kp3 = h->kp3;
+      d.proj3c = h->proj3c;
+      d.cprj3 = h->cprj3;
       d.ekb = h->ekb_dev;
       d.cprj = h->cprj;
       d.cprj32 = h->cprj32;
@@ -1254,10 +1260,17 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
     if (h->nproj > 0) {
       TRY(dalloc(h, &h->proj32, (size_t)(npw * h->nproj)));
       HIPCHK(ctx, launch_block_to_f32(npw, h->nproj, h->proj, npw, h->proj32, npw, s));
-      h->kp3 = (int)((h->nproj + 7) / 8 * 8);
-      TRY(dalloc(h, &h->proj3, (size_t)6 * npw * h->kp3));
-      HIPCHK(ctx, launch_split3_t(npw, (int)h->nproj, h->kp3, h->proj32, npw, h->proj3, s));
+      TRY(dalloc(h, &h->proj3, split3_elems(npw, h->nproj)));
+      HIPCHK(ctx, launch_split3(npw, h->nproj, h->proj32, 1, npw, h->proj3, s));
+      TRY(dalloc(h, &h->proj3c, split3_elems(h->nproj, npw)));
+      HIPCHK(ctx, launch_split3(h->nproj, npw, h->proj32, npw, 1, h->proj3c, s));
       TRY(dalloc(h, &h->cprj32, (size_t)(h->nproj * h->nb_max)));
+      // the reduction writes the entries of the nb bands it forms: the
+      // projector padding stays zero, and rows of bands past a call's nb
+      // (zero, or an earlier call's values) reach only columns not stored
+      const size_t n3 = split3_elems(h->nb_max, h->nproj);
+      TRY(dalloc(h, &h->cprj3, n3));
+      HIPCHK(ctx, hipMemsetAsync(h->cprj3, 0, n3 * sizeof(uint16_t), s));
     }
     {
       // split-K partials of the FP32 / BF16 projections and Gram matrices

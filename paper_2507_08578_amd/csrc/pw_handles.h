@@ -126,8 +126,11 @@ struct pw_ham {
   float* kin32 = nullptr;
   float* vs32 = nullptr;
   float2* proj32 = nullptr;
-  uint16_t* proj3 = nullptr;   // proj32 as three bf16 terms, projector-contiguous (FP32 P C)
-  int kp3 = 0;
+  // proj32 split into three bf16 terms (launch_split3 layout) for the FP32
+  // products: rows = plane waves (P C) and rows = projectors (P^H psi)
+  uint16_t* proj3 = nullptr;
+  uint16_t* proj3c = nullptr;
+  uint16_t* cprj3 = nullptr;   // cprj32^T in three terms (rows = bands), written by P^H psi
   float2* T32 = nullptr;
   float2* cprj32 = nullptr;
   float2* work32 = nullptr;

@@ -104,8 +104,9 @@ struct ItemDev {
   const float* vs32;
   const cplx* proj;
   const float2* proj32;
-  const uint16_t* proj3;               // three-term bf16 copy of proj32, projector-contiguous
-  int kp3;                             // its padded projector count (multiple of 8)
+  const uint16_t* proj3;               // stored three-term copies of proj32 (launch_split3):
+  const uint16_t* proj3c;              //   rows = plane waves / rows = projectors
+  uint16_t* cprj3;                     // three-term copy of cprj32^T (rows = bands)
   const double* ekb;
   cplx* cprj;
   float2* cprj32;
@@ -324,12 +325,20 @@ hipError_t launch_gemm_cn32(int bf16, int64_t m, int64_t n, int64_t k, double al
                             int64_t lda, const float2* B, int64_t ldb, float2* C, int64_t ldc,
                             const double* rowscale, float2* work, hipStream_t s,
                             const double* alpha_dev = nullptr, int target_blocks = 2048);
-// FP32 (bf16 = 0) with a3 given: P C from the three-term bf16 copy a3 of A
-// (launch_split3_t layout, kp3 = padded k); tile then has no effect.
+// FP32 (bf16 = 0) with a3 and b3 given: A B from the stored three-term
+// copies a3 of A (rows m, contraction k) and b3 of B^T (rows n, contraction
+// k); A and B are then not read and tile has no effect.
 hipError_t launch_gemm_nn32(int bf16, int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                             int64_t lda, const float2* B, int64_t ldb, double beta, float2* C,
                             int64_t ldc, hipStream_t s, int tile = 0, const uint16_t* a3 = nullptr,
-                            int kp3 = 0);
+                            const uint16_t* b3 = nullptr);
+// As launch_gemm_cn32 with bf16 = 0, A given as the stored three-term copy a3
+// of A^T (rows m, contraction k); with c3, the reduction also stores the
+// three-term copy of C^T (rows n, contraction m) for launch_gemm_nn32.
+hipError_t launch_gemm_cn32_s3(int64_t m, int64_t n, int64_t k, double alpha, const uint16_t* a3,
+                               const float2* B, int64_t ldb, float2* C, int64_t ldc,
+                               const double* rowscale, float2* work, hipStream_t s,
+                               const double* alpha_dev, int target_blocks, uint16_t* c3);
 // bf16 operands with the block operand stored as bf16 pairs: A^H B with B a
 // bf16-pair block (split-K partials and result complex64, as launch_gemm_cn32
 // with bf16 = 1), and C (bf16 pairs) = alpha A B + beta C with A, B complex64.
@@ -340,10 +349,14 @@ hipError_t launch_gemm_cn32_s16(int64_t m, int64_t n, int64_t k, double alpha, c
 hipError_t launch_gemm_nn32_s16(int64_t m, int64_t n, int64_t k, double alpha, const float2* A,
                                 int64_t lda, const float2* B, int64_t ldb, double beta, bf16c* C,
                                 int64_t ldc, hipStream_t s, int tile = 0);
-// a3[(t 2 + c) rows kp + i kp + k] = term t of part c of P[i + k ldp] split
-// into three bf16 terms (zero for nk <= k < kp; kp a multiple of 8).
-hipError_t launch_split3_t(int64_t rows, int nk, int kp, const float2* P, int64_t ldp, uint16_t* P3,
-                           hipStream_t s);
+// Stored three-term copies: X3 holds X (rows x k; element (r, c) at
+// X[r sr + c sk]) split exactly into three bf16 terms per real part, in
+// chunks of 32 contraction values (six planes of 32 bf16 per chunk, a row's
+// chunks consecutive), rows padded to a multiple of 64 and k to 32, with
+// zeros; split3_elems gives its size in bf16.
+size_t split3_elems(int64_t rows, int64_t k);
+hipError_t launch_split3(int64_t rows, int64_t k, const float2* X, int64_t sr, int64_t sk,
+                         uint16_t* X3, hipStream_t s);
 
 // Precision conversions
 hipError_t launch_block_to_f32(int64_t rows, int64_t cols, const cplx* x, int64_t ldx, float2* y,
