@@ -72,13 +72,13 @@ BATCHED = ("C2", "C4")
 # (config, precision, stage, kernel) -> committed rocprofv3 counter summary and
 # the sources whose hash it records
 COUNTER_FILES = {
-    ("C5", "fp32", "fft_plane", "k_plane_reg"): (
-        "profiles/c5_plane_fp32_counters.md",
+    ("C5", "fp64", "fft_plane", "k_plane_reg"): (
+        "profiles/c5_plane_fp64_counters.md",
         ("paper_2507_08578_amd/csrc/fft_reg.hip", "paper_2507_08578_amd/csrc/fft_common.h")),
-    ("C5", "fp32", "proj", "k_gemm_cn32"): (
+    ("C5", "fp32", "proj", "k_gemm_cn32_s3"): (
         "profiles/c5_gemm_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/gemm32_kernels.hip",)),
-    ("C5", "fp32", "nonlocal", "k_gemm_nn32_b3"): (
+    ("C5", "fp32", "nonlocal", "k_gemm_nn32_s3"): (
         "profiles/c5_gemm_nn32_fp32_counters.md",
         ("paper_2507_08578_amd/csrc/gemm32_kernels.hip",)),
     ("C5", "fp64", "density", "k_density_reg"): (
@@ -172,13 +172,15 @@ def roofline(stages, steps, w, ham, nb, prec, config=None):
             key = f"k_gemm_cn{sx}"
             kname = f"k_gemm_cn{sx}{mode} + k_splitk_reduce{sx} (P^H psi, split-K, KB scale)"
             if prec == "fp32":
-                kname += "; FP32 operands split into three bf16 terms, bf16 MFMA"
+                key = "k_gemm_cn32_s3"
+                kname = ("k_gemm_cn32_s3 + k_splitk_reduce32 (P^H psi, split-K, KB scale; P as "
+                         "a stored three-term bf16 copy, psi split per stage, bf16 MFMA)")
                 extra = {"executed_mfma_flop_per_launch": 6.0 * fl,
                          "executed_TFLOPs": 6.0 * ach, "executed_frac": 6.0 * ach / peak}
         elif prec == "fp32":
-            key = "k_gemm_nn32_b3"
-            kname = ("k_gemm_nn32_b3 (H psi += P C; P as a stored three-term bf16 copy, "
-                     "C split per tile, bf16 MFMA)")
+            key = "k_gemm_nn32_s3"
+            kname = ("k_gemm_nn32_s3 (H psi += P C; P and C as stored three-term bf16 copies, "
+                     "bf16 MFMA)")
             extra = {"executed_mfma_flop_per_launch": 6.0 * fl,
                      "executed_TFLOPs": 6.0 * ach, "executed_frac": 6.0 * ach / peak}
         else:
