@@ -653,7 +653,9 @@ k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
             const cplx* __restrict__ Qk, const int* __restrict__ conv) {
   if (conv[0]) return;
   constexpr int LX = kBJS + 1;                         // odd row pitch of the A sub-block
-  __shared__ cplx sm[(kBJS + 1) * kBJS + 2 * kBJS * kBJS];
+  // the A sub-block and both unitaries, or a V tile and one unitary
+  constexpr int kSmA = (kBJS + 1) * kBJS + 2 * kBJS * kBJS, kSmV = kBJTile * kBJS + kBJS * kBJS;
+  __shared__ cplx sm[kSmA > kSmV ? kSmA : kSmV];
   const int tid = threadIdx.x;
   const int nblk = n2p / kBJ, npair = nblk / 2;
   const int w = blockIdx.x;
@@ -746,8 +748,6 @@ k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
       V[(r0 + i) + (int64_t)bj_index(jg + t * G, Iq, Jq) * n] = acc[t];
   }
 }
-static_assert(kBJTile * kBJS + kBJS * kBJS <= (kBJS + 1) * kBJS + 2 * kBJS * kBJS,
-              "the update workgroup's LDS also holds a V tile and its unitary");
 
 // A0 = [a 0; 0 0] (n2 x n2), V0 = [I 0] (n x n2)
 __global__ void k_jacobi_init(int n, int n2, const cplx* __restrict__ a, int64_t lda,
