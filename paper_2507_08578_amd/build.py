@@ -28,8 +28,12 @@ CFLAGS = [
 
 
 # per-source extra flags: the LDS-exchange FFT feeds literal zeros into its
-# pruned transforms, and folding x + 0 -> x needs signed zeros ignored
-FILE_FLAGS = {"fft_ls.hip": ["-fno-signed-zeros"]}
+# pruned transforms, and folding x + 0 -> x needs signed zeros ignored; the
+# FP64 matrix products keep their MFMA accumulators in ordinary VGPRs (with
+# the accumulation registers the compiler copies them out and back on every
+# K stage of the A B kernels, and the split register budget halves occupancy)
+FILE_FLAGS = {"fft_ls.hip": ["-fno-signed-zeros"],
+              "gemm_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:

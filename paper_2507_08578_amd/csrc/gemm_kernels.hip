@@ -14,6 +14,12 @@
 #include <algorithm>
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+// complex value in registers and LDS as a native 2-vector: loads, stores and
+// selects stay in registers (struct copies through cplx can leave the staging
+// arrays in scratch memory)
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ d2 ld2(const cplx* p) { return *reinterpret_cast<const d2*>(p); }
 
 namespace {
 
@@ -40,8 +46,8 @@ __device__ __forceinline__ void gemm_nn_tile(int64_t M, int64_t N, int64_t K, do
                                              const cplx* __restrict__ B, int64_t ldb, double beta,
                                              cplx* __restrict__ C, int64_t ldc, int bx, int by) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
-  __shared__ cplx As[KC][BM];
-  __shared__ cplx Bs[KC][BN + 1];
+  __shared__ d2 As[KC][BM];
+  __shared__ d2 Bs[KC][BN + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
   const int64_t i0 = (int64_t)by * BM, j0 = (int64_t)bx * BN;
@@ -57,24 +63,27 @@ __device__ __forceinline__ void gemm_nn_tile(int64_t M, int64_t N, int64_t K, do
   // global -> register prefetch of the next K stage overlaps this stage's MFMAs
   constexpr int QA = BM * KC / kThreads, QB = BN * KC / kThreads;
   static_assert(QA * kThreads == BM * KC && QB * kThreads == BN * KC, "tile split");
-  cplx ra[QA], rb[QB];
+  d2 ra[QA], rb[QB];
+  // Every lane loads from a clamped in-bounds address, so the K loop has no
+  // branches (branches around the loads make the compiler copy the
+  // accumulators out of and back into the matrix-core registers every
+  // stage).  Rows of A past M and columns of B past N only feed results that
+  // are not stored; B's rows past K are zeroed as the stage goes to LDS.
   auto fetch = [&](int64_t k0) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = tid + q * kThreads;
       const int kk = e / BM, ii = e - kk * BM;
-      const int64_t gi = i0 + ii, gk = k0 + kk;
-      ra[q] = (gi < M && gk < K) ? A[gi + gk * lda] : make_double2(0.0, 0.0);
+      ra[q] = ld2(A + min(i0 + ii, M - 1) + min(k0 + kk, K - 1) * lda);
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int e = tid + q * kThreads;
       const int jj = e / KC, kk = e - jj * KC;
-      const int64_t gk = k0 + kk, gj = j0 + jj;
-      rb[q] = (gk < K && gj < N) ? B[gk + gj * ldb] : make_double2(0.0, 0.0);
+      rb[q] = ld2(B + min(k0 + kk, K - 1) + min(j0 + jj, N - 1) * ldb);
     }
   };
-  fetch(0);
+  if (K > 0) fetch(0);
   for (int64_t k0 = 0; k0 < K; k0 += KC) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
@@ -86,13 +95,13 @@ __device__ __forceinline__ void gemm_nn_tile(int64_t M, int64_t N, int64_t K, do
     for (int q = 0; q < QB; ++q) {
       const int e = tid + q * kThreads;
       const int jj = e / KC, kk = e - jj * KC;
-      Bs[kk][jj] = rb[q];
+      Bs[kk][jj] = k0 + kk < K ? rb[q] : d2{0.0, 0.0};
     }
     __syncthreads();
-    if (k0 + KC < K) fetch(k0 + KC);
+    fetch(k0 + KC);   // after the last stage: clamped loads, never used
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 4) {
-      cplx a[TM], b[TN];
+      d2 a[TM], b[TN];
 #pragma unroll
       for (int t = 0; t < TM; ++t) a[t] = As[ks + lk][wi * 16 * TM + t * 16 + lr];
 #pragma unroll
@@ -188,8 +197,8 @@ __device__ __forceinline__ void gemm_cn_body(int64_t M, int64_t N, int64_t K, in
                                              int bx, int by, int bz, int64_t oi0 = 0,
                                              int64_t oj0 = 0) {
   if (alpha_dev) alpha = alpha_dev[0];
-  __shared__ cplx As[kKcCN][kBM + 1];
-  __shared__ cplx Bs[kKcCN][kBN + 1];
+  __shared__ d2 As[kKcCN][kBM + 1];
+  __shared__ d2 Bs[kKcCN][kBN + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
   const int64_t i0 = (int64_t)by * kBM, j0 = (int64_t)bx * kBN;
@@ -206,21 +215,21 @@ __device__ __forceinline__ void gemm_cn_body(int64_t M, int64_t N, int64_t K, in
   const int lr = lane & 15, lk = lane >> 4;
   constexpr int QA = kBM * kKcCN / kThreads, QB = kBN * kKcCN / kThreads;
   static_assert(QA * kThreads == kBM * kKcCN && QB * kThreads == kBN * kKcCN, "tile split");
-  cplx ra[QA], rb[QB];
+  d2 ra[QA], rb[QB];
+  // clamped loads, no branches in the K loop; B's rows past the split's
+  // end are zeroed as the stage goes to LDS (as in gemm_nn_tile)
   auto fetch = [&](int64_t k0) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int e = tid + q * kThreads;
       const int ii = e / kKcCN, kk = e - ii * kKcCN;
-      const int64_t gi = i0 + ii, gk = k0 + kk;
-      ra[q] = (gi < M && gk < ke) ? A[gk + gi * lda] : make_double2(0.0, 0.0);
+      ra[q] = ld2(A + min(k0 + kk, ke - 1) + min(i0 + ii, M - 1) * lda);
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const int e = tid + q * kThreads;
       const int jj = e / kKcCN, kk = e - jj * kKcCN;
-      const int64_t gj = j0 + jj, gk = k0 + kk;
-      rb[q] = (gj < N && gk < ke) ? B[gk + gj * ldb] : make_double2(0.0, 0.0);
+      rb[q] = ld2(B + min(k0 + kk, ke - 1) + min(j0 + jj, N - 1) * ldb);
     }
   };
   if (kb < ke) fetch(kb);
@@ -235,13 +244,13 @@ __device__ __forceinline__ void gemm_cn_body(int64_t M, int64_t N, int64_t K, in
     for (int q = 0; q < QB; ++q) {
       const int e = tid + q * kThreads;
       const int jj = e / kKcCN, kk = e - jj * kKcCN;
-      Bs[kk][jj] = rb[q];
+      Bs[kk][jj] = k0 + kk < ke ? rb[q] : d2{0.0, 0.0};
     }
     __syncthreads();
-    if (k0 + kKcCN < ke) fetch(k0 + kKcCN);
+    fetch(k0 + kKcCN);
 #pragma unroll
     for (int ks = 0; ks < kKcCN; ks += 4) {
-      cplx a[2], b[2];
+      d2 a[2], b[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         a[t] = As[ks + lk][wi * 32 + t * 16 + lr];
