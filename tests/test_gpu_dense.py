@@ -35,6 +35,19 @@ def test_gemm_nn(ctx, m, n, k):
     assert np.abs(out.T - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
 
 
+def test_gemm_nn_empty_contraction(pw, ctx):
+    """k = 0: C = beta C (no operand element is read)."""
+    import torch
+    rng = np.random.default_rng(5)
+    m, n = 70, 9
+    C0 = crand(rng, n, m)
+    Cd = to_dev(C0)
+    one = torch.zeros(1, dtype=torch.complex128, device="cuda")   # valid pointers, never read
+    ctx.check(pw._LIB.pw_gemm_nn(ctx.handle, m, n, 0, 2.0, one.data_ptr(), m, one.data_ptr(),
+                                      1, 0.5, Cd.data_ptr(), m))
+    assert np.array_equal(to_host(Cd), 0.5 * C0)
+
+
 def hpd(rng, n, cond=1e3):
     Q, _ = np.linalg.qr(crand(rng, n, n))
     d = np.geomspace(1.0, cond, n)
