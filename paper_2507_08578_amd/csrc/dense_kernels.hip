@@ -299,14 +299,8 @@ struct Rot {
 // Round r of the circle method over n2 (even) indices: pair k -> (p < q).
 __device__ __forceinline__ void rr_pair(int r, int k, int n2, int* p, int* q) {
   const int m = n2 - 1;
-  int a, b;
-  if (k == 0) {
-    a = m;
-    b = r;
-  } else {
-    a = (r + k) % m;
-    b = (r - k + m) % m;
-  }
+  const int a = k == 0 ? m : (r + k) % m;
+  const int b = k == 0 ? r : (r - k + m) % m;
   *p = min(a, b);
   *q = max(a, b);
 }
@@ -334,25 +328,25 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // denormal range) counts as zero: no rotation.  (Matrix entries here are
 // O(1) Hamiltonian elements.)
 __device__ __forceinline__ Rot make_rot(double a, double b, cplx c) {
+  // branch-free (callers form several rotations side by side); a zero c
+  // selects the identity at the end (the arithmetic before it may be inf/NaN)
   Rot R;
   const double m2 = c.x * c.x + c.y * c.y;
-  if (!(m2 > 1e-300)) {
-    R.cs = 1.0; R.sn = 0.0; R.t = 0.0; R.ph = make_double2(1.0, 0.0); R.on = false;
-    return R;
-  }
+  R.on = m2 > 1e-300;
   const double rmag = rsqrt_nr(m2);
   const double mag = m2 * rmag;
   const double tau = 0.5 * (b - a) * rmag;
   const double at = fabs(tau);
   // for |tau| > 1e100, sqrt(1 + tau^2) = |tau| to working precision
   const double u = 1.0 + tau * tau;
-  const double root = at > 1e100 ? at : u * rsqrt_nr(u);
+  const double ru = u * rsqrt_nr(u);
+  const double root = at > 1e100 ? at : ru;
   const double t = copysign(rcp_nr(at + root), tau);
-  R.cs = rsqrt_nr(1.0 + t * t);
-  R.sn = t * R.cs;
-  R.t = t * mag;
-  R.ph = make_double2(c.x * rmag, c.y * rmag);
-  R.on = true;
+  const double cs = rsqrt_nr(1.0 + t * t);
+  R.cs = R.on ? cs : 1.0;
+  R.sn = R.on ? t * cs : 0.0;
+  R.t = R.on ? t * mag : 0.0;
+  R.ph = R.on ? make_double2(c.x * rmag, c.y * rmag) : make_double2(1.0, 0.0);
   return R;
 }
 
@@ -567,73 +561,65 @@ __device__ __forceinline__ int bj_index(int i, int I, int J) {
 
 // One sweep on each block pair of outer round r (workgroup k: pair k);
 // Qout[k] (kBJS x kBJS, column-major) receives the accumulated rotations.
-// Each inner round: kBJ threads form the rotations, then one thread per 2x2
-// block of A (kBJ^2 blocks: it reads the block's four entries once and
-// writes all four) and per two (row, pair) items of V.  Every entry belongs
-// to exactly one block or item, so the updates are in place.
+// One thread per 2x2 block of A (kBJ^2 blocks: thread (P, Qb) takes rows
+// of pair P and columns of pair Qb of the inner round) and per two (row,
+// pair) items of V (rows Qb and Qb + kBJ, pair P).  A is double-buffered:
+// each inner round reads one copy and writes the other, so every thread
+// forms the two rotations it needs from the entries it reads (the same
+// arithmetic on the same values in every thread that forms one) and an
+// inner round needs a single barrier.
 constexpr int kBJInnerThreads = kBJ * kBJ;
 static_assert(2 * kBJInnerThreads == kBJS * kBJ, "V (row, pair) items: two per thread");
 __global__ void __launch_bounds__(kBJInnerThreads)
 k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout,
            const int* __restrict__ conv) {
   if (conv[0]) return;
-  __shared__ cplx a[kBJS * (kBJS + 1)];   // ld kBJS + 1 (odd: spreads the LDS banks)
+  constexpr int LA = kBJS + 1;            // ld kBJS + 1 (odd: spreads the LDS banks)
+  __shared__ cplx a[2][kBJS * LA];
   __shared__ cplx v[kBJS * kBJS];
-  __shared__ Rot rots[kBJ];
-  __shared__ int pp[kBJ], pq[kBJ];
-  constexpr int LA = kBJS + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
   int I, J;
   rr_pair(r, blockIdx.x, n2p / kBJ, &I, &J);
   for (int idx = tid; idx < kBJS * kBJS; idx += nt) {
     const int j = idx / kBJS, i = idx - j * kBJS;
-    a[i + j * LA] = A[bj_index(i, I, J) + (int64_t)bj_index(j, I, J) * n2p];
+    a[0][i + j * LA] = A[bj_index(i, I, J) + (int64_t)bj_index(j, I, J) * n2p];
     v[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  const int P = tid / kBJ, Qb = tid - P * kBJ;   // this thread's 2x2 block of A
+  const int P = tid / kBJ, Qb = tid - P * kBJ;
   for (int rr = 0; rr < kBJS - 1; ++rr) {
-    if (tid < kBJ) {
-      int p, q;
-      rr_pair(rr, tid, kBJS, &p, &q);
-      pp[tid] = p;
-      pq[tid] = q;
-      rots[tid] = make_rot(a[p + p * LA].x, a[q + q * LA].x, a[p + q * LA]);
-    }
-    __syncthreads();
-    {
-      const Rot& RP = rots[P];
-      const Rot& RQ = rots[Qb];
-      const int p1 = pp[P], q1 = pq[P], p2 = pp[Qb], q2 = pq[Qb];
-      if (P == Qb) {
-        if (RP.on) {
-          a[p1 + p1 * LA] = make_double2(a[p1 + p1 * LA].x - RP.t, 0.0);
-          a[q1 + q1 * LA] = make_double2(a[q1 + q1 * LA].x + RP.t, 0.0);
-          a[p1 + q1 * LA] = make_double2(0.0, 0.0);
-          a[q1 + p1 * LA] = make_double2(0.0, 0.0);
-        }
-      } else if (RP.on || RQ.on) {
-        cplx x11 = a[p1 + p2 * LA], x12 = a[p1 + q2 * LA];
-        cplx x21 = a[q1 + p2 * LA], x22 = a[q1 + q2 * LA];
-        rot_block(RP, RQ, &x11, &x12, &x21, &x22);
-        a[p1 + p2 * LA] = x11;
-        a[p1 + q2 * LA] = x12;
-        a[q1 + p2 * LA] = x21;
-        a[q1 + q2 * LA] = x22;
+    const cplx* ac = a[rr & 1];
+    cplx* an = a[(rr & 1) ^ 1];
+    int p1, q1, p2, q2;
+    rr_pair(rr, P, kBJS, &p1, &q1);
+    rr_pair(rr, Qb, kBJS, &p2, &q2);
+    const Rot RP = make_rot(ac[p1 + p1 * LA].x, ac[q1 + q1 * LA].x, ac[p1 + q1 * LA]);
+    const Rot RQ = make_rot(ac[p2 + p2 * LA].x, ac[q2 + q2 * LA].x, ac[p2 + q2 * LA]);   // RP if P == Qb
+    cplx x11 = ac[p1 + p2 * LA], x12 = ac[p1 + q2 * LA];
+    cplx x21 = ac[q1 + p2 * LA], x22 = ac[q1 + q2 * LA];
+    // an identity rotation (pair off) leaves the values unchanged exactly;
+    // the diagonal block reads RQ (= RP there), so both are formed up front
+    if (P == Qb) {
+      if (RQ.on) {
+        x11 = make_double2(x11.x - RQ.t, 0.0);
+        x22 = make_double2(x22.x + RQ.t, 0.0);
+        x12 = make_double2(0.0, 0.0);
+        x21 = make_double2(0.0, 0.0);
       }
+    } else {
+      rot_block(RP, RQ, &x11, &x12, &x21, &x22);
     }
+    an[p1 + p2 * LA] = x11;
+    an[p1 + q2 * LA] = x12;
+    an[q1 + p2 * LA] = x21;
+    an[q1 + q2 * LA] = x22;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int item = tid + h * kBJInnerThreads;
-      const int vQ = item / kBJS, vi = item - vQ * kBJS;
-      const Rot& RV = rots[vQ];
-      if (RV.on) {
-        const int p2 = pp[vQ], q2 = pq[vQ];
-        cplx x1 = v[vi + p2 * kBJS], x2 = v[vi + q2 * kBJS];
-        rot_row(RV, &x1, &x2);
-        v[vi + p2 * kBJS] = x1;
-        v[vi + q2 * kBJS] = x2;
-      }
+      const int vi = Qb + h * kBJ;
+      cplx x1 = v[vi + p1 * kBJS], x2 = v[vi + q1 * kBJS];
+      rot_row(RP, &x1, &x2);
+      v[vi + p1 * kBJS] = x1;
+      v[vi + q1 * kBJS] = x2;
     }
     __syncthreads();
   }
