@@ -651,14 +651,14 @@ k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
     rr_pair(r, p, nblk, &Ip, &Jp);
     rr_pair(r, q, nblk, &Iq, &Jq);
     cplx* X = sm;                       // [i + j LX]
-    cplx* Qp = sm + LX * kBJS;          // [m + i kBJS] = Q_p(m, i)
-    cplx* Qq = Qp + kBJS * kBJS;
+    cplx* Qp = sm + LX * kBJS;          // [i + m kBJS] = conj(Q_p(m, i)): the lanes of
+    cplx* Qq = Qp + kBJS * kBJS;        //   a wavefront read consecutive i
     const cplx* gp = Qk + (int64_t)p * kBJS * kBJS;
     const cplx* gq = Qk + (int64_t)q * kBJS * kBJS;
     for (int idx = tid; idx < kBJS * kBJS; idx += kBJUThreads) {
       const int j = idx / kBJS, i = idx - j * kBJS;
       X[i + j * LX] = A[bj_index(i, Ip, Jp) + (int64_t)bj_index(j, Iq, Jq) * n2p];
-      Qp[idx] = gp[idx];
+      Qp[j + i * kBJS] = cconj(gp[idx]);
       Qq[idx] = gq[idx];
     }
     __syncthreads();
@@ -669,8 +669,9 @@ k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
 #pragma unroll
     for (int t = 0; t < NJ; ++t) acc[t] = make_double2(0.0, 0.0);
     // T = Q_p^H X
+#pragma unroll 8
     for (int m = 0; m < kBJS; ++m) {
-      const cplx qh = cconj(Qp[m + i * kBJS]);
+      const cplx qh = Qp[i + m * kBJS];
 #pragma unroll
       for (int t = 0; t < NJ; ++t) {
         const cplx x = X[m + (jg + t * G) * LX];
@@ -685,6 +686,7 @@ k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
     // out = T Q_q
 #pragma unroll
     for (int t = 0; t < NJ; ++t) acc[t] = make_double2(0.0, 0.0);
+#pragma unroll 8
     for (int m = 0; m < kBJS; ++m) {
       const cplx x = X[i + m * LX];
 #pragma unroll
@@ -719,6 +721,7 @@ k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
   cplx acc[NJ];
 #pragma unroll
   for (int t = 0; t < NJ; ++t) acc[t] = make_double2(0.0, 0.0);
+#pragma unroll 8
   for (int m = 0; m < kBJS; ++m) {
     const cplx x = T[i + m * kBJTile];
 #pragma unroll
