@@ -506,7 +506,7 @@ pw_status pw_heev(pw_ctx* ctx, int64_t n, void* a_dev, int64_t lda, double* w_de
  * pw_heev for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation):
  * the same eigensolver and the same results as pw_heev, with its workspace
- * in a static device array of 9 MiB that every call on the device shares
+ * in a static device array of 13 MiB that every call on the device shares
  * (held by each GPU the library runs on until the process ends).  n <= 512
  * (INVALID_ARG above); a is read only.  Does not allocate and does not
  * synchronise: the sweep count goes to pw_ctx_last_sweeps and a sweep-limit

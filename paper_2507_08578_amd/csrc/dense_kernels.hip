@@ -567,29 +567,23 @@ __device__ __forceinline__ int bj_index(int i, int I, int J) {
 // each inner round reads one copy and writes the other, so every thread
 // forms the two rotations it needs from the entries it reads (the same
 // arithmetic on the same values in every thread that forms one) and an
-// inner round needs a single barrier.
+// inner round needs a single barrier.  a0 holds the sub-problem on entry
+// (ld kBJS + 1); a1 and v are LDS of the same size.
 constexpr int kBJInnerThreads = kBJ * kBJ;
+constexpr int kBJLA = kBJS + 1;           // ld of the sub-problem (odd: spreads the LDS banks)
 static_assert(2 * kBJInnerThreads == kBJS * kBJ, "V (row, pair) items: two per thread");
-__global__ void __launch_bounds__(kBJInnerThreads)
-k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout,
-           const int* __restrict__ conv) {
-  if (conv[0]) return;
-  constexpr int LA = kBJS + 1;            // ld kBJS + 1 (odd: spreads the LDS banks)
-  __shared__ cplx a[2][kBJS * LA];
-  __shared__ cplx v[kBJS * kBJS];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  int I, J;
-  rr_pair(r, blockIdx.x, n2p / kBJ, &I, &J);
-  for (int idx = tid; idx < kBJS * kBJS; idx += nt) {
+__device__ __forceinline__ void bj_inner_sweep(cplx* a0, cplx* a1, cplx* v, cplx* __restrict__ qo) {
+  constexpr int LA = kBJLA;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kBJS * kBJS; idx += kBJInnerThreads) {
     const int j = idx / kBJS, i = idx - j * kBJS;
-    a[0][i + j * LA] = A[bj_index(i, I, J) + (int64_t)bj_index(j, I, J) * n2p];
     v[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
   const int P = tid / kBJ, Qb = tid - P * kBJ;
   for (int rr = 0; rr < kBJS - 1; ++rr) {
-    const cplx* ac = a[rr & 1];
-    cplx* an = a[(rr & 1) ^ 1];
+    const cplx* ac = rr & 1 ? a1 : a0;
+    cplx* an = rr & 1 ? a0 : a1;
     int p1, q1, p2, q2;
     rr_pair(rr, P, kBJS, &p1, &q1);
     rr_pair(rr, Qb, kBJS, &p2, &q2);
@@ -623,28 +617,42 @@ k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout,
     }
     __syncthreads();
   }
-  cplx* qo = Qout + (int64_t)blockIdx.x * kBJS * kBJS;
-  for (int idx = tid; idx < kBJS * kBJS; idx += nt) qo[idx] = v[idx];
+  for (int idx = tid; idx < kBJS * kBJS; idx += kBJInnerThreads) qo[idx] = v[idx];
+}
+
+// Round 0 of a sweep: the sub-problems read straight from A.
+__global__ void __launch_bounds__(kBJInnerThreads)
+k_bj_inner(int n2p, int r, const cplx* __restrict__ A, cplx* __restrict__ Qout,
+           const int* __restrict__ conv) {
+  if (conv[0]) return;
+  __shared__ cplx a[2][kBJS * kBJLA];
+  __shared__ cplx v[kBJS * kBJS];
+  int I, J;
+  rr_pair(r, blockIdx.x, n2p / kBJ, &I, &J);
+  for (int idx = threadIdx.x; idx < kBJS * kBJS; idx += kBJInnerThreads) {
+    const int j = idx / kBJS, i = idx - j * kBJS;
+    a[0][i + j * kBJLA] = A[bj_index(i, I, J) + (int64_t)bj_index(j, I, J) * n2p];
+  }
+  bj_inner_sweep(a[0], a[1], v, Qout + (int64_t)blockIdx.x * kBJS * kBJS);
 }
 
 // Two-sided update of outer round r.  Workgroup w < npair^2 takes the
 // sub-block of A on block pair p = w / npair (rows) and block pair q =
-// w % npair (columns): A[idx_p, idx_q] <- Q_p^H A[idx_p, idx_q] Q_q, both
-// products in LDS.  Workgroup npair^2 + t npair + q takes kBJTile rows of V
-// from row t kBJTile: V[rows, idx_q] <- V[rows, idx_q] Q_q.  Each workgroup
-// reads and writes only its own elements, so the update is in place.
+// w % npair (columns): Aout[idx_p, idx_q] <- Q_p^H Ain[idx_p, idx_q] Q_q,
+// both products in LDS.  Workgroup npair^2 + t npair + q takes kBJTile rows
+// of V from row t kBJTile: V[rows, idx_q] <- V[rows, idx_q] Q_q.  Each
+// workgroup reads and writes only its own elements, so Ain may be Aout.
+// sm: LDS of kBJUpdateSm entries.
 constexpr int kBJUThreads = 256;
-__global__ void __launch_bounds__(kBJUThreads)
-k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
-            const cplx* __restrict__ Qk, const int* __restrict__ conv) {
-  if (conv[0]) return;
+static_assert(kBJUThreads == kBJInnerThreads, "fused step: one workgroup size");
+constexpr int kBJUSmA = (kBJS + 1) * kBJS + 2 * kBJS * kBJS, kBJUSmV = kBJTile * kBJS + kBJS * kBJS;
+constexpr int kBJUpdateSm = kBJUSmA > kBJUSmV ? kBJUSmA : kBJUSmV;
+__device__ __forceinline__ void bj_update_body(int n, int n2p, int r, const cplx* Ain, cplx* Aout,
+                                               cplx* __restrict__ V, const cplx* __restrict__ Qk,
+                                               int w, cplx* sm) {
   constexpr int LX = kBJS + 1;                         // odd row pitch of the A sub-block
-  // the A sub-block and both unitaries, or a V tile and one unitary
-  constexpr int kSmA = (kBJS + 1) * kBJS + 2 * kBJS * kBJS, kSmV = kBJTile * kBJS + kBJS * kBJS;
-  __shared__ cplx sm[kSmA > kSmV ? kSmA : kSmV];
   const int tid = threadIdx.x;
   const int nblk = n2p / kBJ, npair = nblk / 2;
-  const int w = blockIdx.x;
   if (w < npair * npair) {
     const int p = w / npair, q = w - p * npair;
     int Ip, Jp, Iq, Jq;
@@ -657,7 +665,7 @@ k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
     const cplx* gq = Qk + (int64_t)q * kBJS * kBJS;
     for (int idx = tid; idx < kBJS * kBJS; idx += kBJUThreads) {
       const int j = idx / kBJS, i = idx - j * kBJS;
-      X[i + j * LX] = A[bj_index(i, Ip, Jp) + (int64_t)bj_index(j, Iq, Jq) * n2p];
+      X[i + j * LX] = Ain[bj_index(i, Ip, Jp) + (int64_t)bj_index(j, Iq, Jq) * n2p];
       Qp[j + i * kBJS] = cconj(gp[idx]);
       Qq[idx] = gq[idx];
     }
@@ -699,11 +707,11 @@ k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
     const int gi = bj_index(i, Ip, Jp);
 #pragma unroll
     for (int t = 0; t < NJ; ++t)
-      A[gi + (int64_t)bj_index(jg + t * G, Iq, Jq) * n2p] = acc[t];
+      Aout[gi + (int64_t)bj_index(jg + t * G, Iq, Jq) * n2p] = acc[t];
     return;
   }
-  const int v = w - npair * npair;
-  const int tile = v / npair, q = v - tile * npair;
+  const int vw = w - npair * npair;
+  const int tile = vw / npair, q = vw - tile * npair;
   int Iq, Jq;
   rr_pair(r, q, nblk, &Iq, &Jq);
   const int r0 = tile * kBJTile;
@@ -736,6 +744,150 @@ k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
     for (int t = 0; t < NJ; ++t)
       V[(r0 + i) + (int64_t)bj_index(jg + t * G, Iq, Jq) * n] = acc[t];
   }
+}
+
+// The update of the last round of a sweep, in place.
+__global__ void __launch_bounds__(kBJUThreads)
+k_bj_update(int n, int n2p, int r, cplx* __restrict__ A, cplx* __restrict__ V,
+            const cplx* __restrict__ Qk, const int* __restrict__ conv) {
+  if (conv[0]) return;
+  __shared__ cplx sm[kBJUpdateSm];
+  bj_update_body(n, n2p, r, A, A, V, Qk, blockIdx.x, sm);
+}
+
+// Sub-problem of round r's pair (I, J) of M_r = G^H M G, G the block-
+// diagonal unitary of round r - 1 (Qin, its pairs), M = Min, formed by the
+// workgroup itself: with block I in round-(r-1) pair p1 (offset o1 = 0 for
+// its first block, kBJ for its second) and J in p2, entry (a, b) of the
+// (I, I) block is sum conj(Q_p1(m, o1 + a)) M[idx_p1(m), idx_p1(n)]
+// Q_p1(n, o1 + b), and so on for (I, J) and (J, J); (J, I) is the conjugate
+// transpose of (I, J).  The products run in the order of bj_update_body
+// (Q^H M first, then the right factor), the sums over m and n ascending.
+// sm: kBJLookSm entries of scratch (disjoint from a0).
+constexpr int kBJLookSm = (kBJS + 1) * kBJS + 4 * kBJS * kBJ + kBJ * (kBJS + 1);
+__device__ __forceinline__ void bj_lookahead(int n2p, int r, int I, int J, const cplx* __restrict__ Min,
+                                             const cplx* __restrict__ Qin, cplx* a0, cplx* sm) {
+  constexpr int LX = kBJS + 1, LT = kBJ;
+  const int tid = threadIdx.x;
+  const int nblk = n2p / kBJ, npair = nblk / 2;
+  int p1 = 0, o1 = 0, p2 = 0, o2 = 0;
+  for (int k = 0; k < npair; ++k) {
+    int Ik, Jk;
+    rr_pair(r - 1, k, nblk, &Ik, &Jk);
+    if (Ik == I) { p1 = k; o1 = 0; }
+    if (Jk == I) { p1 = k; o1 = kBJ; }
+    if (Ik == J) { p2 = k; o2 = 0; }
+    if (Jk == J) { p2 = k; o2 = kBJ; }
+  }
+  int I1, J1, I2, J2;
+  rr_pair(r - 1, p1, nblk, &I1, &J1);
+  rr_pair(r - 1, p2, nblk, &I2, &J2);
+  cplx* X = sm;                         // [i + j LX]: a kBJS x kBJS block of Min
+  cplx* L1 = X + LX * kBJS;             // [a + m kBJ] = conj(Q_p1(m, o1 + a))
+  cplx* L2 = L1 + kBJS * kBJ;           // the same for p2
+  cplx* R1 = L2 + kBJS * kBJ;           // [m + b kBJS] = Q_p1(m, o1 + b)
+  cplx* R2 = R1 + kBJS * kBJ;
+  cplx* T = R2 + kBJS * kBJ;            // [a + j LT]: (Q^H X)(a, j), kBJ x kBJS
+  const cplx* q1 = Qin + (int64_t)p1 * kBJS * kBJS;
+  const cplx* q2 = Qin + (int64_t)p2 * kBJS * kBJS;
+  // three blocks: (I, I) from (p1, p1), (I, J) from (p1, p2), (J, J) from
+  // (p2, p2); each block's entries are loaded into registers while the
+  // previous block's products run
+  constexpr int NX = kBJS * kBJS / kBJInnerThreads;
+  typedef double dv2 __attribute__((ext_vector_type(2)));   // native vector: stays in registers
+  dv2 xr[NX];
+  auto load_x = [&](int blk) {
+    const int Ir = blk < 2 ? I1 : I2, Jr = blk < 2 ? J1 : J2;       // row pair of Min
+    const int Ic = blk == 0 ? I1 : I2, Jc = blk == 0 ? J1 : J2;     // column pair
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+      const int idx = tid + t * kBJInnerThreads;
+      const int j = idx / kBJS, i = idx - j * kBJS;
+      xr[t] = *reinterpret_cast<const dv2*>(Min + bj_index(i, Ir, Jr) + (int64_t)bj_index(j, Ic, Jc) * n2p);
+    }
+  };
+  load_x(0);
+  for (int idx = tid; idx < kBJS * kBJ; idx += kBJInnerThreads) {
+    const int b = idx / kBJS, m = idx - b * kBJS;
+    const cplx v1 = q1[m + (o1 + b) * kBJS], v2 = q2[m + (o2 + b) * kBJS];
+    R1[idx] = v1;
+    R2[idx] = v2;
+    L1[b + m * kBJ] = cconj(v1);
+    L2[b + m * kBJ] = cconj(v2);
+  }
+  for (int blk = 0; blk < 3; ++blk) {
+    const cplx* L = blk < 2 ? L1 : L2;
+    const cplx* R = blk == 0 ? R1 : R2;
+    const int da = blk < 2 ? 0 : kBJ, db = blk == 0 ? 0 : kBJ;      // place in the sub-problem
+    __syncthreads();   // X and T free (previous block done; Q copies stored)
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+      const int idx = tid + t * kBJInnerThreads;
+      const int j = idx / kBJS, i = idx - j * kBJS;
+      X[i + j * LX] = make_double2(xr[t].x, xr[t].y);
+    }
+    if (blk < 2) load_x(blk + 1);
+    __syncthreads();
+    {   // T = L X: kBJ x kBJS, two entries per thread
+      const int a = tid % kBJ, j0 = tid / kBJ;
+      cplx acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+#pragma unroll 8
+      for (int m = 0; m < kBJS; ++m) {
+        const cplx qh = L[a + m * kBJ];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const cplx x = X[m + (j0 + t * kBJ) * LX];
+          acc[t].x += qh.x * x.x - qh.y * x.y;
+          acc[t].y += qh.x * x.y + qh.y * x.x;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) T[a + (j0 + t * kBJ) * LT] = acc[t];
+    }
+    __syncthreads();
+    {   // S = T R: kBJ x kBJ, one entry per thread
+      const int a = tid % kBJ, b = tid / kBJ;
+      cplx acc = make_double2(0.0, 0.0);
+#pragma unroll 8
+      for (int m = 0; m < kBJS; ++m) {
+        const cplx x = T[a + m * LT];
+        const cplx qv = R[m + b * kBJS];
+        acc.x += x.x * qv.x - x.y * qv.y;
+        acc.y += x.x * qv.y + x.y * qv.x;
+      }
+      a0[(da + a) + (db + b) * kBJLA] = acc;
+      if (blk == 1) a0[(db + b) + (da + a) * kBJLA] = cconj(acc);
+    }
+  }
+  __syncthreads();
+}
+
+// Outer round r >= 1 of a sweep fused with the update of round r - 1.
+// Workgroups [0, npair): the inner sweep of round r, each forming its
+// sub-problem of the rotated matrix itself (bj_lookahead from Ain and Qin)
+// and writing its rotations to Qout.  Workgroups [npair, npair + ugrid):
+// the update of round r - 1 from Ain into Aout (and V) with Qin.  The two
+// kinds read the same inputs and write disjoint outputs, so the update of
+// one round runs beside the inner sweep of the next.
+constexpr int kBJStepSm = kBJUpdateSm > kBJLA * kBJS + kBJLookSm ? kBJUpdateSm : kBJLA * kBJS + kBJLookSm;
+static_assert(kBJLookSm >= kBJLA * kBJS + kBJS * kBJS, "the inner sweep's a1 and v fit the scratch");
+__global__ void __launch_bounds__(kBJUThreads)
+k_bj_step(int n, int n2p, int r, const cplx* __restrict__ Ain, cplx* __restrict__ Aout,
+          cplx* __restrict__ V, const cplx* __restrict__ Qin, cplx* __restrict__ Qout,
+          const int* __restrict__ conv) {
+  if (conv[0]) return;
+  __shared__ cplx sm[kBJStepSm];
+  const int npair = n2p / kBJ / 2;
+  if ((int)blockIdx.x >= npair) {
+    bj_update_body(n, n2p, r - 1, Ain, Aout, V, Qin, blockIdx.x - npair, sm);
+    return;
+  }
+  int I, J;
+  rr_pair(r, blockIdx.x, n2p / kBJ, &I, &J);
+  cplx* a0 = sm;
+  cplx* scr = sm + kBJLA * kBJS;
+  bj_lookahead(n2p, r, I, J, Ain, Qin, a0, scr);
+  bj_inner_sweep(a0, scr, scr + kBJLA * kBJS, Qout + (int64_t)blockIdx.x * kBJS * kBJS);
 }
 
 // A0 = [a 0; 0 0] (n2 x n2), V0 = [I 0] (n x n2)
@@ -1225,8 +1377,8 @@ static int64_t bj_padded(int64_t n) { return (n + kBJTile - 1) / kBJTile * kBJTi
 // aligned doubles.
 size_t heev_work_bytes(int64_t n) {
   const int64_t n2p = bj_padded(n);
-  return (size_t)(n2p * n2p + n * n2p + n2p * kBJS) * sizeof(cplx) + (size_t)(n + 8) * sizeof(int) +
-         64 + 2 * kOffParts * sizeof(double);
+  return (size_t)(2 * n2p * n2p + n * n2p + 2 * n2p * kBJS) * sizeof(cplx) +
+         (size_t)(n + 8) * sizeof(int) + 64 + 2 * kOffParts * sizeof(double);
 }
 
 hipError_t heev_set_lds_limit(size_t bytes) {
@@ -1259,14 +1411,19 @@ hipError_t launch_heev_async(int64_t n, const cplx* a, int64_t lda, double* w, c
   if (max_sweeps < 1 || max_sweeps > kMaxSweeps) return hipErrorInvalidValue;
   const int64_t n2p = bj_padded(n);
   char* base = static_cast<char*>(work);
-  const size_t mat_bytes = (size_t)(n2p * n2p + n * n2p + n2p * kBJS) * sizeof(cplx);
+  const size_t mat_bytes = (size_t)(2 * n2p * n2p + n * n2p + 2 * n2p * kBJS) * sizeof(cplx);
   int* rank = reinterpret_cast<int*>(base + mat_bytes);
   int* conv = rank + n;                  // {converged, sweeps}
   const size_t stat_off = (mat_bytes + (size_t)(n + 8) * sizeof(int) + 15) & ~(size_t)15;
   double* dpart = reinterpret_cast<double*>(base + stat_off) + 2;   // kOffParts pairs
+  // A: the matrix at the start of every sweep; A1: the other copy of the
+  // fused rounds (each reads one and writes the other, an even number per
+  // sweep); Q0 / Q1: the unitaries of consecutive rounds
   cplx* A = reinterpret_cast<cplx*>(base);
-  cplx* V = A + n2p * n2p;
-  cplx* Qk = V + n * n2p;
+  cplx* A1 = A + n2p * n2p;
+  cplx* V = A1 + n2p * n2p;
+  cplx* Q0 = V + n * n2p;
+  cplx* Q1 = Q0 + n2p * kBJS;
   hipLaunchKernelGGL(k_jacobi_init, dim3(nblocks(n2p * n2p + n * n2p, 256)), dim3(256), 0, s,
                      (int)n, (int)n2p, a, lda, A, V, conv);
   hipError_t e = hipGetLastError();
@@ -1281,12 +1438,20 @@ hipError_t launch_heev_async(int64_t n, const cplx* a, int64_t lda, double* w, c
     hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(kOffParts), 0, s, (const double*)dpart,
                        tl * tl, sw, conv);
     if (sw == max_sweeps) break;
-    for (int r = 0; r < nblk - 1; ++r) {
-      hipLaunchKernelGGL(k_bj_inner, dim3(npair), dim3(kBJInnerThreads), 0, s, (int)n2p, r,
-                         (const cplx*)A, Qk, (const int*)conv);
-      hipLaunchKernelGGL(k_bj_update, dim3(ugrid), dim3(kBJUThreads), 0, s, (int)n, (int)n2p, r, A,
-                         V, (const cplx*)Qk, (const int*)conv);
+    // round 0 from A; rounds 1 .. nblk - 2 each beside the previous round's
+    // update (A -> A1 -> A ...: nblk - 2 copies, even); the last update in place
+    hipLaunchKernelGGL(k_bj_inner, dim3(npair), dim3(kBJInnerThreads), 0, s, (int)n2p, 0,
+                       (const cplx*)A, Q0, (const int*)conv);
+    cplx* cur = A;
+    cplx* nxt = A1;
+    for (int r = 1; r < nblk - 1; ++r) {
+      hipLaunchKernelGGL(k_bj_step, dim3((unsigned)npair + ugrid), dim3(kBJUThreads), 0, s, (int)n,
+                         (int)n2p, r, (const cplx*)cur, nxt, V, (const cplx*)(r & 1 ? Q0 : Q1),
+                         r & 1 ? Q1 : Q0, (const int*)conv);
+      std::swap(cur, nxt);
     }
+    hipLaunchKernelGGL(k_bj_update, dim3(ugrid), dim3(kBJUThreads), 0, s, (int)n, (int)n2p,
+                       nblk - 2, cur, V, (const cplx*)((nblk - 2) & 1 ? Q1 : Q0), (const int*)conv);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -69,7 +69,7 @@ struct pw_batch {
 // uses the symbol itself (on the host it is only a stand-in): pw_ctx_create
 // resolves each device's own address of it once, with that device current,
 // and every later use goes through that address.
-constexpr size_t kScratchBytes = (size_t)9 << 20;
+constexpr size_t kScratchBytes = (size_t)13 << 20;
 constexpr int kScratchHeevMax = 512;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
