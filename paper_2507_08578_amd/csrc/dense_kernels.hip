@@ -572,6 +572,7 @@ __device__ __forceinline__ int bj_index(int i, int I, int J) {
 constexpr int kBJInnerThreads = kBJ * kBJ;
 constexpr int kBJLA = kBJS + 1;           // ld of the sub-problem (odd: spreads the LDS banks)
 static_assert(2 * kBJInnerThreads == kBJS * kBJ, "V (row, pair) items: two per thread");
+static_assert(64 % kBJ == 0, "the lanes P < kBJ of every wavefront hold the pairs' rotations");
 __device__ __forceinline__ void bj_inner_sweep(cplx* a0, cplx* a1, cplx* v, cplx* __restrict__ qo) {
   constexpr int LA = kBJLA;
   const int tid = threadIdx.x;
@@ -587,8 +588,15 @@ __device__ __forceinline__ void bj_inner_sweep(cplx* a0, cplx* a1, cplx* v, cplx
     int p1, q1, p2, q2;
     rr_pair(rr, P, kBJS, &p1, &q1);
     rr_pair(rr, Qb, kBJS, &p2, &q2);
-    const Rot RP = make_rot(ac[p1 + p1 * LA].x, ac[q1 + q1 * LA].x, ac[p1 + q1 * LA]);
-    const Rot RQ = make_rot(ac[p2 + p2 * LA].x, ac[q2 + q2 * LA].x, ac[p2 + q2 * LA]);   // RP if P == Qb
+    // every thread forms the rotation of its pair Qb; RP (pair P) comes from
+    // lane P of the same wavefront (its Qb is P)
+    const Rot RQ = make_rot(ac[p2 + p2 * LA].x, ac[q2 + q2 * LA].x, ac[p2 + q2 * LA]);
+    Rot RP;
+    RP.cs = __shfl(RQ.cs, P, 64);
+    RP.sn = __shfl(RQ.sn, P, 64);
+    RP.t = __shfl(RQ.t, P, 64);
+    RP.ph = make_double2(__shfl(RQ.ph.x, P, 64), __shfl(RQ.ph.y, P, 64));
+    RP.on = __shfl((int)RQ.on, P, 64) != 0;
     cplx x11 = ac[p1 + p2 * LA], x12 = ac[p1 + q2 * LA];
     cplx x21 = ac[q1 + p2 * LA], x22 = ac[q1 + q2 * LA];
     // an identity rotation (pair off) leaves the values unchanged exactly;
