@@ -192,44 +192,65 @@ k_chol_init(int n, const cplx* __restrict__ A, int64_t lda,
 // Factor the kb x kb diagonal block at A(k0, k0) (upper triangle read),
 // write U back (zeros below its diagonal) and U^{-1} to dinv (ld kb).  A
 // pivot at or below tol records k0 + p in status unless an earlier block did.
+// 1/sqrt(x) and 1/x for x > 0 (normal): the hardware estimate refined by two
+// Newton steps (each doubles the correct bits), much shorter dependency
+// chains than the correctly rounded sequences; about 1 ulp.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+
+// Upper Cholesky of the kb x kb diagonal block at (k0, k0) (kb <= 64; 256
+// threads, as both launchers give) and the inverse of its factor into dinv (ld kb).  Right-looking
+// with the pivot row left unscaled, a_ij -= conj(a_pi) a_pj / a_pp for
+// p < i <= j (thread (ti, tj) of a 16 x 16 grid owns the entries i = ti + 16u,
+// j = tj + 16v), one barrier per pivot; the rows are scaled by 1/sqrt(a_pp)
+// at the end.  The inverse is formed column by column, each entry's sum
+// split over four lanes and joined by shuffles.
 __device__ __forceinline__ void chol_diag_body(int kb, int k0, cplx* __restrict__ A, int64_t lda, cplx* __restrict__ dinv,
             const double* __restrict__ tol, int* status) {
   extern __shared__ cplx sm[];
   const int trs = kb + 1;
   cplx* a = sm;
   cplx* x = sm + kb * trs;
-  __shared__ int fail;
-  __shared__ double sinv;
+  __shared__ double sq[kCholBlock], rs[kCholBlock];   // sqrt(a_pp), 1 / sqrt(a_pp)
   const int tid = threadIdx.x, nt = blockDim.x;
   cplx* Ab = A + k0 + (int64_t)k0 * lda;
   for (int idx = tid; idx < kb * kb; idx += nt) {
     const int j = idx / kb, i = idx - j * kb;
     a[i + j * trs] = (i <= j) ? Ab[i + (int64_t)j * lda] : make_double2(0.0, 0.0);
   }
-  if (tid == 0) fail = -1;
   __syncthreads();
   const double t = tol[0];
+  const int ti = tid & 15, tj = (tid >> 4) & 15;
+  int fail = -1;
   for (int p = 0; p < kb; ++p) {
-    if (tid == 0) {
-      const double d = a[p + p * trs].x;
-      if (!(d > t)) {
-        fail = p;
-      } else {
-        const double u = sqrt(d);
-        a[p + p * trs] = make_double2(u, 0.0);
-        sinv = 1.0 / u;
-      }
+    const double d = a[p + p * trs].x;   // the same value in every thread
+    if (!(d > t)) {
+      fail = p;
+      break;
     }
-    __syncthreads();
-    if (fail >= 0) break;
-    for (int j = p + 1 + tid; j < kb; j += nt) a[p + j * trs] = cscale(a[p + j * trs], sinv);
-    __syncthreads();
-    const int m = kb - p - 1;
-    for (int idx = tid; idx < m * m; idx += nt) {
-      const int jj = idx / m, ii = idx - jj * m;
-      if (ii > jj) continue;
-      const int i = p + 1 + ii, j = p + 1 + jj;
-      a[i + j * trs] = csub(a[i + j * trs], cmul(cconj(a[p + i * trs]), a[p + j * trs]));
+    const double rd = rcp_nr(d);
+#pragma unroll
+    for (int u = 0; u < kCholBlock / 16; ++u) {
+      const int i = ti + 16 * u;
+      if (i <= p || i >= kb) continue;
+      const cplx c = cscale(cconj(a[p + i * trs]), rd);
+#pragma unroll
+      for (int v = 0; v < kCholBlock / 16; ++v) {
+        const int j = tj + 16 * v;
+        if (j < i || j >= kb) continue;
+        a[i + j * trs] = csub(a[i + j * trs], cmul(c, a[p + j * trs]));
+      }
     }
     __syncthreads();
   }
@@ -237,27 +258,38 @@ __device__ __forceinline__ void chol_diag_body(int kb, int k0, cplx* __restrict_
     if (tid == 0 && status[0] < 0) status[0] = k0 + fail;
     return;
   }
+  for (int i = tid; i < kb; i += nt) {
+    sq[i] = sqrt(a[i + i * trs].x);
+    rs[i] = rsqrt_nr(a[i + i * trs].x);
+  }
+  __syncthreads();
   for (int idx = tid; idx < kb * kb; idx += nt) {
     const int j = idx / kb, i = idx - j * kb;
-    Ab[i + (int64_t)j * lda] = (i <= j) ? a[i + j * trs] : make_double2(0.0, 0.0);
+    cplx u = make_double2(0.0, 0.0);
+    if (i == j) u = make_double2(sq[i], 0.0);
+    else if (i < j) u = cscale(a[i + j * trs], rs[i]);
+    a[i + j * trs] = u;
+    Ab[i + (int64_t)j * lda] = u;
   }
-  // x = U^{-1} column by column
+  __syncthreads();
+  // x = U^{-1}: x_jj = 1/u_jj, x_ij = -(sum_{i <= p < j} x_ip u_pj) / u_jj
+  const int i = tid >> 2, q = tid & 3;
   for (int j = 0; j < kb; ++j) {
-    const double rinv = 1.0 / a[j + j * trs].x;
-    for (int i = tid; i < kb; i += nt) {
-      cplx v = make_double2(0.0, 0.0);
-      if (i < j) {
-        double sr = 0.0, si = 0.0;
-        for (int p = i; p < j; ++p) {
-          const cplx xv = x[i + p * trs], uv = a[p + j * trs];
-          sr += xv.x * uv.x - xv.y * uv.y;
-          si += xv.x * uv.y + xv.y * uv.x;
-        }
-        v = make_double2(-sr * rinv, -si * rinv);
-      } else if (i == j) {
-        v = make_double2(rinv, 0.0);
+    double sr = 0.0, si = 0.0;
+    if (i < j)
+      for (int p = i + q; p < j; p += 4) {
+        const cplx xv = x[i + p * trs], uv = a[p + j * trs];
+        sr += xv.x * uv.x - xv.y * uv.y;
+        si += xv.x * uv.y + xv.y * uv.x;
       }
-      x[i + j * trs] = v;
+    sr += __shfl_xor(sr, 1, 64);
+    si += __shfl_xor(si, 1, 64);
+    sr += __shfl_xor(sr, 2, 64);
+    si += __shfl_xor(si, 2, 64);
+    if (q == 0 && i < kb) {
+      const double rinv = rs[j];
+      x[i + j * trs] = i < j ? make_double2(-sr * rinv, -si * rinv)
+                             : make_double2(i == j ? rinv : 0.0, 0.0);
     }
     __syncthreads();
   }
@@ -303,23 +335,6 @@ __device__ __forceinline__ void rr_pair(int r, int k, int n2, int* p, int* q) {
   const int b = k == 0 ? r : (r - k + m) % m;
   *p = min(a, b);
   *q = max(a, b);
-}
-
-// 1/sqrt(x) and 1/x for x > 0 (normal): the hardware estimate refined by two
-// Newton steps (each doubles the correct bits), much shorter dependency
-// chains than the correctly rounded sequences; about 1 ulp.
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
-}
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = y * fma(-x, y, 2.0);
-  y = y * fma(-x, y, 2.0);
-  return y;
 }
 
 // Rotation J = [[cs, sn ph], [-sn conj(ph), cs]] with J^H [[a, c], [conj c, b]] J diagonal:
