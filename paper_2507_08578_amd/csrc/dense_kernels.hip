@@ -559,15 +559,16 @@ k_jacobi_small(int n, const cplx* __restrict__ Ain, int64_t lda, double* __restr
 // A <- G^H A G and V <- V G with G the block-diagonal product of the Q_k, as
 // two tiled products.  Every index pair meets in each outer sweep (pairs
 // inside a block in every round), so the outer sweeps converge like cyclic
-// Jacobi, with 2 launches per outer round instead of one per scalar round.
-// Padding indices have zero rows and columns and never rotate.  The
+// Jacobi.  Rounds 1 .. nblk - 2 of a sweep each take one launch that also
+// applies the previous round's update (k_bj_step); round 0 and the last
+// update have launches of their own.  Padding indices have zero rows and
+// columns and never rotate.  The
 // convergence test runs on the device before every outer sweep; once it
 // passes, conv[0] is set and every later launch of the solve returns at
 // once, so a fixed number of sweeps can be issued with no host read.
 constexpr int kBJ = 16;           // block size
 constexpr int kBJS = 2 * kBJ;     // sub-problem size
-constexpr int kBJTile = 64;       // row / column tile of the update products
-constexpr int kBJThreads = 1024;  // workgroup of the update products
+constexpr int kBJTile = 64;       // row tile of the V update (and the padding of n)
 
 // global index of sub-problem index i of block pair (I, J)
 __device__ __forceinline__ int bj_index(int i, int I, int J) {
