@@ -61,10 +61,14 @@ __device__ __forceinline__ void col_inv_reg_body(const BoxPlan& P, const C* __re
     for (int q = 0; q < R; ++q) col[q + base] = v[q];
   }
   __syncthreads();
+  // rows of CT columns (no division by the tile's column count): lane lc
+  // of every CT-lane slice writes column lc of row j3
   C* dst = T + (size_t)b * N3 * P.ncols + c0;
-  for (int i = threadIdx.x; i < ncl * N3; i += blockDim.x) {
-    const int j3 = i / ncl, lc = i - j3 * ncl;
-    dst[(size_t)j3 * P.ncols + lc] = tile[lc * TRS + j3];
+  {
+    const int lc = threadIdx.x % CT;
+    if (lc < ncl)
+      for (int j3 = threadIdx.x / CT; j3 < N3; j3 += kColThreads / CT)
+        dst[(size_t)j3 * P.ncols + lc] = tile[lc * TRS + j3];
   }
 }
 
@@ -96,9 +100,11 @@ __device__ __forceinline__ void col_fwd_reg_body(const BoxPlan& P, const C* __re
   const int c0 = cb * CT;
   const int ncl = min(CT, P.ncols - c0);
   const C* srcT = T + (size_t)b * N3 * P.ncols + c0;
-  for (int i = threadIdx.x; i < ncl * N3; i += blockDim.x) {
-    const int j3 = i / ncl, lc = i - j3 * ncl;
-    tile[lc * TRS + j3] = srcT[(size_t)j3 * P.ncols + lc];
+  {
+    const int lc = threadIdx.x % CT;
+    if (lc < ncl)
+      for (int j3 = threadIdx.x / CT; j3 < N3; j3 += kColThreads / CT)
+        tile[lc * TRS + j3] = srcT[(size_t)j3 * P.ncols + lc];
   }
   __syncthreads();
   const int grp = threadIdx.x / G, lb = threadIdx.x % G;
