@@ -69,7 +69,7 @@ k_density_reg(BoxPlan P, const double2* __restrict__ tw, const double2* __restri
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[k][q] = 0.0;
   for (int b = g; b < nbc; b += ngroup) {
-    const double2* tp = T + ((size_t)b * P.n3 + j3) * P.ncols;
+    const double2* tp = T + ((size_t)b * P.n3 + j3) * P.ldt;
     __syncthreads();   // the previous band's rows are done with E; slot is complete
     for (int i = tid; i < P.xr * TRS; i += kDensThreads) E[i] = czero<double2>();
     __syncthreads();

@@ -98,7 +98,7 @@ __device__ void fft_lds(C* buf, int ntr, int trs, const FftAxis& ax) {
 }
 
 struct PlanArgs {            // BoxPlan fields passed by value to kernels
-  int n1, n2, n3, ncols, xr;
+  int n1, n2, n3, ncols, ldt, xr;
   const int* col_start;
   const int* col_e;
   const int* col_m2;
@@ -111,7 +111,7 @@ struct PlanArgs {            // BoxPlan fields passed by value to kernels
 
 PlanArgs plan_args(const BoxPlan& p) {
   PlanArgs a;
-  a.n1 = p.n1; a.n2 = p.n2; a.n3 = p.n3; a.ncols = p.ncols; a.xr = p.xr;
+  a.n1 = p.n1; a.n2 = p.n2; a.n3 = p.n3; a.ncols = p.ncols; a.ldt = p.ldt; a.xr = p.xr;
   a.col_start = p.col_start; a.col_e = p.col_e; a.col_m2 = p.col_m2;
   a.pt_perm = p.pt_perm; a.pt_col = p.pt_col; a.pt_m3 = p.pt_m3; a.ext_m1 = p.ext_m1;
   a.ax1 = p.ax1; a.ax2 = p.ax2; a.ax3 = p.ax3;
@@ -134,10 +134,10 @@ __device__ __forceinline__ void col_inv_body(const PL& P, int ct, const C* __res
     lds[(P.pt_col[k] - c0) * trs + P.pt_m3[k]] = src[P.pt_perm[k]];
   __syncthreads();
   fft_lds<+1>(lds, ncl, trs, P.ax3);
-  C* dst = T + (size_t)b * P.n3 * P.ncols + c0;
+  C* dst = T + (size_t)b * P.n3 * P.ldt + c0;
   for (int i = threadIdx.x; i < ncl * P.n3; i += blockDim.x) {
     const int j3 = i / ncl, lc = i - j3 * ncl;
-    dst[(size_t)j3 * P.ncols + lc] = lds[lc * trs + j3];
+    dst[(size_t)j3 * P.ldt + lc] = lds[lc * trs + j3];
   }
 }
 
@@ -156,7 +156,7 @@ __device__ __forceinline__ void plane_body(const PL& P, int rb, const real_t<C>*
   const int trsr = P.n1 + 1;
   C* E = lds;
   C* Rw = lds + P.xr * trse;
-  C* tp = T + (size_t)b * P.n3 * P.ncols + (size_t)j3 * P.ncols;
+  C* tp = T + (size_t)b * P.n3 * P.ldt + (size_t)j3 * P.ldt;
   for (int i = threadIdx.x; i < P.xr * trse; i += blockDim.x) E[i] = czero<C>();
   __syncthreads();
   for (int c = threadIdx.x; c < P.ncols; c += blockDim.x) E[P.col_e[c] * trse + P.col_m2[c]] = tp[c];
@@ -215,7 +215,7 @@ k_density_plane(PlanArgs P, int rb, const double2* __restrict__ T, int nbc,
   }
   bool fresh = !add;
   for (int b = g; b < nbc; b += ngroup) {
-    const double2* tp = T + ((size_t)b * P.n3 + j3) * P.ncols;
+    const double2* tp = T + ((size_t)b * P.n3 + j3) * P.ldt;
     __syncthreads();
     for (int i = threadIdx.x; i < P.xr * trse; i += blockDim.x) E[i] = czero<double2>();
     __syncthreads();
@@ -265,10 +265,10 @@ __device__ __forceinline__ void col_fwd_body(const PL& P, int ct, const C* __res
   const int c0 = cb * ct;
   const int ncl = min(ct, P.ncols - c0);
   const int trs = P.n3 + 1;
-  const C* srcT = T + (size_t)b * P.n3 * P.ncols + c0;
+  const C* srcT = T + (size_t)b * P.n3 * P.ldt + c0;
   for (int i = threadIdx.x; i < ncl * P.n3; i += blockDim.x) {
     const int j3 = i / ncl, lc = i - j3 * ncl;
-    lds[lc * trs + j3] = srcT[(size_t)j3 * P.ncols + lc];
+    lds[lc * trs + j3] = srcT[(size_t)j3 * P.ldt + lc];
   }
   __syncthreads();
   fft_lds<-1>(lds, ncl, trs, P.ax3);

@@ -143,7 +143,7 @@ k_plane_ls(BoxPlan Pl, const float2* __restrict__ tw, const float* __restrict__ 
   // holds columns r kColSpacing GPW + t + kColSpacing gw.
   const int rstride = (N + GPW - 1) / GPW;
   const int ctasks = kColSpacing * ((Pl.xr + kColSpacing * GPW - 1) / (kColSpacing * GPW));
-  const int64_t plane_elems = Pl.ncols;
+  const int64_t plane_elems = Pl.ldt;
   // per plane invariants: extent slots, twiddles, this thread's column positions in E
   for (int i = tid; i < N; i += nt) slot[i] = -1;
   __syncthreads();
@@ -157,7 +157,7 @@ k_plane_ls(BoxPlan Pl, const float2* __restrict__ tw, const float* __restrict__ 
   float2 w[P - 1];
 #pragma unroll
   for (int k = 1; k < P; ++k) w[k - 1] = tw[(lb * k) % N];
-  // plane L's block of T: band b = L / n3, z-plane j3 = L % n3, i.e. offset L ncols
+  // plane L's row of T: band b = L / n3, z-plane j3 = L % n3, i.e. offset L ldt
   float2 pre[KPA];
   auto fetch = [&](int L) {
     if (L < nplanes) {

@@ -63,12 +63,12 @@ __device__ __forceinline__ void col_inv_reg_body(const BoxPlan& P, const C* __re
   __syncthreads();
   // rows of CT columns (no division by the tile's column count): lane lc
   // of every CT-lane slice writes column lc of row j3
-  C* dst = T + (size_t)b * N3 * P.ncols + c0;
+  C* dst = T + (size_t)b * N3 * P.ldt + c0;
   {
     const int lc = threadIdx.x % CT;
     if (lc < ncl)
       for (int j3 = threadIdx.x / CT; j3 < N3; j3 += kColThreads / CT)
-        dst[(size_t)j3 * P.ncols + lc] = tile[lc * TRS + j3];
+        dst[(size_t)j3 * P.ldt + lc] = tile[lc * TRS + j3];
   }
 }
 
@@ -99,12 +99,12 @@ __device__ __forceinline__ void col_fwd_reg_body(const BoxPlan& P, const C* __re
   const Rl alpha = (Rl)alpha_d, beta = (Rl)beta_d, gamma = (Rl)gamma_d;
   const int c0 = cb * CT;
   const int ncl = min(CT, P.ncols - c0);
-  const C* srcT = T + (size_t)b * N3 * P.ncols + c0;
+  const C* srcT = T + (size_t)b * N3 * P.ldt + c0;
   {
     const int lc = threadIdx.x % CT;
     if (lc < ncl)
       for (int j3 = threadIdx.x / CT; j3 < N3; j3 += kColThreads / CT)
-        tile[lc * TRS + j3] = srcT[(size_t)j3 * P.ncols + lc];
+        tile[lc * TRS + j3] = srcT[(size_t)j3 * P.ldt + lc];
   }
   __syncthreads();
   const int grp = threadIdx.x / G, lb = threadIdx.x % G;
@@ -176,7 +176,7 @@ __device__ __forceinline__ void plane_reg_body(const BoxPlan& P, const C* __rest
   C* E = reinterpret_cast<C*>(lds_raw);                            // xr x TRS
   int* slot = reinterpret_cast<int*>(E + (size_t)P.xr * TRS);      // N1 entries
   const int tid = threadIdx.x, nt = blockDim.x;
-  C* tp = T + (size_t)b * P.n3 * P.ncols + (size_t)j3 * P.ncols;
+  C* tp = T + (size_t)b * P.n3 * P.ldt + (size_t)j3 * P.ldt;
   for (int i = tid; i < P.xr * TRS; i += nt) E[i] = czero<C>();
   for (int i = tid; i < N1; i += nt) slot[i] = -1;
   __syncthreads();

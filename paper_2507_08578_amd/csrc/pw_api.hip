@@ -1104,6 +1104,7 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   }
   col_start.push_back((int)npw);
   P.ncols = (int)col_m1.size();
+  P.ldt = (P.ncols + 15) / 16 * 16;
   std::vector<int> ext;   // distinct m1 sorted by centred value
   {
     std::vector<int> tmp(col_m1.begin(), col_m1.end());
@@ -1211,7 +1212,7 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
                           hipMemcpyHostToDevice));
   }
   // workspaces
-  const size_t per_band = (size_t)P.n3 * P.ncols;
+  const size_t per_band = (size_t)P.n3 * P.ldt;
   const size_t budget = (size_t)512 << 20;
   h->chunk = std::max<int64_t>(1, std::min<int64_t>(h->nb_max, budget / (per_band * sizeof(cplx))));
   h->chunk_alloc = h->chunk;
@@ -1283,7 +1284,7 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
       TRY(dalloc(h, &h->work32, w32));
       TRY(dalloc(h, &h->gram32, (size_t)(h->nb_max * h->nb_max)));
     }
-    const size_t per_band32 = (size_t)P.n3 * P.ncols;
+    const size_t per_band32 = (size_t)P.n3 * P.ldt;
     TRY(dalloc(h, &h->T32, per_band32 * h->chunk_alloc));
     TRY(dalloc(h, &h->blk32[0], (size_t)(npw * h->nb_max)));
     TRY(dalloc(h, &h->blk32[1], (size_t)(npw * h->nb_max)));

@@ -63,6 +63,10 @@ struct BoxPlan {
   int n1, n2, n3;
   int64_t npw;
   int ncols;                // distinct (m1, m2) among sphere points ("columns" along N3)
+  // row stride, in columns, of the column intermediate T[b][j3][c]: ncols
+  // rounded up to a multiple of 16, so that every 16-column slice of a row
+  // the column kernels store or load covers whole 128-byte lines
+  int ldt;
   int xr;                   // distinct m1 among sphere points (extent along N1)
   // columns ordered by (n1, n2) of the Miller indices; column c holds the
   // points perm[col_start[c] .. col_start[c+1]) (indices into the caller's order)

@@ -132,16 +132,18 @@ def test_apply_fp32_uneven_box(pw, ctx, cell):
         assert err < tol
 
 
-@pytest.mark.parametrize("shape", ["quarter", "wide"])
+@pytest.mark.parametrize("shape", ["quarter", "wide", "wide3"])
 def test_apply_fp32_lds_exchange_plane_c5(pw, ctx, shape):
     """144^3 box (C5 cell, local part): the FP32 plane kernel with LDS
     exchanges (plane_variant32 = 2) against the lane-shuffle kernel and the
     FP64 oracle, on a ragged block of 21 bands.  "quarter": C5 at 20 Ha, the
     sphere (|m| <= 31) lies inside the outer quarters of every axis and the
     kernel prunes its transforms; "wide": the cell stretched 6% along a2 at
-    25 Ha, m2 reaches +-36 and the transforms run whole."""
+    25 Ha, m2 reaches +-36 and the transforms run whole; "wide3": the same
+    along a3, m3 reaches +-36 (the pruning holds, the columns are longer)."""
     import torch
-    strain, ecut = ((0.0, 0.0, 0.0), 20.0) if shape == "quarter" else ((0.0, 0.06, 0.0), 25.0)
+    strain, ecut = {"quarter": ((0.0, 0.0, 0.0), 20.0), "wide": ((0.0, 0.06, 0.0), 25.0),
+                    "wide3": ((0.0, 0.0, 0.06), 25.0)}[shape]
     w = synth.make_workload("C5", synth.diamond_cell(reps=(3, 3, 3), strain=strain), (0.0, 0.0, 0.0),
                             ecut, (144, 144, 144), "sp", nb=21, degree=12, iters=1, with_proj=False)
     ham = pw.Hamiltonian.from_workload(ctx, w, nb_max=21, low_prec=True)
