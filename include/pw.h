@@ -392,7 +392,8 @@ pw_status pw_ham_set_tuning(pw_ham* ham, const pw_tuning* t);
 /*
  * Coordinate search over (1) the FFT kernel families, (2) the band chunk,
  * (3) the split-K block count, (4) the tile of the tall products, each step
- * keeping the fastest; every
+ * keeping the fastest (an alternative replaces the current choice only when
+ * it is more than 1% faster, above the spread of repeated timings); every
  * candidate timed as the median of reps H*psi applications of nb bands in
  * precision prec (after one warm-up) with HIP events on the context's
  * stream.  Leaves the handle at *best; *initial (may be NULL) receives the

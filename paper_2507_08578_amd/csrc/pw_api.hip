@@ -872,6 +872,9 @@ struct EventGuard {
 
 // Median time of one H application of nb bands under the handle's current
 // tuning (one untimed warm-up).
+// Relative margin by which an autotuning candidate must beat the current choice.
+constexpr double kTuneMargin = 0.01;
+
 pw_status time_apply(pw_ham* h, pw_prec prec, int64_t nb, void* in, void* out, int reps, double* ms) {
   pw_ctx* c = h->ctx;
   EventGuard a, b;
@@ -1707,7 +1710,8 @@ pw_status pw_ham_autotune(pw_ham* h, pw_prec prec, int64_t nb, int32_t reps, pw_
     if (s2 != PW_OK) return s2;
     double ms = 0.0;
     if ((s2 = time_apply(h, prec, nb, in, out, reps, &ms)) != PW_OK) return s2;
-    if (ms < cur_ms) {
+    // a change must win by more than the spread of repeated timings (about 1%)
+    if (ms < (1.0 - kTuneMargin) * cur_ms) {
       cur = t;
       cur_ms = ms;
     }
