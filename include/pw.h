@@ -96,8 +96,10 @@ const char* pw_last_error(const pw_ctx* ctx);
 
 /*
  * Deferred status of the hot calls.  A failure that only the device can see
- * -- a Cholesky pivot at or below the threshold (PW_ERR_NOT_POSDEF), the
- * dense eigensolver reaching its sweep limit (PW_ERR_NO_CONVERGENCE) -- is
+ * -- a Cholesky pivot at or below the threshold (PW_ERR_NOT_POSDEF), a Gram
+ * diagonal entry that is NaN or infinite, i.e. a column of the block that
+ * is not finite (PW_ERR_NONFINITE, naming the column), the dense
+ * eigensolver reaching its sweep limit (PW_ERR_NO_CONVERGENCE) -- is
  * written to a status word of the context by the kernels themselves; the
  * first one since the last check is kept, later ones are dropped, and the
  * outputs of the failing call and of every later call that used them are
@@ -253,7 +255,8 @@ pw_status pw_cheb_filter(pw_ham* ham, pw_prec prec, int32_t degree, double a, do
  * twice), so the final block is orthonormal to FP64 accuracy whatever S1's
  * precision.  Does not synchronise: a squared pivot at or below
  * nb * eps * max_i S_ii (either pass) is reported by pw_ctx_check as
- * PW_ERR_NOT_POSDEF naming the pivot.
+ * PW_ERR_NOT_POSDEF naming the pivot, a column of Y holding a NaN or an
+ * infinity (a non-finite S_ii) as PW_ERR_NONFINITE naming the column.
  */
 pw_status pw_orthonormalize(pw_ham* ham, pw_prec gram_prec, int64_t nb, void* y_dev, int64_t ld,
                             void* hy_dev, int64_t ldhy);
@@ -522,7 +525,8 @@ pw_status pw_heev_noalloc(pw_ctx* ctx, int64_t n, const void* a_dev, int64_t lda
  * overwritten; strictly lower part set to 0); then ainv_dev (n x n, ldi)
  * receives U^{-1} (upper, zeros below), formed as I U^{-1} by the same
  * blocked right-side triangular solve pw_orthonormalize applies to Y.
- * Synchronises; NOT_POSDEF as above. */
+ * Synchronises; NOT_POSDEF as above; PW_ERR_NONFINITE when a diagonal
+ * entry of a is NaN or infinite. */
 pw_status pw_potrf_inv(pw_ctx* ctx, int64_t n, void* a_dev, int64_t lda, void* ainv_dev,
                        int64_t ldi);
 

@@ -169,17 +169,27 @@ k_residuals(int64_t npw, const cplx* __restrict__ W, int64_t ldw, const cplx* __
 __device__ __forceinline__ void chol_init_body(int n, const cplx* __restrict__ A, int64_t lda,
                                                     double* tol, int* status) {
   __shared__ double red[1024];
+  __shared__ int bad[1024];
   double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, A[i + (int64_t)i * lda].x);
+  int b = n;   // first diagonal entry that is NaN or infinite (a non-finite column)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double d = A[i + (int64_t)i * lda].x;
+    m = fmax(m, d);
+    if (!isfinite(d)) b = min(b, i);
+  }
   red[threadIdx.x] = m;
+  bad[threadIdx.x] = b;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+      bad[threadIdx.x] = min(bad[threadIdx.x], bad[threadIdx.x + s]);
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     tol[0] = (double)n * DBL_EPSILON * red[0];
-    status[0] = -1;
+    status[0] = bad[0] < n ? kCholNonFinite - bad[0] : -1;
   }
 }
 
@@ -255,7 +265,7 @@ __device__ __forceinline__ void chol_diag_body(int kb, int k0, cplx* __restrict_
     __syncthreads();
   }
   if (fail >= 0) {
-    if (tid == 0 && status[0] < 0) status[0] = k0 + fail;
+    if (tid == 0 && status[0] == -1) status[0] = k0 + fail;
     return;
   }
   for (int i = tid; i < kb; i += nt) {
@@ -1125,13 +1135,15 @@ k_cheb_coef(const double* __restrict__ eig, int nb, const double* __restrict__ u
 }
 
 // Sticky per-item failure flags of a batched iteration:
-// flags[0] = first failing Cholesky pivot + 1, flags[1] = eigensolver hit the
+// flags[0] = first failing Cholesky pivot + 1 (or -(column + 1) for a Gram
+// diagonal entry that is not finite), flags[1] = eigensolver hit the
 // sweep limit, flags[2] = bad filter interval (set by k_cheb_coef),
 // flags[3] = largest sweep count seen.
 __device__ __forceinline__ void batch_flags_body(const int* __restrict__ chol_status, const int* __restrict__ sweeps,
                               int* flags) {
   if (threadIdx.x != 0) return;
-  if (chol_status && chol_status[0] >= 0 && flags[0] == 0) flags[0] = chol_status[0] + 1;
+  if (chol_status && chol_status[0] != -1 && flags[0] == 0)
+    flags[0] = chol_status[0] >= 0 ? chol_status[0] + 1 : chol_status[0] - kCholNonFinite - 1;
   const int sw = sweeps[0];
   if (sw < 0) flags[1] = 1;
   else if (sw > flags[3]) flags[3] = sw;
@@ -1504,6 +1516,10 @@ __global__ void k_status_record(const int* __restrict__ chol_status, const int* 
     rec[0] = 5;   // PW_ERR_NOT_POSDEF
     rec[1] = op;
     rec[2] = chol_status[0];
+  } else if (chol_status && chol_status[0] <= kCholNonFinite) {
+    rec[0] = 6;   // PW_ERR_NONFINITE
+    rec[1] = op;
+    rec[2] = kCholNonFinite - chol_status[0];
   } else if (sweeps && sweeps[0] < 0) {
     rec[0] = 7;   // PW_ERR_NO_CONVERGENCE
     rec[1] = op;

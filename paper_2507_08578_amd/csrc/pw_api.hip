@@ -836,9 +836,12 @@ pw_status batch_check(pw_batch* b) {
     const int* f = b->flags_host + 4 * i;
     b->max_sweeps = std::max(b->max_sweeps, f[3]);
     const std::string who = "batch item " + std::to_string(i) + ": ";
-    if (f[0])
+    if (f[0] > 0)
       return fail(c, PW_ERR_NOT_POSDEF,
                   who + "Gram matrix not positive definite at pivot " + std::to_string(f[0] - 1));
+    if (f[0] < 0)
+      return fail(c, PW_ERR_NONFINITE,
+                  who + "column " + std::to_string(-f[0] - 1) + " of the block is NaN or infinite");
     if (f[1]) return fail(c, PW_ERR_NO_CONVERGENCE, who + "Jacobi eigensolver hit its sweep limit");
     if (f[2])
       return fail(c, PW_ERR_INVALID_ARG,
@@ -2188,7 +2191,7 @@ pw_status pw_potrf_inv(pw_ctx* c, int64_t n, void* a, int64_t lda, void* ainv, i
   int hs = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&hs, stat, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e == hipSuccess && hs < 0) {
+  if (e == hipSuccess && hs == -1) {
     e = launch_zero_lower(n, A, lda, s);
     if (e == hipSuccess) e = launch_identity(n, X, ldi, s);
     if (e == hipSuccess) e = trsm_right(n, n, X, ldi, A, lda, dinv, ytmp, s);
@@ -2197,6 +2200,9 @@ pw_status pw_potrf_inv(pw_ctx* c, int64_t n, void* a, int64_t lda, void* ainv, i
   free_ham(&tmp);
   if (e != hipSuccess) return fail(c, PW_ERR_HIP, hipGetErrorString(e));
   if (hs >= 0) return fail(c, PW_ERR_NOT_POSDEF, "matrix not positive definite at pivot " + std::to_string(hs));
+  if (hs <= kCholNonFinite)
+    return fail(c, PW_ERR_NONFINITE,
+                "diagonal entry " + std::to_string(kCholNonFinite - hs) + " is NaN or infinite");
   return PW_OK;
 }
 
@@ -2275,6 +2281,10 @@ pw_status pw_ctx_check(pw_ctx* c) {
     return fail(c, PW_ERR_NOT_POSDEF,
                 std::string(op_name(op)) + ": Gram matrix not positive definite at pivot " +
                     std::to_string(info));
+  if (code == PW_ERR_NONFINITE)
+    return fail(c, PW_ERR_NONFINITE,
+                std::string(op_name(op)) + ": column " + std::to_string(info) +
+                    " of the block is NaN or infinite (its Gram diagonal entry)");
   if (code == PW_ERR_NO_CONVERGENCE)
     return fail(c, PW_ERR_NO_CONVERGENCE,
                 std::string(op_name(op)) + ": Jacobi eigensolver reached its limit of " +

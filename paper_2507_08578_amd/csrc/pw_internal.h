@@ -405,8 +405,12 @@ hipError_t launch_cheb_coef(const double* eig, int nb, const double* upper, int 
 // status: 0 if every element finite, else 1
 hipError_t launch_check_finite(int64_t n, const double* x, int* flag, hipStream_t s);
 // Blocked Cholesky pieces: tol = n eps max diag, status = -1; per diagonal
-// block (kb <= 64) factor + inverse of the factor in LDS.
+// block (kb <= 64) factor + inverse of the factor in LDS.  The status word:
+// -1 no failure, p >= 0 the first pivot at or below tol, kCholNonFinite - j
+// diagonal entry j is NaN or infinite (column j of the block is not finite;
+// set by the init step, never overwritten by a pivot).
 constexpr int kCholBlock = 64;
+constexpr int kCholNonFinite = -2;
 hipError_t launch_chol_init(int64_t n, const cplx* a, int64_t lda, double* tol, int* status,
                             hipStream_t s);
 hipError_t launch_chol_diag(int kb, int k0, cplx* a, int64_t lda, cplx* dinv, const double* tol,

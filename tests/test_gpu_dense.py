@@ -94,6 +94,20 @@ def test_potrf_not_posdef(pw, ctx):
     assert e.value.status == 5 and "pivot 4" in str(e.value)
 
 
+def test_potrf_nonfinite_diagonal(pw, ctx):
+    """A NaN column of Y gives S = Y^H Y a NaN diagonal entry: reported as
+    PW_ERR_NONFINITE with its index (the first one, here in the second
+    64-wide diagonal block), ahead of any pivot test."""
+    rng = np.random.default_rng(2)
+    Y = crand(rng, 200, 90)
+    Y[7, 70] = np.nan
+    Y[3, 81] = np.inf
+    S = Y.conj().T @ Y
+    with pytest.raises(pw.PWError) as e:
+        ctx.potrf_inv(to_dev(S.T.copy()))
+    assert e.value.status == 6 and "diagonal entry 70 " in str(e.value), str(e.value)
+
+
 @pytest.mark.parametrize("n", [1, 2, 16, 24, 63, 64, 65, 100, 160, 257, 512])
 def test_heev_random(ctx, n):
     rng = np.random.default_rng(100 + n)

@@ -88,6 +88,23 @@ def test_deferred_not_posdef_then_cleared(pw):
     ctx.check_status()                               # the word was cleared
 
 
+def test_deferred_nonfinite_column_then_cleared(pw):
+    """A NaN in one band of the block makes that band's Gram diagonal entry
+    NaN: the Cholesky step's init kernel reports the column as non-finite
+    (PW_ERR_NONFINITE), not as a failed pivot; an infinity likewise."""
+    import torch
+    for bad in (float("nan"), float("inf")):
+        ctx, ham, s, Y, HY, eig, res = _state(pw, 8, seed=1)
+        with torch.cuda.stream(s):
+            Y[6, 17] = bad
+            ham.orthonormalize(Y, check=False)
+        with pytest.raises(pw.PWError) as e:
+            ctx.check_status()
+        assert e.value.status == 6 and "pw_orthonormalize" in str(e.value), str(e.value)
+        assert "column 6 " in str(e.value), str(e.value)
+        ctx.check_status()
+
+
 def test_deferred_sweep_limit(pw):
     """A random 96 x 96 subspace matrix cannot be diagonalised in one Jacobi
     sweep: with the limit at 1 the device reports NO_CONVERGENCE; at the
