@@ -1,6 +1,7 @@
 """Build libpwdft.so (HIP, gfx950) in-tree with hipcc.
 
-Every .hip file under csrc/ is compiled to an object in _build/ and linked
+Every .hip file under csrc/ (and the host-only .cpp files there, such as
+the sphere -> box map builder) is compiled to an object in _build/ and linked
 into paper_2507_08578_amd/libpwdft.so.  Always rebuilds (the caller asked
 for a build); objects compile in parallel.
 """
@@ -44,7 +45,7 @@ def hipcc() -> str:
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
+    obj = os.path.join(BUILD, os.path.splitext(os.path.basename(src))[0] + ".o")
     extra = FILE_FLAGS.get(os.path.basename(src), [])
     cmd = [hipcc(), *CFLAGS, *extra, "-I", os.path.join(HERE, "..", "include"), "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,7 +56,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"

@@ -5,6 +5,7 @@
 //   pw_cheb_filter    section 5.1 (Chebyshev filtering, textbook scaled recurrence)
 //   pw_orthonormalize section 5.4 (full-band Cholesky orthogonalisation)
 //   pw_rayleigh_ritz  section 5.1 (Rayleigh-Ritz subspace diagonalisation)
+#include "plan_host.h"
 #include "pw_handles.h"
 
 #include <algorithm>
@@ -112,8 +113,6 @@ void free_ham(pw_ham* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
 }
-
-inline int center(int m, int n) { return m <= n / 2 ? m : m - n; }
 
 bool ranges_overlap(const void* a, int64_t lda, const void* b, int64_t ldb, int64_t rows,
                     int64_t cols, int64_t elem) {
@@ -1064,70 +1063,22 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
   }
   // ---- sphere -> box maps (host) ----
   const int64_t npw = d->npw;
-  std::vector<int> m1(npw), m2(npw), m3(npw);
-  {
-    std::unordered_set<int64_t> cells;
-    cells.reserve((size_t)npw * 2);
-    for (int64_t g = 0; g < npw; ++g) {
-      const int64_t a = d->miller[3 * g], b = d->miller[3 * g + 1], cc = d->miller[3 * g + 2];
-      m1[g] = (int)(((a % P.n1) + P.n1) % P.n1);
-      m2[g] = (int)(((b % P.n2) + P.n2) % P.n2);
-      m3[g] = (int)(((cc % P.n3) + P.n3) % P.n3);
-      const int64_t key = ((int64_t)m3[g] * P.n2 + m2[g]) * P.n1 + m1[g];
-      if (!cells.insert(key).second) {
-        delete h;
-        return fail(ctx, PW_ERR_INVALID_ARG,
-                    "two sphere points fall in the same box cell (box too small), point " +
-                        std::to_string(g));
-      }
-    }
+  pwplan::HostPlan hp;
+  int64_t bad_point = -1;
+  const int prc = pwplan::build_host_plan(d->miller, d->npw, P.n1, P.n2, P.n3, &hp, &bad_point);
+  if (prc != 0) {
+    delete h;
+    if (prc == 1)
+      return fail(ctx, PW_ERR_INVALID_ARG,
+                  "two sphere points fall in the same box cell (box too small), point " +
+                      std::to_string(bad_point));
+    return fail(ctx, PW_ERR_INVALID_ARG, "sphere -> box map arguments out of range");
   }
-  // points ordered by (centred m1, centred m2, centred m3): columns = runs of equal (m1, m2)
-  std::vector<int> order(npw);
-  for (int64_t g = 0; g < npw; ++g) order[g] = (int)g;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    const int ax = center(m1[x], P.n1), ay = center(m1[y], P.n1);
-    if (ax != ay) return ax < ay;
-    const int bx = center(m2[x], P.n2), by = center(m2[y], P.n2);
-    if (bx != by) return bx < by;
-    return center(m3[x], P.n3) < center(m3[y], P.n3);
-  });
-  std::vector<int> col_start, col_m1, col_m2v, col_m3lo, pt_col(npw), pt_m3(npw);
-  P.runs = 1;
-  for (int64_t k = 0; k < npw; ++k) {
-    const int g = order[k];
-    if (k == 0 || m1[g] != m1[order[k - 1]] || m2[g] != m2[order[k - 1]]) {
-      col_start.push_back((int)k);
-      col_m1.push_back(m1[g]);
-      col_m2v.push_back(m2[g]);
-      col_m3lo.push_back(center(m3[g], P.n3));
-    } else if (center(m3[g], P.n3) != center(m3[order[k - 1]], P.n3) + 1) {
-      P.runs = 0;   // a gap along N3 inside a column
-    }
-    if (g != (int)k) P.runs = 0;   // not in column order
-    pt_col[k] = (int)col_start.size() - 1;
-    pt_m3[k] = m3[g];
-  }
-  col_start.push_back((int)npw);
-  P.ncols = (int)col_m1.size();
-  P.ldt = (P.ncols + 15) / 16 * 16;
-  std::vector<int> ext;   // distinct m1 sorted by centred value
-  {
-    std::vector<int> tmp(col_m1.begin(), col_m1.end());
-    std::sort(tmp.begin(), tmp.end(), [&](int x, int y) { return center(x, P.n1) < center(y, P.n1); });
-    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-    ext = tmp;
-  }
-  P.xr = (int)ext.size();
-  P.quarter12 = 1;
-  for (int c = 0; c < P.ncols; ++c) {
-    const int a1 = center(col_m1[c], P.n1), a2 = center(col_m2v[c], P.n2);
-    if (4 * a1 < -P.n1 || 4 * a1 >= P.n1 || 4 * a2 < -P.n2 || 4 * a2 >= P.n2) P.quarter12 = 0;
-  }
-  std::vector<int> slot(P.n1, -1);
-  for (int e = 0; e < P.xr; ++e) slot[ext[e]] = e;
-  std::vector<int> col_e(P.ncols);
-  for (int c = 0; c < P.ncols; ++c) col_e[c] = slot[col_m1[c]];
+  P.ncols = hp.ncols;
+  P.ldt = hp.ldt;
+  P.xr = hp.xr;
+  P.quarter12 = hp.quarter12;
+  P.runs = hp.runs;
 
   pw_status st = PW_OK;
   auto upload_int = [&](int** dst, const std::vector<int>& v) -> pw_status {
@@ -1146,14 +1097,14 @@ pw_status pw_ham_create(pw_ctx* ctx, const pw_ham_desc* d, pw_ham** out) {
       return st;       \
     }                  \
   } while (0)
-  TRY(upload_int(&P.col_start, col_start));
-  TRY(upload_int(&P.col_e, col_e));
-  TRY(upload_int(&P.col_m2, col_m2v));
-  TRY(upload_int(&P.pt_perm, order));
-  TRY(upload_int(&P.pt_col, pt_col));
-  TRY(upload_int(&P.pt_m3, pt_m3));
-  TRY(upload_int(&P.col_m3lo, col_m3lo));
-  TRY(upload_int(&P.ext_m1, ext));
+  TRY(upload_int(&P.col_start, hp.col_start));
+  TRY(upload_int(&P.col_e, hp.col_e));
+  TRY(upload_int(&P.col_m2, hp.col_m2));
+  TRY(upload_int(&P.pt_perm, hp.pt_perm));
+  TRY(upload_int(&P.pt_col, hp.pt_col));
+  TRY(upload_int(&P.pt_m3, hp.pt_m3));
+  TRY(upload_int(&P.col_m3lo, hp.col_m3lo));
+  TRY(upload_int(&P.ext_m1, hp.ext_m1));
   // twiddles
   FftAxis* axes[3] = {&P.ax1, &P.ax2, &P.ax3};
   for (FftAxis* ax : axes) {
