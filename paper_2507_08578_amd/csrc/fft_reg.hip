@@ -28,33 +28,37 @@ __device__ __forceinline__ void col_inv_reg_body(const BoxPlan& P, const C* __re
   __shared__ C tile[CT * TRS];
   const int c0 = cb * CT;
   const int ncl = min(CT, P.ncols - c0);
-  for (int i = threadIdx.x; i < CT * TRS; i += blockDim.x) tile[i] = czero<C>();
-  __syncthreads();
   const S* src = psi + (size_t)b * ldpsi;
   const int grp = threadIdx.x / G, lb = threadIdx.x % G;
-  if (P.runs) {
-    // one lane group per column: its points are consecutive in psi and in m3
-    if (grp < ncl) {
-      const int c = c0 + grp, ks = P.col_start[c], len = P.col_start[c + 1] - ks;
-      const int lo = P.col_m3lo[c];
-      for (int j = lb; j < len; j += G) {
-        const int m = lo + j;
-        tile[grp * TRS + (m < 0 ? m + N3 : m)] = ld_c(src[ks + j]);
-      }
-    }
-  } else {
+  if (!P.runs) {
+    for (int i = threadIdx.x; i < CT * TRS; i += blockDim.x) tile[i] = czero<C>();
+    __syncthreads();
     const int k0 = P.col_start[c0], k1 = P.col_start[c0 + ncl];
     for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x)
       tile[(P.pt_col[k] - c0) * TRS + P.pt_m3[k]] = ld_c(src[P.pt_perm[k]]);
+    __syncthreads();
   }
-  __syncthreads();
   if (grp < ncl) {
     C v[R];
     C* col = tile + grp * TRS;
     LaneTw<R, G, C> tw;
     tw.load(lb, tw3);
+    if (P.runs) {
+      // one lane group per column, its points consecutive in psi and in
+      // centred m3 from lo: lane lb loads box positions G a + lb straight
+      // into registers (zero outside the run)
+      const int c = c0 + grp, ks = P.col_start[c], len = P.col_start[c + 1] - ks;
+      const int lo = P.col_m3lo[c];
 #pragma unroll
-    for (int a = 0; a < R; ++a) v[a] = col[G * a + lb];
+      for (int a = 0; a < R; ++a) {
+        const int m = G * a + lb;
+        const int j = (m <= N3 / 2 ? m : m - N3) - lo;
+        v[a] = (unsigned)j < (unsigned)len ? ld_c(src[ks + j]) : czero<C>();
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < R; ++a) v[a] = col[G * a + lb];
+    }
     lane_fft_bwd<R, G>(v, lb, tw);
     const int base = R * brev<G>(lb);
 #pragma unroll

@@ -40,6 +40,30 @@ def test_c1_full_block(pw, ctx):
     assert err < TOL, err
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_points_out_of_column_order(pw, ctx, prec):
+    """C1 with its sphere points shuffled (Miller rows and projector columns
+    permuted together): the column kernels take their general gather and
+    scatter instead of the contiguous runs; against the oracle on the same
+    shuffled workload, in FP64 and in FP32."""
+    import dataclasses
+    import torch
+    w = synth.config_c1()
+    perm = np.random.default_rng(5).permutation(w.npw)
+    ws = dataclasses.replace(w, miller=w.miller[perm].copy(), proj=w.proj[:, perm].copy())
+    if prec == "fp64":
+        err, _ = run_apply(pw, ctx, ws, 9, seed=3)
+        assert err < TOL, err
+        return
+    ham = pw.Hamiltonian.from_workload(ctx, ws, nb_max=9, low_prec=True)
+    X0 = synth.start_block(ws.npw, 9, 3).astype(np.complex64)
+    X = to_dev(X0.astype(np.complex128)).to(torch.complex64)
+    HX = to_host(ham.apply_h(X, prec="fp32")).astype(np.complex128)
+    ref = oracle.apply_h(oracle.OracleHam.from_workload(ws), X0.astype(np.complex128).T).T
+    err = rel_err(HX, ref)
+    assert err < 2e-6, err
+
+
 def test_c1_local_only_and_single_band(pw, ctx):
     w = synth.config_c1()
     w.proj = w.proj[:0]
